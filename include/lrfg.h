@@ -1,0 +1,200 @@
+/*
+ * lrfg.h -- C ABI of the MI355X (gfx950) low-rank Fourier-Galerkin
+ * homogenisation library (liblrfg.so).
+ *
+ * The library computes the effective (homogenised) matrix A_H of the scalar
+ * periodic cell problem of Vondrejc, Liu, Ladecky and Matthies,
+ * "FFT-based homogenisation accelerated by low-rank tensor approximations"
+ * (arXiv:1902.07455):
+ *
+ *   A_H E.E = min over zero-mean periodic v of  mean_Y a(x) |E + grad v|^2
+ *   (Sec. 2.1, eq. homog / bilinear),
+ *
+ * discretised with trigonometric polynomials on an odd grid N^d and the
+ * rectangle rule ("GaNi", Sec. 2.2.1-2.2.2, eq. ls_GaNi_fourier),
+ * preconditioned by the Fourier Laplacian (Sec. 2.3, eq. Pls_GaNi_fourier).
+ * Two solution paths:
+ *   FULL    the corrector is a full grid tensor; preconditioned CG with
+ *           3-D FFTs (the plain method of Sec. 4);
+ *   TT / TUCKER / CP
+ *           the corrector is held in a low-rank format (Sec. 3.1) and the
+ *           operator is applied with truncation after every rank-raising
+ *           step (Sec. 3.2, eq. Pls_lowrank, Table 1); solved by truncated
+ *           PCG or the truncated minimal-residual iteration (Sec. 3.3).
+ *
+ * Conventions shared by every call
+ *   - Grid point j in [0, N) of an axis sits at x_j = -1/2 + (j + 1/2)/N
+ *     (the regular grid k/N of Sec. 2.2.1 for odd N).  Full fields are
+ *     FP64, C order, axis 0 = x_1 slowest.
+ *   - Device pointers are HIP device addresses; "stream" is a hipStream_t
+ *     passed as void* (NULL = the default stream).  Calls are ordered on
+ *     that stream.
+ *   - The library never allocates device memory in a solve or an op call:
+ *     all device storage is the caller's workspace (d_ws, ws_bytes), whose
+ *     required size comes from lrfg_plan_workspace_bytes.  d_ws must be
+ *     256-byte aligned.
+ *   - Every call returns an lrfg_status; no exception crosses the ABI.
+ *     lrfg_last_error() returns a thread-local message for the last failure.
+ *   - A plan may be used by one thread at a time.
+ */
+#ifndef LRFG_H
+#define LRFG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRFG_ABI_VERSION 1
+
+typedef enum {
+  LRFG_OK = 0,
+  LRFG_NOT_CONVERGED = 1,   /* A_H written; some corrector hit max_iter      */
+  LRFG_EINVAL = -1,         /* bad argument (d, even or < 3 N, rank_cap < 1,
+                               negative or NaN tolerance, CP with d = 3, ...) */
+  LRFG_ECOEFF = -2,         /* coefficient not finite and positive           */
+  LRFG_EWORKSPACE = -3,     /* workspace too small or misaligned             */
+  LRFG_EDEVICE = -4,        /* HIP error or no usable gfx950 device           */
+  LRFG_EUNSUPPORTED = -5    /* valid request this build does not implement   */
+} lrfg_status;
+
+typedef enum {
+  LRFG_FORMAT_FULL = 0,
+  LRFG_FORMAT_CP = 1,       /* d = 2 only (Sec. 3.1.1)                       */
+  LRFG_FORMAT_TUCKER = 2,   /* Sec. 3.1.2, Appendix A.2                      */
+  LRFG_FORMAT_TT = 3        /* Sec. 3.1.3, Appendix A.3                      */
+} lrfg_format;
+
+typedef enum {
+  LRFG_SOLVER_PCG = 0,      /* preconditioned conjugate gradients            */
+  LRFG_SOLVER_MR = 1        /* minimal-residual iteration (Sec. 3.3)         */
+} lrfg_solver;
+
+typedef enum {
+  LRFG_PREC_FP64 = 0,
+  LRFG_PREC_MIXED_FP32 = 1,
+  LRFG_PREC_MIXED_BF16 = 2
+} lrfg_precision;
+
+/* Problem description (the paper's problem statement, Sec. 2.1-2.3, 3.2). */
+typedef struct {
+  int d;                /* 2 or 3                                            */
+  int N[3];             /* odd grid sizes >= 3 (Sec. 2.2.1: odd N only)      */
+  int format;           /* lrfg_format of the corrector                      */
+  int rank_cap;         /* low-rank formats: maximal rank kept by truncation */
+  double trunc_tol;     /* relative truncation tolerance (0: rank cap only)  */
+  double solver_tol;    /* stop at ||P^-1 r|| <= solver_tol ||P^-1 b||       */
+  int max_iter;         /* iteration limit per corrector (>= 1)              */
+  int solver;           /* lrfg_solver                                       */
+  int precision;        /* lrfg_precision                                    */
+  int precond_terms;    /* low-rank: exponential-sum terms M (0 = automatic) */
+  int oversample;       /* low-rank: sketch oversampling p (0 = automatic)   */
+  uint64_t seed;        /* low-rank: seed of the sketching generator         */
+  uint32_t flags;       /* reserved, must be 0                               */
+} lrfg_problem;
+
+/* Coefficient a(x) > 0 (scalar isotropic A = a I).  For FULL, `full` holds
+ * a[N1*...*Nd] (C order).  For the low-rank formats the coefficient is given
+ * in the CP form a = sum_t w[t] prod_i f_i[t, j_i]: `weights` (R values) and
+ * `factors[i]` (R x N_i, row-major) -- every coefficient of the paper's
+ * workloads is given this way (Sec. 4.1: rank 2 inclusions, rank-limited
+ * smooth fields) -- or in TT form (`tt_cores[i]`, [r_{i-1}][N_i][r_i],
+ * tt_ranks[0..d]).  Exactly one of full / weights / tt_cores is non-NULL.
+ * Pointers are host addresses unless on_device != 0.  Borrowed for the call.
+ */
+typedef struct {
+  int on_device;
+  const double* full;
+  int rank;                       /* CP form: number of terms R                 */
+  const double* weights;          /* CP form: R                                 */
+  const double* factors[3];       /* CP form: R x N_i                           */
+  int tt_ranks[4];                /* TT form: r_0..r_d (r_0 = r_d = 1)           */
+  const double* tt_cores[3];      /* TT form                                    */
+} lrfg_coeff;
+
+/* Results, host memory owned by the caller (any pointer may be NULL). */
+typedef struct {
+  double* A_H;        /* nE*nE row-major: A_H E_i . E_j (= A_H for E = I)    */
+  int* iters;         /* nE: iterations per corrector                        */
+  double* res_hist;   /* nE*max_iter: relative preconditioned residual norm,
+                         the Euclidean norm of the residual's Fourier
+                         coefficients (Sec. 4.2); unused entries set to 0    */
+  int* ranks;         /* nE*(d+1): final corrector ranks (low-rank formats)  */
+  int* status;        /* nE: per-corrector lrfg_status                       */
+  double setup_ms;    /* coefficient upload/compression, transforms          */
+  double solve_ms;    /* iterations and A_H evaluation                       */
+} lrfg_result;
+
+typedef struct lrfg_plan lrfg_plan;
+
+/* Version of this ABI (LRFG_ABI_VERSION). */
+int lrfg_abi_version(void);
+
+/* Static description of a status code. */
+const char* lrfg_status_string(int status);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* lrfg_last_error(void);
+
+/* LRFG_OK if a HIP device is visible and usable, else LRFG_EDEVICE. */
+int lrfg_device_check(void);
+
+/* Validate `p` and build a host-side plan (FFT factorisations, twiddle
+ * tables, workspace layout).  No device call.  *out is owned by the caller
+ * and released with lrfg_plan_destroy. */
+int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out);
+
+/* Device workspace (bytes) lrfg_solve needs for up to `max_nE` macroscopic
+ * fields. */
+int lrfg_plan_workspace_bytes(const lrfg_plan* plan, int max_nE, size_t* bytes);
+
+/* Solve the d cell problems for E_1..E_nE and form A_H (eq. homog).
+ * E: host array nE x d (row-major) or NULL for the canonical basis (nE = d).
+ * Stream-ordered; synchronises `stream` before writing host results.
+ * Returns LRFG_NOT_CONVERGED if some corrector stopped at max_iter. */
+int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE,
+               void* d_ws, size_t ws_bytes, void* stream, lrfg_result* out);
+
+void lrfg_plan_destroy(lrfg_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Operation-level entry points: the kernels of the solve paths, exposed so
+ * that each can be checked on its own.  Device pointers, stream-ordered,
+ * no allocation, no synchronisation.
+ * ---------------------------------------------------------------------- */
+
+/* Batched 1-D DFT of length N along the middle index of a complex array
+ * x[outer][N][inner] (interleaved re,im FP64), in place.  direction -1 is
+ * the forward transform F_N with its 1/N factor, +1 the unnormalised
+ * inverse (Sec. 2.2.1, DFT matrices).  Odd N only.
+ * d_ws: lrfg_fft_workspace_bytes(N) bytes (twiddle table). */
+size_t lrfg_fft_workspace_bytes(int N);
+int lrfg_fft_lines(double* x, int outer, int N, int inner, int direction,
+                   void* d_ws, size_t ws_bytes, void* stream);
+
+/* Real circulant operator along the middle index of a real array
+ * x[outer][N][inner], in place: x <- F^-1 diag(s(k)) F x per fibre, with
+ *   op 0: s(k) = 2 pi i k                (spectral derivative, eq. grad_trig)
+ *   op 1: s(k) = exp(-t k^2)             (heat kernel factor of the
+ *                                         exponential-sum preconditioner)
+ * k the centred frequency.  This is the per-mode 1-D DFT the low-rank
+ * formats apply to their factors (Sec. 3.1, Appendix A). */
+int lrfg_mode_op(double* x, int outer, int N, int inner, int op, double t,
+                 void* d_ws, size_t ws_bytes, void* stream);
+
+/* Full-grid operator on half-spectrum arrays u[N1][N2][(N3+1)/2] (complex):
+ *   which 0: out = K u  = grad*^ F a F^-1 grad^ u    (eq. ls_GaNi_fourier)
+ *   which 1: out = P^-1 u = u / (4 pi^2 k.k), 0 at k = 0 (Sec. 2.3)
+ * `a` is the real coefficient [N1][N2][N3] on the device. d = 3 only.
+ * d_ws: lrfg_full_op_workspace_bytes bytes. */
+size_t lrfg_full_op_workspace_bytes(const int N[3]);
+int lrfg_full_op(int which, const int N[3], const double* a, const double* u,
+                 double* out, void* d_ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRFG_H */

@@ -1,0 +1,231 @@
+"""MI355X-native low-rank Fourier-Galerkin homogenisation (liblrfg).
+
+Python binding of the C ABI in include/lrfg.h.  PyTorch provides device
+memory (the workspace and device-resident inputs) and the HIP stream; every
+step of the solve runs in the library's HIP kernels.
+
+    from paper_1902_07455_amd import Solver
+    s = Solver(d=3, N=(135, 135, 135), format="full", solver_tol=1e-8)
+    res = s.solve(full=a)          # a: numpy array or torch tensor
+    res.A_H                        # (d, d)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import LrfgError, check, lib
+
+__all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
+           "abi_version", "device_check"]
+
+_FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
+            "tt": _lib.FORMAT_TT}
+_SOLVERS = {"pcg": _lib.SOLVER_PCG, "mr": _lib.SOLVER_MR}
+_PRECS = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_MIXED_FP32, "bf16": _lib.PREC_MIXED_BF16}
+
+
+def abi_version() -> int:
+    return lib().lrfg_abi_version()
+
+
+def device_check() -> int:
+    return lib().lrfg_device_check()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class _Held:
+    """Keeps host/device buffers alive while a call runs; yields pointers."""
+
+    def __init__(self, device):
+        self.keep = []
+        self.device = device
+
+    def ptr(self, x, dtype=np.float64):
+        """Pointer and on-device flag for a numpy array or torch tensor."""
+        if x is None:
+            return None, 0
+        torch = _torch() if not isinstance(x, np.ndarray) else None
+        if torch is not None and isinstance(x, torch.Tensor):
+            t = x.detach()
+            if t.dtype != torch.float64:
+                raise TypeError("FP64 tensors expected")
+            t = t.contiguous()
+            self.keep.append(t)
+            return t.data_ptr(), int(t.is_cuda)
+        arr = np.ascontiguousarray(np.asarray(x, dtype=dtype))
+        self.keep.append(arr)
+        return arr.ctypes.data, 0
+
+
+@dataclasses.dataclass
+class SolveResult:
+    A_H: np.ndarray
+    iters: np.ndarray
+    res_hist: np.ndarray
+    ranks: np.ndarray
+    status: np.ndarray
+    rc: int
+    setup_ms: float
+    solve_ms: float
+
+
+class Solver:
+    """A plan plus its device workspace, reusable across solves."""
+
+    def __init__(self, d: int, N: Sequence[int], format: str = "full", rank_cap: int = 0,
+                 trunc_tol: float = 0.0, solver_tol: float = 1e-10, max_iter: int = 1000,
+                 solver: str = "pcg", precision: str = "fp64", precond_terms: int = 0,
+                 oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
+                 device: str = "cuda:0"):
+        L = lib()
+        p = _lib.Problem()
+        p.d = int(d)
+        Ns = list(N) + [1] * (3 - len(N))
+        for i in range(3):
+            p.N[i] = int(Ns[i])
+        p.format = _FORMATS[format]
+        p.rank_cap = int(rank_cap)
+        p.trunc_tol = float(trunc_tol)
+        p.solver_tol = float(solver_tol)
+        p.max_iter = int(max_iter)
+        p.solver = _SOLVERS[solver]
+        p.precision = _PRECS[precision]
+        p.precond_terms = int(precond_terms)
+        p.oversample = int(oversample)
+        p.seed = int(seed)
+        p.flags = 0
+        self.problem = p
+        self.d = int(d)
+        self.max_iter = int(max_iter)
+        self._plan = C.c_void_p()
+        check(L.lrfg_plan_create(C.byref(p), C.byref(self._plan)))
+        self.max_nE = int(max_nE or d)
+        nb = C.c_size_t()
+        check(L.lrfg_plan_workspace_bytes(self._plan, self.max_nE, C.byref(nb)))
+        self.workspace_bytes = int(nb.value)
+        self.device = device
+        self._ws = None
+
+    def workspace(self):
+        if self._ws is None:
+            torch = _torch()
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def solve(self, full=None, cp=None, tt=None, E=None, stream=None) -> SolveResult:
+        """full: nodal values; cp: (weights (R,), [factors (R, N_i)]);
+        tt: list of cores [r_{i-1}][N_i][r_i].  E: (nE, d) or None."""
+        L = lib()
+        torch = _torch()
+        h = _Held(self.device)
+        c = _lib.Coeff()
+        on_dev = 0
+        if full is not None:
+            ptr, on_dev = h.ptr(full)
+            c.full = ptr
+        elif cp is not None:
+            w, fac = cp
+            ptr, on_dev = h.ptr(w)
+            c.weights = ptr
+            c.rank = int(len(w))
+            for i, f in enumerate(fac):
+                c.factors[i] = h.ptr(f)[0]
+        elif tt is not None:
+            for i, G in enumerate(tt):
+                c.tt_cores[i], on_dev = h.ptr(G)
+                c.tt_ranks[i] = int(G.shape[0])
+            c.tt_ranks[len(tt)] = int(tt[-1].shape[2])
+        else:
+            raise ValueError("give one of full / cp / tt")
+        c.on_device = on_dev
+        d = self.d
+        if E is None:
+            nE = d
+            Eptr = None
+        else:
+            Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, d))
+            nE = Earr.shape[0]
+            h.keep.append(Earr)
+            Eptr = Earr.ctypes.data
+        A = np.zeros((nE, nE))
+        iters = np.zeros(nE, dtype=np.int32)
+        hist = np.zeros((nE, self.max_iter))
+        ranks = np.zeros((nE, d + 1), dtype=np.int32)
+        status = np.zeros(nE, dtype=np.int32)
+        r = _lib.Result()
+        r.A_H = A.ctypes.data
+        r.iters = iters.ctypes.data
+        r.res_hist = hist.ctypes.data
+        r.ranks = ranks.ctypes.data
+        r.status = status.ctypes.data
+        ws = self.workspace()
+        with torch.cuda.device(torch.device(self.device)):
+            sh = _stream_handle(stream)
+            rc = L.lrfg_solve(self._plan, C.byref(c), Eptr, nE, C.c_void_p(ws.data_ptr()),
+                              self.workspace_bytes, C.c_void_p(sh), C.byref(r))
+        check(rc, allow=(_lib.OK, _lib.NOT_CONVERGED))
+        return SolveResult(A, iters, hist, ranks, status, rc, r.setup_ms, r.solve_ms)
+
+    def close(self):
+        if self._plan:
+            lib().lrfg_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- op level
+def _ws_tensor(nbytes, device):
+    torch = _torch()
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def fft_lines(x, outer: int, N: int, inner: int, direction: int, stream=None):
+    """In-place batched 1-D DFT of a complex128 CUDA tensor viewed as
+    [outer][N][inner]; direction -1 = F_N (with 1/N), +1 = inverse."""
+    L = lib()
+    ws = _ws_tensor(L.lrfg_fft_workspace_bytes(N), x.device)
+    check(L.lrfg_fft_lines(C.c_void_p(x.data_ptr()), outer, N, inner, direction,
+                           C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream_handle(stream))))
+    return x
+
+
+def mode_op(x, outer: int, N: int, inner: int, op: int, t: float = 0.0, stream=None):
+    """In-place real circulant along the middle index of a float64 CUDA
+    tensor [outer][N][inner]: op 0 derivative, op 1 heat kernel exp(-t k^2)."""
+    L = lib()
+    ws = _ws_tensor(L.lrfg_fft_workspace_bytes(N), x.device)
+    check(L.lrfg_mode_op(C.c_void_p(x.data_ptr()), outer, N, inner, op, float(t),
+                         C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream_handle(stream))))
+    return x
+
+
+def full_op(which: int, N, a, u, out, stream=None):
+    """Full-grid K (which 0) or P^-1 (which 1) on complex128 half spectra."""
+    L = lib()
+    Nc = (C.c_int * 3)(*[int(n) for n in N])
+    ws = _ws_tensor(L.lrfg_full_op_workspace_bytes(Nc), u.device)
+    aptr = C.c_void_p(a.data_ptr()) if a is not None else None
+    check(L.lrfg_full_op(which, Nc, aptr, C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
+                         C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream_handle(stream))))
+    return out

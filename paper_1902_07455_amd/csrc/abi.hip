@@ -1,0 +1,386 @@
+// C ABI of liblrfg: validation, plans, dispatch to the solve paths and the
+// operation-level entry points.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fft.h"
+#include "full.h"
+#include "lowrank.h"
+
+namespace lrfg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace lrfg
+
+using namespace lrfg;
+
+struct lrfg_plan {
+  lrfg_problem p;
+  int N3d[3];            // full grid: internal 3-D geometry (d = 2: 1, N1, N2)
+  FftPlan axis[3];       // plans for N3d
+  FftPlan mode[3];       // plans for the user's N_i (low-rank mode transforms)
+  int* pinned = nullptr; // pinned host flags for the full-grid loop
+  int pinned_n = 0;
+  LowRankPlan* lr = nullptr;
+};
+
+namespace {
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+int validate(const lrfg_problem* p) {
+  if (p == nullptr) {
+    set_error("problem is NULL");
+    return LRFG_EINVAL;
+  }
+  if (p->d != 2 && p->d != 3) {
+    set_error("d must be 2 or 3 (got %d)", p->d);
+    return LRFG_EINVAL;
+  }
+  for (int i = 0; i < p->d; ++i) {
+    if (p->N[i] < 3 || (p->N[i] % 2) == 0) {
+      set_error("N[%d] = %d: grid sizes must be odd and >= 3", i, p->N[i]);
+      return LRFG_EINVAL;
+    }
+  }
+  if (p->format < LRFG_FORMAT_FULL || p->format > LRFG_FORMAT_TT) {
+    set_error("unknown format %d", p->format);
+    return LRFG_EINVAL;
+  }
+  if (p->format == LRFG_FORMAT_CP && p->d != 2) {
+    set_error("CP format is used for d = 2 only");
+    return LRFG_EINVAL;
+  }
+  if (p->format != LRFG_FORMAT_FULL && p->rank_cap < 1) {
+    set_error("rank_cap must be >= 1 (got %d)", p->rank_cap);
+    return LRFG_EINVAL;
+  }
+  if (!finite_nonneg(p->trunc_tol)) {
+    set_error("trunc_tol must be finite and >= 0");
+    return LRFG_EINVAL;
+  }
+  if (!(std::isfinite(p->solver_tol) && p->solver_tol > 0.0)) {
+    set_error("solver_tol must be finite and > 0");
+    return LRFG_EINVAL;
+  }
+  if (p->max_iter < 1) {
+    set_error("max_iter must be >= 1");
+    return LRFG_EINVAL;
+  }
+  if (p->solver != LRFG_SOLVER_PCG && p->solver != LRFG_SOLVER_MR) {
+    set_error("unknown solver %d", p->solver);
+    return LRFG_EINVAL;
+  }
+  if (p->precision < LRFG_PREC_FP64 || p->precision > LRFG_PREC_MIXED_BF16) {
+    set_error("unknown precision %d", p->precision);
+    return LRFG_EINVAL;
+  }
+  if (p->precond_terms < 0 || p->precond_terms == 1 || p->oversample < 0) {
+    set_error("precond_terms must be 0 or >= 2; oversample >= 0");
+    return LRFG_EINVAL;
+  }
+  if (p->flags != 0) {
+    set_error("flags must be 0");
+    return LRFG_EINVAL;
+  }
+  if (p->format == LRFG_FORMAT_FULL && p->precision != LRFG_PREC_FP64) {
+    set_error("the full-grid path runs in FP64 only");
+    return LRFG_EUNSUPPORTED;
+  }
+  if (p->format == LRFG_FORMAT_FULL && p->solver != LRFG_SOLVER_PCG) {
+    set_error("the full-grid path uses PCG");
+    return LRFG_EUNSUPPORTED;
+  }
+  return LRFG_OK;
+}
+
+int device_ok() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return LRFG_EDEVICE;
+  }
+  return LRFG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lrfg_abi_version(void) { return LRFG_ABI_VERSION; }
+
+const char* lrfg_status_string(int s) {
+  switch (s) {
+    case LRFG_OK: return "ok";
+    case LRFG_NOT_CONVERGED: return "not converged (A_H written)";
+    case LRFG_EINVAL: return "invalid argument";
+    case LRFG_ECOEFF: return "coefficient not finite and positive";
+    case LRFG_EWORKSPACE: return "workspace too small or misaligned";
+    case LRFG_EDEVICE: return "HIP device error or no device";
+    case LRFG_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+const char* lrfg_last_error(void) { return g_last_error.c_str(); }
+
+int lrfg_device_check(void) {
+  clear_error();
+  return device_ok();
+}
+
+int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
+  clear_error();
+  if (out == nullptr) {
+    set_error("out is NULL");
+    return LRFG_EINVAL;
+  }
+  *out = nullptr;
+  LRFG_TRY(validate(p));
+  lrfg_plan* pl = new lrfg_plan();
+  pl->p = *p;
+  if (p->d == 3) {
+    pl->N3d[0] = p->N[0];
+    pl->N3d[1] = p->N[1];
+    pl->N3d[2] = p->N[2];
+  } else {
+    pl->N3d[0] = 1;
+    pl->N3d[1] = p->N[0];
+    pl->N3d[2] = p->N[1];
+  }
+  for (int i = 0; i < 3; ++i) {
+    int rc = fft_plan_make(pl->N3d[i], &pl->axis[i]);
+    if (rc != LRFG_OK) {
+      delete pl;
+      return rc;
+    }
+  }
+  for (int i = 0; i < p->d; ++i) {
+    int rc = fft_plan_make(p->N[i], &pl->mode[i]);
+    if (rc != LRFG_OK) {
+      delete pl;
+      return rc;
+    }
+  }
+  if (p->format != LRFG_FORMAT_FULL) {
+    int rc = lowrank_plan_create(*p, pl->mode, &pl->lr);
+    if (rc != LRFG_OK) {
+      delete pl;
+      return rc;
+    }
+  }
+  *out = pl;
+  return LRFG_OK;
+}
+
+int lrfg_plan_workspace_bytes(const lrfg_plan* plan, int max_nE, size_t* bytes) {
+  clear_error();
+  if (plan == nullptr || bytes == nullptr || max_nE < 1) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  const lrfg_problem& p = plan->p;
+  if (p.format == LRFG_FORMAT_FULL) {
+    *bytes = full_workspace_bytes(plan->N3d, max_nE, p.d, p.max_iter) + coeff_staging_bytes(p);
+  } else {
+    *bytes = lowrank_workspace_bytes(plan->lr, max_nE);
+  }
+  return LRFG_OK;
+}
+
+void lrfg_plan_destroy(lrfg_plan* plan) {
+  if (plan == nullptr) return;
+  if (plan->pinned) (void)hipHostFree(plan->pinned);
+  lowrank_plan_destroy(plan->lr);
+  delete plan;
+}
+
+int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* d_ws,
+               size_t ws_bytes, void* stream, lrfg_result* out) {
+  clear_error();
+  if (plan == nullptr || a == nullptr || out == nullptr) {
+    set_error("plan, coefficient and result must be non-NULL");
+    return LRFG_EINVAL;
+  }
+  const lrfg_problem& p = plan->p;
+  if (E == nullptr && nE != p.d) {
+    set_error("E = NULL means the canonical basis: nE must equal d");
+    return LRFG_EINVAL;
+  }
+  if (nE < 1 || nE > 3) {
+    set_error("nE must be in [1, 3]");
+    return LRFG_EINVAL;
+  }
+  if (d_ws == nullptr || (reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) {
+    set_error("workspace must be non-NULL and 256-byte aligned");
+    return LRFG_EWORKSPACE;
+  }
+  size_t need = 0;
+  LRFG_TRY(lrfg_plan_workspace_bytes(plan, nE, &need));
+  if (ws_bytes < need) {
+    set_error("workspace too small: need %zu bytes, have %zu", need, ws_bytes);
+    return LRFG_EWORKSPACE;
+  }
+  int nsrc = (a->full != nullptr) + (a->weights != nullptr) + (a->tt_cores[0] != nullptr);
+  if (nsrc != 1) {
+    set_error("exactly one of full / weights / tt_cores must be given");
+    return LRFG_EINVAL;
+  }
+  LRFG_TRY(device_ok());
+  std::vector<double> Ebuf;
+  if (E == nullptr) {
+    Ebuf.assign(p.d * p.d, 0.0);
+    for (int i = 0; i < p.d; ++i) Ebuf[i * p.d + i] = 1.0;
+    E = Ebuf.data();
+  }
+  for (int i = 0; i < nE * p.d; ++i) {
+    if (!std::isfinite(E[i])) {
+      set_error("E must be finite");
+      return LRFG_EINVAL;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p.format == LRFG_FORMAT_FULL) {
+    if (plan->pinned == nullptr) {
+      LRFG_HIP(hipHostMalloc((void**)&plan->pinned, sizeof(int) * 4 * 3, hipHostMallocDefault));
+      plan->pinned_n = 12;
+    }
+    // Coefficient on the device as a full field (CP / TT forms expanded).
+    const double* afull = nullptr;
+    int on_dev = a->on_device;
+    char* wsc = static_cast<char*>(d_ws);
+    const size_t stage = coeff_staging_bytes(p);
+    const size_t full_need = need - stage;
+    if (a->full != nullptr) {
+      afull = a->full;
+    } else {
+      double* dst = reinterpret_cast<double*>(wsc + full_need);
+      LRFG_TRY(expand_coeff(p, *a, dst, stage, s));
+      afull = dst;
+      on_dev = 1;
+    }
+    FullSolveArgs fa;
+    fa.d = p.d;
+    for (int i = 0; i < 3; ++i) fa.N[i] = p.N[i];
+    fa.plan1 = &plan->axis[0];
+    fa.plan2 = &plan->axis[1];
+    fa.plan3 = &plan->axis[2];
+    fa.a = afull;
+    fa.a_on_device = on_dev;
+    fa.E = E;
+    fa.nE = nE;
+    fa.tol = p.solver_tol;
+    fa.max_iter = p.max_iter;
+    fa.ws = d_ws;
+    fa.ws_bytes = full_need;
+    fa.stream = stream;
+    fa.pinned_flags = plan->pinned;
+    FullSolveOut fo;
+    fo.A_H = out->A_H;
+    fo.iters = out->iters;
+    fo.res_hist = out->res_hist;
+    fo.status = out->status;
+    const int rc = full_solve(fa, &fo);
+    out->setup_ms = fo.setup_ms;
+    out->solve_ms = fo.solve_ms;
+    return rc;
+  }
+  return lowrank_solve(plan->lr, *a, E, nE, d_ws, ws_bytes, s, out);
+}
+
+size_t lrfg_fft_workspace_bytes(int N) { return sizeof(double2) * (size_t)(N > 0 ? N : 1) + 256; }
+
+int lrfg_fft_lines(double* x, int outer, int N, int inner, int direction, void* d_ws, size_t ws_bytes,
+                   void* stream) {
+  clear_error();
+  if (x == nullptr || outer < 0 || inner < 1 || (direction != -1 && direction != 1)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  if (N < 1 || N % 2 == 0) {
+    set_error("odd N only");
+    return LRFG_EINVAL;
+  }
+  if (d_ws == nullptr || ws_bytes < lrfg_fft_workspace_bytes(N)) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  const FftPlan* pl = fft_plan_cached(N);
+  if (pl == nullptr) return LRFG_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FftDev f;
+  LRFG_TRY(fft_dev_upload(*pl, static_cast<double2*>(d_ws), s, &f));
+  return launch_fft_lines(reinterpret_cast<double2*>(x), outer, N, inner, direction, f,
+                          direction < 0 ? 1.0 / N : 1.0, s);
+}
+
+int lrfg_mode_op(double* x, int outer, int N, int inner, int op, double t, void* d_ws, size_t ws_bytes,
+                 void* stream) {
+  clear_error();
+  if (x == nullptr || outer < 0 || inner < 1 || (op != 0 && op != 1) || !std::isfinite(t)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  if (N < 1 || N % 2 == 0) {
+    set_error("odd N only");
+    return LRFG_EINVAL;
+  }
+  if (d_ws == nullptr || ws_bytes < lrfg_fft_workspace_bytes(N)) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  const FftPlan* pl = fft_plan_cached(N);
+  if (pl == nullptr) return LRFG_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FftDev f;
+  LRFG_TRY(fft_dev_upload(*pl, static_cast<double2*>(d_ws), s, &f));
+  return launch_mode_op(x, outer, N, inner, op, t, f, s);
+}
+
+size_t lrfg_full_op_workspace_bytes(const int N[3]) { return full_op_workspace_bytes(N); }
+
+int lrfg_full_op(int which, const int N[3], const double* a, const double* u, double* outp, void* d_ws,
+                 size_t ws_bytes, void* stream) {
+  clear_error();
+  if (N == nullptr || u == nullptr || outp == nullptr || (which != 0 && which != 1) ||
+      (which == 0 && a == nullptr)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i) {
+    if (N[i] < 1 || N[i] % 2 == 0) {
+      set_error("odd N only");
+      return LRFG_EINVAL;
+    }
+  }
+  if (d_ws == nullptr || ws_bytes < full_op_workspace_bytes(N)) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  const FftPlan* p1 = fft_plan_cached(N[0]);
+  const FftPlan* p2 = fft_plan_cached(N[1]);
+  const FftPlan* p3 = fft_plan_cached(N[2]);
+  if (!p1 || !p2 || !p3) return LRFG_EINVAL;
+  return full_op(which, N, p1, p2, p3, a, u, outp, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

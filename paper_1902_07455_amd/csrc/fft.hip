@@ -1,0 +1,184 @@
+// Host-side FFT plans and the generic batched line kernels
+// (lrfg_fft_lines, lrfg_mode_op).
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "fft.h"
+
+namespace lrfg {
+
+int fft_plan_make(int N, FftPlan* out) {
+  if (N < 1 || (N % 2) == 0) {
+    set_error("FFT length %d: odd lengths only", N);
+    return LRFG_EINVAL;
+  }
+  FftPlan p;
+  p.N = N;
+  int n = N;
+  // radix order: 5s, then 3s, then the remaining odd primes ascending
+  const int pref[2] = {5, 3};
+  for (int r : pref) {
+    while (n % r == 0) {
+      p.radix[p.nstage++] = r;
+      n /= r;
+    }
+  }
+  for (int f = 7; n > 1; f += 2) {
+    while (n % f == 0) {
+      if (p.nstage >= kMaxStages) {
+        set_error("FFT length %d: too many factors", N);
+        return LRFG_EINVAL;
+      }
+      p.radix[p.nstage++] = f;
+      n /= f;
+    }
+    if ((long long)f * f > n && n > 1) {
+      p.radix[p.nstage++] = n;  // remaining prime
+      n = 1;
+    }
+  }
+  p.table.resize(N);
+  for (int i = 0; i < N; ++i) {
+    // exp(-2 pi i i/N) in extended precision, rounded once to double
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)i / (long double)N;
+    p.table[i] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+  *out = std::move(p);
+  return LRFG_OK;
+}
+
+const FftPlan* fft_plan_cached(int N) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<FftPlan>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(N);
+  if (it != cache.end()) return it->second.get();
+  std::unique_ptr<FftPlan> p(new FftPlan());
+  if (fft_plan_make(N, p.get()) != LRFG_OK) return nullptr;
+  const FftPlan* raw = p.get();
+  cache[N] = std::move(p);
+  return raw;
+}
+
+// ---------------------------------------------------------------- kernels
+// Tile = T consecutive line ids of the view x[outer][N][inner]; line id
+// l = o*inner + i.  Elements of a tile are loaded so that consecutive
+// threads touch consecutive addresses.
+__device__ inline long long line_addr(long long l, int n, int N, int inner) {
+  const long long o = l / inner;
+  const long long i = l - o * inner;
+  return (o * N + n) * (long long)inner + i;
+}
+
+template <int DIR>
+__global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner, int T,
+                            FftDev f, double scale) {
+  extern __shared__ double2 sm[];
+  const int N = f.N;
+  double2* a = sm;
+  double2* b = sm + T * N;
+  const long long l0 = (long long)blockIdx.x * T;
+  const int tcount = (int)min((long long)T, nlines - l0);
+  const int total = T * N;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    a[t * N + n] = (t < tcount) ? x[line_addr(l0 + t, n, N, inner)] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double2* r = lds_fft<DIR>(a, b, T, f);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    if (t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(r[t * N + n], scale);
+  }
+}
+
+// Real circulant along the mode index: two real fibres packed into one
+// complex line (the operator is real, so it acts on real and imaginary
+// parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2).
+__global__ void k_mode_op(double* __restrict__ x, long long nfib, int inner, int T, FftDev f,
+                          int op, double tparam) {
+  extern __shared__ double2 sm[];
+  const int N = f.N;
+  double2* a = sm;
+  double2* b = sm + T * N;
+  const long long f0 = (long long)blockIdx.x * (2 * T);
+  const int total = T * N;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    const long long fa = f0 + 2 * t, fb = fa + 1;
+    const double re = (fa < nfib) ? x[line_addr(fa, n, N, inner)] : 0.0;
+    const double im = (fb < nfib) ? x[line_addr(fb, n, N, inner)] : 0.0;
+    a[t * N + n] = make_double2(re, im);
+  }
+  __syncthreads();
+  double2* r = lds_fft<-1>(a, b, T, f);
+  double2* o = (r == a) ? b : a;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int n = idx % N;
+    const int k = freq_of(n, N);
+    double2 v = r[idx];
+    if (op == 0) {
+      v = cmul_i(v, 2.0 * kPi * (double)k / (double)N);
+    } else {
+      v = cscale(v, exp(-tparam * (double)k * (double)k) / (double)N);
+    }
+    r[idx] = v;
+  }
+  __syncthreads();
+  double2* s = lds_fft<1>(r, o, T, f);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    const long long fa = f0 + 2 * t, fb = fa + 1;
+    const double2 v = s[t * N + n];
+    if (fa < nfib) x[line_addr(fa, n, N, inner)] = v.x;
+    if (fb < nfib) x[line_addr(fb, n, N, inner)] = v.y;
+  }
+}
+
+int fft_dev_upload(const FftPlan& p, double2* d_table, hipStream_t s, FftDev* out) {
+  LRFG_HIP(hipMemcpyAsync(d_table, p.table.data(), sizeof(double2) * p.N, hipMemcpyHostToDevice, s));
+  FftDev f;
+  f.N = p.N;
+  f.nstage = p.nstage;
+  for (int i = 0; i < kMaxStages; ++i) f.radix[i] = p.radix[i];
+  f.tw = d_table;
+  *out = f;
+  return LRFG_OK;
+}
+
+int launch_fft_lines(double2* x, long long outer, int N, long long inner, int dir, const FftDev& f,
+                     double scale, hipStream_t s) {
+  const long long nlines = outer * inner;
+  if (nlines == 0) return LRFG_OK;
+  const int T = lines_per_tile(N);
+  const size_t shm = size_t(2) * T * N * sizeof(double2);
+  const int grid = ceil_div(nlines, T);
+  if (dir < 0) {
+    hipLaunchKernelGGL(k_fft_lines<-1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale);
+  } else {
+    hipLaunchKernelGGL(k_fft_lines<1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale);
+  }
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t,
+                   const FftDev& f, hipStream_t s) {
+  const long long nfib = outer * inner;
+  if (nfib == 0) return LRFG_OK;
+  const int T = lines_per_tile(N);
+  const size_t shm = size_t(2) * T * N * sizeof(double2);
+  const int grid = ceil_div(nfib, 2 * T);
+  hipLaunchKernelGGL(k_mode_op, dim3(grid), dim3(256), shm, s, x, nfib, (int)inner, T, f, op, t);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+}  // namespace lrfg

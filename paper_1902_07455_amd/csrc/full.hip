@@ -1,0 +1,875 @@
+// Full-grid GaNi solve: preconditioned CG on the Fourier-space system
+//   K u^ = b^,  K = grad*^ F a F^-1 grad^,  b^ = -grad*^ F (a E)
+// (paper Sec. 2.2.2, eq. ls_GaNi_fourier), preconditioner P^-1 = the
+// pseudo-inverse of the Fourier Laplacian 4 pi^2 k.k (Sec. 2.3,
+// eq. Pls_GaNi_fourier), A_H from the energy form of eq. (homog).
+//
+// Storage: real fields [N1][N2][N3] (FP64), Fourier fields as the half
+// spectrum [N1][N2][H] (H = (N3+1)/2 complex; odd N3 has no Nyquist plane),
+// the other half given by Hermitian symmetry.  A d = 2 problem is stored as
+// N1 = 1.
+//
+// One matvec q = K p for all right-hand sides is five LDS-FFT passes:
+//   P1 axis 1, inverse, prologue x 2 pi i k_alpha (one output per alpha)
+//   P2 axis 2, inverse, in place
+//   P3 axis 3: C2R, x a, R2C in one pass (two real lines per complex FFT)
+//   P4 axis 2, forward, in place
+//   P5 axis 1, forward, sum_alpha -2 pi i k_alpha (.), 1/|N| scale, and the
+//      partial sums of (p, q) for the CG step length
+// followed by two CG vector kernels.  All CG scalars stay on the device;
+// converged systems are skipped by a device flag.
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "fft.h"
+#include "full.h"
+
+namespace lrfg {
+
+int launch_pinv(const double2* u, double2* o, int N1, int N2, int N3, hipStream_t s);
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPer = 16;  // P5 accumulator entries per thread: T1*N1 <= kMaxPer*kBlock
+
+struct G3 {
+  int N1, N2, N3, H;
+  long long S;  // complex entries of a half spectrum
+  long long R;  // real entries
+};
+
+__device__ inline long long addr3(long long l, int n, int N, long long inner) {
+  const long long o = l / inner;
+  const long long i = l - o * inner;
+  return (o * N + n) * inner + i;
+}
+
+// Frequencies of half-spectrum entry (n1, n2, h).
+__device__ inline void kvec(const G3& g, int n1, int n2, int h, double k[3]) {
+  k[0] = (double)freq_of(n1, g.N1);
+  k[1] = (double)freq_of(n2, g.N2);
+  k[2] = (double)h;
+}
+
+__device__ inline double pinv_of(const double k[3]) {
+  const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  return kk > 0.0 ? 1.0 / (4.0 * kPi * kPi * kk) : 0.0;
+}
+
+// ---------------------------------------------------------------- P1
+// dst[e][a] = F^-1_axis1 ( 2 pi i k_alpha src[e] ),  alpha = alpha0 + a.
+// grid.x = tiles * nalpha (alpha fastest, so the tiles of one src share L2),
+// grid.y = e.
+__global__ void k_grad_axis1(const double2* __restrict__ src, double2* __restrict__ dst, G3 g,
+                             int alpha0, int nalpha, long long dst_stride_e, long long dst_stride_a,
+                             int T, FftDev f, const int* __restrict__ done) {
+  extern __shared__ double2 sm[];
+  const int e = blockIdx.y;
+  if (done != nullptr && done[e]) return;
+  const int a = blockIdx.x % nalpha;
+  const int tile = blockIdx.x / nalpha;
+  const int alpha = alpha0 + a;
+  const int N = g.N1;
+  const long long inner = (long long)g.N2 * g.H;
+  const long long l0 = (long long)tile * T;
+  const int tcount = (int)min((long long)T, inner - l0);
+  const double2* s = src + (long long)e * g.S;
+  double2* d = dst + e * dst_stride_e + a * dst_stride_a;
+  double2* A = sm;
+  double2* B = sm + T * N;
+  const int total = T * N;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int t = idx % T, n = idx / T;
+    double2 v = make_double2(0.0, 0.0);
+    if (t < tcount) {
+      const long long i = l0 + t;
+      v = s[(long long)n * inner + i];
+      double kk;
+      if (alpha == 0) kk = (double)freq_of(n, g.N1);
+      else if (alpha == 1) kk = (double)freq_of((int)(i / g.H), g.N2);
+      else kk = (double)(i % g.H);
+      v = cmul_i(v, 2.0 * kPi * kk);
+    }
+    A[t * N + n] = v;
+  }
+  __syncthreads();
+  double2* r = lds_fft<1>(A, B, T, f);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int t = idx % T, n = idx / T;
+    if (t < tcount) d[(long long)n * inner + l0 + t] = r[t * N + n];
+  }
+}
+
+// ---------------------------------------------------------------- P5
+// q[e] = (1/|N|) sum_alpha -2 pi i k_alpha F_axis1(t[e][alpha]); also the
+// partial sums of (p[e], q[e]) (Hermitian weights: 1 on h = 0, else 2).
+__global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
+                            const double2* __restrict__ p, G3 g, int alpha0, int nalpha,
+                            double inv_vol, int T, FftDev f, const int* __restrict__ done,
+                            double* __restrict__ part_pq) {
+  extern __shared__ double2 sm[];
+  __shared__ double red[kBlock / 64];
+  const int e = blockIdx.y;
+  if (done[e]) return;
+  const int N = g.N1;
+  const long long inner = (long long)g.N2 * g.H;
+  const long long l0 = (long long)blockIdx.x * T;
+  const int tcount = (int)min((long long)T, inner - l0);
+  double2* A = sm;
+  double2* B = sm + T * N;
+  const int total = T * N;
+  double2 acc[kMaxPer];
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int a = 0; a < nalpha; ++a) {
+    const int alpha = alpha0 + a;
+    const double2* s = t + ((long long)e * nalpha + a) * g.S;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int tt = idx % T, n = idx / T;
+      A[tt * N + n] = (tt < tcount) ? s[(long long)n * inner + l0 + tt] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2* r = lds_fft<-1>(A, B, T, f);
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+      const int idx = threadIdx.x + j * kBlock;
+      if (idx < total) {
+        const int tt = idx % T, n = idx / T;
+        const long long i = l0 + tt;
+        double kk;
+        if (alpha == 0) kk = (double)freq_of(n, g.N1);
+        else if (alpha == 1) kk = (double)freq_of((int)(i / g.H), g.N2);
+        else kk = (double)(i % g.H);
+        const double2 v = r[tt * N + n];
+        const double c = -2.0 * kPi * kk * inv_vol;
+        acc[j].x += -v.y * c;
+        acc[j].y += v.x * c;
+      }
+    }
+    __syncthreads();
+  }
+  double pq = 0.0;
+  const double2* pe = p + (long long)e * g.S;
+  double2* qe = q + (long long)e * g.S;
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) {
+    const int idx = threadIdx.x + j * kBlock;
+    const int tt = idx % T, n = idx / T;
+    if (idx < total && tt < tcount) {
+      const long long i = l0 + tt;
+      const long long ad = (long long)n * inner + i;
+      qe[ad] = acc[j];
+      const double2 pv = pe[ad];
+      const double w = (i % g.H) == 0 ? 1.0 : 2.0;
+      pq += w * (pv.x * acc[j].x + pv.y * acc[j].y);
+    }
+  }
+  const double s = block_sum(pq, red);
+  if (threadIdx.x == 0) part_pq[(long long)e * gridDim.x + blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- P3 / axis 3
+// MODE 0: in place  X <- R2C( a . C2R(X) )        (material law)
+// MODE 1: real src -> half spectrum dst (R2C, scale)
+// MODE 2: half spectrum src -> real dst (C2R)
+// Two real lines (l0, l0+1) share one complex FFT.  grid.x = pair tiles,
+// grid.y = array index b (array b at src + b*src_stride, dst likewise),
+// done index = b / done_div.
+template <int MODE>
+__global__ void k_axis3(const void* __restrict__ src_, void* __restrict__ dst_,
+                        const double* __restrict__ acoef, G3 g, long long src_stride,
+                        long long dst_stride, int T, FftDev f, double scale,
+                        const int* __restrict__ done, int done_div) {
+  extern __shared__ double2 sm[];
+  const int b = blockIdx.y;
+  if (done != nullptr && done[b / done_div]) return;
+  const int N = g.N3, H = g.H;
+  const long long nl = (long long)g.N1 * g.N2;
+  const long long p0 = (long long)blockIdx.x * T;      // first pair
+  double2* A = sm;
+  double2* B = sm + T * N;
+  const int total = T * N;
+  // load
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int n = idx % N, t = idx / N;
+    const long long la = 2 * (p0 + t), lb = la + 1;
+    double2 z = make_double2(0.0, 0.0);
+    if (MODE == 1) {
+      const double* s = static_cast<const double*>(src_) + b * src_stride;
+      const double xa = la < nl ? s[la * N + n] : 0.0;
+      const double xb = lb < nl ? s[lb * N + n] : 0.0;
+      z = make_double2(xa, xb);
+    } else {
+      const double2* s = static_cast<const double2*>(src_) + b * src_stride;
+      const int m = n < H ? n : N - n;
+      const bool cj = n >= H;
+      double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
+      if (la < nl) xa = s[la * H + m];
+      if (lb < nl) xb = s[lb * H + m];
+      if (cj) { xa.y = -xa.y; xb.y = -xb.y; }
+      z = make_double2(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+    }
+    A[t * N + n] = z;
+  }
+  __syncthreads();
+  double2* r = A;
+  if (MODE != 1) {
+    r = lds_fft<1>(A, B, T, f);
+    if (MODE == 2) {
+      double* d = static_cast<double*>(dst_) + b * dst_stride;
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int n = idx % N, t = idx / N;
+        const long long la = 2 * (p0 + t), lb = la + 1;
+        const double2 v = r[t * N + n];
+        if (la < nl) d[la * N + n] = v.x * scale;
+        if (lb < nl) d[lb * N + n] = v.y * scale;
+      }
+      return;
+    }
+    // multiply real parts by the two coefficient lines
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int n = idx % N, t = idx / N;
+      const long long la = 2 * (p0 + t), lb = la + 1;
+      const double aa = la < nl ? acoef[la * N + n] : 0.0;
+      const double ab = lb < nl ? acoef[lb * N + n] : 0.0;
+      const double2 v = r[t * N + n];
+      r[t * N + n] = make_double2(v.x * aa, v.y * ab);
+    }
+    __syncthreads();
+  }
+  double2* o = (r == A) ? B : A;
+  double2* w = lds_fft<-1>(r, o, T, f);
+  // separate the two Hermitian spectra and store h in [0, H)
+  double2* d = static_cast<double2*>(MODE == 0 ? const_cast<void*>(src_) : dst_) +
+               b * (MODE == 0 ? src_stride : dst_stride);
+  const int htot = T * H;
+  for (int idx = threadIdx.x; idx < htot; idx += blockDim.x) {
+    const int h = idx % H, t = idx / H;
+    const long long la = 2 * (p0 + t), lb = la + 1;
+    const double2 W1 = w[t * N + h];
+    const double2 W2 = w[t * N + (h == 0 ? 0 : N - h)];
+    // Xa = (W1 + conj W2)/2, Xb = (W1 - conj W2)/(2i)
+    const double2 xa = make_double2(0.5 * (W1.x + W2.x), 0.5 * (W1.y - W2.y));
+    const double2 dd = make_double2(W1.x - W2.x, W1.y + W2.y);
+    const double2 xb = make_double2(0.5 * dd.y, -0.5 * dd.x);
+    if (la < nl) d[la * H + h] = cscale(xa, scale);
+    if (lb < nl) d[lb * H + h] = cscale(xb, scale);
+  }
+}
+
+// ---------------------------------------------------------------- CG kernels
+struct CgState {
+  double rho[2];
+  double z0;
+  double floor_abs;
+  double pq;
+  double alpha;
+  double res;
+  int done;     // 0 running, 1 converged/zero rhs, 2 breakdown
+  int iters;
+};
+
+__device__ inline void decode(const G3& g, long long s, int& n1, int& n2, int& h) {
+  h = (int)(s % g.H);
+  const long long r = s / g.H;
+  n2 = (int)(r % g.N2);
+  n1 = (int)(r / g.N2);
+}
+
+// Sum of part[0..n) by one block, same order in every block; result broadcast.
+__device__ inline double block_reduce_array(const double* __restrict__ part, int n, double* red,
+                                            double* bcast) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) *bcast = s;
+  __syncthreads();
+  return *bcast;
+}
+
+// r = b^ = 2 pi i (k.E_e) a^ ; x = 0 ; z = P^-1 r ; p = z ; partial (r,z), (z,z)
+__global__ void k_cg_init(const double2* __restrict__ ahat, const double* __restrict__ E3, G3 g,
+                          double2* __restrict__ x, double2* __restrict__ r, double2* __restrict__ p,
+                          double* __restrict__ part_rz, double* __restrict__ part_zz) {
+  __shared__ double red[kBlock / 64];
+  const int e = blockIdx.y;
+  const double* E = E3 + 3 * e;
+  double rz = 0.0, zz = 0.0;
+  const long long off = (long long)e * g.S;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    double k[3];
+    kvec(g, n1, n2, h, k);
+    const double ke = k[0] * E[0] + k[1] * E[1] + k[2] * E[2];
+    const double2 rv = cmul_i(ahat[s], 2.0 * kPi * ke);
+    const double pi = pinv_of(k);
+    const double2 zv = cscale(rv, pi);
+    x[off + s] = make_double2(0.0, 0.0);
+    r[off + s] = rv;
+    p[off + s] = zv;
+    const double w = h == 0 ? 1.0 : 2.0;
+    rz += w * (rv.x * zv.x + rv.y * zv.y);
+    zz += w * (zv.x * zv.x + zv.y * zv.y);
+  }
+  const double a = block_sum(rz, red);
+  const double b = block_sum(zz, red);
+  if (threadIdx.x == 0) {
+    part_rz[(long long)e * gridDim.x + blockIdx.x] = a;
+    part_zz[(long long)e * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+__global__ void k_cg_init2(CgState* st, int* done, const double* __restrict__ part_rz,
+                           const double* __restrict__ part_zz, int nparts,
+                           const double* __restrict__ floor_abs) {
+  __shared__ double red[kBlock / 64];
+  __shared__ double bc;
+  const int e = blockIdx.x;
+  const double rz = block_reduce_array(part_rz + (long long)e * nparts, nparts, red, &bc);
+  const double zz = block_reduce_array(part_zz + (long long)e * nparts, nparts, red, &bc);
+  if (threadIdx.x == 0) {
+    CgState s;
+    s.rho[0] = rz;
+    s.rho[1] = 0.0;
+    s.z0 = sqrt(zz);
+    s.floor_abs = floor_abs[e];
+    s.pq = 0.0;
+    s.alpha = 0.0;
+    s.res = 1.0;
+    s.iters = 0;
+    s.done = (s.z0 <= s.floor_abs) ? 1 : 0;
+    st[e] = s;
+    done[e] = s.done;
+  }
+}
+
+// x += alpha p ; r -= alpha q ; partial (r, P^-1 r), (P^-1 r, P^-1 r)
+__global__ void k_cg_update1(CgState* st, int* done, G3 g, int it, const double* __restrict__ part_pq,
+                             int npq, double2* __restrict__ x, double2* __restrict__ r,
+                             const double2* __restrict__ p, const double2* __restrict__ q,
+                             double* __restrict__ part_rz, double* __restrict__ part_zz) {
+  __shared__ double red[kBlock / 64];
+  __shared__ double bc;
+  const int e = blockIdx.y;
+  if (done[e]) return;
+  const double pq = block_reduce_array(part_pq + (long long)e * npq, npq, red, &bc);
+  const double rho = st[e].rho[it & 1];
+  const double alpha = rho / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[e].pq = pq;
+    st[e].alpha = alpha;
+  }
+  const long long off = (long long)e * g.S;
+  double rz = 0.0, zz = 0.0;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    double k[3];
+    kvec(g, n1, n2, h, k);
+    const double2 pv = p[off + s], qv = q[off + s];
+    double2 xv = x[off + s], rv = r[off + s];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    x[off + s] = xv;
+    r[off + s] = rv;
+    const double2 zv = cscale(rv, pinv_of(k));
+    const double w = h == 0 ? 1.0 : 2.0;
+    rz += w * (rv.x * zv.x + rv.y * zv.y);
+    zz += w * (zv.x * zv.x + zv.y * zv.y);
+  }
+  const double a = block_sum(rz, red);
+  const double b = block_sum(zz, red);
+  if (threadIdx.x == 0) {
+    part_rz[(long long)e * gridDim.x + blockIdx.x] = a;
+    part_zz[(long long)e * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// p = P^-1 r + beta p ; convergence test ; residual history
+__global__ void k_cg_update2(CgState* st, int* done, G3 g, int it, const double* __restrict__ part_rz,
+                             const double* __restrict__ part_zz, int nparts, const double2* __restrict__ r,
+                             double2* __restrict__ p, double tol, double* __restrict__ hist,
+                             int max_iter) {
+  __shared__ double red[kBlock / 64];
+  __shared__ double bc;
+  const int e = blockIdx.y;
+  if (done[e]) return;
+  const double rz = block_reduce_array(part_rz + (long long)e * nparts, nparts, red, &bc);
+  const double zz = block_reduce_array(part_zz + (long long)e * nparts, nparts, red, &bc);
+  const double rho = st[e].rho[it & 1];
+  const double beta = rz / rho;
+  const long long off = (long long)e * g.S;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    double k[3];
+    kvec(g, n1, n2, h, k);
+    const double2 zv = cscale(r[off + s], pinv_of(k));
+    double2 pv = p[off + s];
+    pv.x = zv.x + beta * pv.x;
+    pv.y = zv.y + beta * pv.y;
+    p[off + s] = pv;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double zn = sqrt(zz);
+    const double res = zn / st[e].z0;
+    st[e].rho[(it + 1) & 1] = rz;
+    st[e].res = res;
+    st[e].iters = it + 1;
+    if (hist != nullptr && it < max_iter) hist[(long long)e * max_iter + it] = res;
+    if (!(st[e].pq > 0.0)) done[e] = 2;
+    else if (res <= tol || zn <= st[e].floor_abs) done[e] = 1;
+  }
+}
+
+// Partial sums of a and a^2 over the real grid.
+__global__ void k_coef_stats(const double* __restrict__ a, long long n, double* __restrict__ part,
+                             int* __restrict__ bad) {
+  __shared__ double red[kBlock / 64];
+  double s1 = 0.0, s2 = 0.0;
+  int nb = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = a[i];
+    if (!(v > 0.0) || !isfinite(v)) nb = 1;
+    s1 += v;
+    s2 += v * v;
+  }
+  if (nb) atomicOr(bad, 1);
+  const double x = block_sum(s1, red);
+  const double y = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = x;
+    part[2 * blockIdx.x + 1] = y;
+  }
+}
+
+// Per-block partial sums for A_H at one alpha: sum a g_e (nE values) and
+// sum a g_i g_j (i <= j), real fields g_e at g + e*gstride.
+__global__ void k_ah_reduce(const double* __restrict__ a, const double* __restrict__ gf,
+                            long long gstride, int nE, long long n, double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const int nv = nE + nE * (nE + 1) / 2;
+  double acc[3 + 6];
+  for (int v = 0; v < nv; ++v) acc[v] = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double av = a[i];
+    double gv[3];
+    for (int e = 0; e < nE; ++e) gv[e] = gf[e * gstride + i];
+    int v = 0;
+    for (int e = 0; e < nE; ++e) acc[v++] += av * gv[e];
+    for (int ii = 0; ii < nE; ++ii)
+      for (int jj = ii; jj < nE; ++jj) acc[v++] += av * gv[ii] * gv[jj];
+  }
+  for (int v = 0; v < nv; ++v) {
+    const double s = block_sum(acc[v], red);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * nv + v] = s;
+  }
+}
+
+}  // namespace
+
+// ====================================================================== host
+struct FullLayout {
+  G3 g;
+  int nE;
+  double2 *tw1, *tw2, *tw3;
+  double* a;       // real coefficient
+  double2 *x, *r, *p, *q, *t;
+  double* part_pq;
+  double* part_rz;
+  double* part_zz;
+  double* part_misc;
+  double* floor_abs;
+  double* E3;
+  CgState* st;
+  int* done;
+  int* bad;
+  double* hist;
+  int grid_vec;   // blocks of the vector kernels
+  int tiles1;     // axis-1 tiles
+  int T1, T3;
+  int nstat;      // blocks of coef stats / ah reduce
+};
+
+static int tile1_lines(int N1) {
+  int T = lines_per_tile(N1);
+  while (T > 1 && T * N1 > kMaxPer * kBlock) --T;
+  return T;
+}
+
+static G3 make_g3(const int N[3]) {
+  G3 g;
+  g.N1 = N[0];
+  g.N2 = N[1];
+  g.N3 = N[2];
+  g.H = (N[2] + 1) / 2;
+  g.S = (long long)g.N1 * g.N2 * g.H;
+  g.R = (long long)g.N1 * g.N2 * g.N3;
+  return g;
+}
+
+static void carve(Arena& ar, FullLayout& L, const int N3d[3], int nE, int d, int max_iter) {
+  L.g = make_g3(N3d);
+  L.nE = nE;
+  const G3& g = L.g;
+  L.T1 = tile1_lines(g.N1);
+  L.T3 = lines_per_tile(g.N3);
+  L.tiles1 = ceil_div((long long)g.N2 * g.H, L.T1);
+  long long gv = ceil_div(g.S, kBlock * 4);
+  if (gv > 1024) gv = 1024;
+  if (gv < 1) gv = 1;
+  L.grid_vec = (int)gv;
+  long long gs = ceil_div(g.R, kBlock * 8);
+  if (gs > 1024) gs = 1024;
+  if (gs < 1) gs = 1;
+  L.nstat = (int)gs;
+  L.tw1 = ar.take<double2>(g.N1);
+  L.tw2 = ar.take<double2>(g.N2);
+  L.tw3 = ar.take<double2>(g.N3);
+  L.a = ar.take<double>(g.R);
+  L.x = ar.take<double2>(g.S * nE);
+  L.r = ar.take<double2>(g.S * nE);
+  L.p = ar.take<double2>(g.S * nE);
+  L.q = ar.take<double2>(g.S * nE);
+  L.t = ar.take<double2>(g.S * nE * d);
+  L.part_pq = ar.take<double>((size_t)L.tiles1 * nE);
+  L.part_rz = ar.take<double>((size_t)L.grid_vec * nE);
+  L.part_zz = ar.take<double>((size_t)L.grid_vec * nE);
+  L.part_misc = ar.take<double>((size_t)L.nstat * 9 + 16);
+  L.floor_abs = ar.take<double>(nE);
+  L.E3 = ar.take<double>(3 * nE);
+  L.st = ar.take<CgState>(nE);
+  L.done = ar.take<int>(nE);
+  L.bad = ar.take<int>(4);
+  L.hist = ar.take<double>((size_t)nE * max_iter);
+}
+
+size_t full_workspace_bytes(const int N3d[3], int nE, int d, int max_iter) {
+  Arena ar;
+  FullLayout L;
+  carve(ar, L, N3d, nE, d, max_iter);
+  return ar.used + 256;
+}
+
+int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
+  hipStream_t s = static_cast<hipStream_t>(A.stream);
+  const int d = A.d;
+  const int nE = A.nE;
+  // internal 3-D geometry: d = 2 is stored with a unit first axis
+  int N3d[3];
+  if (d == 3) {
+    N3d[0] = A.N[0];
+    N3d[1] = A.N[1];
+    N3d[2] = A.N[2];
+  } else {
+    N3d[0] = 1;
+    N3d[1] = A.N[0];
+    N3d[2] = A.N[1];
+  }
+  const int alpha0 = 3 - d;
+  Arena ar;
+  ar.base = static_cast<char*>(A.ws);
+  ar.cap = A.ws_bytes;
+  FullLayout L;
+  carve(ar, L, N3d, nE, d, A.max_iter);
+  if (ar.overflow) {
+    set_error("workspace too small: need %zu bytes, have %zu", ar.used, A.ws_bytes);
+    return LRFG_EWORKSPACE;
+  }
+  const G3 g = L.g;
+  hipEvent_t ev0, ev1, ev2;
+  LRFG_HIP(hipEventCreate(&ev0));
+  LRFG_HIP(hipEventCreate(&ev1));
+  LRFG_HIP(hipEventCreate(&ev2));
+  LRFG_HIP(hipEventRecord(ev0, s));
+
+  FftDev f1, f2, f3;
+  LRFG_TRY(fft_dev_upload(*A.plan1, L.tw1, s, &f1));
+  LRFG_TRY(fft_dev_upload(*A.plan2, L.tw2, s, &f2));
+  LRFG_TRY(fft_dev_upload(*A.plan3, L.tw3, s, &f3));
+
+  // coefficient
+  if (A.a_on_device) {
+    LRFG_HIP(hipMemcpyAsync(L.a, A.a, sizeof(double) * g.R, hipMemcpyDeviceToDevice, s));
+  } else {
+    LRFG_HIP(hipMemcpyAsync(L.a, A.a, sizeof(double) * g.R, hipMemcpyHostToDevice, s));
+  }
+  // E embedded in 3-D
+  std::vector<double> E3(3 * nE, 0.0);
+  for (int e = 0; e < nE; ++e)
+    for (int al = 0; al < d; ++al) E3[3 * e + alpha0 + al] = A.E[e * d + al];
+  LRFG_HIP(hipMemcpyAsync(L.E3, E3.data(), sizeof(double) * 3 * nE, hipMemcpyHostToDevice, s));
+  LRFG_HIP(hipMemsetAsync(L.bad, 0, sizeof(int) * 4, s));
+  LRFG_HIP(hipMemsetAsync(L.done, 0, sizeof(int) * nE, s));
+  if (A.max_iter > 0)
+    LRFG_HIP(hipMemsetAsync(L.hist, 0, sizeof(double) * nE * A.max_iter, s));
+
+  hipLaunchKernelGGL(k_coef_stats, dim3(L.nstat), dim3(kBlock), 0, s, L.a, g.R, L.part_misc, L.bad);
+  LRFG_LAUNCHED();
+  std::vector<double> stat(2 * L.nstat);
+  int bad = 0;
+  LRFG_HIP(hipMemcpyAsync(stat.data(), L.part_misc, sizeof(double) * 2 * L.nstat, hipMemcpyDeviceToHost, s));
+  LRFG_HIP(hipMemcpyAsync(&bad, L.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  LRFG_HIP(hipStreamSynchronize(s));
+  if (bad) {
+    set_error("coefficient must be finite and positive");
+    return LRFG_ECOEFF;
+  }
+  double sum_a = 0.0, sum_a2 = 0.0;
+  for (int i = 0; i < L.nstat; ++i) {
+    sum_a += stat[2 * i];
+    sum_a2 += stat[2 * i + 1];
+  }
+  const double mean_a = sum_a / (double)g.R;
+  const double rms_a = std::sqrt(sum_a2 / (double)g.R);
+  std::vector<double> floors(nE);
+  for (int e = 0; e < nE; ++e) {
+    double en = 0.0;
+    for (int al = 0; al < d; ++al) en += A.E[e * d + al] * A.E[e * d + al];
+    floors[e] = 1e-14 * rms_a * std::sqrt(en);
+  }
+  LRFG_HIP(hipMemcpyAsync(L.floor_abs, floors.data(), sizeof(double) * nE, hipMemcpyHostToDevice, s));
+
+  const size_t shm1 = size_t(2) * L.T1 * g.N1 * sizeof(double2);
+  const size_t shm3 = size_t(2) * L.T3 * g.N3 * sizeof(double2);
+  const long long pairs = ((long long)g.N1 * g.N2 + 1) / 2;
+  const int tiles3 = ceil_div(pairs, L.T3);
+  const double inv_vol = 1.0 / (double)g.R;
+
+  // a^ = F(a): R2C along axis 3, then axes 2 and 1 (scale 1/|N| at the end).
+  double2* ahat = L.q;  // q[0] is free until the first matvec
+  hipLaunchKernelGGL(k_axis3<1>, dim3(tiles3, 1), dim3(kBlock), shm3, s, (const void*)L.a, (void*)ahat,
+                     (const double*)nullptr, g, 0LL, 0LL, L.T3, f3, 1.0, (const int*)nullptr, 1);
+  LRFG_LAUNCHED();
+  LRFG_TRY(launch_fft_lines(ahat, g.N1, g.N2, g.H, -1, f2, 1.0, s));
+  LRFG_TRY(launch_fft_lines(ahat, 1, g.N1, (long long)g.N2 * g.H, -1, f1, inv_vol, s));
+
+  hipLaunchKernelGGL(k_cg_init, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, (const double2*)ahat,
+                     (const double*)L.E3, g, L.x, L.r, L.p, L.part_rz, L.part_zz);
+  LRFG_LAUNCHED();
+  hipLaunchKernelGGL(k_cg_init2, dim3(nE), dim3(kBlock), 0, s, L.st, L.done, (const double*)L.part_rz,
+                     (const double*)L.part_zz, L.grid_vec, (const double*)L.floor_abs);
+  LRFG_LAUNCHED();
+  LRFG_HIP(hipEventRecord(ev1, s));
+
+  // ------------------------------------------------------------ PCG loop
+  const int ring = 4;
+  int* pinned = A.pinned_flags;  // ring * nE ints, pinned host memory from the plan
+  hipEvent_t evs[4];
+  for (int i = 0; i < ring; ++i) LRFG_HIP(hipEventCreateWithFlags(&evs[i], hipEventDisableTiming));
+  int it = 0;
+  bool all_done = false;
+  int checked = -1;
+  for (it = 0; it < A.max_iter; ++it) {
+    // P1
+    hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1 * d, nE), dim3(kBlock), shm1, s, (const double2*)L.p,
+                       L.t, g, alpha0, d, (long long)d * g.S, g.S, L.T1, f1, (const int*)L.done);
+    LRFG_LAUNCHED();
+    // P2
+    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, 1, f2, 1.0, s));
+    // P3
+    hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, nE * d), dim3(kBlock), shm3, s, (const void*)L.t,
+                       (void*)nullptr, (const double*)L.a, g, g.S, 0LL, L.T3, f3, 1.0,
+                       (const int*)L.done, d);
+    LRFG_LAUNCHED();
+    // P4
+    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, -1, f2, 1.0, s));
+    // P5
+    hipLaunchKernelGGL(k_div_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.t, L.q,
+                       (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1, (const int*)L.done,
+                       L.part_pq);
+    LRFG_LAUNCHED();
+    hipLaunchKernelGGL(k_cg_update1, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
+                       (const double*)L.part_pq, L.tiles1, L.x, L.r, (const double2*)L.p,
+                       (const double2*)L.q, L.part_rz, L.part_zz);
+    LRFG_LAUNCHED();
+    hipLaunchKernelGGL(k_cg_update2, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
+                       (const double*)L.part_rz, (const double*)L.part_zz, L.grid_vec,
+                       (const double2*)L.r, L.p, A.tol, L.hist, A.max_iter);
+    LRFG_LAUNCHED();
+    LRFG_HIP(hipMemcpyAsync(pinned + (it % ring) * nE, L.done, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipEventRecord(evs[it % ring], s));
+    // look at the flags of an earlier iteration while this one runs
+    const int look = it - (ring - 1);
+    if (look >= 0) {
+      LRFG_HIP(hipEventSynchronize(evs[look % ring]));
+      checked = look;
+      bool ad = true;
+      for (int e = 0; e < nE; ++e) ad = ad && (pinned[(look % ring) * nE + e] != 0);
+      if (ad) {
+        all_done = true;
+        ++it;
+        break;
+      }
+    }
+  }
+  (void)checked;
+  (void)all_done;
+  LRFG_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < ring; ++i) LRFG_HIP(hipEventDestroy(evs[i]));
+
+  // ------------------------------------------------------------ A_H
+  // For each alpha: g_{e,alpha} = F^-1(2 pi i k_alpha x_e) into the q buffers
+  // (real layout), then partial sums of a g and a g g.
+  const int nv = nE + nE * (nE + 1) / 2;
+  std::vector<double> m1(nE * d, 0.0), m2((size_t)nE * nE * d, 0.0);
+  std::vector<double> part((size_t)L.nstat * nv);
+  for (int al = 0; al < d; ++al) {
+    hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.x, L.t, g,
+                       alpha0 + al, 1, g.S, 0LL, L.T1, f1, (const int*)nullptr);
+    LRFG_LAUNCHED();
+    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * g.N1, g.N2, g.H, 1, f2, 1.0, s));
+    hipLaunchKernelGGL(k_axis3<2>, dim3(tiles3, nE), dim3(kBlock), shm3, s, (const void*)L.t, (void*)L.q,
+                       (const double*)nullptr, g, g.S, 2 * g.S, L.T3, f3, 1.0, (const int*)nullptr, 1);
+    LRFG_LAUNCHED();
+    hipLaunchKernelGGL(k_ah_reduce, dim3(L.nstat), dim3(kBlock), 0, s, (const double*)L.a,
+                       (const double*)L.q, 2 * g.S, nE, g.R, L.part_misc);
+    LRFG_LAUNCHED();
+    LRFG_HIP(hipMemcpyAsync(part.data(), L.part_misc, sizeof(double) * L.nstat * nv, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+    std::vector<double> acc(nv, 0.0);
+    for (int b = 0; b < L.nstat; ++b)
+      for (int v = 0; v < nv; ++v) acc[v] += part[(size_t)b * nv + v];
+    int v = 0;
+    for (int e = 0; e < nE; ++e) m1[e * d + al] = acc[v++] / (double)g.R;
+    for (int i = 0; i < nE; ++i)
+      for (int j = i; j < nE; ++j) {
+        const double val = acc[v++] / (double)g.R;
+        m2[((size_t)i * nE + j) * d + al] = val;
+        m2[((size_t)j * nE + i) * d + al] = val;
+      }
+  }
+  LRFG_HIP(hipEventRecord(ev2, s));
+  std::vector<CgState> st(nE);
+  LRFG_HIP(hipMemcpyAsync(st.data(), L.st, sizeof(CgState) * nE, hipMemcpyDeviceToHost, s));
+  std::vector<double> hist((size_t)nE * A.max_iter);
+  if (A.max_iter > 0)
+    LRFG_HIP(hipMemcpyAsync(hist.data(), L.hist, sizeof(double) * nE * A.max_iter, hipMemcpyDeviceToHost, s));
+  std::vector<int> dn(nE);
+  LRFG_HIP(hipMemcpyAsync(dn.data(), L.done, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+  LRFG_HIP(hipStreamSynchronize(s));
+  float ms_setup = 0.f, ms_solve = 0.f;
+  LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
+  LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+  LRFG_HIP(hipEventDestroy(ev0));
+  LRFG_HIP(hipEventDestroy(ev1));
+  LRFG_HIP(hipEventDestroy(ev2));
+
+  // A_H[i][j] = mean(a) E_i.E_j + sum_alpha (E_i,alpha m1[j] + E_j,alpha m1[i] + m2[i][j])
+  int rc = LRFG_OK;
+  for (int i = 0; i < nE; ++i) {
+    for (int j = 0; j < nE; ++j) {
+      double v = 0.0;
+      for (int al = 0; al < d; ++al) {
+        const double ei = A.E[i * d + al], ej = A.E[j * d + al];
+        v += mean_a * ei * ej + ei * m1[j * d + al] + ej * m1[i * d + al] + m2[((size_t)i * nE + j) * d + al];
+      }
+      if (out->A_H) out->A_H[i * nE + j] = v;
+    }
+    const int its = dn[i] == 0 ? A.max_iter : st[i].iters;
+    if (out->iters) out->iters[i] = its;
+    int stc = LRFG_OK;
+    if (dn[i] == 0) stc = LRFG_NOT_CONVERGED;
+    if (dn[i] == 2) stc = LRFG_NOT_CONVERGED;
+    if (out->status) out->status[i] = stc;
+    if (stc != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+    if (out->res_hist)
+      for (int k = 0; k < A.max_iter; ++k) out->res_hist[(size_t)i * A.max_iter + k] = hist[(size_t)i * A.max_iter + k];
+  }
+  out->setup_ms = ms_setup;
+  out->solve_ms = ms_solve;
+  return rc;
+}
+
+// ------------------------------------------------------------ op-level entry
+size_t full_op_workspace_bytes(const int N[3]) {
+  Arena ar;
+  G3 g = make_g3(N);
+  ar.take<double2>(g.N1);
+  ar.take<double2>(g.N2);
+  ar.take<double2>(g.N3);
+  ar.take<double2>(g.S * 3);
+  ar.take<double>(ceil_div((long long)g.N2 * g.H, 1) + 16);
+  ar.take<int>(4);
+  return ar.used + 256;
+}
+
+int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, const FftPlan* p3,
+            const double* a, const double* u, double* outp, void* ws, size_t ws_bytes, hipStream_t s) {
+  G3 g = make_g3(N);
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  double2* tw1 = ar.take<double2>(g.N1);
+  double2* tw2 = ar.take<double2>(g.N2);
+  double2* tw3 = ar.take<double2>(g.N3);
+  double2* t = ar.take<double2>(g.S * 3);
+  double* part = ar.take<double>(ceil_div((long long)g.N2 * g.H, 1) + 16);
+  int* done = ar.take<int>(4);
+  if (ar.overflow) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  const double2* uh = reinterpret_cast<const double2*>(u);
+  double2* oh = reinterpret_cast<double2*>(outp);
+  if (which == 1) return launch_pinv(uh, oh, g.N1, g.N2, g.N3, s);
+  FftDev f1, f2, f3;
+  LRFG_TRY(fft_dev_upload(*p1, tw1, s, &f1));
+  LRFG_TRY(fft_dev_upload(*p2, tw2, s, &f2));
+  LRFG_TRY(fft_dev_upload(*p3, tw3, s, &f3));
+  LRFG_HIP(hipMemsetAsync(done, 0, sizeof(int) * 4, s));
+  const int T1 = tile1_lines(g.N1);
+  const int T3 = lines_per_tile(g.N3);
+  const int tiles1 = ceil_div((long long)g.N2 * g.H, T1);
+  const size_t shm1 = size_t(2) * T1 * g.N1 * sizeof(double2);
+  const size_t shm3 = size_t(2) * T3 * g.N3 * sizeof(double2);
+  const long long pairs = ((long long)g.N1 * g.N2 + 1) / 2;
+  const int tiles3 = ceil_div(pairs, T3);
+  hipLaunchKernelGGL(k_grad_axis1, dim3(tiles1 * 3, 1), dim3(kBlock), shm1, s, uh, t, g, 0, 3, 3 * g.S, g.S, T1,
+                     f1, (const int*)done);
+  LRFG_LAUNCHED();
+  LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, 1, f2, 1.0, s));
+  hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, 3), dim3(kBlock), shm3, s, (const void*)t, (void*)nullptr, a, g, g.S,
+                     0LL, T3, f3, 1.0, (const int*)done, 3);
+  LRFG_LAUNCHED();
+  LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, -1, f2, 1.0, s));
+  hipLaunchKernelGGL(k_div_axis1, dim3(tiles1, 1), dim3(kBlock), shm1, s, (const double2*)t, oh, uh, g, 0, 3,
+                     1.0 / (double)g.R, T1, f1, (const int*)done, part);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+namespace {
+__global__ void k_pinv(const double2* __restrict__ u, double2* __restrict__ o, G3 g) {
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    double k[3];
+    kvec(g, n1, n2, h, k);
+    o[s] = cscale(u[s], pinv_of(k));
+  }
+}
+}  // namespace
+
+int launch_pinv(const double2* u, double2* o, int N1, int N2, int N3, hipStream_t s) {
+  const int N[3] = {N1, N2, N3};
+  G3 g = make_g3(N);
+  long long gv = ceil_div(g.S, kBlock * 4);
+  if (gv > 4096) gv = 4096;
+  hipLaunchKernelGGL(k_pinv, dim3((int)gv), dim3(kBlock), 0, s, u, o, g);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+}  // namespace lrfg

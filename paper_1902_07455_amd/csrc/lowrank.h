@@ -1,0 +1,24 @@
+// Low-rank (CP / Tucker / TT) solve path (internal interface) and the
+// coefficient staging shared with the full-grid path.
+#pragma once
+
+#include "fft.h"
+
+namespace lrfg {
+
+struct LowRankPlan;
+
+// Coefficient given in CP or TT form, expanded to a full field on the device
+// (setup of the full-grid path).  Staging limits: CP rank <= kMaxCoeffRank,
+// TT ranks <= kMaxCoeffRank.
+constexpr int kMaxCoeffRank = 64;
+size_t coeff_staging_bytes(const lrfg_problem& p);
+int expand_coeff(const lrfg_problem& p, const lrfg_coeff& a, double* dst, size_t bytes, hipStream_t s);
+
+int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out);
+void lowrank_plan_destroy(LowRankPlan* lr);
+size_t lowrank_workspace_bytes(const LowRankPlan* lr, int max_nE);
+int lowrank_solve(LowRankPlan* lr, const lrfg_coeff& a, const double* E, int nE, void* ws, size_t ws_bytes,
+                  hipStream_t s, lrfg_result* out);
+
+}  // namespace lrfg

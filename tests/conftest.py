@@ -9,3 +9,18 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(scope="session")
+def dev():
+    """cuda:0 with the HIP library loaded (fails if the library is missing)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_1902_07455_amd as P
+    assert P.abi_version() == 1          # loads liblrfg.so or raises
+    assert P.device_check() == 0
+    return torch.device("cuda:0")

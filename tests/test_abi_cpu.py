@@ -1,0 +1,135 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/lrfg.h declares, and validates arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrfg.h")
+
+
+def _lib():
+    from paper_1902_07455_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblrfg.so not built (run __graft_entry__.build())")
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lrfg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = _lib()
+    lib = C.CDLL(L.LIB_PATH)
+    names = declared_functions()
+    assert "lrfg_solve" in names and "lrfg_plan_create" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lrfg.h but not exported"
+    assert set(L.EXPORTS) <= set(names)
+
+
+def test_version_and_status_strings():
+    L = _lib()
+    lib = L.lib()
+    assert lib.lrfg_abi_version() == 1
+    for s in (0, 1, -1, -2, -3, -4, -5):
+        assert len(lib.lrfg_status_string(s)) > 0
+
+
+def _problem(L, **kw):
+    p = L.Problem()
+    p.d = kw.get("d", 3)
+    for i, n in enumerate(kw.get("N", (15, 15, 15))):
+        p.N[i] = n
+    p.format = kw.get("format", L.FORMAT_FULL)
+    p.rank_cap = kw.get("rank_cap", 10)
+    p.trunc_tol = kw.get("trunc_tol", 0.0)
+    p.solver_tol = kw.get("solver_tol", 1e-8)
+    p.max_iter = kw.get("max_iter", 100)
+    p.solver = kw.get("solver", L.SOLVER_PCG)
+    p.precision = kw.get("precision", L.PREC_FP64)
+    p.precond_terms = kw.get("precond_terms", 0)
+    p.oversample = kw.get("oversample", 0)
+    p.seed = 0
+    p.flags = kw.get("flags", 0)
+    return p
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(d=4), -1),
+    (dict(N=(14, 15, 15)), -1),
+    (dict(N=(1, 15, 15)), -1),
+    (dict(d=3, format=1), -1),                 # CP needs d = 2
+    (dict(format=3, rank_cap=0), -1),
+    (dict(solver_tol=0.0), -1),
+    (dict(solver_tol=float("nan")), -1),
+    (dict(trunc_tol=-1.0), -1),
+    (dict(max_iter=0), -1),
+    (dict(flags=1), -1),
+    (dict(precond_terms=1), -1),
+    (dict(precision=1), -5),                   # full grid is FP64 only
+    (dict(solver=1), -5),                      # full grid uses PCG
+])
+def test_plan_validation(kw, code):
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    rc = lib.lrfg_plan_create(C.byref(_problem(L, **kw)), C.byref(plan))
+    assert rc == code
+    assert not plan.value
+    assert len(lib.lrfg_last_error()) > 0
+
+
+def test_plan_and_workspace_sizes():
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, N=(45, 45, 45))), C.byref(plan)) == 0
+    nb = C.c_size_t()
+    assert lib.lrfg_plan_workspace_bytes(plan, 3, C.byref(nb)) == 0
+    S = 45 * 45 * 23 * 16
+    assert nb.value >= 3 * 7 * S            # x, r, p, q and d gradients per E
+    nb1 = C.c_size_t()
+    assert lib.lrfg_plan_workspace_bytes(plan, 1, C.byref(nb1)) == 0
+    assert nb1.value < nb.value
+    assert lib.lrfg_plan_workspace_bytes(plan, 0, C.byref(nb1)) == -1
+    lib.lrfg_plan_destroy(plan)
+    lib.lrfg_plan_destroy(None)
+
+
+def test_solve_rejects_bad_workspace_before_device():
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, d=2, N=(9, 9, 1))), C.byref(plan)) == 0
+    c = L.Coeff()
+    buf = (C.c_double * 81)()
+    c.full = C.addressof(buf)
+    r = L.Result()
+    # misaligned / too small workspace: EWORKSPACE without any device call
+    assert lib.lrfg_solve(plan, C.byref(c), None, 2, C.c_void_p(8), 16, None, C.byref(r)) == -3
+    # nE must equal d when E is NULL
+    assert lib.lrfg_solve(plan, C.byref(c), None, 1, C.c_void_p(256), 1 << 30, None, C.byref(r)) == -1
+    lib.lrfg_plan_destroy(plan)
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and not os.path.exists("/dev/kfd"),
+                    reason="no ROCm device nodes")
+def test_device_check_runs():
+    L = _lib()
+    assert L.lib().lrfg_device_check() in (0, -4)
+
+
+def test_product_path_does_not_import_oracle():
+    """The package never imports the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_1902_07455_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.findall(r"(?:import|from)\s+(\w+)", text), f
