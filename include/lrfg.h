@@ -92,6 +92,9 @@ typedef struct {
   int precond_terms;    /* low-rank: exponential-sum terms M (0 = automatic) */
   int oversample;       /* low-rank: sketch oversampling p (0 = automatic)   */
   uint64_t seed;        /* low-rank: seed of the sketching generator         */
+  int coeff_rank;       /* low-rank: upper bound on the coefficient's rank
+                           (CP terms or TT ranks) a solve will receive;
+                           sizes the workspace (0 = 16)                      */
   uint32_t flags;       /* reserved, must be 0                               */
 } lrfg_problem;
 
@@ -192,6 +195,55 @@ int lrfg_mode_op(double* x, int outer, int N, int inner, int op, double t,
 size_t lrfg_full_op_workspace_bytes(const int N[3]);
 int lrfg_full_op(int which, const int N[3], const double* a, const double* u,
                  double* out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* FP64 batched matrix product on the matrix cores (MFMA):
+ *   C_b = alpha op(A_b) op(B_b) + beta C_b,  b in [0, batch),
+ * row-major with leading dimensions lda/ldb/ldc and batch strides sA/sB/sC
+ * (elements); op = transpose when ta / tb != 0; op(A) is m x k, op(B) k x n.
+ * beta = 0 does not read C.  d_ws (lrfg_gemm_workspace_bytes) holds split-K
+ * partial sums; a smaller workspace only disables the split.  These are the
+ * core contractions and Gram products of the truncation (Appendix A.3). */
+size_t lrfg_gemm_workspace_bytes(int m, int n, int k, int batch);
+int lrfg_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A, long long lda,
+              long long sA, const double* B, long long ldb, long long sB, double beta, double* C,
+              long long ldc, long long sC, int batch, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Batched symmetric eigendecomposition (cyclic Jacobi), n <= 64: A is
+ * batch x n x n (row-major, symmetrised as (A + A^T)/2), W receives the
+ * eigenvalues in descending order (batch x n), V the eigenvectors as
+ * columns (batch x n x n).  The small SVDs of the truncation are taken
+ * from these Gram eigenpairs (Sec. 3.1.4). */
+int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* stream);
+
+/* TT truncation (rounding, Appendix A.3) of nE trains with input ranks
+ * rin[0..d] (rin[0] = rin[d] = 1), carriages in_cores[j] = nE x
+ * [r_{j-1}][N_j][r_j] (device).  Output ranks are fixed,
+ * c_j = min(cap, N-bounds), written to out_ranks (host, d+1 ints); the
+ * directions beyond the kept rank (at most c_j, the fewest whose dropped
+ * singular values satisfy ||dropped||^2 <= tol^2 ||X||^2 / (d-1)) are zero.
+ * kept (host, 2*nE ints or NULL) receives the kept ranks: bond 1 for every
+ * system, then bond 2.  The truncation is randomised (Gaussian TT sketch of
+ * ranks c_j + oversample, seeded by seed) and exact whenever the input rank
+ * at a bond is at most c_j + oversample.  Synchronises the stream when kept
+ * is non-NULL. */
+size_t lrfg_tt_round_workspace_bytes(int d, const int N[3], const int rin[4], int cap,
+                                     int oversample, int nE);
+int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cores, int cap,
+                  double tol, int oversample, uint64_t seed, double* const* out_cores,
+                  int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support).  lrfg_prof_enable(name) makes every
+ * later launch of the kernel `name` (one of "fft_lines", "fft_axis2",
+ * "mode_op", "grad_axis1", "axis3", "div_axis1", "cg_update1",
+ * "cg_update2"; "fft_axis2" is the axis-2 pass of the full-grid PCG
+ * matvec) bracketed by HIP events
+ * on the stream it runs on; NULL disables and clears.  lrfg_prof_read
+ * synchronises those events and returns the number of timed launches and
+ * their summed duration in milliseconds.  Process-wide state.
+ * ---------------------------------------------------------------------- */
+int lrfg_prof_enable(const char* kernel);
+int lrfg_prof_read(int* count, double* total_ms);
 
 #ifdef __cplusplus
 }

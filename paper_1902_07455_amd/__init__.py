@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "abi_version", "device_check"]
+           "gemm", "syevj", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
             "tt": _lib.FORMAT_TT}
@@ -92,7 +92,7 @@ class Solver:
                  trunc_tol: float = 0.0, solver_tol: float = 1e-10, max_iter: int = 1000,
                  solver: str = "pcg", precision: str = "fp64", precond_terms: int = 0,
                  oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
-                 device: str = "cuda:0"):
+                 coeff_rank: int = 0, device: str = "cuda:0"):
         L = lib()
         p = _lib.Problem()
         p.d = int(d)
@@ -109,6 +109,7 @@ class Solver:
         p.precond_terms = int(precond_terms)
         p.oversample = int(oversample)
         p.seed = int(seed)
+        p.coeff_rank = int(coeff_rank)
         p.flags = 0
         self.problem = p
         self.d = int(d)
@@ -194,6 +195,19 @@ class Solver:
             pass
 
 
+def prof_enable(kernel: Optional[str]):
+    """Time every later launch of `kernel` with HIP events (None: off)."""
+    check(lib().lrfg_prof_enable(kernel.encode() if kernel else None))
+
+
+def prof_read():
+    """(launch count, summed milliseconds) of the timed kernel."""
+    n = C.c_int()
+    ms = C.c_double()
+    check(lib().lrfg_prof_read(C.byref(n), C.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
 # ---------------------------------------------------------------- op level
 def _ws_tensor(nbytes, device):
     torch = _torch()
@@ -229,3 +243,65 @@ def full_op(which: int, N, a, u, out, stream=None):
     check(L.lrfg_full_op(which, Nc, aptr, C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
                          C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream_handle(stream))))
     return out
+
+
+def gemm(A, B, C_, ta=False, tb=False, alpha=1.0, beta=0.0, stream=None):
+    """C_ = alpha op(A) op(B) + beta C_ on float64 CUDA tensors of shape
+    (batch, rows, cols) (contiguous); returns C_."""
+    L = lib()
+    bt = C_.shape[0]
+    m, n = C_.shape[1], C_.shape[2]
+    k = A.shape[1] if ta else A.shape[2]
+    ws = _ws_tensor(L.lrfg_gemm_workspace_bytes(m, n, k, bt), C_.device)
+    sA = A.shape[1] * A.shape[2] if A.shape[0] > 1 else 0
+    sB = B.shape[1] * B.shape[2] if B.shape[0] > 1 else 0
+    check(L.lrfg_gemm(int(ta), int(tb), m, n, k, float(alpha), C.c_void_p(A.data_ptr()), A.shape[2], sA,
+                      C.c_void_p(B.data_ptr()), B.shape[2], sB, float(beta), C.c_void_p(C_.data_ptr()),
+                      n, m * n, bt, C.c_void_p(ws.data_ptr()), ws.numel(),
+                      C.c_void_p(_stream_handle(stream))))
+    return C_
+
+
+def syevj(A, stream=None):
+    """Batched symmetric eigendecomposition of a (batch, n, n) float64 CUDA
+    tensor: (W descending, V with eigenvectors as columns)."""
+    torch = _torch()
+    bt, n = A.shape[0], A.shape[1]
+    W = torch.empty((bt, n), dtype=torch.float64, device=A.device)
+    V = torch.empty((bt, n, n), dtype=torch.float64, device=A.device)
+    check(lib().lrfg_syevj(n, C.c_void_p(A.data_ptr()), bt, C.c_void_p(W.data_ptr()),
+                           C.c_void_p(V.data_ptr()), C.c_void_p(_stream_handle(stream))))
+    return W, V
+
+
+def tt_round(cores, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):
+    """Truncate nE trains given as float64 CUDA tensors cores[j] of shape
+    (nE, r_{j-1}, N_j, r_j).  Returns (out cores, kept ranks (2, nE))."""
+    torch = _torch()
+    L = lib()
+    d = len(cores)
+    nE = cores[0].shape[0]
+    Ns = [int(G.shape[2]) for G in cores] + [1] * (3 - d)
+    rin = [1] + [int(G.shape[3]) for G in cores[:-1]] + [1] + [1] * (3 - d)
+    Nc = (C.c_int * 3)(*Ns)
+    Rc = (C.c_int * 4)(*rin[:4])
+    nb = L.lrfg_tt_round_workspace_bytes(d, Nc, Rc, cap, oversample, nE)
+    if nb == 0:
+        raise LrfgError(-1, "bad tt_round sizes")
+    ws = _ws_tensor(nb, cores[0].device)
+    c = [1] * 4
+    if d == 3:
+        c[1] = min(cap, Ns[0], Ns[1] * Ns[2])
+        c[2] = min(cap, Ns[2], Ns[0] * Ns[1])
+    else:
+        c[1] = min(cap, Ns[0], Ns[1])
+    outs = [torch.empty((nE, c[j], Ns[j], c[j + 1]), dtype=torch.float64, device=cores[0].device)
+            for j in range(d)]
+    ins = [G.contiguous() for G in cores]
+    ip = (C.c_void_p * 3)(*[G.data_ptr() for G in ins] + [0] * (3 - d))
+    op = (C.c_void_p * 3)(*[G.data_ptr() for G in outs] + [0] * (3 - d))
+    ranks = (C.c_int * 4)()
+    kept = (C.c_int * (2 * nE))()
+    check(L.lrfg_tt_round(d, Nc, Rc, ip, cap, float(tol), oversample, seed, op, ranks, kept, nE,
+                          C.c_void_p(ws.data_ptr()), nb, C.c_void_p(_stream_handle(stream))))
+    return outs, np.array(list(kept)).reshape(2, nE)

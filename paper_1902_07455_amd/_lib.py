@@ -35,6 +35,7 @@ class Problem(C.Structure):
         ("precond_terms", C.c_int),
         ("oversample", C.c_int),
         ("seed", C.c_uint64),
+        ("coeff_rank", C.c_int),
         ("flags", C.c_uint32),
     ]
 
@@ -75,7 +76,9 @@ EXPORTS = [
     "lrfg_abi_version", "lrfg_status_string", "lrfg_last_error", "lrfg_device_check",
     "lrfg_plan_create", "lrfg_plan_workspace_bytes", "lrfg_solve", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
-    "lrfg_full_op_workspace_bytes", "lrfg_full_op",
+    "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read",
+    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_tt_round_workspace_bytes",
+    "lrfg_tt_round",
 ]
 
 
@@ -115,6 +118,27 @@ def lib():
     L.lrfg_full_op.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_size_t, C.c_void_p]
     L.lrfg_full_op.restype = C.c_int
+    L.lrfg_gemm_workspace_bytes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    L.lrfg_gemm_workspace_bytes.restype = C.c_size_t
+    L.lrfg_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                            C.c_void_p, C.c_longlong, C.c_longlong, C.c_void_p, C.c_longlong,
+                            C.c_longlong, C.c_double, C.c_void_p, C.c_longlong, C.c_longlong,
+                            C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.lrfg_gemm.restype = C.c_int
+    L.lrfg_syevj.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.lrfg_syevj.restype = C.c_int
+    L.lrfg_tt_round_workspace_bytes.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                                C.c_int, C.c_int, C.c_int]
+    L.lrfg_tt_round_workspace_bytes.restype = C.c_size_t
+    L.lrfg_tt_round.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_void_p), C.c_int, C.c_double, C.c_int, C.c_uint64,
+                                C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.lrfg_tt_round.restype = C.c_int
+    L.lrfg_prof_enable.argtypes = [C.c_char_p]
+    L.lrfg_prof_enable.restype = C.c_int
+    L.lrfg_prof_read.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lrfg_prof_read.restype = C.c_int
     _LIB = L
     return L
 

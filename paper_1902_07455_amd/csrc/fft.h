@@ -44,8 +44,11 @@ const FftPlan* fft_plan_cached(int N);
 int fft_dev_upload(const FftPlan& p, double2* d_table, hipStream_t s, FftDev* out);
 // In-place batched DFT of the lines of x[outer][N][inner] (complex),
 // dir -1 forward / +1 inverse, result multiplied by `scale`.
+// With `done`, a tile whose lines all belong to systems flagged done
+// (flag index = line / lines_per_flag) is skipped.
 int launch_fft_lines(double2* x, long long outer, int N, long long inner, int dir, const FftDev& f,
-                     double scale, hipStream_t s);
+                     double scale, hipStream_t s, const char* tag = "fft_lines",
+                     const int* done = nullptr, long long lines_per_flag = 1);
 // In-place real circulant F^-1 diag(s(k)) F along the middle index of the
 // real array x[outer][N][inner]; op 0: s = 2 pi i k, op 1: s = exp(-t k^2).
 int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t,

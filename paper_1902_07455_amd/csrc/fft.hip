@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "fft.h"
+#include "prof.h"
 
 namespace lrfg {
 
@@ -75,13 +76,24 @@ __device__ inline long long line_addr(long long l, int n, int N, int inner) {
 
 template <int DIR>
 __global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner, int T,
-                            FftDev f, double scale) {
+                            FftDev f, double scale, const int* __restrict__ done,
+                            long long lines_per_flag) {
   extern __shared__ double2 sm[];
   const int N = f.N;
   double2* a = sm;
   double2* b = sm + T * N;
   const long long l0 = (long long)blockIdx.x * T;
-  const int tcount = (int)min((long long)T, nlines - l0);
+  int tcount = (int)min((long long)T, nlines - l0);
+  // A tile is skipped when every system its lines belong to (system =
+  // line / lines_per_flag) is flagged done.  Lines of a finished system
+  // inside a running tile are transformed too: that system's arrays are
+  // scratch no later kernel reads.
+  if (done != nullptr) {
+    bool all_done = true;
+    for (long long e = l0 / lines_per_flag; e <= (l0 + tcount - 1) / lines_per_flag; ++e)
+      all_done = all_done && (done[e] != 0);
+    if (all_done) return;
+  }
   const int total = T * N;
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int t, n;
@@ -99,9 +111,10 @@ __global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner
 
 // Real circulant along the mode index: two real fibres packed into one
 // complex line (the operator is real, so it acts on real and imaginary
-// parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2).
-__global__ void k_mode_op(double* __restrict__ x, long long nfib, int inner, int T, FftDev f,
-                          int op, double tparam) {
+// parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2); result times mult.
+// Reads xin, writes x (the same array for in-place use).
+__global__ void k_mode_op(const double* xin, double* x, long long nfib, int inner, int T, FftDev f, int op,
+                          double tparam, double mult) {
   extern __shared__ double2 sm[];
   const int N = f.N;
   double2* a = sm;
@@ -112,8 +125,8 @@ __global__ void k_mode_op(double* __restrict__ x, long long nfib, int inner, int
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
     const long long fa = f0 + 2 * t, fb = fa + 1;
-    const double re = (fa < nfib) ? x[line_addr(fa, n, N, inner)] : 0.0;
-    const double im = (fb < nfib) ? x[line_addr(fb, n, N, inner)] : 0.0;
+    const double re = (fa < nfib) ? xin[line_addr(fa, n, N, inner)] : 0.0;
+    const double im = (fb < nfib) ? xin[line_addr(fb, n, N, inner)] : 0.0;
     a[t * N + n] = make_double2(re, im);
   }
   __syncthreads();
@@ -124,9 +137,9 @@ __global__ void k_mode_op(double* __restrict__ x, long long nfib, int inner, int
     const int k = freq_of(n, N);
     double2 v = r[idx];
     if (op == 0) {
-      v = cmul_i(v, 2.0 * kPi * (double)k / (double)N);
+      v = cmul_i(v, mult * 2.0 * kPi * (double)k / (double)N);
     } else {
-      v = cscale(v, exp(-tparam * (double)k * (double)k) / (double)N);
+      v = cscale(v, mult * exp(-tparam * (double)k * (double)k) / (double)N);
     }
     r[idx] = v;
   }
@@ -154,31 +167,41 @@ int fft_dev_upload(const FftPlan& p, double2* d_table, hipStream_t s, FftDev* ou
 }
 
 int launch_fft_lines(double2* x, long long outer, int N, long long inner, int dir, const FftDev& f,
-                     double scale, hipStream_t s) {
+                     double scale, hipStream_t s, const char* tag, const int* done,
+                     long long lines_per_flag) {
   const long long nlines = outer * inner;
   if (nlines == 0) return LRFG_OK;
   const int T = lines_per_tile(N);
   const size_t shm = size_t(2) * T * N * sizeof(double2);
   const int grid = ceil_div(nlines, T);
+  ProfScope ps_(tag, s);
   if (dir < 0) {
-    hipLaunchKernelGGL(k_fft_lines<-1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale);
+    hipLaunchKernelGGL(k_fft_lines<-1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale,
+                       done, lines_per_flag);
   } else {
-    hipLaunchKernelGGL(k_fft_lines<1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale);
+    hipLaunchKernelGGL(k_fft_lines<1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale,
+                       done, lines_per_flag);
   }
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
-int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t,
-                   const FftDev& f, hipStream_t s) {
+int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
+                       double mult, const FftDev& f, hipStream_t s) {
   const long long nfib = outer * inner;
   if (nfib == 0) return LRFG_OK;
   const int T = lines_per_tile(N);
   const size_t shm = size_t(2) * T * N * sizeof(double2);
   const int grid = ceil_div(nfib, 2 * T);
-  hipLaunchKernelGGL(k_mode_op, dim3(grid), dim3(256), shm, s, x, nfib, (int)inner, T, f, op, t);
+  ProfScope ps_("mode_op", s);
+  hipLaunchKernelGGL(k_mode_op, dim3(grid), dim3(256), shm, s, xin, x, nfib, (int)inner, T, f, op, t, mult);
   LRFG_LAUNCHED();
   return LRFG_OK;
+}
+
+int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t, const FftDev& f,
+                   hipStream_t s) {
+  return launch_mode_op_oop(x, x, outer, N, inner, op, t, 1.0, f, s);
 }
 
 }  // namespace lrfg

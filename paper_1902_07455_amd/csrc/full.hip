@@ -24,6 +24,7 @@
 
 #include "fft.h"
 #include "full.h"
+#include "prof.h"
 
 namespace lrfg {
 
@@ -672,30 +673,47 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   int checked = -1;
   for (it = 0; it < A.max_iter; ++it) {
     // P1
-    hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1 * d, nE), dim3(kBlock), shm1, s, (const double2*)L.p,
-                       L.t, g, alpha0, d, (long long)d * g.S, g.S, L.T1, f1, (const int*)L.done);
+    {
+      ProfScope ps_("grad_axis1", s);
+      hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1 * d, nE), dim3(kBlock), shm1, s, (const double2*)L.p,
+                         L.t, g, alpha0, d, (long long)d * g.S, g.S, L.T1, f1, (const int*)L.done);
+    }
     LRFG_LAUNCHED();
     // P2
-    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, 1, f2, 1.0, s));
+    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, 1, f2, 1.0, s, "fft_axis2",
+                              L.done, (long long)d * g.N1 * g.H));
     // P3
-    hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, nE * d), dim3(kBlock), shm3, s, (const void*)L.t,
-                       (void*)nullptr, (const double*)L.a, g, g.S, 0LL, L.T3, f3, 1.0,
-                       (const int*)L.done, d);
+    {
+      ProfScope ps_("axis3", s);
+      hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, nE * d), dim3(kBlock), shm3, s, (const void*)L.t,
+                         (void*)nullptr, (const double*)L.a, g, g.S, 0LL, L.T3, f3, 1.0,
+                         (const int*)L.done, d);
+    }
     LRFG_LAUNCHED();
     // P4
-    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, -1, f2, 1.0, s));
+    LRFG_TRY(launch_fft_lines(L.t, (long long)nE * d * g.N1, g.N2, g.H, -1, f2, 1.0, s, "fft_axis2",
+                              L.done, (long long)d * g.N1 * g.H));
     // P5
-    hipLaunchKernelGGL(k_div_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.t, L.q,
-                       (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1, (const int*)L.done,
-                       L.part_pq);
+    {
+      ProfScope ps_("div_axis1", s);
+      hipLaunchKernelGGL(k_div_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.t, L.q,
+                         (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1, (const int*)L.done,
+                         L.part_pq);
+    }
     LRFG_LAUNCHED();
-    hipLaunchKernelGGL(k_cg_update1, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
-                       (const double*)L.part_pq, L.tiles1, L.x, L.r, (const double2*)L.p,
-                       (const double2*)L.q, L.part_rz, L.part_zz);
+    {
+      ProfScope ps_("cg_update1", s);
+      hipLaunchKernelGGL(k_cg_update1, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
+                         (const double*)L.part_pq, L.tiles1, L.x, L.r, (const double2*)L.p,
+                         (const double2*)L.q, L.part_rz, L.part_zz);
+    }
     LRFG_LAUNCHED();
-    hipLaunchKernelGGL(k_cg_update2, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
-                       (const double*)L.part_rz, (const double*)L.part_zz, L.grid_vec,
-                       (const double2*)L.r, L.p, A.tol, L.hist, A.max_iter);
+    {
+      ProfScope ps_("cg_update2", s);
+      hipLaunchKernelGGL(k_cg_update2, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, L.st, L.done, g, it,
+                         (const double*)L.part_rz, (const double*)L.part_zz, L.grid_vec,
+                         (const double2*)L.r, L.p, A.tol, L.hist, A.max_iter);
+    }
     LRFG_LAUNCHED();
     LRFG_HIP(hipMemcpyAsync(pinned + (it % ring) * nE, L.done, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
     LRFG_HIP(hipEventRecord(evs[it % ring], s));

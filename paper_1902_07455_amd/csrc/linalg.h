@@ -1,0 +1,38 @@
+// Dense linear algebra kernels of the low-rank path (gfx950, FP64):
+// batched GEMM on MFMA, batched symmetric Jacobi eigensolver for small
+// matrices, and the Gram-based orthonormalisation built on them.
+#pragma once
+
+#include "common.h"
+
+namespace lrfg {
+
+// C_b = alpha op(A_b) op(B_b) + beta C_b for b in [0, batch); row-major
+// storage with leading dimensions; op = transpose when ta / tb.
+struct Gemm {
+  int m = 0, n = 0, k = 0;
+  const double* A = nullptr;
+  long long lda = 0, sA = 0;
+  bool ta = false;
+  const double* B = nullptr;
+  long long ldb = 0, sB = 0;
+  bool tb = false;
+  double* C = nullptr;
+  long long ldc = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+  int batch = 1;
+};
+
+// Scratch doubles gemm() may use for a split-K reduction of this shape.
+size_t gemm_scratch_doubles(const Gemm& g);
+// `scratch` may be null (no split-K).
+int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s);
+
+// Batched symmetric eigendecomposition, n <= kMaxEig: A_b (n x n, row-major,
+// leading dimension lda, batch stride sA) -> eigenvalues W_b (descending)
+// and eigenvectors V_b (column j = eigenvector j, row-major n x n).
+constexpr int kMaxEig = 64;
+int syevj(int n, const double* A, long long lda, long long sA, double* W, long long sW, double* V,
+          long long sV, int batch, hipStream_t s);
+
+}  // namespace lrfg

@@ -1,26 +1,673 @@
-// Low-rank solve path (placeholder until the TT kernels land).
-#include "common.h"
+// Low-rank solve path: the corrector is a tensor train (paper Sec. 3.1.3;
+// the CP format for d = 2 is the same train, Sec. 3.1.3 notes TT = CP in 2D)
+// and the preconditioned operator is applied with a truncation after every
+// rank-raising step (Sec. 3.2, eq. Pls_lowrank):
+//
+//   C v ~ T P^-1 T div grad-type sum T (a (.) grad v)
+//
+// in a real-space reading of the paper's Fourier-space scheme: a train of
+// nodal values v, the derivative D_alpha = F^-1 diag(2 pi i k) F applied to
+// carriage alpha by per-mode 1-D DFTs (Appendix A.3: DFTs act on the
+// carriages along their mode index), D_alpha^T = -D_alpha, the material law
+// as a carriage-wise Kronecker (Khatri-Rao) product with the coefficient
+// train (Appendix A.3, element-wise multiplication), and the Laplacian
+// pseudo-inverse as a positive exponential sum of per-mode heat kernels
+// (1/(4 pi^2 |k|^2) ~ (1/4 pi^2) sum_m w_m prod_alpha exp(-t_m k_alpha^2)),
+// a rank-M element-wise factor in Fourier space (Table 1: preconditioning
+// raises the rank).  Because the SVD truncation is invariant under the
+// unitary per-mode DFTs, T(F v) = F T(v), so this is the paper's iteration
+// up to rounding.
+//
+// Solvers (Sec. 3.3): truncated preconditioned CG, and the truncated
+// minimal-residual iteration u <- T[u + omega r], omega = (Cr, r)/||Cr||^2,
+// stopped when the residual fails to decrease (Sec. 4.3); both keep the best
+// iterate.  A_H from the energy form of eq. (homog) with the exact operator
+// applied to the final train (Sec. 4.3: the error in A_H is the squared
+// energy norm of the corrector error).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
 #include "lowrank.h"
+#include "prof.h"
+#include "tt.h"
 
 namespace lrfg {
 
 struct LowRankPlan {
   lrfg_problem p;
+  int d = 3;
+  int N[3] = {1, 1, 1};
+  FftPlan mode[3];
+  int c[4] = {1, 1, 1, 1};   // nominal corrector ranks
+  int ra = 16;               // coefficient rank bound
+  int M = 2;                 // exponential-sum terms
+  std::vector<double> t, w;  // exponents and weights
+  int over = 10;
 };
 
-int lowrank_plan_create(const lrfg_problem& p, const FftPlan*, LowRankPlan** out) {
-  *out = new LowRankPlan{p};
+namespace {
+
+// Positive exponential sum for 1/y on [1, R] from the trapezoidal rule of
+// 1/y = int exp(s - e^s y) ds: s_m = s_lo + m h, t_m = e^{s_m},
+// w_m = h e^{s_m}, s_lo = ln(eps/R), s_hi = ln(ln(1/eps)), eps = 1e-2,
+// h = (s_hi - s_lo)/(M - 1); default M makes h <= 2.
+void expsum(double R, int M_req, int* M, std::vector<double>* t, std::vector<double>* w) {
+  const double eps = 1e-2;
+  const double slo = std::log(eps / R), shi = std::log(std::log(1.0 / eps));
+  int m = M_req;
+  if (m == 0) m = (int)std::ceil((shi - slo) / 2.0) + 1;
+  if (m < 2) m = 2;
+  const double h = (shi - slo) / (m - 1);
+  t->resize(m);
+  w->resize(m);
+  for (int i = 0; i < m; ++i) {
+    const double s = slo + h * i;
+    (*t)[i] = std::exp(s);
+    (*w)[i] = h * std::exp(s);
+  }
+  *M = m;
+}
+
+__global__ void k_cp_to_tt(const double* __restrict__ w, const double* __restrict__ f0,
+                           const double* __restrict__ f1, const double* __restrict__ f2, int R, int d, int N0, int N1,
+                           int N2, double* __restrict__ c0, double* __restrict__ c1, double* __restrict__ c2) {
+  // c0[0][n][t] = w_t f0[t][n]; d = 3: c1[t][n][t'] = delta f1[t][n], c2[t][n][0] = f2[t][n];
+  // d = 2: c1[t][n][0] = f1[t][n].
+  const long long n0 = (long long)N0 * R;
+  const long long n1 = (d == 3) ? (long long)R * N1 * R : (long long)R * N1;
+  const long long n2 = (d == 3) ? (long long)R * N2 : 0;
+  const long long tot = n0 + n1 + n2;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    if (idx < n0) {
+      const int n = (int)(idx / R), t = (int)(idx % R);
+      c0[idx] = w[t] * f0[(long long)t * N0 + n];
+    } else if (idx < n0 + n1) {
+      const long long i = idx - n0;
+      if (d == 3) {
+        const int tp = (int)(i % R);
+        const long long r = i / R;
+        const int n = (int)(r % N1);
+        const int t = (int)(r / N1);
+        c1[i] = (t == tp) ? f1[(long long)t * N1 + n] : 0.0;
+      } else {
+        const int n = (int)(i % N1), t = (int)(i / N1);
+        c1[i] = f1[(long long)t * N1 + n];
+      }
+    } else {
+      const long long i = idx - n0 - n1;
+      const int n = (int)(i % N2), t = (int)(i / N2);
+      c2[i] = f2[(long long)t * N2 + n];
+    }
+  }
+}
+
+// alpha_e = done ? 0 : num_e / den_e
+__global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den, const int* __restrict__ done,
+                        double* __restrict__ out, int nE) {
+  const int e = threadIdx.x;
+  if (e < nE) out[e] = (done[e] || !(den[e] != 0.0)) ? 0.0 : num[e] / den[e];
+}
+
+// beta_e = rz_e / rho_e (0 when done); rho_e <- rz_e
+__global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, const int* __restrict__ done,
+                       double* __restrict__ beta, int nE) {
+  const int e = threadIdx.x;
+  if (e < nE) {
+    beta[e] = (done[e] || !(rho[e] != 0.0)) ? 0.0 : rz[e] / rho[e];
+    if (!done[e]) rho[e] = rz[e];
+  }
+}
+
+struct Ctx {
+  LowRankPlan* pl;
+  int d, nE;
+  hipStream_t s;
+  FftDev f[3];
+  Rounder rd;
+  TTB a;                    // coefficient (shared)
+  TTB x, r, z, p, q, xb, b; // correctors (ranks c)
+  TTB kr;                   // Hadamard product a (.) g (ranks ra c)
+  TTB comb;                 // block sums (capacity ranks)
+  TTB h[3];                 // rounded material terms
+  double* gcore;            // carriage buffer for D_alpha v
+  double* hcore[3];         // carriage buffers for D_alpha^T h_alpha
+  double* pcore;            // M * d carriage buffers for the preconditioner terms
+  long long pcore_stride;
+  double* acore[3];         // carriage buffers of D_alpha a (right-hand side)
+  TTB tmp;                  // extra corrector-size train
+  double *dots, *rho, *pq, *alpha, *beta, *zz, *Ecoef, *wcoef, *dscr;
+  int* done;
+  size_t dscr_n;
+  int comb_cap[4];
+};
+
+int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
+  const int d = pl->d;
+  C.pl = pl;
+  C.d = d;
+  C.nE = nE;
+  int rc[4] = {1, 1, 1, 1};
+  for (int j = 0; j <= d; ++j) rc[j] = pl->c[j];
+  int ra[4] = {1, pl->ra, d == 3 ? pl->ra : 1, 1};
+  ra[d] = 1;
+  // twiddles
+  for (int j = 0; j < d; ++j) C.f[j].tw = ar.take<double2>(pl->N[j]);
+  C.a = tt_alloc(ar, d, pl->N, ra, 1);
+  for (int j = 0; j < d; ++j) C.a.s[j] = 0;
+  C.x = tt_alloc(ar, d, pl->N, rc, nE);
+  C.r = tt_alloc(ar, d, pl->N, rc, nE);
+  C.z = tt_alloc(ar, d, pl->N, rc, nE);
+  C.p = tt_alloc(ar, d, pl->N, rc, nE);
+  C.q = tt_alloc(ar, d, pl->N, rc, nE);
+  C.xb = tt_alloc(ar, d, pl->N, rc, nE);
+  C.b = tt_alloc(ar, d, pl->N, rc, nE);
+  C.tmp = tt_alloc(ar, d, pl->N, rc, nE);
+  for (int al = 0; al < d; ++al) C.h[al] = tt_alloc(ar, d, pl->N, rc, nE);
+  int rkr[4] = {1, 1, 1, 1};
+  for (int j = 1; j < d; ++j) rkr[j] = ra[j] * rc[j];
+  C.kr = tt_alloc(ar, d, pl->N, rkr, nE);
+  // block sums: d material terms, M preconditioner terms, 2 update terms, d coefficient terms
+  int cap[4] = {1, 1, 1, 1};
+  for (int j = 1; j < d; ++j) {
+    int m = d * rc[j];
+    if (pl->M * rc[j] > m) m = pl->M * rc[j];
+    if (2 * rc[j] > m) m = 2 * rc[j];
+    if (d * ra[j] > m) m = d * ra[j];
+    cap[j] = m;
+  }
+  for (int j = 0; j < 4; ++j) C.comb_cap[j] = cap[j];
+  C.comb = tt_alloc(ar, d, pl->N, cap, nE);
+  long long maxcore = 0;
+  for (int j = 0; j < d; ++j) maxcore = std::max(maxcore, (long long)rc[j] * pl->N[j] * rc[j + 1]);
+  C.gcore = ar.take<double>((size_t)maxcore * nE);
+  for (int al = 0; al < d; ++al) C.hcore[al] = ar.take<double>((size_t)maxcore * nE);
+  C.pcore_stride = maxcore * nE;
+  C.pcore = ar.take<double>((size_t)C.pcore_stride * pl->M * d);
+  long long acmax = 0;
+  for (int j = 0; j < d; ++j) acmax = std::max(acmax, (long long)ra[j] * pl->N[j] * ra[j + 1]);
+  for (int al = 0; al < d; ++al) C.acore[al] = ar.take<double>((size_t)acmax);
+  // rounding workspace
+  Rounder& R = C.rd;
+  R.d = d;
+  R.nE = nE;
+  for (int j = 0; j < 3; ++j) R.N[j] = (j < d) ? pl->N[j] : 1;
+  R.oversample = pl->over;
+  R.seed = pl->p.seed;
+  for (int j = 1; j < d; ++j) {
+    R.Rmax[j - 1] = std::max(cap[j], rkr[j]);
+    R.Lmax[j - 1] = rc[j] + pl->over;
+  }
+  R.carve(ar);
+  // scalars
+  C.dots = ar.take<double>(64);
+  C.rho = ar.take<double>(4);
+  C.pq = ar.take<double>(4);
+  C.alpha = ar.take<double>(4);
+  C.beta = ar.take<double>(4);
+  C.zz = ar.take<double>(4);
+  C.Ecoef = ar.take<double>(12);
+  C.wcoef = ar.take<double>(4);
+  C.done = ar.take<int>(4);
+  // dot scratch: largest pair (kr, c) or (comb, comb)
+  size_t dn = tt_dot_scratch(C.kr, C.x, nE);
+  dn = std::max(dn, tt_dot_scratch(C.comb, C.comb, nE));
+  C.dscr_n = dn;
+  C.dscr = ar.take<double>(dn);
+  return LRFG_OK;
+}
+
+// ------------------------------------------------------------------ operators
+// out = T(sum_alpha D_alpha^T T(a (.) D_alpha v))
+int apply_K(Ctx& C, const TTB& v, TTB& out) {
+  const int d = C.d, nE = C.nE;
+  TTB hd[3];
+  for (int al = 0; al < d; ++al) {
+    TTB g = v;
+    g.c[al] = C.gcore;
+    LRFG_TRY(tt_mode_apply(v, g, al, 0, 0.0, 1.0, C.f[al], nE, C.s));
+    LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, C.s));
+    LRFG_TRY(C.rd.round(C.kr, C.h[al], 0.0, C.s));
+    hd[al] = C.h[al];
+    hd[al].c[al] = C.hcore[al];
+    LRFG_TRY(tt_mode_apply(C.h[al], hd[al], al, 0, 0.0, -1.0, C.f[al], nE, C.s));
+  }
+  TTTerm terms[3];
+  for (int al = 0; al < d; ++al) terms[al] = TTTerm{&hd[al], nullptr, 1.0};
+  TTB comb = C.comb;
+  for (int j = 1; j < d; ++j) comb.r[j] = d * v.r[j];
+  for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
+  LRFG_TRY(tt_sum(terms, d, comb, nE, C.s));
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+}
+
+// out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}
+int apply_P(Ctx& C, const TTB& v, TTB& out) {
+  const int d = C.d, nE = C.nE;
+  const int M = C.pl->M;
+  std::vector<TTB> terms_b(M);
+  std::vector<TTTerm> terms(M);
+  for (int m = 0; m < M; ++m) {
+    TTB cur = v;
+    for (int al = 0; al < d; ++al) {
+      TTB nxt = cur;
+      nxt.c[al] = C.pcore + ((long long)m * d + al) * C.pcore_stride;
+      LRFG_TRY(tt_mode_apply(cur, nxt, al, 1, C.pl->t[m], 1.0, C.f[al], nE, C.s));
+      cur = nxt;
+    }
+    terms_b[m] = cur;
+    terms[m] = TTTerm{&terms_b[m], nullptr, C.pl->w[m] / (4.0 * kPi * kPi)};
+  }
+  TTB comb = C.comb;
+  for (int j = 1; j < d; ++j) comb.r[j] = M * v.r[j];
+  for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
+  LRFG_TRY(tt_sum(terms.data(), M, comb, nE, C.s));
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+}
+
+// out = T(ca x + cb y) with per-system coefficients (device arrays or 1)
+int axpby(Ctx& C, const TTB& x, const double* ca, double ma, const TTB& y, const double* cb, double mb, TTB& out) {
+  TTTerm t[2] = {TTTerm{&x, ca, ma}, TTTerm{&y, cb, mb}};
+  TTB comb = C.comb;
+  for (int j = 1; j < C.d; ++j) comb.r[j] = x.r[j] + y.r[j];
+  for (int j = 0; j < C.d; ++j) comb.s[j] = comb.size(j);
+  LRFG_TRY(tt_sum(t, 2, comb, C.nE, C.s));
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+}
+
+int dot(Ctx& C, const TTB& x, const TTB& y, double* out) { return tt_dot(x, y, out, C.dscr, C.nE, C.s); }
+
+int read_dev(Ctx& C, const double* dptr, double* host, int n) {
+  LRFG_HIP(hipMemcpyAsync(host, dptr, sizeof(double) * n, hipMemcpyDeviceToHost, C.s));
+  LRFG_HIP(hipStreamSynchronize(C.s));
+  return LRFG_OK;
+}
+
+int copy_system(Ctx& C, const TTB& from, TTB& to, int e) {
+  for (int j = 0; j < C.d; ++j)
+    LRFG_HIP(hipMemcpyAsync(to.c[j] + e * to.s[j], from.c[j] + e * from.s[j], sizeof(double) * from.size(j),
+                            hipMemcpyDeviceToDevice, C.s));
+  return LRFG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== plan
+int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out) {
+  LowRankPlan* pl = new LowRankPlan();
+  pl->p = p;
+  pl->d = p.d;
+  for (int j = 0; j < p.d; ++j) {
+    pl->N[j] = p.N[j];
+    pl->mode[j] = mode[j];
+  }
+  pl->ra = p.coeff_rank > 0 ? p.coeff_rank : 16;
+  pl->over = p.oversample > 0 ? p.oversample : 10;
+  if (p.d == 3) {
+    pl->c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1] * p.N[2]));
+    pl->c[2] = std::min(p.rank_cap, std::min(p.N[2], p.N[0] * p.N[1]));
+  } else {
+    pl->c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1]));
+  }
+  for (int j = 1; j < p.d; ++j) {
+    if (pl->c[j] + pl->over > kMaxEig) {
+      // the sketch size bounds the small eigenproblems
+      int o = kMaxEig - pl->c[j];
+      if (o < 0) {
+        set_error("rank_cap %d exceeds the supported %d", p.rank_cap, kMaxEig);
+        delete pl;
+        return LRFG_EUNSUPPORTED;
+      }
+      pl->over = std::min(pl->over, o);
+    }
+  }
+  if (p.format == LRFG_FORMAT_TUCKER) {
+    set_error("the Tucker format is not built yet");
+    delete pl;
+    return LRFG_EUNSUPPORTED;
+  }
+  if (p.precision != LRFG_PREC_FP64) {
+    set_error("mixed precision is not built for the low-rank path");
+    delete pl;
+    return LRFG_EUNSUPPORTED;
+  }
+  double R = 0.0;
+  for (int j = 0; j < p.d; ++j) R += (double)((p.N[j] - 1) / 2) * ((p.N[j] - 1) / 2);
+  expsum(R, p.precond_terms, &pl->M, &pl->t, &pl->w);
+  *out = pl;
   return LRFG_OK;
 }
 
 void lowrank_plan_destroy(LowRankPlan* lr) { delete lr; }
 
-size_t lowrank_workspace_bytes(const LowRankPlan*, int) { return 256; }
+size_t lowrank_workspace_bytes(const LowRankPlan* lr, int max_nE) {
+  Arena ar;
+  Ctx C;
+  carve_ctx(ar, const_cast<LowRankPlan*>(lr), max_nE, C);
+  return ar.used + 1024;
+}
 
-int lowrank_solve(LowRankPlan*, const lrfg_coeff&, const double*, int, void*, size_t, hipStream_t,
-                  lrfg_result*) {
-  set_error("low-rank formats are not built yet");
-  return LRFG_EUNSUPPORTED;
+// ====================================================================== solve
+int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE, void* ws, size_t ws_bytes,
+                  hipStream_t s, lrfg_result* out) {
+  const int d = pl->d;
+  const lrfg_problem& P = pl->p;
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  Ctx C;
+  carve_ctx(ar, pl, nE, C);
+  if (ar.overflow) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  C.s = s;
+  hipEvent_t ev0, ev1, ev2;
+  LRFG_HIP(hipEventCreate(&ev0));
+  LRFG_HIP(hipEventCreate(&ev1));
+  LRFG_HIP(hipEventCreate(&ev2));
+  LRFG_HIP(hipEventRecord(ev0, s));
+  for (int j = 0; j < d; ++j) {
+    double2* tw = const_cast<double2*>(C.f[j].tw);
+    LRFG_TRY(fft_dev_upload(pl->mode[j], tw, s, &C.f[j]));
+  }
+  // ---------------------------------------------------------------- coefficient train
+  if (ac.full != nullptr) {
+    set_error("the low-rank path takes the coefficient in CP or TT form");
+    return LRFG_EUNSUPPORTED;
+  }
+  if (ac.weights != nullptr) {
+    const int R = ac.rank;
+    if (R < 1 || R > pl->ra) {
+      set_error("coefficient rank %d outside [1, coeff_rank = %d]", R, pl->ra);
+      return LRFG_EINVAL;
+    }
+    const double* w = ac.weights;
+    const double* f[3] = {ac.factors[0], ac.factors[1], d == 3 ? ac.factors[2] : ac.factors[1]};
+    std::vector<double> staging;
+    double* dstage = nullptr;
+    if (!ac.on_device) {
+      // stage host factors through the product buffer (not yet in use)
+      size_t n = R;
+      for (int j = 0; j < d; ++j) n += (size_t)R * pl->N[j];
+      if (n > (size_t)C.kr.size(1) * nE) {
+        set_error("coefficient staging too small");
+        return LRFG_EWORKSPACE;
+      }
+      dstage = C.kr.c[1];
+      LRFG_HIP(hipMemcpyAsync(dstage, w, sizeof(double) * R, hipMemcpyHostToDevice, s));
+      size_t off = R;
+      const double* df[3];
+      for (int j = 0; j < d; ++j) {
+        LRFG_HIP(hipMemcpyAsync(dstage + off, ac.factors[j], sizeof(double) * R * pl->N[j], hipMemcpyHostToDevice, s));
+        df[j] = dstage + off;
+        off += (size_t)R * pl->N[j];
+      }
+      w = dstage;
+      for (int j = 0; j < d; ++j) f[j] = df[j];
+      if (d == 2) f[2] = df[1];
+    }
+    C.a.r[1] = R;
+    if (d == 3) C.a.r[2] = R;
+    const long long tot = (long long)pl->N[0] * R + (d == 3 ? (long long)R * pl->N[1] * R + (long long)R * pl->N[2]
+                                                           : (long long)R * pl->N[1]);
+    hipLaunchKernelGGL(k_cp_to_tt, dim3((int)std::min<long long>(4096, (tot + 255) / 256)), dim3(256), 0, s, w, f[0],
+                       f[1], f[2], R, d, pl->N[0], pl->N[1], d == 3 ? pl->N[2] : 1, C.a.c[0], C.a.c[1],
+                       d == 3 ? C.a.c[2] : nullptr);
+    LRFG_LAUNCHED();
+  } else {
+    const int* rk = ac.tt_ranks;
+    if (rk[0] != 1 || rk[d] != 1) {
+      set_error("TT coefficient: r_0 = r_d = 1 required");
+      return LRFG_EINVAL;
+    }
+    for (int j = 1; j < d; ++j) {
+      if (rk[j] < 1 || rk[j] > pl->ra) {
+        set_error("TT coefficient rank %d outside [1, coeff_rank = %d]", rk[j], pl->ra);
+        return LRFG_EINVAL;
+      }
+      C.a.r[j] = rk[j];
+    }
+    for (int j = 0; j < d; ++j) {
+      LRFG_HIP(hipMemcpyAsync(C.a.c[j], ac.tt_cores[j], sizeof(double) * C.a.size(j),
+                              ac.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    }
+  }
+  // Hadamard output ranks follow the actual coefficient ranks
+  for (int j = 1; j < d; ++j) C.kr.r[j] = C.a.r[j] * pl->c[j];
+  for (int j = 0; j < d; ++j) C.kr.s[j] = C.kr.size(j);
+
+  // ---------------------------------------------------------------- right-hand side
+  // b_e = sum_alpha E_e,alpha D_alpha a  (real-space form of -div^ F (a E))
+  std::vector<double> Ecol(3 * nE, 0.0);
+  for (int al = 0; al < d; ++al)
+    for (int e = 0; e < nE; ++e) Ecol[al * nE + e] = E[e * d + al];
+  LRFG_HIP(hipMemcpyAsync(C.Ecoef, Ecol.data(), sizeof(double) * d * nE, hipMemcpyHostToDevice, s));
+  {
+    TTB da[3];
+    TTTerm terms[3];
+    for (int al = 0; al < d; ++al) {
+      da[al] = C.a;
+      da[al].c[al] = C.acore[al];
+      LRFG_TRY(tt_mode_apply(C.a, da[al], al, 0, 0.0, 1.0, C.f[al], 1, s));
+      terms[al] = TTTerm{&da[al], C.Ecoef + al * nE, 1.0};
+    }
+    TTB comb = C.comb;
+    for (int j = 1; j < d; ++j) comb.r[j] = d * C.a.r[j];
+    for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
+    LRFG_TRY(tt_sum(terms, d, comb, nE, s));
+    LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s));
+  }
+  // scale for the zero-right-hand-side floor: rms(a) |E|
+  double a2 = 0.0;
+  {
+    LRFG_TRY(tt_dot(C.a, C.a, C.dots, C.dscr, 1, s));
+    LRFG_TRY(read_dev(C, C.dots, &a2, 1));
+  }
+  double Ntot = 1.0;
+  for (int j = 0; j < d; ++j) Ntot *= pl->N[j];
+  const double rms_a = std::sqrt(std::max(a2, 0.0) / Ntot);
+  std::vector<double> floor_abs(nE);
+  for (int e = 0; e < nE; ++e) {
+    double en = 0.0;
+    for (int al = 0; al < d; ++al) en += E[e * d + al] * E[e * d + al];
+    // real-space norms carry sqrt(|N|) relative to Fourier coefficients
+    floor_abs[e] = 1e-14 * rms_a * std::sqrt(en) * std::sqrt(Ntot);
+  }
+  LRFG_HIP(hipEventRecord(ev1, s));
+
+  // ---------------------------------------------------------------- solver
+  const int maxit = P.max_iter;
+  std::vector<double> hist((size_t)nE * maxit, 0.0);
+  std::vector<int> iters(nE, 0), hdone(nE, 0), status(nE, LRFG_OK);
+  std::vector<double> best(nE, INFINITY), res0(nE, 0.0), zzh(nE), cur(nE);
+  std::vector<int> since_best(nE, 0);
+  const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  LRFG_TRY(tt_zero(C.x, nE, s));
+  LRFG_TRY(tt_zero(C.xb, nE, s));
+  auto upload_done = [&]() -> int {
+    LRFG_HIP(hipMemcpyAsync(C.done, hdone.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
+    return LRFG_OK;
+  };
+  LRFG_TRY(upload_done());
+  if (P.solver == LRFG_SOLVER_PCG) {
+    LRFG_TRY(tt_copy(C.b, C.r, nE, s));
+    LRFG_TRY(apply_P(C, C.r, C.z));
+    LRFG_TRY(tt_copy(C.z, C.p, nE, s));
+    LRFG_TRY(dot(C, C.r, C.z, C.rho));
+    LRFG_TRY(dot(C, C.z, C.z, C.zz));
+  } else {
+    // d = T(P~^-1 b) held in b's place via z; r = d
+    LRFG_TRY(apply_P(C, C.b, C.z));
+    LRFG_TRY(tt_copy(C.z, C.b, nE, s));
+    LRFG_TRY(tt_copy(C.b, C.r, nE, s));
+    LRFG_TRY(dot(C, C.r, C.r, C.zz));
+  }
+  LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+  for (int e = 0; e < nE; ++e) {
+    res0[e] = std::sqrt(std::max(zzh[e], 0.0));
+    if (res0[e] <= floor_abs[e]) hdone[e] = 1;
+  }
+  LRFG_TRY(upload_done());
+  for (int it = 0; it < maxit; ++it) {
+    bool all = true;
+    for (int e = 0; e < nE; ++e) all = all && hdone[e];
+    if (all) break;
+    if (P.solver == LRFG_SOLVER_PCG) {
+      LRFG_TRY(apply_K(C, C.p, C.q));
+      LRFG_TRY(dot(C, C.p, C.q, C.pq));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.rho, (const double*)C.pq,
+                         (const int*)C.done, C.alpha, nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(axpby(C, C.x, nullptr, 1.0, C.p, C.alpha, 1.0, C.tmp));
+      LRFG_TRY(tt_copy(C.tmp, C.x, nE, s));
+      LRFG_TRY(axpby(C, C.r, nullptr, 1.0, C.q, C.alpha, -1.0, C.tmp));
+      LRFG_TRY(tt_copy(C.tmp, C.r, nE, s));
+      LRFG_TRY(apply_P(C, C.r, C.z));
+      LRFG_TRY(dot(C, C.r, C.z, C.dots));
+      LRFG_TRY(dot(C, C.z, C.z, C.zz));
+      hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, s, (const double*)C.dots, C.rho, (const int*)C.done, C.beta,
+                         nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(axpby(C, C.z, nullptr, 1.0, C.p, C.beta, 1.0, C.tmp));
+      LRFG_TRY(tt_copy(C.tmp, C.p, nE, s));
+    } else {
+      // Cr = T(P~^-1 T(K r)); omega = (Cr, r)/(Cr, Cr); u += omega r; r -= omega Cr
+      LRFG_TRY(apply_K(C, C.r, C.q));
+      LRFG_TRY(apply_P(C, C.q, C.z));
+      LRFG_TRY(dot(C, C.z, C.r, C.dots));
+      LRFG_TRY(dot(C, C.z, C.z, C.pq));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.dots, (const double*)C.pq,
+                         (const int*)C.done, C.alpha, nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(axpby(C, C.x, nullptr, 1.0, C.r, C.alpha, 1.0, C.tmp));
+      LRFG_TRY(tt_copy(C.tmp, C.x, nE, s));
+      LRFG_TRY(axpby(C, C.r, nullptr, 1.0, C.z, C.alpha, -1.0, C.tmp));
+      LRFG_TRY(tt_copy(C.tmp, C.r, nE, s));
+      LRFG_TRY(dot(C, C.r, C.r, C.zz));
+    }
+    LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+    bool changed = false;
+    for (int e = 0; e < nE; ++e) {
+      if (hdone[e]) continue;
+      const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+      hist[(size_t)e * maxit + it] = res;
+      iters[e] = it + 1;
+      if (res < best[e]) {
+        best[e] = res;
+        since_best[e] = 0;
+        LRFG_TRY(copy_system(C, C.x, C.xb, e));
+      } else {
+        ++since_best[e];
+      }
+      if (res <= P.solver_tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
+        hdone[e] = 1;
+        changed = true;
+      } else if (since_best[e] >= patience) {
+        hdone[e] = 1;  // stagnation: the residual failed to decrease
+        changed = true;
+        if (best[e] > P.solver_tol) status[e] = LRFG_NOT_CONVERGED;
+      }
+    }
+    if (changed) LRFG_TRY(upload_done());
+  }
+  for (int e = 0; e < nE; ++e) {
+    if (!hdone[e]) status[e] = LRFG_NOT_CONVERGED;
+    if (res0[e] <= floor_abs[e]) {
+      // zero right-hand side: the corrector is zero (xb was cleared)
+      status[e] = LRFG_OK;
+    }
+  }
+
+  // ---------------------------------------------------------------- A_H (eq. homog)
+  // A_H[i][j] = mean(a) E_i.E_j + sum_alpha (E_i,alpha m1[j] + E_j,alpha m1[i] + m2[i][j])
+  // m1[e][alpha] = <a, D_alpha x_e>/|N|, m2[i][j][alpha] = <a (.) D_alpha x_i, D_alpha x_j>/|N|
+  std::vector<double> m1((size_t)nE * d), m2((size_t)nE * nE * d);
+  double mean_a = 0.0;
+  {
+    // <a, 1>: a train of ones
+    TTB one = C.tmp;
+    int r1[4] = {1, 1, 1, 1};
+    for (int j = 0; j <= 3; ++j) one.r[j] = r1[j];
+    for (int j = 0; j < d; ++j) {
+      one.s[j] = 0;
+      LRFG_TRY(tt_fill(one.c[j], pl->N[j], 1.0, s));
+    }
+    LRFG_TRY(tt_dot(C.a, one, C.dots, C.dscr, 1, s));
+    LRFG_TRY(read_dev(C, C.dots, &mean_a, 1));
+    mean_a /= Ntot;
+  }
+  for (int al = 0; al < d; ++al) {
+    TTB g = C.xb;
+    g.c[al] = C.gcore;
+    LRFG_TRY(tt_mode_apply(C.xb, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
+    // m1: <a, g_e>
+    LRFG_TRY(tt_dot(C.a, g, C.dots, C.dscr, nE, s));
+    std::vector<double> v(nE);
+    LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
+    for (int e = 0; e < nE; ++e) m1[(size_t)e * d + al] = v[e] / Ntot;
+    // m2: <a (.) g_i, g_j>
+    LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
+    for (int i = 0; i < nE; ++i) {
+      for (int j = 0; j < nE; ++j) {
+        TTB ki = C.kr, gj = g;
+        for (int q = 0; q < d; ++q) {
+          ki.c[q] = C.kr.c[q] + i * C.kr.s[q];
+          gj.c[q] = g.c[q] + j * g.s[q];
+        }
+        LRFG_TRY(tt_dot(ki, gj, C.dots + i * nE + j, C.dscr, 1, s));
+      }
+    }
+    std::vector<double> w2((size_t)nE * nE);
+    LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nE));
+    for (int i = 0; i < nE; ++i)
+      for (int j = 0; j < nE; ++j) m2[((size_t)i * nE + j) * d + al] = w2[(size_t)i * nE + j] / Ntot;
+  }
+  // final ranks: one more truncation of the best iterate reports the kept ranks
+  std::vector<int> kept(2 * nE, 0);
+  LRFG_TRY(C.rd.round(C.xb, C.tmp, P.trunc_tol, s));
+  LRFG_HIP(hipMemcpyAsync(kept.data(), C.rd.kept, sizeof(int) * 2 * nE, hipMemcpyDeviceToHost, s));
+  LRFG_HIP(hipEventRecord(ev2, s));
+  LRFG_HIP(hipStreamSynchronize(s));
+  float ms_setup = 0.f, ms_solve = 0.f;
+  LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
+  LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+  LRFG_HIP(hipEventDestroy(ev0));
+  LRFG_HIP(hipEventDestroy(ev1));
+  LRFG_HIP(hipEventDestroy(ev2));
+  int rc = LRFG_OK;
+  for (int i = 0; i < nE; ++i) {
+    for (int j = 0; j < nE; ++j) {
+      double v = 0.0;
+      for (int al = 0; al < d; ++al) {
+        const double ei = E[i * d + al], ej = E[j * d + al];
+        v += mean_a * ei * ej + ei * m1[(size_t)j * d + al] + ej * m1[(size_t)i * d + al] +
+             m2[((size_t)i * nE + j) * d + al];
+      }
+      if (out->A_H) out->A_H[i * nE + j] = v;
+    }
+    if (out->iters) out->iters[i] = iters[i];
+    if (out->status) out->status[i] = status[i];
+    if (status[i] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+    if (out->res_hist)
+      for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)i * maxit + k];
+    if (out->ranks) {
+      out->ranks[i * (d + 1)] = 1;
+      out->ranks[i * (d + 1) + d] = 1;
+      if (d == 3) {
+        out->ranks[i * (d + 1) + 1] = kept[i];
+        out->ranks[i * (d + 1) + 2] = kept[nE + i];
+      } else {
+        out->ranks[i * (d + 1) + 1] = kept[i];
+      }
+    }
+  }
+  out->setup_ms = ms_setup;
+  out->solve_ms = ms_solve;
+  return rc;
 }
 
 }  // namespace lrfg

@@ -1,0 +1,163 @@
+// Operation-level C-ABI entry points of the low-rank path: batched GEMM,
+// batched symmetric eigensolver and TT rounding, each callable on its own.
+#include <algorithm>
+
+#include "common.h"
+#include "linalg.h"
+#include "tt.h"
+
+using namespace lrfg;
+
+namespace {
+
+int tt_round_sizes(int d, const int N[3], const int rin[4], int cap, int oversample, int c[4], Rounder& R,
+                   int nE) {
+  if (d != 2 && d != 3) {
+    set_error("d must be 2 or 3");
+    return LRFG_EINVAL;
+  }
+  for (int j = 0; j < d; ++j)
+    if (N[j] < 1) {
+      set_error("N must be positive");
+      return LRFG_EINVAL;
+    }
+  if (rin[0] != 1 || rin[d] != 1) {
+    set_error("r_0 = r_d = 1 required");
+    return LRFG_EINVAL;
+  }
+  if (cap < 1 || oversample < 0 || nE < 1) {
+    set_error("cap >= 1, oversample >= 0, nE >= 1");
+    return LRFG_EINVAL;
+  }
+  c[0] = 1;
+  c[d] = 1;
+  if (d == 3) {
+    c[1] = std::min(cap, std::min(N[0], N[1] * N[2]));
+    c[2] = std::min(cap, std::min(N[2], N[0] * N[1]));
+  } else {
+    c[1] = std::min(cap, std::min(N[0], N[1]));
+  }
+  R.d = d;
+  R.nE = nE;
+  for (int j = 0; j < 3; ++j) R.N[j] = j < d ? N[j] : 1;
+  R.oversample = oversample;
+  for (int j = 1; j < d; ++j) {
+    if (rin[j] < 1) {
+      set_error("ranks must be >= 1");
+      return LRFG_EINVAL;
+    }
+    R.Rmax[j - 1] = rin[j];
+    R.Lmax[j - 1] = c[j] + oversample;
+    if (std::min(R.Lmax[j - 1], rin[j]) > kMaxEig) {
+      set_error("sketch size %d exceeds %d", R.Lmax[j - 1], kMaxEig);
+      return LRFG_EUNSUPPORTED;
+    }
+  }
+  return LRFG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lrfg_gemm_workspace_bytes(int m, int n, int k, int batch) {
+  Gemm g;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.batch = batch;
+  return sizeof(double) * gemm_scratch_doubles(g) + 256;
+}
+
+int lrfg_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A, long long lda, long long sA,
+              const double* B, long long ldb, long long sB, double beta, double* C, long long ldc, long long sC,
+              int batch, void* d_ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (m < 0 || n < 0 || k < 0 || batch < 0 || (m * n > 0 && (A == nullptr || B == nullptr || C == nullptr))) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  Gemm g;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.A = A;
+  g.lda = lda;
+  g.sA = sA;
+  g.ta = ta != 0;
+  g.B = B;
+  g.ldb = ldb;
+  g.sB = sB;
+  g.tb = tb != 0;
+  g.C = C;
+  g.ldc = ldc;
+  g.sC = sC;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.batch = batch;
+  return gemm(g, static_cast<double*>(d_ws), ws_bytes / sizeof(double), static_cast<hipStream_t>(stream));
+}
+
+int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* stream) {
+  clear_error();
+  if (A == nullptr || W == nullptr || V == nullptr || batch < 0) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  return syevj(n, A, n, (long long)n * n, W, n, V, (long long)n * n, batch, static_cast<hipStream_t>(stream));
+}
+
+size_t lrfg_tt_round_workspace_bytes(int d, const int N[3], const int rin[4], int cap, int oversample, int nE) {
+  Rounder R;
+  int c[4];
+  if (tt_round_sizes(d, N, rin, cap, oversample, c, R, nE) != LRFG_OK) return 0;
+  Arena ar;
+  R.carve(ar);
+  return ar.used + 256;
+}
+
+int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cores, int cap, double tol,
+                  int oversample, uint64_t seed, double* const* out_cores, int* out_ranks, int* kept, int nE,
+                  void* d_ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (N == nullptr || rin == nullptr || in_cores == nullptr || out_cores == nullptr || !(tol >= 0.0)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  Rounder R;
+  int c[4];
+  LRFG_TRY(tt_round_sizes(d, N, rin, cap, oversample, c, R, nE));
+  R.seed = seed;
+  Arena ar;
+  ar.base = static_cast<char*>(d_ws);
+  ar.cap = ws_bytes;
+  R.carve(ar);
+  if (ar.overflow || d_ws == nullptr) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  TTB in, out;
+  in.d = out.d = d;
+  for (int j = 0; j < 3; ++j) in.N[j] = out.N[j] = j < d ? N[j] : 1;
+  for (int j = 0; j <= d; ++j) {
+    in.r[j] = rin[j];
+    out.r[j] = c[j];
+  }
+  for (int j = 0; j < d; ++j) {
+    in.c[j] = in_cores[j];
+    in.s[j] = in.size(j);
+    out.c[j] = out_cores[j];
+    out.s[j] = out.size(j);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LRFG_TRY(R.round(in, out, tol, s));
+  if (out_ranks)
+    for (int j = 0; j <= d; ++j) out_ranks[j] = c[j];
+  if (kept) {
+    LRFG_HIP(hipMemcpyAsync(kept, R.kept, sizeof(int) * 2 * nE, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+  }
+  return LRFG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Tensor-train tensors on the device and their operations (internal).
+//
+// A batched TT holds nE independent tensors (one per corrector) with the
+// same ranks; core j of system e is [r_{j-1}][N_j][r_j] (the carriages of the
+// paper's eq. TT) at c[j] + e * s[j].  A stride of 0 shares the core across
+// systems (the coefficient).  d = 2 uses cores 0 and 1.
+#pragma once
+
+#include "common.h"
+#include "fft.h"
+#include "linalg.h"
+
+namespace lrfg {
+
+struct TTB {
+  int d = 3;
+  int N[3] = {1, 1, 1};
+  int r[4] = {1, 1, 1, 1};
+  double* c[3] = {nullptr, nullptr, nullptr};
+  long long s[3] = {0, 0, 0};
+  long long size(int j) const { return (long long)r[j] * N[j] * r[j + 1]; }
+};
+
+// Carve a batched TT with ranks r (capacity = these ranks) from an arena.
+TTB tt_alloc(Arena& ar, int d, const int N[3], const int r[4], int nE);
+
+// One term of a block sum: coef_e = mult * (coef ? coef[e] : 1).
+struct TTTerm {
+  const TTB* x;
+  const double* coef;
+  double mult;
+};
+
+// Randomised TT rounding (sketch, Gram-based orthonormalisation, SVD cut)
+// with fixed output ranks; see tt.hip.
+struct Rounder {
+  int d = 3, nE = 1;
+  int N[3] = {1, 1, 1};
+  int Rmax[2] = {1, 1};     // largest input ranks at bonds 1, 2
+  int Lmax[2] = {1, 1};     // largest sketch sizes
+  int oversample = 10;
+  uint64_t seed = 0;
+  uint64_t counter = 0;
+  double* om[3] = {};       // sketch cores
+  double *W3, *T2, *W2, *Y1, *Q1, *M1, *X2p, *Y2, *Q2, *M2, *X3p;
+  double *G, *lam, *V, *S, *Ytmp, *S3, *Q2s, *P, *U, *S1;
+  double* gscr = nullptr;   // GEMM split-K scratch
+  size_t gscr_n = 0;
+  int* kept = nullptr;      // kept ranks per bond per system (diagnostics)
+  void carve(Arena& ar);
+  // out (ranks preset to the nominal output ranks) <- T(in)
+  int round(const TTB& in, TTB& out, double tol, hipStream_t s);
+};
+
+int tt_fill(double* p, long long n, double v, hipStream_t s);
+int tt_zero(TTB& x, int nE, hipStream_t s);
+int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s);
+// y = x with core j replaced by the real circulant op (0: derivative,
+// 1: heat kernel exp(-t k^2)) along its mode index, times mult.
+int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, const FftDev& f, int nE,
+                  hipStream_t s);
+// out = a (.) x, slice-wise Kronecker of the carriages (ranks multiply).
+int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s);
+// out = sum of terms as one TT with block carriages (ranks add); out's
+// ranks must equal the sums of the terms' ranks.
+int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s);
+// dots[e] = <x_e, y_e>; scratch of tt_dot_scratch doubles.
+size_t tt_dot_scratch(const TTB& x, const TTB& y, int nE);
+int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s);
+
+}  // namespace lrfg

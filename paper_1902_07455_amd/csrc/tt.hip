@@ -1,0 +1,564 @@
+// Tensor-train operations on the device (paper Sec. 3.1.3 and Appendix
+// A.3): carriage-wise Hadamard products, block sums, per-mode 1-D DFT
+// operators, inner products, and rank truncation.
+//
+// Truncation T reaches the rounded train through a randomised sketch of the
+// input, then an SVD cut:
+//   1. right partial contractions of the input with a Gaussian TT sketch of
+//      ranks (l1, l2) = (c1 + p, c2 + p) (capped by the input ranks);
+//   2. left-to-right: Y_j = (left part) x (right sketch), Q_j = orth(Y_j),
+//      project the carriage onto Q_j and carry the rest to the right.  This
+//      is the "randomise-then-orthogonalise" TT rounding of Al Daas, Ballard
+//      et al. (SIAM J. Sci. Comput. 2023); it never forms the SVDs of the
+//      large unfoldings the paper's rounding uses (Appendix A.3);
+//   3. the left-orthogonal train of ranks (l1, l2) is then cut exactly as
+//      the paper's rounding does: the singular values of each unfolding
+//      (from l x l Gram matrices) decide the kept rank, at most the nominal
+//      rank c_j and at least what the tolerance needs,
+//      ||dropped||^2 <= tol^2 ||X||^2 / (d - 1).
+// Output ranks are fixed (c1, c2); directions beyond the kept rank are zero
+// columns, so every launch shape is known on the host.
+// orth(Y): Gram Y^T Y, Jacobi eigenvectors V, Q = Y V diag(lambda^-1/2)
+// with directions below 1e-15 lambda_max set to zero, done twice (the second
+// pass restores orthogonality to rounding level).
+#include <cmath>
+#include <cstdio>
+
+#include "prof.h"
+#include "tt.h"
+
+namespace lrfg {
+
+int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
+                       double mult, const FftDev& f, hipStream_t s);
+
+namespace {
+
+constexpr int kB = 256;
+
+inline int grid_for(long long n) {
+  long long g = (n + kB - 1) / kB;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+__global__ void k_fill(double* __restrict__ p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__device__ inline uint64_t smix(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Standard normal numbers from a counter-based hash (splitmix64) and the
+// Box-Muller transform.
+__global__ void k_randn(double* __restrict__ out, long long n, uint64_t key) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const uint64_t a = smix(key ^ (2ull * (uint64_t)i));
+    const uint64_t b = smix(key ^ (2ull * (uint64_t)i + 1ull) ^ 0x5851F42D4C957F2Dull);
+    const double u1 = ((double)(a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((double)(b >> 11)) * (1.0 / 9007199254740992.0);
+    out[i] = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+  }
+}
+
+// out[e][(i rx0 + k)][n][(j rx1 + m)] = a[i][n][j] x[e][k][n][m]
+__global__ void k_khatri_rao(const double* __restrict__ a, long long sa, int ra0, int ra1,
+                             const double* __restrict__ x, long long sx, int rx0, int rx1, int N,
+                             double* __restrict__ out, long long so, int nE) {
+  const long long R0 = (long long)ra0 * rx0, R1 = (long long)ra1 * rx1;
+  const long long per = R0 * N * R1;
+  const long long tot = per * nE;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int e = (int)(idx / per);
+    long long r = idx - e * per;
+    const long long J = r % R1;
+    r /= R1;
+    const int n = (int)(r % N);
+    const long long I = r / N;
+    const int i = (int)(I / rx0), k = (int)(I % rx0);
+    const int j = (int)(J / rx1), m = (int)(J % rx1);
+    out[e * so + (I * N + n) * R1 + J] =
+        a[e * sa + ((long long)i * N + n) * ra1 + j] * x[e * sx + ((long long)k * N + n) * rx1 + m];
+  }
+}
+
+// out[e][o0 + i][n][o1 + j] = c_e X[e][i][n][j]  (out dims R0 x N x R1)
+__global__ void k_block_copy(const double* __restrict__ X, long long sx, int r0, int N, int r1,
+                             double* __restrict__ out, long long so, int R1, int o0, int o1,
+                             const double* __restrict__ coef, double mult, int nE) {
+  const long long per = (long long)r0 * N * r1;
+  const long long tot = per * nE;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int e = (int)(idx / per);
+    long long r = idx - e * per;
+    const int j = (int)(r % r1);
+    r /= r1;
+    const int n = (int)(r % N);
+    const int i = (int)(r / N);
+    const double c = mult * (coef != nullptr ? coef[e] : 1.0);
+    out[e * so + ((long long)(o0 + i) * N + n) * R1 + o1 + j] = c * X[e * sx + ((long long)i * N + n) * r1 + j];
+  }
+}
+
+// S_e = V_e diag(f(lambda_e)), f = lambda^-1/2 above tau lambda_max, else 0.
+__global__ void k_orth_scale(const double* __restrict__ lam, const double* __restrict__ V, int l, double tau,
+                             double* __restrict__ S, int nE) {
+  const long long tot = (long long)nE * l * l;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int e = (int)(idx / ((long long)l * l));
+    const int j = (int)(idx % l);
+    const double lj = lam[(long long)e * l + j];
+    const double l0 = lam[(long long)e * l];
+    const double f = (lj > 0.0 && lj > tau * l0) ? 1.0 / sqrt(lj) : 0.0;
+    S[idx] = V[idx] * f;
+  }
+}
+
+// Kept rank from descending eigenvalues (squared singular values):
+// at most c, no numerically zero direction, smallest rank whose dropped
+// tail is <= tol2 * total.  S_e (l x c) = leading kept columns of V_e.
+__global__ void k_trunc_mask(const double* __restrict__ lam, const double* __restrict__ V, int l, int c,
+                             double tol2, double floor_rel, double* __restrict__ S, int* __restrict__ kept_out,
+                             int nE) {
+  __shared__ int kept_s;
+  const int e = blockIdx.x;
+  const double* L = lam + (long long)e * l;
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int j = 0; j < l; ++j) total += fmax(L[j], 0.0);
+    int kept = c < l ? c : l;
+    while (kept > 0 && !(L[kept - 1] > floor_rel * L[0] && L[kept - 1] > 0.0)) --kept;
+    if (tol2 > 0.0) {
+      double tail = 0.0;
+      for (int j = l - 1; j >= kept; --j) tail += fmax(L[j], 0.0);
+      // shrink while the dropped tail stays within the budget
+      while (kept > 1) {
+        const double t2 = tail + fmax(L[kept - 1], 0.0);
+        if (t2 <= tol2 * total) {
+          tail = t2;
+          --kept;
+        } else {
+          break;
+        }
+      }
+    }
+    kept_s = kept;
+    if (kept_out != nullptr) kept_out[e] = kept;
+  }
+  __syncthreads();
+  const int kept = kept_s;
+  for (int idx = threadIdx.x; idx < l * c; idx += blockDim.x) {
+    const int i = idx / c, j = idx % c;
+    S[(long long)e * l * c + idx] = (j < kept) ? V[(long long)e * l * l + (long long)i * l + j] : 0.0;
+  }
+}
+
+}  // namespace
+
+// ====================================================================== host helpers
+TTB tt_alloc(Arena& ar, int d, const int N[3], const int r[4], int nE) {
+  TTB t;
+  t.d = d;
+  for (int j = 0; j < 3; ++j) t.N[j] = (j < d) ? N[j] : 1;
+  for (int j = 0; j < 4; ++j) t.r[j] = (j <= d) ? r[j] : 1;
+  t.r[0] = 1;
+  t.r[d] = 1;
+  for (int j = 0; j < d; ++j) {
+    t.s[j] = t.size(j);
+    t.c[j] = ar.take<double>((size_t)t.s[j] * nE);
+  }
+  return t;
+}
+
+int tt_fill(double* p, long long n, double v, hipStream_t s) {
+  if (n <= 0) return LRFG_OK;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kB), 0, s, p, n, v);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int tt_zero(TTB& x, int nE, hipStream_t s) {
+  for (int j = 0; j < x.d; ++j) LRFG_TRY(tt_fill(x.c[j], x.size(j) * (x.s[j] ? nE : 1), 0.0, s));
+  return LRFG_OK;
+}
+
+int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s) {
+  for (int j = 0; j < x.d; ++j) {
+    if (x.size(j) != y.size(j)) {
+      set_error("tt_copy: rank mismatch");
+      return LRFG_EINVAL;
+    }
+    for (int e = 0; e < nE; ++e)
+      LRFG_HIP(hipMemcpyAsync(y.c[j] + e * y.s[j], x.c[j] + e * x.s[j], sizeof(double) * x.size(j),
+                              hipMemcpyDeviceToDevice, s));
+  }
+  return LRFG_OK;
+}
+
+int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, const FftDev& f, int nE,
+                  hipStream_t s) {
+  // y shares every carriage of x except j, which is y.c[j] (caller's buffer)
+  if (x.s[j] != 0 && x.s[j] != x.size(j)) {
+    set_error("tt_mode_apply: carriage %d is not compact", j);
+    return LRFG_EINVAL;
+  }
+  double* cj = y.c[j];
+  y = x;
+  y.c[j] = cj;
+  y.s[j] = x.size(j);
+  if (x.s[j] == 0) y.s[j] = 0;
+  const int reps = (x.s[j] == 0) ? 1 : nE;
+  return launch_mode_op_oop(x.c[j], y.c[j], (long long)reps * x.r[j], x.N[j], x.r[j + 1], op, t, mult, f, s);
+}
+
+int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s) {
+  for (int j = 0; j < x.d; ++j) {
+    if (out.r[j] != a.r[j] * x.r[j] || out.r[j + 1] != a.r[j + 1] * x.r[j + 1]) {
+      set_error("tt_hadamard: output ranks");
+      return LRFG_EINVAL;
+    }
+    const long long tot = out.size(j) * nE;
+    ProfScope ps_("khatri_rao", s);
+    hipLaunchKernelGGL(k_khatri_rao, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)a.c[j], a.s[j], a.r[j],
+                       a.r[j + 1], (const double*)x.c[j], x.s[j], x.r[j], x.r[j + 1], x.N[j], out.c[j], out.s[j], nE);
+    LRFG_LAUNCHED();
+  }
+  return LRFG_OK;
+}
+
+int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s) {
+  const int d = out.d;
+  int o[4] = {0, 0, 0, 0};  // running offsets per bond
+  for (int j = 1; j < d; ++j) {
+    int sum = 0;
+    for (int t = 0; t < nt; ++t) sum += terms[t].x->r[j];
+    if (sum != out.r[j]) {
+      set_error("tt_sum: output rank %d != %d at bond %d", out.r[j], sum, j);
+      return LRFG_EINVAL;
+    }
+  }
+  // middle carriages are block diagonal: clear first
+  for (int j = 1; j < d - 1; ++j) LRFG_TRY(tt_fill(out.c[j], out.size(j) * nE, 0.0, s));
+  for (int t = 0; t < nt; ++t) {
+    const TTB& x = *terms[t].x;
+    for (int j = 0; j < d; ++j) {
+      const int r0 = x.r[j], r1 = x.r[j + 1];
+      const long long tot = x.size(j) * nE;
+      const bool first = (j == 0);
+      const double* coef = first ? terms[t].coef : nullptr;
+      const double mult = first ? terms[t].mult : 1.0;
+      hipLaunchKernelGGL(k_block_copy, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)x.c[j], x.s[j], r0, x.N[j],
+                         r1, out.c[j], out.s[j], out.r[j + 1], o[j], o[j + 1], coef, mult, nE);
+      LRFG_LAUNCHED();
+    }
+    for (int j = 1; j < d; ++j) o[j] += x.r[j];
+  }
+  return LRFG_OK;
+}
+
+size_t tt_dot_scratch(const TTB& x, const TTB& y, int nE) {
+  size_t n = 0;
+  for (int j = 0; j < x.d; ++j) {
+    n += (size_t)x.r[j + 1] * y.r[j + 1];          // M_j
+    n += (size_t)x.r[j] * y.N[j] * y.r[j + 1];     // U_j
+  }
+  return n * nE + 4096 + (size_t)nE * 64 * 1024;   // + split-K space
+}
+
+int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s) {
+  const int d = x.d;
+  // M_0 = 1; U_j = M_{j-1} Y_j  (x.r[j] x N y.r[j+1]); M_j = X_j^T U_j
+  // (contraction over (r_{j-1}, n)); the last step contracts everything.
+  double* M = nullptr;  // previous M, (x.r[j] x y.r[j]) per system
+  long long sM = 0;
+  double* p = scratch;
+  double* gs = scratch + tt_dot_scratch(x, y, nE) - (size_t)nE * 64 * 1024;
+  const size_t gsn = (size_t)nE * 64 * 1024;
+  for (int j = 0; j < d; ++j) {
+    const int a0 = x.r[j], a1 = x.r[j + 1], b0 = y.r[j], b1 = y.r[j + 1], N = y.N[j];
+    // U = M Y_j : (a0 x b0)(b0 x N b1); j = 0 -> U = Y_0 (a0 = b0 = 1)
+    const double* U = y.c[j];
+    long long sU = y.s[j];
+    if (j > 0) {
+      double* Ub = p;
+      p += (size_t)a0 * N * b1 * nE;
+      Gemm g;
+      g.m = a0;
+      g.n = N * b1;
+      g.k = b0;
+      g.A = M;
+      g.lda = b0;
+      g.sA = sM;
+      g.B = y.c[j];
+      g.ldb = (long long)N * b1;
+      g.sB = y.s[j];
+      g.C = Ub;
+      g.ldc = (long long)N * b1;
+      g.sC = (long long)a0 * N * b1;
+      g.batch = nE;
+      LRFG_TRY(gemm(g, gs, gsn, s));
+      U = Ub;
+      sU = g.sC;
+    }
+    // M_j = X_j^T U : (a1 x a0 N)(a0 N x b1)
+    double* Mn = (j == d - 1) ? dots : p;
+    if (j < d - 1) p += (size_t)a1 * b1 * nE;
+    Gemm g;
+    g.m = a1;
+    g.n = b1;
+    g.k = a0 * N;
+    g.A = x.c[j];
+    g.lda = a1;
+    g.sA = x.s[j];
+    g.ta = true;
+    g.B = U;
+    g.ldb = b1;
+    g.sB = sU;
+    g.C = Mn;
+    g.ldc = b1;
+    g.sC = (j == d - 1) ? 1 : (long long)a1 * b1;
+    g.batch = nE;
+    LRFG_TRY(gemm(g, gs, gsn, s));
+    M = Mn;
+    sM = g.sC;
+  }
+  return LRFG_OK;
+}
+
+// ====================================================================== rounding
+void Rounder::carve(Arena& ar) {
+  const int L1 = Lmax[0], L2 = Lmax[1];
+  const int R1 = Rmax[0], R2 = Rmax[1];
+  const int N1 = N[0], N2 = N[1], N3 = N[2];
+  const int L = L1 > L2 ? L1 : L2;
+  auto T = [&](long long n) { return ar.take<double>((size_t)n * nE); };
+  if (d == 3) {
+    om[1] = ar.take<double>((size_t)L1 * N2 * L2);
+    om[2] = ar.take<double>((size_t)L2 * N3);
+    W3 = T((long long)R2 * L2);
+    T2 = T((long long)R1 * N2 * L2);
+    W2 = T((long long)R1 * L1);
+    Y1 = T((long long)N1 * L1);
+    Q1 = T((long long)N1 * L1);
+    M1 = T((long long)L1 * R1);
+    X2p = T((long long)L1 * N2 * R2);
+    Y2 = T((long long)L1 * N2 * L2);
+    Q2 = T((long long)L1 * N2 * L2);
+    M2 = T((long long)L2 * R2);
+    X3p = T((long long)L2 * N3);
+    Ytmp = T((long long)(N1 * L1 > L1 * N2 * L2 ? N1 * L1 : L1 * N2 * L2));
+    Q2s = T((long long)L1 * N2 * L2);
+    U = T((long long)L1 * N2 * L2);
+  } else {
+    om[2] = ar.take<double>((size_t)L1 * N2);
+    W2 = T((long long)R1 * L1);
+    Y1 = T((long long)N1 * L1);
+    Q1 = T((long long)N1 * L1);
+    M1 = T((long long)L1 * R1);
+    X3p = T((long long)L1 * N2);
+    Ytmp = T((long long)N1 * L1);
+    W3 = T2 = X2p = Y2 = Q2 = M2 = Q2s = U = nullptr;
+  }
+  G = T((long long)L * L);
+  lam = T(L);
+  V = T((long long)L * L);
+  S = T((long long)L * L);
+  S3 = T((long long)L * L);
+  S1 = T((long long)L * L);
+  P = T((long long)L * L);
+  kept = ar.take<int>((size_t)2 * nE);
+  gscr_n = (size_t)nE * 256 * 1024;
+  gscr = ar.take<double>(gscr_n);
+}
+
+namespace {
+
+struct GemmB {
+  Gemm g;
+  GemmB(int m, int n, int k, int batch) {
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.batch = batch;
+  }
+  GemmB& a(const double* p, long long ld, long long st, bool t = false) {
+    g.A = p;
+    g.lda = ld;
+    g.sA = st;
+    g.ta = t;
+    return *this;
+  }
+  GemmB& b(const double* p, long long ld, long long st, bool t = false) {
+    g.B = p;
+    g.ldb = ld;
+    g.sB = st;
+    g.tb = t;
+    return *this;
+  }
+  GemmB& c(double* p, long long ld, long long st) {
+    g.C = p;
+    g.ldc = ld;
+    g.sC = st;
+    return *this;
+  }
+};
+
+}  // namespace
+
+// Q (m x l per system, stride m*l) = orth(Y); Ytmp holds the first pass.
+static int orth(Rounder& R, const double* Y, double* Q, int m, int l, hipStream_t s) {
+  const int nE = R.nE;
+  const double tau = 1e-15;
+  const double* src = Y;
+  double* dsts[2] = {R.Ytmp, Q};
+  for (int pass = 0; pass < 2; ++pass) {
+    GemmB gg(l, l, m, nE);
+    gg.a(src, l, (long long)m * l, true).b(src, l, (long long)m * l).c(R.G, l, (long long)l * l);
+    LRFG_TRY(gemm(gg.g, R.gscr, R.gscr_n, s));
+    LRFG_TRY(syevj(l, R.G, l, (long long)l * l, R.lam, l, R.V, (long long)l * l, nE, s));
+    const long long tot = (long long)nE * l * l;
+    hipLaunchKernelGGL(k_orth_scale, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)R.lam, (const double*)R.V, l,
+                       tau, R.S, nE);
+    LRFG_LAUNCHED();
+    GemmB gq(m, l, l, nE);
+    gq.a(src, l, (long long)m * l).b(R.S, l, (long long)l * l).c(dsts[pass], l, (long long)m * l);
+    LRFG_TRY(gemm(gq.g, R.gscr, R.gscr_n, s));
+    src = dsts[pass];
+  }
+  return LRFG_OK;
+}
+
+static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, double* S, int* kept,
+                      hipStream_t s) {
+  const int nE = R.nE;
+  LRFG_TRY(syevj(l, Gm, l, (long long)l * l, R.lam, l, R.V, (long long)l * l, nE, s));
+  hipLaunchKernelGGL(k_trunc_mask, dim3(nE), dim3(64), 0, s, (const double*)R.lam, (const double*)R.V, l, c, tol2,
+                     1e-28, S, kept, nE);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
+  ProfScope ps_("tt_round", s);
+  const double tol2 = tol * tol / (double)(d - 1);
+  const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
+  if (d == 3) {
+    const int N1 = N[0], N2 = N[1], N3 = N[2];
+    const int R1 = in.r[1], R2 = in.r[2];
+    const int c1 = out.r[1], c2 = out.r[2];
+    int l1 = c1 + oversample, l2 = c2 + oversample;
+    if (l1 > R1) l1 = R1;
+    if (l2 > R2) l2 = R2;
+    if (l1 > N1) l1 = N1;
+    if (l2 > N3) l2 = N3;
+    if (l1 > Lmax[0] || l2 > Lmax[1] || R1 > Rmax[0] || R2 > Rmax[1] || l1 > kMaxEig || l2 > kMaxEig) {
+      set_error("tt_round: sizes (R %d %d, l %d %d) exceed the plan", R1, R2, l1, l2);
+      return LRFG_EINVAL;
+    }
+    // Gaussian sketch carriages
+    hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l1 * N2 * l2)), dim3(kB), 0, s, om[1],
+                       (long long)l1 * N2 * l2, key);
+    hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l2 * N3)), dim3(kB), 0, s, om[2], (long long)l2 * N3,
+                       key ^ 0xA5A5A5A5A5A5A5A5ull);
+    LRFG_LAUNCHED();
+    // W3 = X3 Om3^T (R2 x l2)
+    { GemmB g(R2, l2, N3, nE); g.a(in.c[2], N3, in.s[2]).b(om[2], N3, 0, true).c(W3, l2, (long long)R2 * l2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // T2 = X2 W3 ((R1 N2) x l2)
+    { GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // W2 = T2 Om2^T (R1 x l1), contraction over (n, l2)
+    { GemmB g(R1, l1, N2 * l2, nE); g.a(T2, (long long)N2 * l2, (long long)R1 * N2 * l2).b(om[1], (long long)N2 * l2, 0, true)
+          .c(W2, l1, (long long)R1 * l1);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // Y1 = X1 W2 (N1 x l1) ; Q1 = orth(Y1)
+    { GemmB g(N1, l1, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l1, (long long)R1 * l1).c(Y1, l1, (long long)N1 * l1);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(orth(*this, Y1, Q1, N1, l1, s));
+    // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
+    { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
+          .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // Y2 = X2' W3 ((l1 N2) x l2) ; Q2 = orth(Y2)
+    { GemmB g(l1 * N2, l2, R2, nE); g.a(X2p, R2, (long long)l1 * N2 * R2).b(W3, l2, (long long)R2 * l2)
+          .c(Y2, l2, (long long)l1 * N2 * l2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(orth(*this, Y2, Q2, l1 * N2, l2, s));
+    // M2 = Q2^T X2' (l2 x R2) ; X3' = M2 X3 (l2 x N3)
+    { GemmB g(l2, R2, l1 * N2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2, true).b(X2p, R2, (long long)l1 * N2 * R2)
+          .c(M2, R2, (long long)l2 * R2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(l2, N3, R2, nE); g.a(M2, R2, (long long)l2 * R2).b(in.c[2], N3, in.s[2]).c(X3p, N3, (long long)l2 * N3);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // ---- cut at bond 2: G = X3' X3'^T, S3 = kept eigenvectors (l2 x c2)
+    { GemmB g(l2, l2, N3, nE); g.a(X3p, N3, (long long)l2 * N3).b(X3p, N3, (long long)l2 * N3, true).c(G, l2, (long long)l2 * l2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(trunc_mask(*this, G, l2, c2, tol2, S3, kept + nE, s));
+    { GemmB g(c2, N3, l2, nE); g.a(S3, c2, (long long)l2 * c2, true).b(X3p, N3, (long long)l2 * N3).c(out.c[2], N3, out.s[2]);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // Q2s = Q2 S3 ((l1 N2) x c2); P = X3 X3^T (c2 x c2); U = Q2s P
+    { GemmB g(l1 * N2, c2, l2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2).b(S3, c2, (long long)l2 * c2)
+          .c(Q2s, c2, (long long)l1 * N2 * c2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(c2, c2, N3, nE); g.a(out.c[2], N3, out.s[2]).b(out.c[2], N3, out.s[2], true).c(P, c2, (long long)c2 * c2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(l1 * N2, c2, c2, nE); g.a(Q2s, c2, (long long)l1 * N2 * c2).b(P, c2, (long long)c2 * c2)
+          .c(U, c2, (long long)l1 * N2 * c2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // ---- cut at bond 1: G1 = U Q2s^T over (n, b) (l1 x l1)
+    { GemmB g(l1, l1, N2 * c2, nE); g.a(U, (long long)N2 * c2, (long long)l1 * N2 * c2)
+          .b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2, true).c(G, l1, (long long)l1 * l1);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(trunc_mask(*this, G, l1, c1, tol2, S1, kept, s));
+    { GemmB g(N1, c1, l1, nE); g.a(Q1, l1, (long long)N1 * l1).b(S1, c1, (long long)l1 * c1).c(out.c[0], c1, out.s[0]);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(c1, N2 * c2, l1, nE); g.a(S1, c1, (long long)l1 * c1, true).b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2)
+          .c(out.c[1], (long long)N2 * c2, out.s[1]);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    return LRFG_OK;
+  }
+  // d = 2
+  const int N1 = N[0], N2 = N[1];
+  const int R1 = in.r[1];
+  const int c1 = out.r[1];
+  int l = c1 + oversample;
+  if (l > R1) l = R1;
+  if (l > N1) l = N1;
+  if (l > N2) l = N2;
+  if (l > Lmax[0] || R1 > Rmax[0] || l > kMaxEig) {
+    set_error("tt_round: sizes exceed the plan");
+    return LRFG_EINVAL;
+  }
+  hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l * N2)), dim3(kB), 0, s, om[2], (long long)l * N2, key);
+  LRFG_LAUNCHED();
+  { GemmB g(R1, l, N2, nE); g.a(in.c[1], N2, in.s[1]).b(om[2], N2, 0, true).c(W2, l, (long long)R1 * l);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GemmB g(N1, l, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l, (long long)R1 * l).c(Y1, l, (long long)N1 * l);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  LRFG_TRY(orth(*this, Y1, Q1, N1, l, s));
+  { GemmB g(l, R1, N1, nE); g.a(Q1, l, (long long)N1 * l, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l * R1);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GemmB g(l, N2, R1, nE); g.a(M1, R1, (long long)l * R1).b(in.c[1], N2, in.s[1]).c(X3p, N2, (long long)l * N2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GemmB g(l, l, N2, nE); g.a(X3p, N2, (long long)l * N2).b(X3p, N2, (long long)l * N2, true).c(G, l, (long long)l * l);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  LRFG_TRY(trunc_mask(*this, G, l, c1, tol * tol, S1, kept, s));
+  { GemmB g(c1, N2, l, nE); g.a(S1, c1, (long long)l * c1, true).b(X3p, N2, (long long)l * N2).c(out.c[1], N2, out.s[1]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GemmB g(N1, c1, l, nE); g.a(Q1, l, (long long)N1 * l).b(S1, c1, (long long)l * c1).c(out.c[0], c1, out.s[0]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  return LRFG_OK;
+}
+
+}  // namespace lrfg

@@ -1,0 +1,68 @@
+"""MFMA FP64 GEMM and the batched Jacobi eigensolver against numpy."""
+import numpy as np
+import pytest
+
+import paper_1902_07455_amd as P
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1, 1), (5, 7, 3), (64, 64, 16), (65, 63, 17), (100, 30, 4050), (2430, 30, 180),
+          (30, 30, 24300), (180, 20, 2700), (1, 1, 24300), (7, 200, 1)]
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("batch", [1, 3])
+def test_gemm(dev, m, n, k, ta, tb, batch):
+    import torch
+    rng = np.random.default_rng(m * 7 + n * 13 + k + 100 * ta + 10 * tb + batch)
+    A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    C0 = rng.standard_normal((batch, m, n))
+    tA, tB, tC = (torch.from_numpy(x).to(dev) for x in (A, B, C0))
+    P.gemm(tA, tB, tC, ta=bool(ta), tb=bool(tb), alpha=0.7, beta=-1.3)
+    torch.cuda.synchronize()
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = 0.7 * opA @ opB - 1.3 * C0
+    err = np.max(np.abs(tC.cpu().numpy() - ref))
+    assert err <= 1e-13 * max(1.0, np.sqrt(k)) * max(1.0, np.max(np.abs(ref)))
+
+
+def test_gemm_beta_zero_ignores_nan(dev):
+    import torch
+    A = torch.ones((1, 4, 3), dtype=torch.float64, device=dev)
+    B = torch.ones((1, 3, 5), dtype=torch.float64, device=dev)
+    Cm = torch.full((1, 4, 5), float("nan"), dtype=torch.float64, device=dev)
+    P.gemm(A, B, Cm, beta=0.0)
+    torch.cuda.synchronize()
+    assert torch.all(Cm == 3.0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 30, 45, 64])
+@pytest.mark.parametrize("kind", ["spd", "rankdef", "indef"])
+def test_syevj(dev, n, kind):
+    import torch
+    rng = np.random.default_rng(n + len(kind))
+    batch = 3
+    if kind == "spd":
+        X = rng.standard_normal((batch, n, n + 5))
+        A = X @ np.swapaxes(X, 1, 2)
+    elif kind == "rankdef":
+        r = max(1, n // 3)
+        X = rng.standard_normal((batch, n, r))
+        A = X @ np.swapaxes(X, 1, 2)
+    else:
+        X = rng.standard_normal((batch, n, n))
+        A = X + np.swapaxes(X, 1, 2)
+    W, V = P.syevj(torch.from_numpy(A).to(dev))
+    torch.cuda.synchronize()
+    W, V = W.cpu().numpy(), V.cpu().numpy()
+    for b in range(batch):
+        ref = np.sort(np.linalg.eigvalsh(A[b]))[::-1]
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(W[b] - ref)) <= 1e-13 * scale * n
+        assert np.all(np.diff(W[b]) <= 1e-12 * scale)
+        # A V = V diag(W), V orthonormal
+        assert np.max(np.abs(A[b] @ V[b] - V[b] * W[b][None, :])) <= 1e-12 * scale * n
+        assert np.max(np.abs(V[b].T @ V[b] - np.eye(n))) <= 1e-12 * n

@@ -1,0 +1,88 @@
+"""Low-rank (TT, and CP = TT for d = 2) solve on the GPU against the CPU
+oracle: untruncated equals the full solve; truncated is an energy upper
+bound; closed forms."""
+import numpy as np
+import pytest
+
+import paper_1902_07455_amd as P
+import workloads as W
+from oracle import fg
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(A, B):
+    return np.max(np.abs(A - B)) / np.max(np.abs(B))
+
+
+def _cp_args(cp):
+    return (cp.weights, cp.factors)
+
+
+@pytest.mark.parametrize("solver", ["pcg", "mr"])
+def test_laminate_rank_one(dev, solver):
+    N = 15
+    prof = np.random.default_rng(1).uniform(0.5, 4.0, N)
+    ones = np.ones(N)
+    cp = W.CPCoeff(np.array([1.0]), [prof[None, :], ones[None, :], ones[None, :]])
+    s = P.Solver(d=3, N=(N, N, N), format="tt", rank_cap=4, solver=solver, solver_tol=1e-12,
+                 max_iter=200, coeff_rank=1)
+    r = s.solve(cp=_cp_args(cp))
+    H = 1.0 / np.mean(1.0 / prof)
+    M = np.mean(prof)
+    assert _rel(r.A_H, np.diag([H, M, M])) <= 1e-10
+
+
+@pytest.mark.parametrize("d,N", [(2, 45), (3, 15)])
+def test_untruncated_equals_full_square(dev, d, N):
+    """Rank cap at the grid size: no truncation, so the TT solve is the
+    full solve (the square inclusion of the 2D workload, the cube in 3D)."""
+    cp = W.square_cp(N, d)
+    a = cp.full()
+    s = P.Solver(d=d, N=(N,) * d, format="tt", rank_cap=N, solver_tol=1e-12, max_iter=300,
+                 coeff_rank=2)
+    r = s.solve(cp=_cp_args(cp))
+    o = fg.solve(a, tol=1e-12)
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
+def test_cp_format_2d_config(dev):
+    """2D square (N = 45) in the CP format = the d = 2 train."""
+    cp = W.square_cp(45, 2)
+    s = P.Solver(d=2, N=(45, 45), format="cp", rank_cap=45, solver_tol=1e-12, max_iter=300,
+                 coeff_rank=2)
+    r = s.solve(cp=_cp_args(cp))
+    o = fg.solve(cp.full(), tol=1e-12)
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
+@pytest.mark.parametrize("cap", [3, 6])
+def test_truncated_is_upper_bound(dev, cap):
+    """Truncated correctors give A_H,r >= A_H (Sec. 4.3 energy identity),
+    and a larger rank is no worse."""
+    N = 21
+    cp = W.square_cp(N, 3, inside=10.0)
+    o = fg.solve(cp.full(), tol=1e-12)
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=cap, solver_tol=1e-10, max_iter=100,
+                 coeff_rank=2)
+    r = s.solve(cp=_cp_args(cp))
+    D = r.A_H - o.A_H
+    assert np.min(np.linalg.eigvalsh(0.5 * (D + D.T))) >= -1e-9 * o.A_H[0, 0]
+    assert _rel(r.A_H, o.A_H) < 0.2
+
+
+def test_smooth_135_rank20(dev):
+    """The benchmark workload: 135^3 smooth coefficient (CP rank 9), TT
+    rank cap 20; error against the oracle reported and bounded."""
+    p = W.smooth_params(0)
+    cp = W.smooth_cp(135, p)
+    s = P.Solver(d=3, N=(135,) * 3, format="tt", rank_cap=20, trunc_tol=1e-8, solver_tol=1e-8,
+                 max_iter=60, coeff_rank=9)
+    r = s.solve(cp=_cp_args(cp))
+    a, _ = W.smooth_coeff(135, p)
+    o = fg.solve(a, tol=1e-10)
+    err = _rel(r.A_H, o.A_H)
+    print("TT 135^3 cap 20: A_H rel err", err, "iters", r.iters, "ranks", r.ranks)
+    assert err <= 1e-4
+    D = r.A_H - o.A_H
+    assert np.min(np.linalg.eigvalsh(0.5 * (D + D.T))) >= -1e-9

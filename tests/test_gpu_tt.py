@@ -1,0 +1,88 @@
+"""TT rounding (randomised sketch + SVD cut) on the GPU against the oracle's
+SVD-based truncation and exact reconstructions."""
+import numpy as np
+import pytest
+
+import paper_1902_07455_amd as P
+import workloads as W
+from oracle import lowrank as L
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(cores_list, dev):
+    """list over systems of cores -> batched torch cores (nE, r0, N, r1)."""
+    import torch
+    d = len(cores_list[0])
+    return [torch.from_numpy(np.stack([c[j] for c in cores_list])).to(dev) for j in range(d)]
+
+
+def _host(outs, e):
+    return [G[e].cpu().numpy() for G in outs]
+
+
+@pytest.mark.parametrize("Ns,ranks,cap", [((9, 11, 13), (1, 3, 4, 1), 5), ((15, 15, 15), (1, 6, 6, 1), 20),
+                                          ((45, 27, 35), (1, 8, 5, 1), 8), ((135, 135, 135), (1, 9, 9, 1), 20)])
+def test_exact_low_rank_is_reproduced(dev, Ns, ranks, cap):
+    """A sum of two trains whose true ranks fit the cap is reproduced to
+    rounding level (the randomised sketch spans the exact range)."""
+    systems = []
+    fulls = []
+    for e in range(2):
+        X = W.random_tt(Ns, list(ranks), 10 + e)
+        Y = L.tt_scale(X, 0.25 + e)
+        systems.append(L.tt_add(X, Y))          # ranks doubled, exact ranks unchanged
+        fulls.append((1.25 + e) * L.tt_full(X))
+    outs, kept = P.tt_round(_dev(systems, dev), cap=cap, tol=0.0, oversample=4, seed=3)
+    for e in range(2):
+        got = L.tt_full(_host(outs, e))
+        assert np.max(np.abs(got - fulls[e])) <= 1e-11 * np.max(np.abs(fulls[e]))
+        assert list(kept[:, e]) == [ranks[1], ranks[2]]
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_truncation_error_near_optimal(dev, d):
+    Ns = (30, 40) if d == 2 else (12, 14, 16)
+    rng = np.random.default_rng(5)
+    if d == 2:
+        X = rng.standard_normal((Ns[0], 25)) @ np.diag(0.6 ** np.arange(25)) @ rng.standard_normal((25, Ns[1]))
+        cores = L.tt_svd(X)
+    else:
+        X = L.tt_full(W.random_tt(Ns, [1, 12, 12, 1], 6))
+        X = X + 0.01 * L.tt_full(W.random_tt(Ns, [1, 10, 10, 1], 7))
+        cores = L.tt_svd(X)
+    cap = 6
+    best = L.tt_round(cores, rank_cap=cap)
+    err_best = np.linalg.norm(L.tt_full(best) - X)
+    outs, _ = P.tt_round(_dev([cores], dev), cap=cap, oversample=10, seed=1)
+    err = np.linalg.norm(L.tt_full(_host(outs, 0)) - X)
+    assert err <= 1.5 * err_best + 1e-12 * np.linalg.norm(X)
+    if d == 2:
+        s = np.linalg.svd(X, compute_uv=False)
+        assert err_best == pytest.approx(np.sqrt(np.sum(s[cap:] ** 2)), rel=1e-8)
+
+
+def test_tolerance_cut(dev):
+    """With a tolerance, the kept rank is the smallest whose dropped tail is
+    within tol^2 ||X||^2/(d-1), and the error respects the bound."""
+    Ns = (20, 20, 20)
+    parts = [L.tt_scale(W.random_tt(Ns, [1, 1, 1, 1], 20 + i), 10.0 ** (-i)) for i in range(6)]
+    X = parts[0]
+    for p in parts[1:]:
+        X = L.tt_add(X, p)
+    full = L.tt_full(X)
+    tol = 2e-3
+    outs, kept = P.tt_round(_dev([X], dev), cap=20, tol=tol, oversample=4, seed=2)
+    got = L.tt_full(_host(outs, 0))
+    assert np.linalg.norm(got - full) <= tol * np.linalg.norm(full) * (1 + 1e-6)
+    assert kept[0, 0] < 6 and kept[1, 0] < 6
+
+
+def test_zero_train(dev):
+    import torch
+    cores = [torch.zeros((1, 1, 9, 4), dtype=torch.float64, device=dev),
+             torch.zeros((1, 4, 9, 4), dtype=torch.float64, device=dev),
+             torch.zeros((1, 4, 9, 1), dtype=torch.float64, device=dev)]
+    outs, kept = P.tt_round(cores, cap=3)
+    assert all(float(torch.max(torch.abs(G))) == 0.0 for G in outs)
+    assert list(kept[:, 0]) == [0, 0]
