@@ -46,6 +46,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    ap.add_argument("--tt-steps", type=int, default=10)
+    ap.add_argument("--no-tt", action="store_true", help="skip the tensor-train leg")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
@@ -145,6 +147,60 @@ def main(argv=None):
                      "A_H_rel_err": err, "sweep": sweep},
         "roofline": roofline,
     }
+
+    # ---------------------------------------------------------------- TT leg
+    if not args.no_tt:
+        w_dev = torch.from_numpy(cp.weights).to(dev)
+        f_dev = [torch.from_numpy(f).to(dev) for f in cp.factors]
+
+        def tt_solver(cap, tol):
+            return P.Solver(d=3, N=(N, N, N), format="tt", rank_cap=cap, trunc_tol=0.0,
+                            solver_tol=tol, max_iter=100, coeff_rank=cp.rank, device=dev)
+
+        tt_sweep = []
+        tt_cap = None
+        for cap in [4, 6, 8, 10, 12, 16, 20]:
+            s = tt_solver(cap, 1e-8)
+            r = s.solve(cp=(w_dev, f_dev))
+            e = rel_err(r.A_H, A_ref)
+            tt_sweep.append(("cap", cap, e, r.iters.tolist()))
+            s.close()
+            if e <= TARGET_ERR:
+                tt_cap = cap
+                break
+        tt_tol = None
+        if tt_cap is not None:
+            for tol in [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]:
+                s = tt_solver(tt_cap, tol)
+                r = s.solve(cp=(w_dev, f_dev))
+                e = rel_err(r.A_H, A_ref)
+                tt_sweep.append(("tol", tol, e, r.iters.tolist()))
+                s.close()
+                if e <= TARGET_ERR:
+                    tt_tol = tol
+                    break
+        log(f"TT sweep: {tt_sweep}")
+        if tt_tol is not None:
+            tts = tt_solver(tt_cap, tt_tol)
+            r = tts.solve(cp=(w_dev, f_dev))
+            torch.cuda.synchronize()
+            tlat = []
+            t0 = time.perf_counter()
+            for _ in range(args.tt_steps):
+                ts = time.perf_counter()
+                r = tts.solve(cp=(w_dev, f_dev))
+                tlat.append((time.perf_counter() - ts) * 1e3)
+            torch.cuda.synchronize()
+            ttot = time.perf_counter() - t0
+            terr = rel_err(r.A_H, A_ref)
+            out["tt"] = {"solves_per_s": round(args.tt_steps / ttot, 3), "rank_cap": tt_cap,
+                         "solver_tol": tt_tol, "iters": r.iters.tolist(), "ranks": r.ranks.tolist(),
+                         "A_H_rel_err": terr, "ms_per_solve": round(1e3 * ttot / args.tt_steps, 3),
+                         "latency_ms": {"p50": round(float(np.percentile(tlat, 50)), 3),
+                                        "p99": round(float(np.percentile(tlat, 99)), 3)},
+                         "sweep": tt_sweep}
+        else:
+            out["tt"] = {"solves_per_s": None, "sweep": tt_sweep}
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:

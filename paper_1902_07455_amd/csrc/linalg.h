@@ -35,4 +35,10 @@ constexpr int kMaxEig = 64;
 int syevj(int n, const double* A, long long lda, long long sA, double* W, long long sW, double* V,
           long long sV, int batch, hipStream_t s);
 
+// Rank-revealing pivoted Cholesky of batched PSD G (n x n, stride sG):
+// S (n x n, stride sS) = P R^-1 on the numerical rank (zeros elsewhere),
+// so Y S is orthonormal when G = Y^T Y; rank (device, batch ints) or null.
+int pchol_s(int n, const double* G, long long sG, double tau, double* S, long long sS, int* rank, int batch,
+            hipStream_t s);
+
 }  // namespace lrfg

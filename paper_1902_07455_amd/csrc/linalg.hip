@@ -127,62 +127,70 @@ int choose_ksplit(const Gemm& g) {
 }
 
 // ---------------------------------------------------------------- Jacobi
-// One 64-thread block per matrix; A and V in LDS (stride n).  Cyclic
-// round-robin ordering: m = n rounded up to even, position 0 fixed, the
-// others rotate; pair k of step s joins positions k and m-1-k.  Rotation of
-// Golub and Van Loan's symmetric Schur step: tau = (a_qq - a_pp)/(2 a_pq),
-// t = sign(tau)/(|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1+t^2), s = t c;
-// rows: p' = c p - s q, q' = s p + c q; the same on columns and on V.
-__global__ __launch_bounds__(64) void k_syevj(int n, const double* __restrict__ Ag, long long lda,
-                                              long long sA, double* __restrict__ Wg, long long sW,
-                                              double* __restrict__ Vg, long long sV, int max_sweeps) {
+// One block per matrix (64 threads for n <= 32, else 256); A and V in LDS
+// (stride n).  Cyclic round-robin ordering: m = n rounded up to even,
+// position 0 fixed, the others rotate by one per step; pair k of a step
+// joins positions k and m-1-k, so the pairs of a step are disjoint.
+// Rotation of the symmetric Schur step (Golub and Van Loan):
+// tau = (a_qq - a_pp)/(2 a_pq), t = sign(tau)/(|tau| + sqrt(1 + tau^2)),
+// c = 1/sqrt(1 + t^2), s = t c, J = [[c, s], [-s, c]] on (p, q).
+// A <- J^T A J is applied as independent 2 x 2 blocks (pair k rows,
+// pair l columns), V <- V J row by row.
+__global__ void k_syevj(int n, const double* __restrict__ Ag, long long lda, long long sA,
+                        double* __restrict__ Wg, long long sW, double* __restrict__ Vg, long long sV,
+                        int max_sweeps) {
   extern __shared__ double sm[];
   double* a = sm;
   double* v = sm + n * n;
   __shared__ double cs[2 * 32];
   __shared__ int pq[2 * 32];
-  __shared__ double red[2];
+  __shared__ double red[2 * 4];
   const int b = blockIdx.x;
   const double* A = Ag + b * sA;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += 64) {
-    const int i = e / n, j = e % n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, j = e - (e / n) * n;
     a[e] = 0.5 * (A[(long long)i * lda + j] + A[(long long)j * lda + i]);
     v[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int m = n + (n & 1);
   const int np = m / 2;
+  const int nblk = np * np;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal mass against the total
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += 64) {
+    for (int e = tid; e < n * n; e += nt) {
       const double x = a[e] * a[e];
       tot += x;
-      if (e / n != e % n) off += x;
+      off += (e % (n + 1) != 0) ? x : 0.0;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_down(off, o, 64);
       tot += __shfl_down(tot, o, 64);
     }
-    if (tid == 0) {
-      red[0] = off;
-      red[1] = tot;
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = off;
+      red[2 * (tid >> 6) + 1] = tot;
     }
     __syncthreads();
-    const bool conv = !(red[0] > 1e-30 * red[1]);
+    double offs = 0.0, tots = 0.0;
+    for (int w = 0; w < nt / 64; ++w) {
+      offs += red[2 * w];
+      tots += red[2 * w + 1];
+    }
     __syncthreads();
-    if (conv) break;
+    if (!(offs > 1e-28 * tots)) break;
     for (int step = 0; step < m - 1; ++step) {
       if (tid < np) {
         const int k = tid;
-        auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + step) % (m - 1); };
-        int p = pos(k), q = pos(m - 1 - k);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
+        int p, q;
+        {
+          int t0 = (k == 0) ? 0 : 1 + (k - 1 + step) - ((k - 1 + step) >= m - 1 ? m - 1 : 0);
+          const int kk = m - 1 - k;
+          int t1 = 1 + (kk - 1 + step) - ((kk - 1 + step) >= m - 1 ? m - 1 : 0);
+          p = t0 < t1 ? t0 : t1;
+          q = t0 < t1 ? t1 : t0;
         }
         double c = 1.0, s = 0.0;
         if (q < n) {
@@ -194,6 +202,8 @@ __global__ __launch_bounds__(64) void k_syevj(int n, const double* __restrict__ 
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
           }
+        } else {
+          q = p;  // dummy partner: identity
         }
         cs[2 * k] = c;
         cs[2 * k + 1] = s;
@@ -201,29 +211,45 @@ __global__ __launch_bounds__(64) void k_syevj(int n, const double* __restrict__ 
         pq[2 * k + 1] = q;
       }
       __syncthreads();
-      // rows
-      for (int w = tid; w < np * n; w += 64) {
-        const int k = w / n, j = w % n;
+      // 2 x 2 blocks (rows of pair k, columns of pair l): B' = J_k^T B J_l
+      for (int w = tid; w < nblk; w += nt) {
+        const int k = w / np, l = w - (w / np) * np;
         const int p = pq[2 * k], q = pq[2 * k + 1];
-        if (q >= n) continue;
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double xp = a[p * n + j], xq = a[q * n + j];
-        a[p * n + j] = c * xp - s * xq;
-        a[q * n + j] = s * xp + c * xq;
+        const int r = pq[2 * l], t = pq[2 * l + 1];
+        const double ck = cs[2 * k], sk = cs[2 * k + 1];
+        const double cl = cs[2 * l], sl = cs[2 * l + 1];
+        if (p == q && r == t) {
+          continue;
+        } else if (p == q) {  // single row p, columns (r, t)
+          const double x0 = a[p * n + r], x1 = a[p * n + t];
+          a[p * n + r] = cl * x0 - sl * x1;
+          a[p * n + t] = sl * x0 + cl * x1;
+        } else if (r == t) {  // rows (p, q), single column r
+          const double x0 = a[p * n + r], x1 = a[q * n + r];
+          a[p * n + r] = ck * x0 - sk * x1;
+          a[q * n + r] = sk * x0 + ck * x1;
+        } else {
+          const double b00 = a[p * n + r], b01 = a[p * n + t];
+          const double b10 = a[q * n + r], b11 = a[q * n + t];
+          // rows: J_k^T
+          const double u00 = ck * b00 - sk * b10, u01 = ck * b01 - sk * b11;
+          const double u10 = sk * b00 + ck * b10, u11 = sk * b01 + ck * b11;
+          // columns: J_l
+          a[p * n + r] = cl * u00 - sl * u01;
+          a[p * n + t] = sl * u00 + cl * u01;
+          a[q * n + r] = cl * u10 - sl * u11;
+          a[q * n + t] = sl * u10 + cl * u11;
+        }
       }
-      __syncthreads();
-      // columns of A and V
-      for (int w = tid; w < np * n; w += 64) {
-        const int k = w / n, i = w % n;
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        if (q >= n) continue;
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double xp = a[i * n + p], xq = a[i * n + q];
-        a[i * n + p] = c * xp - s * xq;
-        a[i * n + q] = s * xp + c * xq;
-        const double vp = v[i * n + p], vq = v[i * n + q];
-        v[i * n + p] = c * vp - s * vq;
-        v[i * n + q] = s * vp + c * vq;
+      // V <- V J: row i, pair l
+      for (int w = tid; w < n * np; w += nt) {
+        const int i = w / np, l = w - (w / np) * np;
+        const int r = pq[2 * l], t = pq[2 * l + 1];
+        if (r == t) continue;
+        const double cl = cs[2 * l], sl = cs[2 * l + 1];
+        const double x0 = v[i * n + r], x1 = v[i * n + t];
+        v[i * n + r] = cl * x0 - sl * x1;
+        v[i * n + t] = sl * x0 + cl * x1;
       }
       __syncthreads();
     }
@@ -231,7 +257,7 @@ __global__ __launch_bounds__(64) void k_syevj(int n, const double* __restrict__ 
   // sort descending: rank of eigenvalue j = #{i : w_i > w_j or (w_i == w_j and i < j)}
   double* W = Wg + b * sW;
   double* V = Vg + b * sV;
-  for (int j = tid; j < n; j += 64) {
+  for (int j = tid; j < n; j += nt) {
     const double wj = a[j * n + j];
     int rank = 0;
     for (int i = 0; i < n; ++i) {
@@ -241,6 +267,105 @@ __global__ __launch_bounds__(64) void k_syevj(int n, const double* __restrict__ 
     W[rank] = wj;
     for (int i = 0; i < n; ++i) V[(long long)i * n + rank] = v[i * n + j];
   }
+}
+
+// Rank-revealing Cholesky with diagonal pivoting of a symmetric positive
+// semidefinite G (n x n): G[perm, perm] = L L^T with L n x r lower
+// trapezoidal, stopped when the largest remaining diagonal entry is below
+// tau times the largest initial one.  Writes S (n x n) = P R^-1 with
+// R = L^T (r x r) in the first r columns and zeros elsewhere, so Q = Y S
+// has orthonormal columns spanning the numerical range of Y when
+// G = Y^T Y.  One block of 64 threads per matrix.
+__global__ void k_pchol_s(int n, const double* __restrict__ Gg, long long sG, double tau,
+                          double* __restrict__ Sg, long long sS, int* __restrict__ rank_out) {
+  extern __shared__ double sm[];
+  double* g = sm;            // n x n working matrix
+  double* ri = sm + n * n;   // n x n: R^-1 (upper)
+  __shared__ int perm[64];
+  __shared__ int piv_s;
+  __shared__ double dmax0_s;
+  __shared__ int rank_s;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* G = Gg + b * sG;
+  for (int e = tid; e < n * n; e += 64) {
+    g[e] = G[e];
+    ri[e] = 0.0;
+  }
+  if (tid < n) perm[tid] = tid;
+  __syncthreads();
+  if (tid == 0) {
+    double m0 = 0.0;
+    for (int i = 0; i < n; ++i) m0 = fmax(m0, g[i * n + i]);
+    dmax0_s = m0;
+    rank_s = n;
+  }
+  __syncthreads();
+  const double dmax0 = dmax0_s;
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      int p = k;
+      double best = g[k * n + k];
+      for (int i = k + 1; i < n; ++i)
+        if (g[i * n + i] > best) {
+          best = g[i * n + i];
+          p = i;
+        }
+      piv_s = p;
+      if (!(best > tau * dmax0) || !(best > 0.0)) rank_s = k;
+    }
+    __syncthreads();
+    if (rank_s <= k) break;
+    const int p = piv_s;
+    if (p != k) {
+      // symmetric swap of rows/cols k and p (and the permutation)
+      for (int j = tid; j < n; j += 64) {
+        const double t = g[k * n + j];
+        g[k * n + j] = g[p * n + j];
+        g[p * n + j] = t;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += 64) {
+        const double t = g[i * n + k];
+        g[i * n + k] = g[i * n + p];
+        g[i * n + p] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[k];
+        perm[k] = perm[p];
+        perm[p] = t;
+      }
+      __syncthreads();
+    }
+    const double lkk = sqrt(g[k * n + k]);
+    __syncthreads();
+    // column k of L below the diagonal, stored in g[i][k]
+    for (int i = k + tid; i < n; i += 64) g[i * n + k] = (i == k) ? lkk : g[i * n + k] / lkk;
+    __syncthreads();
+    // trailing update g[i][j] -= L[i][k] L[j][k], i, j > k
+    for (int e = tid; e < (n - k - 1) * (n - k - 1); e += 64) {
+      const int i = k + 1 + e / (n - k - 1), j = k + 1 + e % (n - k - 1);
+      g[i * n + j] -= g[i * n + k] * g[j * n + k];
+    }
+    __syncthreads();
+  }
+  const int r = rank_s;
+  // R = L^T (r x r upper): R[i][j] = L[j][i] = g[j][i] for j >= i.
+  // Column j of R^-1 by back substitution (one thread per column).
+  for (int j = tid; j < r; j += 64) {
+    for (int i = j; i >= 0; --i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int t = i + 1; t <= j; ++t) acc -= g[t * n + i] * ri[t * n + j];
+      ri[i * n + j] = acc / g[i * n + i];
+    }
+  }
+  __syncthreads();
+  double* S = Sg + b * sS;
+  for (int e = tid; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;  // S[perm[i]][j] = Rinv[i][j]
+    S[perm[i] * n + j] = (i < r && j < r) ? ri[i * n + j] : 0.0;
+  }
+  if (tid == 0 && rank_out != nullptr) rank_out[b] = r;
 }
 
 }  // namespace
@@ -254,7 +379,13 @@ size_t gemm_scratch_doubles(const Gemm& g) {
 int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return LRFG_OK;
   int ks = choose_ksplit(g);
-  if (ks > 1 && (scratch == nullptr || scratch_doubles < (size_t)g.batch * ks * g.m * g.n)) ks = 1;
+  if (ks > 1) {
+    // as many splits as the scratch holds
+    const size_t per = (size_t)g.batch * g.m * g.n;
+    const size_t fit = scratch == nullptr ? 0 : scratch_doubles / per;
+    if ((size_t)ks > fit) ks = (int)fit;
+    if (ks < 2) ks = 1;
+  }
   const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + BK - 1) / BK * BK : (g.k > 0 ? g.k : 1);
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
   dim3 grid(ceil_div(g.n, BN), ceil_div(g.m, BM), g.batch * ks);
@@ -292,7 +423,26 @@ int syevj(int n, const double* A, long long lda, long long sA, double* W, long l
                                                      (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));
   (void)attr;
   ProfScope ps_("syevj", s);
-  hipLaunchKernelGGL(k_syevj, dim3(batch), dim3(64), shm, s, n, A, lda, sA, W, sW, V, sV, 30);
+  const int nt = n <= 32 ? 64 : 256;
+  hipLaunchKernelGGL(k_syevj, dim3(batch), dim3(nt), shm, s, n, A, lda, sA, W, sW, V, sV, 30);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int pchol_s(int n, const double* G, long long sG, double tau, double* S, long long sS, int* rank, int batch,
+            hipStream_t s) {
+  if (n < 1 || n > kMaxEig) {
+    set_error("pchol: n = %d outside [1, %d]", n, kMaxEig);
+    return LRFG_EINVAL;
+  }
+  if (batch <= 0) return LRFG_OK;
+  const size_t shm = sizeof(double) * 2 * n * n;
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));
+  (void)attr;
+  ProfScope ps_("pchol", s);
+  hipLaunchKernelGGL(k_pchol_s, dim3(batch), dim3(64), shm, s, n, G, sG, tau, S, sS, rank);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }

@@ -112,6 +112,15 @@ __global__ void k_ratio(const double* __restrict__ num, const double* __restrict
   if (e < nE) out[e] = (done[e] || !(den[e] != 0.0)) ? 0.0 : num[e] / den[e];
 }
 
+// coef2 = [c; -c]
+__global__ void k_pm(const double* __restrict__ c, double* __restrict__ coef2, int nE) {
+  const int e = threadIdx.x;
+  if (e < nE) {
+    coef2[e] = c[e];
+    coef2[nE + e] = -c[e];
+  }
+}
+
 // beta_e = rz_e / rho_e (0 when done); rho_e <- rz_e
 __global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, const int* __restrict__ done,
                        double* __restrict__ beta, int nE) {
@@ -129,17 +138,20 @@ struct Ctx {
   FftDev f[3];
   Rounder rd;
   TTB a;                    // coefficient (shared)
-  TTB x, r, z, p, q, xb, b; // correctors (ranks c)
-  TTB kr;                   // Hadamard product a (.) g (ranks ra c)
-  TTB comb;                 // block sums (capacity ranks)
-  TTB h[3];                 // rounded material terms
+  TTB xr;                   // [x; r]: 2 nE trains updated by one truncation
+  TTB pq;                   // [p; q]
+  TTB x, r, p, q;           // views of the halves
+  TTB z, xb, b;             // correctors (ranks c)
+  TTB kr;                   // Hadamard products a (.) D_alpha v, d nE trains (ranks ra c)
+  TTB comb;                 // block sums (capacity ranks, 2 nE trains)
+  TTB h;                    // rounded material terms, d nE trains
   double* gcore;            // carriage buffer for D_alpha v
   double* hcore[3];         // carriage buffers for D_alpha^T h_alpha
   double* pcore;            // M * d carriage buffers for the preconditioner terms
   long long pcore_stride;
   double* acore[3];         // carriage buffers of D_alpha a (right-hand side)
   TTB tmp;                  // extra corrector-size train
-  double *dots, *rho, *pq, *alpha, *beta, *zz, *Ecoef, *wcoef, *dscr;
+  double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
   int* done;
   size_t dscr_n;
   int comb_cap[4];
@@ -158,18 +170,24 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
   for (int j = 0; j < d; ++j) C.f[j].tw = ar.take<double2>(pl->N[j]);
   C.a = tt_alloc(ar, d, pl->N, ra, 1);
   for (int j = 0; j < d; ++j) C.a.s[j] = 0;
-  C.x = tt_alloc(ar, d, pl->N, rc, nE);
-  C.r = tt_alloc(ar, d, pl->N, rc, nE);
+  C.xr = tt_alloc(ar, d, pl->N, rc, 2 * nE);
+  C.pq = tt_alloc(ar, d, pl->N, rc, 2 * nE);
+  C.x = C.xr;
+  C.r = C.xr;
+  C.p = C.pq;
+  C.q = C.pq;
+  for (int j = 0; j < d; ++j) {
+    C.r.c[j] = C.xr.c[j] + (long long)nE * C.xr.s[j];
+    C.q.c[j] = C.pq.c[j] + (long long)nE * C.pq.s[j];
+  }
   C.z = tt_alloc(ar, d, pl->N, rc, nE);
-  C.p = tt_alloc(ar, d, pl->N, rc, nE);
-  C.q = tt_alloc(ar, d, pl->N, rc, nE);
   C.xb = tt_alloc(ar, d, pl->N, rc, nE);
   C.b = tt_alloc(ar, d, pl->N, rc, nE);
   C.tmp = tt_alloc(ar, d, pl->N, rc, nE);
-  for (int al = 0; al < d; ++al) C.h[al] = tt_alloc(ar, d, pl->N, rc, nE);
+  C.h = tt_alloc(ar, d, pl->N, rc, d * nE);
   int rkr[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) rkr[j] = ra[j] * rc[j];
-  C.kr = tt_alloc(ar, d, pl->N, rkr, nE);
+  C.kr = tt_alloc(ar, d, pl->N, rkr, d * nE);
   // block sums: d material terms, M preconditioner terms, 2 update terms, d coefficient terms
   int cap[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) {
@@ -180,7 +198,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
     cap[j] = m;
   }
   for (int j = 0; j < 4; ++j) C.comb_cap[j] = cap[j];
-  C.comb = tt_alloc(ar, d, pl->N, cap, nE);
+  C.comb = tt_alloc(ar, d, pl->N, cap, 2 * nE);
   long long maxcore = 0;
   for (int j = 0; j < d; ++j) maxcore = std::max(maxcore, (long long)rc[j] * pl->N[j] * rc[j + 1]);
   C.gcore = ar.take<double>((size_t)maxcore * nE);
@@ -193,7 +211,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
   // rounding workspace
   Rounder& R = C.rd;
   R.d = d;
-  R.nE = nE;
+  R.nE = std::max(d, 2) * nE;
   for (int j = 0; j < 3; ++j) R.N[j] = (j < d) ? pl->N[j] : 1;
   R.oversample = pl->over;
   R.seed = pl->p.seed;
@@ -205,43 +223,50 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
   // scalars
   C.dots = ar.take<double>(64);
   C.rho = ar.take<double>(4);
-  C.pq = ar.take<double>(4);
+  C.pqd = ar.take<double>(4);
   C.alpha = ar.take<double>(4);
   C.beta = ar.take<double>(4);
   C.zz = ar.take<double>(4);
   C.Ecoef = ar.take<double>(12);
-  C.wcoef = ar.take<double>(4);
+  C.coef2 = ar.take<double>(8);
   C.done = ar.take<int>(4);
-  // dot scratch: largest pair (kr, c) or (comb, comb)
-  size_t dn = tt_dot_scratch(C.kr, C.x, nE);
-  dn = std::max(dn, tt_dot_scratch(C.comb, C.comb, nE));
+  // dot scratch: largest pair (kr, c) or (a, a)
+  size_t dn = tt_dot_scratch(C.kr, C.z, nE);
+  dn = std::max(dn, tt_dot_scratch(C.a, C.a, nE));
   C.dscr_n = dn;
   C.dscr = ar.take<double>(dn);
   return LRFG_OK;
 }
 
 // ------------------------------------------------------------------ operators
-// out = T(sum_alpha D_alpha^T T(a (.) D_alpha v))
+// out = T(sum_alpha D_alpha^T T(a (.) D_alpha v)); the d material
+// truncations run as one batched truncation of d nE trains.
 int apply_K(Ctx& C, const TTB& v, TTB& out) {
   const int d = C.d, nE = C.nE;
-  TTB hd[3];
   for (int al = 0; al < d; ++al) {
     TTB g = v;
     g.c[al] = C.gcore;
     LRFG_TRY(tt_mode_apply(v, g, al, 0, 0.0, 1.0, C.f[al], nE, C.s));
-    LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, C.s));
-    LRFG_TRY(C.rd.round(C.kr, C.h[al], 0.0, C.s));
-    hd[al] = C.h[al];
-    hd[al].c[al] = C.hcore[al];
-    LRFG_TRY(tt_mode_apply(C.h[al], hd[al], al, 0, 0.0, -1.0, C.f[al], nE, C.s));
+    TTB kra = C.kr;
+    for (int j = 0; j < d; ++j) kra.c[j] = C.kr.c[j] + (long long)al * nE * C.kr.s[j];
+    LRFG_TRY(tt_hadamard(C.a, g, kra, nE, C.s));
   }
+  LRFG_TRY(C.rd.round(C.kr, C.h, 0.0, C.s, d * nE));
+  TTB ha[3], hd[3];
   TTTerm terms[3];
-  for (int al = 0; al < d; ++al) terms[al] = TTTerm{&hd[al], nullptr, 1.0};
+  for (int al = 0; al < d; ++al) {
+    ha[al] = C.h;
+    for (int j = 0; j < d; ++j) ha[al].c[j] = C.h.c[j] + (long long)al * nE * C.h.s[j];
+    hd[al] = ha[al];
+    hd[al].c[al] = C.hcore[al];
+    LRFG_TRY(tt_mode_apply(ha[al], hd[al], al, 0, 0.0, -1.0, C.f[al], nE, C.s));
+    terms[al] = TTTerm{&hd[al], nullptr, 1.0};
+  }
   TTB comb = C.comb;
   for (int j = 1; j < d; ++j) comb.r[j] = d * v.r[j];
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
   LRFG_TRY(tt_sum(terms, d, comb, nE, C.s));
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
 }
 
 // out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}
@@ -265,17 +290,27 @@ int apply_P(Ctx& C, const TTB& v, TTB& out) {
   for (int j = 1; j < d; ++j) comb.r[j] = M * v.r[j];
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
   LRFG_TRY(tt_sum(terms.data(), M, comb, nE, C.s));
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
 }
 
-// out = T(ca x + cb y) with per-system coefficients (device arrays or 1)
-int axpby(Ctx& C, const TTB& x, const double* ca, double ma, const TTB& y, const double* cb, double mb, TTB& out) {
-  TTTerm t[2] = {TTTerm{&x, ca, ma}, TTTerm{&y, cb, mb}};
+// [x; r] <- T([x; r] + coef2 [p; q]) as one truncation of 2 nE trains
+int update_xr(Ctx& C) {
+  TTTerm t[2] = {TTTerm{&C.xr, nullptr, 1.0}, TTTerm{&C.pq, C.coef2, 1.0}};
+  TTB comb = C.comb;
+  for (int j = 1; j < C.d; ++j) comb.r[j] = 2 * C.xr.r[j];
+  for (int j = 0; j < C.d; ++j) comb.s[j] = comb.size(j);
+  LRFG_TRY(tt_sum(t, 2, comb, 2 * C.nE, C.s));
+  return C.rd.round(comb, C.xr, C.pl->p.trunc_tol, C.s, 2 * C.nE);
+}
+
+// out = T(x + cb y) for nE trains
+int axpby(Ctx& C, const TTB& x, const TTB& y, const double* cb, TTB& out) {
+  TTTerm t[2] = {TTTerm{&x, nullptr, 1.0}, TTTerm{&y, cb, 1.0}};
   TTB comb = C.comb;
   for (int j = 1; j < C.d; ++j) comb.r[j] = x.r[j] + y.r[j];
   for (int j = 0; j < C.d; ++j) comb.s[j] = comb.size(j);
   LRFG_TRY(tt_sum(t, 2, comb, C.nE, C.s));
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s);
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, C.nE);
 }
 
 int dot(Ctx& C, const TTB& x, const TTB& y, double* out) { return tt_dot(x, y, out, C.dscr, C.nE, C.s); }
@@ -459,7 +494,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
     for (int j = 1; j < d; ++j) comb.r[j] = d * C.a.r[j];
     for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
     LRFG_TRY(tt_sum(terms, d, comb, nE, s));
-    LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s));
+    LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s, nE));
   }
   // scale for the zero-right-hand-side floor: rms(a) |E|
   double a2 = 0.0;
@@ -486,7 +521,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
   std::vector<double> best(nE, INFINITY), res0(nE, 0.0), zzh(nE), cur(nE);
   std::vector<int> since_best(nE, 0);
   const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
-  LRFG_TRY(tt_zero(C.x, nE, s));
+  LRFG_TRY(tt_zero(C.xr, 2 * nE, s));
   LRFG_TRY(tt_zero(C.xb, nE, s));
   auto upload_done = [&]() -> int {
     LRFG_HIP(hipMemcpyAsync(C.done, hdone.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
@@ -518,35 +553,34 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
     if (all) break;
     if (P.solver == LRFG_SOLVER_PCG) {
       LRFG_TRY(apply_K(C, C.p, C.q));
-      LRFG_TRY(dot(C, C.p, C.q, C.pq));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.rho, (const double*)C.pq,
+      LRFG_TRY(dot(C, C.p, C.q, C.pqd));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.rho, (const double*)C.pqd,
                          (const int*)C.done, C.alpha, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(64), 0, s, (const double*)C.alpha, C.coef2, nE);
       LRFG_LAUNCHED();
-      LRFG_TRY(axpby(C, C.x, nullptr, 1.0, C.p, C.alpha, 1.0, C.tmp));
-      LRFG_TRY(tt_copy(C.tmp, C.x, nE, s));
-      LRFG_TRY(axpby(C, C.r, nullptr, 1.0, C.q, C.alpha, -1.0, C.tmp));
-      LRFG_TRY(tt_copy(C.tmp, C.r, nE, s));
+      LRFG_TRY(update_xr(C));   // x += alpha p ; r -= alpha q
       LRFG_TRY(apply_P(C, C.r, C.z));
       LRFG_TRY(dot(C, C.r, C.z, C.dots));
       LRFG_TRY(dot(C, C.z, C.z, C.zz));
       hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, s, (const double*)C.dots, C.rho, (const int*)C.done, C.beta,
                          nE);
       LRFG_LAUNCHED();
-      LRFG_TRY(axpby(C, C.z, nullptr, 1.0, C.p, C.beta, 1.0, C.tmp));
+      LRFG_TRY(axpby(C, C.z, C.p, C.beta, C.tmp));
       LRFG_TRY(tt_copy(C.tmp, C.p, nE, s));
     } else {
       // Cr = T(P~^-1 T(K r)); omega = (Cr, r)/(Cr, Cr); u += omega r; r -= omega Cr
-      LRFG_TRY(apply_K(C, C.r, C.q));
-      LRFG_TRY(apply_P(C, C.q, C.z));
+      LRFG_TRY(apply_K(C, C.r, C.tmp));
+      LRFG_TRY(apply_P(C, C.tmp, C.z));
       LRFG_TRY(dot(C, C.z, C.r, C.dots));
-      LRFG_TRY(dot(C, C.z, C.z, C.pq));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.dots, (const double*)C.pq,
+      LRFG_TRY(dot(C, C.z, C.z, C.pqd));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.dots, (const double*)C.pqd,
                          (const int*)C.done, C.alpha, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(64), 0, s, (const double*)C.alpha, C.coef2, nE);
       LRFG_LAUNCHED();
-      LRFG_TRY(axpby(C, C.x, nullptr, 1.0, C.r, C.alpha, 1.0, C.tmp));
-      LRFG_TRY(tt_copy(C.tmp, C.x, nE, s));
-      LRFG_TRY(axpby(C, C.r, nullptr, 1.0, C.z, C.alpha, -1.0, C.tmp));
-      LRFG_TRY(tt_copy(C.tmp, C.r, nE, s));
+      // [p; q] = [r; Cr] then [u; r] += [omega; -omega] [r; Cr]
+      LRFG_TRY(tt_copy(C.r, C.p, nE, s));
+      LRFG_TRY(tt_copy(C.z, C.q, nE, s));
+      LRFG_TRY(update_xr(C));
       LRFG_TRY(dot(C, C.r, C.r, C.zz));
     }
     LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
@@ -628,8 +662,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
   }
   // final ranks: one more truncation of the best iterate reports the kept ranks
   std::vector<int> kept(2 * nE, 0);
-  LRFG_TRY(C.rd.round(C.xb, C.tmp, P.trunc_tol, s));
-  LRFG_HIP(hipMemcpyAsync(kept.data(), C.rd.kept, sizeof(int) * 2 * nE, hipMemcpyDeviceToHost, s));
+  LRFG_TRY(C.rd.round(C.xb, C.tmp, P.trunc_tol, s, nE));
+  LRFG_HIP(hipMemcpyAsync(kept.data(), C.rd.kept, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+  LRFG_HIP(hipMemcpyAsync(kept.data() + nE, C.rd.kept + C.rd.nE, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
   LRFG_HIP(hipEventRecord(ev2, s));
   LRFG_HIP(hipStreamSynchronize(s));
   float ms_setup = 0.f, ms_solve = 0.f;

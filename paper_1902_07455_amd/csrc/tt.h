@@ -48,8 +48,9 @@ struct Rounder {
   size_t gscr_n = 0;
   int* kept = nullptr;      // kept ranks per bond per system (diagnostics)
   void carve(Arena& ar);
-  // out (ranks preset to the nominal output ranks) <- T(in)
-  int round(const TTB& in, TTB& out, double tol, hipStream_t s);
+  // out (ranks preset to the nominal output ranks) <- T(in) for `batch`
+  // systems (default: nE, the capacity it was carved for)
+  int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1);
 };
 
 int tt_fill(double* p, long long n, double v, hipStream_t s);

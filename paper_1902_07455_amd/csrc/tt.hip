@@ -32,6 +32,8 @@ namespace lrfg {
 int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
                        double mult, const FftDev& f, hipStream_t s);
 
+constexpr size_t kDotSplitK = (size_t)2 * 1024 * 1024;  // doubles of split-K partials in tt_dot
+
 namespace {
 
 constexpr int kB = 256;
@@ -271,7 +273,7 @@ size_t tt_dot_scratch(const TTB& x, const TTB& y, int nE) {
     n += (size_t)x.r[j + 1] * y.r[j + 1];          // M_j
     n += (size_t)x.r[j] * y.N[j] * y.r[j + 1];     // U_j
   }
-  return n * nE + 4096 + (size_t)nE * 64 * 1024;   // + split-K space
+  return n * nE + 4096 + kDotSplitK;               // + split-K space
 }
 
 int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s) {
@@ -281,8 +283,8 @@ int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hi
   double* M = nullptr;  // previous M, (x.r[j] x y.r[j]) per system
   long long sM = 0;
   double* p = scratch;
-  double* gs = scratch + tt_dot_scratch(x, y, nE) - (size_t)nE * 64 * 1024;
-  const size_t gsn = (size_t)nE * 64 * 1024;
+  double* gs = scratch + tt_dot_scratch(x, y, nE) - kDotSplitK;
+  const size_t gsn = kDotSplitK;
   for (int j = 0; j < d; ++j) {
     const int a0 = x.r[j], a1 = x.r[j + 1], b0 = y.r[j], b1 = y.r[j + 1], N = y.N[j];
     // U = M Y_j : (a0 x b0)(b0 x N b1); j = 0 -> U = Y_0 (a0 = b0 = 1)
@@ -376,7 +378,7 @@ void Rounder::carve(Arena& ar) {
   S1 = T((long long)L * L);
   P = T((long long)L * L);
   kept = ar.take<int>((size_t)2 * nE);
-  gscr_n = (size_t)nE * 256 * 1024;
+  gscr_n = (size_t)4 * 1024 * 1024;
   gscr = ar.take<double>(gscr_n);
 }
 
@@ -414,22 +416,20 @@ struct GemmB {
 
 }  // namespace
 
-// Q (m x l per system, stride m*l) = orth(Y); Ytmp holds the first pass.
-static int orth(Rounder& R, const double* Y, double* Q, int m, int l, hipStream_t s) {
-  const int nE = R.nE;
-  const double tau = 1e-15;
+// Q (m x l per system, stride m*l) = orth(Y): Gram Y^T Y, rank-revealing
+// pivoted Cholesky, Q = Y P R^-1 (zero columns beyond the numerical rank);
+// a second pass on Q restores orthogonality to rounding level.  Ytmp holds
+// the first pass.
+static int orth(Rounder& R, const double* Y, double* Q, int m, int l, int batch, hipStream_t s) {
+  const double tau = 1e-14;
   const double* src = Y;
   double* dsts[2] = {R.Ytmp, Q};
   for (int pass = 0; pass < 2; ++pass) {
-    GemmB gg(l, l, m, nE);
+    GemmB gg(l, l, m, batch);
     gg.a(src, l, (long long)m * l, true).b(src, l, (long long)m * l).c(R.G, l, (long long)l * l);
     LRFG_TRY(gemm(gg.g, R.gscr, R.gscr_n, s));
-    LRFG_TRY(syevj(l, R.G, l, (long long)l * l, R.lam, l, R.V, (long long)l * l, nE, s));
-    const long long tot = (long long)nE * l * l;
-    hipLaunchKernelGGL(k_orth_scale, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)R.lam, (const double*)R.V, l,
-                       tau, R.S, nE);
-    LRFG_LAUNCHED();
-    GemmB gq(m, l, l, nE);
+    LRFG_TRY(pchol_s(l, R.G, (long long)l * l, tau, R.S, (long long)l * l, nullptr, batch, s));
+    GemmB gq(m, l, l, batch);
     gq.a(src, l, (long long)m * l).b(R.S, l, (long long)l * l).c(dsts[pass], l, (long long)m * l);
     LRFG_TRY(gemm(gq.g, R.gscr, R.gscr_n, s));
     src = dsts[pass];
@@ -438,8 +438,7 @@ static int orth(Rounder& R, const double* Y, double* Q, int m, int l, hipStream_
 }
 
 static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, double* S, int* kept,
-                      hipStream_t s) {
-  const int nE = R.nE;
+                      int nE, hipStream_t s) {
   LRFG_TRY(syevj(l, Gm, l, (long long)l * l, R.lam, l, R.V, (long long)l * l, nE, s));
   hipLaunchKernelGGL(k_trunc_mask, dim3(nE), dim3(64), 0, s, (const double*)R.lam, (const double*)R.V, l, c, tol2,
                      1e-28, S, kept, nE);
@@ -447,8 +446,14 @@ static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, d
   return LRFG_OK;
 }
 
-int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
+int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch) {
   ProfScope ps_("tt_round", s);
+  if (batch < 0) batch = nE;
+  if (batch > nE) {
+    set_error("tt_round: batch %d exceeds the plan's %d", batch, nE);
+    return LRFG_EINVAL;
+  }
+  const int nE = batch;
   const double tol2 = tol * tol / (double)(d - 1);
   const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
   if (d == 3) {
@@ -483,7 +488,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
     // Y1 = X1 W2 (N1 x l1) ; Q1 = orth(Y1)
     { GemmB g(N1, l1, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l1, (long long)R1 * l1).c(Y1, l1, (long long)N1 * l1);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-    LRFG_TRY(orth(*this, Y1, Q1, N1, l1, s));
+    LRFG_TRY(orth(*this, Y1, Q1, N1, l1, nE, s));
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
@@ -494,7 +499,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
     { GemmB g(l1 * N2, l2, R2, nE); g.a(X2p, R2, (long long)l1 * N2 * R2).b(W3, l2, (long long)R2 * l2)
           .c(Y2, l2, (long long)l1 * N2 * l2);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-    LRFG_TRY(orth(*this, Y2, Q2, l1 * N2, l2, s));
+    LRFG_TRY(orth(*this, Y2, Q2, l1 * N2, l2, nE, s));
     // M2 = Q2^T X2' (l2 x R2) ; X3' = M2 X3 (l2 x N3)
     { GemmB g(l2, R2, l1 * N2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2, true).b(X2p, R2, (long long)l1 * N2 * R2)
           .c(M2, R2, (long long)l2 * R2);
@@ -504,7 +509,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
     // ---- cut at bond 2: G = X3' X3'^T, S3 = kept eigenvectors (l2 x c2)
     { GemmB g(l2, l2, N3, nE); g.a(X3p, N3, (long long)l2 * N3).b(X3p, N3, (long long)l2 * N3, true).c(G, l2, (long long)l2 * l2);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-    LRFG_TRY(trunc_mask(*this, G, l2, c2, tol2, S3, kept + nE, s));
+    LRFG_TRY(trunc_mask(*this, G, l2, c2, tol2, S3, kept + this->nE, nE, s));
     { GemmB g(c2, N3, l2, nE); g.a(S3, c2, (long long)l2 * c2, true).b(X3p, N3, (long long)l2 * N3).c(out.c[2], N3, out.s[2]);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
     // Q2s = Q2 S3 ((l1 N2) x c2); P = X3 X3^T (c2 x c2); U = Q2s P
@@ -520,7 +525,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
     { GemmB g(l1, l1, N2 * c2, nE); g.a(U, (long long)N2 * c2, (long long)l1 * N2 * c2)
           .b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2, true).c(G, l1, (long long)l1 * l1);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-    LRFG_TRY(trunc_mask(*this, G, l1, c1, tol2, S1, kept, s));
+    LRFG_TRY(trunc_mask(*this, G, l1, c1, tol2, S1, kept, nE, s));
     { GemmB g(N1, c1, l1, nE); g.a(Q1, l1, (long long)N1 * l1).b(S1, c1, (long long)l1 * c1).c(out.c[0], c1, out.s[0]);
       LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
     { GemmB g(c1, N2 * c2, l1, nE); g.a(S1, c1, (long long)l1 * c1, true).b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2)
@@ -546,14 +551,14 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s) {
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   { GemmB g(N1, l, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l, (long long)R1 * l).c(Y1, l, (long long)N1 * l);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-  LRFG_TRY(orth(*this, Y1, Q1, N1, l, s));
+  LRFG_TRY(orth(*this, Y1, Q1, N1, l, nE, s));
   { GemmB g(l, R1, N1, nE); g.a(Q1, l, (long long)N1 * l, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l * R1);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   { GemmB g(l, N2, R1, nE); g.a(M1, R1, (long long)l * R1).b(in.c[1], N2, in.s[1]).c(X3p, N2, (long long)l * N2);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   { GemmB g(l, l, N2, nE); g.a(X3p, N2, (long long)l * N2).b(X3p, N2, (long long)l * N2, true).c(G, l, (long long)l * l);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-  LRFG_TRY(trunc_mask(*this, G, l, c1, tol * tol, S1, kept, s));
+  LRFG_TRY(trunc_mask(*this, G, l, c1, tol * tol, S1, kept, nE, s));
   { GemmB g(c1, N2, l, nE); g.a(S1, c1, (long long)l * c1, true).b(X3p, N2, (long long)l * N2).c(out.c[1], N2, out.s[1]);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   { GemmB g(N1, c1, l, nE); g.a(Q1, l, (long long)N1 * l).b(S1, c1, (long long)l * c1).c(out.c[0], c1, out.s[0]);
