@@ -60,6 +60,12 @@ int validate(const lrfg_problem* p) {
       return LRFG_EINVAL;
     }
   }
+  for (int i = 0; i < p->d; ++i) {
+    if (p->N[i] > 2048) {
+      set_error("N[%d] = %d: grid sizes above 2048 are not supported", i, p->N[i]);
+      return LRFG_EUNSUPPORTED;
+    }
+  }
   if (p->format < LRFG_FORMAT_FULL || p->format > LRFG_FORMAT_TT) {
     set_error("unknown format %d", p->format);
     return LRFG_EINVAL;

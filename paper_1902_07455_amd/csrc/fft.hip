@@ -74,16 +74,14 @@ __device__ inline long long line_addr(long long l, int n, int N, int inner) {
   return (o * N + n) * (long long)inner + i;
 }
 
-template <int DIR>
-__global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner, int T,
-                            FftDev f, double scale, const int* __restrict__ done,
-                            long long lines_per_flag) {
+template <int DIR, bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x, long long nlines, int inner,
+                                                          int T, FftDev f, double scale, const int* __restrict__ done,
+                                                          long long lines_per_flag) {
   extern __shared__ double2 sm[];
   const int N = f.N;
-  double2* a = sm;
-  double2* b = sm + T * N;
   const long long l0 = (long long)blockIdx.x * T;
-  int tcount = (int)min((long long)T, nlines - l0);
+  const int tcount = (int)min((long long)T, nlines - l0);
   // A tile is skipped when every system its lines belong to (system =
   // line / lines_per_flag) is flagged done.  Lines of a finished system
   // inside a running tile are transformed too: that system's arrays are
@@ -95,17 +93,31 @@ __global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner
     if (all_done) return;
   }
   const int total = T * N;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  double2 v[kFftMaxE];
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    a[t * N + n] = (t < tcount) ? x[line_addr(l0 + t, n, N, inner)] : make_double2(0.0, 0.0);
+    v[i] = (idx < total && t < tcount) ? x[line_addr(l0 + t, n, N, inner)] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
-  double2* r = lds_fft<DIR>(a, b, T, f);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  lds_fft1<DIR, GEN>(sm, T, f, tw);
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    if (t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(r[t * N + n], scale);
+    if (idx < total && t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(sm[t * N + n], scale);
   }
 }
 
@@ -113,45 +125,61 @@ __global__ void k_fft_lines(double2* __restrict__ x, long long nlines, int inner
 // complex line (the operator is real, so it acts on real and imaginary
 // parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2); result times mult.
 // Reads xin, writes x (the same array for in-place use).
-__global__ void k_mode_op(const double* xin, double* x, long long nfib, int inner, int T, FftDev f, int op,
-                          double tparam, double mult) {
+template <bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double* x, long long nfib, int inner, int T,
+                                                        FftDev f, int op, double tparam, double mult) {
   extern __shared__ double2 sm[];
   const int N = f.N;
-  double2* a = sm;
-  double2* b = sm + T * N;
   const long long f0 = (long long)blockIdx.x * (2 * T);
   const int total = T * N;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  double2 v[kFftMaxE];
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
     const long long fa = f0 + 2 * t, fb = fa + 1;
-    const double re = (fa < nfib) ? xin[line_addr(fa, n, N, inner)] : 0.0;
-    const double im = (fb < nfib) ? xin[line_addr(fb, n, N, inner)] : 0.0;
-    a[t * N + n] = make_double2(re, im);
+    const double re = (idx < total && fa < nfib) ? xin[line_addr(fa, n, N, inner)] : 0.0;
+    const double im = (idx < total && fb < nfib) ? xin[line_addr(fb, n, N, inner)] : 0.0;
+    v[i] = make_double2(re, im);
+  }
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    int t, n;
+    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
-  double2* r = lds_fft<-1>(a, b, T, f);
-  double2* o = (r == a) ? b : a;
+  lds_fft1<-1, GEN>(sm, T, f, tw);
+  __syncthreads();
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int n = idx % N;
     const int k = freq_of(n, N);
-    double2 v = r[idx];
+    double2 w = sm[idx];
     if (op == 0) {
-      v = cmul_i(v, mult * 2.0 * kPi * (double)k / (double)N);
+      w = cmul_i(w, mult * 2.0 * kPi * (double)k / (double)N);
     } else {
-      v = cscale(v, mult * exp(-tparam * (double)k * (double)k) / (double)N);
+      w = cscale(w, mult * exp(-tparam * (double)k * (double)k) / (double)N);
     }
-    r[idx] = v;
+    sm[idx] = w;
   }
   __syncthreads();
-  double2* s = lds_fft<1>(r, o, T, f);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  lds_fft1<1, GEN>(sm, T, f, tw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
     const long long fa = f0 + 2 * t, fb = fa + 1;
-    const double2 v = s[t * N + n];
-    if (fa < nfib) x[line_addr(fa, n, N, inner)] = v.x;
-    if (fb < nfib) x[line_addr(fb, n, N, inner)] = v.y;
+    if (idx < total) {
+      const double2 w = sm[t * N + n];
+      if (fa < nfib) x[line_addr(fa, n, N, inner)] = w.x;
+      if (fb < nfib) x[line_addr(fb, n, N, inner)] = w.y;
+    }
   }
 }
 
@@ -171,17 +199,24 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
                      long long lines_per_flag) {
   const long long nlines = outer * inner;
   if (nlines == 0) return LRFG_OK;
-  const int T = lines_per_tile(N);
-  const size_t shm = size_t(2) * T * N * sizeof(double2);
+  if (N > kFftMaxE * kFftBlock) {
+    set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
+    return LRFG_EUNSUPPORTED;
+  }
+  const int T = lines_per_tile1(N);
+  const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(nlines, T);
   ProfScope ps_(tag, s);
+  const bool gen = plan_generic(f);
+#define LRFG_FL(D, G) \
+  hipLaunchKernelGGL((k_fft_lines<D, G>), dim3(grid), dim3(kFftBlock), shm, s, x, nlines, (int)inner, T, f, scale, \
+                     done, lines_per_flag)
   if (dir < 0) {
-    hipLaunchKernelGGL(k_fft_lines<-1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale,
-                       done, lines_per_flag);
+    if (gen) LRFG_FL(-1, true); else LRFG_FL(-1, false);
   } else {
-    hipLaunchKernelGGL(k_fft_lines<1>, dim3(grid), dim3(256), shm, s, x, nlines, (int)inner, T, f, scale,
-                       done, lines_per_flag);
+    if (gen) LRFG_FL(1, true); else LRFG_FL(1, false);
   }
+#undef LRFG_FL
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
@@ -190,11 +225,19 @@ int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, lon
                        double mult, const FftDev& f, hipStream_t s) {
   const long long nfib = outer * inner;
   if (nfib == 0) return LRFG_OK;
-  const int T = lines_per_tile(N);
-  const size_t shm = size_t(2) * T * N * sizeof(double2);
+  if (N > kFftMaxE * kFftBlock) {
+    set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
+    return LRFG_EUNSUPPORTED;
+  }
+  const int T = lines_per_tile1(N);
+  const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(nfib, 2 * T);
   ProfScope ps_("mode_op", s);
-  hipLaunchKernelGGL(k_mode_op, dim3(grid), dim3(256), shm, s, xin, x, nfib, (int)inner, T, f, op, t, mult);
+  if (plan_generic(f))
+    hipLaunchKernelGGL(k_mode_op<true>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, (int)inner, T, f, op, t, mult);
+  else
+    hipLaunchKernelGGL(k_mode_op<false>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, (int)inner, T, f, op, t,
+                       mult);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }

@@ -33,7 +33,6 @@ int launch_pinv(const double2* u, double2* o, int N1, int N2, int N3, hipStream_
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxPer = 16;  // P5 accumulator entries per thread: T1*N1 <= kMaxPer*kBlock
 
 struct G3 {
   int N1, N2, N3, H;
@@ -63,9 +62,11 @@ __device__ inline double pinv_of(const double k[3]) {
 // dst[e][a] = F^-1_axis1 ( 2 pi i k_alpha src[e] ),  alpha = alpha0 + a.
 // grid.x = tiles * nalpha (alpha fastest, so the tiles of one src share L2),
 // grid.y = e.
-__global__ void k_grad_axis1(const double2* __restrict__ src, double2* __restrict__ dst, G3 g,
-                             int alpha0, int nalpha, long long dst_stride_e, long long dst_stride_a,
-                             int T, FftDev f, const int* __restrict__ done) {
+template <bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_grad_axis1(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                           G3 g, int alpha0, int nalpha, long long dst_stride_e,
+                                                           long long dst_stride_a, int T, FftDev f,
+                                                           const int* __restrict__ done) {
   extern __shared__ double2 sm[];
   const int e = blockIdx.y;
   if (done != nullptr && done[e]) return;
@@ -78,38 +79,47 @@ __global__ void k_grad_axis1(const double2* __restrict__ src, double2* __restric
   const int tcount = (int)min((long long)T, inner - l0);
   const double2* s = src + (long long)e * g.S;
   double2* d = dst + e * dst_stride_e + a * dst_stride_a;
-  double2* A = sm;
-  double2* B = sm + T * N;
   const int total = T * N;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  double2 v[kFftMaxE];
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     const int t = idx % T, n = idx / T;
-    double2 v = make_double2(0.0, 0.0);
-    if (t < tcount) {
-      const long long i = l0 + t;
-      v = s[(long long)n * inner + i];
+    v[i] = (idx < total && t < tcount) ? s[(long long)n * inner + l0 + t] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    const int t = idx % T, n = idx / T;
+    if (idx < total) {
+      const long long ii = l0 + t;
       double kk;
       if (alpha == 0) kk = (double)freq_of(n, g.N1);
-      else if (alpha == 1) kk = (double)freq_of((int)(i / g.H), g.N2);
-      else kk = (double)(i % g.H);
-      v = cmul_i(v, 2.0 * kPi * kk);
+      else if (alpha == 1) kk = (double)freq_of((int)(ii / g.H), g.N2);
+      else kk = (double)(ii % g.H);
+      sm[t * N + n] = cmul_i(v[i], 2.0 * kPi * kk);
     }
-    A[t * N + n] = v;
   }
   __syncthreads();
-  double2* r = lds_fft<1>(A, B, T, f);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+  lds_fft1<1, GEN>(sm, T, f, tw);
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
     const int t = idx % T, n = idx / T;
-    if (t < tcount) d[(long long)n * inner + l0 + t] = r[t * N + n];
+    if (idx < total && t < tcount) d[(long long)n * inner + l0 + t] = sm[t * N + n];
   }
 }
 
 // ---------------------------------------------------------------- P5
 // q[e] = (1/|N|) sum_alpha -2 pi i k_alpha F_axis1(t[e][alpha]); also the
 // partial sums of (p[e], q[e]) (Hermitian weights: 1 on h = 0, else 2).
-__global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
-                            const double2* __restrict__ p, G3 g, int alpha0, int nalpha,
-                            double inv_vol, int T, FftDev f, const int* __restrict__ done,
-                            double* __restrict__ part_pq) {
+template <bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
+                                                          const double2* __restrict__ p, G3 g, int alpha0, int nalpha,
+                                                          double inv_vol, int T, FftDev f,
+                                                          const int* __restrict__ done, double* __restrict__ part_pq) {
   extern __shared__ double2 sm[];
   __shared__ double red[kBlock / 64];
   const int e = blockIdx.y;
@@ -118,24 +128,33 @@ __global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__
   const long long inner = (long long)g.N2 * g.H;
   const long long l0 = (long long)blockIdx.x * T;
   const int tcount = (int)min((long long)T, inner - l0);
-  double2* A = sm;
-  double2* B = sm + T * N;
   const int total = T * N;
-  double2 acc[kMaxPer];
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  double2 acc[kFftMaxE];
 #pragma unroll
-  for (int j = 0; j < kMaxPer; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int j = 0; j < kFftMaxE; ++j) acc[j] = make_double2(0.0, 0.0);
   for (int a = 0; a < nalpha; ++a) {
     const int alpha = alpha0 + a;
     const double2* s = t + ((long long)e * nalpha + a) * g.S;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    double2 v[kFftMaxE];
+#pragma unroll
+    for (int i = 0; i < kFftMaxE; ++i) {
+      const int idx = threadIdx.x + i * kFftBlock;
       const int tt = idx % T, n = idx / T;
-      A[tt * N + n] = (tt < tcount) ? s[(long long)n * inner + l0 + tt] : make_double2(0.0, 0.0);
+      v[i] = (idx < total && tt < tcount) ? s[(long long)n * inner + l0 + tt] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < kFftMaxE; ++i) {
+      const int idx = threadIdx.x + i * kFftBlock;
+      const int tt = idx % T, n = idx / T;
+      if (idx < total) sm[tt * N + n] = v[i];
     }
     __syncthreads();
-    const double2* r = lds_fft<-1>(A, B, T, f);
+    lds_fft1<-1, GEN>(sm, T, f, tw);
 #pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) {
-      const int idx = threadIdx.x + j * kBlock;
+    for (int j = 0; j < kFftMaxE; ++j) {
+      const int idx = threadIdx.x + j * kFftBlock;
       if (idx < total) {
         const int tt = idx % T, n = idx / T;
         const long long i = l0 + tt;
@@ -143,10 +162,10 @@ __global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__
         if (alpha == 0) kk = (double)freq_of(n, g.N1);
         else if (alpha == 1) kk = (double)freq_of((int)(i / g.H), g.N2);
         else kk = (double)(i % g.H);
-        const double2 v = r[tt * N + n];
+        const double2 w = sm[tt * N + n];
         const double c = -2.0 * kPi * kk * inv_vol;
-        acc[j].x += -v.y * c;
-        acc[j].y += v.x * c;
+        acc[j].x += -w.y * c;
+        acc[j].y += w.x * c;
       }
     }
     __syncthreads();
@@ -155,8 +174,8 @@ __global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__
   const double2* pe = p + (long long)e * g.S;
   double2* qe = q + (long long)e * g.S;
 #pragma unroll
-  for (int j = 0; j < kMaxPer; ++j) {
-    const int idx = threadIdx.x + j * kBlock;
+  for (int j = 0; j < kFftMaxE; ++j) {
+    const int idx = threadIdx.x + j * kFftBlock;
     const int tt = idx % T, n = idx / T;
     if (idx < total && tt < tcount) {
       const long long i = l0 + tt;
@@ -178,70 +197,91 @@ __global__ void k_div_axis1(const double2* __restrict__ t, double2* __restrict__
 // Two real lines (l0, l0+1) share one complex FFT.  grid.x = pair tiles,
 // grid.y = array index b (array b at src + b*src_stride, dst likewise),
 // done index = b / done_div.
-template <int MODE>
-__global__ void k_axis3(const void* __restrict__ src_, void* __restrict__ dst_,
-                        const double* __restrict__ acoef, G3 g, long long src_stride,
-                        long long dst_stride, int T, FftDev f, double scale,
-                        const int* __restrict__ done, int done_div) {
+template <int MODE, bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ src_, void* __restrict__ dst_,
+                                                      const double* __restrict__ acoef, G3 g, long long src_stride,
+                                                      long long dst_stride, int T, FftDev f, double scale,
+                                                      const int* __restrict__ done, int done_div) {
   extern __shared__ double2 sm[];
   const int b = blockIdx.y;
   if (done != nullptr && done[b / done_div]) return;
   const int N = g.N3, H = g.H;
   const long long nl = (long long)g.N1 * g.N2;
   const long long p0 = (long long)blockIdx.x * T;      // first pair
-  double2* A = sm;
-  double2* B = sm + T * N;
   const int total = T * N;
-  // load
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int n = idx % N, t = idx / N;
-    const long long la = 2 * (p0 + t), lb = la + 1;
-    double2 z = make_double2(0.0, 0.0);
-    if (MODE == 1) {
-      const double* s = static_cast<const double*>(src_) + b * src_stride;
-      const double xa = la < nl ? s[la * N + n] : 0.0;
-      const double xb = lb < nl ? s[lb * N + n] : 0.0;
-      z = make_double2(xa, xb);
-    } else {
-      const double2* s = static_cast<const double2*>(src_) + b * src_stride;
-      const int m = n < H ? n : N - n;
-      const bool cj = n >= H;
-      double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
-      if (la < nl) xa = s[la * H + m];
-      if (lb < nl) xb = s[lb * H + m];
-      if (cj) { xa.y = -xa.y; xb.y = -xb.y; }
-      z = make_double2(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  // load (two real lines per complex line)
+  {
+    double2 v[kFftMaxE];
+#pragma unroll
+    for (int i = 0; i < kFftMaxE; ++i) {
+      const int idx = threadIdx.x + i * kFftBlock;
+      const int n = idx % N, t = idx / N;
+      const long long la = 2 * (p0 + t), lb = la + 1;
+      double2 z = make_double2(0.0, 0.0);
+      if (idx < total) {
+        if (MODE == 1) {
+          const double* s = static_cast<const double*>(src_) + b * src_stride;
+          const double xa = la < nl ? s[la * N + n] : 0.0;
+          const double xb = lb < nl ? s[lb * N + n] : 0.0;
+          z = make_double2(xa, xb);
+        } else {
+          const double2* s = static_cast<const double2*>(src_) + b * src_stride;
+          const int m = n < H ? n : N - n;
+          const bool cj = n >= H;
+          double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
+          if (la < nl) xa = s[la * H + m];
+          if (lb < nl) xb = s[lb * H + m];
+          if (cj) {
+            xa.y = -xa.y;
+            xb.y = -xb.y;
+          }
+          z = make_double2(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+        }
+      }
+      v[i] = z;
     }
-    A[t * N + n] = z;
+#pragma unroll
+    for (int i = 0; i < kFftMaxE; ++i) {
+      const int idx = threadIdx.x + i * kFftBlock;
+      if (idx < total) sm[idx] = v[i];
+    }
   }
   __syncthreads();
-  double2* r = A;
   if (MODE != 1) {
-    r = lds_fft<1>(A, B, T, f);
+    lds_fft1<1, GEN>(sm, T, f, tw);
     if (MODE == 2) {
       double* d = static_cast<double*>(dst_) + b * dst_stride;
-      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+#pragma unroll
+      for (int i = 0; i < kFftMaxE; ++i) {
+        const int idx = threadIdx.x + i * kFftBlock;
         const int n = idx % N, t = idx / N;
         const long long la = 2 * (p0 + t), lb = la + 1;
-        const double2 v = r[t * N + n];
-        if (la < nl) d[la * N + n] = v.x * scale;
-        if (lb < nl) d[lb * N + n] = v.y * scale;
+        if (idx < total) {
+          const double2 w = sm[idx];
+          if (la < nl) d[la * N + n] = w.x * scale;
+          if (lb < nl) d[lb * N + n] = w.y * scale;
+        }
       }
       return;
     }
-    // multiply real parts by the two coefficient lines
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    // multiply the two real parts by their coefficient lines
+#pragma unroll
+    for (int i = 0; i < kFftMaxE; ++i) {
+      const int idx = threadIdx.x + i * kFftBlock;
       const int n = idx % N, t = idx / N;
       const long long la = 2 * (p0 + t), lb = la + 1;
-      const double aa = la < nl ? acoef[la * N + n] : 0.0;
-      const double ab = lb < nl ? acoef[lb * N + n] : 0.0;
-      const double2 v = r[t * N + n];
-      r[t * N + n] = make_double2(v.x * aa, v.y * ab);
+      if (idx < total) {
+        const double aa = la < nl ? acoef[la * N + n] : 0.0;
+        const double ab = lb < nl ? acoef[lb * N + n] : 0.0;
+        const double2 w = sm[idx];
+        sm[idx] = make_double2(w.x * aa, w.y * ab);
+      }
     }
     __syncthreads();
   }
-  double2* o = (r == A) ? B : A;
-  double2* w = lds_fft<-1>(r, o, T, f);
+  lds_fft1<-1, GEN>(sm, T, f, tw);
   // separate the two Hermitian spectra and store h in [0, H)
   double2* d = static_cast<double2*>(MODE == 0 ? const_cast<void*>(src_) : dst_) +
                b * (MODE == 0 ? src_stride : dst_stride);
@@ -249,8 +289,8 @@ __global__ void k_axis3(const void* __restrict__ src_, void* __restrict__ dst_,
   for (int idx = threadIdx.x; idx < htot; idx += blockDim.x) {
     const int h = idx % H, t = idx / H;
     const long long la = 2 * (p0 + t), lb = la + 1;
-    const double2 W1 = w[t * N + h];
-    const double2 W2 = w[t * N + (h == 0 ? 0 : N - h)];
+    const double2 W1 = sm[t * N + h];
+    const double2 W2 = sm[t * N + (h == 0 ? 0 : N - h)];
     // Xa = (W1 + conj W2)/2, Xb = (W1 - conj W2)/(2i)
     const double2 xa = make_double2(0.5 * (W1.x + W2.x), 0.5 * (W1.y - W2.y));
     const double2 dd = make_double2(W1.x - W2.x, W1.y + W2.y);
@@ -502,11 +542,7 @@ struct FullLayout {
   int nstat;      // blocks of coef stats / ah reduce
 };
 
-static int tile1_lines(int N1) {
-  int T = lines_per_tile(N1);
-  while (T > 1 && T * N1 > kMaxPer * kBlock) --T;
-  return T;
-}
+static int tile1_lines(int N1) { return lines_per_tile1(N1); }
 
 static G3 make_g3(const int N[3]) {
   G3 g;
@@ -524,7 +560,7 @@ static void carve(Arena& ar, FullLayout& L, const int N3d[3], int nE, int d, int
   L.nE = nE;
   const G3& g = L.g;
   L.T1 = tile1_lines(g.N1);
-  L.T3 = lines_per_tile(g.N3);
+  L.T3 = lines_per_tile1(g.N3);
   L.tiles1 = ceil_div((long long)g.N2 * g.H, L.T1);
   long long gv = ceil_div(g.S, kBlock * 4);
   if (gv > 1024) gv = 1024;
@@ -598,6 +634,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   LRFG_TRY(fft_dev_upload(*A.plan1, L.tw1, s, &f1));
   LRFG_TRY(fft_dev_upload(*A.plan2, L.tw2, s, &f2));
   LRFG_TRY(fft_dev_upload(*A.plan3, L.tw3, s, &f3));
+  const bool G1 = plan_generic(f1), G3 = plan_generic(f3);
 
   // coefficient
   if (A.a_on_device) {
@@ -641,15 +678,15 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   }
   LRFG_HIP(hipMemcpyAsync(L.floor_abs, floors.data(), sizeof(double) * nE, hipMemcpyHostToDevice, s));
 
-  const size_t shm1 = size_t(2) * L.T1 * g.N1 * sizeof(double2);
-  const size_t shm3 = size_t(2) * L.T3 * g.N3 * sizeof(double2);
+  const size_t shm1 = size_t(L.T1 + 1) * g.N1 * sizeof(double2);
+  const size_t shm3 = size_t(L.T3 + 1) * g.N3 * sizeof(double2);
   const long long pairs = ((long long)g.N1 * g.N2 + 1) / 2;
   const int tiles3 = ceil_div(pairs, L.T3);
   const double inv_vol = 1.0 / (double)g.R;
 
   // a^ = F(a): R2C along axis 3, then axes 2 and 1 (scale 1/|N| at the end).
   double2* ahat = L.q;  // q[0] is free until the first matvec
-  hipLaunchKernelGGL(k_axis3<1>, dim3(tiles3, 1), dim3(kBlock), shm3, s, (const void*)L.a, (void*)ahat,
+  hipLaunchKernelGGL((G3 ? k_axis3<1, true> : k_axis3<1, false>), dim3(tiles3, 1), dim3(kBlock), shm3, s, (const void*)L.a, (void*)ahat,
                      (const double*)nullptr, g, 0LL, 0LL, L.T3, f3, 1.0, (const int*)nullptr, 1);
   LRFG_LAUNCHED();
   LRFG_TRY(launch_fft_lines(ahat, g.N1, g.N2, g.H, -1, f2, 1.0, s));
@@ -675,7 +712,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     // P1
     {
       ProfScope ps_("grad_axis1", s);
-      hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1 * d, nE), dim3(kBlock), shm1, s, (const double2*)L.p,
+      hipLaunchKernelGGL((G1 ? k_grad_axis1<true> : k_grad_axis1<false>), dim3(L.tiles1 * d, nE), dim3(kBlock), shm1, s, (const double2*)L.p,
                          L.t, g, alpha0, d, (long long)d * g.S, g.S, L.T1, f1, (const int*)L.done);
     }
     LRFG_LAUNCHED();
@@ -685,7 +722,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     // P3
     {
       ProfScope ps_("axis3", s);
-      hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, nE * d), dim3(kBlock), shm3, s, (const void*)L.t,
+      hipLaunchKernelGGL((G3 ? k_axis3<0, true> : k_axis3<0, false>), dim3(tiles3, nE * d), dim3(kBlock), shm3, s, (const void*)L.t,
                          (void*)nullptr, (const double*)L.a, g, g.S, 0LL, L.T3, f3, 1.0,
                          (const int*)L.done, d);
     }
@@ -696,7 +733,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     // P5
     {
       ProfScope ps_("div_axis1", s);
-      hipLaunchKernelGGL(k_div_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.t, L.q,
+      hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.t, L.q,
                          (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1, (const int*)L.done,
                          L.part_pq);
     }
@@ -743,11 +780,11 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   std::vector<double> m1(nE * d, 0.0), m2((size_t)nE * nE * d, 0.0);
   std::vector<double> part((size_t)L.nstat * nv);
   for (int al = 0; al < d; ++al) {
-    hipLaunchKernelGGL(k_grad_axis1, dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.x, L.t, g,
+    hipLaunchKernelGGL((G1 ? k_grad_axis1<true> : k_grad_axis1<false>), dim3(L.tiles1, nE), dim3(kBlock), shm1, s, (const double2*)L.x, L.t, g,
                        alpha0 + al, 1, g.S, 0LL, L.T1, f1, (const int*)nullptr);
     LRFG_LAUNCHED();
     LRFG_TRY(launch_fft_lines(L.t, (long long)nE * g.N1, g.N2, g.H, 1, f2, 1.0, s));
-    hipLaunchKernelGGL(k_axis3<2>, dim3(tiles3, nE), dim3(kBlock), shm3, s, (const void*)L.t, (void*)L.q,
+    hipLaunchKernelGGL((G3 ? k_axis3<2, true> : k_axis3<2, false>), dim3(tiles3, nE), dim3(kBlock), shm3, s, (const void*)L.t, (void*)L.q,
                        (const double*)nullptr, g, g.S, 2 * g.S, L.T3, f3, 1.0, (const int*)nullptr, 1);
     LRFG_LAUNCHED();
     hipLaunchKernelGGL(k_ah_reduce, dim3(L.nstat), dim3(kBlock), 0, s, (const double*)L.a,
@@ -845,23 +882,24 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   LRFG_TRY(fft_dev_upload(*p1, tw1, s, &f1));
   LRFG_TRY(fft_dev_upload(*p2, tw2, s, &f2));
   LRFG_TRY(fft_dev_upload(*p3, tw3, s, &f3));
+  const bool G1 = plan_generic(f1), G3 = plan_generic(f3);
   LRFG_HIP(hipMemsetAsync(done, 0, sizeof(int) * 4, s));
   const int T1 = tile1_lines(g.N1);
-  const int T3 = lines_per_tile(g.N3);
+  const int T3 = lines_per_tile1(g.N3);
   const int tiles1 = ceil_div((long long)g.N2 * g.H, T1);
-  const size_t shm1 = size_t(2) * T1 * g.N1 * sizeof(double2);
-  const size_t shm3 = size_t(2) * T3 * g.N3 * sizeof(double2);
+  const size_t shm1 = size_t(T1 + 1) * g.N1 * sizeof(double2);
+  const size_t shm3 = size_t(T3 + 1) * g.N3 * sizeof(double2);
   const long long pairs = ((long long)g.N1 * g.N2 + 1) / 2;
   const int tiles3 = ceil_div(pairs, T3);
-  hipLaunchKernelGGL(k_grad_axis1, dim3(tiles1 * 3, 1), dim3(kBlock), shm1, s, uh, t, g, 0, 3, 3 * g.S, g.S, T1,
+  hipLaunchKernelGGL((G1 ? k_grad_axis1<true> : k_grad_axis1<false>), dim3(tiles1 * 3, 1), dim3(kBlock), shm1, s, uh, t, g, 0, 3, 3 * g.S, g.S, T1,
                      f1, (const int*)done);
   LRFG_LAUNCHED();
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, 1, f2, 1.0, s));
-  hipLaunchKernelGGL(k_axis3<0>, dim3(tiles3, 3), dim3(kBlock), shm3, s, (const void*)t, (void*)nullptr, a, g, g.S,
+  hipLaunchKernelGGL((G3 ? k_axis3<0, true> : k_axis3<0, false>), dim3(tiles3, 3), dim3(kBlock), shm3, s, (const void*)t, (void*)nullptr, a, g, g.S,
                      0LL, T3, f3, 1.0, (const int*)done, 3);
   LRFG_LAUNCHED();
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, -1, f2, 1.0, s));
-  hipLaunchKernelGGL(k_div_axis1, dim3(tiles1, 1), dim3(kBlock), shm1, s, (const double2*)t, oh, uh, g, 0, 3,
+  hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(tiles1, 1), dim3(kBlock), shm1, s, (const double2*)t, oh, uh, g, 0, 3,
                      1.0 / (double)g.R, T1, f1, (const int*)done, part);
   LRFG_LAUNCHED();
   return LRFG_OK;
