@@ -21,6 +21,7 @@
 namespace lrfg {
 
 constexpr int kMaxStages = 24;
+constexpr int kMaxTerms = 32;   // exponential-sum terms handled per launch
 
 // Device view of one length's plan, passed by value to kernels.
 struct FftDev {
@@ -53,6 +54,11 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
 // real array x[outer][N][inner]; op 0: s = 2 pi i k, op 1: s = exp(-t k^2).
 int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t,
                    const FftDev& f, hipStream_t s);
+// All M heat-kernel terms of one carriage in one launch, written into the
+// block carriage of their sum (see fft.hip).
+int launch_mode_op_blocks(const double* xin, long long sx, int r0, int r1, int nE, double* out, long long so,
+                          int R1, bool bl0, bool bl1, int M, const double* t, const double* sc, const FftDev& f,
+                          hipStream_t s);
 
 // ---------------------------------------------------------------- device
 template <int DIR>

@@ -183,6 +183,121 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   }
 }
 
+// Heat-kernel terms of a separable exponential sum written straight into
+// the block carriage of their sum: for term m (blockIdx.y), the fibres of
+// the input carriage x[e][a][:][b] (r0 x N x r1 per system, stride sx) go
+// through F^-1 diag(exp(-t_m k^2)) F, are scaled by sc_m, and land at
+// out[e][o0 + a][:][o1 + b] of the R0 x N x R1 output (stride so) with
+// o0 = m r0 when bl0, o1 = m r1 when bl1.
+struct TermParams {
+  double t[kMaxTerms];
+  double sc[kMaxTerms];
+};
+
+template <bool GEN>
+__global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __restrict__ xin, long long sx, int r0,
+                                                               int r1, int nE, double* __restrict__ out,
+                                                               long long so, int R1, int bl0, int bl1, int T,
+                                                               FftDev f, TermParams tp) {
+  extern __shared__ double2 sm[];
+  const int N = f.N;
+  const int m = blockIdx.y;
+  const long long nfib = (long long)nE * r0 * r1;
+  const long long f0 = (long long)blockIdx.x * (2 * T);
+  const int total = T * N;
+  double2* tw = sm + total;
+  stage_twiddles(tw, f);
+  const int o0 = bl0 ? m * r0 : 0, o1 = bl1 ? m * r1 : 0;
+  auto in_addr = [&](long long l, int n) -> long long {
+    const long long e = l / ((long long)r0 * r1);
+    const long long rem = l - e * r0 * r1;
+    const int a = (int)(rem / r1), b = (int)(rem - (long long)(rem / r1) * r1);
+    return e * sx + ((long long)a * N + n) * r1 + b;
+  };
+  auto out_addr = [&](long long l, int n) -> long long {
+    const long long e = l / ((long long)r0 * r1);
+    const long long rem = l - e * r0 * r1;
+    const int a = (int)(rem / r1), b = (int)(rem - (long long)(rem / r1) * r1);
+    return e * so + ((long long)(o0 + a) * N + n) * R1 + o1 + b;
+  };
+  const bool fibre_fast = r1 > 1;  // consecutive fibres are adjacent in memory
+  double2 v[kFftMaxE];
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    int t, n;
+    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    const long long fa = f0 + 2 * t, fb = fa + 1;
+    const double re = (idx < total && fa < nfib) ? xin[in_addr(fa, n)] : 0.0;
+    const double im = (idx < total && fb < nfib) ? xin[in_addr(fb, n)] : 0.0;
+    v[i] = make_double2(re, im);
+  }
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    int t, n;
+    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    if (idx < total) sm[t * N + n] = v[i];
+  }
+  __syncthreads();
+  lds_fft1<-1, GEN>(sm, T, f, tw);
+  __syncthreads();
+  const double tm = tp.t[m], scm = tp.sc[m];
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int n = idx % N;
+    const int k = freq_of(n, N);
+    sm[idx] = cscale(sm[idx], scm * exp(-tm * (double)k * (double)k) / (double)N);
+  }
+  __syncthreads();
+  lds_fft1<1, GEN>(sm, T, f, tw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kFftMaxE; ++i) {
+    const int idx = threadIdx.x + i * kFftBlock;
+    int t, n;
+    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    const long long fa = f0 + 2 * t, fb = fa + 1;
+    if (idx < total) {
+      const double2 w = sm[t * N + n];
+      if (fa < nfib) out[out_addr(fa, n)] = w.x;
+      if (fb < nfib) out[out_addr(fb, n)] = w.y;
+    }
+  }
+}
+
+int launch_mode_op_blocks(const double* xin, long long sx, int r0, int r1, int nE, double* out, long long so,
+                          int R1, bool bl0, bool bl1, int M, const double* t, const double* sc, const FftDev& f,
+                          hipStream_t s) {
+  if (M < 1 || M > kMaxTerms) {
+    set_error("exponential sum with %d terms (1..%d)", M, kMaxTerms);
+    return LRFG_EUNSUPPORTED;
+  }
+  const int N = f.N;
+  if (N > kFftMaxE * kFftBlock) {
+    set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
+    return LRFG_EUNSUPPORTED;
+  }
+  const long long nfib = (long long)nE * r0 * r1;
+  if (nfib == 0) return LRFG_OK;
+  TermParams tp;
+  for (int i = 0; i < kMaxTerms; ++i) {
+    tp.t[i] = i < M ? t[i] : 0.0;
+    tp.sc[i] = i < M ? sc[i] : 0.0;
+  }
+  const int T = lines_per_tile1(N);
+  const size_t shm = size_t(T + 1) * N * sizeof(double2);
+  dim3 grid(ceil_div(nfib, 2 * T), M);
+  ProfScope ps_("mode_op_blocks", s);
+  if (plan_generic(f))
+    hipLaunchKernelGGL(k_mode_op_blocks<true>, grid, dim3(kFftBlock), shm, s, xin, sx, r0, r1, nE, out, so, R1,
+                       (int)bl0, (int)bl1, T, f, tp);
+  else
+    hipLaunchKernelGGL(k_mode_op_blocks<false>, grid, dim3(kFftBlock), shm, s, xin, sx, r0, r1, nE, out, so, R1,
+                       (int)bl0, (int)bl1, T, f, tp);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
 int fft_dev_upload(const FftPlan& p, double2* d_table, hipStream_t s, FftDev* out) {
   LRFG_HIP(hipMemcpyAsync(d_table, p.table.data(), sizeof(double2) * p.N, hipMemcpyHostToDevice, s));
   FftDev f;

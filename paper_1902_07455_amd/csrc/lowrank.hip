@@ -269,27 +269,23 @@ int apply_K(Ctx& C, const TTB& v, TTB& out) {
   return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
 }
 
-// out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}
+// out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}:
+// the M terms are written straight into the block carriages of their sum
+// (one launch per carriage), then truncated.
 int apply_P(Ctx& C, const TTB& v, TTB& out) {
   const int d = C.d, nE = C.nE;
   const int M = C.pl->M;
-  std::vector<TTB> terms_b(M);
-  std::vector<TTTerm> terms(M);
-  for (int m = 0; m < M; ++m) {
-    TTB cur = v;
-    for (int al = 0; al < d; ++al) {
-      TTB nxt = cur;
-      nxt.c[al] = C.pcore + ((long long)m * d + al) * C.pcore_stride;
-      LRFG_TRY(tt_mode_apply(cur, nxt, al, 1, C.pl->t[m], 1.0, C.f[al], nE, C.s));
-      cur = nxt;
-    }
-    terms_b[m] = cur;
-    terms[m] = TTTerm{&terms_b[m], nullptr, C.pl->w[m] / (4.0 * kPi * kPi)};
-  }
   TTB comb = C.comb;
   for (int j = 1; j < d; ++j) comb.r[j] = M * v.r[j];
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
-  LRFG_TRY(tt_sum(terms.data(), M, comb, nE, C.s));
+  for (int j = 1; j < d - 1; ++j) LRFG_TRY(tt_fill(comb.c[j], comb.size(j) * nE, 0.0, C.s));
+  std::vector<double> sc(M), one(M, 1.0);
+  for (int m = 0; m < M; ++m) sc[m] = C.pl->w[m] / (4.0 * kPi * kPi);
+  for (int j = 0; j < d; ++j) {
+    LRFG_TRY(launch_mode_op_blocks(v.c[j], v.s[j], v.r[j], v.r[j + 1], nE, comb.c[j], comb.s[j], comb.r[j + 1],
+                                   j > 0, j < d - 1, M, C.pl->t.data(), j == 0 ? sc.data() : one.data(), C.f[j],
+                                   C.s));
+  }
   return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
 }
 
