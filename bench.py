@@ -48,6 +48,12 @@ def main(argv=None):
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
     ap.add_argument("--tt-steps", type=int, default=10)
     ap.add_argument("--no-tt", action="store_true", help="skip the tensor-train leg")
+    ap.add_argument("--full-tol", type=float, default=None,
+                    help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
+    ap.add_argument("--tt-cap", type=int, default=None, help="TT rank cap (skips the cap sweep)")
+    ap.add_argument("--tt-tol", type=float, default=None, help="TT solver tolerance (skips the tol sweep)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (scale for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
@@ -60,6 +66,14 @@ def main(argv=None):
     import workloads as W
 
     dev = "cuda:0"
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
+        del src, dst
     p = W.smooth_params(0)
     cp = W.smooth_cp(N, p)
     a_np = cp.full()
@@ -76,7 +90,9 @@ def main(argv=None):
     # ---------------------------------------------------------------- full-grid tolerance sweep
     full_tol = None
     sweep = []
-    for tol in [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8]:
+    full_tols = [args.full_tol] if args.full_tol else [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5,
+                                                        1e-5, 1e-6, 1e-7, 1e-8]
+    for tol in full_tols:
         s = P.Solver(d=3, N=(N, N, N), format="full", solver_tol=tol, max_iter=500, device=dev)
         r = s.solve(full=a_dev)
         e = rel_err(r.A_H, A_ref)
@@ -159,7 +175,7 @@ def main(argv=None):
 
         tt_sweep = []
         tt_cap = None
-        for cap in [4, 6, 8, 10, 12, 16, 20]:
+        for cap in ([args.tt_cap] if args.tt_cap else [4, 6, 8, 10, 12, 16, 20]):
             s = tt_solver(cap, 1e-8)
             r = s.solve(cp=(w_dev, f_dev))
             e = rel_err(r.A_H, A_ref)
@@ -170,7 +186,7 @@ def main(argv=None):
                 break
         tt_tol = None
         if tt_cap is not None:
-            for tol in [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]:
+            for tol in ([args.tt_tol] if args.tt_tol else [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]):
                 s = tt_solver(tt_cap, tol)
                 r = s.solve(cp=(w_dev, f_dev))
                 e = rel_err(r.A_H, A_ref)
