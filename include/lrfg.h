@@ -215,6 +215,22 @@ int lrfg_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A
  * from these Gram eigenpairs (Sec. 3.1.4). */
 int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* stream);
 
+/* Truncation basis of batched symmetric positive semidefinite Gram
+ * matrices (the l x l Gram matrices of the truncation's SVD cut, Sec. 3.1.4
+ * and Appendix A.3), n <= 64, all pointers device: G is batch x n x n
+ * (row-major); S (batch x n x c) receives the eigenvectors of the kept
+ * eigenvalues as columns, largest first, with zero columns beyond the kept
+ * count.  Kept: at most c, above the rank threshold of the pivoted
+ * Cholesky factorisation G = L^T L (largest remaining diagonal > 1e-15 of
+ * the largest initial one), and, when tol > 0, the fewest whose dropped
+ * eigenvalue sum (with the mass below that threshold) is at most
+ * tol^2 trace(G).  The eigenpairs come from one-sided Jacobi on the columns
+ * of L^T.  kept and sweeps (batch ints each: kept count, Jacobi sweeps
+ * used) may be NULL.  Stream-ordered; returns LRFG_EINVAL for n outside
+ * [1, 64], c < 1, negative or NaN tol or null G/S. */
+int lrfg_gram_cut(int n, int c, const double* G, int batch, double tol, double* S, int* kept, int* sweeps,
+                  void* stream);
+
 /* TT truncation (rounding, Appendix A.3) of nE trains with input ranks
  * rin[0..d] (rin[0] = rin[d] = 1), carriages in_cores[j] = nE x
  * [r_{j-1}][N_j][r_j] (device).  Output ranks are fixed,

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read"]
+           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
             "tt": _lib.FORMAT_TT}
@@ -272,6 +272,22 @@ def syevj(A, stream=None):
     check(lib().lrfg_syevj(n, C.c_void_p(A.data_ptr()), bt, C.c_void_p(W.data_ptr()),
                            C.c_void_p(V.data_ptr()), C.c_void_p(_stream_handle(stream))))
     return W, V
+
+
+def gram_cut(G, c: int, tol: float = 0.0, stream=None):
+    """Truncation basis of a (batch, n, n) float64 CUDA tensor of PSD Gram
+    matrices: (S (batch, n, c) kept eigenvectors, kept (batch,), sweeps
+    (batch,)) as tensors."""
+    torch = _torch()
+    bt, n = G.shape[0], G.shape[1]
+    G = G.contiguous()
+    S = torch.empty((bt, n, c), dtype=torch.float64, device=G.device)
+    kept = torch.empty((bt,), dtype=torch.int32, device=G.device)
+    sweeps = torch.empty((bt,), dtype=torch.int32, device=G.device)
+    check(lib().lrfg_gram_cut(n, c, C.c_void_p(G.data_ptr()), bt, float(tol), C.c_void_p(S.data_ptr()),
+                              C.c_void_p(kept.data_ptr()), C.c_void_p(sweeps.data_ptr()),
+                              C.c_void_p(_stream_handle(stream))))
+    return S, kept, sweeps
 
 
 def tt_round(cores, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):

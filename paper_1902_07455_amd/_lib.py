@@ -77,7 +77,7 @@ EXPORTS = [
     "lrfg_plan_create", "lrfg_plan_workspace_bytes", "lrfg_solve", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read",
-    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_tt_round_workspace_bytes",
+    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_gram_cut", "lrfg_tt_round_workspace_bytes",
     "lrfg_tt_round",
 ]
 
@@ -127,6 +127,9 @@ def lib():
     L.lrfg_gemm.restype = C.c_int
     L.lrfg_syevj.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     L.lrfg_syevj.restype = C.c_int
+    L.lrfg_gram_cut.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p]
+    L.lrfg_gram_cut.restype = C.c_int
     L.lrfg_tt_round_workspace_bytes.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                                 C.c_int, C.c_int, C.c_int]
     L.lrfg_tt_round_workspace_bytes.restype = C.c_size_t

@@ -41,4 +41,16 @@ int syevj(int n, const double* A, long long lda, long long sA, double* W, long l
 int pchol_s(int n, const double* G, long long sG, double tau, double* S, long long sS, int* rank, int batch,
             hipStream_t s);
 
+// Truncation basis of batched PSD Gram matrices G (n x n, stride sG):
+// S (n x c, stride sS) = eigenvectors of the kept eigenvalues, largest
+// first (at most c, none below the Cholesky threshold kCutTau or the
+// floor kCutFloor relative to the largest, and with tol2 > 0 the fewest
+// whose dropped eigenvalue sum is <= tol2 * trace G), zero columns beyond;
+// kept and sweeps (device, batch ints: kept rank, Jacobi sweeps) or null.
+constexpr double kCutTau = 1e-15;    // pivoted-Cholesky rank threshold (relative diagonal)
+constexpr double kCutEps = 2.5e-16;  // one-sided Jacobi: pair orthogonality, relative, per row
+constexpr double kCutFloor = 1e-28;  // smallest kept eigenvalue relative to the largest
+int cut_psd(int n, int c, const double* G, long long sG, double tol2, double* S, long long sS, int* kept, int batch,
+            hipStream_t s, int* sweeps = nullptr);
+
 }  // namespace lrfg

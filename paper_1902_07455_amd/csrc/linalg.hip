@@ -198,20 +198,40 @@ __global__ __launch_bounds__(64) void k_gemm_s(int m, int n, int k, const double
       }
 }
 
-__global__ void k_splitk_reduce(int m, int n, int ksplit, int batch, const double* __restrict__ part,
-                                double* __restrict__ C, long long ldc, long long sC, double alpha,
-                                double beta) {
-  const long long tot = (long long)batch * m * n;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int col = (int)(e % n);
-    const long long r = e / n;
-    const int row = (int)(r % m);
-    const int bt = (int)(r / m);
-    double v = 0.0;
-    for (int ks = 0; ks < ksplit; ++ks) v += part[(((long long)bt * ksplit + ks) * m + row) * n + col];
+// C = alpha * sum_ks part[ks] + beta * C.  The partials were just written
+// from every XCD, so they come from HBM / the Infinity Cache: a block
+// spreads the splits of 32 outputs over 8 thread groups, each with eight
+// loads in flight, and adds the 8 group sums in a fixed order.
+__global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit, int batch,
+                                                       const double* __restrict__ part, double* __restrict__ C,
+                                                       long long ldc, long long sC, double alpha, double beta) {
+  __shared__ double red[8][33];
+  const long long mn = (long long)m * n;
+  const long long tot = (long long)batch * mn;
+  const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long long e = (long long)blockIdx.x * 32 + o;
+  double v = 0.0;
+  if (e < tot) {
+    const long long bt = e / mn, idx = e - bt * mn;
+    const double* p = part + bt * ksplit * mn + idx;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = g;
+    for (; k + 56 < ksplit; k += 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += p[(long long)(k + 8 * u) * mn];
+    }
+    for (; k < ksplit; k += 8) a[0] += p[(long long)k * mn];
+    v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
+  red[g][o] = v;
+  __syncthreads();
+  if (g == 0 && e < tot) {
+    const double sum = ((red[0][o] + red[1][o]) + (red[2][o] + red[3][o])) +
+                       ((red[4][o] + red[5][o]) + (red[6][o] + red[7][o]));
+    const long long bt = e / mn, idx = e - bt * mn;
+    const int row = (int)(idx / n), col = (int)(idx - (idx / n) * n);
     double* c = C + bt * sC + (long long)row * ldc + col;
-    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+    *c = (beta == 0.0) ? alpha * sum : alpha * sum + beta * (*c);
   }
 }
 
@@ -372,107 +392,307 @@ __global__ __launch_bounds__(256) void k_syevj(int n, const double* __restrict__
   }
 }
 
-// Rank-revealing Cholesky with diagonal pivoting of a symmetric positive
-// semidefinite G (n x n): G[perm, perm] = L L^T with L n x r lower
-// trapezoidal, stopped when the largest remaining diagonal entry is below
-// tau times the largest initial one.  Writes S (n x n) = P R^-1 with
-// R = L^T (r x r) in the first r columns and zeros elsewhere, so Q = Y S
-// has orthonormal columns spanning the numerical range of Y when
-// G = Y^T Y.  One 64-lane wave per matrix, lane i owns row i; R^-1 by
-// Gauss-Jordan elimination on the triangle (r parallel steps).
-__global__ __launch_bounds__(64) void k_pchol_s(int n, const double* __restrict__ Gg, long long sG, double tau,
-                                                double* __restrict__ Sg, long long sS, int* __restrict__ rank_out) {
-  extern __shared__ double sm[];
-  double* g = sm;            // n x n working matrix
-  double* ri = sm + n * n;   // n x n: R^-1 (upper)
-  __shared__ int perm[64];
-  __shared__ double lcol[64];
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x;
-  const double* G = Gg + b * sG;
-  for (int e = lane; e < n * n; e += 64) g[e] = G[e];
-  if (lane < n) perm[lane] = lane;
-  __syncthreads();
-  double dmax0 = (lane < n) ? g[lane * n + lane] : 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dmax0 = fmax(dmax0, __shfl_xor(dmax0, o, 64));
+// DPP lane moves within a row of 16 lanes (quad_perm swaps, half-row and
+// row mirrors) on 64-bit values.
+template <int CTRL>
+__device__ inline unsigned long long dpp_move_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
+
+// Maximum of a 64-bit key over the 64-lane wave (every lane gets it).
+__device__ inline unsigned long long wave_max_u64(unsigned long long k) {
+  unsigned long long o;
+  o = dpp_move_u64<kDppSwap1>(k);
+  k = o > k ? o : k;
+  o = dpp_move_u64<kDppSwap2>(k);
+  k = o > k ? o : k;
+  o = dpp_move_u64<kDppHalfMirror>(k);
+  k = o > k ? o : k;
+  o = dpp_move_u64<kDppMirror>(k);
+  k = o > k ? o : k;
+  o = __shfl_xor(k, 16, 64);
+  k = o > k ? o : k;
+  o = __shfl_xor(k, 32, 64);
+  k = o > k ? o : k;
+  return k;
+}
+
+// Rank-revealing Cholesky with diagonal pivoting of the symmetric positive
+// semidefinite n x n matrix in g (LDS, overwritten by the Schur
+// complements), n <= 64, by a block of NT threads (a multiple of 64).
+// Step k takes the largest remaining diagonal entry p = perm[k] as pivot
+// (near-ties within 64 ulps go to the lower index) and stores the pivot
+// column of the factor, in the original index order, as row k of L (LDS,
+// n x n): G = sum_{k<r} L[k]^T L[k].  It stops when the largest remaining
+// diagonal entry is at most tau times the largest initial one; returns r
+// (the same in every thread).  With Z != null it also builds Z (LDS, row k
+// = z_k, original coordinates) with z_k = (e_p - sum_{j<k} L[j][p] z_j) /
+// L[k][p], the columns of P R^-1 (Gram-Schmidt in the G inner product), so
+// that Y z_k are orthonormal when G = Y^T Y.  Wave 0 picks the pivot; the
+// last wave builds z_k; all threads update the Schur complement, thread t
+// on row t / (NT / 64) and every (NT / 64)-th column.
+template <int NT>
+__device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L, double* __restrict__ Z,
+                           int* __restrict__ perm, double tau, int* __restrict__ bc) {
+  constexpr int CG = NT / 64;
+  const int tid = threadIdx.x;
+  const bool w0 = tid < 64;
+  const int lane = tid & 63;
+  const int zl = tid - (NT - 64);  // lane of the last wave
+  const int ri = tid / CG, rj = tid - ri * CG;
+  bool chosen = lane >= n;
+  double d0 = 0.0;
+  if (w0) {
+    const double dv = (lane < n) ? fmax(g[lane * n + lane], 0.0) : 0.0;
+    d0 = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(dv)));
+  }
   int r = n;
   for (int k = 0; k < n; ++k) {
-    // argmax of the remaining diagonal over the wave (ties: lowest index)
-    double best = (lane >= k && lane < n) ? g[lane * n + lane] : -1.0;
-    int p = lane;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int op = __shfl_xor(p, o, 64);
-      if (ob > best || (ob == best && op < p)) {
-        best = ob;
-        p = op;
+    if (w0) {
+      // key: value bits of the (non-negative) diagonal, low 6 bits = 63 - lane
+      const double dv = chosen ? 0.0 : fmax(g[lane * n + lane], 0.0);
+      unsigned long long key = chosen ? 0ull : (((unsigned long long)__double_as_longlong(dv) & ~63ull) |
+                                                (unsigned long long)(63 - lane));
+      key = wave_max_u64(key);
+      const int p = 63 - (int)(key & 63ull);
+      const double best = (key == 0ull) ? 0.0 : g[p * n + p];
+      const bool stop = !(best > tau * d0) || !(best > 0.0);
+      if (!stop) {
+        const double inv = 1.0 / sqrt(best);
+        if (lane < n) L[k * n + lane] = chosen ? 0.0 : g[p * n + lane] * inv;
+        if (lane == p) chosen = true;
+        if (lane == 0) {
+          perm[k] = p;
+          bc[1] = p;
+        }
       }
+      if (lane == 0) bc[0] = stop ? 1 : 0;
     }
-    if (!(best > tau * dmax0) || !(best > 0.0)) {
+    __syncthreads();
+    if (bc[0]) {
       r = k;
       break;
     }
-    if (p != k) {
-      // symmetric swap of rows/cols k and p (and the permutation)
-      for (int j = lane; j < n; j += 64) {
-        const double t = g[k * n + j];
-        g[k * n + j] = g[p * n + j];
-        g[p * n + j] = t;
-      }
-      __syncthreads();
-      for (int i = lane; i < n; i += 64) {
-        const double t = g[i * n + k];
-        g[i * n + k] = g[i * n + p];
-        g[i * n + p] = t;
-      }
-      if (lane == 0) {
-        const int t = perm[k];
-        perm[k] = perm[p];
-        perm[p] = t;
-      }
-      __syncthreads();
+    const double* lk = L + k * n;
+    if (ri < n) {
+      const double li = lk[ri];
+      if (li != 0.0)
+        for (int j = rj; j < n; j += CG) g[ri * n + j] -= li * lk[j];
     }
-    const double lkk = sqrt(g[k * n + k]);
-    const double inv = 1.0 / lkk;
-    // column k of L (L[i][k] = g[i][k]/lkk) published in lcol, then each
-    // lane i > k updates its row: g[i][j] -= L[i][k] L[j][k], j > k
-    double lik = 0.0;
-    if (lane > k && lane < n) lik = g[lane * n + k] * inv;
-    if (lane < n) lcol[lane] = lik;
-    __syncthreads();
-    if (lane == k) g[k * n + k] = lkk;
-    if (lane > k && lane < n) {
-      g[lane * n + k] = lik;
-      for (int j = k + 1; j < n; ++j) g[lane * n + j] -= lik * lcol[j];
+    if (Z != nullptr && zl >= 0 && zl < n) {
+      const int p = bc[1];
+      double acc = (zl == p) ? 1.0 : 0.0;
+      for (int j = 0; j < k; ++j) acc -= L[j * n + p] * Z[j * n + zl];
+      Z[k * n + zl] = acc / lk[p];
     }
     __syncthreads();
   }
-  // R = L^T (r x r upper): R[i][j] = g[j][i] for j >= i.  Gauss-Jordan on
-  // [R | I]: for c = r-1 down to 0, scale row c by 1/R[c][c] and eliminate
-  // column c from the rows above (lane i owns row i of R^-1).
-  for (int e = lane; e < n * n; e += 64) ri[e] = 0.0;
+  return r;
+}
+
+// S = P R^-1 (n x n) for the pivoted Cholesky factor of G (see
+// pchol_block): Q = Y S has orthonormal columns spanning the numerical
+// range of Y when G = Y^T Y; columns r.. of S are zero.
+__global__ __launch_bounds__(256) void k_pchol_s(int n, const double* __restrict__ Gg, long long sG, double tau,
+                                                 double* __restrict__ Sg, long long sS, int* __restrict__ rank_out) {
+  extern __shared__ double sm[];
+  double* g = sm;
+  double* L = sm + n * n;
+  double* Z = sm + 2 * n * n;
+  __shared__ int perm[64];
+  __shared__ int bc[2];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* G = Gg + b * sG;
+  for (int e = tid; e < n * n; e += 256) g[e] = G[e];
   __syncthreads();
-  if (lane < r) ri[lane * n + lane] = 1.0;
-  __syncthreads();
-  for (int c = r - 1; c >= 0; --c) {
-    const double rcc = g[c * n + c];
-    if (lane == c)
-      for (int j = c; j < r; ++j) ri[c * n + j] /= rcc;
-    __syncthreads();
-    if (lane < c) {
-      const double f = g[c * n + lane];  // R[lane][c]
-      for (int j = c; j < r; ++j) ri[lane * n + j] -= f * ri[c * n + j];
-    }
-    __syncthreads();
-  }
+  const int r = pchol_block<256>(n, g, L, Z, perm, tau, bc);
   double* S = Sg + b * sS;
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, j = e - (e / n) * n;  // S[perm[i]][j] = Rinv[i][j]
-    S[perm[i] * n + j] = (i < r && j < r) ? ri[i * n + j] : 0.0;
+  const int ri = tid >> 2, rj = tid & 3;  // S[o][k] = z_k[o]
+  if (ri < n)
+    for (int k = rj; k < n; k += 4) S[ri * n + k] = (k < r) ? Z[k * n + ri] : 0.0;
+  if (tid == 0 && rank_out != nullptr) rank_out[b] = r;
+}
+
+// Truncation basis of a PSD Gram matrix G (n x n, n <= 64) in one block:
+// pivoted Cholesky G = L^T L (numerical rank r at tau), then one-sided
+// Jacobi on the r columns of W = L^T until every pair is orthogonal to
+// eps relative; the columns w_j then give the eigenpairs of G as
+// lambda_j = |w_j|^2, v_j = w_j / |w_j|.  Kept: at most c, positive and
+// above floor_rel * lambda_max, and (tol2 > 0) the fewest whose dropped
+// tail (with the mass below the Cholesky threshold) stays within tol2 *
+// trace(G).  S (n x c, row-major) = kept eigenvectors by decreasing
+// eigenvalue, zero columns beyond.  Groups of 8 lanes rotate one column
+// pair each (round-robin ordering, up to 32 pairs per round).
+constexpr int kCutSweeps = 30;
+// Sum over each aligned group of 8 lanes, the same value in all 8 lanes.
+__device__ inline double sum8(double v) {
+  v += dpp_move<kDppSwap1>(v);
+  v += dpp_move<kDppSwap2>(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  return v;
+}
+// 1 / x and 1 / sqrt(x) from the hardware estimates plus one Newton step
+__device__ inline double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ inline double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
+// NT threads = 8 lanes x NT / 8 column pairs (2 NT / 8 >= n); NE = 8 * NE >= n.
+template <int NT, int NE>
+__global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __restrict__ Gg, long long sG,
+                                                 double tau, double eps, double tol2, double floor_rel,
+                                                 double* __restrict__ Sg, long long sS, int* __restrict__ kept_out,
+                                                 int* __restrict__ sweeps_out) {
+  extern __shared__ double sm[];
+  double* g = sm;
+  double* W = sm + n * n;  // column j of W = row j of L
+  __shared__ int perm[64];
+  __shared__ int order[64];
+  __shared__ double lam[64];
+  __shared__ int flags[kCutSweeps];
+  __shared__ int bc[2];
+  __shared__ double trace_s;
+  __shared__ int kept_s;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* G = Gg + b * sG;
+  for (int e = tid; e < n * n; e += NT) g[e] = G[e];
+  if (tid < kCutSweeps) flags[tid] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    double t = (tid < n) ? fmax(g[tid * n + tid], 0.0) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (tid == 0) trace_s = t;
   }
-  if (lane == 0 && rank_out != nullptr) rank_out[b] = r;
+  const int r = pchol_block<NT>(n, g, W, nullptr, perm, tau, bc);
+  // one-sided Jacobi on columns 0..r-1 of W (length n)
+  const int sub = tid & 7, grp = tid >> 3;
+  const int m = r + (r & 1), np = m / 2;
+  const double eps2 = (eps * n) * (eps * n);
+  int sweeps = 0;
+  for (int sweep = 0; sweep < kCutSweeps && r > 1; ++sweep) {
+    sweeps = sweep + 1;
+    for (int step = 0; step < m - 1; ++step) {
+      if (grp < np) {
+        int t0 = 0;
+        if (grp != 0) {
+          const int u = grp - 1 + step;
+          t0 = 1 + (u >= m - 1 ? u - (m - 1) : u);
+        }
+        const int u1 = (m - 1 - grp) - 1 + step;
+        const int t1 = 1 + (u1 >= m - 1 ? u1 - (m - 1) : u1);
+        const int p = t0 < t1 ? t0 : t1, q = t0 < t1 ? t1 : t0;
+        if (q < r) {
+          double wp[NE], wq[NE];
+          double a = 0.0, bb = 0.0, gg = 0.0;
+#pragma unroll
+          for (int t = 0; t < NE; ++t) {
+            const int i = sub + 8 * t;
+            wp[t] = (i < n) ? W[p * n + i] : 0.0;
+            wq[t] = (i < n) ? W[q * n + i] : 0.0;
+            a += wp[t] * wp[t];
+            bb += wq[t] * wq[t];
+            gg += wp[t] * wq[t];
+          }
+          a = sum8(a);
+          bb = sum8(bb);
+          gg = sum8(gg);
+          if (gg * gg > eps2 * a * bb) {
+            // rotation angle in reduced precision is harmless (any angle is
+            // a rotation; only the pair's next inner product depends on
+            // it); c is refined so that c^2 (1 + t^2) = 1 to rounding
+            const double z = (bb - a) * 0.5 * rcp_nr(gg);
+            double t;
+            if (fabs(z) > 1e150) {
+              t = 0.5 * rcp_nr(z);
+            } else {
+              const double w = 1.0 + z * z;
+              const double sq = w * rsq_nr(w);
+              t = (z >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(z) + sq);
+            }
+            const double cs = rsq_nr(1.0 + t * t), sn = t * cs;
+#pragma unroll
+            for (int tt = 0; tt < NE; ++tt) {
+              const int i = sub + 8 * tt;
+              if (i < n) {
+                W[p * n + i] = cs * wp[tt] - sn * wq[tt];
+                W[q * n + i] = sn * wp[tt] + cs * wq[tt];
+              }
+            }
+            if (sub == 0) flags[sweep] = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!flags[sweep]) break;
+  }
+  // eigenvalues, order by decreasing value (ties: lower index first)
+  if (tid < r) {
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) v += W[tid * n + i] * W[tid * n + i];
+    lam[tid] = v;
+  }
+  __syncthreads();
+  if (tid < r) {
+    const double v = lam[tid];
+    int rank = 0;
+    for (int i = 0; i < r; ++i) rank += (lam[i] > v) || (lam[i] == v && i < tid);
+    order[rank] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int j = 0; j < r; ++j) sum += lam[j];
+    int kept = c < r ? c : r;
+    const double l0 = r > 0 ? lam[order[0]] : 0.0;
+    while (kept > 0 && !(lam[order[kept - 1]] > floor_rel * l0 && lam[order[kept - 1]] > 0.0)) --kept;
+    if (tol2 > 0.0) {
+      const double total = trace_s;
+      double tail = fmax(total - sum, 0.0);
+      for (int j = r - 1; j >= kept; --j) tail += lam[order[j]];
+      while (kept > 1) {
+        const double t2 = tail + lam[order[kept - 1]];
+        if (t2 <= tol2 * total) {
+          tail = t2;
+          --kept;
+        } else {
+          break;
+        }
+      }
+    }
+    kept_s = kept;
+    if (kept_out != nullptr) kept_out[b] = kept;
+    if (sweeps_out != nullptr) sweeps_out[b] = sweeps;
+  }
+  __syncthreads();
+  const int kept = kept_s;
+  double* S = Sg + b * sS;
+  for (int e = tid; e < n * c; e += NT) {
+    const int i = e / c, j = e - (e / c) * c;
+    double v = 0.0;
+    if (j < kept) {
+      const int col = order[j];
+      v = W[col * n + i] / sqrt(lam[col]);
+    }
+    S[e] = v;
+  }
 }
 
 }  // namespace
@@ -494,7 +714,7 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     if (ks < 2) ks = 1;
   }
   const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + BK - 1) / BK * BK : (g.k > 0 ? g.k : 1);
-  // (BK == SK, so the chunk suits both tile shapes)
+  // (a multiple of BK is one of SK too)
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
   const bool sm = use_small(g);
   dim3 grid(ceil_div(g.n, sm ? SM : BN), ceil_div(g.m, sm ? SM : BM), g.batch * ks);
@@ -517,7 +737,7 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   LRFG_LAUNCHED();
   if (ks > 1) {
     const long long tot = (long long)g.batch * g.m * g.n;
-    const int gr = (int)std::min<long long>(1024, (tot + 255) / 256);
+    const int gr = (int)((tot + 31) / 32);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, g.m, g.n, ks, g.batch, (const double*)part, g.C,
                        g.ldc, g.sC, g.alpha, g.beta);
     LRFG_LAUNCHED();
@@ -550,13 +770,42 @@ int pchol_s(int n, const double* G, long long sG, double tau, double* S, long lo
     return LRFG_EINVAL;
   }
   if (batch <= 0) return LRFG_OK;
-  const size_t shm = sizeof(double) * 2 * n * n;
+  const size_t shm = sizeof(double) * 3 * n * n;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));
+                                                     (int)(sizeof(double) * 3 * kMaxEig * kMaxEig));
   (void)attr;
   ProfScope ps_("pchol", s);
-  hipLaunchKernelGGL(k_pchol_s, dim3(batch), dim3(64), shm, s, n, G, sG, tau, S, sS, rank);
+  hipLaunchKernelGGL(k_pchol_s, dim3(batch), dim3(256), shm, s, n, G, sG, tau, S, sS, rank);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int cut_psd(int n, int c, const double* G, long long sG, double tol2, double* S, long long sS, int* kept, int batch,
+            hipStream_t s, int* sweeps) {
+  if (n < 1 || n > kMaxEig || c < 1) {
+    set_error("cut: n = %d outside [1, %d] or c = %d < 1", n, kMaxEig, c);
+    return LRFG_EINVAL;
+  }
+  if (batch <= 0) return LRFG_OK;
+  const size_t shm = sizeof(double) * 2 * n * n;
+  ProfScope ps_("cut", s);
+#define LRFG_CUT_LAUNCH(NT, NE)                                                                               \
+  do {                                                                                                       \
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cut_psd<NT, NE>),    \
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,          \
+                                                       (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));       \
+    (void)attr;                                                                                              \
+    hipLaunchKernelGGL((k_cut_psd<NT, NE>), dim3(batch), dim3(NT), shm, s, n, c, G, sG, kCutTau, kCutEps,     \
+                       tol2, kCutFloor, S, sS, kept, sweeps);                                                \
+  } while (0)
+  if (n <= 16)
+    LRFG_CUT_LAUNCH(64, 2);
+  else if (n <= 32)
+    LRFG_CUT_LAUNCH(128, 4);
+  else
+    LRFG_CUT_LAUNCH(256, 8);
+#undef LRFG_CUT_LAUNCH
   LRFG_LAUNCHED();
   return LRFG_OK;
 }

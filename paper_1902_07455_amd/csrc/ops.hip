@@ -107,6 +107,17 @@ int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* st
   return syevj(n, A, n, (long long)n * n, W, n, V, (long long)n * n, batch, static_cast<hipStream_t>(stream));
 }
 
+int lrfg_gram_cut(int n, int c, const double* G, int batch, double tol, double* S, int* kept, int* sweeps,
+                  void* stream) {
+  clear_error();
+  if (G == nullptr || S == nullptr || batch < 0 || !(tol >= 0.0)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  return cut_psd(n, c, G, (long long)n * n, tol * tol, S, (long long)n * c, kept, batch,
+                 static_cast<hipStream_t>(stream), sweeps);
+}
+
 size_t lrfg_tt_round_workspace_bytes(int d, const int N[3], const int rin[4], int cap, int oversample, int nE) {
   Rounder R;
   int c[4];

@@ -43,7 +43,7 @@ struct Rounder {
   uint64_t counter = 0;
   double* om[3] = {};       // sketch cores
   double *W3, *T2, *W2, *Y1, *Q1, *M1, *X2p, *Y2, *Q2, *M2, *X3p;
-  double *G, *lam, *V, *S, *Ytmp, *S3, *Q2s, *P, *U, *S1;
+  double *G, *S, *Ytmp, *S3, *Q2s, *P, *U, *S1;
   double* gscr = nullptr;   // GEMM split-K scratch
   size_t gscr_n = 0;
   int* kept = nullptr;      // kept ranks per bond per system (diagnostics)

@@ -18,9 +18,11 @@
 //      ||dropped||^2 <= tol^2 ||X||^2 / (d - 1).
 // Output ranks are fixed (c1, c2); directions beyond the kept rank are zero
 // columns, so every launch shape is known on the host.
-// orth(Y): Gram Y^T Y, Jacobi eigenvectors V, Q = Y V diag(lambda^-1/2)
-// with directions below 1e-15 lambda_max set to zero, done twice (the second
-// pass restores orthogonality to rounding level).
+// orth(Y): Gram Y^T Y, rank-revealing pivoted Cholesky Y^T Y = R^T R,
+// Q = Y P R^-1 on the numerical rank, done twice (the second pass restores
+// orthogonality to rounding level).  The cut's eigenvectors come from the
+// same pivoted Cholesky followed by one-sided Jacobi on the factor
+// (cut_psd), which needs a handful of sweeps on the graded factor.
 #include <cmath>
 #include <cstdio>
 
@@ -107,60 +109,6 @@ __global__ void k_block_copy(const double* __restrict__ X, long long sx, int r0,
     const int i = (int)(r / N);
     const double c = mult * (coef != nullptr ? coef[e] : 1.0);
     out[e * so + ((long long)(o0 + i) * N + n) * R1 + o1 + j] = c * X[e * sx + ((long long)i * N + n) * r1 + j];
-  }
-}
-
-// S_e = V_e diag(f(lambda_e)), f = lambda^-1/2 above tau lambda_max, else 0.
-__global__ void k_orth_scale(const double* __restrict__ lam, const double* __restrict__ V, int l, double tau,
-                             double* __restrict__ S, int nE) {
-  const long long tot = (long long)nE * l * l;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int e = (int)(idx / ((long long)l * l));
-    const int j = (int)(idx % l);
-    const double lj = lam[(long long)e * l + j];
-    const double l0 = lam[(long long)e * l];
-    const double f = (lj > 0.0 && lj > tau * l0) ? 1.0 / sqrt(lj) : 0.0;
-    S[idx] = V[idx] * f;
-  }
-}
-
-// Kept rank from descending eigenvalues (squared singular values):
-// at most c, no numerically zero direction, smallest rank whose dropped
-// tail is <= tol2 * total.  S_e (l x c) = leading kept columns of V_e.
-__global__ void k_trunc_mask(const double* __restrict__ lam, const double* __restrict__ V, int l, int c,
-                             double tol2, double floor_rel, double* __restrict__ S, int* __restrict__ kept_out,
-                             int nE) {
-  __shared__ int kept_s;
-  const int e = blockIdx.x;
-  const double* L = lam + (long long)e * l;
-  if (threadIdx.x == 0) {
-    double total = 0.0;
-    for (int j = 0; j < l; ++j) total += fmax(L[j], 0.0);
-    int kept = c < l ? c : l;
-    while (kept > 0 && !(L[kept - 1] > floor_rel * L[0] && L[kept - 1] > 0.0)) --kept;
-    if (tol2 > 0.0) {
-      double tail = 0.0;
-      for (int j = l - 1; j >= kept; --j) tail += fmax(L[j], 0.0);
-      // shrink while the dropped tail stays within the budget
-      while (kept > 1) {
-        const double t2 = tail + fmax(L[kept - 1], 0.0);
-        if (t2 <= tol2 * total) {
-          tail = t2;
-          --kept;
-        } else {
-          break;
-        }
-      }
-    }
-    kept_s = kept;
-    if (kept_out != nullptr) kept_out[e] = kept;
-  }
-  __syncthreads();
-  const int kept = kept_s;
-  for (int idx = threadIdx.x; idx < l * c; idx += blockDim.x) {
-    const int i = idx / c, j = idx % c;
-    S[(long long)e * l * c + idx] = (j < kept) ? V[(long long)e * l * l + (long long)i * l + j] : 0.0;
   }
 }
 
@@ -371,8 +319,6 @@ void Rounder::carve(Arena& ar) {
     W3 = T2 = X2p = Y2 = Q2 = M2 = Q2s = U = nullptr;
   }
   G = T((long long)L * L);
-  lam = T(L);
-  V = T((long long)L * L);
   S = T((long long)L * L);
   S3 = T((long long)L * L);
   S1 = T((long long)L * L);
@@ -439,11 +385,8 @@ static int orth(Rounder& R, const double* Y, double* Q, int m, int l, int batch,
 
 static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, double* S, int* kept,
                       int nE, hipStream_t s) {
-  LRFG_TRY(syevj(l, Gm, l, (long long)l * l, R.lam, l, R.V, (long long)l * l, nE, s));
-  hipLaunchKernelGGL(k_trunc_mask, dim3(nE), dim3(64), 0, s, (const double*)R.lam, (const double*)R.V, l, c, tol2,
-                     1e-28, S, kept, nE);
-  LRFG_LAUNCHED();
-  return LRFG_OK;
+  (void)R;
+  return cut_psd(l, c, Gm, (long long)l * l, tol2, S, (long long)l * c, kept, nE, s);
 }
 
 int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch) {

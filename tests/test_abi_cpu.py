@@ -118,6 +118,20 @@ def test_solve_rejects_bad_workspace_before_device():
     lib.lrfg_plan_destroy(plan)
 
 
+def test_gram_cut_validation_before_device():
+    lib = _lib().lib()
+    buf = (C.c_double * 16)()
+    # n out of range, c < 1, negative / NaN tol, null pointers: EINVAL, no device call
+    assert lib.lrfg_gram_cut(65, 4, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(0, 4, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(4, 0, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(4, 2, C.addressof(buf), 1, -1.0, C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(4, 2, C.addressof(buf), 1, float("nan"), C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(4, 2, None, 1, 0.0, C.addressof(buf), None, None, None) == -1
+    # empty batch: nothing to do
+    assert lib.lrfg_gram_cut(4, 2, C.addressof(buf), 0, 0.0, C.addressof(buf), None, None, None) == 0
+
+
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and not os.path.exists("/dev/kfd"),
                     reason="no ROCm device nodes")
 def test_device_check_runs():

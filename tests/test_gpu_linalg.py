@@ -66,3 +66,57 @@ def test_syevj(dev, n, kind):
         # A V = V diag(W), V orthonormal
         assert np.max(np.abs(A[b] @ V[b] - V[b] * W[b][None, :])) <= 1e-12 * scale * n
         assert np.max(np.abs(V[b].T @ V[b] - np.eye(n))) <= 1e-12 * n
+
+
+def _graded_gram(rng, n, rank, decades):
+    Y = rng.standard_normal((3 * n + 8, rank)) * np.logspace(0, -decades, rank)
+    Y = Y @ rng.standard_normal((rank, n))
+    return Y.T @ Y
+
+
+@pytest.mark.parametrize("n,rank,c", [(1, 1, 1), (2, 2, 1), (5, 3, 4), (26, 26, 16), (26, 10, 16),
+                                      (40, 40, 30), (64, 64, 54), (64, 20, 40)])
+@pytest.mark.parametrize("decades", [2, 7])
+def test_gram_cut_subspace(dev, n, rank, c, decades):
+    """Kept eigenvectors of a PSD Gram matrix: orthonormal, eigen-relation,
+    and the captured energy equals the top-c eigenvalue sum (Eckart-Young)."""
+    import torch
+    rng = np.random.default_rng(7 * n + rank + decades)
+    G = np.stack([_graded_gram(rng, n, rank, decades) for _ in range(3)])
+    S, kept, sweeps = P.gram_cut(torch.from_numpy(G).to(dev), c)
+    torch.cuda.synchronize()
+    S, kept, sweeps = S.cpu().numpy(), kept.cpu().numpy(), sweeps.cpu().numpy()
+    for b in range(3):
+        lam = np.sort(np.linalg.eigvalsh(G[b]))[::-1]
+        k = int(kept[b])
+        # exact rank <= c: every direction above the Cholesky threshold is kept
+        assert k <= min(c, n)
+        assert k >= min(c, rank) - (1 if decades > 6 else 0)
+        Sk = S[b][:, :k]
+        assert np.all(S[b][:, k:] == 0.0)
+        assert np.max(np.abs(Sk.T @ Sk - np.eye(k))) <= 1e-13 * max(n, 4)
+        GS = G[b] @ Sk
+        mu = np.sum(Sk * GS, axis=0)
+        assert np.all(np.diff(mu) <= 1e-13 * lam[0])
+        assert np.max(np.abs(GS - Sk * mu[None, :])) <= 1e-12 * lam[0]
+        captured = np.sum(mu)
+        assert captured >= np.sum(lam[:k]) - 1e-13 * n * lam[0]
+        assert sweeps[b] <= 12
+
+
+def test_gram_cut_tolerance_and_zero(dev):
+    import torch
+    rng = np.random.default_rng(3)
+    n = 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = 10.0 ** -np.arange(n, dtype=np.float64)
+    G = (Q * lam) @ Q.T
+    G = np.stack([G, np.zeros((n, n))])
+    tol = 3e-3
+    S, kept, _ = P.gram_cut(torch.from_numpy(G).to(dev), 20, tol=tol)
+    torch.cuda.synchronize()
+    kept = kept.cpu().numpy()
+    tail = np.cumsum(lam[::-1])[::-1]          # tail[k] = sum_{j >= k} lam_j
+    want = int(np.argmax(tail <= tol * tol * np.sum(lam)))
+    assert kept[0] == want
+    assert kept[1] == 0 and float(torch.max(torch.abs(S[1]))) == 0.0
