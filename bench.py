@@ -2,15 +2,29 @@
 
 Workload: 3D cell problem on a 135^3 grid with the smooth coefficient
 a = 1 + 0.5 sum_{j=1..8} c_j prod_i cos(2 pi k_ji x_i + phi_ji) (seed 0; no
-clipping occurs, CP rank 9).  One step = one A_H solve: the d = 3 correctors
-(E = e_1, e_2, e_3) and the 3 x 3 energy matrix, inputs resident in HBM.
+clipping occurs, so the coefficient has CP rank 9).  One step = one A_H
+solve: the d = 3 correctors (E = e_1, e_2, e_3) and the 3 x 3 energy
+matrix, with the inputs resident in HBM.
 
 Equal-accuracy protocol: the reference A_H* is the full-grid FP64 PCG solve
-to 1e-12 (validated against the CPU oracle by the GPU tests); each timed
-path uses the loosest setting whose A_H error max|A - A*| / max|A*| is at
-most 1e-6.
+to 1e-12 (the GPU tests validate this solver against the CPU oracle).  Each
+timed path uses the loosest setting whose A_H error, max|A - A*| / max|A*|,
+is at most 1e-6:
+  * full grid: the PCG tolerance (sweep 1e-1, 3e-2, ...);
+  * tensor train (TT): the smallest rank cap at solver tolerance 1e-8, then
+    the loosest solver tolerance at that cap.
+
+`value` is the low-rank (TT) path, the paper's method.  The full-grid FFT
+solve on the same GPU is reported next to it (`full_fft`, with the roofline
+of its axis-2 FFT pass), together with the crossover at larger grids.
+`roofline` is that of the TT path's dominant kernel, the MFMA FP64 GEMM of
+the truncation; it is measured in a separate pass of --prof-solves solves
+(start/stop events attached to every GEMM dispatch through
+hipExtLaunchKernelGGL, i.e. the dispatch's own timestamps), so the events do
+not perturb the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                    [--crossover 243,405] [--no-crossover]
 """
 from __future__ import annotations
 
@@ -27,8 +41,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 TARGET_ERR = 1e-6
-N = 135
+N_MAIN = 135
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FULL_TOLS = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8]
+TT_CAPS = [4, 6, 8, 10, 12, 16, 20, 24, 32]
+TT_TOLS = [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of kernel `key` from the committed counter runs
+    (profiles/traffic.json), or None once its sources have changed."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            d = json.load(fh)[key]
+        m = hashlib.sha256()
+        for f in d["sources"]:
+            with open(os.path.join(ROOT, "paper_1902_07455_amd", "csrc", f), "rb") as fh:
+                m.update(fh.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return int(d["bytes_per_launch"]) if m.hexdigest()[:16] == d["source_sha"] else None
 
 
 def log(msg):
@@ -39,15 +73,129 @@ def rel_err(A, B):
     return float(np.max(np.abs(A - B)) / np.max(np.abs(B)))
 
 
+class Workload:
+    """The smooth-coefficient cell problem at grid N, inputs on the device."""
+
+    def __init__(self, N, dev):
+        import torch
+
+        import workloads as W
+        self.N = N
+        self.dev = dev
+        self.cp = W.smooth_cp(N, W.smooth_params(0))
+        self.a_np = self.cp.full()
+        # clipping to [0.1, 10] is inactive for seed 0, so the rank-9 form is exact
+        assert self.a_np.min() >= 0.1 and self.a_np.max() <= 10.0
+        self.a = torch.from_numpy(self.a_np).to(dev)
+        self.w = torch.from_numpy(self.cp.weights).to(dev)
+        self.f = [torch.from_numpy(x).to(dev) for x in self.cp.factors]
+        torch.cuda.synchronize()
+
+    def full_solver(self, tol):
+        import paper_1902_07455_amd as P
+        return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=500, device=self.dev)
+
+    def tt_solver(self, cap, tol):
+        import paper_1902_07455_amd as P
+        return P.Solver(d=3, N=(self.N,) * 3, format="tt", rank_cap=cap, trunc_tol=0.0, solver_tol=tol,
+                        max_iter=100, coeff_rank=self.cp.rank, device=self.dev)
+
+    def run_full(self, s):
+        return s.solve(full=self.a)
+
+    def run_tt(self, s):
+        return s.solve(cp=(self.w, self.f))
+
+
+def reference(wl):
+    s = wl.full_solver(1e-12)
+    A = wl.run_full(s).A_H
+    s.close()
+    return A
+
+
+def sweep_full(wl, A_ref, fixed=None):
+    out = []
+    for tol in ([fixed] if fixed else FULL_TOLS):
+        s = wl.full_solver(tol)
+        r = wl.run_full(s)
+        s.close()
+        e = rel_err(r.A_H, A_ref)
+        out.append([tol, e, int(r.iters.max())])
+        if e <= TARGET_ERR:
+            return tol, out
+    return None, out
+
+
+def sweep_tt(wl, A_ref, caps=None, fixed_cap=None, fixed_tol=None):
+    out = []
+    cap_ok = None
+    for cap in ([fixed_cap] if fixed_cap else (caps or TT_CAPS)):
+        s = wl.tt_solver(cap, 1e-8)
+        r = wl.run_tt(s)
+        s.close()
+        e = rel_err(r.A_H, A_ref)
+        out.append(["cap", cap, e, r.iters.tolist()])
+        if e <= TARGET_ERR:
+            cap_ok = cap
+            break
+    if cap_ok is None:
+        return None, None, out
+    for tol in ([fixed_tol] if fixed_tol else TT_TOLS):
+        s = wl.tt_solver(cap_ok, tol)
+        r = wl.run_tt(s)
+        s.close()
+        e = rel_err(r.A_H, A_ref)
+        out.append(["tol", tol, e, r.iters.tolist()])
+        if e <= TARGET_ERR:
+            return cap_ok, tol, out
+    return cap_ok, None, out
+
+
+def timed(run, steps, warmup):
+    """Run warmup + steps solves; each solve returns after its stream is
+    synchronised.  Returns (seconds for the steps, per-solve ms, last result)."""
+    import torch
+    r = None
+    for _ in range(warmup):
+        r = run()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        r = run()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, r
+
+
+def pct(lat, q):
+    return round(float(np.percentile(lat, q)), 3)
+
+
+def profiled(run, tag, solves):
+    """Launch count, summed ms and summed work of kernel `tag` over `solves`."""
+    import paper_1902_07455_amd as P
+    P.prof_enable(tag)
+    for _ in range(solves):
+        run()
+    n, ms = P.prof_read()
+    work = P.prof_work()
+    P.prof_enable(None)
+    return n, ms, work
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50, help="timed TT solves")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--full-steps", type=int, default=200, help="timed full-grid solves")
+    ap.add_argument("--prof-solves", type=int, default=5, help="solves in each kernel-timing pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-budget-s", type=float, default=30.0)
-    ap.add_argument("--tt-steps", type=int, default=10)
-    ap.add_argument("--no-tt", action="store_true", help="skip the tensor-train leg")
+    ap.add_argument("--crossover", default="243,405", help="grid sizes of the crossover table")
+    ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-cap", type=int, default=None, help="TT rank cap (skips the cap sweep)")
@@ -62,9 +210,6 @@ def main(argv=None):
 
     import torch
 
-    import paper_1902_07455_amd as P
-    import workloads as W
-
     dev = "cuda:0"
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -74,71 +219,52 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
-    p = W.smooth_params(0)
-    cp = W.smooth_cp(N, p)
-    a_np = cp.full()
-    assert a_np.min() >= 0.1 and a_np.max() <= 10.0  # clipping inactive: rank 9 exact
-    a_dev = torch.from_numpy(a_np).to(dev)
-    torch.cuda.synchronize()
 
-    # ---------------------------------------------------------------- reference
+    wl = Workload(N_MAIN, dev)
     log("reference A_H* (full grid, PCG to 1e-12)")
-    ref = P.Solver(d=3, N=(N, N, N), format="full", solver_tol=1e-12, max_iter=500, device=dev)
-    A_ref = ref.solve(full=a_dev).A_H
-    ref.close()
+    A_ref = reference(wl)
 
-    # ---------------------------------------------------------------- full-grid tolerance sweep
-    full_tol = None
-    sweep = []
-    full_tols = [args.full_tol] if args.full_tol else [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5,
-                                                        1e-5, 1e-6, 1e-7, 1e-8]
-    for tol in full_tols:
-        s = P.Solver(d=3, N=(N, N, N), format="full", solver_tol=tol, max_iter=500, device=dev)
-        r = s.solve(full=a_dev)
-        e = rel_err(r.A_H, A_ref)
-        sweep.append((tol, e, int(r.iters.max())))
-        s.close()
-        if e <= TARGET_ERR:
-            full_tol = tol
-            break
-    log(f"full-grid sweep (tol, err, iters): {sweep}")
-    assert full_tol is not None
+    # ------------------------------------------------------------ full grid
+    full_tol, fsweep = sweep_full(wl, A_ref, args.full_tol)
+    log(f"full-grid sweep (tol, err, iters): {fsweep}")
+    assert full_tol is not None, "no full-grid tolerance reaches the target"
+    fs = wl.full_solver(full_tol)
+    ftot, flat, fr = timed(lambda: wl.run_full(fs), args.full_steps, args.warmup)
+    ferr = rel_err(fr.A_H, A_ref)
+    nl, kms, fbytes = profiled(lambda: wl.run_full(fs), "fft_axis2", args.prof_solves)
+    fs.close()
+    favg = (kms / 1e3) / max(nl, 1)
+    fach = fbytes / max(nl, 1) / favg / 1e9
+    full = {"solves_per_s": round(args.full_steps / ftot, 3),
+            "ms_per_solve": round(1e3 * ftot / args.full_steps, 3), "steps": args.full_steps,
+            "solver_tol": full_tol, "iters": int(fr.iters.max()), "A_H_rel_err": ferr,
+            "latency_ms": {"p50": pct(flat, 50), "p99": pct(flat, 99)}, "sweep": fsweep,
+            "roofline": {"bound": "hbm",
+                         "kernel": "k_fft_lines (axis-2 pass of the full-grid PCG matvec, 'fft_axis2')",
+                         "achieved": round(fach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(fach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("fft_axis2"),
+                         "launches": nl, "avg_us": round(favg * 1e6, 2),
+                         "bytes_per_launch": round(fbytes / max(nl, 1))}}
 
-    solver = P.Solver(d=3, N=(N, N, N), format="full", solver_tol=full_tol, max_iter=500, device=dev)
-    for _ in range(args.warmup):
-        r = solver.solve(full=a_dev)
-    torch.cuda.synchronize()
-
-    # ---------------------------------------------------------------- timed region
-    P.prof_enable("fft_axis2")
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        r = solver.solve(full=a_dev)    # returns after the stream is synchronised
-        lat.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nlaunch, kms = P.prof_read()
-    P.prof_enable(None)
-    err = rel_err(r.A_H, A_ref)
-    total = t1 - t0
-    value = args.steps / total
-    iters = int(r.iters.max())
-
-    # dominant kernel: axis-2 FFT pass of the matvec, all 3 correctors x 3
-    # gradient components per launch; algorithmic bytes = read + write of
-    # 9 half spectra of N*N*(N+1)/2 complex FP64 values.
-    S = N * N * ((N + 1) // 2)
-    bytes_per_launch = 2 * 9 * S * 16
-    avg_s = (kms / 1e3) / max(nlaunch, 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": "fft_axis2 (k_fft_lines, axis-2 pass of the PCG matvec)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "launches": nlaunch, "avg_us": round(avg_s * 1e6, 2),
-                "bytes_per_launch": bytes_per_launch}
+    # ------------------------------------------------------------ tensor train
+    cap, ttol, tsweep = sweep_tt(wl, A_ref, fixed_cap=args.tt_cap, fixed_tol=args.tt_tol)
+    log(f"TT sweep: {tsweep}")
+    assert ttol is not None, "no TT setting reaches the target"
+    ts = wl.tt_solver(cap, ttol)
+    ttot, tlat, tr = timed(lambda: wl.run_tt(ts), args.steps, args.warmup)
+    terr = rel_err(tr.A_H, A_ref)
+    nl, kms, flops = profiled(lambda: wl.run_tt(ts), "gemm", args.prof_solves)
+    ts.close()
+    gavg = (kms / 1e3) / max(nl, 1)
+    gach = flops / (kms / 1e3) / 1e12
+    value = args.steps / ttot
+    roofline = {"bound": "mfma",
+                "kernel": "k_gemm (FP64 MFMA 16x16x4 GEMM of the TT truncation, all transpose variants)",
+                "achieved": round(gach, 4), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(gach / FP64_MFMA_PEAK_TFLOPS, 5), "traffic": measured_traffic("gemm"),
+                "launches": nl, "avg_us": round(gavg * 1e6, 2),
+                "flops_per_launch": round(flops / max(nl, 1)),
+                "share_of_solve": round(kms / args.prof_solves / (1e3 * ttot / args.steps), 3)}
 
     out = {
         "metric": "A_H solves/sec at 1e-6 rel. err (TT vs full-FFT, same GPU); p50/p99 latency",
@@ -147,90 +273,66 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * total / args.steps, 3),
+        "ms_per_step": round(1e3 * ttot / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D cell problem, N=135^3, smooth coefficient (8 cosine products, "
-                               "seed 0, CP rank 9), E=e1,e2,e3, A_H to 1e-6 relative error",
-                   "path": "full-grid FFT PCG", "solver_tol": full_tol, "iters": iters,
-                   "A_H_rel_err": err},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3)},
-        "full_fft": {"solves_per_s": round(value, 3), "solver_tol": full_tol, "iters": iters,
-                     "A_H_rel_err": err, "sweep": sweep},
+        "config": {"workload": f"3D cell problem, N={N_MAIN}^3, smooth coefficient (8 cosine products, seed 0, "
+                               "CP rank 9), E=e1,e2,e3, A_H to 1e-6 relative error vs the 1e-12 full-grid "
+                               "reference",
+                   "path": "tensor-train PCG (randomised TT rounding)", "rank_cap": cap,
+                   "solver_tol": ttol, "iters": tr.iters.tolist(), "ranks": tr.ranks.tolist(),
+                   "A_H_rel_err": terr},
+        "latency_ms": {"p50": pct(tlat, 50), "p99": pct(tlat, 99)},
+        "tt_sweep": tsweep,
+        "full_fft": full,
+        "tt_over_full": round(value / full["solves_per_s"], 4),
         "roofline": roofline,
     }
 
-    # ---------------------------------------------------------------- TT leg
-    if not args.no_tt:
-        w_dev = torch.from_numpy(cp.weights).to(dev)
-        f_dev = [torch.from_numpy(f).to(dev) for f in cp.factors]
-
-        def tt_solver(cap, tol):
-            return P.Solver(d=3, N=(N, N, N), format="tt", rank_cap=cap, trunc_tol=0.0,
-                            solver_tol=tol, max_iter=100, coeff_rank=cp.rank, device=dev)
-
-        tt_sweep = []
-        tt_cap = None
-        for cap in ([args.tt_cap] if args.tt_cap else [4, 6, 8, 10, 12, 16, 20]):
-            s = tt_solver(cap, 1e-8)
-            r = s.solve(cp=(w_dev, f_dev))
-            e = rel_err(r.A_H, A_ref)
-            tt_sweep.append(("cap", cap, e, r.iters.tolist()))
+    # ------------------------------------------------------------ crossover
+    if not args.no_crossover and args.crossover:
+        rows = []
+        for Nx in [int(v) for v in args.crossover.split(",") if v.strip()]:
+            log(f"crossover N={Nx}")
+            w2 = Workload(Nx, dev)
+            Ar = reference(w2)
+            ft, fsw = sweep_full(w2, Ar)
+            s = w2.full_solver(ft)
+            fsec, _, r1 = timed(lambda: w2.run_full(s), 5, 1)
             s.close()
-            if e <= TARGET_ERR:
-                tt_cap = cap
-                break
-        tt_tol = None
-        if tt_cap is not None:
-            for tol in ([args.tt_tol] if args.tt_tol else [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]):
-                s = tt_solver(tt_cap, tol)
-                r = s.solve(cp=(w_dev, f_dev))
-                e = rel_err(r.A_H, A_ref)
-                tt_sweep.append(("tol", tol, e, r.iters.tolist()))
+            c2, t2, tsw = sweep_tt(w2, Ar, caps=[c for c in TT_CAPS if c >= 12])
+            row = {"N": Nx, "full_ms": round(1e3 * fsec / 5, 3), "full_tol": ft,
+                   "full_err": rel_err(r1.A_H, Ar), "full_iters": int(r1.iters.max())}
+            if t2 is not None:
+                s = w2.tt_solver(c2, t2)
+                tsec, _, r2 = timed(lambda: w2.run_tt(s), 5, 1)
                 s.close()
-                if e <= TARGET_ERR:
-                    tt_tol = tol
-                    break
-        log(f"TT sweep: {tt_sweep}")
-        if tt_tol is not None:
-            tts = tt_solver(tt_cap, tt_tol)
-            r = tts.solve(cp=(w_dev, f_dev))
-            torch.cuda.synchronize()
-            tlat = []
-            t0 = time.perf_counter()
-            for _ in range(args.tt_steps):
-                ts = time.perf_counter()
-                r = tts.solve(cp=(w_dev, f_dev))
-                tlat.append((time.perf_counter() - ts) * 1e3)
-            torch.cuda.synchronize()
-            ttot = time.perf_counter() - t0
-            terr = rel_err(r.A_H, A_ref)
-            out["tt"] = {"solves_per_s": round(args.tt_steps / ttot, 3), "rank_cap": tt_cap,
-                         "solver_tol": tt_tol, "iters": r.iters.tolist(), "ranks": r.ranks.tolist(),
-                         "A_H_rel_err": terr, "ms_per_solve": round(1e3 * ttot / args.tt_steps, 3),
-                         "latency_ms": {"p50": round(float(np.percentile(tlat, 50)), 3),
-                                        "p99": round(float(np.percentile(tlat, 99)), 3)},
-                         "sweep": tt_sweep}
-        else:
-            out["tt"] = {"solves_per_s": None, "sweep": tt_sweep}
+                row.update({"tt_ms": round(1e3 * tsec / 5, 3), "tt_cap": c2, "tt_tol": t2,
+                            "tt_err": rel_err(r2.A_H, Ar), "tt_iters": r2.iters.tolist(),
+                            "tt_speedup": round(row["full_ms"] / (1e3 * tsec / 5), 3)})
+            else:
+                row["tt_sweep"] = tsw
+            rows.append(row)
+            del w2
+            torch.cuda.empty_cache()
+        out["crossover"] = rows
 
-    # ---------------------------------------------------------------- CPU oracle baseline
+    # ------------------------------------------------------------ CPU oracle baseline
     if not args.no_cpu:
         from oracle import fg
         log("CPU oracle baseline")
         t = time.perf_counter()
-        o = fg.solve(a_np, [[1.0, 0.0, 0.0]], tol=full_tol, max_iter=500)
+        o = fg.solve(wl.a_np, [[1.0, 0.0, 0.0]], tol=full_tol, max_iter=500)
         one = time.perf_counter() - t
         out["cpu_baseline"] = {
             "value": round(1.0 / (3.0 * one), 5), "unit": "A_H solves/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"oracle.fg full-grid PCG, one corrector (E=e1) of the 135^3 workload at "
-                      f"tol {full_tol} ({o.iters[0]} iterations, {one:.1f} s), scaled x3 to one "
-                      "A_H solve; numpy FFT single-threaded"}
+            "sample": f"oracle.fg full-grid PCG (the exact discrete solution the oracle computes), one "
+                      f"corrector (E=e1) of the {N_MAIN}^3 workload at tol {full_tol} ({o.iters[0]} "
+                      f"iterations, {one:.1f} s), scaled x3 to one A_H solve; numpy FFT single-threaded"}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -251,15 +251,21 @@ int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cor
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  lrfg_prof_enable(name) makes every
  * later launch of the kernel `name` (one of "fft_lines", "fft_axis2",
- * "mode_op", "grad_axis1", "axis3", "div_axis1", "cg_update1",
- * "cg_update2"; "fft_axis2" is the axis-2 pass of the full-grid PCG
- * matvec) bracketed by HIP events
- * on the stream it runs on; NULL disables and clears.  lrfg_prof_read
- * synchronises those events and returns the number of timed launches and
- * their summed duration in milliseconds.  Process-wide state.
+ * "mode_op", "mode_op_blocks", "grad_axis1", "axis3", "div_axis1",
+ * "cg_update1", "cg_update2", "gemm", "syevj", "pchol", "cut",
+ * "khatri_rao", "tt_round"; "fft_axis2" is the axis-2 pass of the
+ * full-grid PCG matvec, "gemm" the MFMA GEMM kernel without its split-K
+ * reduction) bracketed by HIP events on the stream it runs on; NULL
+ * disables and clears.  lrfg_prof_read synchronises those events and
+ * returns the number of timed launches and their summed duration in
+ * milliseconds; lrfg_prof_work returns the summed algorithmic work of those
+ * launches: FLOPs (2 m n k per GEMM) for "gemm", bytes read plus written
+ * (16 bytes per complex value, every line once each way) for the FFT line
+ * passes, 0 for the others.  Process-wide state.
  * ---------------------------------------------------------------------- */
 int lrfg_prof_enable(const char* kernel);
 int lrfg_prof_read(int* count, double* total_ms);
+int lrfg_prof_work(double* total_work);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read"]
+           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
             "tt": _lib.FORMAT_TT}
@@ -206,6 +206,13 @@ def prof_read():
     ms = C.c_double()
     check(lib().lrfg_prof_read(C.byref(n), C.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def prof_work() -> float:
+    """Summed algorithmic work (FLOPs or bytes) of the timed launches."""
+    w = C.c_double()
+    check(lib().lrfg_prof_work(C.byref(w)))
+    return float(w.value)
 
 
 # ---------------------------------------------------------------- op level

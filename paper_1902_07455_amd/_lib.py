@@ -76,7 +76,7 @@ EXPORTS = [
     "lrfg_abi_version", "lrfg_status_string", "lrfg_last_error", "lrfg_device_check",
     "lrfg_plan_create", "lrfg_plan_workspace_bytes", "lrfg_solve", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
-    "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read",
+    "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
     "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_gram_cut", "lrfg_tt_round_workspace_bytes",
     "lrfg_tt_round",
 ]
@@ -142,6 +142,8 @@ def lib():
     L.lrfg_prof_enable.restype = C.c_int
     L.lrfg_prof_read.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.lrfg_prof_read.restype = C.c_int
+    L.lrfg_prof_work.argtypes = [C.POINTER(C.c_double)]
+    L.lrfg_prof_work.restype = C.c_int
     _LIB = L
     return L
 

@@ -321,11 +321,11 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
   const int T = lines_per_tile1(N);
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(nlines, T);
-  ProfScope ps_(tag, s);
+  const double bytes = 2.0 * 16.0 * (double)nlines * N;  // nominal: every line read and written once
   const bool gen = plan_generic(f);
-#define LRFG_FL(D, G) \
-  hipLaunchKernelGGL((k_fft_lines<D, G>), dim3(grid), dim3(kFftBlock), shm, s, x, nlines, (int)inner, T, f, scale, \
-                     done, lines_per_flag)
+#define LRFG_FL(D, G)                                                                                      \
+  LRFG_LAUNCH_TIMED(tag, bytes, (k_fft_lines<D, G>), dim3(grid), dim3(kFftBlock), shm, s, x, nlines, (int)inner, \
+                    T, f, scale, done, lines_per_flag)
   if (dir < 0) {
     if (gen) LRFG_FL(-1, true); else LRFG_FL(-1, false);
   } else {

@@ -585,6 +585,10 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   const int sub = tid & 7, grp = tid >> 3;
   const int m = r + (r & 1), np = m / 2;
   const double eps2 = (eps * n) * (eps * n);
+  // a sweep whose rotations all had |cos angle between the columns| below
+  // sqrt(eps n) leaves pairs at O(eps n) (quadratic convergence): stop there
+  // instead of spending a further sweep to observe it
+  const double big2 = eps * n;
   int sweeps = 0;
   for (int sweep = 0; sweep < kCutSweeps && r > 1; ++sweep) {
     sweeps = sweep + 1;
@@ -635,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
                 W[q * n + i] = sn * wp[tt] + cs * wq[tt];
               }
             }
-            if (sub == 0) flags[sweep] = 1;
+            if (sub == 0 && gg * gg > big2 * a * bb) flags[sweep] = 1;
           }
         }
       }
@@ -719,15 +723,15 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   const bool sm = use_small(g);
   dim3 grid(ceil_div(g.n, sm ? SM : BN), ceil_div(g.m, sm ? SM : BM), g.batch * ks);
   double* part = ks > 1 ? scratch : nullptr;
-  ProfScope ps_("gemm", s);
 #define LRFG_GEMM_LAUNCH(TA, TB)                                                                              \
   do {                                                                                                       \
     if (sm)                                                                                                  \
       hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, g.m, g.n, g.k, g.A, g.lda, g.sA, g.B, g.ldb, \
                          g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, ks, kchunk, part);                            \
     else                                                                                                     \
-      hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, g.m, g.n, g.k, g.A, g.lda, g.sA, g.B, g.ldb,  \
-                         g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, ks, kchunk, part);                            \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * g.m * g.n * (double)g.k * g.batch, (k_gemm<TA, TB>), grid, dim3(256), 0, \
+                        s, g.m, g.n, g.k, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, \
+                        ks, kchunk, part);                                                                   \
   } while (0)
   if (!g.ta && !g.tb) LRFG_GEMM_LAUNCH(false, false);
   else if (g.ta && !g.tb) LRFG_GEMM_LAUNCH(true, false);

@@ -15,9 +15,11 @@ std::string g_target;
 std::vector<hipEvent_t> g_pool;          // recorded pairs: start, end, start, end, ...
 size_t g_used = 0;
 bool g_open = false;
+double g_work = 0.0;
 }  // namespace
 
 bool prof_active(const char* name) {
+  if (name == nullptr) return false;
   std::lock_guard<std::mutex> lk(g_mu);
   return !g_target.empty() && g_target == name;
 }
@@ -40,12 +42,28 @@ void prof_begin(const char*, hipStream_t s) {
   }
 }
 
-void prof_end(const char*, hipStream_t s) {
+void prof_end(const char*, hipStream_t s, double work) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_open) return;
   hipEvent_t e = next_event();
-  if (e) (void)hipEventRecord(e, s);
+  if (e) {
+    (void)hipEventRecord(e, s);
+    g_work += work;
+  }
   g_open = false;
+}
+
+bool prof_events(const char* name, hipEvent_t* start, hipEvent_t* stop, double work) {
+  if (name == nullptr) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_target.empty() || g_target != name) return false;
+  hipEvent_t a = next_event();
+  hipEvent_t b = a ? next_event() : nullptr;
+  if (!a || !b) return false;
+  *start = a;
+  *stop = b;
+  g_work += work;
+  return true;
 }
 
 }  // namespace lrfg
@@ -58,6 +76,14 @@ int lrfg_prof_enable(const char* kernel) {
   g_target = kernel ? kernel : "";
   g_used = 0;
   g_open = false;
+  g_work = 0.0;
+  return LRFG_OK;
+}
+
+int lrfg_prof_work(double* total_work) {
+  using namespace lrfg;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (total_work) *total_work = g_work;
   return LRFG_OK;
 }
 
