@@ -160,6 +160,20 @@ int lrfg_plan_workspace_bytes(const lrfg_plan* plan, int max_nE, size_t* bytes);
 int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE,
                void* d_ws, size_t ws_bytes, void* stream, lrfg_result* out);
 
+/* Batched solve: `count` microstructures a[0..count-1] of the same problem
+ * (and, for the low-rank formats, the same coefficient ranks), each with
+ * the nE fields E, one result each in results[0..count-1].  The low-rank
+ * formats run all count*nE correctors as one batch through every kernel
+ * (count*nE <= 256; workspace lrfg_plan_workspace_bytes(plan, count*nE));
+ * the full grid runs the microstructures one after another in the
+ * workspace of one (lrfg_plan_workspace_bytes(plan, nE)).  Each result
+ * equals that of lrfg_solve on the same microstructure up to rounding
+ * (the batched kernels split their sums differently).  Errors as
+ * lrfg_solve; LRFG_EINVAL also for count < 1 or unequal coefficient
+ * ranks. */
+int lrfg_solve_batch(lrfg_plan* plan, const lrfg_coeff* a, int count, const double* E, int nE,
+                     void* d_ws, size_t ws_bytes, void* stream, lrfg_result* results);
+
 void lrfg_plan_destroy(lrfg_plan* plan);
 
 /* ------------------------------------------------------------------------
@@ -247,6 +261,56 @@ size_t lrfg_tt_round_workspace_bytes(int d, const int N[3], const int rin[4], in
 int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cores, int cap,
                   double tol, int oversample, uint64_t seed, double* const* out_cores,
                   int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching on one device.
+ * `slots` worker threads (each with its own HIP stream at the default
+ * priority) admit queued requests while the caller's device pool
+ * (d_pool, pool_bytes, 256-byte aligned, owned by the caller and untouched
+ * outside the requests' workspaces) has room for their workspace: the
+ * oldest request that fits is taken with the other queued requests of the
+ * same problem, fields and coefficient ranks, up to max_batch of them, and
+ * solved as one lrfg_solve_batch.  Requests arriving while others run join
+ * the next batch a worker forms; batches on different streams overlap on
+ * the device.  Results equal those of lrfg_solve up to rounding.
+ * ---------------------------------------------------------------------- */
+typedef struct lrfg_server lrfg_server;
+
+typedef struct {
+  uint64_t tag;           /* the submit call's tag                          */
+  int status;             /* lrfg_status of the request                     */
+  int batch_size;         /* microstructures solved in the same batch       */
+  double queue_ms;        /* submit to start of its batch (host clock)      */
+  double run_ms;          /* its batch's solve time                         */
+  double total_ms;        /* submit to completion                           */
+  size_t workspace_bytes; /* pool bytes its batch held                      */
+} lrfg_completion;
+
+/* Start the loop on `device`; slots in [1, 16], max_batch >= 1.  Returns
+ * LRFG_EINVAL for bad arguments, LRFG_EDEVICE for a missing device. */
+int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_t pool_bytes,
+                       lrfg_server** out);
+
+/* Queue one request: problem p (copied), coefficient a and the arrays it
+ * points to (read in place when its batch runs: keep them valid and
+ * unchanged until the completion is polled), fields E (nE x d, copied;
+ * NULL = canonical basis with nE = d), result `out` (the struct and its
+ * arrays are written by the worker; read them after the completion).
+ * Returns the plan-validation codes of lrfg_plan_create, LRFG_EWORKSPACE
+ * when the request's workspace exceeds the whole pool. */
+int lrfg_server_submit(lrfg_server* s, const lrfg_problem* p, const lrfg_coeff* a, const double* E,
+                       int nE, lrfg_result* out, uint64_t tag);
+
+/* Move up to `max` completions into done[0..*n-1]; waits up to timeout_ms
+ * for the first (0: no wait, < 0: until one arrives). */
+int lrfg_server_poll(lrfg_server* s, lrfg_completion* done, int max, int* n, int timeout_ms);
+
+/* Requests queued or running. */
+int lrfg_server_pending(lrfg_server* s);
+
+/* Finish every queued and running request, then stop the workers (the
+ * completions not yet polled are dropped). */
+void lrfg_server_destroy(lrfg_server* s);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  lrfg_prof_enable(name) makes every

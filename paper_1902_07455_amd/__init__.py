@@ -21,7 +21,8 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work"]
+           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
+           "Completion"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
             "tt": _lib.FORMAT_TT}
@@ -85,6 +86,66 @@ class SolveResult:
     solve_ms: float
 
 
+def _fill_coeff(c, h, full=None, cp=None, tt=None):
+    """Fill an lrfg_coeff from numpy arrays or torch tensors (kept alive by h)."""
+    on_dev = 0
+    if full is not None:
+        ptr, on_dev = h.ptr(full)
+        c.full = ptr
+    elif cp is not None:
+        w, fac = cp
+        ptr, on_dev = h.ptr(w)
+        c.weights = ptr
+        c.rank = int(len(w))
+        for i, f in enumerate(fac):
+            c.factors[i] = h.ptr(f)[0]
+    elif tt is not None:
+        for i, G in enumerate(tt):
+            c.tt_cores[i], on_dev = h.ptr(G)
+            c.tt_ranks[i] = int(G.shape[0])
+        c.tt_ranks[len(tt)] = int(tt[-1].shape[2])
+    else:
+        raise ValueError("give one of full / cp / tt")
+    c.on_device = on_dev
+
+
+def _result_buffers(r, nE, d, max_iter):
+    """Host arrays behind one lrfg_result."""
+    A = np.zeros((nE, nE))
+    iters = np.zeros(nE, dtype=np.int32)
+    hist = np.zeros((nE, max_iter))
+    ranks = np.zeros((nE, d + 1), dtype=np.int32)
+    status = np.zeros(nE, dtype=np.int32)
+    r.A_H = A.ctypes.data
+    r.iters = iters.ctypes.data
+    r.res_hist = hist.ctypes.data
+    r.ranks = ranks.ctypes.data
+    r.status = status.ctypes.data
+    return A, iters, hist, ranks, status
+
+
+def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-10, max_iter=1000,
+                  solver="pcg", precision="fp64", precond_terms=0, oversample=0, seed=0, coeff_rank=0):
+    p = _lib.Problem()
+    p.d = int(d)
+    Ns = list(N) + [1] * (3 - len(N))
+    for i in range(3):
+        p.N[i] = int(Ns[i])
+    p.format = _FORMATS[format]
+    p.rank_cap = int(rank_cap)
+    p.trunc_tol = float(trunc_tol)
+    p.solver_tol = float(solver_tol)
+    p.max_iter = int(max_iter)
+    p.solver = _SOLVERS[solver]
+    p.precision = _PRECS[precision]
+    p.precond_terms = int(precond_terms)
+    p.oversample = int(oversample)
+    p.seed = int(seed)
+    p.coeff_rank = int(coeff_rank)
+    p.flags = 0
+    return p
+
+
 class Solver:
     """A plan plus its device workspace, reusable across solves."""
 
@@ -94,23 +155,8 @@ class Solver:
                  oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
                  coeff_rank: int = 0, device: str = "cuda:0"):
         L = lib()
-        p = _lib.Problem()
-        p.d = int(d)
-        Ns = list(N) + [1] * (3 - len(N))
-        for i in range(3):
-            p.N[i] = int(Ns[i])
-        p.format = _FORMATS[format]
-        p.rank_cap = int(rank_cap)
-        p.trunc_tol = float(trunc_tol)
-        p.solver_tol = float(solver_tol)
-        p.max_iter = int(max_iter)
-        p.solver = _SOLVERS[solver]
-        p.precision = _PRECS[precision]
-        p.precond_terms = int(precond_terms)
-        p.oversample = int(oversample)
-        p.seed = int(seed)
-        p.coeff_rank = int(coeff_rank)
-        p.flags = 0
+        p = _make_problem(d, N, format, rank_cap, trunc_tol, solver_tol, max_iter, solver, precision,
+                          precond_terms, oversample, seed, coeff_rank)
         self.problem = p
         self.d = int(d)
         self.max_iter = int(max_iter)
@@ -132,29 +178,19 @@ class Solver:
     def solve(self, full=None, cp=None, tt=None, E=None, stream=None) -> SolveResult:
         """full: nodal values; cp: (weights (R,), [factors (R, N_i)]);
         tt: list of cores [r_{i-1}][N_i][r_i].  E: (nE, d) or None."""
+        return self.solve_batch([dict(full=full, cp=cp, tt=tt)], E=E, stream=stream)[0]
+
+    def solve_batch(self, coeffs, E=None, stream=None):
+        """Several microstructures of this problem in one batched solve
+        (lrfg_solve_batch): coeffs is a list of dicts with one of the keys
+        full / cp / tt (as in solve).  Needs max_nE >= len(coeffs) * nE.
+        Returns one SolveResult per microstructure."""
         L = lib()
         torch = _torch()
         h = _Held(self.device)
-        c = _lib.Coeff()
-        on_dev = 0
-        if full is not None:
-            ptr, on_dev = h.ptr(full)
-            c.full = ptr
-        elif cp is not None:
-            w, fac = cp
-            ptr, on_dev = h.ptr(w)
-            c.weights = ptr
-            c.rank = int(len(w))
-            for i, f in enumerate(fac):
-                c.factors[i] = h.ptr(f)[0]
-        elif tt is not None:
-            for i, G in enumerate(tt):
-                c.tt_cores[i], on_dev = h.ptr(G)
-                c.tt_ranks[i] = int(G.shape[0])
-            c.tt_ranks[len(tt)] = int(tt[-1].shape[2])
-        else:
-            raise ValueError("give one of full / cp / tt")
-        c.on_device = on_dev
+        cs = (_lib.Coeff * len(coeffs))()
+        for k, kw in enumerate(coeffs):
+            _fill_coeff(cs[k], h, kw.get("full"), kw.get("cp"), kw.get("tt"))
         d = self.d
         if E is None:
             nE = d
@@ -164,29 +200,114 @@ class Solver:
             nE = Earr.shape[0]
             h.keep.append(Earr)
             Eptr = Earr.ctypes.data
-        A = np.zeros((nE, nE))
-        iters = np.zeros(nE, dtype=np.int32)
-        hist = np.zeros((nE, self.max_iter))
-        ranks = np.zeros((nE, d + 1), dtype=np.int32)
-        status = np.zeros(nE, dtype=np.int32)
-        r = _lib.Result()
-        r.A_H = A.ctypes.data
-        r.iters = iters.ctypes.data
-        r.res_hist = hist.ctypes.data
-        r.ranks = ranks.ctypes.data
-        r.status = status.ctypes.data
+        rs = (_lib.Result * len(coeffs))()
+        bufs = [_result_buffers(rs[k], nE, d, self.max_iter) for k in range(len(coeffs))]
         ws = self.workspace()
         with torch.cuda.device(torch.device(self.device)):
             sh = _stream_handle(stream)
-            rc = L.lrfg_solve(self._plan, C.byref(c), Eptr, nE, C.c_void_p(ws.data_ptr()),
-                              self.workspace_bytes, C.c_void_p(sh), C.byref(r))
+            rc = L.lrfg_solve_batch(self._plan, cs, len(coeffs), Eptr, nE, C.c_void_p(ws.data_ptr()),
+                                    self.workspace_bytes, C.c_void_p(sh), rs)
         check(rc, allow=(_lib.OK, _lib.NOT_CONVERGED))
-        return SolveResult(A, iters, hist, ranks, status, rc, r.setup_ms, r.solve_ms)
+        out = []
+        for k, (A, iters, hist, ranks, status) in enumerate(bufs):
+            rck = _lib.OK if np.all(status == 0) else _lib.NOT_CONVERGED
+            out.append(SolveResult(A, iters, hist, ranks, status, rck, rs[k].setup_ms, rs[k].solve_ms))
+        return out
 
     def close(self):
         if self._plan:
             lib().lrfg_plan_destroy(self._plan)
             self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class Completion:
+    tag: int
+    status: int
+    batch_size: int
+    queue_ms: float
+    run_ms: float
+    total_ms: float
+    workspace_bytes: int
+    result: SolveResult
+
+
+class Server:
+    """Continuous-batching request loop (lrfg_server_*): `slots` worker
+    threads with their own HIP streams admit queued requests by workspace
+    footprint in a device pool of pool_bytes, batching queued requests of the
+    same problem (up to max_batch microstructures per solve)."""
+
+    def __init__(self, slots: int = 2, max_batch: int = 8, pool_bytes: int = 8 << 30, device: str = "cuda:0"):
+        torch = _torch()
+        dev = torch.device(device)
+        self.device = device
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=dev)
+        self._h = C.c_void_p()
+        check(lib().lrfg_server_create(dev.index or 0, int(slots), int(max_batch), C.c_void_p(self.pool.data_ptr()),
+                                       int(pool_bytes), C.byref(self._h)))
+        self._pending = {}
+        self._next = 0
+
+    def submit(self, problem: dict, full=None, cp=None, tt=None, E=None, tag: Optional[int] = None) -> int:
+        """Queue one request; problem holds Solver's keyword arguments
+        (d, N, format, rank_cap, ...).  Returns its tag."""
+        h = _Held(self.device)
+        pr = _make_problem(**problem)
+        c = _lib.Coeff()
+        _fill_coeff(c, h, full, cp, tt)
+        d = pr.d
+        if E is None:
+            nE, Eptr = d, None
+        else:
+            Earr = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1, d))
+            nE = Earr.shape[0]
+            h.keep.append(Earr)
+            Eptr = Earr.ctypes.data
+        r = _lib.Result()
+        bufs = _result_buffers(r, nE, d, pr.max_iter)
+        if tag is None:
+            tag = self._next
+        self._next = max(self._next, int(tag)) + 1
+        check(lib().lrfg_server_submit(self._h, C.byref(pr), C.byref(c), Eptr, nE, C.byref(r), int(tag)))
+        self._pending[int(tag)] = (h, pr, c, r, bufs)
+        return int(tag)
+
+    def poll(self, timeout_ms: int = 0, max_n: int = 256):
+        """Completed requests (waits up to timeout_ms for the first; < 0: until one)."""
+        done = (_lib.Completion * max_n)()
+        n = C.c_int()
+        check(lib().lrfg_server_poll(self._h, done, max_n, C.byref(n), int(timeout_ms)))
+        out = []
+        for k in range(n.value):
+            c = done[k]
+            h, pr, coeff, r, (A, iters, hist, ranks, status) = self._pending.pop(int(c.tag))
+            res = SolveResult(A, iters, hist, ranks, status, int(c.status), r.setup_ms, r.solve_ms)
+            out.append(Completion(int(c.tag), int(c.status), int(c.batch_size), float(c.queue_ms),
+                                  float(c.run_ms), float(c.total_ms), int(c.workspace_bytes), res))
+        return out
+
+    def pending(self) -> int:
+        return int(lib().lrfg_server_pending(self._h))
+
+    def drain(self):
+        """Wait for every submitted request; returns their completions."""
+        out = []
+        while self._pending:
+            out += self.poll(timeout_ms=1000)
+        return out
+
+    def close(self):
+        if self._h:
+            lib().lrfg_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._pending.clear()
 
     def __del__(self):
         try:

@@ -64,6 +64,18 @@ class Result(C.Structure):
     ]
 
 
+class Completion(C.Structure):
+    _fields_ = [
+        ("tag", C.c_uint64),
+        ("status", C.c_int),
+        ("batch_size", C.c_int),
+        ("queue_ms", C.c_double),
+        ("run_ms", C.c_double),
+        ("total_ms", C.c_double),
+        ("workspace_bytes", C.c_size_t),
+    ]
+
+
 class LrfgError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"lrfg status {status}: {msg}")
@@ -74,7 +86,8 @@ _LIB = None
 
 EXPORTS = [
     "lrfg_abi_version", "lrfg_status_string", "lrfg_last_error", "lrfg_device_check",
-    "lrfg_plan_create", "lrfg_plan_workspace_bytes", "lrfg_solve", "lrfg_plan_destroy",
+    "lrfg_plan_create", "lrfg_plan_workspace_bytes", "lrfg_solve", "lrfg_solve_batch", "lrfg_server_create", "lrfg_server_submit",
+    "lrfg_server_poll", "lrfg_server_pending", "lrfg_server_destroy", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
     "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_gram_cut", "lrfg_tt_round_workspace_bytes",
@@ -90,6 +103,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not found: build it with "
                           "`python -m paper_1902_07455_amd.build`")
+    # torch first: its HIP runtime is then the one liblrfg.so binds to, so
+    # the process holds a single runtime (device memory and streams come
+    # from torch)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     L.lrfg_abi_version.restype = C.c_int
     L.lrfg_status_string.restype = C.c_char_p
@@ -103,6 +120,20 @@ def lib():
     L.lrfg_solve.argtypes = [C.c_void_p, C.POINTER(Coeff), C.c_void_p, C.c_int, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.POINTER(Result)]
     L.lrfg_solve.restype = C.c_int
+    L.lrfg_solve_batch.argtypes = [C.c_void_p, C.POINTER(Coeff), C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                   C.c_size_t, C.c_void_p, C.POINTER(Result)]
+    L.lrfg_solve_batch.restype = C.c_int
+    L.lrfg_server_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
+    L.lrfg_server_create.restype = C.c_int
+    L.lrfg_server_submit.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Coeff), C.c_void_p, C.c_int,
+                                     C.POINTER(Result), C.c_uint64]
+    L.lrfg_server_submit.restype = C.c_int
+    L.lrfg_server_poll.argtypes = [C.c_void_p, C.POINTER(Completion), C.c_int, C.POINTER(C.c_int), C.c_int]
+    L.lrfg_server_poll.restype = C.c_int
+    L.lrfg_server_pending.argtypes = [C.c_void_p]
+    L.lrfg_server_pending.restype = C.c_int
+    L.lrfg_server_destroy.argtypes = [C.c_void_p]
+    L.lrfg_server_destroy.restype = None
     L.lrfg_plan_destroy.argtypes = [C.c_void_p]
     L.lrfg_plan_destroy.restype = None
     L.lrfg_fft_workspace_bytes.argtypes = [C.c_int]

@@ -220,14 +220,22 @@ void lrfg_plan_destroy(lrfg_plan* plan) {
   delete plan;
 }
 
-int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* d_ws,
-               size_t ws_bytes, void* stream, lrfg_result* out) {
+static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* d_ws, size_t need,
+                    void* stream, lrfg_result* out);
+
+// count microstructures (coefficients a[0..count-1]) with the same fields E.
+static int solve_impl(lrfg_plan* plan, const lrfg_coeff* a, int count, const double* E, int nE, void* d_ws,
+                      size_t ws_bytes, void* stream, lrfg_result* outs) {
   clear_error();
-  if (plan == nullptr || a == nullptr || out == nullptr) {
+  if (plan == nullptr || a == nullptr || outs == nullptr) {
     set_error("plan, coefficient and result must be non-NULL");
     return LRFG_EINVAL;
   }
   const lrfg_problem& p = plan->p;
+  if (count < 1 || (p.format != LRFG_FORMAT_FULL && count * nE > kMaxSystems)) {
+    set_error("count %d outside [1, %d / nE]", count, kMaxSystems);
+    return LRFG_EINVAL;
+  }
   if (E == nullptr && nE != p.d) {
     set_error("E = NULL means the canonical basis: nE must equal d");
     return LRFG_EINVAL;
@@ -241,15 +249,17 @@ int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, vo
     return LRFG_EWORKSPACE;
   }
   size_t need = 0;
-  LRFG_TRY(lrfg_plan_workspace_bytes(plan, nE, &need));
+  LRFG_TRY(lrfg_plan_workspace_bytes(plan, p.format == LRFG_FORMAT_FULL ? nE : count * nE, &need));
   if (ws_bytes < need) {
     set_error("workspace too small: need %zu bytes, have %zu", need, ws_bytes);
     return LRFG_EWORKSPACE;
   }
-  int nsrc = (a->full != nullptr) + (a->weights != nullptr) + (a->tt_cores[0] != nullptr);
-  if (nsrc != 1) {
-    set_error("exactly one of full / weights / tt_cores must be given");
-    return LRFG_EINVAL;
+  for (int b = 0; b < count; ++b) {
+    const int nsrc = (a[b].full != nullptr) + (a[b].weights != nullptr) + (a[b].tt_cores[0] != nullptr);
+    if (nsrc != 1) {
+      set_error("coefficient %d: exactly one of full / weights / tt_cores must be given", b);
+      return LRFG_EINVAL;
+    }
   }
   LRFG_TRY(device_ok());
   std::vector<double> Ebuf;
@@ -265,7 +275,33 @@ int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, vo
     }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (p.format == LRFG_FORMAT_FULL) {
+  if (p.format != LRFG_FORMAT_FULL) return lowrank_solve(plan->lr, a, count, E, nE, d_ws, ws_bytes, s, outs);
+  // full grid: the microstructures run one after another in the same workspace
+  int worst = LRFG_OK;
+  for (int b = 0; b < count; ++b) {
+    const int rc = full_one(plan, &a[b], E, nE, d_ws, need, stream, &outs[b]);
+    if (rc < 0) return rc;
+    if (rc != LRFG_OK) worst = rc;
+  }
+  return worst;
+}
+
+int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* d_ws, size_t ws_bytes,
+               void* stream, lrfg_result* out) {
+  return solve_impl(plan, a, 1, E, nE, d_ws, ws_bytes, stream, out);
+}
+
+int lrfg_solve_batch(lrfg_plan* plan, const lrfg_coeff* a, int count, const double* E, int nE, void* d_ws,
+                     size_t ws_bytes, void* stream, lrfg_result* results) {
+  return solve_impl(plan, a, count, E, nE, d_ws, ws_bytes, stream, results);
+}
+
+// One full-grid solve (validated arguments).
+static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* d_ws, size_t need,
+                    void* stream, lrfg_result* out) {
+  const lrfg_problem& p = plan->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
     if (plan->pinned == nullptr) {
       LRFG_HIP(hipHostMalloc((void**)&plan->pinned, sizeof(int) * 4 * 3, hipHostMallocDefault));
       plan->pinned_n = 12;
@@ -310,7 +346,6 @@ int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, vo
     out->solve_ms = fo.solve_ms;
     return rc;
   }
-  return lowrank_solve(plan->lr, *a, E, nE, d_ws, ws_bytes, s, out);
 }
 
 size_t lrfg_fft_workspace_bytes(int N) { return sizeof(double2) * (size_t)(N > 0 ? N : 1) + 256; }

@@ -121,16 +121,30 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   }
 }
 
+// Fibre pairs: the F fibres of each system are paired among themselves
+// (2q, 2q+1; the last one alone when F is odd), so a fibre's rounding never
+// depends on a neighbouring system and a batch reproduces its systems'
+// single results bit for bit.  Pair p of P = ceil(F/2) per system.
+__device__ inline long long pair_first(long long p, long long F, long long P, bool* has_second) {
+  const long long e = p / P, q = p - e * P;
+  *has_second = 2 * q + 1 < F;
+  return e * F + 2 * q;
+}
+
 // Real circulant along the mode index: two real fibres packed into one
 // complex line (the operator is real, so it acts on real and imaginary
 // parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2); result times mult.
-// Reads xin, writes x (the same array for in-place use).
+// Reads xin, writes x (the same array for in-place use).  Fibres are paired
+// within groups of F (one system).
 template <bool GEN>
-__global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double* x, long long nfib, int inner, int T,
-                                                        FftDev f, int op, double tparam, double mult) {
+__global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double* x, long long nfib, long long F,
+                                                        int inner, int T, FftDev f, int op, double tparam,
+                                                        double mult) {
   extern __shared__ double2 sm[];
   const int N = f.N;
-  const long long f0 = (long long)blockIdx.x * (2 * T);
+  const long long P = (F + 1) / 2;
+  const long long npair = (nfib / F) * P;
+  const long long p0 = (long long)blockIdx.x * T;
   const int total = T * N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
@@ -140,9 +154,11 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    const long long fa = f0 + 2 * t, fb = fa + 1;
-    const double re = (idx < total && fa < nfib) ? xin[line_addr(fa, n, N, inner)] : 0.0;
-    const double im = (idx < total && fb < nfib) ? xin[line_addr(fb, n, N, inner)] : 0.0;
+    bool hb = false;
+    const bool ok = idx < total && p0 + t < npair;
+    const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
+    const double re = ok ? xin[line_addr(fa, n, N, inner)] : 0.0;
+    const double im = (ok && hb) ? xin[line_addr(fa + 1, n, N, inner)] : 0.0;
     v[i] = make_double2(re, im);
   }
 #pragma unroll
@@ -174,11 +190,12 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    const long long fa = f0 + 2 * t, fb = fa + 1;
-    if (idx < total) {
+    if (idx < total && p0 + t < npair) {
+      bool hb = false;
+      const long long fa = pair_first(p0 + t, F, P, &hb);
       const double2 w = sm[t * N + n];
-      if (fa < nfib) x[line_addr(fa, n, N, inner)] = w.x;
-      if (fb < nfib) x[line_addr(fb, n, N, inner)] = w.y;
+      x[line_addr(fa, n, N, inner)] = w.x;
+      if (hb) x[line_addr(fa + 1, n, N, inner)] = w.y;
     }
   }
 }
@@ -202,8 +219,10 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   extern __shared__ double2 sm[];
   const int N = f.N;
   const int m = blockIdx.y;
-  const long long nfib = (long long)nE * r0 * r1;
-  const long long f0 = (long long)blockIdx.x * (2 * T);
+  const long long F = (long long)r0 * r1;
+  const long long P = (F + 1) / 2;
+  const long long npair = (long long)nE * P;
+  const long long p0 = (long long)blockIdx.x * T;
   const int total = T * N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
@@ -227,9 +246,11 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    const long long fa = f0 + 2 * t, fb = fa + 1;
-    const double re = (idx < total && fa < nfib) ? xin[in_addr(fa, n)] : 0.0;
-    const double im = (idx < total && fb < nfib) ? xin[in_addr(fb, n)] : 0.0;
+    bool hb = false;
+    const bool ok = idx < total && p0 + t < npair;
+    const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
+    const double re = ok ? xin[in_addr(fa, n)] : 0.0;
+    const double im = (ok && hb) ? xin[in_addr(fa + 1, n)] : 0.0;
     v[i] = make_double2(re, im);
   }
 #pragma unroll
@@ -256,11 +277,12 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
     if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
-    const long long fa = f0 + 2 * t, fb = fa + 1;
-    if (idx < total) {
+    if (idx < total && p0 + t < npair) {
+      bool hb = false;
+      const long long fa = pair_first(p0 + t, F, P, &hb);
       const double2 w = sm[t * N + n];
-      if (fa < nfib) out[out_addr(fa, n)] = w.x;
-      if (fb < nfib) out[out_addr(fb, n)] = w.y;
+      out[out_addr(fa, n)] = w.x;
+      if (hb) out[out_addr(fa + 1, n)] = w.y;
     }
   }
 }
@@ -286,7 +308,7 @@ int launch_mode_op_blocks(const double* xin, long long sx, int r0, int r1, int n
   }
   const int T = lines_per_tile1(N);
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
-  dim3 grid(ceil_div(nfib, 2 * T), M);
+  dim3 grid(ceil_div((long long)nE * ((r0 * r1 + 1) / 2), T), M);
   ProfScope ps_("mode_op_blocks", s);
   if (plan_generic(f))
     hipLaunchKernelGGL(k_mode_op_blocks<true>, grid, dim3(kFftBlock), shm, s, xin, sx, r0, r1, nE, out, so, R1,
@@ -337,29 +359,36 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
 }
 
 int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
-                       double mult, const FftDev& f, hipStream_t s) {
+                       double mult, const FftDev& f, hipStream_t s, long long fib_per_group) {
   const long long nfib = outer * inner;
   if (nfib == 0) return LRFG_OK;
+  const long long F = fib_per_group > 0 ? fib_per_group : nfib;
+  if (nfib % F != 0) {
+    set_error("mode op: %lld fibres are not whole groups of %lld", nfib, F);
+    return LRFG_EINVAL;
+  }
+  const long long npair = (nfib / F) * ((F + 1) / 2);
   if (N > kFftMaxE * kFftBlock) {
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
   }
   const int T = lines_per_tile1(N);
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
-  const int grid = ceil_div(nfib, 2 * T);
+  const int grid = ceil_div(npair, T);
   ProfScope ps_("mode_op", s);
   if (plan_generic(f))
-    hipLaunchKernelGGL(k_mode_op<true>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, (int)inner, T, f, op, t, mult);
+    hipLaunchKernelGGL(k_mode_op<true>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, F, (int)inner, T, f, op,
+                       t, mult);
   else
-    hipLaunchKernelGGL(k_mode_op<false>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, (int)inner, T, f, op, t,
-                       mult);
+    hipLaunchKernelGGL(k_mode_op<false>, dim3(grid), dim3(kFftBlock), shm, s, xin, x, nfib, F, (int)inner, T, f, op,
+                       t, mult);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
 int launch_mode_op(double* x, long long outer, int N, long long inner, int op, double t, const FftDev& f,
                    hipStream_t s) {
-  return launch_mode_op_oop(x, x, outer, N, inner, op, t, 1.0, f, s);
+  return launch_mode_op_oop(x, x, outer, N, inner, op, t, 1.0, f, s, 0);
 }
 
 }  // namespace lrfg

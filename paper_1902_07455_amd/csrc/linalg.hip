@@ -1,5 +1,6 @@
 // FP64 batched GEMM on MFMA (v_mfma_f64_16x16x4f64) and a batched cyclic
 // Jacobi eigensolver for small symmetric matrices.
+#include <algorithm>
 #include <cmath>
 
 #include "linalg.h"
@@ -239,10 +240,13 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
 // truncation's shapes (more blocks, same K loop), so it is not selected.
 bool use_small(const Gemm&) { return false; }
 
+// K splits from the shape of one matrix only, so a matrix gets the same
+// summation order whatever the batch it travels in (batched solves
+// reproduce single solves bit for bit).
 int choose_ksplit(const Gemm& g) {
   const bool sm = use_small(g);
   const int tm = sm ? SM : BM, tn = sm ? SM : BN;
-  const long long tiles = (long long)ceil_div(g.m, tm) * ceil_div(g.n, tn) * g.batch;
+  const long long tiles = (long long)ceil_div(g.m, tm) * ceil_div(g.n, tn);
   if (tiles >= 128 || g.k < 256) return 1;
   long long ks = 512 / tiles;
   const long long kmax = g.k / 64;  // at least 64 of K per split
@@ -711,40 +715,53 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return LRFG_OK;
   int ks = choose_ksplit(g);
   if (ks > 1) {
-    // as many splits as the scratch holds
-    const size_t per = (size_t)g.batch * g.m * g.n;
-    const size_t fit = scratch == nullptr ? 0 : scratch_doubles / per;
+    // as many splits as the scratch holds for one matrix
+    const size_t per1 = (size_t)g.m * g.n;
+    const size_t fit = scratch == nullptr ? 0 : scratch_doubles / per1;
     if ((size_t)ks > fit) ks = (int)fit;
     if (ks < 2) ks = 1;
   }
   const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + BK - 1) / BK * BK : (g.k > 0 ? g.k : 1);
   // (a multiple of BK is one of SK too)
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
+  // matrices per launch: all of them, or as many as the split partials fit
+  int chunk = g.batch;
+  if (ks > 1) {
+    const size_t per = (size_t)ks * g.m * g.n;
+    chunk = (int)std::min<size_t>((size_t)g.batch, scratch_doubles / per);
+  }
   const bool sm = use_small(g);
-  dim3 grid(ceil_div(g.n, sm ? SM : BN), ceil_div(g.m, sm ? SM : BM), g.batch * ks);
   double* part = ks > 1 ? scratch : nullptr;
+  for (int b0 = 0; b0 < g.batch; b0 += chunk) {
+    Gemm c = g;
+    c.batch = std::min(chunk, g.batch - b0);
+    c.A = g.A + (long long)b0 * g.sA;
+    c.B = g.B + (long long)b0 * g.sB;
+    c.C = g.C + (long long)b0 * g.sC;
+    dim3 grid(ceil_div(c.n, sm ? SM : BN), ceil_div(c.m, sm ? SM : BM), c.batch * ks);
 #define LRFG_GEMM_LAUNCH(TA, TB)                                                                              \
   do {                                                                                                       \
     if (sm)                                                                                                  \
-      hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, g.m, g.n, g.k, g.A, g.lda, g.sA, g.B, g.ldb, \
-                         g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, ks, kchunk, part);                            \
+      hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, \
+                         c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, kchunk, part);                            \
     else                                                                                                     \
-      LRFG_LAUNCH_TIMED("gemm", 2.0 * g.m * g.n * (double)g.k * g.batch, (k_gemm<TA, TB>), grid, dim3(256), 0, \
-                        s, g.m, g.n, g.k, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm<TA, TB>), grid, dim3(256), 0, \
+                        s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
                         ks, kchunk, part);                                                                   \
   } while (0)
-  if (!g.ta && !g.tb) LRFG_GEMM_LAUNCH(false, false);
-  else if (g.ta && !g.tb) LRFG_GEMM_LAUNCH(true, false);
-  else if (!g.ta && g.tb) LRFG_GEMM_LAUNCH(false, true);
-  else LRFG_GEMM_LAUNCH(true, true);
+    if (!c.ta && !c.tb) LRFG_GEMM_LAUNCH(false, false);
+    else if (c.ta && !c.tb) LRFG_GEMM_LAUNCH(true, false);
+    else if (!c.ta && c.tb) LRFG_GEMM_LAUNCH(false, true);
+    else LRFG_GEMM_LAUNCH(true, true);
 #undef LRFG_GEMM_LAUNCH
-  LRFG_LAUNCHED();
-  if (ks > 1) {
-    const long long tot = (long long)g.batch * g.m * g.n;
-    const int gr = (int)((tot + 31) / 32);
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, g.m, g.n, ks, g.batch, (const double*)part, g.C,
-                       g.ldc, g.sC, g.alpha, g.beta);
     LRFG_LAUNCHED();
+    if (ks > 1) {
+      const long long tot = (long long)c.batch * c.m * c.n;
+      const int gr = (int)((tot + 31) / 32);
+      hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, c.m, c.n, ks, c.batch, (const double*)part,
+                         c.C, c.ldc, c.sC, c.alpha, c.beta);
+      LRFG_LAUNCHED();
+    }
   }
   return LRFG_OK;
 }

@@ -17,8 +17,13 @@ int expand_coeff(const lrfg_problem& p, const lrfg_coeff& a, double* dst, size_t
 
 int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out);
 void lowrank_plan_destroy(LowRankPlan* lr);
+// Systems in one solve (microstructures x fields) are limited to this.
+constexpr int kMaxSystems = 256;
 size_t lowrank_workspace_bytes(const LowRankPlan* lr, int max_nE);
-int lowrank_solve(LowRankPlan* lr, const lrfg_coeff& a, const double* E, int nE, void* ws, size_t ws_bytes,
-                  hipStream_t s, lrfg_result* out);
+// nB microstructures (coefficients a[0..nB-1], equal ranks), each with the
+// nE fields E (nE x d), solved as one batch of nB nE trains; out[b]
+// receives microstructure b's nE x nE A_H and per-field diagnostics.
+int lowrank_solve(LowRankPlan* lr, const lrfg_coeff* a, int nB, const double* E, int nE, void* ws,
+                  size_t ws_bytes, hipStream_t s, lrfg_result* out);
 
 }  // namespace lrfg

@@ -108,13 +108,13 @@ __global__ void k_cp_to_tt(const double* __restrict__ w, const double* __restric
 // alpha_e = done ? 0 : num_e / den_e
 __global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den, const int* __restrict__ done,
                         double* __restrict__ out, int nE) {
-  const int e = threadIdx.x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nE) out[e] = (done[e] || !(den[e] != 0.0)) ? 0.0 : num[e] / den[e];
 }
 
 // coef2 = [c; -c]
 __global__ void k_pm(const double* __restrict__ c, double* __restrict__ coef2, int nE) {
-  const int e = threadIdx.x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nE) {
     coef2[e] = c[e];
     coef2[nE + e] = -c[e];
@@ -124,7 +124,7 @@ __global__ void k_pm(const double* __restrict__ c, double* __restrict__ coef2, i
 // beta_e = rz_e / rho_e (0 when done); rho_e <- rz_e
 __global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, const int* __restrict__ done,
                        double* __restrict__ beta, int nE) {
-  const int e = threadIdx.x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nE) {
     beta[e] = (done[e] || !(rho[e] != 0.0)) ? 0.0 : rz[e] / rho[e];
     if (!done[e]) rho[e] = rz[e];
@@ -134,10 +134,11 @@ __global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, 
 struct Ctx {
   LowRankPlan* pl;
   int d, nE;
+  int na;                   // coefficient trains held: 1 (shared) or nE (one per system)
   hipStream_t s;
   FftDev f[3];
   Rounder rd;
-  TTB a;                    // coefficient (shared)
+  TTB a;                    // coefficient: shared (stride 0) or one train per system
   TTB xr;                   // [x; r]: 2 nE trains updated by one truncation
   TTB pq;                   // [p; q]
   TTB x, r, p, q;           // views of the halves
@@ -157,19 +158,22 @@ struct Ctx {
   int comb_cap[4];
 };
 
-int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
+// na = 1: one coefficient shared by the nE systems; na = nE: one each.
+int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   const int d = pl->d;
   C.pl = pl;
   C.d = d;
   C.nE = nE;
+  C.na = na;
   int rc[4] = {1, 1, 1, 1};
   for (int j = 0; j <= d; ++j) rc[j] = pl->c[j];
   int ra[4] = {1, pl->ra, d == 3 ? pl->ra : 1, 1};
   ra[d] = 1;
   // twiddles
   for (int j = 0; j < d; ++j) C.f[j].tw = ar.take<double2>(pl->N[j]);
-  C.a = tt_alloc(ar, d, pl->N, ra, 1);
-  for (int j = 0; j < d; ++j) C.a.s[j] = 0;
+  C.a = tt_alloc(ar, d, pl->N, ra, na);
+  if (na == 1)
+    for (int j = 0; j < d; ++j) C.a.s[j] = 0;
   C.xr = tt_alloc(ar, d, pl->N, rc, 2 * nE);
   C.pq = tt_alloc(ar, d, pl->N, rc, 2 * nE);
   C.x = C.xr;
@@ -207,7 +211,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
   C.pcore = ar.take<double>((size_t)C.pcore_stride * pl->M * d);
   long long acmax = 0;
   for (int j = 0; j < d; ++j) acmax = std::max(acmax, (long long)ra[j] * pl->N[j] * ra[j + 1]);
-  for (int al = 0; al < d; ++al) C.acore[al] = ar.take<double>((size_t)acmax);
+  for (int al = 0; al < d; ++al) C.acore[al] = ar.take<double>((size_t)acmax * na);
   // rounding workspace
   Rounder& R = C.rd;
   R.d = d;
@@ -220,16 +224,16 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, Ctx& C) {
     R.Lmax[j - 1] = rc[j] + pl->over;
   }
   R.carve(ar);
-  // scalars
-  C.dots = ar.take<double>(64);
-  C.rho = ar.take<double>(4);
-  C.pqd = ar.take<double>(4);
-  C.alpha = ar.take<double>(4);
-  C.beta = ar.take<double>(4);
-  C.zz = ar.take<double>(4);
-  C.Ecoef = ar.take<double>(12);
-  C.coef2 = ar.take<double>(8);
-  C.done = ar.take<int>(4);
+  // per-system scalars (dots also holds the nE x 3 energy-form products)
+  C.dots = ar.take<double>((size_t)3 * nE + 64);
+  C.rho = ar.take<double>(nE);
+  C.pqd = ar.take<double>(nE);
+  C.alpha = ar.take<double>(nE);
+  C.beta = ar.take<double>(nE);
+  C.zz = ar.take<double>(nE);
+  C.Ecoef = ar.take<double>((size_t)3 * nE);
+  C.coef2 = ar.take<double>((size_t)2 * nE);
+  C.done = ar.take<int>(nE);
   // dot scratch: largest pair (kr, c) or (a, a)
   size_t dn = tt_dot_scratch(C.kr, C.z, nE);
   dn = std::max(dn, tt_dot_scratch(C.a, C.a, nE));
@@ -375,37 +379,24 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
 void lowrank_plan_destroy(LowRankPlan* lr) { delete lr; }
 
 size_t lowrank_workspace_bytes(const LowRankPlan* lr, int max_nE) {
+  // room for one coefficient train per system (the batched form)
   Arena ar;
   Ctx C;
-  carve_ctx(ar, const_cast<LowRankPlan*>(lr), max_nE, C);
+  carve_ctx(ar, const_cast<LowRankPlan*>(lr), max_nE, max_nE, C);
   return ar.used + 1024;
 }
 
 // ====================================================================== solve
-int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE, void* ws, size_t ws_bytes,
-                  hipStream_t s, lrfg_result* out) {
-  const int d = pl->d;
-  const lrfg_problem& P = pl->p;
-  Arena ar;
-  ar.base = static_cast<char*>(ws);
-  ar.cap = ws_bytes;
-  Ctx C;
-  carve_ctx(ar, pl, nE, C);
-  if (ar.overflow) {
-    set_error("workspace too small");
-    return LRFG_EWORKSPACE;
-  }
-  C.s = s;
-  hipEvent_t ev0, ev1, ev2;
-  LRFG_HIP(hipEventCreate(&ev0));
-  LRFG_HIP(hipEventCreate(&ev1));
-  LRFG_HIP(hipEventCreate(&ev2));
-  LRFG_HIP(hipEventRecord(ev0, s));
-  for (int j = 0; j < d; ++j) {
-    double2* tw = const_cast<double2*>(C.f[j].tw);
-    LRFG_TRY(fft_dev_upload(pl->mode[j], tw, s, &C.f[j]));
-  }
-  // ---------------------------------------------------------------- coefficient train
+namespace {
+
+// Coefficient b as a TT into system slot `e` of C.a (CP factors -> TT
+// carriages, or TT cores copied); checks its ranks against `rk`.
+int load_coeff(Ctx& C, const lrfg_coeff& ac, int e, int* rk) {
+  LowRankPlan* pl = C.pl;
+  const int d = C.d;
+  hipStream_t s = C.s;
+  double* dst[3];
+  for (int j = 0; j < d; ++j) dst[j] = C.a.c[j] + (long long)e * C.a.s[j];
   if (ac.full != nullptr) {
     set_error("the low-rank path takes the coefficient in CP or TT form");
     return LRFG_EUNSUPPORTED;
@@ -416,24 +407,30 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
       set_error("coefficient rank %d outside [1, coeff_rank = %d]", R, pl->ra);
       return LRFG_EINVAL;
     }
+    if (rk[1] != 0 && rk[1] != R) {
+      set_error("all coefficients of one batch need the same rank (%d vs %d)", R, rk[1]);
+      return LRFG_EINVAL;
+    }
+    rk[0] = 1;
+    rk[d] = 1;
+    for (int j = 1; j < d; ++j) rk[j] = R;
     const double* w = ac.weights;
     const double* f[3] = {ac.factors[0], ac.factors[1], d == 3 ? ac.factors[2] : ac.factors[1]};
-    std::vector<double> staging;
-    double* dstage = nullptr;
     if (!ac.on_device) {
       // stage host factors through the product buffer (not yet in use)
       size_t n = R;
       for (int j = 0; j < d; ++j) n += (size_t)R * pl->N[j];
-      if (n > (size_t)C.kr.size(1) * nE) {
+      if (n > (size_t)C.kr.size(1) * C.nE) {
         set_error("coefficient staging too small");
         return LRFG_EWORKSPACE;
       }
-      dstage = C.kr.c[1];
+      double* dstage = C.kr.c[1];
       LRFG_HIP(hipMemcpyAsync(dstage, w, sizeof(double) * R, hipMemcpyHostToDevice, s));
       size_t off = R;
       const double* df[3];
       for (int j = 0; j < d; ++j) {
-        LRFG_HIP(hipMemcpyAsync(dstage + off, ac.factors[j], sizeof(double) * R * pl->N[j], hipMemcpyHostToDevice, s));
+        LRFG_HIP(hipMemcpyAsync(dstage + off, ac.factors[j], sizeof(double) * R * pl->N[j], hipMemcpyHostToDevice,
+                                s));
         df[j] = dstage + off;
         off += (size_t)R * pl->N[j];
       }
@@ -441,41 +438,93 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
       for (int j = 0; j < d; ++j) f[j] = df[j];
       if (d == 2) f[2] = df[1];
     }
-    C.a.r[1] = R;
-    if (d == 3) C.a.r[2] = R;
     const long long tot = (long long)pl->N[0] * R + (d == 3 ? (long long)R * pl->N[1] * R + (long long)R * pl->N[2]
                                                            : (long long)R * pl->N[1]);
     hipLaunchKernelGGL(k_cp_to_tt, dim3((int)std::min<long long>(4096, (tot + 255) / 256)), dim3(256), 0, s, w, f[0],
-                       f[1], f[2], R, d, pl->N[0], pl->N[1], d == 3 ? pl->N[2] : 1, C.a.c[0], C.a.c[1],
-                       d == 3 ? C.a.c[2] : nullptr);
+                       f[1], f[2], R, d, pl->N[0], pl->N[1], d == 3 ? pl->N[2] : 1, dst[0], dst[1],
+                       d == 3 ? dst[2] : nullptr);
     LRFG_LAUNCHED();
-  } else {
-    const int* rk = ac.tt_ranks;
-    if (rk[0] != 1 || rk[d] != 1) {
-      set_error("TT coefficient: r_0 = r_d = 1 required");
+    return LRFG_OK;
+  }
+  const int* r = ac.tt_ranks;
+  if (r[0] != 1 || r[d] != 1) {
+    set_error("TT coefficient: r_0 = r_d = 1 required");
+    return LRFG_EINVAL;
+  }
+  for (int j = 1; j < d; ++j) {
+    if (r[j] < 1 || r[j] > pl->ra) {
+      set_error("TT coefficient rank %d outside [1, coeff_rank = %d]", r[j], pl->ra);
       return LRFG_EINVAL;
     }
-    for (int j = 1; j < d; ++j) {
-      if (rk[j] < 1 || rk[j] > pl->ra) {
-        set_error("TT coefficient rank %d outside [1, coeff_rank = %d]", rk[j], pl->ra);
-        return LRFG_EINVAL;
-      }
-      C.a.r[j] = rk[j];
+    if (rk[j] != 0 && rk[j] != r[j]) {
+      set_error("all coefficients of one batch need the same TT ranks");
+      return LRFG_EINVAL;
     }
-    for (int j = 0; j < d; ++j) {
-      LRFG_HIP(hipMemcpyAsync(C.a.c[j], ac.tt_cores[j], sizeof(double) * C.a.size(j),
-                              ac.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-    }
+  }
+  for (int j = 0; j <= d; ++j) rk[j] = r[j];
+  for (int j = 0; j < d; ++j) {
+    const size_t n = (size_t)r[j] * pl->N[j] * r[j + 1];
+    LRFG_HIP(hipMemcpyAsync(dst[j], ac.tt_cores[j], sizeof(double) * n,
+                            ac.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  }
+  return LRFG_OK;
+}
+
+}  // namespace
+
+int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E, int nEp, void* ws,
+                  size_t ws_bytes, hipStream_t s, lrfg_result* outs) {
+  const int d = pl->d;
+  const lrfg_problem& P = pl->p;
+  const int nE = nB * nEp;  // system e = b nEp + f: microstructure b, field f
+  if (nB < 1 || nEp < 1 || nE > kMaxSystems) {
+    set_error("%d microstructures x %d fields outside [1, %d] systems", nB, nEp, kMaxSystems);
+    return LRFG_EINVAL;
+  }
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  Ctx C;
+  carve_ctx(ar, pl, nE, nB == 1 ? 1 : nE, C);
+  if (ar.overflow) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  C.s = s;
+  const int na = C.na;
+  hipEvent_t ev0, ev1, ev2;
+  LRFG_HIP(hipEventCreate(&ev0));
+  LRFG_HIP(hipEventCreate(&ev1));
+  LRFG_HIP(hipEventCreate(&ev2));
+  LRFG_HIP(hipEventRecord(ev0, s));
+  for (int j = 0; j < d; ++j) {
+    double2* tw = const_cast<double2*>(C.f[j].tw);
+    LRFG_TRY(fft_dev_upload(pl->mode[j], tw, s, &C.f[j]));
+  }
+  // ---------------------------------------------------------------- coefficient trains
+  int rk[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nB; ++b) LRFG_TRY(load_coeff(C, acs[b], na == 1 ? 0 : b * nEp, rk));
+  for (int j = 1; j < d; ++j) C.a.r[j] = rk[j];
+  if (na > 1) {
+    // every field of microstructure b reads its own copy of the train
+    for (int j = 0; j < d; ++j) C.a.s[j] = C.a.size(j);
+    for (int b = 0; b < nB; ++b)
+      for (int f = 1; f < nEp; ++f)
+        for (int j = 0; j < d; ++j)
+          LRFG_HIP(hipMemcpyAsync(C.a.c[j] + (long long)(b * nEp + f) * C.a.s[j],
+                                  C.a.c[j] + (long long)(b * nEp) * C.a.s[j], sizeof(double) * C.a.size(j),
+                                  hipMemcpyDeviceToDevice, s));
   }
   // Hadamard output ranks follow the actual coefficient ranks
   for (int j = 1; j < d; ++j) C.kr.r[j] = C.a.r[j] * pl->c[j];
   for (int j = 0; j < d; ++j) C.kr.s[j] = C.kr.size(j);
 
   // ---------------------------------------------------------------- right-hand side
-  // b_e = sum_alpha E_e,alpha D_alpha a  (real-space form of -div^ F (a E))
+  // b_e = sum_alpha E_e,alpha D_alpha a_e  (real-space form of -div^ F (a E))
+  auto Ev = [&](int e, int al) { return E[(e % nEp) * d + al]; };
   std::vector<double> Ecol(3 * nE, 0.0);
   for (int al = 0; al < d; ++al)
-    for (int e = 0; e < nE; ++e) Ecol[al * nE + e] = E[e * d + al];
+    for (int e = 0; e < nE; ++e) Ecol[al * nE + e] = Ev(e, al);
   LRFG_HIP(hipMemcpyAsync(C.Ecoef, Ecol.data(), sizeof(double) * d * nE, hipMemcpyHostToDevice, s));
   {
     TTB da[3];
@@ -483,7 +532,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
     for (int al = 0; al < d; ++al) {
       da[al] = C.a;
       da[al].c[al] = C.acore[al];
-      LRFG_TRY(tt_mode_apply(C.a, da[al], al, 0, 0.0, 1.0, C.f[al], 1, s));
+      LRFG_TRY(tt_mode_apply(C.a, da[al], al, 0, 0.0, 1.0, C.f[al], na, s));
       terms[al] = TTTerm{&da[al], C.Ecoef + al * nE, 1.0};
     }
     TTB comb = C.comb;
@@ -492,19 +541,19 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
     LRFG_TRY(tt_sum(terms, d, comb, nE, s));
     LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s, nE));
   }
-  // scale for the zero-right-hand-side floor: rms(a) |E|
-  double a2 = 0.0;
+  // scale for the zero-right-hand-side floor: rms(a) |E|, per coefficient train
+  std::vector<double> a2(na, 0.0);
   {
-    LRFG_TRY(tt_dot(C.a, C.a, C.dots, C.dscr, 1, s));
-    LRFG_TRY(read_dev(C, C.dots, &a2, 1));
+    LRFG_TRY(tt_dot(C.a, C.a, C.dots, C.dscr, na, s));
+    LRFG_TRY(read_dev(C, C.dots, a2.data(), na));
   }
   double Ntot = 1.0;
   for (int j = 0; j < d; ++j) Ntot *= pl->N[j];
-  const double rms_a = std::sqrt(std::max(a2, 0.0) / Ntot);
   std::vector<double> floor_abs(nE);
   for (int e = 0; e < nE; ++e) {
+    const double rms_a = std::sqrt(std::max(a2[na == 1 ? 0 : e], 0.0) / Ntot);
     double en = 0.0;
-    for (int al = 0; al < d; ++al) en += E[e * d + al] * E[e * d + al];
+    for (int al = 0; al < d; ++al) en += Ev(e, al) * Ev(e, al);
     // real-space norms carry sqrt(|N|) relative to Fourier coefficients
     floor_abs[e] = 1e-14 * rms_a * std::sqrt(en) * std::sqrt(Ntot);
   }
@@ -550,15 +599,15 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
     if (P.solver == LRFG_SOLVER_PCG) {
       LRFG_TRY(apply_K(C, C.p, C.q));
       LRFG_TRY(dot(C, C.p, C.q, C.pqd));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.rho, (const double*)C.pqd,
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.rho, (const double*)C.pqd,
                          (const int*)C.done, C.alpha, nE);
-      hipLaunchKernelGGL(k_pm, dim3(1), dim3(64), 0, s, (const double*)C.alpha, C.coef2, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
       LRFG_LAUNCHED();
       LRFG_TRY(update_xr(C));   // x += alpha p ; r -= alpha q
       LRFG_TRY(apply_P(C, C.r, C.z));
       LRFG_TRY(dot(C, C.r, C.z, C.dots));
       LRFG_TRY(dot(C, C.z, C.z, C.zz));
-      hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, s, (const double*)C.dots, C.rho, (const int*)C.done, C.beta,
+      hipLaunchKernelGGL(k_beta, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, C.rho, (const int*)C.done, C.beta,
                          nE);
       LRFG_LAUNCHED();
       LRFG_TRY(axpby(C, C.z, C.p, C.beta, C.tmp));
@@ -569,9 +618,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
       LRFG_TRY(apply_P(C, C.tmp, C.z));
       LRFG_TRY(dot(C, C.z, C.r, C.dots));
       LRFG_TRY(dot(C, C.z, C.z, C.pqd));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, (const double*)C.dots, (const double*)C.pqd,
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, (const double*)C.pqd,
                          (const int*)C.done, C.alpha, nE);
-      hipLaunchKernelGGL(k_pm, dim3(1), dim3(64), 0, s, (const double*)C.alpha, C.coef2, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
       LRFG_LAUNCHED();
       // [p; q] = [r; Cr] then [u; r] += [omega; -omega] [r; Cr]
       LRFG_TRY(tt_copy(C.r, C.p, nE, s));
@@ -614,9 +663,10 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
 
   // ---------------------------------------------------------------- A_H (eq. homog)
   // A_H[i][j] = mean(a) E_i.E_j + sum_alpha (E_i,alpha m1[j] + E_j,alpha m1[i] + m2[i][j])
-  // m1[e][alpha] = <a, D_alpha x_e>/|N|, m2[i][j][alpha] = <a (.) D_alpha x_i, D_alpha x_j>/|N|
-  std::vector<double> m1((size_t)nE * d), m2((size_t)nE * nE * d);
-  double mean_a = 0.0;
+  // m1[e][alpha] = <a, D_alpha x_e>/|N|, m2[i][j][alpha] = <a (.) D_alpha x_i, D_alpha x_j>/|N|,
+  // i and j fields of the same microstructure
+  std::vector<double> m1((size_t)nE * d), m2((size_t)nE * nEp * d);
+  std::vector<double> mean_a(na, 0.0);
   {
     // <a, 1>: a train of ones
     TTB one = C.tmp;
@@ -626,35 +676,37 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
       one.s[j] = 0;
       LRFG_TRY(tt_fill(one.c[j], pl->N[j], 1.0, s));
     }
-    LRFG_TRY(tt_dot(C.a, one, C.dots, C.dscr, 1, s));
-    LRFG_TRY(read_dev(C, C.dots, &mean_a, 1));
-    mean_a /= Ntot;
+    LRFG_TRY(tt_dot(C.a, one, C.dots, C.dscr, na, s));
+    LRFG_TRY(read_dev(C, C.dots, mean_a.data(), na));
+    for (auto& v : mean_a) v /= Ntot;
   }
   for (int al = 0; al < d; ++al) {
     TTB g = C.xb;
     g.c[al] = C.gcore;
     LRFG_TRY(tt_mode_apply(C.xb, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
-    // m1: <a, g_e>
+    // m1: <a_e, g_e>
     LRFG_TRY(tt_dot(C.a, g, C.dots, C.dscr, nE, s));
     std::vector<double> v(nE);
     LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
     for (int e = 0; e < nE; ++e) m1[(size_t)e * d + al] = v[e] / Ntot;
-    // m2: <a (.) g_i, g_j>
+    // m2: <a (.) g_i, g_j> within each microstructure
     LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-    for (int i = 0; i < nE; ++i) {
-      for (int j = 0; j < nE; ++j) {
-        TTB ki = C.kr, gj = g;
-        for (int q = 0; q < d; ++q) {
-          ki.c[q] = C.kr.c[q] + i * C.kr.s[q];
-          gj.c[q] = g.c[q] + j * g.s[q];
+    for (int b = 0; b < nB; ++b) {
+      for (int i = 0; i < nEp; ++i) {
+        for (int j = 0; j < nEp; ++j) {
+          const int ei = b * nEp + i, ej = b * nEp + j;
+          TTB ki = C.kr, gj = g;
+          for (int q = 0; q < d; ++q) {
+            ki.c[q] = C.kr.c[q] + ei * C.kr.s[q];
+            gj.c[q] = g.c[q] + ej * g.s[q];
+          }
+          LRFG_TRY(tt_dot(ki, gj, C.dots + (size_t)ei * nEp + j, C.dscr, 1, s));
         }
-        LRFG_TRY(tt_dot(ki, gj, C.dots + i * nE + j, C.dscr, 1, s));
       }
     }
-    std::vector<double> w2((size_t)nE * nE);
-    LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nE));
-    for (int i = 0; i < nE; ++i)
-      for (int j = 0; j < nE; ++j) m2[((size_t)i * nE + j) * d + al] = w2[(size_t)i * nE + j] / Ntot;
+    std::vector<double> w2((size_t)nE * nEp);
+    LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nEp));
+    for (size_t k = 0; k < w2.size(); ++k) m2[k * d + al] = w2[k] / Ntot;
   }
   // final ranks: one more truncation of the best iterate reports the kept ranks
   std::vector<int> kept(2 * nE, 0);
@@ -670,34 +722,40 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE
   LRFG_HIP(hipEventDestroy(ev1));
   LRFG_HIP(hipEventDestroy(ev2));
   int rc = LRFG_OK;
-  for (int i = 0; i < nE; ++i) {
-    for (int j = 0; j < nE; ++j) {
-      double v = 0.0;
-      for (int al = 0; al < d; ++al) {
-        const double ei = E[i * d + al], ej = E[j * d + al];
-        v += mean_a * ei * ej + ei * m1[(size_t)j * d + al] + ej * m1[(size_t)i * d + al] +
-             m2[((size_t)i * nE + j) * d + al];
+  for (int b = 0; b < nB; ++b) {
+    lrfg_result* out = &outs[b];
+    const double ma = mean_a[na == 1 ? 0 : b * nEp];
+    for (int i = 0; i < nEp; ++i) {
+      const int ei = b * nEp + i;
+      for (int j = 0; j < nEp; ++j) {
+        const int ej = b * nEp + j;
+        double v = 0.0;
+        for (int al = 0; al < d; ++al) {
+          const double xi = E[i * d + al], xj = E[j * d + al];
+          v += ma * xi * xj + xi * m1[(size_t)ej * d + al] + xj * m1[(size_t)ei * d + al] +
+               m2[((size_t)ei * nEp + j) * d + al];
+        }
+        if (out->A_H) out->A_H[i * nEp + j] = v;
       }
-      if (out->A_H) out->A_H[i * nE + j] = v;
-    }
-    if (out->iters) out->iters[i] = iters[i];
-    if (out->status) out->status[i] = status[i];
-    if (status[i] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
-    if (out->res_hist)
-      for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)i * maxit + k];
-    if (out->ranks) {
-      out->ranks[i * (d + 1)] = 1;
-      out->ranks[i * (d + 1) + d] = 1;
-      if (d == 3) {
-        out->ranks[i * (d + 1) + 1] = kept[i];
-        out->ranks[i * (d + 1) + 2] = kept[nE + i];
-      } else {
-        out->ranks[i * (d + 1) + 1] = kept[i];
+      if (out->iters) out->iters[i] = iters[ei];
+      if (out->status) out->status[i] = status[ei];
+      if (status[ei] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+      if (out->res_hist)
+        for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)ei * maxit + k];
+      if (out->ranks) {
+        out->ranks[i * (d + 1)] = 1;
+        out->ranks[i * (d + 1) + d] = 1;
+        if (d == 3) {
+          out->ranks[i * (d + 1) + 1] = kept[ei];
+          out->ranks[i * (d + 1) + 2] = kept[nE + ei];
+        } else {
+          out->ranks[i * (d + 1) + 1] = kept[ei];
+        }
       }
     }
+    out->setup_ms = ms_setup;
+    out->solve_ms = ms_solve;
   }
-  out->setup_ms = ms_setup;
-  out->solve_ms = ms_solve;
   return rc;
 }
 

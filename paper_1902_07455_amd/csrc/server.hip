@@ -1,0 +1,334 @@
+// Request loop with continuous batching on one device (host runtime).
+//
+// Requests are homogenisation queries (a problem, its coefficient in place,
+// the fields E).  Worker threads, each with its own HIP stream, admit
+// queued requests while the caller's device pool has room for their
+// workspace (admission by HBM footprint, first fit): the oldest request that
+// fits is taken together with the other queued requests of the same problem
+// (and coefficient ranks and fields), up to max_batch of them, and solved as
+// one lrfg_solve_batch.  A request that arrives while others run joins the
+// next batch a worker forms; batches on different streams overlap on the
+// device.  The coefficient data is read where the caller keeps it (device
+// pointers stay on the device).
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace lrfg {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Request {
+  lrfg_problem p;
+  lrfg_coeff a;
+  std::vector<double> E;  // nE x d, empty = canonical basis
+  int nE = 0;
+  lrfg_result* out = nullptr;
+  uint64_t tag = 0;
+  lrfg_plan* plan = nullptr;
+  size_t ws_one = 0;
+  Clock::time_point t_submit;
+};
+
+// First-fit allocator over [0, size) in 256-byte units.
+class Pool {
+ public:
+  explicit Pool(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~(size_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, at = it->first + n;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~(size_t)255;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  size_t size_;
+  std::map<size_t, size_t> free_;
+};
+
+bool same_problem(const lrfg_problem& x, const lrfg_problem& y) {
+  return x.d == y.d && x.N[0] == y.N[0] && x.N[1] == y.N[1] && x.N[2] == y.N[2] && x.format == y.format &&
+         x.rank_cap == y.rank_cap && x.trunc_tol == y.trunc_tol && x.solver_tol == y.solver_tol &&
+         x.max_iter == y.max_iter && x.solver == y.solver && x.precision == y.precision &&
+         x.precond_terms == y.precond_terms && x.oversample == y.oversample && x.seed == y.seed &&
+         x.coeff_rank == y.coeff_rank && x.flags == y.flags;
+}
+
+bool same_batch_key(const Request& x, const Request& y) {
+  if (!same_problem(x.p, y.p)) return false;
+  if (x.nE != y.nE || x.E != y.E) return false;
+  if (x.p.format == LRFG_FORMAT_FULL) return true;
+  const bool xc = x.a.weights != nullptr, yc = y.a.weights != nullptr;
+  if (xc != yc || x.a.on_device != y.a.on_device) return false;
+  if (xc) return x.a.rank == y.a.rank;
+  for (int j = 0; j <= x.p.d; ++j)
+    if (x.a.tt_ranks[j] != y.a.tt_ranks[j]) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace lrfg
+
+struct lrfg_server {
+  int device = 0;
+  int max_batch = 1;
+  char* pool_base = nullptr;
+  std::unique_ptr<lrfg::Pool> pool;
+  size_t pool_bytes = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<lrfg::Request>> queue;
+  std::deque<lrfg_completion> done;
+  int running = 0;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+  int worker_error = LRFG_OK;
+};
+
+namespace lrfg {
+namespace {
+
+void worker_main(lrfg_server* S) {
+  hipStream_t st = nullptr;
+  if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->worker_error = LRFG_EDEVICE;
+    S->cv_done.notify_all();
+    return;
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    // admission: the oldest request whose batch workspace fits, plus queued
+    // requests with the same key
+    std::vector<std::unique_ptr<Request>> batch;
+    size_t off = 0, bytes = 0;
+    for (;;) {
+      if (S->stopping && S->queue.empty()) break;
+      for (size_t hi = 0; hi < S->queue.size(); ++hi) {
+        Request& head = *S->queue[hi];
+        if (head.ws_one > S->pool->largest()) continue;
+        std::vector<size_t> pick = {hi};
+        size_t need = head.ws_one;
+        if (head.p.format != LRFG_FORMAT_FULL) {
+          for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < S->max_batch; ++j) {
+            if (!same_batch_key(head, *S->queue[j])) continue;
+            size_t more = 0;
+            if (lrfg_plan_workspace_bytes(head.plan, (int)(pick.size() + 1) * head.nE, &more) != LRFG_OK) break;
+            if (more > S->pool->largest()) break;
+            pick.push_back(j);
+            need = more;
+          }
+        }
+        if (!S->pool->alloc(need, &off)) continue;
+        bytes = need;
+        for (size_t k = 0; k < pick.size(); ++k) batch.push_back(std::move(S->queue[pick[k]]));
+        for (size_t k = pick.size(); k-- > 0;) S->queue.erase(S->queue.begin() + (long)pick[k]);
+        break;
+      }
+      if (!batch.empty()) break;
+      S->cv_work.wait(lk);
+    }
+    if (batch.empty()) break;  // stopping and drained
+    ++S->running;
+    lk.unlock();
+
+    const Clock::time_point t0 = Clock::now();
+    std::vector<lrfg_coeff> coeffs(batch.size());
+    std::vector<lrfg_result> res(batch.size());
+    for (size_t k = 0; k < batch.size(); ++k) {
+      coeffs[k] = batch[k]->a;
+      res[k] = *batch[k]->out;
+    }
+    Request& h = *batch[0];
+    const int nE = h.nE;
+    const double* E = h.E.empty() ? nullptr : h.E.data();
+    const int rc = lrfg_solve_batch(h.plan, coeffs.data(), (int)batch.size(), E, nE, S->pool_base + off, bytes, st,
+                                    res.data());
+    const Clock::time_point t1 = Clock::now();
+
+    lk.lock();
+    S->pool->release(off, bytes);
+    --S->running;
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Request& r = *batch[k];
+      *r.out = res[k];
+      lrfg_completion c;
+      c.tag = r.tag;
+      int st_k = rc;
+      if (rc >= 0) {
+        st_k = LRFG_OK;
+        if (r.out->status != nullptr)
+          for (int e = 0; e < nE; ++e)
+            if (r.out->status[e] != LRFG_OK) st_k = LRFG_NOT_CONVERGED;
+      }
+      c.status = st_k;
+      c.batch_size = (int)batch.size();
+      c.queue_ms = ms_between(r.t_submit, t0);
+      c.run_ms = ms_between(t0, t1);
+      c.total_ms = ms_between(r.t_submit, t1);
+      c.workspace_bytes = bytes;
+      S->done.push_back(c);
+      lrfg_plan_destroy(r.plan);
+      r.plan = nullptr;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  lk.unlock();
+  (void)hipStreamDestroy(st);
+}
+
+}  // namespace
+}  // namespace lrfg
+
+extern "C" {
+
+int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_t pool_bytes, lrfg_server** out) {
+  using namespace lrfg;
+  clear_error();
+  if (out == nullptr || slots < 1 || slots > 16 || max_batch < 1 || d_pool == nullptr ||
+      (reinterpret_cast<uintptr_t>(d_pool) & 255) != 0 || pool_bytes < 256) {
+    set_error("bad server arguments (slots in [1, 16], max_batch >= 1, 256-aligned pool)");
+    return LRFG_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    set_error("device %d not available", device);
+    return LRFG_EDEVICE;
+  }
+  auto* S = new lrfg_server();
+  S->device = device;
+  S->max_batch = max_batch;
+  S->pool_base = static_cast<char*>(d_pool);
+  S->pool_bytes = pool_bytes;
+  S->pool.reset(new Pool(pool_bytes));
+  for (int i = 0; i < slots; ++i) S->workers.emplace_back(worker_main, S);
+  *out = S;
+  return LRFG_OK;
+}
+
+int lrfg_server_submit(lrfg_server* S, const lrfg_problem* p, const lrfg_coeff* a, const double* E, int nE,
+                       lrfg_result* out, uint64_t tag) {
+  using namespace lrfg;
+  clear_error();
+  if (S == nullptr || p == nullptr || a == nullptr || out == nullptr) {
+    set_error("server, problem, coefficient and result must be non-NULL");
+    return LRFG_EINVAL;
+  }
+  if (nE < 1 || nE > 3 || (E == nullptr && nE != p->d)) {
+    set_error("nE must be in [1, 3], and equal d when E is NULL");
+    return LRFG_EINVAL;
+  }
+  std::unique_ptr<Request> r(new Request());
+  r->p = *p;
+  r->a = *a;
+  r->nE = nE;
+  if (E != nullptr) r->E.assign(E, E + (size_t)nE * p->d);
+  r->out = out;
+  r->tag = tag;
+  LRFG_TRY(lrfg_plan_create(p, &r->plan));
+  if (lrfg_plan_workspace_bytes(r->plan, nE, &r->ws_one) != LRFG_OK || r->ws_one > S->pool_bytes) {
+    set_error("request workspace %zu exceeds the server pool %zu", r->ws_one, S->pool_bytes);
+    lrfg_plan_destroy(r->plan);
+    return LRFG_EWORKSPACE;
+  }
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stopping) {
+      lrfg_plan_destroy(r->plan);
+      set_error("server is stopping");
+      return LRFG_EINVAL;
+    }
+    S->queue.push_back(std::move(r));
+  }
+  S->cv_work.notify_one();
+  return LRFG_OK;
+}
+
+int lrfg_server_poll(lrfg_server* S, lrfg_completion* done, int max, int* n, int timeout_ms) {
+  using namespace lrfg;
+  clear_error();
+  if (S == nullptr || n == nullptr || (max > 0 && done == nullptr)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto ready = [&] { return !S->done.empty() || S->worker_error != LRFG_OK; };
+  if (timeout_ms < 0)
+    S->cv_done.wait(lk, ready);
+  else if (timeout_ms > 0)
+    S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+  int k = 0;
+  while (k < max && !S->done.empty()) {
+    done[k++] = S->done.front();
+    S->done.pop_front();
+  }
+  *n = k;
+  if (S->worker_error != LRFG_OK) {
+    set_error("a server worker could not start on device %d", S->device);
+    return S->worker_error;
+  }
+  return LRFG_OK;
+}
+
+int lrfg_server_pending(lrfg_server* S) {
+  if (S == nullptr) return 0;
+  std::lock_guard<std::mutex> lk(S->mu);
+  return (int)S->queue.size() + S->running;
+}
+
+void lrfg_server_destroy(lrfg_server* S) {
+  if (S == nullptr) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stopping = true;
+  }
+  S->cv_work.notify_all();
+  for (auto& t : S->workers) t.join();
+  for (auto& r : S->queue)
+    if (r->plan) lrfg_plan_destroy(r->plan);
+  delete S;
+}
+
+}  // extern "C"

@@ -32,7 +32,7 @@
 namespace lrfg {
 
 int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
-                       double mult, const FftDev& f, hipStream_t s);
+                       double mult, const FftDev& f, hipStream_t s, long long fib_per_group);
 
 constexpr size_t kDotSplitK = (size_t)2 * 1024 * 1024;  // doubles of split-K partials in tt_dot
 
@@ -147,6 +147,11 @@ int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s) {
       set_error("tt_copy: rank mismatch");
       return LRFG_EINVAL;
     }
+    if (x.s[j] == x.size(j) && y.s[j] == y.size(j)) {
+      // both batches contiguous: one copy of the whole carriage batch
+      LRFG_HIP(hipMemcpyAsync(y.c[j], x.c[j], sizeof(double) * x.size(j) * nE, hipMemcpyDeviceToDevice, s));
+      continue;
+    }
     for (int e = 0; e < nE; ++e)
       LRFG_HIP(hipMemcpyAsync(y.c[j] + e * y.s[j], x.c[j] + e * x.s[j], sizeof(double) * x.size(j),
                               hipMemcpyDeviceToDevice, s));
@@ -167,7 +172,8 @@ int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, co
   y.s[j] = x.size(j);
   if (x.s[j] == 0) y.s[j] = 0;
   const int reps = (x.s[j] == 0) ? 1 : nE;
-  return launch_mode_op_oop(x.c[j], y.c[j], (long long)reps * x.r[j], x.N[j], x.r[j + 1], op, t, mult, f, s);
+  return launch_mode_op_oop(x.c[j], y.c[j], (long long)reps * x.r[j], x.N[j], x.r[j + 1], op, t, mult, f, s,
+                            (long long)x.r[j] * x.r[j + 1]);
 }
 
 int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s) {

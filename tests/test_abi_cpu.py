@@ -118,6 +118,37 @@ def test_solve_rejects_bad_workspace_before_device():
     lib.lrfg_plan_destroy(plan)
 
 
+def test_server_validation_before_device():
+    lib = _lib().lib()
+    h = C.c_void_p()
+    buf = (C.c_double * 64)()
+    # slots / batch / pool checks come before any device call
+    assert lib.lrfg_server_create(0, 0, 4, C.addressof(buf), 1 << 20, C.byref(h)) == -1
+    assert lib.lrfg_server_create(0, 17, 4, C.addressof(buf), 1 << 20, C.byref(h)) == -1
+    assert lib.lrfg_server_create(0, 2, 0, C.addressof(buf), 1 << 20, C.byref(h)) == -1
+    assert lib.lrfg_server_create(0, 2, 4, None, 1 << 20, C.byref(h)) == -1
+    assert lib.lrfg_server_create(0, 2, 4, C.addressof(buf) + 8, 1 << 20, C.byref(h)) == -1
+    n = C.c_int()
+    assert lib.lrfg_server_submit(None, None, None, None, 3, None, 0) == -1
+    assert lib.lrfg_server_poll(None, None, 0, C.byref(n), 0) == -1
+    assert lib.lrfg_server_pending(None) == 0
+    lib.lrfg_server_destroy(None)
+
+
+def test_solve_batch_validation_before_device():
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, d=2, N=(9, 9, 1))), C.byref(plan)) == 0
+    cs = (L.Coeff * 2)()
+    rs = (L.Result * 2)()
+    # count < 1
+    assert lib.lrfg_solve_batch(plan, cs, 0, None, 2, C.c_void_p(256), 1 << 30, None, rs) == -1
+    # misaligned workspace
+    assert lib.lrfg_solve_batch(plan, cs, 2, None, 2, C.c_void_p(8), 1 << 30, None, rs) == -3
+    lib.lrfg_plan_destroy(plan)
+
+
 def test_gram_cut_validation_before_device():
     lib = _lib().lib()
     buf = (C.c_double * 16)()

@@ -1,0 +1,185 @@
+"""Batched solves of several microstructures and the continuous-batching
+request loop, against single solves and the CPU oracle.
+
+Stated tolerance for "the same alone and in the mix": every kernel treats
+the systems of a batch independently and the GEMM's K splits depend on one
+matrix's shape only, so a microstructure follows the same arithmetic alone
+and in any batch; the results agree to max|A_mix - A_alone| <= 1e-12
+max|A_alone| (bit for bit in practice), with the same iteration counts.
+Full-grid batches run the microstructures one after another through the same
+kernels and must agree to 1e-13."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_1902_07455_amd as P
+import workloads as W
+from oracle import fg
+
+pytestmark = pytest.mark.gpu
+
+MIX_TOL = 1e-12
+
+
+def _rel(A, B):
+    return float(np.max(np.abs(A - B)) / np.max(np.abs(B)))
+
+
+def _smooth(N, seed, contrast):
+    return W.rescale_contrast_cp(W.smooth_cp(N, W.smooth_params(seed)), contrast)
+
+
+def test_batch_untruncated_matches_oracle(dev):
+    """Three cube inclusions of different contrast in one batch, rank cap at
+    the grid size (no truncation): each A_H equals the oracle's full-grid
+    solve to 1e-10."""
+    N = 15
+    cps = [W.cube_cp(N, c) for c in (3.0, 10.0, 30.0)]
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=N, solver_tol=1e-12, max_iter=300, coeff_rank=2,
+                 max_nE=9)
+    rs = s.solve_batch([dict(cp=(cp.weights, cp.factors)) for cp in cps])
+    for cp, r in zip(cps, rs):
+        o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
+        assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
+@pytest.mark.parametrize("nE_fields", [None, [[1.0, 0.0, 0.0], [0.3, -0.2, 0.9]]])
+def test_batch_equals_single(dev, nE_fields):
+    """Four smooth microstructures (different seeds and contrasts) batched
+    equal their single solves (truncated, cap 10)."""
+    N = 45
+    cps = [_smooth(N, seed, c) for seed, c in zip(range(4), (2.0, 5.0, 20.0, 60.0))]
+    kw = dict(d=3, N=(N,) * 3, format="tt", rank_cap=10, solver_tol=1e-6, max_iter=60, coeff_rank=9)
+    single = P.Solver(**kw)
+    alone = [single.solve(cp=(cp.weights, cp.factors), E=nE_fields) for cp in cps]
+    nE = 3 if nE_fields is None else len(nE_fields)
+    batch = P.Solver(**kw, max_nE=4 * nE)
+    mix = batch.solve_batch([dict(cp=(cp.weights, cp.factors)) for cp in cps], E=nE_fields)
+    for a, m in zip(alone, mix):
+        assert _rel(m.A_H, a.A_H) <= MIX_TOL
+        assert list(m.iters) == list(a.iters)
+        assert m.A_H.shape == (nE, nE)
+
+
+def test_batch_full_grid_equals_single(dev):
+    N = 21
+    coeffs = [W.random_positive_coeff(N, 3, seed) for seed in range(3)]
+    s = P.Solver(d=3, N=(N,) * 3, format="full", solver_tol=1e-10, max_iter=300)
+    alone = [s.solve(full=a) for a in coeffs]
+    mix = s.solve_batch([dict(full=a) for a in coeffs])
+    for a, m, c in zip(alone, mix, coeffs):
+        assert _rel(m.A_H, a.A_H) <= 1e-13
+    o = fg.solve(coeffs[1], tol=1e-12, max_iter=500)
+    assert _rel(mix[1].A_H, o.A_H) <= 1e-9
+
+
+def test_batch_rejects_unequal_ranks(dev):
+    N = 15
+    a, b = W.cube_cp(N, 5.0), _smooth(N, 0, 4.0)
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=6, solver_tol=1e-6, max_iter=20, coeff_rank=9, max_nE=6)
+    with pytest.raises(P.LrfgError):
+        s.solve_batch([dict(cp=(a.weights, a.factors)), dict(cp=(b.weights, b.factors))])
+
+
+def _requests():
+    """A mixed stream: two grids, two caps, smooth and cube coefficients."""
+    reqs = []
+    for i in range(12):
+        N = (45, 63)[i % 2]
+        cap = (8, 12)[(i // 2) % 2]
+        if i % 3 == 2:
+            cp = W.cube_cp(N, 2.0 + 3.0 * i)
+            rank = 2
+        else:
+            cp = _smooth(N, 100 + i, 2.0 + 4.0 * i)
+            rank = 9
+        prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=cap, solver_tol=1e-4, max_iter=60, coeff_rank=rank)
+        reqs.append((prob, cp))
+    return reqs
+
+
+def _alone(reqs, dev):
+    out = []
+    for prob, cp in reqs:
+        s = P.Solver(**prob)
+        out.append(s.solve(cp=(cp.weights, cp.factors)))
+        s.close()
+    return out
+
+
+def test_server_solo_vs_mix(dev):
+    """All requests submitted at once to 3 slots with batches of up to 4:
+    same A_H as each request alone, and batching really happened."""
+    import torch
+    reqs = _requests()
+    alone = _alone(reqs, dev)
+    # coefficients kept on the device, read in place by the server
+    dreqs = [(prob, torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors])
+             for prob, cp in reqs]
+    srv = P.Server(slots=3, max_batch=4, pool_bytes=2 << 30)
+    for i, (prob, w, f) in enumerate(dreqs):
+        srv.submit(prob, cp=(w, f), tag=i)
+    done = srv.drain()
+    srv.close()
+    assert sorted(c.tag for c in done) == list(range(len(reqs)))
+    for c in done:
+        assert c.status == alone[c.tag].rc
+        assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL
+        assert list(c.result.iters) == list(alone[c.tag].iters)
+    assert max(c.batch_size for c in done) > 1
+
+
+def test_server_admission_by_footprint(dev):
+    """A pool that holds one request's workspace runs one batch at a time;
+    a request larger than the pool is refused at submit."""
+    reqs = _requests()[:4]
+    prob0 = reqs[0][0]
+    s = P.Solver(**prob0)
+    one = s.workspace_bytes
+    s.close()
+    pool = max(P.Solver(**p).workspace_bytes for p, _ in reqs) + 4096
+    srv = P.Server(slots=3, max_batch=4, pool_bytes=pool)
+    t_sub = []
+    for i, (prob, cp) in enumerate(reqs):
+        t_sub.append(time.perf_counter())
+        srv.submit(prob, cp=(cp.weights, cp.factors), tag=i)
+    big = dict(prob0, N=(135,) * 3, rank_cap=20)
+    cp_big = _smooth(135, 1, 3.0)
+    with pytest.raises(P.LrfgError):
+        srv.submit(big, cp=(cp_big.weights, cp_big.factors), tag=99)
+    done = srv.drain()
+    srv.close()
+    assert len(done) == 4 and all(c.status >= 0 for c in done)
+    assert all(c.workspace_bytes <= pool for c in done)
+    assert one <= pool
+    # at every batch start, the workspaces of the batches then running fit the pool
+    iv = []
+    for c in done:
+        t0 = t_sub[c.tag] * 1e3 + c.queue_ms
+        iv.append((t0, t0 + c.run_ms, c.workspace_bytes))
+    for t0, _, _ in iv:
+        held = sum(w for a, b, w in iv if a <= t0 < b - 0.5)
+        assert held <= pool
+
+
+def test_server_arrivals_while_running(dev):
+    """Requests that arrive while others run are admitted when slots free up
+    and give the same results as alone."""
+    reqs = _requests()[:8]
+    alone = _alone(reqs, dev)
+    srv = P.Server(slots=2, max_batch=2, pool_bytes=2 << 30)
+    for i, (prob, cp) in enumerate(reqs[:3]):
+        srv.submit(prob, cp=(cp.weights, cp.factors), tag=i)
+    got = []
+    while len(got) < 1:
+        got += srv.poll(timeout_ms=5000)
+    for i, (prob, cp) in enumerate(reqs[3:], start=3):
+        srv.submit(prob, cp=(cp.weights, cp.factors), tag=i)
+        time.sleep(0.002)
+    got += srv.drain()
+    srv.close()
+    assert sorted(c.tag for c in got) == list(range(8))
+    for c in got:
+        assert c.status == alone[c.tag].rc
+        assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL

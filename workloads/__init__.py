@@ -190,6 +190,44 @@ def rescale_contrast(a: np.ndarray, contrast: float) -> np.ndarray:
     return 1.0 + (contrast - 1.0) * (a - lo) / (hi - lo)
 
 
+def rescale_contrast_cp(cp: CPCoeff, contrast: float) -> CPCoeff:
+    """rescale_contrast for a CP coefficient whose first term is a constant
+    (weights[0] times all-ones factors, as smooth_cp builds it): the affine
+    map only changes the weights, so the rank is kept.  The grid min and max
+    are taken slab by slab."""
+    d = len(cp.factors)
+    lo, hi = np.inf, -np.inf
+    for n0 in range(cp.factors[0].shape[1]):
+        sub = CPCoeff(cp.weights * cp.factors[0][:, n0], list(cp.factors[1:])) if d > 1 else None
+        v = sub.full() if sub is not None else cp.weights @ cp.factors[0][:, n0:n0 + 1]
+        lo, hi = min(lo, float(np.min(v))), max(hi, float(np.max(v)))
+    if hi - lo <= 0:
+        return CPCoeff(np.concatenate([[1.0], np.zeros(cp.rank - 1)]), [f.copy() for f in cp.factors])
+    beta = (contrast - 1.0) / (hi - lo)
+    w = beta * cp.weights
+    w[0] += 1.0 - beta * lo
+    return CPCoeff(w, [f.copy() for f in cp.factors])
+
+
+def cube_cp(N: int, contrast: float, half_side: float = 0.3, d: int = 3) -> CPCoeff:
+    """Centred cube |x_i| < half_side with a = contrast inside, 1 outside, as
+    the two separable terms 1 + (contrast - 1) chi."""
+    x = grid_points(N)
+    ind = (np.abs(x) < half_side).astype(np.float64)
+    ones = np.ones(N)
+    return CPCoeff(np.array([1.0, contrast - 1.0]), [np.stack([ones, ind]) for _ in range(d)])
+
+
+def request_coeff(req: "ServingRequest") -> CPCoeff:
+    """The CP coefficient of a serving request: the contrast-rescaled smooth
+    family (seed = request id), or for kind "ball" its separable stand-in,
+    the centred cube of half side 0.3 at the same contrast (the ball itself
+    is not separable and would need a compressed TT)."""
+    if req.kind == "smooth":
+        return rescale_contrast_cp(smooth_cp(req.N, smooth_params(req.rid)), req.contrast)
+    return cube_cp(req.N, req.contrast)
+
+
 # --------------------------------------------------------------------------
 # Random inputs for tests
 # --------------------------------------------------------------------------
