@@ -186,6 +186,89 @@ def profiled(run, tag, solves):
     return n, ms, work
 
 
+def serving_leg(nreq, nmax, capmax, dev):
+    """Request stream of mixed homogenisation queries through the
+    continuous-batching loop: saturated throughput (all queued at once),
+    then Poisson arrivals at 0.7x that rate (p50/p99 latency); and a
+    same-shape stream (16 smooth 135^3 microstructures, cap 16) solved one
+    by one vs in batches of 8.  Grids and rank caps are bounded (defaults
+    N <= 135, cap <= 20) so that the leg takes seconds; --serve-nmax 405
+    --serve-capmax 60 gives the full request distribution."""
+    import torch
+
+    import paper_1902_07455_amd as P
+    import workloads as W
+
+    def problem(req):
+        return dict(d=3, N=(req.N,) * 3, format="tt", rank_cap=req.rank_cap, solver_tol=1e-3, max_iter=200,
+                    coeff_rank=9 if req.kind == "smooth" else 2)
+
+    def coeffs(reqs):
+        out = []
+        for q in reqs:
+            cp = W.request_coeff(q)
+            out.append((torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors]))
+        return out
+
+    def run(reqs, cps, slots, max_batch, arrivals):
+        srv = P.Server(slots=slots, max_batch=max_batch, pool_bytes=32 << 30, device=dev)
+        t0 = time.perf_counter()
+        done = []
+        for i, (q, (w, f)) in enumerate(zip(reqs, cps)):
+            if arrivals:
+                wait = t0 + q.arrival_s - time.perf_counter()
+                if wait > 0:
+                    done += srv.poll(timeout_ms=int(wait * 1e3))
+                    wait = t0 + q.arrival_s - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+            srv.submit(problem(q), cp=(w, f), tag=i)
+        done += srv.drain()
+        span = time.perf_counter() - t0
+        srv.close()
+        lat = [c.total_ms for c in done]
+        return {"requests": len(done), "solves_per_s": round(len(done) / span, 3),
+                "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+                "not_converged": sum(c.status != 0 for c in done),
+                "max_batch_seen": max(c.batch_size for c in done)}
+
+    probe = W.serving_requests(nreq, 1.0, seed=0, N_lo=45, N_hi=nmax, cap_hi=capmax)
+    cps = coeffs(probe)
+    log(f"serving: {nreq} requests, saturated")
+    sat = run(probe, cps, 4, 8, arrivals=False)
+    rate = 0.7 * sat["solves_per_s"]
+    reqs = W.serving_requests(nreq, rate, seed=0, N_lo=45, N_hi=nmax, cap_hi=capmax)
+    log(f"serving: Poisson arrivals at {rate:.2f}/s")
+    poi = run(reqs, cps, 4, 8, arrivals=True)
+    poi["rate_per_s"] = round(rate, 3)
+
+    # same-shape stream: batching proper
+    N = 135
+    same = [W.ServingRequest(i, N, "smooth", 1.0, 16, 0.0) for i in range(16)]
+    sc = []
+    for q in same:
+        cp = W.smooth_cp(N, W.smooth_params(q.rid))
+        sc.append((torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors]))
+    prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=16, solver_tol=1e-2, max_iter=100, coeff_rank=9)
+    res = {}
+    for name, mb in (("one_by_one", 1), ("batches_of_8", 8)):
+        srv = P.Server(slots=1, max_batch=mb, pool_bytes=32 << 30, device=dev)
+        t0 = time.perf_counter()
+        for i, (w, f) in enumerate(sc):
+            srv.submit(prob, cp=(w, f), tag=i)
+        done = srv.drain()
+        span = time.perf_counter() - t0
+        srv.close()
+        res[name] = {"solves_per_s": round(len(done) / span, 3), "max_batch_seen": max(c.batch_size for c in done)}
+    return {"workload": f"{nreq} requests (workloads.serving_requests seed 0): N odd in [45, {nmax}], smooth "
+                        "(contrast-rescaled, CP rank 9) or the separable cube stand-in for the ball (rank 2), "
+                        f"contrast log-uniform [2, 100], TT rank cap in [10, {capmax}], solver tol 1e-3; 4 slots, "
+                        "batches up to 8, device-resident factors; latency = submit to completion",
+            "saturated": sat, "poisson": poi,
+            "same_shape_135": dict(res, workload="16 smooth 135^3 microstructures (seeds 0..15), cap 16, tol 1e-2, "
+                                                 "one slot")}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +283,10 @@ def main(argv=None):
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-cap", type=int, default=None, help="TT rank cap (skips the cap sweep)")
     ap.add_argument("--tt-tol", type=float, default=None, help="TT solver tolerance (skips the tol sweep)")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-nmax", type=int, default=135, help="largest grid of the serving requests")
+    ap.add_argument("--serve-capmax", type=int, default=20, help="largest rank cap of the serving requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -319,6 +406,10 @@ def main(argv=None):
             del w2
             torch.cuda.empty_cache()
         out["crossover"] = rows
+
+    # ------------------------------------------------------------ serving
+    if args.serve_requests > 0:
+        out["serving"] = serving_leg(args.serve_requests, args.serve_nmax, args.serve_capmax, dev)
 
     # ------------------------------------------------------------ CPU oracle baseline
     if not args.no_cpu:
