@@ -72,6 +72,13 @@ typedef enum {
   LRFG_SOLVER_MR = 1        /* minimal-residual iteration (Sec. 3.3)         */
 } lrfg_solver;
 
+/* Mixed precision (low-rank formats only): iterative refinement whose
+ * inner truncated solves run the truncation's contractions with FP32 or
+ * BF16 inputs and FP32 accumulation (inner tolerance max(solver_tol, 1e-4)
+ * for FP32, max(solver_tol, 1e-2) for BF16), while the correction update,
+ * the residual b - K x, the small factorisations of the truncation, the
+ * solver scalars and A_H stay FP64; it stops when the FP64 preconditioned
+ * residual reaches solver_tol or stops decreasing. */
 typedef enum {
   LRFG_PREC_FP64 = 0,
   LRFG_PREC_MIXED_FP32 = 1,
@@ -221,6 +228,17 @@ size_t lrfg_gemm_workspace_bytes(int m, int n, int k, int batch);
 int lrfg_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A, long long lda,
               long long sA, const double* B, long long ldb, long long sB, double beta, double* C,
               long long ldc, long long sC, int batch, void* d_ws, size_t ws_bytes, void* stream);
+
+/* lrfg_gemm with the operands rounded to FP32 (LRFG_PREC_MIXED_FP32) or
+ * BF16 (LRFG_PREC_MIXED_BF16) and the products accumulated in FP32 on MFMA
+ * (v_mfma_f32_16x16x4f32 / v_mfma_f32_16x16x32_bf16); A, B and C stay FP64
+ * in memory, split-K partial sums are added in FP64.  The core
+ * contractions of the mixed-precision low-rank solve run here.
+ * LRFG_PREC_FP64 is lrfg_gemm.  Workspace as lrfg_gemm_workspace_bytes. */
+int lrfg_gemm_mixed(int precision, int ta, int tb, int m, int n, int k, double alpha, const double* A,
+                    long long lda, long long sA, const double* B, long long ldb, long long sB,
+                    double beta, double* C, long long ldc, long long sC, int batch, void* d_ws,
+                    size_t ws_bytes, void* stream);
 
 /* Batched symmetric eigendecomposition (cyclic Jacobi), n <= 64: A is
  * batch x n x n (row-major, symmetrised as (A + A^T)/2), W receives the

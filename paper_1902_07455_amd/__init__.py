@@ -373,9 +373,10 @@ def full_op(which: int, N, a, u, out, stream=None):
     return out
 
 
-def gemm(A, B, C_, ta=False, tb=False, alpha=1.0, beta=0.0, stream=None):
+def gemm(A, B, C_, ta=False, tb=False, alpha=1.0, beta=0.0, stream=None, precision: str = "fp64"):
     """C_ = alpha op(A) op(B) + beta C_ on float64 CUDA tensors of shape
-    (batch, rows, cols) (contiguous); returns C_."""
+    (batch, rows, cols) (contiguous); returns C_.  precision "fp32" / "bf16":
+    operands rounded to that type, FP32 accumulation (lrfg_gemm_mixed)."""
     L = lib()
     bt = C_.shape[0]
     m, n = C_.shape[1], C_.shape[2]
@@ -383,10 +384,10 @@ def gemm(A, B, C_, ta=False, tb=False, alpha=1.0, beta=0.0, stream=None):
     ws = _ws_tensor(L.lrfg_gemm_workspace_bytes(m, n, k, bt), C_.device)
     sA = A.shape[1] * A.shape[2] if A.shape[0] > 1 else 0
     sB = B.shape[1] * B.shape[2] if B.shape[0] > 1 else 0
-    check(L.lrfg_gemm(int(ta), int(tb), m, n, k, float(alpha), C.c_void_p(A.data_ptr()), A.shape[2], sA,
-                      C.c_void_p(B.data_ptr()), B.shape[2], sB, float(beta), C.c_void_p(C_.data_ptr()),
-                      n, m * n, bt, C.c_void_p(ws.data_ptr()), ws.numel(),
-                      C.c_void_p(_stream_handle(stream))))
+    check(L.lrfg_gemm_mixed(_PRECS[precision], int(ta), int(tb), m, n, k, float(alpha), C.c_void_p(A.data_ptr()),
+                            A.shape[2], sA, C.c_void_p(B.data_ptr()), B.shape[2], sB, float(beta),
+                            C.c_void_p(C_.data_ptr()), n, m * n, bt, C.c_void_p(ws.data_ptr()), ws.numel(),
+                            C.c_void_p(_stream_handle(stream))))
     return C_
 
 

@@ -90,7 +90,7 @@ EXPORTS = [
     "lrfg_server_poll", "lrfg_server_pending", "lrfg_server_destroy", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
-    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_syevj", "lrfg_gram_cut", "lrfg_tt_round_workspace_bytes",
+    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_gemm_mixed", "lrfg_syevj", "lrfg_gram_cut", "lrfg_tt_round_workspace_bytes",
     "lrfg_tt_round",
 ]
 
@@ -156,6 +156,8 @@ def lib():
                             C.c_longlong, C.c_double, C.c_void_p, C.c_longlong, C.c_longlong,
                             C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
     L.lrfg_gemm.restype = C.c_int
+    L.lrfg_gemm_mixed.argtypes = [C.c_int] + L.lrfg_gemm.argtypes
+    L.lrfg_gemm_mixed.restype = C.c_int
     L.lrfg_syevj.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     L.lrfg_syevj.restype = C.c_int
     L.lrfg_gram_cut.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,

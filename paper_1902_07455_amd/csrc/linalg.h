@@ -21,6 +21,7 @@ struct Gemm {
   long long ldc = 0, sC = 0;
   double alpha = 1.0, beta = 0.0;
   int batch = 1;
+  int prec = 0;  // lrfg_precision: FP64, or FP32 / BF16 inputs with FP32 accumulation
 };
 
 // Scratch doubles gemm() may use for a split-K reduction of this shape.

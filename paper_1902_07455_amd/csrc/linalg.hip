@@ -1,5 +1,7 @@
-// FP64 batched GEMM on MFMA (v_mfma_f64_16x16x4f64) and a batched cyclic
-// Jacobi eigensolver for small symmetric matrices.
+// Batched GEMM on MFMA (FP64 v_mfma_f64_16x16x4f64; FP32 and BF16 inputs
+// with FP32 accumulation for the mixed-precision solve), the small dense
+// factorisations of the truncation (pivoted Cholesky, one-sided Jacobi)
+// and a batched cyclic Jacobi eigensolver.
 #include <algorithm>
 #include <cmath>
 
@@ -107,6 +109,130 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
         const int col = n0 + wn * 32 + bj * 16 + (lane & 15);
         if (row < m && col < n) {
           const double v = acc[bi][bj][r];
+          if (part != nullptr) {
+            part[((long long)bz * m + row) * n + col] = v;
+          } else {
+            double* c = C + bt * sC + (long long)row * ldc + col;
+            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+          }
+        }
+      }
+}
+
+// Reduced-precision variant for the mixed-precision solve: FP64 operands
+// in memory, rounded to FP32 (BF = false) or BF16 (BF = true) when staged,
+// products accumulated in FP32 on MFMA, the sum stored as FP64.  Tile
+// 64 x 64 x 32 per 256-thread block, waves as in k_gemm.  Lane layouts
+// (checked on gfx950): v_mfma_f32_16x16x4f32 takes A[l % 16][l / 16] and
+// B[l / 16][l % 16]; v_mfma_f32_16x16x32_bf16 takes A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16], j < 8; both return D[4 (l / 16) + i][l % 16].
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int LK = 32;
+
+template <bool TA, bool TB, bool BF>
+__global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const double* __restrict__ A, long long lda,
+                                                 long long sA, const double* __restrict__ B, long long ldb,
+                                                 long long sB, double* __restrict__ C, long long ldc, long long sC,
+                                                 double alpha, double beta, int ksplit, int kchunk,
+                                                 double* __restrict__ part) {
+  __shared__ float As[LK][BM + 1];
+  __shared__ float Bs[LK][BN + 1];
+  const int bz = blockIdx.z;
+  const int bt = bz / ksplit;
+  const int ks = bz - bt * ksplit;
+  A += bt * sA;
+  B += bt * sB;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kb = ks * kchunk;
+  const int ke = min(k, kb + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  constexpr int RA = (BM * LK) / 256, RB = (LK * BN) / 256;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+  float pa[RA], pb[RB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / LK; kk = e % LK; } else { kk = e / BM; i = e % BM; }
+      const int gi = m0 + i, gk = k0 + kk;
+      pa[r] = (gi < m && gk < ke) ? (float)(TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk]) : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / LK; kk = e % LK; }
+      const int gk = k0 + kk, gj = n0 + j;
+      pb[r] = (gj < n && gk < ke) ? (float)(TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.f;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += LK) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / LK; kk = e % LK; } else { kk = e / BM; i = e % BM; }
+      As[kk][i] = pa[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / LK; kk = e % LK; }
+      Bs[kk][j] = pb[r];
+    }
+    __syncthreads();
+    if (k0 + LK < ke) fetch(k0 + LK);
+    if (BF) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[bi][j] = (__bf16)As[8 * (lane >> 4) + j][wm * 32 + bi * 16 + (lane & 15)];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[bj][j] = (__bf16)Bs[8 * (lane >> 4) + j][wn * 32 + bj * 16 + (lane & 15)];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < LK; kk += 4) {
+        float a[2], b[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) a[bi] = As[kk + (lane >> 4)][wm * 32 + bi * 16 + (lane & 15)];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[kk + (lane >> 4)][wn * 32 + bj * 16 + (lane & 15)];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + bi * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 32 + bj * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const double v = (double)acc[bi][bj][r];
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
@@ -721,7 +847,8 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     if ((size_t)ks > fit) ks = (int)fit;
     if (ks < 2) ks = 1;
   }
-  const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + BK - 1) / BK * BK : (g.k > 0 ? g.k : 1);
+  const int KQ = g.prec != 0 ? LK : BK;  // K tile of the kernel used
+  const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + KQ - 1) / KQ * KQ : (g.k > 0 ? g.k : 1);
   // (a multiple of BK is one of SK too)
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
   // matrices per launch: all of them, or as many as the split partials fit
@@ -741,7 +868,15 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     dim3 grid(ceil_div(c.n, sm ? SM : BN), ceil_div(c.m, sm ? SM : BM), c.batch * ks);
 #define LRFG_GEMM_LAUNCH(TA, TB)                                                                              \
   do {                                                                                                       \
-    if (sm)                                                                                                  \
+    if (c.prec == LRFG_PREC_MIXED_FP32)                                                                      \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, false>), grid,   \
+                        dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
+                        c.alpha, c.beta, ks, kchunk, part);                                                  \
+    else if (c.prec == LRFG_PREC_MIXED_BF16)                                                                 \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, true>), grid,    \
+                        dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
+                        c.alpha, c.beta, ks, kchunk, part);                                                  \
+    else if (sm)                                                                                             \
       hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, \
                          c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, kchunk, part);                            \
     else                                                                                                     \

@@ -98,6 +98,40 @@ int lrfg_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A
   return gemm(g, static_cast<double*>(d_ws), ws_bytes / sizeof(double), static_cast<hipStream_t>(stream));
 }
 
+int lrfg_gemm_mixed(int precision, int ta, int tb, int m, int n, int k, double alpha, const double* A, long long lda,
+                    long long sA, const double* B, long long ldb, long long sB, double beta, double* C,
+                    long long ldc, long long sC, int batch, void* d_ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (precision != LRFG_PREC_FP64 && precision != LRFG_PREC_MIXED_FP32 && precision != LRFG_PREC_MIXED_BF16) {
+    set_error("unknown precision %d", precision);
+    return LRFG_EINVAL;
+  }
+  if (m < 0 || n < 0 || k < 0 || batch < 0 || (m * n > 0 && (A == nullptr || B == nullptr || C == nullptr))) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  Gemm g;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.A = A;
+  g.lda = lda;
+  g.sA = sA;
+  g.ta = ta != 0;
+  g.B = B;
+  g.ldb = ldb;
+  g.sB = sB;
+  g.tb = tb != 0;
+  g.C = C;
+  g.ldc = ldc;
+  g.sC = sC;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.batch = batch;
+  g.prec = precision;
+  return gemm(g, static_cast<double*>(d_ws), ws_bytes / sizeof(double), static_cast<hipStream_t>(stream));
+}
+
 int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* stream) {
   clear_error();
   if (A == nullptr || W == nullptr || V == nullptr || batch < 0) {

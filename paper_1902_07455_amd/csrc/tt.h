@@ -39,6 +39,10 @@ struct Rounder {
   int Rmax[2] = {1, 1};     // largest input ranks at bonds 1, 2
   int Lmax[2] = {1, 1};     // largest sketch sizes
   int oversample = 10;
+  int prec = 0;             // lrfg_precision of the sketch and projection
+                            // contractions; the orthonormalisation, the
+                            // Gram matrices of the cut and the small
+                            // factorisations are always FP64
   uint64_t seed = 0;
   uint64_t counter = 0;
   double* om[3] = {};       // sketch cores

@@ -336,6 +336,12 @@ void Rounder::carve(Arena& ar) {
 
 namespace {
 
+// The truncation's contractions run in the Rounder's precision.
+inline Gemm& prec_of(Gemm& g, int prec) {
+  g.prec = prec;
+  return g;
+}
+
 struct GemmB {
   Gemm g;
   GemmB(int m, int n, int k, int batch) {
@@ -379,11 +385,11 @@ static int orth(Rounder& R, const double* Y, double* Q, int m, int l, int batch,
   for (int pass = 0; pass < 2; ++pass) {
     GemmB gg(l, l, m, batch);
     gg.a(src, l, (long long)m * l, true).b(src, l, (long long)m * l).c(R.G, l, (long long)l * l);
-    LRFG_TRY(gemm(gg.g, R.gscr, R.gscr_n, s));
+    LRFG_TRY(gemm(prec_of(gg.g, LRFG_PREC_FP64), R.gscr, R.gscr_n, s));
     LRFG_TRY(pchol_s(l, R.G, (long long)l * l, tau, R.S, (long long)l * l, nullptr, batch, s));
     GemmB gq(m, l, l, batch);
     gq.a(src, l, (long long)m * l).b(R.S, l, (long long)l * l).c(dsts[pass], l, (long long)m * l);
-    LRFG_TRY(gemm(gq.g, R.gscr, R.gscr_n, s));
+    LRFG_TRY(gemm(prec_of(gq.g, LRFG_PREC_FP64), R.gscr, R.gscr_n, s));
     src = dsts[pass];
   }
   return LRFG_OK;
@@ -426,60 +432,60 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     LRFG_LAUNCHED();
     // W3 = X3 Om3^T (R2 x l2)
     { GemmB g(R2, l2, N3, nE); g.a(in.c[2], N3, in.s[2]).b(om[2], N3, 0, true).c(W3, l2, (long long)R2 * l2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // T2 = X2 W3 ((R1 N2) x l2)
     { GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // W2 = T2 Om2^T (R1 x l1), contraction over (n, l2)
     { GemmB g(R1, l1, N2 * l2, nE); g.a(T2, (long long)N2 * l2, (long long)R1 * N2 * l2).b(om[1], (long long)N2 * l2, 0, true)
           .c(W2, l1, (long long)R1 * l1);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // Y1 = X1 W2 (N1 x l1) ; Q1 = orth(Y1)
     { GemmB g(N1, l1, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l1, (long long)R1 * l1).c(Y1, l1, (long long)N1 * l1);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     LRFG_TRY(orth(*this, Y1, Q1, N1, l1, nE, s));
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     { GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
           .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // Y2 = X2' W3 ((l1 N2) x l2) ; Q2 = orth(Y2)
     { GemmB g(l1 * N2, l2, R2, nE); g.a(X2p, R2, (long long)l1 * N2 * R2).b(W3, l2, (long long)R2 * l2)
           .c(Y2, l2, (long long)l1 * N2 * l2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     LRFG_TRY(orth(*this, Y2, Q2, l1 * N2, l2, nE, s));
     // M2 = Q2^T X2' (l2 x R2) ; X3' = M2 X3 (l2 x N3)
     { GemmB g(l2, R2, l1 * N2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2, true).b(X2p, R2, (long long)l1 * N2 * R2)
           .c(M2, R2, (long long)l2 * R2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     { GemmB g(l2, N3, R2, nE); g.a(M2, R2, (long long)l2 * R2).b(in.c[2], N3, in.s[2]).c(X3p, N3, (long long)l2 * N3);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // ---- cut at bond 2: G = X3' X3'^T, S3 = kept eigenvectors (l2 x c2)
     { GemmB g(l2, l2, N3, nE); g.a(X3p, N3, (long long)l2 * N3).b(X3p, N3, (long long)l2 * N3, true).c(G, l2, (long long)l2 * l2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     LRFG_TRY(trunc_mask(*this, G, l2, c2, tol2, S3, kept + this->nE, nE, s));
     { GemmB g(c2, N3, l2, nE); g.a(S3, c2, (long long)l2 * c2, true).b(X3p, N3, (long long)l2 * N3).c(out.c[2], N3, out.s[2]);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // Q2s = Q2 S3 ((l1 N2) x c2); P = X3 X3^T (c2 x c2); U = Q2s P
     { GemmB g(l1 * N2, c2, l2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2).b(S3, c2, (long long)l2 * c2)
           .c(Q2s, c2, (long long)l1 * N2 * c2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     { GemmB g(c2, c2, N3, nE); g.a(out.c[2], N3, out.s[2]).b(out.c[2], N3, out.s[2], true).c(P, c2, (long long)c2 * c2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     { GemmB g(l1 * N2, c2, c2, nE); g.a(Q2s, c2, (long long)l1 * N2 * c2).b(P, c2, (long long)c2 * c2)
           .c(U, c2, (long long)l1 * N2 * c2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     // ---- cut at bond 1: G1 = U Q2s^T over (n, b) (l1 x l1)
     { GemmB g(l1, l1, N2 * c2, nE); g.a(U, (long long)N2 * c2, (long long)l1 * N2 * c2)
           .b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2, true).c(G, l1, (long long)l1 * l1);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     LRFG_TRY(trunc_mask(*this, G, l1, c1, tol2, S1, kept, nE, s));
     { GemmB g(N1, c1, l1, nE); g.a(Q1, l1, (long long)N1 * l1).b(S1, c1, (long long)l1 * c1).c(out.c[0], c1, out.s[0]);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     { GemmB g(c1, N2 * c2, l1, nE); g.a(S1, c1, (long long)l1 * c1, true).b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2)
           .c(out.c[1], (long long)N2 * c2, out.s[1]);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
     return LRFG_OK;
   }
   // d = 2
@@ -497,21 +503,21 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
   hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l * N2)), dim3(kB), 0, s, om[2], (long long)l * N2, key);
   LRFG_LAUNCHED();
   { GemmB g(R1, l, N2, nE); g.a(in.c[1], N2, in.s[1]).b(om[2], N2, 0, true).c(W2, l, (long long)R1 * l);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   { GemmB g(N1, l, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l, (long long)R1 * l).c(Y1, l, (long long)N1 * l);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   LRFG_TRY(orth(*this, Y1, Q1, N1, l, nE, s));
   { GemmB g(l, R1, N1, nE); g.a(Q1, l, (long long)N1 * l, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l * R1);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   { GemmB g(l, N2, R1, nE); g.a(M1, R1, (long long)l * R1).b(in.c[1], N2, in.s[1]).c(X3p, N2, (long long)l * N2);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   { GemmB g(l, l, N2, nE); g.a(X3p, N2, (long long)l * N2).b(X3p, N2, (long long)l * N2, true).c(G, l, (long long)l * l);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
   LRFG_TRY(trunc_mask(*this, G, l, c1, tol * tol, S1, kept, nE, s));
   { GemmB g(c1, N2, l, nE); g.a(S1, c1, (long long)l * c1, true).b(X3p, N2, (long long)l * N2).c(out.c[1], N2, out.s[1]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   { GemmB g(N1, c1, l, nE); g.a(Q1, l, (long long)N1 * l).b(S1, c1, (long long)l * c1).c(out.c[0], c1, out.s[0]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   return LRFG_OK;
 }
 

@@ -120,3 +120,42 @@ def test_gram_cut_tolerance_and_zero(dev):
     want = int(np.argmax(tail <= tol * tol * np.sum(lam)))
     assert kept[0] == want
     assert kept[1] == 0 and float(torch.max(torch.abs(S[1]))) == 0.0
+
+
+def _round_f32(x):
+    return x.astype(np.float32).astype(np.float64)
+
+
+def _round_bf16(x):
+    """FP64 -> FP32 (nearest) -> BF16 (nearest even), as the kernel stages it."""
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (64, 64, 32), (65, 63, 33), (100, 30, 4050), (2430, 30, 180),
+                                   (30, 30, 24300), (7, 200, 1)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_gemm_mixed(dev, m, n, k, ta, tb, prec):
+    """Reduced-precision MFMA GEMM against numpy on operands rounded the same
+    way; the FP32 accumulation error bound is k u32 sum|a||b| (u32 = 2^-24)."""
+    import torch
+    rng = np.random.default_rng(m + 3 * n + 7 * k + 11 * ta + 13 * tb + len(prec))
+    batch = 2
+    A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    C0 = rng.standard_normal((batch, m, n))
+    tA, tB, tC = (torch.from_numpy(x).to(dev) for x in (A, B, C0))
+    P.gemm(tA, tB, tC, ta=bool(ta), tb=bool(tb), alpha=0.5, beta=2.0, precision=prec)
+    torch.cuda.synchronize()
+    rnd = _round_f32 if prec == "fp32" else _round_bf16
+    opA = rnd(np.swapaxes(A, 1, 2) if ta else A)
+    opB = rnd(np.swapaxes(B, 1, 2) if tb else B)
+    ref = 0.5 * opA @ opB + 2.0 * C0
+    bound = 0.5 * (k + 2) * 2.0 ** -24 * (np.abs(opA) @ np.abs(opB)) + 1e-15 * np.abs(ref)
+    assert np.all(np.abs(tC.cpu().numpy() - ref) <= bound)
+    # and the rounding really happened (BF16 differs from FP64 visibly)
+    if prec == "bf16" and k >= 32:
+        exact = 0.5 * (np.swapaxes(A, 1, 2) if ta else A) @ (np.swapaxes(B, 1, 2) if tb else B) + 2.0 * C0
+        assert np.max(np.abs(tC.cpu().numpy() - exact)) > 1e-6

@@ -86,3 +86,41 @@ def test_smooth_135_rank20(dev):
     assert err <= 1e-4
     D = r.A_H - o.A_H
     assert np.min(np.linalg.eigvalsh(0.5 * (D + D.T))) >= -1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_refinement(dev, prec):
+    """Mixed-precision TT solve (FP32 / BF16 contractions, FP64 refinement)
+    of the smooth 3D workload at N = 45, cap 16: the A_H error per entry
+    against the FP64 oracle is within 1e-6 of max|A_H| (the config-4 bar).
+    The FP64 residual of the truncated operator has a floor set by the rank
+    cap; the refinement runs at least one outer step and its best residual
+    is below the first one's."""
+    N = 45
+    cp = W.smooth_cp(N, W.smooth_params(0))
+    o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=16, solver_tol=1e-5, max_iter=60, coeff_rank=9,
+                 precision=prec)
+    r = s.solve(cp=_cp_args(cp))
+    err = np.abs(r.A_H - o.A_H) / np.max(np.abs(o.A_H))
+    assert np.max(err) <= 1e-6, err
+    for e in range(3):
+        hist = r.res_hist[e][r.res_hist[e] > 0]
+        assert hist.size >= 1 and np.min(hist) <= hist[0]
+    # and agrees with the FP64 solve of the same problem to the same bar
+    r64 = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=16, solver_tol=1e-5, max_iter=60,
+                   coeff_rank=9).solve(cp=_cp_args(cp))
+    assert _rel(r.A_H, r64.A_H) <= 1e-6
+
+
+def test_mixed_precision_untruncated_exact(dev):
+    """Without truncation the refined solve reaches the FP64 oracle's A_H to
+    1e-10 even with BF16 contractions inside (the 2D N = 45 square)."""
+    N = 45
+    cp = W.square_cp(N, 2)
+    o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
+    s = P.Solver(d=2, N=(N, N), format="tt", rank_cap=N, solver_tol=1e-11, max_iter=200, coeff_rank=2,
+                 precision="bf16")
+    r = s.solve(cp=_cp_args(cp))
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+    assert r.rc == 0
