@@ -107,6 +107,12 @@ class Workload:
         return s.solve(cp=(self.w, self.f))
 
 
+def P_solver_tt(wl, cap, tol, precision):
+    import paper_1902_07455_amd as P
+    return P.Solver(d=3, N=(wl.N,) * 3, format="tt", rank_cap=cap, trunc_tol=0.0, solver_tol=tol, max_iter=100,
+                    coeff_rank=wl.cp.rank, precision=precision, device=wl.dev)
+
+
 def reference(wl):
     s = wl.full_solver(1e-12)
     A = wl.run_full(s).A_H
@@ -378,6 +384,41 @@ def main(argv=None):
         "tt_over_full": round(value / full["solves_per_s"], 4),
         "roofline": roofline,
     }
+
+    # ------------------------------------------------------------ mixed precision (same workload)
+    mixed = {}
+    for prec, peak in (("fp32", 157.3), ("bf16", 2500.0)):
+        mtol, msweep = None, []
+        for tol in [ttol, 1e-3, 1e-4, 1e-5, 1e-6]:
+            if tol > ttol:
+                continue
+            ms = P_solver_tt(wl, cap, tol, prec)
+            r = wl.run_tt(ms)
+            ms.close()
+            e = rel_err(r.A_H, A_ref)
+            msweep.append([tol, e])
+            if e <= TARGET_ERR:
+                mtol = tol
+                break
+        if mtol is None:
+            mixed[prec] = {"solves_per_s": None, "sweep": msweep}
+            continue
+        ms = P_solver_tt(wl, cap, mtol, prec)
+        nmix = max(3, args.steps // 5)
+        msec, mlat, mr = timed(lambda: wl.run_tt(ms), nmix, 1)
+        nl, kms, flops = profiled(lambda: wl.run_tt(ms), "gemm", 2)
+        ms.close()
+        per_entry = (np.abs(mr.A_H - A_ref) / np.max(np.abs(A_ref))).round(10).tolist()
+        mixed[prec] = {"solves_per_s": round(nmix / msec, 3), "ms_per_solve": round(1e3 * msec / nmix, 3),
+                       "solver_tol": mtol, "sweep": msweep,
+                       "A_H_rel_err_per_entry": per_entry, "A_H_rel_err": rel_err(mr.A_H, A_ref),
+                       "status": mr.status.tolist(), "inner_iters": mr.iters.tolist(),
+                       "gemm_tflops": round(flops / (kms / 1e3) / 1e12, 4) if kms > 0 else None,
+                       "gemm_peak_tflops": peak}
+    out["mixed_precision"] = dict(mixed, note="rank cap of the FP64 TT leg, loosest solver tol reaching the "
+                                              "1e-6 target; contractions of the truncation in FP32/BF16 with "
+                                              "FP32 accumulation inside FP64 iterative refinement; errors per "
+                                              "A_H entry against the FP64 1e-12 reference, normwise")
 
     # ------------------------------------------------------------ crossover
     if not args.no_crossover and args.crossover:
