@@ -280,6 +280,24 @@ int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cor
                   double tol, int oversample, uint64_t seed, double* const* out_cores,
                   int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Coefficient compression (setup of the low-rank path, Sec. 3.1.3 and
+ * Appendix A.3): the full field a (device, N1 x ... x Nd, C order) as a
+ * tensor train with ranks at most cap, the fewest directions whose dropped
+ * singular values satisfy ||dropped||^2 <= tol^2 ||a||^2 / (d-1) (tol = 0:
+ * cap only).  The field enters as the exact train (I, a, I) of ranks
+ * (1, N1, N3, 1) (d = 2: (1, N1, 1)) and goes through the same randomised
+ * TT rounding as lrfg_tt_round (sketch ranks cap + oversample <= 64).
+ * out_cores[j] (device) receive [c_{j-1}][N_j][c_j] with the nominal ranks
+ * c (written to out_ranks, host, d+1 ints; directions beyond the kept rank
+ * are zero); kept (host, d-1 ints, or NULL) the kept ranks.  The TT solve
+ * takes the cores as its coefficient (tt_ranks = out_ranks); the full-grid
+ * solve of the same coefficient takes them too (it expands them), so both
+ * solve for the compressed field. */
+size_t lrfg_compress_workspace_bytes(int d, const int N[3], int cap, int oversample);
+int lrfg_compress_tt(int d, const int N[3], const double* a, int cap, double tol, int oversample,
+                     uint64_t seed, double* const* out_cores, int* out_ranks, int* kept, void* d_ws,
+                     size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching on one device.
  * `slots` worker threads (each with its own HIP stream at the default

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
+           "gemm", "syevj", "gram_cut", "compress_tt", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
            "Completion"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
@@ -417,6 +417,35 @@ def gram_cut(G, c: int, tol: float = 0.0, stream=None):
                               C.c_void_p(kept.data_ptr()), C.c_void_p(sweeps.data_ptr()),
                               C.c_void_p(_stream_handle(stream))))
     return S, kept, sweeps
+
+
+def compress_tt(a, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):
+    """Full field a (float64 CUDA tensor, 2 or 3 dims) -> (TT cores
+    [r_{j-1}][N_j][r_j] as CUDA tensors with the nominal ranks, kept ranks)."""
+    torch = _torch()
+    L = lib()
+    d = a.dim()
+    Ns = list(a.shape) + [1] * (3 - d)
+    Nc = (C.c_int * 3)(*Ns)
+    nb = L.lrfg_compress_workspace_bytes(d, Nc, int(cap), int(oversample))
+    if nb == 0:
+        raise LrfgError(-1, "bad compression sizes")
+    ws = _ws_tensor(nb, a.device)
+    c = [1] * 4
+    if d == 3:
+        c[1] = min(cap, Ns[0], Ns[1] * Ns[2])
+        c[2] = min(cap, Ns[2], Ns[0] * Ns[1])
+    else:
+        c[1] = min(cap, Ns[0], Ns[1])
+    outs = [torch.empty((c[j], Ns[j], c[j + 1]), dtype=torch.float64, device=a.device) for j in range(d)]
+    optr = (C.c_void_p * 3)(*([o.data_ptr() for o in outs] + [0] * (3 - d)))
+    ranks = (C.c_int * 4)()
+    kept = (C.c_int * 2)()
+    a = a.contiguous()
+    check(L.lrfg_compress_tt(d, Nc, C.c_void_p(a.data_ptr()), int(cap), float(tol), int(oversample), int(seed),
+                             optr, ranks, kept, C.c_void_p(ws.data_ptr()), ws.numel(),
+                             C.c_void_p(_stream_handle(stream))))
+    return outs, [int(kept[j]) for j in range(d - 1)]
 
 
 def tt_round(cores, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):

@@ -161,6 +161,104 @@ size_t lrfg_tt_round_workspace_bytes(int d, const int N[3], const int rin[4], in
   return ar.used + 256;
 }
 
+}  // extern "C"
+
+namespace lrfg {
+namespace {
+
+// n x n identity (row-major)
+__global__ void k_identity(double* __restrict__ p, int n) {
+  const long long tot = (long long)n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x)
+    p[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+// A full field as an exact train: identity carriage, the field, identity
+// carriage (d = 3: ranks 1, N1, N3, 1; d = 2: 1, N1, 1).
+void full_as_tt_ranks(int d, const int N[3], int rin[4]) {
+  rin[0] = 1;
+  rin[1] = N[0];
+  rin[2] = d == 3 ? N[2] : 1;
+  rin[3] = 1;
+  if (d == 2) rin[2] = 1;
+}
+
+}  // namespace
+}  // namespace lrfg
+
+extern "C" {
+
+size_t lrfg_compress_workspace_bytes(int d, const int N[3], int cap, int oversample) {
+  using namespace lrfg;
+  if (N == nullptr || (d != 2 && d != 3)) return 0;
+  int rin[4];
+  full_as_tt_ranks(d, N, rin);
+  Rounder R;
+  int c[4];
+  if (tt_round_sizes(d, N, rin, cap, oversample, c, R, 1) != LRFG_OK) return 0;
+  Arena ar;
+  R.carve(ar);
+  ar.take<double>((size_t)N[0] * N[0]);
+  if (d == 3) ar.take<double>((size_t)N[2] * N[2]);
+  return ar.used + 256;
+}
+
+int lrfg_compress_tt(int d, const int N[3], const double* a, int cap, double tol, int oversample, uint64_t seed,
+                     double* const* out_cores, int* out_ranks, int* kept, void* d_ws, size_t ws_bytes,
+                     void* stream) {
+  using namespace lrfg;
+  clear_error();
+  if (N == nullptr || a == nullptr || out_cores == nullptr || !(tol >= 0.0) || (d != 2 && d != 3)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  int rin[4];
+  full_as_tt_ranks(d, N, rin);
+  Rounder R;
+  int c[4];
+  LRFG_TRY(tt_round_sizes(d, N, rin, cap, oversample, c, R, 1));
+  R.seed = seed;
+  Arena ar;
+  ar.base = static_cast<char*>(d_ws);
+  ar.cap = ws_bytes;
+  R.carve(ar);
+  double* id0 = ar.take<double>((size_t)N[0] * N[0]);
+  double* id2 = d == 3 ? ar.take<double>((size_t)N[2] * N[2]) : nullptr;
+  if (ar.overflow || d_ws == nullptr) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_identity, dim3(std::min(4096, (N[0] * N[0] + 255) / 256)), dim3(256), 0, s, id0, N[0]);
+  if (d == 3)
+    hipLaunchKernelGGL(k_identity, dim3(std::min(4096, (N[2] * N[2] + 255) / 256)), dim3(256), 0, s, id2, N[2]);
+  LRFG_LAUNCHED();
+  TTB in, out;
+  in.d = out.d = d;
+  for (int j = 0; j < 3; ++j) in.N[j] = out.N[j] = j < d ? N[j] : 1;
+  for (int j = 0; j <= d; ++j) {
+    in.r[j] = rin[j];
+    out.r[j] = c[j];
+  }
+  in.c[0] = id0;
+  in.c[1] = const_cast<double*>(a);
+  if (d == 3) in.c[2] = id2;
+  for (int j = 0; j < d; ++j) {
+    in.s[j] = in.size(j);
+    out.c[j] = out_cores[j];
+    out.s[j] = out.size(j);
+  }
+  LRFG_TRY(R.round(in, out, tol, s));
+  if (out_ranks)
+    for (int j = 0; j <= d; ++j) out_ranks[j] = c[j];
+  if (kept) {
+    LRFG_HIP(hipMemcpyAsync(kept, R.kept, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (d == 3) LRFG_HIP(hipMemcpyAsync(kept + 1, R.kept + R.nE, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+  }
+  return LRFG_OK;
+}
+
 int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cores, int cap, double tol,
                   int oversample, uint64_t seed, double* const* out_cores, int* out_ranks, int* kept, int nE,
                   void* d_ws, size_t ws_bytes, void* stream) {

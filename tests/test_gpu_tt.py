@@ -86,3 +86,42 @@ def test_zero_train(dev):
     outs, kept = P.tt_round(cores, cap=3)
     assert all(float(torch.max(torch.abs(G))) == 0.0 for G in outs)
     assert list(kept[:, 0]) == [0, 0]
+
+
+def test_compress_exact_low_rank(dev):
+    """The smooth coefficient (CP rank 9, so TT ranks <= 9) compressed from
+    its full field at cap 20, tol 0: reproduced to rounding, kept ranks equal
+    the numerical ranks of the unfoldings."""
+    import torch
+    import workloads as W
+    from oracle import lowrank as LR
+    N = 45
+    a = W.smooth_cp(N, W.smooth_params(0)).full()
+    cores, kept = P.compress_tt(torch.from_numpy(a).to(dev), cap=20, tol=0.0, seed=1)
+    torch.cuda.synchronize()
+    got = LR.tt_full([G.cpu().numpy() for G in cores])
+    assert np.max(np.abs(got - a)) <= 1e-11 * np.max(np.abs(a))
+    ref_ranks = LR.tt_ranks(LR.tt_svd(a, tol=1e-13))[1:3]
+    assert kept == ref_ranks
+
+
+@pytest.mark.parametrize("cap,tol", [(12, 0.0), (16, 0.0), (40, 1e-3)])
+def test_compress_ball_near_optimal(dev, cap, tol):
+    """Ball inclusion (not separable; TT ranks grow with N): the compressed
+    train is within 1.5x the error of the oracle's deterministic TT-SVD at the
+    same kept ranks, and respects the tolerance when the cap is not binding."""
+    import torch
+    import workloads as W
+    from oracle import lowrank as LR
+    N = 63
+    a = W.ball_coeff(N)
+    cores, kept = P.compress_tt(torch.from_numpy(a).to(dev), cap=cap, tol=tol, seed=2)
+    torch.cuda.synchronize()
+    got = LR.tt_full([G.cpu().numpy() for G in cores])
+    err = np.linalg.norm(got - a)
+    # the oracle's TT-SVD at the same rank (the ball is symmetric: equal kept ranks)
+    assert kept[0] == kept[1]
+    err_opt = np.linalg.norm(LR.tt_full(LR.tt_svd(a, rank_cap=kept[0])) - a)
+    assert err <= 1.5 * err_opt + 1e-12 * np.linalg.norm(a)
+    if tol > 0 and max(kept) < cap:
+        assert err <= tol * np.linalg.norm(a) * (1 + 1e-6)
