@@ -45,7 +45,7 @@ N_MAIN = 135
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FULL_TOLS = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6, 1e-7, 1e-8]
-TT_CAPS = [4, 6, 8, 10, 12, 16, 20, 24, 32]
+TT_CAPS = [4, 6, 8, 10, 12, 14, 16, 20, 24, 32]
 TT_TOLS = [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-8]
 
 

@@ -610,6 +610,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   std::vector<double> hist((size_t)nE * maxit, 0.0);
   std::vector<int> iters(nE, 0), status(nE, LRFG_OK);
   const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  // kept ranks of the latest x truncation (bond 1 then bond 2, per system),
+  // copied with the residual read, and those of each system's kept iterate
+  std::vector<int> kx(2 * nE, 0), kbest(2 * nE, 0);
+  auto fetch_kept = [&]() -> int {
+    LRFG_HIP(hipMemcpyAsync(kx.data(), C.rd.kept, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipMemcpyAsync(kx.data() + nE, C.rd.kept + C.rd.nE, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+    return LRFG_OK;
+  };
   auto upload_done = [&](const std::vector<int>& hd) -> int {
     LRFG_HIP(hipMemcpyAsync(C.done, hd.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
     return LRFG_OK;
@@ -658,6 +666,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
         LRFG_LAUNCHED();
         LRFG_TRY(update_xr(C));   // x += alpha p ; r -= alpha q
+        LRFG_TRY(fetch_kept());
         LRFG_TRY(apply_P(C, C.r, C.z));
         LRFG_TRY(dot(C, C.r, C.z, C.dots));
         LRFG_TRY(dot(C, C.z, C.z, C.zz));
@@ -680,6 +689,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         LRFG_TRY(tt_copy(C.r, C.p, nE, s));
         LRFG_TRY(tt_copy(C.z, C.q, nE, s));
         LRFG_TRY(update_xr(C));
+        LRFG_TRY(fetch_kept());
         LRFG_TRY(dot(C, C.r, C.r, C.zz));
       }
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
@@ -693,6 +703,10 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
           best[e] = res;
           since_best[e] = 0;
           LRFG_TRY(copy_system(C, C.x, C.xb, e));
+          if (record) {
+            kbest[e] = kx[e];
+            kbest[nE + e] = kx[nE + e];
+          }
         } else {
           ++since_best[e];
         }
@@ -760,6 +774,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(inner(tol_in, maxit, odone, r0_in, st_in, false));
       C.rd.prec = LRFG_PREC_FP64;
       LRFG_TRY(axpby(C, C.xa, C.xb, C.ones, C.tmp));   // x <- T(x + delta)
+      LRFG_TRY(fetch_kept());
       LRFG_TRY(tt_copy(C.tmp, C.xa, nE, s));
       LRFG_TRY(apply_K(C, C.xa, C.tmp));               // r <- T(b - K x)
       LRFG_TRY(axpby(C, C.b0, C.tmp, C.mones, C.b));
@@ -775,6 +790,8 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         if (en[e] < best[e]) {
           best[e] = en[e];
           LRFG_TRY(copy_system(C, C.xa, C.xbest, e));
+          kbest[e] = kx[e];
+          kbest[nE + e] = kx[nE + e];
         }
         if (rel <= P.solver_tol || !gain) {
           odone[e] = 1;
@@ -820,11 +837,8 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nEp));
     for (size_t k = 0; k < w2.size(); ++k) m2[k * d + al] = w2[k] / Ntot;
   }
-  // final ranks: one more truncation of the best iterate reports the kept ranks
-  std::vector<int> kept(2 * nE, 0);
-  LRFG_TRY(C.rd.round(C.xb, C.tmp, P.trunc_tol, s, nE));
-  LRFG_HIP(hipMemcpyAsync(kept.data(), C.rd.kept, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
-  LRFG_HIP(hipMemcpyAsync(kept.data() + nE, C.rd.kept + C.rd.nE, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+  // final ranks: those the truncation kept for each system's returned iterate
+  const std::vector<int>& kept = kbest;
   LRFG_HIP(hipEventRecord(ev2, s));
   LRFG_HIP(hipStreamSynchronize(s));
   float ms_setup = 0.f, ms_solve = 0.f;

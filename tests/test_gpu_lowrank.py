@@ -31,6 +31,9 @@ def test_laminate_rank_one(dev, solver):
     H = 1.0 / np.mean(1.0 / prof)
     M = np.mean(prof)
     assert _rel(r.A_H, np.diag([H, M, M])) <= 1e-10
+    # the corrector of E = e1 is a rank-1 train u(x1); the others vanish
+    assert list(r.ranks[0]) == [1, 1, 1, 1]
+    assert np.all(r.ranks[1:, 1:3] == 0)
 
 
 @pytest.mark.parametrize("d,N", [(2, 45), (3, 15)])
