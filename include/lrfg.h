@@ -280,6 +280,24 @@ int lrfg_tt_round(int d, const int N[3], const int rin[4], double* const* in_cor
                   double tol, int oversample, uint64_t seed, double* const* out_cores,
                   int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Tucker truncation (Appendix A.2) of nE tensors of mode ranks rin (d = 3):
+ * frames in_frames[j] = nE x [N_j][rin_j] (row-major: columns are the mode
+ * fibres), core in_core = nE x [rin_1][rin_2][rin_3] (device).  Output
+ * mode ranks are fixed, c_j = min(cap, N_j) (written to out_ranks, host,
+ * 3 ints), frames out_frames[j] = nE x [N_j][c_j], core out_core =
+ * nE x [c_1][c_2][c_3]; directions beyond the kept rank (at most c_j, the
+ * fewest whose dropped singular values of the mode-j unfolding satisfy
+ * ||dropped||^2 <= tol^2 ||X||^2 / 3) are zero.  Randomised HOSVD with
+ * Khatri-Rao structured sketches of size min(max c_j + oversample, 64),
+ * seeded by seed; exact whenever every mode rank is at most that.  kept
+ * (host, 3*nE ints, mode-major, or NULL) receives the kept ranks and makes
+ * the call synchronise the stream. */
+size_t lrfg_tucker_round_workspace_bytes(const int N[3], const int rin[3], int cap, int oversample, int nE);
+int lrfg_tucker_round(const int N[3], const int rin[3], double* const* in_frames, const double* in_core,
+                      int cap, double tol, int oversample, uint64_t seed, double* const* out_frames,
+                      double* out_core, int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes,
+                      void* stream);
+
 /* Coefficient compression (setup of the low-rank path, Sec. 3.1.3 and
  * Appendix A.3): the full field a (device, N1 x ... x Nd, C order) as a
  * tensor train with ranks at most cap, the fewest directions whose dropped

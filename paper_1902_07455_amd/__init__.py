@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "compress_tt", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
+           "gemm", "syevj", "gram_cut", "compress_tt", "tucker_round", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
            "Completion"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
@@ -417,6 +417,36 @@ def gram_cut(G, c: int, tol: float = 0.0, stream=None):
                               C.c_void_p(kept.data_ptr()), C.c_void_p(sweeps.data_ptr()),
                               C.c_void_p(_stream_handle(stream))))
     return S, kept, sweeps
+
+
+def tucker_round(frames, core, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):
+    """Truncate nE Tucker tensors: frames[j] (nE, N_j, r_j) and core
+    (nE, r_1, r_2, r_3) float64 CUDA tensors.  Returns (frames, core, kept
+    ranks (3, nE))."""
+    torch = _torch()
+    L = lib()
+    nE = core.shape[0]
+    Ns = [int(F.shape[1]) for F in frames]
+    rin = [int(F.shape[2]) for F in frames]
+    Nc = (C.c_int * 3)(*Ns)
+    Rc = (C.c_int * 3)(*rin)
+    nb = L.lrfg_tucker_round_workspace_bytes(Nc, Rc, int(cap), int(oversample), nE)
+    if nb == 0:
+        raise LrfgError(-1, "bad tucker_round sizes")
+    ws = _ws_tensor(nb, core.device)
+    c = [min(cap, n) for n in Ns]
+    fo = [torch.empty((nE, Ns[j], c[j]), dtype=torch.float64, device=core.device) for j in range(3)]
+    co = torch.empty((nE, c[0], c[1], c[2]), dtype=torch.float64, device=core.device)
+    fi = [F.contiguous() for F in frames]
+    ci = core.contiguous()
+    ip = (C.c_void_p * 3)(*[F.data_ptr() for F in fi])
+    op = (C.c_void_p * 3)(*[F.data_ptr() for F in fo])
+    ranks = (C.c_int * 3)()
+    kept = (C.c_int * (3 * nE))()
+    check(L.lrfg_tucker_round(Nc, Rc, ip, C.c_void_p(ci.data_ptr()), int(cap), float(tol), int(oversample),
+                              int(seed), op, C.c_void_p(co.data_ptr()), ranks, kept, nE,
+                              C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream_handle(stream))))
+    return fo, co, np.array(list(kept), dtype=np.int32).reshape(3, nE)
 
 
 def compress_tt(a, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):

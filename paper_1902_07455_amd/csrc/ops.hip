@@ -5,6 +5,7 @@
 #include "common.h"
 #include "linalg.h"
 #include "tt.h"
+#include "tucker.h"
 
 using namespace lrfg;
 
@@ -187,6 +188,96 @@ void full_as_tt_ranks(int d, const int N[3], int rin[4]) {
 }  // namespace lrfg
 
 extern "C" {
+
+}  // extern "C"
+
+namespace {
+
+int tucker_round_sizes(const int N[3], const int rin[3], int cap, int oversample, int nE, int c[3], TkRounder& R) {
+  if (N == nullptr || rin == nullptr || cap < 1 || oversample < 0 || nE < 1) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  int cmax = 1;
+  for (int j = 0; j < 3; ++j) {
+    if (N[j] < 1 || rin[j] < 1) {
+      set_error("N and ranks must be positive");
+      return LRFG_EINVAL;
+    }
+    c[j] = std::min(cap, N[j]);
+    cmax = std::max(cmax, c[j]);
+  }
+  if (cmax > kMaxEig) {
+    set_error("rank cap %d exceeds %d", cmax, kMaxEig);
+    return LRFG_EUNSUPPORTED;
+  }
+  R.nE = nE;
+  for (int j = 0; j < 3; ++j) {
+    R.N[j] = N[j];
+    R.Rmax[j] = rin[j];
+  }
+  R.oversample = oversample;
+  R.Lmax = std::min(cmax + oversample, kMaxEig);
+  return LRFG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lrfg_tucker_round_workspace_bytes(const int N[3], const int rin[3], int cap, int oversample, int nE) {
+  TkRounder R;
+  int c[3];
+  if (tucker_round_sizes(N, rin, cap, oversample, nE, c, R) != LRFG_OK) return 0;
+  Arena ar;
+  R.carve(ar);
+  return ar.used + 256;
+}
+
+int lrfg_tucker_round(const int N[3], const int rin[3], double* const* in_frames, const double* in_core, int cap,
+                      double tol, int oversample, uint64_t seed, double* const* out_frames, double* out_core,
+                      int* out_ranks, int* kept, int nE, void* d_ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (in_frames == nullptr || in_core == nullptr || out_frames == nullptr || out_core == nullptr || !(tol >= 0.0)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  TkRounder R;
+  int c[3];
+  LRFG_TRY(tucker_round_sizes(N, rin, cap, oversample, nE, c, R));
+  R.seed = seed;
+  Arena ar;
+  ar.base = static_cast<char*>(d_ws);
+  ar.cap = ws_bytes;
+  R.carve(ar);
+  if (ar.overflow || d_ws == nullptr) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  TKB in, out;
+  for (int j = 0; j < 3; ++j) {
+    in.N[j] = out.N[j] = N[j];
+    in.r[j] = rin[j];
+    out.r[j] = c[j];
+    in.U[j] = in_frames[j];
+    in.sU[j] = in.usize(j);
+    out.U[j] = out_frames[j];
+    out.sU[j] = out.usize(j);
+  }
+  in.G = const_cast<double*>(in_core);
+  in.sG = in.gsize();
+  out.G = out_core;
+  out.sG = out.gsize();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LRFG_TRY(R.round(in, out, tol, s));
+  if (out_ranks)
+    for (int j = 0; j < 3; ++j) out_ranks[j] = c[j];
+  if (kept) {
+    LRFG_HIP(hipMemcpyAsync(kept, R.kept, sizeof(int) * 3 * nE, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+  }
+  return LRFG_OK;
+}
 
 size_t lrfg_compress_workspace_bytes(int d, const int N[3], int cap, int oversample) {
   using namespace lrfg;

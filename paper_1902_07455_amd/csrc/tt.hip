@@ -114,6 +114,13 @@ __global__ void k_block_copy(const double* __restrict__ X, long long sx, int r0,
 
 }  // namespace
 
+int launch_randn(double* out, long long n, uint64_t key, hipStream_t s) {
+  if (n <= 0) return LRFG_OK;
+  hipLaunchKernelGGL(k_randn, dim3(grid_for(n)), dim3(kB), 0, s, out, n, key);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
 // ====================================================================== host helpers
 TTB tt_alloc(Arena& ar, int d, const int N[3], const int r[4], int nE) {
   TTB t;

@@ -1,0 +1,535 @@
+// Tucker-format operations on the device (paper Sec. 3.1.2 and Appendix
+// A.2), d = 3: per-mode DFT operators on the frames, the element-wise
+// product (Khatri-Rao frames and Kronecker core), sums (frames side by side,
+// block-diagonal core), inner products, and truncation.
+//
+// Truncation reaches the paper's HOSVD cut through a randomised range
+// finder (Halko, Martinsson and Tropp) with Khatri-Rao structured sketches,
+// so that no frame QR or core unfolding larger than the sketch is ever
+// factorised:
+//   1. Z_j = U_j^T Om_j for Gaussian Om_j (N_j x l), and the sketch of the
+//      mode-j unfolding Y_j = X_(j) (Om_k (.) Om_m) = U_j G_(j) (Z_k (.) Z_m),
+//      formed from the core without expanding anything (the structured
+//      sketch of Sun, Guo, Luo, Tropp and Udell, SIMAX 2020);
+//   2. Q_j = orth(Y_j) (Gram matrix and pivoted Cholesky, twice);
+//   3. the core of the projected tensor C = G x_j (Q_j^T U_j) (l x l x l);
+//   4. the paper's cut: the HOSVD of C from its three l x l mode Gram
+//      matrices, at most c_j per mode and the fewest whose dropped
+//      eigenvalues stay within tol^2 ||X||^2 / 3 per mode, so the total
+//      error is within tol ||X|| (Appendix A.2 bound).
+// Output ranks are fixed (c_1, c_2, c_3); directions beyond the kept rank
+// are zero columns.
+#include <algorithm>
+#include <cmath>
+
+#include "prof.h"
+#include "tucker.h"
+
+namespace lrfg {
+
+int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, long long inner, int op, double t,
+                       double mult, const FftDev& f, hipStream_t s, long long fib_per_group);
+int launch_randn(double* out, long long n, uint64_t key, hipStream_t s);
+
+namespace {
+
+constexpr int kB = 256;
+
+inline int grid_for(long long n) {
+  long long g = (n + kB - 1) / kB;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+// out[e][n][i s + k] = a[e][n][i] x[e][n][k]   (frames [N][r])
+__global__ void k_frame_kr(const double* __restrict__ a, long long sa, int ra, const double* __restrict__ x,
+                           long long sx, int rx, int N, double* __restrict__ out, long long so, int nE) {
+  const long long R = (long long)ra * rx, per = N * R;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    const long long rem = idx - e * per;
+    const long long n = rem / R, c = rem - n * R;
+    const long long i = c / rx, k = c - i * rx;
+    out[e * so + rem] = a[e * sa + n * ra + i] * x[e * sx + n * rx + k];
+  }
+}
+
+// out[e][I1][I2][I3] = a[e][p1][p2][p3] x[e][q1][q2][q3], I_j = p_j rx_j + q_j
+__global__ void k_core_kron(const double* __restrict__ a, long long sa, int a1, int a2, int a3,
+                            const double* __restrict__ x, long long sx, int x1, int x2, int x3,
+                            double* __restrict__ out, long long so, int nE) {
+  const long long R2 = (long long)a2 * x2, R3 = (long long)a3 * x3;
+  const long long per = (long long)a1 * x1 * R2 * R3;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    long long rem = idx - e * per;
+    const long long I3 = rem % R3;
+    rem /= R3;
+    const long long I2 = rem % R2, I1 = rem / R2;
+    const long long p1 = I1 / x1, q1 = I1 - p1 * x1;
+    const long long p2 = I2 / x2, q2 = I2 - p2 * x2;
+    const long long p3 = I3 / x3, q3 = I3 - p3 * x3;
+    out[e * so + (idx - e * per)] =
+        a[e * sa + (p1 * a2 + p2) * a3 + p3] * x[e * sx + (q1 * x2 + q2) * x3 + q3];
+  }
+}
+
+// out[e][n][o + k] = x[e][n][k]   (frame of rank r into a frame of rank R)
+__global__ void k_frame_place(const double* __restrict__ x, long long sx, int r, int N, double* __restrict__ out,
+                              long long so, int R, int o, int nE) {
+  const long long per = (long long)N * r;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    const long long rem = idx - e * per;
+    const long long n = rem / r, k = rem - n * r;
+    out[e * so + n * R + o + k] = x[e * sx + rem];
+  }
+}
+
+// out[e][o1 + i][o2 + j][o3 + k] = c_e x[e][i][j][k]
+__global__ void k_core_place(const double* __restrict__ x, long long sx, int r1, int r2, int r3,
+                             const double* __restrict__ coef, double mult, double* __restrict__ out, long long so,
+                             int R2, int R3, int o1, int o2, int o3, int nE) {
+  const long long per = (long long)r1 * r2 * r3;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    long long rem = idx - e * per;
+    const long long k = rem % r3;
+    rem /= r3;
+    const long long j = rem % r2, i = rem / r2;
+    const double c = mult * (coef != nullptr ? coef[e] : 1.0);
+    out[e * so + ((o1 + i) * R2 + o2 + j) * R3 + o3 + k] = c * x[e * sx + (idx - e * per)];
+  }
+}
+
+// Mode-2 product: out[e][a][b][c] = sum_q W'[b][q] in[e][a][q][c] with
+// W' = W[e] (Bo x Bi) or, transposed, W[e]^T (W[e] is Bi x Bo).
+__global__ void k_mode2(const double* __restrict__ in, long long sin, int A, int Bi, int Cd,
+                        const double* __restrict__ W, long long sW, int Bo, int wt, double* __restrict__ out,
+                        long long sout, int nE) {
+  const long long per = (long long)A * Bo * Cd;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    long long rem = idx - e * per;
+    const long long c = rem % Cd;
+    rem /= Cd;
+    const long long b = rem % Bo, a = rem / Bo;
+    const double* w = W + e * sW;
+    const double* x = in + e * sin + a * Bi * Cd + c;
+    double acc = 0.0;
+    if (wt) {
+      for (int q = 0; q < Bi; ++q) acc += w[(long long)q * Bo + b] * x[(long long)q * Cd];
+    } else {
+      for (int q = 0; q < Bi; ++q) acc += w[b * Bi + q] * x[(long long)q * Cd];
+    }
+    out[e * sout + (idx - e * per)] = acc;
+  }
+}
+
+// Y cores of modes 1 and 2 from H = G x_3 Z_3^T (R1 x R2 x l):
+// y1[i1][t] = sum_i2 H[i1][i2][t] Z2[i2][t], y2[i2][t] = sum_i1 H[i1][i2][t] Z1[i1][t].
+__global__ void k_tcontract(const double* __restrict__ H, long long sH, const double* __restrict__ Z1,
+                            long long sZ1, const double* __restrict__ Z2, long long sZ2, int R1, int R2, int l,
+                            double* __restrict__ y1, long long sy1, double* __restrict__ y2, long long sy2,
+                            int nE) {
+  const long long per = (long long)(R1 + R2) * l;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    const long long rem = idx - e * per;
+    const long long row = rem / l, t = rem - row * l;
+    const double* h = H + e * sH;
+    double acc = 0.0;
+    if (row < R1) {
+      const double* z = Z2 + e * sZ2;
+      for (int i2 = 0; i2 < R2; ++i2) acc += h[(row * R2 + i2) * l + t] * z[(long long)i2 * l + t];
+      y1[e * sy1 + row * l + t] = acc;
+    } else {
+      const long long i2 = row - R1;
+      const double* z = Z1 + e * sZ1;
+      for (int i1 = 0; i1 < R1; ++i1) acc += h[((long long)i1 * R2 + i2) * l + t] * z[(long long)i1 * l + t];
+      y2[e * sy2 + i2 * l + t] = acc;
+    }
+  }
+}
+
+// KR[e][i1 R2 + i2][t] = Z1[e][i1][t] Z2[e][i2][t]
+__global__ void k_kr_rows(const double* __restrict__ Z1, long long s1, int R1, const double* __restrict__ Z2,
+                          long long s2, int R2, int l, double* __restrict__ KR, long long sk, int nE) {
+  const long long per = (long long)R1 * R2 * l;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    const long long rem = idx - e * per;
+    const long long t = rem % l, row = rem / l;
+    const long long i1 = row / R2, i2 = row - i1 * R2;
+    KR[e * sk + rem] = Z1[e * s1 + i1 * l + t] * Z2[e * s2 + i2 * l + t];
+  }
+}
+
+// Gram matrix of the mode-2 unfolding of C (l x l x l):
+// Gr[e][b][b'] = sum_{a,c} C[e][a][b][c] C[e][a][b'][c]
+__global__ void k_gram_mode2(const double* __restrict__ Cc, long long sc, int l, double* __restrict__ Gr,
+                             long long sg, int nE) {
+  const long long per = (long long)l * l;
+  GRID_STRIDE(idx, per * nE) {
+    const long long e = idx / per;
+    const long long rem = idx - e * per;
+    const long long b = rem / l, bp = rem - b * l;
+    const double* c = Cc + e * sc;
+    double acc = 0.0;
+    for (int a = 0; a < l; ++a)
+      for (int k = 0; k < l; ++k) acc += c[((long long)a * l + b) * l + k] * c[((long long)a * l + bp) * l + k];
+    Gr[e * sg + rem] = acc;
+  }
+}
+
+struct GB {
+  Gemm g;
+  GB(int m, int n, int k, int batch) {
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.batch = batch;
+  }
+  GB& a(const double* p, long long ld, long long st, bool t = false) {
+    g.A = p;
+    g.lda = ld;
+    g.sA = st;
+    g.ta = t;
+    return *this;
+  }
+  GB& b(const double* p, long long ld, long long st, bool t = false) {
+    g.B = p;
+    g.ldb = ld;
+    g.sB = st;
+    g.tb = t;
+    return *this;
+  }
+  GB& c(double* p, long long ld, long long st) {
+    g.C = p;
+    g.ldc = ld;
+    g.sC = st;
+    return *this;
+  }
+};
+
+constexpr size_t kTkDotSplitK = (size_t)2 * 1024 * 1024;
+
+}  // namespace
+
+// ====================================================================== basics
+TKB tk_alloc(Arena& ar, const int N[3], const int r[3], int nE) {
+  TKB t;
+  for (int j = 0; j < 3; ++j) {
+    t.N[j] = N[j];
+    t.r[j] = r[j];
+    t.sU[j] = t.usize(j);
+    t.U[j] = ar.take<double>((size_t)t.sU[j] * nE);
+  }
+  t.sG = t.gsize();
+  t.G = ar.take<double>((size_t)t.sG * nE);
+  return t;
+}
+
+int tk_zero(TKB& x, int nE, hipStream_t s) {
+  for (int j = 0; j < 3; ++j)
+    if (x.U[j]) LRFG_HIP(hipMemsetAsync(x.U[j], 0, sizeof(double) * x.usize(j) * (x.sU[j] ? nE : 1), s));
+  LRFG_HIP(hipMemsetAsync(x.G, 0, sizeof(double) * x.gsize() * (x.sG ? nE : 1), s));
+  return LRFG_OK;
+}
+
+static int copy_block(double* dst, long long sd, const double* src, long long ss, long long n, int nE,
+                      hipStream_t s) {
+  if (sd == n && ss == n) {
+    LRFG_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n * nE, hipMemcpyDeviceToDevice, s));
+    return LRFG_OK;
+  }
+  for (int e = 0; e < nE; ++e)
+    LRFG_HIP(hipMemcpyAsync(dst + e * sd, src + e * ss, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  return LRFG_OK;
+}
+
+int tk_copy(const TKB& x, TKB& y, int nE, hipStream_t s) {
+  for (int j = 0; j < 3; ++j) {
+    if (x.r[j] != y.r[j]) {
+      set_error("tk_copy: rank mismatch");
+      return LRFG_EINVAL;
+    }
+    LRFG_TRY(copy_block(y.U[j], y.sU[j], x.U[j], x.sU[j], x.usize(j), nE, s));
+  }
+  return copy_block(y.G, y.sG, x.G, x.sG, x.gsize(), nE, s);
+}
+
+int tk_copy_system(const TKB& x, TKB& y, int e, hipStream_t s) {
+  for (int j = 0; j < 3; ++j)
+    LRFG_HIP(hipMemcpyAsync(y.U[j] + e * y.sU[j], x.U[j] + e * x.sU[j], sizeof(double) * x.usize(j),
+                            hipMemcpyDeviceToDevice, s));
+  LRFG_HIP(hipMemcpyAsync(y.G + e * y.sG, x.G + e * x.sG, sizeof(double) * x.gsize(), hipMemcpyDeviceToDevice, s));
+  return LRFG_OK;
+}
+
+int tk_mode_apply(const TKB& x, TKB& y, int j, int op, double t, double mult, const FftDev& f, int nE,
+                  hipStream_t s) {
+  double* uj = y.U[j];
+  y = x;
+  y.U[j] = uj;
+  y.sU[j] = x.sU[j] == 0 ? 0 : x.usize(j);
+  const int reps = x.sU[j] == 0 ? 1 : nE;
+  return launch_mode_op_oop(x.U[j], uj, reps, x.N[j], x.r[j], op, t, mult, f, s, x.r[j]);
+}
+
+int tk_hadamard(const TKB& a, const TKB& x, TKB& out, int nE, hipStream_t s) {
+  ProfScope ps_("tk_hadamard", s);
+  for (int j = 0; j < 3; ++j) {
+    out.r[j] = a.r[j] * x.r[j];
+    out.sU[j] = out.usize(j);
+  }
+  out.sG = out.gsize();
+  for (int j = 0; j < 3; ++j) {
+    const long long tot = out.usize(j) * nE;
+    hipLaunchKernelGGL(k_frame_kr, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)a.U[j], a.sU[j], a.r[j],
+                       (const double*)x.U[j], x.sU[j], x.r[j], x.N[j], out.U[j], out.sU[j], nE);
+  }
+  hipLaunchKernelGGL(k_core_kron, dim3(grid_for(out.gsize() * nE)), dim3(kB), 0, s, (const double*)a.G, a.sG, a.r[0],
+                     a.r[1], a.r[2], (const double*)x.G, x.sG, x.r[0], x.r[1], x.r[2], out.G, out.sG, nE);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int tk_place_core(const TKB& x, const double* coef, double mult, TKB& out, const int o[3], int nE, hipStream_t s) {
+  hipLaunchKernelGGL(k_core_place, dim3(grid_for(x.gsize() * nE)), dim3(kB), 0, s, (const double*)x.G, x.sG, x.r[0],
+                     x.r[1], x.r[2], coef, mult, out.G, out.sG, out.r[1], out.r[2], o[0], o[1], o[2], nE);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int tk_sum(const TKTerm* terms, int nt, TKB& out, int nE, hipStream_t s) {
+  int R[3] = {0, 0, 0};
+  for (int t = 0; t < nt; ++t)
+    for (int j = 0; j < 3; ++j) R[j] += terms[t].x->r[j];
+  for (int j = 0; j < 3; ++j) {
+    if (R[j] != out.r[j]) {
+      set_error("tk_sum: output ranks do not match the terms");
+      return LRFG_EINVAL;
+    }
+  }
+  LRFG_HIP(hipMemsetAsync(out.G, 0, sizeof(double) * out.gsize() * nE, s));
+  int o[3] = {0, 0, 0};
+  for (int t = 0; t < nt; ++t) {
+    const TKB& x = *terms[t].x;
+    for (int j = 0; j < 3; ++j) {
+      hipLaunchKernelGGL(k_frame_place, dim3(grid_for(x.usize(j) * nE)), dim3(kB), 0, s, (const double*)x.U[j],
+                         x.sU[j], x.r[j], x.N[j], out.U[j], out.sU[j], out.r[j], o[j], nE);
+    }
+    LRFG_LAUNCHED();
+    LRFG_TRY(tk_place_core(x, terms[t].coef, terms[t].mult, out, o, nE, s));
+    for (int j = 0; j < 3; ++j) o[j] += x.r[j];
+  }
+  return LRFG_OK;
+}
+
+size_t tk_dot_scratch(const TKB& x, const TKB& y, int nE) {
+  size_t n = 0;
+  for (int j = 0; j < 3; ++j) n += (size_t)x.r[j] * y.r[j];
+  n += (size_t)y.r[0] * y.r[1] * x.r[2];   // T1
+  n += (size_t)x.r[0] * y.r[1] * x.r[2];   // T2
+  n += (size_t)x.gsize();                  // T3
+  return n * nE + 4096 + kTkDotSplitK;
+}
+
+int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s) {
+  double* p = scratch;
+  double* W[3];
+  for (int j = 0; j < 3; ++j) {
+    W[j] = p;
+    p += (size_t)x.r[j] * y.r[j] * nE;
+    // W_j = U_xj^T U_yj (rx_j x ry_j)
+    GB g(x.r[j], y.r[j], x.N[j], nE);
+    g.a(x.U[j], x.r[j], x.sU[j], true).b(y.U[j], y.r[j], y.sU[j]).c(W[j], y.r[j], (long long)x.r[j] * y.r[j]);
+    LRFG_TRY(gemm(g.g, scratch + tk_dot_scratch(x, y, nE) - kTkDotSplitK, kTkDotSplitK, s));
+  }
+  double* gs = scratch + tk_dot_scratch(x, y, nE) - kTkDotSplitK;
+  const int rx1 = x.r[0], rx2 = x.r[1], rx3 = x.r[2], ry1 = y.r[0], ry2 = y.r[1], ry3 = y.r[2];
+  double* T1 = p;
+  p += (size_t)ry1 * ry2 * rx3 * nE;
+  double* T2 = p;
+  p += (size_t)rx1 * ry2 * rx3 * nE;
+  double* T3 = p;
+  // T1 = G_y (ry1 ry2 x ry3) W3^T
+  { GB g(ry1 * ry2, rx3, ry3, nE); g.a(y.G, ry3, y.sG).b(W[2], ry3, (long long)rx3 * ry3, true)
+        .c(T1, rx3, (long long)ry1 * ry2 * rx3);
+    LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
+  // T2 = W1 (rx1 x ry1) T1 (ry1 x ry2 rx3)
+  { GB g(rx1, ry2 * rx3, ry1, nE); g.a(W[0], ry1, (long long)rx1 * ry1).b(T1, (long long)ry2 * rx3, (long long)ry1 * ry2 * rx3)
+        .c(T2, (long long)ry2 * rx3, (long long)rx1 * ry2 * rx3);
+    LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
+  // T3 = T2 x_2 W2 (rx2 x ry2)
+  const long long n3 = (long long)rx1 * rx2 * rx3;
+  hipLaunchKernelGGL(k_mode2, dim3(grid_for(n3 * nE)), dim3(kB), 0, s, (const double*)T2, (long long)rx1 * ry2 * rx3,
+                     rx1, ry2, rx3, (const double*)W[1], (long long)rx2 * ry2, rx2, 0, T3, n3, nE);
+  LRFG_LAUNCHED();
+  // dots[e] = <G_x, T3>
+  { GB g(1, 1, (int)n3, nE); g.a(x.G, n3, x.sG).b(T3, 1, n3).c(dots, 1, 1);
+    LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
+  return LRFG_OK;
+}
+
+// ====================================================================== rounding
+void TkRounder::carve(Arena& ar) {
+  const int L = Lmax;
+  auto T = [&](long long n) { return ar.take<double>((size_t)n * nE); };
+  const long long R1 = Rmax[0], R2 = Rmax[1], R3 = Rmax[2];
+  long long Nm = 1;
+  for (int j = 0; j < 3; ++j) {
+    om[j] = ar.take<double>((size_t)N[j] * L);
+    Z[j] = T(Rmax[j] * L);
+    Yc[j] = T(Rmax[j] * L);
+    Y[j] = T((long long)N[j] * L);
+    Q[j] = T((long long)N[j] * L);
+    M[j] = T(Rmax[j] * L);
+    S[j] = T((long long)L * L);
+    Nm = std::max<long long>(Nm, N[j]);
+  }
+  H = T(R1 * R2 * L);  // H, then the Khatri-Rao rows, then T1 (R1 R2 x l)
+  T2 = T((long long)L * R2 * L);
+  Cc = T((long long)L * L * L);
+  T3 = T((long long)L * L * L);
+  T4 = T((long long)L * L * L);
+  Gr = T((long long)L * L);
+  Gs = T((long long)L * L);
+  Ss = T((long long)L * L);
+  Ytmp = T(Nm * L);
+  kept = ar.take<int>((size_t)3 * nE);
+  gscr_n = (size_t)4 * 1024 * 1024;
+  gscr = ar.take<double>(gscr_n);
+  KR = H;
+  T1 = H;
+}
+
+namespace {
+
+// Q (m x l) = orth(Y) by Gram matrix + pivoted Cholesky, twice.
+int tk_orth(TkRounder& R, const double* Y, double* Q, int m, int l, int batch, hipStream_t s) {
+  const double tau = 1e-14;
+  const double* src = Y;
+  double* dsts[2] = {R.Ytmp, Q};
+  for (int pass = 0; pass < 2; ++pass) {
+    GB gg(l, l, m, batch);
+    gg.a(src, l, (long long)m * l, true).b(src, l, (long long)m * l).c(R.Gs, l, (long long)l * l);
+    LRFG_TRY(gemm(gg.g, R.gscr, R.gscr_n, s));
+    LRFG_TRY(pchol_s(l, R.Gs, (long long)l * l, tau, R.Ss, (long long)l * l, nullptr, batch, s));
+    GB gq(m, l, l, batch);
+    gq.a(src, l, (long long)m * l).b(R.Ss, l, (long long)l * l).c(dsts[pass], l, (long long)m * l);
+    LRFG_TRY(gemm(gq.g, R.gscr, R.gscr_n, s));
+    src = dsts[pass];
+  }
+  return LRFG_OK;
+}
+
+}  // namespace
+
+int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch) {
+  ProfScope ps_("tk_round", s);
+  if (batch < 0) batch = nE;
+  if (batch > nE) {
+    set_error("tk_round: batch %d exceeds the plan's %d", batch, nE);
+    return LRFG_EINVAL;
+  }
+  const int nb = batch;
+  const int R1 = in.r[0], R2 = in.r[1], R3 = in.r[2];
+  const int Rj[3] = {R1, R2, R3};
+  int cmax = 1;
+  for (int j = 0; j < 3; ++j) cmax = std::max(cmax, out.r[j]);
+  const int l = std::min(cmax + oversample, kMaxEig);
+  for (int j = 0; j < 3; ++j) {
+    if (Rj[j] > Rmax[j] || out.r[j] > l) {
+      set_error("tk_round: sizes exceed the plan");
+      return LRFG_EINVAL;
+    }
+  }
+  if (l > Lmax) {
+    set_error("tk_round: sketch %d exceeds the plan's %d", l, Lmax);
+    return LRFG_EINVAL;
+  }
+  const double tol2 = tol * tol / 3.0;
+  const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
+  const long long sZ[3] = {(long long)R1 * l, (long long)R2 * l, (long long)R3 * l};
+  // 1. Z_j = U_j^T Om_j
+  for (int j = 0; j < 3; ++j) {
+    LRFG_TRY(launch_randn(om[j], (long long)N[j] * l, key ^ (0xA5A5A5A5A5A5A5A5ull * (uint64_t)(j + 1)), s));
+    GB g(Rj[j], l, N[j], nb);
+    g.a(in.U[j], Rj[j], in.sU[j], true).b(om[j], l, 0).c(Z[j], l, sZ[j]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  // 2. sketch cores: H = G x_3 Z3^T, Y cores of modes 1 and 2 from H; mode 3
+  //    from the Khatri-Rao rows of Z1, Z2
+  const long long sH = (long long)R1 * R2 * l;
+  { GB g(R1 * R2, l, R3, nb); g.a(in.G, R3, in.sG).b(Z[2], l, sZ[2]).c(H, l, sH);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  hipLaunchKernelGGL(k_tcontract, dim3(grid_for((long long)(R1 + R2) * l * nb)), dim3(kB), 0, s, (const double*)H, sH,
+                     (const double*)Z[0], sZ[0], (const double*)Z[1], sZ[1], R1, R2, l, Yc[0], sZ[0], Yc[1], sZ[1], nb);
+  hipLaunchKernelGGL(k_kr_rows, dim3(grid_for(sH * nb)), dim3(kB), 0, s, (const double*)Z[0], sZ[0], R1,
+                     (const double*)Z[1], sZ[1], R2, l, KR, sH, nb);
+  LRFG_LAUNCHED();
+  { GB g(R3, l, R1 * R2, nb); g.a(in.G, R3, in.sG, true).b(KR, l, sH).c(Yc[2], l, sZ[2]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  // 3. Y_j = U_j Yc_j, Q_j = orth(Y_j), M_j = Q_j^T U_j
+  for (int j = 0; j < 3; ++j) {
+    const long long sY = (long long)N[j] * l;
+    { GB g(N[j], l, Rj[j], nb); g.a(in.U[j], Rj[j], in.sU[j]).b(Yc[j], l, sZ[j]).c(Y[j], l, sY);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(tk_orth(*this, Y[j], Q[j], N[j], l, nb, s));
+    { GB g(l, Rj[j], N[j], nb); g.a(Q[j], l, sY, true).b(in.U[j], Rj[j], in.sU[j]).c(M[j], Rj[j], sZ[j]);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  }
+  // 4. C = G x_3 M3 x_1 M1 x_2 M2 (l x l x l)
+  const long long l3 = (long long)l * l * l;
+  { GB g(R1 * R2, l, R3, nb); g.a(in.G, R3, in.sG).b(M[2], R3, sZ[2], true).c(T1, l, sH);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  const long long sT2 = (long long)l * R2 * l;
+  { GB g(l, R2 * l, R1, nb); g.a(M[0], R1, sZ[0]).b(T1, (long long)R2 * l, sH).c(T2, (long long)R2 * l, sT2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  hipLaunchKernelGGL(k_mode2, dim3(grid_for(l3 * nb)), dim3(kB), 0, s, (const double*)T2, sT2, l, R2, l,
+                     (const double*)M[1], sZ[1], l, 0, Cc, l3, nb);
+  LRFG_LAUNCHED();
+  // 5. the cut: mode Gram matrices of C, kept eigenvectors S_j (l x c_j)
+  const long long sG2 = (long long)l * l;
+  for (int j = 0; j < 3; ++j) {
+    if (j == 0) {
+      GB g(l, l, l * l, nb);
+      g.a(Cc, (long long)l * l, l3).b(Cc, (long long)l * l, l3, true).c(Gr, l, sG2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    } else if (j == 1) {
+      hipLaunchKernelGGL(k_gram_mode2, dim3(grid_for(sG2 * nb)), dim3(kB), 0, s, (const double*)Cc, l3, l, Gr, sG2,
+                         nb);
+      LRFG_LAUNCHED();
+    } else {
+      GB g(l, l, l * l, nb);
+      g.a(Cc, l, l3, true).b(Cc, l, l3).c(Gr, l, sG2);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    }
+    LRFG_TRY(cut_psd(l, out.r[j], Gr, sG2, tol2, S[j], (long long)l * out.r[j], kept + j * nE, nb, s));
+  }
+  // 6. frames Q_j S_j and core C x_j S_j^T
+  for (int j = 0; j < 3; ++j) {
+    GB g(N[j], out.r[j], l, nb);
+    g.a(Q[j], l, (long long)N[j] * l).b(S[j], out.r[j], (long long)l * out.r[j]).c(out.U[j], out.r[j], out.sU[j]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  const int c1 = out.r[0], c2 = out.r[1], c3 = out.r[2];
+  { GB g(l * l, c3, l, nb); g.a(Cc, l, l3).b(S[2], c3, (long long)l * c3).c(T3, c3, (long long)l * l * c3);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GB g(c1, l * c3, l, nb); g.a(S[0], c1, (long long)l * c1, true).b(T3, (long long)l * c3, (long long)l * l * c3)
+        .c(T4, (long long)l * c3, (long long)c1 * l * c3);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  const long long nout = (long long)c1 * c2 * c3;
+  hipLaunchKernelGGL(k_mode2, dim3(grid_for(nout * nb)), dim3(kB), 0, s, (const double*)T4, (long long)c1 * l * c3,
+                     c1, l, c3, (const double*)S[1], (long long)l * c2, c2, 1, out.G, out.sG, nb);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+}  // namespace lrfg
