@@ -131,7 +131,8 @@ typedef struct {
   double* res_hist;   /* nE*max_iter: relative preconditioned residual norm,
                          the Euclidean norm of the residual's Fourier
                          coefficients (Sec. 4.2); unused entries set to 0    */
-  int* ranks;         /* nE*(d+1): final corrector ranks (low-rank formats)  */
+  int* ranks;         /* nE*(d+1): ranks of the returned corrector: TT r_0..r_d;
+                         Tucker r_1, r_2, r_3 then 0                        */
   int* status;        /* nE: per-corrector lrfg_status                       */
   double setup_ms;    /* coefficient upload/compression, transforms          */
   double solve_ms;    /* iterations and A_H evaluation                       */

@@ -33,6 +33,7 @@
 #include "lowrank.h"
 #include "prof.h"
 #include "tt.h"
+#include "tucker.h"
 
 namespace lrfg {
 
@@ -369,9 +370,17 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
     }
   }
   if (p.format == LRFG_FORMAT_TUCKER) {
-    set_error("the Tucker format is not built yet");
-    delete pl;
-    return LRFG_EUNSUPPORTED;
+    if (p.d != 3 || p.precision != LRFG_PREC_FP64) {
+      set_error("the Tucker format is built for d = 3 in FP64");
+      delete pl;
+      return LRFG_EUNSUPPORTED;
+    }
+    for (int j = 0; j < 3; ++j) pl->c[j + 1] = std::min(p.rank_cap, p.N[j]);  // mode ranks c[1..3]
+    if (std::max(pl->c[1], std::max(pl->c[2], pl->c[3])) + 1 > kMaxEig) {
+      set_error("rank_cap %d exceeds the supported %d", p.rank_cap, kMaxEig - 1);
+      delete pl;
+      return LRFG_EUNSUPPORTED;
+    }
   }
   double R = 0.0;
   for (int j = 0; j < p.d; ++j) R += (double)((p.N[j] - 1) / 2) * ((p.N[j] - 1) / 2);
@@ -382,7 +391,12 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
 
 void lowrank_plan_destroy(LowRankPlan* lr) { delete lr; }
 
+size_t tucker_workspace_bytes(const LowRankPlan* lr, int max_nE);
+int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE, void* ws, size_t ws_bytes,
+                 hipStream_t s, lrfg_result* out);
+
 size_t lowrank_workspace_bytes(const LowRankPlan* lr, int max_nE) {
+  if (lr->p.format == LRFG_FORMAT_TUCKER) return tucker_workspace_bytes(lr, std::min(max_nE, 3));
   // room for one coefficient train per system (the batched form)
   Arena ar;
   Ctx C;
@@ -480,6 +494,16 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
                   size_t ws_bytes, hipStream_t s, lrfg_result* outs) {
   const int d = pl->d;
   const lrfg_problem& P = pl->p;
+  if (P.format == LRFG_FORMAT_TUCKER) {
+    // microstructures one after another in the same workspace
+    int rc = LRFG_OK;
+    for (int b = 0; b < nB; ++b) {
+      const int r = tucker_solve(pl, acs[b], E, nEp, ws, ws_bytes, s, &outs[b]);
+      if (r != LRFG_OK && r != LRFG_NOT_CONVERGED) return r;
+      if (r != LRFG_OK) rc = r;
+    }
+    return rc;
+  }
   const int nE = nB * nEp;  // system e = b nEp + f: microstructure b, field f
   if (nB < 1 || nEp < 1 || nE > kMaxSystems) {
     set_error("%d microstructures x %d fields outside [1, %d] systems", nB, nEp, kMaxSystems);
@@ -882,6 +906,521 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     out->setup_ms = ms_setup;
     out->solve_ms = ms_solve;
   }
+  return rc;
+}
+
+// ====================================================================== Tucker solve
+// The same truncated PCG / MR as the train path with the corrector held in
+// Tucker form (Sec. 3.1.2, Appendix A.2), d = 3, one microstructure: the
+// derivative acts on frame alpha, the material law is the Khatri-Rao /
+// Kronecker product with the coefficient (given in CP form: frames = the
+// factors, superdiagonal core of the weights), the preconditioner's M heat-
+// kernel terms act on all three frames (block sum of M Tuckers), and every
+// rank-raising step is followed by the Tucker truncation.
+namespace {
+
+// Coefficient in CP form as a Tucker tensor: frames f_j^T (N_j x R),
+// superdiagonal core G[t][t][t] = w[t].
+__global__ void k_cp_to_tucker(const double* __restrict__ w, const double* __restrict__ f0,
+                               const double* __restrict__ f1, const double* __restrict__ f2, int R, int N0, int N1,
+                               int N2, double* __restrict__ u0, double* __restrict__ u1, double* __restrict__ u2,
+                               double* __restrict__ G) {
+  const long long n0 = (long long)N0 * R, n1 = (long long)N1 * R, n2 = (long long)N2 * R;
+  const long long ng = (long long)R * R * R;
+  const long long tot = n0 + n1 + n2 + ng;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    if (idx < n0) {
+      const long long n = idx / R, t = idx % R;
+      u0[idx] = f0[t * N0 + n];
+    } else if (idx < n0 + n1) {
+      const long long i = idx - n0, n = i / R, t = i % R;
+      u1[i] = f1[t * N1 + n];
+    } else if (idx < n0 + n1 + n2) {
+      const long long i = idx - n0 - n1, n = i / R, t = i % R;
+      u2[i] = f2[t * N2 + n];
+    } else {
+      const long long i = idx - n0 - n1 - n2;
+      const long long t3 = i % R, t2 = (i / R) % R, t1 = i / ((long long)R * R);
+      G[i] = (t1 == t2 && t2 == t3) ? w[t1] : 0.0;
+    }
+  }
+}
+
+struct TkCtx {
+  LowRankPlan* pl;
+  int nE;
+  hipStream_t s;
+  FftDev f[3];
+  TkRounder rd;
+  TKB a;                    // coefficient (shared, stride 0)
+  TKB xr, pq, x, r, p, q;   // [x; r], [p; q] and their halves
+  TKB z, xb, b, tmp;
+  TKB kr;                   // a (.) D_alpha v, d nE tensors
+  TKB h;                    // truncated material terms, d nE tensors
+  TKB comb;                 // block sums, 2 nE tensors (capacity ranks)
+  double* gframe;           // frame buffer for D_alpha v
+  double* hframe[3];        // frame buffers for D_alpha^T h_alpha
+  double* aframe[3];        // frames of D_alpha a (right-hand side)
+  double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
+  int* done;
+  int cap[3];
+  int ra;
+};
+
+int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
+  C.pl = pl;
+  C.nE = nE;
+  const int* N = pl->N;
+  int rc[3] = {pl->c[1], pl->c[2], pl->c[3]};
+  int ra[3] = {pl->ra, pl->ra, pl->ra};
+  C.ra = pl->ra;
+  for (int j = 0; j < 3; ++j) C.f[j].tw = ar.take<double2>(N[j]);
+  C.a = tk_alloc(ar, N, ra, 1);
+  for (int j = 0; j < 3; ++j) C.a.sU[j] = 0;
+  C.a.sG = 0;
+  C.xr = tk_alloc(ar, N, rc, 2 * nE);
+  C.pq = tk_alloc(ar, N, rc, 2 * nE);
+  C.x = C.xr;
+  C.r = C.xr;
+  C.p = C.pq;
+  C.q = C.pq;
+  for (int j = 0; j < 3; ++j) {
+    C.r.U[j] = C.xr.U[j] + (long long)nE * C.xr.sU[j];
+    C.q.U[j] = C.pq.U[j] + (long long)nE * C.pq.sU[j];
+  }
+  C.r.G = C.xr.G + (long long)nE * C.xr.sG;
+  C.q.G = C.pq.G + (long long)nE * C.pq.sG;
+  C.z = tk_alloc(ar, N, rc, nE);
+  C.xb = tk_alloc(ar, N, rc, nE);
+  C.b = tk_alloc(ar, N, rc, nE);
+  C.tmp = tk_alloc(ar, N, rc, nE);
+  C.h = tk_alloc(ar, N, rc, 3 * nE);
+  int rkr[3], cap[3];
+  for (int j = 0; j < 3; ++j) {
+    rkr[j] = ra[j] * rc[j];
+    int m = 3 * rc[j];
+    m = std::max(m, pl->M * rc[j]);
+    m = std::max(m, 2 * rc[j]);
+    m = std::max(m, 3 * ra[j]);
+    cap[j] = m;
+    C.cap[j] = m;
+  }
+  C.kr = tk_alloc(ar, N, rkr, 3 * nE);
+  C.comb = tk_alloc(ar, N, cap, 2 * nE);
+  long long fmax = 0;
+  for (int j = 0; j < 3; ++j) fmax = std::max(fmax, (long long)N[j] * rc[j]);
+  C.gframe = ar.take<double>((size_t)fmax * nE);
+  for (int al = 0; al < 3; ++al) C.hframe[al] = ar.take<double>((size_t)fmax * nE);
+  long long amax = 0;
+  for (int j = 0; j < 3; ++j) amax = std::max(amax, (long long)N[j] * ra[j]);
+  for (int al = 0; al < 3; ++al) C.aframe[al] = ar.take<double>((size_t)amax);
+  TkRounder& R = C.rd;
+  R.nE = 3 * nE;
+  for (int j = 0; j < 3; ++j) {
+    R.N[j] = N[j];
+    R.Rmax[j] = std::max(cap[j], rkr[j]);
+  }
+  R.oversample = pl->over;
+  R.seed = pl->p.seed;
+  R.Lmax = std::min(std::max(rc[0], std::max(rc[1], rc[2])) + pl->over, kMaxEig);
+  R.carve(ar);
+  C.dots = ar.take<double>((size_t)3 * nE + 64);
+  C.rho = ar.take<double>(nE);
+  C.pqd = ar.take<double>(nE);
+  C.alpha = ar.take<double>(nE);
+  C.beta = ar.take<double>(nE);
+  C.zz = ar.take<double>(nE);
+  C.Ecoef = ar.take<double>((size_t)3 * nE);
+  C.coef2 = ar.take<double>((size_t)2 * nE);
+  C.done = ar.take<int>(nE);
+  size_t dn = tk_dot_scratch(C.kr, C.z, nE);
+  dn = std::max(dn, tk_dot_scratch(C.a, C.a, nE));
+  dn = std::max(dn, tk_dot_scratch(C.z, C.z, nE));
+  C.dscr = ar.take<double>(dn);
+  return LRFG_OK;
+}
+
+// TKB view of a sub-batch (systems off.., stride kept)
+TKB tk_sub(const TKB& x, long long off) {
+  TKB y = x;
+  for (int j = 0; j < 3; ++j) y.U[j] = x.U[j] + off * x.sU[j];
+  y.G = x.G + off * x.sG;
+  return y;
+}
+
+// comb view with ranks rr and compact strides
+TKB tk_comb(const TkCtx& C, const int rr[3]) {
+  TKB c = C.comb;
+  for (int j = 0; j < 3; ++j) {
+    c.r[j] = rr[j];
+    c.sU[j] = c.usize(j);
+  }
+  c.sG = c.gsize();
+  return c;
+}
+
+int tk_apply_K(TkCtx& C, const TKB& v, TKB& out) {
+  const int nE = C.nE;
+  for (int al = 0; al < 3; ++al) {
+    TKB g = v;
+    g.U[al] = C.gframe;
+    LRFG_TRY(tk_mode_apply(v, g, al, 0, 0.0, 1.0, C.f[al], nE, C.s));
+    TKB kra = tk_sub(C.kr, (long long)al * nE);
+    LRFG_TRY(tk_hadamard(C.a, g, kra, nE, C.s));
+  }
+  TKB kr = C.kr;
+  for (int j = 0; j < 3; ++j) {
+    kr.r[j] = C.a.r[j] * v.r[j];
+    kr.sU[j] = kr.usize(j);
+  }
+  kr.sG = kr.gsize();
+  LRFG_TRY(C.rd.round(kr, C.h, 0.0, C.s, 3 * nE));
+  TKB hd[3];
+  TKTerm terms[3];
+  for (int al = 0; al < 3; ++al) {
+    TKB ha = tk_sub(C.h, (long long)al * nE);
+    hd[al] = ha;
+    hd[al].U[al] = C.hframe[al];
+    LRFG_TRY(tk_mode_apply(ha, hd[al], al, 0, 0.0, -1.0, C.f[al], nE, C.s));
+    terms[al] = TKTerm{&hd[al], nullptr, 1.0};
+  }
+  int rr[3];
+  for (int j = 0; j < 3; ++j) rr[j] = 3 * v.r[j];
+  TKB comb = tk_comb(C, rr);
+  LRFG_TRY(tk_sum(terms, 3, comb, nE, C.s));
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+}
+
+// out = T(P~^-1 v): term m has all three frames through the heat kernel
+// exp(-t_m k^2) (frame 0 also scaled by w_m / 4 pi^2), written straight into
+// the block frames of the sum; the core blocks are copies of v's core.
+int tk_apply_P(TkCtx& C, const TKB& v, TKB& out) {
+  const int nE = C.nE;
+  const int M = C.pl->M;
+  int rr[3];
+  for (int j = 0; j < 3; ++j) rr[j] = M * v.r[j];
+  TKB comb = tk_comb(C, rr);
+  std::vector<double> sc(M), one(M, 1.0);
+  for (int m = 0; m < M; ++m) sc[m] = C.pl->w[m] / (4.0 * kPi * kPi);
+  for (int j = 0; j < 3; ++j) {
+    LRFG_TRY(launch_mode_op_blocks(v.U[j], v.sU[j], 1, v.r[j], nE, comb.U[j], comb.sU[j], comb.r[j], false, true, M,
+                                   C.pl->t.data(), j == 0 ? sc.data() : one.data(), C.f[j], C.s));
+  }
+  LRFG_HIP(hipMemsetAsync(comb.G, 0, sizeof(double) * comb.gsize() * nE, C.s));
+  for (int m = 0; m < M; ++m) {
+    const int o[3] = {m * v.r[0], m * v.r[1], m * v.r[2]};
+    LRFG_TRY(tk_place_core(v, nullptr, 1.0, comb, o, nE, C.s));
+  }
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+}
+
+int tk_update_xr(TkCtx& C) {
+  TKTerm t[2] = {TKTerm{&C.xr, nullptr, 1.0}, TKTerm{&C.pq, C.coef2, 1.0}};
+  int rr[3];
+  for (int j = 0; j < 3; ++j) rr[j] = 2 * C.xr.r[j];
+  TKB comb = tk_comb(C, rr);
+  LRFG_TRY(tk_sum(t, 2, comb, 2 * C.nE, C.s));
+  return C.rd.round(comb, C.xr, C.pl->p.trunc_tol, C.s, 2 * C.nE);
+}
+
+int tk_axpby(TkCtx& C, const TKB& x, const TKB& y, const double* cb, TKB& out) {
+  TKTerm t[2] = {TKTerm{&x, nullptr, 1.0}, TKTerm{&y, cb, 1.0}};
+  int rr[3];
+  for (int j = 0; j < 3; ++j) rr[j] = x.r[j] + y.r[j];
+  TKB comb = tk_comb(C, rr);
+  LRFG_TRY(tk_sum(t, 2, comb, C.nE, C.s));
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, C.nE);
+}
+
+int tk_read(TkCtx& C, const double* dptr, double* host, int n) {
+  LRFG_HIP(hipMemcpyAsync(host, dptr, sizeof(double) * n, hipMemcpyDeviceToHost, C.s));
+  LRFG_HIP(hipStreamSynchronize(C.s));
+  return LRFG_OK;
+}
+
+}  // namespace
+
+size_t tucker_workspace_bytes(const LowRankPlan* lr, int max_nE) {
+  Arena ar;
+  TkCtx C;
+  tk_carve(ar, const_cast<LowRankPlan*>(lr), max_nE, C);
+  return ar.used + 1024;
+}
+
+int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE, void* ws, size_t ws_bytes,
+                 hipStream_t s, lrfg_result* out) {
+  const lrfg_problem& P = pl->p;
+  if (nE < 1 || nE > 3) {
+    set_error("Tucker solve: nE in [1, 3]");
+    return LRFG_EINVAL;
+  }
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  TkCtx C;
+  tk_carve(ar, pl, nE, C);
+  if (ar.overflow) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  C.s = s;
+  hipEvent_t ev0, ev1, ev2;
+  LRFG_HIP(hipEventCreate(&ev0));
+  LRFG_HIP(hipEventCreate(&ev1));
+  LRFG_HIP(hipEventCreate(&ev2));
+  LRFG_HIP(hipEventRecord(ev0, s));
+  for (int j = 0; j < 3; ++j) {
+    double2* tw = const_cast<double2*>(C.f[j].tw);
+    LRFG_TRY(fft_dev_upload(pl->mode[j], tw, s, &C.f[j]));
+  }
+  // ---------------------------------------------------------------- coefficient
+  if (ac.weights == nullptr) {
+    set_error("the Tucker path takes the coefficient in CP form");
+    return LRFG_EUNSUPPORTED;
+  }
+  const int Ra = ac.rank;
+  if (Ra < 1 || Ra > pl->ra) {
+    set_error("coefficient rank %d outside [1, coeff_rank = %d]", Ra, pl->ra);
+    return LRFG_EINVAL;
+  }
+  const double* w = ac.weights;
+  const double* f[3] = {ac.factors[0], ac.factors[1], ac.factors[2]};
+  if (!ac.on_device) {
+    size_t n = Ra;
+    for (int j = 0; j < 3; ++j) n += (size_t)Ra * pl->N[j];
+    if (n > (size_t)C.kr.usize(0) * C.nE) {
+      set_error("coefficient staging too small");
+      return LRFG_EWORKSPACE;
+    }
+    double* st = C.kr.U[0];
+    LRFG_HIP(hipMemcpyAsync(st, w, sizeof(double) * Ra, hipMemcpyHostToDevice, s));
+    size_t off = Ra;
+    for (int j = 0; j < 3; ++j) {
+      LRFG_HIP(hipMemcpyAsync(st + off, ac.factors[j], sizeof(double) * Ra * pl->N[j], hipMemcpyHostToDevice, s));
+      f[j] = st + off;
+      off += (size_t)Ra * pl->N[j];
+    }
+    w = st;
+  }
+  for (int j = 0; j < 3; ++j) C.a.r[j] = Ra;
+  {
+    const long long tot = (long long)(pl->N[0] + pl->N[1] + pl->N[2]) * Ra + (long long)Ra * Ra * Ra;
+    hipLaunchKernelGGL(k_cp_to_tucker, dim3((int)std::min<long long>(4096, (tot + 255) / 256)), dim3(256), 0, s, w,
+                       f[0], f[1], f[2], Ra, pl->N[0], pl->N[1], pl->N[2], C.a.U[0], C.a.U[1], C.a.U[2], C.a.G);
+    LRFG_LAUNCHED();
+  }
+  for (int j = 0; j < 3; ++j) {
+    C.kr.r[j] = Ra * C.xr.r[j];
+    C.kr.sU[j] = C.kr.usize(j);
+  }
+  C.kr.sG = C.kr.gsize();
+  // ---------------------------------------------------------------- right-hand side
+  std::vector<double> Ecol(3 * nE, 0.0);
+  for (int al = 0; al < 3; ++al)
+    for (int e = 0; e < nE; ++e) Ecol[al * nE + e] = E[e * 3 + al];
+  LRFG_HIP(hipMemcpyAsync(C.Ecoef, Ecol.data(), sizeof(double) * 3 * nE, hipMemcpyHostToDevice, s));
+  {
+    TKB da[3];
+    TKTerm terms[3];
+    for (int al = 0; al < 3; ++al) {
+      da[al] = C.a;
+      da[al].U[al] = C.aframe[al];
+      LRFG_TRY(tk_mode_apply(C.a, da[al], al, 0, 0.0, 1.0, C.f[al], 1, s));
+      terms[al] = TKTerm{&da[al], C.Ecoef + al * nE, 1.0};
+    }
+    int rr[3] = {3 * Ra, 3 * Ra, 3 * Ra};
+    TKB comb = tk_comb(C, rr);
+    LRFG_TRY(tk_sum(terms, 3, comb, nE, s));
+    LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s, nE));
+  }
+  double a2 = 0.0;
+  LRFG_TRY(tk_dot(C.a, C.a, C.dots, C.dscr, 1, s));
+  LRFG_TRY(tk_read(C, C.dots, &a2, 1));
+  double Ntot = (double)pl->N[0] * pl->N[1] * pl->N[2];
+  const double rms_a = std::sqrt(std::max(a2, 0.0) / Ntot);
+  std::vector<double> floor_abs(nE);
+  for (int e = 0; e < nE; ++e) {
+    double en = 0.0;
+    for (int al = 0; al < 3; ++al) en += E[e * 3 + al] * E[e * 3 + al];
+    floor_abs[e] = 1e-14 * rms_a * std::sqrt(en) * std::sqrt(Ntot);
+  }
+  LRFG_HIP(hipEventRecord(ev1, s));
+  // ---------------------------------------------------------------- solver
+  const int maxit = P.max_iter;
+  std::vector<double> hist((size_t)nE * maxit, 0.0), best(nE, INFINITY), res0(nE, 0.0), zzh(nE);
+  std::vector<int> iters(nE, 0), hdone(nE, 0), status(nE, LRFG_OK), since_best(nE, 0);
+  const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  // kept mode ranks of the latest x truncation (mode j of system e at
+  // kx[j nE + e]) and those of each system's kept iterate
+  std::vector<int> kx(3 * nE, 0), kbest(3 * nE, 0);
+  auto fetch_kept = [&]() -> int {
+    for (int j = 0; j < 3; ++j)
+      LRFG_HIP(hipMemcpyAsync(kx.data() + j * nE, C.rd.kept + (long long)j * C.rd.nE, sizeof(int) * nE,
+                              hipMemcpyDeviceToHost, s));
+    return LRFG_OK;
+  };
+  LRFG_TRY(tk_zero(C.xr, 2 * nE, s));
+  LRFG_TRY(tk_zero(C.xb, nE, s));
+  auto upload_done = [&]() -> int {
+    LRFG_HIP(hipMemcpyAsync(C.done, hdone.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
+    return LRFG_OK;
+  };
+  LRFG_TRY(upload_done());
+  if (P.solver == LRFG_SOLVER_PCG) {
+    LRFG_TRY(tk_copy(C.b, C.r, nE, s));
+    LRFG_TRY(tk_apply_P(C, C.r, C.z));
+    LRFG_TRY(tk_copy(C.z, C.p, nE, s));
+    LRFG_TRY(tk_dot(C.r, C.z, C.rho, C.dscr, nE, s));
+    LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+  } else {
+    LRFG_TRY(tk_apply_P(C, C.b, C.z));
+    LRFG_TRY(tk_copy(C.z, C.b, nE, s));
+    LRFG_TRY(tk_copy(C.b, C.r, nE, s));
+    LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
+  }
+  LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+  for (int e = 0; e < nE; ++e) {
+    res0[e] = std::sqrt(std::max(zzh[e], 0.0));
+    if (res0[e] <= floor_abs[e]) hdone[e] = 1;
+  }
+  LRFG_TRY(upload_done());
+  for (int it = 0; it < maxit; ++it) {
+    bool all = true;
+    for (int e = 0; e < nE; ++e) all = all && hdone[e];
+    if (all) break;
+    if (P.solver == LRFG_SOLVER_PCG) {
+      LRFG_TRY(tk_apply_K(C, C.p, C.q));
+      LRFG_TRY(tk_dot(C.p, C.q, C.pqd, C.dscr, nE, s));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.rho, (const double*)C.pqd,
+                         (const int*)C.done, C.alpha, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(tk_update_xr(C));
+      LRFG_TRY(fetch_kept());
+      LRFG_TRY(tk_apply_P(C, C.r, C.z));
+      LRFG_TRY(tk_dot(C.r, C.z, C.dots, C.dscr, nE, s));
+      LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+      hipLaunchKernelGGL(k_beta, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, C.rho, (const int*)C.done,
+                         C.beta, nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(tk_axpby(C, C.z, C.p, C.beta, C.tmp));
+      LRFG_TRY(tk_copy(C.tmp, C.p, nE, s));
+    } else {
+      LRFG_TRY(tk_apply_K(C, C.r, C.tmp));
+      LRFG_TRY(tk_apply_P(C, C.tmp, C.z));
+      LRFG_TRY(tk_dot(C.z, C.r, C.dots, C.dscr, nE, s));
+      LRFG_TRY(tk_dot(C.z, C.z, C.pqd, C.dscr, nE, s));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, (const double*)C.pqd,
+                         (const int*)C.done, C.alpha, nE);
+      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+      LRFG_LAUNCHED();
+      LRFG_TRY(tk_copy(C.r, C.p, nE, s));
+      LRFG_TRY(tk_copy(C.z, C.q, nE, s));
+      LRFG_TRY(tk_update_xr(C));
+      LRFG_TRY(fetch_kept());
+      LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
+    }
+    LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+    bool changed = false;
+    for (int e = 0; e < nE; ++e) {
+      if (hdone[e]) continue;
+      const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+      hist[(size_t)e * maxit + it] = res;
+      iters[e] = it + 1;
+      if (res < best[e]) {
+        best[e] = res;
+        since_best[e] = 0;
+        LRFG_TRY(tk_copy_system(C.x, C.xb, e, s));
+        for (int j = 0; j < 3; ++j) kbest[j * nE + e] = kx[j * nE + e];
+      } else {
+        ++since_best[e];
+      }
+      if (res <= P.solver_tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
+        hdone[e] = 1;
+        changed = true;
+      } else if (since_best[e] >= patience) {
+        hdone[e] = 1;
+        changed = true;
+        if (best[e] > P.solver_tol) status[e] = LRFG_NOT_CONVERGED;
+      }
+    }
+    if (changed) LRFG_TRY(upload_done());
+  }
+  for (int e = 0; e < nE; ++e) {
+    if (!hdone[e]) status[e] = LRFG_NOT_CONVERGED;
+    if (res0[e] <= floor_abs[e]) status[e] = LRFG_OK;
+  }
+  // ---------------------------------------------------------------- A_H (eq. homog)
+  std::vector<double> m1((size_t)nE * 3), m2((size_t)nE * nE * 3);
+  double mean_a = 0.0;
+  {
+    TKB one = C.tmp;
+    for (int j = 0; j < 3; ++j) {
+      one.r[j] = 1;
+      one.sU[j] = 0;
+      LRFG_TRY(tt_fill(one.U[j], pl->N[j], 1.0, s));
+    }
+    one.sG = 0;
+    LRFG_TRY(tt_fill(one.G, 1, 1.0, s));
+    LRFG_TRY(tk_dot(C.a, one, C.dots, C.dscr, 1, s));
+    LRFG_TRY(tk_read(C, C.dots, &mean_a, 1));
+    mean_a /= Ntot;
+  }
+  for (int al = 0; al < 3; ++al) {
+    TKB g = C.xb;
+    g.U[al] = C.gframe;
+    LRFG_TRY(tk_mode_apply(C.xb, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
+    LRFG_TRY(tk_dot(C.a, g, C.dots, C.dscr, nE, s));
+    std::vector<double> v(nE);
+    LRFG_TRY(tk_read(C, C.dots, v.data(), nE));
+    for (int e = 0; e < nE; ++e) m1[(size_t)e * 3 + al] = v[e] / Ntot;
+    TKB kr = C.kr;
+    LRFG_TRY(tk_hadamard(C.a, g, kr, nE, s));
+    for (int i = 0; i < nE; ++i) {
+      for (int j = 0; j < nE; ++j) {
+        TKB ki = tk_sub(kr, i), gj = tk_sub(g, j);
+        LRFG_TRY(tk_dot(ki, gj, C.dots + i * nE + j, C.dscr, 1, s));
+      }
+    }
+    std::vector<double> w2((size_t)nE * nE);
+    LRFG_TRY(tk_read(C, C.dots, w2.data(), nE * nE));
+    for (int i = 0; i < nE; ++i)
+      for (int j = 0; j < nE; ++j) m2[((size_t)i * nE + j) * 3 + al] = w2[(size_t)i * nE + j] / Ntot;
+  }
+  LRFG_HIP(hipEventRecord(ev2, s));
+  LRFG_HIP(hipStreamSynchronize(s));
+  float ms_setup = 0.f, ms_solve = 0.f;
+  LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
+  LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
+  LRFG_HIP(hipEventDestroy(ev0));
+  LRFG_HIP(hipEventDestroy(ev1));
+  LRFG_HIP(hipEventDestroy(ev2));
+  int rc = LRFG_OK;
+  for (int i = 0; i < nE; ++i) {
+    for (int j = 0; j < nE; ++j) {
+      double v = 0.0;
+      for (int al = 0; al < 3; ++al) {
+        const double ei = E[i * 3 + al], ej = E[j * 3 + al];
+        v += mean_a * ei * ej + ei * m1[(size_t)j * 3 + al] + ej * m1[(size_t)i * 3 + al] +
+             m2[((size_t)i * nE + j) * 3 + al];
+      }
+      if (out->A_H) out->A_H[i * nE + j] = v;
+    }
+    if (out->iters) out->iters[i] = iters[i];
+    if (out->status) out->status[i] = status[i];
+    if (status[i] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+    if (out->res_hist)
+      for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)i * maxit + k];
+    if (out->ranks) {
+      // kept mode ranks (r_1, r_2, r_3) of the returned iterate; the fourth
+      // entry of the d + 1 is 0
+      for (int j = 0; j < 3; ++j) out->ranks[i * 4 + j] = kbest[j * nE + i];
+      out->ranks[i * 4 + 3] = 0;
+    }
+  }
+  out->setup_ms = ms_setup;
+  out->solve_ms = ms_solve;
   return rc;
 }
 

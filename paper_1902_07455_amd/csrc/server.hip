@@ -149,7 +149,7 @@ void worker_main(lrfg_server* S) {
         if (head.ws_one > S->pool->largest()) continue;
         std::vector<size_t> pick = {hi};
         size_t need = head.ws_one;
-        if (head.p.format != LRFG_FORMAT_FULL) {
+        if (head.p.format != LRFG_FORMAT_FULL) {  // Tucker batches run one microstructure at a time
           for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < S->max_batch; ++j) {
             if (!same_batch_key(head, *S->queue[j])) continue;
             size_t more = 0;

@@ -74,6 +74,9 @@ def _problem(L, **kw):
     (dict(precond_terms=1), -1),
     (dict(precision=1), -5),                   # full grid is FP64 only
     (dict(solver=1), -5),                      # full grid uses PCG
+    (dict(format=2, precision=1), -5),         # Tucker path is FP64 only
+    (dict(d=2, N=(15, 15), format=2), -5),     # Tucker path is d = 3 only
+    (dict(N=(65, 65, 65), format=2, rank_cap=64), -5),  # sketch sizes beyond 64
 ])
 def test_plan_validation(kw, code):
     L = _lib()
@@ -100,6 +103,24 @@ def test_plan_and_workspace_sizes():
     assert lib.lrfg_plan_workspace_bytes(plan, 0, C.byref(nb1)) == -1
     lib.lrfg_plan_destroy(plan)
     lib.lrfg_plan_destroy(None)
+
+
+def test_tucker_workspace_one_microstructure_at_a_time():
+    """Tucker batches run one microstructure after another, so the workspace
+    for k microstructures of 3 fields is the one for 3 fields."""
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, N=(45, 45, 45), format=2, rank_cap=8)), C.byref(plan)) == 0
+    sz = []
+    for n in (1, 3, 6, 12):
+        nb = C.c_size_t()
+        assert lib.lrfg_plan_workspace_bytes(plan, n, C.byref(nb)) == 0
+        sz.append(nb.value)
+    lib.lrfg_plan_destroy(plan)
+    assert sz[0] < sz[1] == sz[2] == sz[3]
+    # at least x, r, p, q, z and the mode frames of 3 systems
+    assert sz[1] >= 3 * 5 * 3 * 45 * 8 * 8
 
 
 def test_solve_rejects_bad_workspace_before_device():
