@@ -95,9 +95,9 @@ class Workload:
         import paper_1902_07455_amd as P
         return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=500, device=self.dev)
 
-    def tt_solver(self, cap, tol):
+    def tt_solver(self, cap, tol, fmt="tt"):
         import paper_1902_07455_amd as P
-        return P.Solver(d=3, N=(self.N,) * 3, format="tt", rank_cap=cap, trunc_tol=0.0, solver_tol=tol,
+        return P.Solver(d=3, N=(self.N,) * 3, format=fmt, rank_cap=cap, trunc_tol=0.0, solver_tol=tol,
                         max_iter=100, coeff_rank=self.cp.rank, device=self.dev)
 
     def run_full(self, s):
@@ -133,11 +133,11 @@ def sweep_full(wl, A_ref, fixed=None):
     return None, out
 
 
-def sweep_tt(wl, A_ref, caps=None, fixed_cap=None, fixed_tol=None):
+def sweep_tt(wl, A_ref, caps=None, fixed_cap=None, fixed_tol=None, fmt="tt"):
     out = []
     cap_ok = None
     for cap in ([fixed_cap] if fixed_cap else (caps or TT_CAPS)):
-        s = wl.tt_solver(cap, 1e-8)
+        s = wl.tt_solver(cap, 1e-8, fmt)
         r = wl.run_tt(s)
         s.close()
         e = rel_err(r.A_H, A_ref)
@@ -148,7 +148,7 @@ def sweep_tt(wl, A_ref, caps=None, fixed_cap=None, fixed_tol=None):
     if cap_ok is None:
         return None, None, out
     for tol in ([fixed_tol] if fixed_tol else TT_TOLS):
-        s = wl.tt_solver(cap_ok, tol)
+        s = wl.tt_solver(cap_ok, tol, fmt)
         r = wl.run_tt(s)
         s.close()
         e = rel_err(r.A_H, A_ref)
@@ -285,6 +285,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--crossover", default="243,405", help="grid sizes of the crossover table")
     ap.add_argument("--no-crossover", action="store_true")
+    ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker-format leg")
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-cap", type=int, default=None, help="TT rank cap (skips the cap sweep)")
@@ -384,6 +385,22 @@ def main(argv=None):
         "tt_over_full": round(value / full["solves_per_s"], 4),
         "roofline": roofline,
     }
+
+    # ------------------------------------------------------------ Tucker format (same workload)
+    if not args.no_tucker:
+        kcap, ktol, ksweep = sweep_tt(wl, A_ref, caps=[c for c in TT_CAPS if c >= 8], fmt="tucker")
+        log(f"Tucker sweep: {ksweep}")
+        tk = {"sweep": ksweep, "solves_per_s": None}
+        if ktol is not None:
+            ks = wl.tt_solver(kcap, ktol, "tucker")
+            nk = max(3, args.steps // 5)
+            ksec, klat, kr = timed(lambda: wl.run_tt(ks), nk, 1)
+            ks.close()
+            tk.update({"solves_per_s": round(nk / ksec, 3), "ms_per_solve": round(1e3 * ksec / nk, 3),
+                       "steps": nk, "rank_cap": kcap, "solver_tol": ktol, "iters": kr.iters.tolist(),
+                       "ranks": kr.ranks[:, :3].tolist(), "A_H_rel_err": rel_err(kr.A_H, A_ref),
+                       "over_tt": round((nk / ksec) / value, 4)})
+        out["tucker"] = tk
 
     # ------------------------------------------------------------ mixed precision (same workload)
     mixed = {}
