@@ -22,6 +22,24 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   int batch = 1;
   int prec = 0;  // lrfg_precision: FP64, or FP32 / BF16 inputs with FP32 accumulation
+  // Batch index map: matrix t of the batch reads A at
+  // (t / adiv) sA + (t % amod) sA2 and B at (t / bdiv) sB + (t % bmod) sB2
+  // (a modulus of 0 drops that term); C is always at t sC.
+  int adiv = 1, amod = 0, bdiv = 1, bmod = 0;
+  long long sA2 = 0, sB2 = 0;
+};
+
+// The batch map as the kernels receive it; t = tbase + the launch's batch index.
+struct BatchMap {
+  long long tbase;
+  int adiv, amod, bdiv, bmod;
+  long long sA2, sB2;
+  __host__ __device__ long long a_off(long long t, long long sA) const {
+    return (t / adiv) * sA + (amod > 0 ? (t % amod) * sA2 : 0);
+  }
+  __host__ __device__ long long b_off(long long t, long long sB) const {
+    return (t / bdiv) * sB + (bmod > 0 ? (t % bmod) * sB2 : 0);
+  }
 };
 
 // Scratch doubles gemm() may use for a split-K reduction of this shape.

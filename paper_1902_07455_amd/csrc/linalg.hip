@@ -27,14 +27,15 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
                                               long long lda, long long sA, const double* __restrict__ B,
                                               long long ldb, long long sB, double* __restrict__ C,
                                               long long ldc, long long sC, double alpha, double beta,
-                                              int ksplit, int kchunk, double* __restrict__ part) {
+                                              int ksplit, int kchunk, double* __restrict__ part, BatchMap bm) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int bz = blockIdx.z;
   const int bt = bz / ksplit;
   const int ks = bz - bt * ksplit;
-  A += bt * sA;
-  B += bt * sB;
+  const long long tg = bm.tbase + bt;
+  A += bm.a_off(tg, sA);
+  B += bm.b_off(tg, sB);
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + bt * sC + (long long)row * ldc + col;
+            double* c = C + tg * sC + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -135,14 +136,15 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
                                                  long long sA, const double* __restrict__ B, long long ldb,
                                                  long long sB, double* __restrict__ C, long long ldc, long long sC,
                                                  double alpha, double beta, int ksplit, int kchunk,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, BatchMap bm) {
   __shared__ float As[LK][BM + 1];
   __shared__ float Bs[LK][BN + 1];
   const int bz = blockIdx.z;
   const int bt = bz / ksplit;
   const int ks = bz - bt * ksplit;
-  A += bt * sA;
-  B += bt * sB;
+  const long long tg = bm.tbase + bt;
+  A += bm.a_off(tg, sA);
+  B += bm.b_off(tg, sB);
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + bt * sC + (long long)row * ldc + col;
+            double* c = C + tg * sC + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -251,14 +253,15 @@ __global__ __launch_bounds__(64) void k_gemm_s(int m, int n, int k, const double
                                                long long sA, const double* __restrict__ B, long long ldb,
                                                long long sB, double* __restrict__ C, long long ldc, long long sC,
                                                double alpha, double beta, int ksplit, int kchunk,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, BatchMap bm) {
   __shared__ double As[SK][SM + 1];
   __shared__ double Bs[SK][SM + 1];
   const int bz = blockIdx.z;
   const int bt = bz / ksplit;
   const int ks = bz - bt * ksplit;
-  A += bt * sA;
-  B += bt * sB;
+  const long long tg = bm.tbase + bt;
+  A += bm.a_off(tg, sA);
+  B += bm.b_off(tg, sB);
   const int m0 = blockIdx.y * SM, n0 = blockIdx.x * SM;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(64) void k_gemm_s(int m, int n, int k, const double
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + bt * sC + (long long)row * ldc + col;
+            double* c = C + tg * sC + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -862,27 +865,25 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   for (int b0 = 0; b0 < g.batch; b0 += chunk) {
     Gemm c = g;
     c.batch = std::min(chunk, g.batch - b0);
-    c.A = g.A + (long long)b0 * g.sA;
-    c.B = g.B + (long long)b0 * g.sB;
-    c.C = g.C + (long long)b0 * g.sC;
+    const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2};
     dim3 grid(ceil_div(c.n, sm ? SM : BN), ceil_div(c.m, sm ? SM : BM), c.batch * ks);
 #define LRFG_GEMM_LAUNCH(TA, TB)                                                                              \
   do {                                                                                                       \
     if (c.prec == LRFG_PREC_MIXED_FP32)                                                                      \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, false>), grid,   \
                         dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
-                        c.alpha, c.beta, ks, kchunk, part);                                                  \
+                        c.alpha, c.beta, ks, kchunk, part, bm);                                                  \
     else if (c.prec == LRFG_PREC_MIXED_BF16)                                                                 \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, true>), grid,    \
                         dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
-                        c.alpha, c.beta, ks, kchunk, part);                                                  \
+                        c.alpha, c.beta, ks, kchunk, part, bm);                                                  \
     else if (sm)                                                                                             \
       hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, \
-                         c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, kchunk, part);                            \
+                         c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, kchunk, part, bm);                            \
     else                                                                                                     \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm<TA, TB>), grid, dim3(256), 0, \
                         s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
-                        ks, kchunk, part);                                                                   \
+                        ks, kchunk, part, bm);                                                                 \
   } while (0)
     if (!c.ta && !c.tb) LRFG_GEMM_LAUNCH(false, false);
     else if (c.ta && !c.tb) LRFG_GEMM_LAUNCH(true, false);
@@ -894,7 +895,7 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
       const long long tot = (long long)c.batch * c.m * c.n;
       const int gr = (int)((tot + 31) / 32);
       hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, c.m, c.n, ks, c.batch, (const double*)part,
-                         c.C, c.ldc, c.sC, c.alpha, c.beta);
+                         c.C + (long long)b0 * c.sC, c.ldc, c.sC, c.alpha, c.beta);
       LRFG_LAUNCHED();
     }
   }

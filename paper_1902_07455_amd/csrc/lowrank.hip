@@ -244,8 +244,9 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   C.done = ar.take<int>(nE);
   C.ones = ar.take<double>(nE);
   C.mones = ar.take<double>(nE);
-  // dot scratch: largest pair (kr, c) or (a, a)
-  size_t dn = tt_dot_scratch(C.kr, C.z, nE);
+  // dot scratch: largest pair (kr, c) or (a, a); the A_H cross terms take
+  // up to 3 pairs per system
+  size_t dn = tt_dot_scratch(C.kr, C.z, 3 * nE);
   dn = std::max(dn, tt_dot_scratch(C.a, C.a, nE));
   C.dscr_n = dn;
   C.dscr = ar.take<double>(dn);
@@ -842,21 +843,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     std::vector<double> v(nE);
     LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
     for (int e = 0; e < nE; ++e) m1[(size_t)e * d + al] = v[e] / Ntot;
-    // m2: <a (.) g_i, g_j> within each microstructure
+    // m2: <a (.) g_i, g_j> for every pair within each microstructure, one pass
     LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-    for (int b = 0; b < nB; ++b) {
-      for (int i = 0; i < nEp; ++i) {
-        for (int j = 0; j < nEp; ++j) {
-          const int ei = b * nEp + i, ej = b * nEp + j;
-          TTB ki = C.kr, gj = g;
-          for (int q = 0; q < d; ++q) {
-            ki.c[q] = C.kr.c[q] + ei * C.kr.s[q];
-            gj.c[q] = g.c[q] + ej * g.s[q];
-          }
-          LRFG_TRY(tt_dot(ki, gj, C.dots + (size_t)ei * nEp + j, C.dscr, 1, s));
-        }
-      }
-    }
+    LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s, nEp));
     std::vector<double> w2((size_t)nE * nEp);
     LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nEp));
     for (size_t k = 0; k < w2.size(); ++k) m2[k * d + al] = w2[k] / Ntot;

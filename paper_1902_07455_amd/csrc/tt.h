@@ -69,8 +69,11 @@ int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s);
 // out = sum of terms as one TT with block carriages (ranks add); out's
 // ranks must equal the sums of the terms' ranks.
 int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s);
-// dots[e] = <x_e, y_e>; scratch of tt_dot_scratch doubles.
+// dots[e] = <x_e, y_e>; scratch of tt_dot_scratch(x, y, nE) doubles.  With
+// pairs = P > 0 (nE a multiple of P): dots[e P + j] = <x_e, y_{(e/P) P + j}>,
+// every pair within each group of P systems, scratch of
+// tt_dot_scratch(x, y, nE P) doubles.
 size_t tt_dot_scratch(const TTB& x, const TTB& y, int nE);
-int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s);
+int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s, int pairs = 0);
 
 }  // namespace lrfg

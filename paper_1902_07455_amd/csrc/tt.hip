@@ -237,23 +237,39 @@ size_t tt_dot_scratch(const TTB& x, const TTB& y, int nE) {
   return n * nE + 4096 + kDotSplitK;               // + split-K space
 }
 
-int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s) {
+int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hipStream_t s, int pairs) {
   const int d = x.d;
   // M_0 = 1; U_j = M_{j-1} Y_j  (x.r[j] x N y.r[j+1]); M_j = X_j^T U_j
   // (contraction over (r_{j-1}, n)); the last step contracts everything.
+  // With pairs = P the batch runs over t = e P + j: x system e with y system
+  // (e / P) P + j, so every pair within each group of P systems in one pass.
+  const int P = pairs > 0 ? pairs : 1;
+  const int T = pairs > 0 ? nE * P : nE;
   double* M = nullptr;  // previous M, (x.r[j] x y.r[j]) per system
   long long sM = 0;
   double* p = scratch;
-  double* gs = scratch + tt_dot_scratch(x, y, nE) - kDotSplitK;
+  double* gs = scratch + tt_dot_scratch(x, y, T) - kDotSplitK;
   const size_t gsn = kDotSplitK;
+  // y system of pair t as a batch map on the B operand
+  auto map_y = [&](Gemm& g, long long sy) {
+    if (pairs > 0) {
+      g.bdiv = P * P;
+      g.sB = sy * P;
+      g.bmod = P;
+      g.sB2 = sy;
+    } else {
+      g.sB = sy;
+    }
+  };
   for (int j = 0; j < d; ++j) {
     const int a0 = x.r[j], a1 = x.r[j + 1], b0 = y.r[j], b1 = y.r[j + 1], N = y.N[j];
     // U = M Y_j : (a0 x b0)(b0 x N b1); j = 0 -> U = Y_0 (a0 = b0 = 1)
     const double* U = y.c[j];
     long long sU = y.s[j];
+    bool u_is_y = true;
     if (j > 0) {
       double* Ub = p;
-      p += (size_t)a0 * N * b1 * nE;
+      p += (size_t)a0 * N * b1 * T;
       Gemm g;
       g.m = a0;
       g.n = N * b1;
@@ -263,18 +279,19 @@ int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hi
       g.sA = sM;
       g.B = y.c[j];
       g.ldb = (long long)N * b1;
-      g.sB = y.s[j];
+      map_y(g, y.s[j]);
       g.C = Ub;
       g.ldc = (long long)N * b1;
       g.sC = (long long)a0 * N * b1;
-      g.batch = nE;
+      g.batch = T;
       LRFG_TRY(gemm(g, gs, gsn, s));
       U = Ub;
       sU = g.sC;
+      u_is_y = false;
     }
     // M_j = X_j^T U : (a1 x a0 N)(a0 N x b1)
     double* Mn = (j == d - 1) ? dots : p;
-    if (j < d - 1) p += (size_t)a1 * b1 * nE;
+    if (j < d - 1) p += (size_t)a1 * b1 * T;
     Gemm g;
     g.m = a1;
     g.n = b1;
@@ -282,14 +299,15 @@ int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hi
     g.A = x.c[j];
     g.lda = a1;
     g.sA = x.s[j];
+    g.adiv = P;
     g.ta = true;
     g.B = U;
     g.ldb = b1;
-    g.sB = sU;
+    if (u_is_y) map_y(g, sU); else g.sB = sU;
     g.C = Mn;
     g.ldc = b1;
     g.sC = (j == d - 1) ? 1 : (long long)a1 * b1;
-    g.batch = nE;
+    g.batch = T;
     LRFG_TRY(gemm(g, gs, gsn, s));
     M = Mn;
     sM = g.sC;
