@@ -78,7 +78,10 @@ typedef enum {
  * for FP32, max(solver_tol, 1e-2) for BF16), while the correction update,
  * the residual b - K x, the small factorisations of the truncation, the
  * solver scalars and A_H stay FP64; it stops when the FP64 preconditioned
- * residual reaches solver_tol or stops decreasing. */
+ * residual reaches solver_tol or when two outer steps in a row fail to
+ * lower the energy form of A_H E.E (Sec. 4.3) by solver_tol^2 of itself,
+ * and returns the lowest-energy iterate.  Under BF16 the first outer step
+ * without an energy gain moves the remaining inner solves to FP32. */
 typedef enum {
   LRFG_PREC_FP64 = 0,
   LRFG_PREC_MIXED_FP32 = 1,

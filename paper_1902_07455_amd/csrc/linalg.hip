@@ -14,47 +14,59 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64;  // tile of the mixed-precision kernel
 
-// Tile 64 x 64 per 256-thread block; wave w = (wm, wn) in 2 x 2 computes a
-// 32 x 32 sub-tile as 2 x 2 MFMA 16 x 16 blocks.  MFMA f64 16x16x4 lane
+// Block of 4 waves (256 threads) in a WM x WN x WK layout (WM WN WK = 4):
+// the block tile is (32 WM) x (32 WN); each wave computes a 32 x 32 sub-tile
+// as 2 x 2 MFMA 16 x 16 blocks and, with WK > 1, the WK waves that share a
+// sub-tile take disjoint 16-wide quarters of each K slab (TK = 16 WK) and
+// add their sums through LDS at the end in a fixed order.  MFMA blocks that
+// lie wholly outside the m x n output are skipped (a wave-uniform test), so
+// a small output does not pay for the padded tile.  MFMA f64 16x16x4 lane
 // layout: A operand lane l -> A[l % 16][l / 16]; B operand lane l ->
 // B[l / 16][l % 16]; result lane l holds D[l / 16 + 4 i][l % 16], i < 4.
 // With `part` != null the raw product of this K split is stored to
 // part[(bz * m + row) * n + col] for a later reduction.
-template <bool TA, bool TB>
+template <bool TA, bool TB, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double* __restrict__ A,
                                               long long lda, long long sA, const double* __restrict__ B,
                                               long long ldb, long long sB, double* __restrict__ C,
                                               long long ldc, long long sC, double alpha, double beta,
                                               int ksplit, int kchunk, double* __restrict__ part, BatchMap bm) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  constexpr int WK = 4 / (WM * WN);
+  constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16 * WK;
+  constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  __shared__ double red[WK > 1 ? (WK - 1) * (WM * WN) * 16 * 64 : 1];
   const int bz = blockIdx.z;
   const int bt = bz / ksplit;
   const int ks = bz - bt * ksplit;
   const long long tg = bm.tbase + bt;
   A += bm.a_off(tg, sA);
   B += bm.b_off(tg, sB);
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  constexpr int RA = (BM * BK) / 256, RB = (BK * BN) / 256;
+  const int wk = wave / (WM * WN), wr = wave - wk * (WM * WN);
+  const int wm = wr / WN, wn = wr - (wr / WN) * WN;
+  // which of the wave's 2 x 2 MFMA blocks touch the output
+  const bool r0 = m0 + wm * 32 < m, r1 = m0 + wm * 32 + 16 < m;
+  const bool c0 = n0 + wn * 32 < n, c1 = n0 + wn * 32 + 16 < n;
   dbl4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // register prefetch of the next K tile while the current one is multiplied
+  // register prefetch of the next K slab while the current one is multiplied
   double pa[RA], pb[RB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const int e = threadIdx.x + r * 256;
       int i, kk;
-      if (!TA) { i = e / BK; kk = e % BK; } else { kk = e / BM; i = e % BM; }
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
       const int gi = m0 + i, gk = k0 + kk;
       pa[r] = (gi < m && gk < ke) ? (TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk]) : 0.0;
     }
@@ -62,44 +74,69 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
     for (int r = 0; r < RB; ++r) {
       const int e = threadIdx.x + r * 256;
       int kk, j;
-      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / BK; kk = e % BK; }
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
       const int gk = k0 + kk, gj = n0 + j;
       pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
     }
   };
   if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += BK) {
+  for (int k0 = kb; k0 < ke; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const int e = threadIdx.x + r * 256;
       int i, kk;
-      if (!TA) { i = e / BK; kk = e % BK; } else { kk = e / BM; i = e % BM; }
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
       As[kk][i] = pa[r];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int e = threadIdx.x + r * 256;
       int kk, j;
-      if (!TB) { kk = e / BN; j = e % BN; } else { j = e / BK; kk = e % BK; }
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
       Bs[kk][j] = pb[r];
     }
     __syncthreads();
-    if (k0 + BK < ke) fetch(k0 + BK);
+    if (k0 + TK < ke) fetch(k0 + TK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int kq = 0; kq < 16; kq += 4) {
+      const int kk = wk * 16 + kq;
       double a[2], b[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) a[bi] = As[kk + (lane >> 4)][wm * 32 + bi * 16 + (lane & 15)];
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[kk + (lane >> 4)][wn * 32 + bj * 16 + (lane & 15)];
+      if (r0 && c0) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc[0][0], 0, 0, 0);
+      if (r0 && c1) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[1], acc[0][1], 0, 0, 0);
+      if (r1 && c0) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[0], acc[1][0], 0, 0, 0);
+      if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (WK > 1) {
+    // waves wk > 0 hand their sums to the wave wk = 0 of their sub-tile
+    // through LDS
+    if (wk > 0) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            red[((((wk - 1) * (WM * WN) + wr) * 16) + (bi * 2 + bj) * 4 + r) * 64 + lane] = acc[bi][bj][r];
     }
     __syncthreads();
+    if (wk == 0) {
+#pragma unroll
+      for (int q = 0; q < WK - 1; ++q)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] += red[(((q * (WM * WN) + wr) * 16) + (bi * 2 + bj) * 4 + r) * 64 + lane];
+    }
   }
+  if (wk != 0) return;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -245,89 +282,6 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
       }
 }
 
-// Skinny variant: 32 x 32 tile per 64-thread block (one wave computing
-// 2 x 2 MFMA 16 x 16 blocks), for shapes whose m or n is at most 32.
-constexpr int SM = 32, SK = 16;
-template <bool TA, bool TB>
-__global__ __launch_bounds__(64) void k_gemm_s(int m, int n, int k, const double* __restrict__ A, long long lda,
-                                               long long sA, const double* __restrict__ B, long long ldb,
-                                               long long sB, double* __restrict__ C, long long ldc, long long sC,
-                                               double alpha, double beta, int ksplit, int kchunk,
-                                               double* __restrict__ part, BatchMap bm) {
-  __shared__ double As[SK][SM + 1];
-  __shared__ double Bs[SK][SM + 1];
-  const int bz = blockIdx.z;
-  const int bt = bz / ksplit;
-  const int ks = bz - bt * ksplit;
-  const long long tg = bm.tbase + bt;
-  A += bm.a_off(tg, sA);
-  B += bm.b_off(tg, sB);
-  const int m0 = blockIdx.y * SM, n0 = blockIdx.x * SM;
-  const int kb = ks * kchunk;
-  const int ke = min(k, kb + kchunk);
-  const int lane = threadIdx.x;
-  dbl4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += SK) {
-#pragma unroll
-    for (int r = 0; r < (SM * SK) / 64; ++r) {
-      const int e = lane + r * 64;
-      int i, kk;
-      if (!TA) { i = e / SK; kk = e % SK; } else { kk = e / SM; i = e % SM; }
-      const int gi = m0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < m && gk < ke) v = TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk];
-      As[kk][i] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < (SK * SM) / 64; ++r) {
-      const int e = lane + r * 64;
-      int kk, j;
-      if (!TB) { kk = e / SM; j = e % SM; } else { j = e / SK; kk = e % SK; }
-      const int gk = k0 + kk, gj = n0 + j;
-      double v = 0.0;
-      if (gj < n && gk < ke) v = TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj];
-      Bs[kk][j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < SK; kk += 4) {
-      double a[2], b[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) a[bi] = As[kk + (lane >> 4)][bi * 16 + (lane & 15)];
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[kk + (lane >> 4)][bj * 16 + (lane & 15)];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + bi * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + bj * 16 + (lane & 15);
-        if (row < m && col < n) {
-          const double v = acc[bi][bj][r];
-          if (part != nullptr) {
-            part[((long long)bz * m + row) * n + col] = v;
-          } else {
-            double* c = C + tg * sC + (long long)row * ldc + col;
-            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
-          }
-        }
-      }
-}
-
 // C = alpha * sum_ks part[ks] + beta * C.  The partials were just written
 // from every XCD, so they come from HBM / the Infinity Cache: a block
 // spreads the splits of 32 outputs over 8 thread groups, each with eight
@@ -365,17 +319,29 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
   }
 }
 
-// The one-wave 32 x 32 tile measured slower than the 64 x 64 tile on the
-// truncation's shapes (more blocks, same K loop), so it is not selected.
-bool use_small(const Gemm&) { return false; }
+// Wave layout of k_gemm for one matrix's shape: outputs of at most 32 x 32
+// split K four ways inside the block, narrow outputs stack the waves along
+// the long side, the rest use the 2 x 2 layout of 64 x 64 tiles.
+struct GemmLayout {
+  int wm, wn;
+  int tm() const { return 32 * wm; }
+  int tn() const { return 32 * wn; }
+  int tk() const { return 16 * (4 / (wm * wn)); }
+};
+GemmLayout gemm_layout(const Gemm& g) {
+  if (g.m <= 32 && g.n <= 32) return {1, 1};
+  if (g.n <= 32) return g.m <= 64 ? GemmLayout{2, 1} : GemmLayout{4, 1};
+  if (g.m <= 32) return g.n <= 64 ? GemmLayout{1, 2} : GemmLayout{1, 4};
+  return {2, 2};
+}
 
 // K splits from the shape of one matrix only, so a matrix gets the same
 // summation order whatever the batch it travels in (batched solves
 // reproduce single solves bit for bit).
 int choose_ksplit(const Gemm& g) {
-  const bool sm = use_small(g);
-  const int tm = sm ? SM : BM, tn = sm ? SM : BN;
-  const long long tiles = (long long)ceil_div(g.m, tm) * ceil_div(g.n, tn);
+  const bool lp = g.prec != 0;
+  const GemmLayout L = lp ? GemmLayout{2, 2} : gemm_layout(g);
+  const long long tiles = (long long)ceil_div(g.m, L.tm()) * ceil_div(g.n, L.tn());
   if (tiles >= 128 || g.k < 256) return 1;
   long long ks = 512 / tiles;
   const long long kmax = g.k / 64;  // at least 64 of K per split
@@ -850,9 +816,9 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     if ((size_t)ks > fit) ks = (int)fit;
     if (ks < 2) ks = 1;
   }
-  const int KQ = g.prec != 0 ? LK : BK;  // K tile of the kernel used
+  const GemmLayout lay = g.prec != 0 ? GemmLayout{2, 2} : gemm_layout(g);
+  const int KQ = g.prec != 0 ? LK : lay.tk();  // K slab of the kernel used
   const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + KQ - 1) / KQ * KQ : (g.k > 0 ? g.k : 1);
-  // (a multiple of BK is one of SK too)
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
   // matrices per launch: all of them, or as many as the split partials fit
   int chunk = g.batch;
@@ -860,36 +826,40 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     const size_t per = (size_t)ks * g.m * g.n;
     chunk = (int)std::min<size_t>((size_t)g.batch, scratch_doubles / per);
   }
-  const bool sm = use_small(g);
   double* part = ks > 1 ? scratch : nullptr;
   for (int b0 = 0; b0 < g.batch; b0 += chunk) {
     Gemm c = g;
     c.batch = std::min(chunk, g.batch - b0);
     const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2};
-    dim3 grid(ceil_div(c.n, sm ? SM : BN), ceil_div(c.m, sm ? SM : BM), c.batch * ks);
+    const int gtm = c.prec != 0 ? BM : lay.tm(), gtn = c.prec != 0 ? BN : lay.tn();
+    dim3 grid(ceil_div(c.n, gtn), ceil_div(c.m, gtm), c.batch * ks);
+#define LRFG_GEMM_F64(TA, TB, WM, WN)                                                                         \
+  LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm<TA, TB, WM, WN>), grid, dim3(256), \
+                    0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, \
+                    kchunk, part, bm)
 #define LRFG_GEMM_LAUNCH(TA, TB)                                                                              \
   do {                                                                                                       \
     if (c.prec == LRFG_PREC_MIXED_FP32)                                                                      \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, false>), grid,   \
                         dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
-                        c.alpha, c.beta, ks, kchunk, part, bm);                                                  \
+                        c.alpha, c.beta, ks, kchunk, part, bm);                                              \
     else if (c.prec == LRFG_PREC_MIXED_BF16)                                                                 \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm_lp<TA, TB, true>), grid,    \
                         dim3(256), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC,   \
-                        c.alpha, c.beta, ks, kchunk, part, bm);                                                  \
-    else if (sm)                                                                                             \
-      hipLaunchKernelGGL((k_gemm_s<TA, TB>), grid, dim3(64), 0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, \
-                         c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, ks, kchunk, part, bm);                            \
-    else                                                                                                     \
-      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm<TA, TB>), grid, dim3(256), 0, \
-                        s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
-                        ks, kchunk, part, bm);                                                                 \
+                        c.alpha, c.beta, ks, kchunk, part, bm);                                              \
+    else if (lay.wm == 1 && lay.wn == 1) LRFG_GEMM_F64(TA, TB, 1, 1);                                         \
+    else if (lay.wm == 2 && lay.wn == 1) LRFG_GEMM_F64(TA, TB, 2, 1);                                         \
+    else if (lay.wm == 4 && lay.wn == 1) LRFG_GEMM_F64(TA, TB, 4, 1);                                         \
+    else if (lay.wm == 1 && lay.wn == 2) LRFG_GEMM_F64(TA, TB, 1, 2);                                         \
+    else if (lay.wm == 1 && lay.wn == 4) LRFG_GEMM_F64(TA, TB, 1, 4);                                         \
+    else LRFG_GEMM_F64(TA, TB, 2, 2);                                                                         \
   } while (0)
     if (!c.ta && !c.tb) LRFG_GEMM_LAUNCH(false, false);
     else if (c.ta && !c.tb) LRFG_GEMM_LAUNCH(true, false);
     else if (!c.ta && c.tb) LRFG_GEMM_LAUNCH(false, true);
     else LRFG_GEMM_LAUNCH(true, true);
 #undef LRFG_GEMM_LAUNCH
+#undef LRFG_GEMM_F64
     LRFG_LAUNCHED();
     if (ks > 1) {
       const long long tot = (long long)c.batch * c.m * c.n;

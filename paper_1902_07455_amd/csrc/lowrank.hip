@@ -766,11 +766,16 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     // residual a floor set by the rank cap, so progress is judged by the
     // energy form instead (it decreases to A_H as x improves, Sec. 4.3):
     // the refinement stops when the residual reaches solver_tol or the
-    // energy stops decreasing by more than solver_tol^2 of itself, and keeps
-    // the lowest-energy iterate.  The FP64 residual history (relative to
+    // energy has failed twice in a row to decrease by more than
+    // solver_tol^2 of itself, and keeps the lowest-energy iterate.  A BF16
+    // inner solve can return a correction that makes the iterate worse (its
+    // 8-bit significands perturb the truncated operator by more than the
+    // inner tolerance for some fields): the first outer step without an
+    // energy gain under BF16 moves the remaining inner solves of the call to
+    // FP32.  The FP64 residual history (relative to
     // ||P~^-1 b||) is reported; iters counts inner iterations.
-    const int lowp = P.precision;
-    const double tol_in = std::max(P.solver_tol, lowp == LRFG_PREC_MIXED_BF16 ? 1e-2 : 1e-4);
+    int lowp = P.precision;
+    double tol_in = std::max(P.solver_tol, lowp == LRFG_PREC_MIXED_BF16 ? 1e-2 : 1e-4);
     const double tol_en = std::max(P.solver_tol * P.solver_tol, 1e-15);
     LRFG_TRY(tt_fill(C.ones, nE, 1.0, s));
     LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
@@ -782,7 +787,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     LRFG_TRY(apply_P(C, C.b0, C.z));
     LRFG_TRY(dot(C, C.z, C.z, C.zz));
     LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
-    std::vector<int> odone(nE, 0), st_in(nE), capped(nE, 1);
+    std::vector<int> odone(nE, 0), st_in(nE), capped(nE, 1), no_gain(nE, 0);
     for (int e = 0; e < nE; ++e) {
       rn0[e] = std::sqrt(std::max(zzh[e], 0.0));
       if (rn0[e] <= floor_abs[e]) {
@@ -807,6 +812,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(dot(C, C.z, C.z, C.zz));
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
       LRFG_TRY(energy_diag(C.xa, en));
+      bool escalate = false;
       for (int e = 0; e < nE; ++e) {
         if (odone[e]) continue;
         const double rel = std::sqrt(std::max(zzh[e], 0.0)) / rn0[e];
@@ -818,10 +824,17 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
           kbest[e] = kx[e];
           kbest[nE + e] = kx[nE + e];
         }
-        if (rel <= P.solver_tol || !gain) {
+        no_gain[e] = gain ? 0 : no_gain[e] + 1;
+        if (!gain && lowp == LRFG_PREC_MIXED_BF16) escalate = true;
+        if (rel <= P.solver_tol || no_gain[e] >= 2) {
           odone[e] = 1;
           capped[e] = 0;
         }
+      }
+      if (escalate) {
+        lowp = LRFG_PREC_MIXED_FP32;
+        tol_in = std::max(P.solver_tol, 1e-4);
+        for (int e = 0; e < nE; ++e) no_gain[e] = 0;
       }
     }
     for (int e = 0; e < nE; ++e) status[e] = capped[e] ? LRFG_NOT_CONVERGED : LRFG_OK;

@@ -120,10 +120,11 @@ def test_solve_untruncated_equals_full(dev, solver):
     r = s.solve(cp=(cp.weights, cp.factors))
     o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
     assert _rel(r.A_H, o.A_H) <= 1e-10
-    # the Gram-based truncation resolves directions down to about 1e-8 of
-    # the largest, which floors the residual there (A_H is quadratic in it)
+    # the Gram-based truncation resolves directions down to about
+    # sqrt(machine eps) ~ 1.5e-8 of the largest, which floors the residual at
+    # a small multiple of that (A_H, quadratic in the error, stays at 1e-10)
     for e in range(3):
-        assert np.min(r.res_hist[e][:r.iters[e]]) <= 1e-8
+        assert np.min(r.res_hist[e][:r.iters[e]]) <= 1e-7
 
 
 def test_solve_laminate_closed_form(dev):
