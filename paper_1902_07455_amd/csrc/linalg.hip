@@ -591,10 +591,18 @@ __device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L
         for (int j = rj; j < n; j += CG) g[ri * n + j] -= li * lk[j];
     }
     if (Z != nullptr && zl >= 0 && zl < n) {
+      // four independent partial sums keep several LDS loads in flight
       const int p = bc[1];
-      double acc = (zl == p) ? 1.0 : 0.0;
-      for (int j = 0; j < k; ++j) acc -= L[j * n + p] * Z[j * n + zl];
-      Z[k * n + zl] = acc / lk[p];
+      double a0 = (zl == p) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = 0;
+      for (; j + 3 < k; j += 4) {
+        a0 -= L[j * n + p] * Z[j * n + zl];
+        a1 -= L[(j + 1) * n + p] * Z[(j + 1) * n + zl];
+        a2 -= L[(j + 2) * n + p] * Z[(j + 2) * n + zl];
+        a3 -= L[(j + 3) * n + p] * Z[(j + 3) * n + zl];
+      }
+      for (; j < k; ++j) a0 -= L[j * n + p] * Z[j * n + zl];
+      Z[k * n + zl] = ((a0 + a1) + (a2 + a3)) / lk[p];
     }
     __syncthreads();
   }
@@ -658,9 +666,11 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
                                                  double tau, double eps, double tol2, double floor_rel,
                                                  double* __restrict__ Sg, long long sS, int* __restrict__ kept_out,
                                                  int* __restrict__ sweeps_out) {
+  constexpr int NP = 8 * NE;  // padded column length
   extern __shared__ double sm[];
   double* g = sm;
-  double* W = sm + n * n;  // column j of W = row j of L
+  double* L = sm + n * n;          // rows of the pivoted Cholesky factor
+  double* W = sm + 2 * n * n;      // column j of W = row j of L, zero-padded to NP
   __shared__ int perm[64];
   __shared__ int order[64];
   __shared__ double lam[64];
@@ -679,8 +689,14 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (tid == 0) trace_s = t;
   }
-  const int r = pchol_block<NT>(n, g, W, nullptr, perm, tau, bc);
-  // one-sided Jacobi on columns 0..r-1 of W (length n)
+  const int r = pchol_block<NT>(n, g, L, nullptr, perm, tau, bc);
+  for (int e = tid; e < r * NP; e += NT) {
+    const int j = e / NP, i = e - (e / NP) * NP;
+    W[e] = (i < n) ? L[j * n + i] : 0.0;
+  }
+  __syncthreads();
+  // one-sided Jacobi on columns 0..r-1 of W (the zero padding rotates into
+  // zeros, so the lanes need no bounds tests)
   const int sub = tid & 7, grp = tid >> 3;
   const int m = r + (r & 1), np = m / 2;
   const double eps2 = (eps * n) * (eps * n);
@@ -707,8 +723,8 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
 #pragma unroll
           for (int t = 0; t < NE; ++t) {
             const int i = sub + 8 * t;
-            wp[t] = (i < n) ? W[p * n + i] : 0.0;
-            wq[t] = (i < n) ? W[q * n + i] : 0.0;
+            wp[t] = W[p * NP + i];
+            wq[t] = W[q * NP + i];
             a += wp[t] * wp[t];
             bb += wq[t] * wq[t];
             gg += wp[t] * wq[t];
@@ -717,26 +733,26 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
           bb = sum8(bb);
           gg = sum8(gg);
           if (gg * gg > eps2 * a * bb) {
-            // rotation angle in reduced precision is harmless (any angle is
-            // a rotation; only the pair's next inner product depends on
-            // it); c is refined so that c^2 (1 + t^2) = 1 to rounding
-            const double z = (bb - a) * 0.5 * rcp_nr(gg);
+            // the rotation angle comes from the hardware estimates alone:
+            // any angle gives an orthogonal rotation, and an angle off by
+            // the estimates' relative error leaves the pair's inner product
+            // at that fraction of its old value for the next sweep; c is
+            // refined so that c^2 (1 + t^2) = 1 to rounding
+            const double z = (bb - a) * 0.5 * __builtin_amdgcn_rcp(gg);
             double t;
             if (fabs(z) > 1e150) {
-              t = 0.5 * rcp_nr(z);
+              t = 0.5 * __builtin_amdgcn_rcp(z);
             } else {
               const double w = 1.0 + z * z;
-              const double sq = w * rsq_nr(w);
-              t = (z >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(z) + sq);
+              const double sq = w * __builtin_amdgcn_rsq(w);
+              t = (z >= 0.0 ? 1.0 : -1.0) * __builtin_amdgcn_rcp(fabs(z) + sq);
             }
             const double cs = rsq_nr(1.0 + t * t), sn = t * cs;
 #pragma unroll
             for (int tt = 0; tt < NE; ++tt) {
               const int i = sub + 8 * tt;
-              if (i < n) {
-                W[p * n + i] = cs * wp[tt] - sn * wq[tt];
-                W[q * n + i] = sn * wp[tt] + cs * wq[tt];
-              }
+              W[p * NP + i] = cs * wp[tt] - sn * wq[tt];
+              W[q * NP + i] = sn * wp[tt] + cs * wq[tt];
             }
             if (sub == 0 && gg * gg > big2 * a * bb) flags[sweep] = 1;
           }
@@ -749,7 +765,7 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   // eigenvalues, order by decreasing value (ties: lower index first)
   if (tid < r) {
     double v = 0.0;
-    for (int i = 0; i < n; ++i) v += W[tid * n + i] * W[tid * n + i];
+    for (int i = 0; i < n; ++i) v += W[tid * NP + i] * W[tid * NP + i];
     lam[tid] = v;
   }
   __syncthreads();
@@ -792,7 +808,7 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
     double v = 0.0;
     if (j < kept) {
       const int col = order[j];
-      v = W[col * n + i] / sqrt(lam[col]);
+      v = W[col * NP + i] / sqrt(lam[col]);
     }
     S[e] = v;
   }
@@ -915,13 +931,14 @@ int cut_psd(int n, int c, const double* G, long long sG, double tol2, double* S,
     return LRFG_EINVAL;
   }
   if (batch <= 0) return LRFG_OK;
-  const size_t shm = sizeof(double) * 2 * n * n;
+  const int np_ = n <= 16 ? 16 : (n <= 32 ? 32 : 64);  // padded column length of the launched variant
+  const size_t shm = sizeof(double) * (2 * n * n + (size_t)n * np_);
   ProfScope ps_("cut", s);
 #define LRFG_CUT_LAUNCH(NT, NE)                                                                               \
   do {                                                                                                       \
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cut_psd<NT, NE>),    \
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,          \
-                                                       (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));       \
+                                                       (int)(sizeof(double) * 3 * kMaxEig * kMaxEig));       \
     (void)attr;                                                                                              \
     hipLaunchKernelGGL((k_cut_psd<NT, NE>), dim3(batch), dim3(NT), shm, s, n, c, G, sG, kCutTau, kCutEps,     \
                        tol2, kCutFloor, S, sS, kept, sweeps);                                                \
