@@ -114,8 +114,15 @@ typedef struct {
  * `factors[i]` (R x N_i, row-major) -- every coefficient of the paper's
  * workloads is given this way (Sec. 4.1: rank 2 inclusions, rank-limited
  * smooth fields) -- or in TT form (`tt_cores[i]`, [r_{i-1}][N_i][r_i],
- * tt_ranks[0..d]).  Exactly one of full / weights / tt_cores is non-NULL.
- * Pointers are host addresses unless on_device != 0.  Borrowed for the call.
+ * tt_ranks[0..d]) -- or, for the Tucker format (d = 3), in Tucker form
+ * (Sec. 3.1.2: a = core x_1 U_1 x_2 U_2 x_3 U_3; `tucker_core`
+ * [r_1][r_2][r_3], `tucker_frames[i]` N_i x r_i row-major, i.e. the columns
+ * are the mode vectors, tucker_ranks[0..2]; lrfg_compress_tucker writes this
+ * layout).  Exactly one of full / weights / tt_cores / tucker_core is
+ * non-NULL.  The full-grid format takes full, CP or TT coefficients, the TT
+ * and CP formats CP or TT, the Tucker format CP or Tucker (anything else:
+ * LRFG_EUNSUPPORTED).  Pointers are host addresses unless on_device != 0.
+ * Borrowed for the call.
  */
 typedef struct {
   int on_device;
@@ -125,6 +132,9 @@ typedef struct {
   const double* factors[3];       /* CP form: R x N_i                           */
   int tt_ranks[4];                /* TT form: r_0..r_d (r_0 = r_d = 1)           */
   const double* tt_cores[3];      /* TT form                                    */
+  int tucker_ranks[3];            /* Tucker form: r_1..r_3                      */
+  const double* tucker_core;      /* Tucker form: [r_1][r_2][r_3]               */
+  const double* tucker_frames[3]; /* Tucker form: N_i x r_i                      */
 } lrfg_coeff;
 
 /* Results, host memory owned by the caller (any pointer may be NULL). */
@@ -319,6 +329,23 @@ size_t lrfg_compress_workspace_bytes(int d, const int N[3], int cap, int oversam
 int lrfg_compress_tt(int d, const int N[3], const double* a, int cap, double tol, int oversample,
                      uint64_t seed, double* const* out_cores, int* out_ranks, int* kept, void* d_ws,
                      size_t ws_bytes, void* stream);
+
+/* Coefficient compression to the Tucker form (setup of the Tucker path,
+ * Sec. 3.1.2 and Appendix A.2): the full field a (device, N1 x N2 x N3,
+ * C order) as a Tucker tensor with mode ranks at most cap, the fewest
+ * directions per mode whose dropped singular values of the unfolding
+ * satisfy ||dropped||^2 <= tol^2 ||a||^2 / 3 (tol = 0: cap only).  The
+ * field enters as the exact Tucker tensor (core a, identity frames) and
+ * goes through the randomised HOSVD of lrfg_tucker_round (sketch size
+ * min(cap + oversample, 64)).  out_frames[j] (device) receive N_j x c_j,
+ * out_core c_1 x c_2 x c_3, c_j = min(cap, N_j) (out_ranks, host, 3 ints;
+ * directions beyond the kept rank are zero); kept (host, 3 ints, or NULL)
+ * the kept ranks.  The Tucker solve takes them as its coefficient
+ * (tucker_frames, tucker_core, tucker_ranks = out_ranks). */
+size_t lrfg_compress_tucker_workspace_bytes(const int N[3], int cap, int oversample);
+int lrfg_compress_tucker(const int N[3], const double* a, int cap, double tol, int oversample, uint64_t seed,
+                         double* const* out_frames, double* out_core, int* out_ranks, int* kept, void* d_ws,
+                         size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching on one device.

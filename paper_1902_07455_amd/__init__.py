@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "compress_tt", "tucker_round", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
+           "gemm", "syevj", "gram_cut", "compress_tt", "compress_tucker", "tucker_round", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
            "Completion"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
@@ -86,7 +86,7 @@ class SolveResult:
     solve_ms: float
 
 
-def _fill_coeff(c, h, full=None, cp=None, tt=None):
+def _fill_coeff(c, h, full=None, cp=None, tt=None, tucker=None):
     """Fill an lrfg_coeff from numpy arrays or torch tensors (kept alive by h)."""
     on_dev = 0
     if full is not None:
@@ -104,8 +104,14 @@ def _fill_coeff(c, h, full=None, cp=None, tt=None):
             c.tt_cores[i], on_dev = h.ptr(G)
             c.tt_ranks[i] = int(G.shape[0])
         c.tt_ranks[len(tt)] = int(tt[-1].shape[2])
+    elif tucker is not None:
+        core, frames = tucker
+        c.tucker_core, on_dev = h.ptr(core)
+        for i, F in enumerate(frames):
+            c.tucker_frames[i] = h.ptr(F)[0]
+            c.tucker_ranks[i] = int(F.shape[1])
     else:
-        raise ValueError("give one of full / cp / tt")
+        raise ValueError("give one of full / cp / tt / tucker")
     c.on_device = on_dev
 
 
@@ -175,10 +181,11 @@ class Solver:
             self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def solve(self, full=None, cp=None, tt=None, E=None, stream=None) -> SolveResult:
+    def solve(self, full=None, cp=None, tt=None, tucker=None, E=None, stream=None) -> SolveResult:
         """full: nodal values; cp: (weights (R,), [factors (R, N_i)]);
-        tt: list of cores [r_{i-1}][N_i][r_i].  E: (nE, d) or None."""
-        return self.solve_batch([dict(full=full, cp=cp, tt=tt)], E=E, stream=stream)[0]
+        tt: list of cores [r_{i-1}][N_i][r_i]; tucker: (core (r_1, r_2, r_3),
+        [frames (N_i, r_i)]).  E: (nE, d) or None."""
+        return self.solve_batch([dict(full=full, cp=cp, tt=tt, tucker=tucker)], E=E, stream=stream)[0]
 
     def solve_batch(self, coeffs, E=None, stream=None):
         """Several microstructures of this problem in one batched solve
@@ -190,7 +197,7 @@ class Solver:
         h = _Held(self.device)
         cs = (_lib.Coeff * len(coeffs))()
         for k, kw in enumerate(coeffs):
-            _fill_coeff(cs[k], h, kw.get("full"), kw.get("cp"), kw.get("tt"))
+            _fill_coeff(cs[k], h, kw.get("full"), kw.get("cp"), kw.get("tt"), kw.get("tucker"))
         d = self.d
         if E is None:
             nE = d
@@ -255,13 +262,14 @@ class Server:
         self._pending = {}
         self._next = 0
 
-    def submit(self, problem: dict, full=None, cp=None, tt=None, E=None, tag: Optional[int] = None) -> int:
+    def submit(self, problem: dict, full=None, cp=None, tt=None, tucker=None, E=None,
+               tag: Optional[int] = None) -> int:
         """Queue one request; problem holds Solver's keyword arguments
         (d, N, format, rank_cap, ...).  Returns its tag."""
         h = _Held(self.device)
         pr = _make_problem(**problem)
         c = _lib.Coeff()
-        _fill_coeff(c, h, full, cp, tt)
+        _fill_coeff(c, h, full, cp, tt, tucker)
         d = pr.d
         if E is None:
             nE, Eptr = d, None
@@ -476,6 +484,30 @@ def compress_tt(a, cap: int, tol: float = 0.0, oversample: int = 10, seed: int =
                              optr, ranks, kept, C.c_void_p(ws.data_ptr()), ws.numel(),
                              C.c_void_p(_stream_handle(stream))))
     return outs, [int(kept[j]) for j in range(d - 1)]
+
+
+def compress_tucker(a, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):
+    """Full field a (float64 CUDA tensor, 3 dims) -> ((core (c_1, c_2, c_3),
+    [frames (N_j, c_j)]) as CUDA tensors with the nominal ranks, kept ranks)."""
+    torch = _torch()
+    L = lib()
+    Ns = list(a.shape)
+    Nc = (C.c_int * 3)(*Ns)
+    nb = L.lrfg_compress_tucker_workspace_bytes(Nc, int(cap), int(oversample))
+    if nb == 0:
+        raise LrfgError(-1, "bad compression sizes")
+    ws = _ws_tensor(nb, a.device)
+    c = [min(cap, n) for n in Ns]
+    frames = [torch.empty((Ns[j], c[j]), dtype=torch.float64, device=a.device) for j in range(3)]
+    core = torch.empty(tuple(c), dtype=torch.float64, device=a.device)
+    fptr = (C.c_void_p * 3)(*[F.data_ptr() for F in frames])
+    ranks = (C.c_int * 3)()
+    kept = (C.c_int * 3)()
+    a = a.contiguous()
+    check(L.lrfg_compress_tucker(Nc, C.c_void_p(a.data_ptr()), int(cap), float(tol), int(oversample), int(seed),
+                                 fptr, C.c_void_p(core.data_ptr()), ranks, kept, C.c_void_p(ws.data_ptr()),
+                                 ws.numel(), C.c_void_p(_stream_handle(stream))))
+    return (core, frames), [int(kept[j]) for j in range(3)]
 
 
 def tt_round(cores, cap: int, tol: float = 0.0, oversample: int = 10, seed: int = 0, stream=None):

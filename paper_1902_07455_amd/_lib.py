@@ -49,6 +49,9 @@ class Coeff(C.Structure):
         ("factors", C.c_void_p * 3),
         ("tt_ranks", C.c_int * 4),
         ("tt_cores", C.c_void_p * 3),
+        ("tucker_ranks", C.c_int * 3),
+        ("tucker_core", C.c_void_p),
+        ("tucker_frames", C.c_void_p * 3),
     ]
 
 
@@ -90,7 +93,7 @@ EXPORTS = [
     "lrfg_server_poll", "lrfg_server_pending", "lrfg_server_destroy", "lrfg_plan_destroy",
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
-    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_gemm_mixed", "lrfg_syevj", "lrfg_gram_cut", "lrfg_compress_workspace_bytes", "lrfg_tucker_round_workspace_bytes", "lrfg_tucker_round", "lrfg_compress_tt", "lrfg_tt_round_workspace_bytes",
+    "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_gemm_mixed", "lrfg_syevj", "lrfg_gram_cut", "lrfg_compress_workspace_bytes", "lrfg_tucker_round_workspace_bytes", "lrfg_tucker_round", "lrfg_compress_tt", "lrfg_compress_tucker_workspace_bytes", "lrfg_compress_tucker", "lrfg_tt_round_workspace_bytes",
     "lrfg_tt_round",
 ]
 
@@ -177,6 +180,12 @@ def lib():
                                    C.c_uint64, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.c_void_p, C.c_size_t, C.c_void_p]
     L.lrfg_compress_tt.restype = C.c_int
+    L.lrfg_compress_tucker_workspace_bytes.argtypes = [C.POINTER(C.c_int), C.c_int, C.c_int]
+    L.lrfg_compress_tucker_workspace_bytes.restype = C.c_size_t
+    L.lrfg_compress_tucker.argtypes = [C.POINTER(C.c_int), C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_uint64,
+                                       C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]
+    L.lrfg_compress_tucker.restype = C.c_int
     L.lrfg_tt_round_workspace_bytes.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                                 C.c_int, C.c_int, C.c_int]
     L.lrfg_tt_round_workspace_bytes.restype = C.c_size_t

@@ -255,10 +255,26 @@ static int solve_impl(lrfg_plan* plan, const lrfg_coeff* a, int count, const dou
     return LRFG_EWORKSPACE;
   }
   for (int b = 0; b < count; ++b) {
-    const int nsrc = (a[b].full != nullptr) + (a[b].weights != nullptr) + (a[b].tt_cores[0] != nullptr);
+    const int nsrc = (a[b].full != nullptr) + (a[b].weights != nullptr) + (a[b].tt_cores[0] != nullptr) +
+                     (a[b].tucker_core != nullptr);
     if (nsrc != 1) {
-      set_error("coefficient %d: exactly one of full / weights / tt_cores must be given", b);
+      set_error("coefficient %d: exactly one of full / weights / tt_cores / tucker_core must be given", b);
       return LRFG_EINVAL;
+    }
+    const bool tucker_in = a[b].tucker_core != nullptr;
+    if (tucker_in != (p.format == LRFG_FORMAT_TUCKER && a[b].weights == nullptr)) {
+      set_error("coefficient %d: the Tucker format takes CP or Tucker coefficients, and Tucker coefficients only "
+                "go with the Tucker format", b);
+      return LRFG_EUNSUPPORTED;
+    }
+    if (tucker_in) {
+      for (int j = 0; j < 3; ++j) {
+        if (a[b].tucker_frames[j] == nullptr || a[b].tucker_ranks[j] < 1 || a[b].tucker_ranks[j] > p.N[j]) {
+          set_error("coefficient %d: Tucker frame %d missing or rank %d outside [1, N]", b, j,
+                    a[b].tucker_ranks[j]);
+          return LRFG_EINVAL;
+        }
+      }
     }
   }
   LRFG_TRY(device_ok());

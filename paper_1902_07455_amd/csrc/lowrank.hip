@@ -965,6 +965,7 @@ struct TkCtx {
   double* hframe[3];        // frame buffers for D_alpha^T h_alpha
   double* aframe[3];        // frames of D_alpha a (right-hand side)
   double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
+  double* stage;            // host CP coefficient staged on the device
   int* done;
   int cap[3];
   int ra;
@@ -1036,6 +1037,7 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   C.Ecoef = ar.take<double>((size_t)3 * nE);
   C.coef2 = ar.take<double>((size_t)2 * nE);
   C.done = ar.take<int>(nE);
+  C.stage = ar.take<double>((size_t)pl->ra * (1 + N[0] + N[1] + N[2]));
   size_t dn = tk_dot_scratch(C.kr, C.z, nE);
   dn = std::max(dn, tk_dot_scratch(C.a, C.a, nE));
   dn = std::max(dn, tk_dot_scratch(C.z, C.z, nE));
@@ -1177,43 +1179,52 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     LRFG_TRY(fft_dev_upload(pl->mode[j], tw, s, &C.f[j]));
   }
   // ---------------------------------------------------------------- coefficient
-  if (ac.weights == nullptr) {
-    set_error("the Tucker path takes the coefficient in CP form");
-    return LRFG_EUNSUPPORTED;
-  }
-  const int Ra = ac.rank;
-  if (Ra < 1 || Ra > pl->ra) {
-    set_error("coefficient rank %d outside [1, coeff_rank = %d]", Ra, pl->ra);
-    return LRFG_EINVAL;
-  }
-  const double* w = ac.weights;
-  const double* f[3] = {ac.factors[0], ac.factors[1], ac.factors[2]};
-  if (!ac.on_device) {
-    size_t n = Ra;
-    for (int j = 0; j < 3; ++j) n += (size_t)Ra * pl->N[j];
-    if (n > (size_t)C.kr.usize(0) * C.nE) {
-      set_error("coefficient staging too small");
-      return LRFG_EWORKSPACE;
+  // CP form: frames f_j^T and a superdiagonal core of the weights; Tucker
+  // form: frames and core as given.
+  int ra3[3];
+  if (ac.weights != nullptr) {
+    const int Ra = ac.rank;
+    if (Ra < 1 || Ra > pl->ra) {
+      set_error("coefficient rank %d outside [1, coeff_rank = %d]", Ra, pl->ra);
+      return LRFG_EINVAL;
     }
-    double* st = C.kr.U[0];
-    LRFG_HIP(hipMemcpyAsync(st, w, sizeof(double) * Ra, hipMemcpyHostToDevice, s));
-    size_t off = Ra;
-    for (int j = 0; j < 3; ++j) {
-      LRFG_HIP(hipMemcpyAsync(st + off, ac.factors[j], sizeof(double) * Ra * pl->N[j], hipMemcpyHostToDevice, s));
-      f[j] = st + off;
-      off += (size_t)Ra * pl->N[j];
+    const double* w = ac.weights;
+    const double* f[3] = {ac.factors[0], ac.factors[1], ac.factors[2]};
+    if (!ac.on_device) {
+      double* st = C.stage;
+      LRFG_HIP(hipMemcpyAsync(st, w, sizeof(double) * Ra, hipMemcpyHostToDevice, s));
+      size_t off = Ra;
+      for (int j = 0; j < 3; ++j) {
+        LRFG_HIP(hipMemcpyAsync(st + off, ac.factors[j], sizeof(double) * Ra * pl->N[j], hipMemcpyHostToDevice, s));
+        f[j] = st + off;
+        off += (size_t)Ra * pl->N[j];
+      }
+      w = st;
     }
-    w = st;
-  }
-  for (int j = 0; j < 3; ++j) C.a.r[j] = Ra;
-  {
+    for (int j = 0; j < 3; ++j) ra3[j] = Ra;
     const long long tot = (long long)(pl->N[0] + pl->N[1] + pl->N[2]) * Ra + (long long)Ra * Ra * Ra;
     hipLaunchKernelGGL(k_cp_to_tucker, dim3((int)std::min<long long>(4096, (tot + 255) / 256)), dim3(256), 0, s, w,
                        f[0], f[1], f[2], Ra, pl->N[0], pl->N[1], pl->N[2], C.a.U[0], C.a.U[1], C.a.U[2], C.a.G);
     LRFG_LAUNCHED();
+  } else if (ac.tucker_core != nullptr) {
+    for (int j = 0; j < 3; ++j) {
+      ra3[j] = ac.tucker_ranks[j];
+      if (ra3[j] < 1 || ra3[j] > pl->ra) {
+        set_error("Tucker coefficient rank %d outside [1, coeff_rank = %d]", ra3[j], pl->ra);
+        return LRFG_EINVAL;
+      }
+    }
+    const hipMemcpyKind kind = ac.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int j = 0; j < 3; ++j)
+      LRFG_HIP(hipMemcpyAsync(C.a.U[j], ac.tucker_frames[j], sizeof(double) * pl->N[j] * ra3[j], kind, s));
+    LRFG_HIP(hipMemcpyAsync(C.a.G, ac.tucker_core, sizeof(double) * ra3[0] * ra3[1] * ra3[2], kind, s));
+  } else {
+    set_error("the Tucker path takes the coefficient in CP or Tucker form");
+    return LRFG_EUNSUPPORTED;
   }
+  for (int j = 0; j < 3; ++j) C.a.r[j] = ra3[j];
   for (int j = 0; j < 3; ++j) {
-    C.kr.r[j] = Ra * C.xr.r[j];
+    C.kr.r[j] = ra3[j] * C.xr.r[j];
     C.kr.sU[j] = C.kr.usize(j);
   }
   C.kr.sG = C.kr.gsize();
@@ -1231,7 +1242,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
       LRFG_TRY(tk_mode_apply(C.a, da[al], al, 0, 0.0, 1.0, C.f[al], 1, s));
       terms[al] = TKTerm{&da[al], C.Ecoef + al * nE, 1.0};
     }
-    int rr[3] = {3 * Ra, 3 * Ra, 3 * Ra};
+    int rr[3] = {3 * ra3[0], 3 * ra3[1], 3 * ra3[2]};
     TKB comb = tk_comb(C, rr);
     LRFG_TRY(tk_sum(terms, 3, comb, nE, s));
     LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s, nE));

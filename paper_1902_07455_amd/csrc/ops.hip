@@ -279,6 +279,69 @@ int lrfg_tucker_round(const int N[3], const int rin[3], double* const* in_frames
   return LRFG_OK;
 }
 
+size_t lrfg_compress_tucker_workspace_bytes(const int N[3], int cap, int oversample) {
+  if (N == nullptr) return 0;
+  TkRounder R;
+  int c[3];
+  if (tucker_round_sizes(N, N, cap, oversample, 1, c, R) != LRFG_OK) return 0;
+  Arena ar;
+  R.carve(ar);
+  for (int j = 0; j < 3; ++j) ar.take<double>((size_t)N[j] * N[j]);
+  return ar.used + 256;
+}
+
+int lrfg_compress_tucker(const int N[3], const double* a, int cap, double tol, int oversample, uint64_t seed,
+                         double* const* out_frames, double* out_core, int* out_ranks, int* kept, void* d_ws,
+                         size_t ws_bytes, void* stream) {
+  clear_error();
+  if (N == nullptr || a == nullptr || out_frames == nullptr || out_core == nullptr || !(tol >= 0.0)) {
+    set_error("bad arguments");
+    return LRFG_EINVAL;
+  }
+  TkRounder R;
+  int c[3];
+  LRFG_TRY(tucker_round_sizes(N, N, cap, oversample, 1, c, R));
+  R.seed = seed;
+  Arena ar;
+  ar.base = static_cast<char*>(d_ws);
+  ar.cap = ws_bytes;
+  R.carve(ar);
+  double* id[3];
+  for (int j = 0; j < 3; ++j) id[j] = ar.take<double>((size_t)N[j] * N[j]);
+  if (ar.overflow || d_ws == nullptr) {
+    set_error("workspace too small");
+    return LRFG_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int j = 0; j < 3; ++j)
+    hipLaunchKernelGGL(lrfg::k_identity, dim3(std::min(4096, (N[j] * N[j] + 255) / 256)), dim3(256), 0, s, id[j],
+                       N[j]);
+  LRFG_LAUNCHED();
+  // the exact Tucker form of the field: identity frames, the field as core
+  TKB in, out;
+  for (int j = 0; j < 3; ++j) {
+    in.N[j] = out.N[j] = N[j];
+    in.r[j] = N[j];
+    out.r[j] = c[j];
+    in.U[j] = id[j];
+    in.sU[j] = in.usize(j);
+    out.U[j] = out_frames[j];
+    out.sU[j] = out.usize(j);
+  }
+  in.G = const_cast<double*>(a);
+  in.sG = in.gsize();
+  out.G = out_core;
+  out.sG = out.gsize();
+  LRFG_TRY(R.round(in, out, tol, s));
+  if (out_ranks)
+    for (int j = 0; j < 3; ++j) out_ranks[j] = c[j];
+  if (kept) {
+    LRFG_HIP(hipMemcpyAsync(kept, R.kept, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+  }
+  return LRFG_OK;
+}
+
 size_t lrfg_compress_workspace_bytes(int d, const int N[3], int cap, int oversample) {
   using namespace lrfg;
   if (N == nullptr || (d != 2 && d != 3)) return 0;

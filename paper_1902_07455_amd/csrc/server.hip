@@ -99,8 +99,14 @@ bool same_batch_key(const Request& x, const Request& y) {
   if (x.nE != y.nE || x.E != y.E) return false;
   if (x.p.format == LRFG_FORMAT_FULL) return true;
   const bool xc = x.a.weights != nullptr, yc = y.a.weights != nullptr;
-  if (xc != yc || x.a.on_device != y.a.on_device) return false;
+  const bool xk = x.a.tucker_core != nullptr, yk = y.a.tucker_core != nullptr;
+  if (xc != yc || xk != yk || x.a.on_device != y.a.on_device) return false;
   if (xc) return x.a.rank == y.a.rank;
+  if (xk) {
+    for (int j = 0; j < 3; ++j)
+      if (x.a.tucker_ranks[j] != y.a.tucker_ranks[j]) return false;
+    return true;
+  }
   for (int j = 0; j <= x.p.d; ++j)
     if (x.a.tt_ranks[j] != y.a.tt_ranks[j]) return false;
   return true;

@@ -170,6 +170,45 @@ def test_solve_batch_validation_before_device():
     lib.lrfg_plan_destroy(plan)
 
 
+def test_tucker_coefficient_validation_before_device():
+    """Tucker coefficients go with the Tucker format only, need all three
+    frames and ranks in [1, N]; checked before any device work (the
+    workspace pointer below is never dereferenced)."""
+    L = _lib()
+    lib = L.lib()
+    core = (C.c_double * 8)()
+    frame = (C.c_double * 30)()
+
+    def tucker_coeff(ranks=(2, 2, 2), frames=3):
+        c = L.Coeff()
+        c.tucker_core = C.cast(core, C.c_void_p)
+        for j in range(3):
+            c.tucker_ranks[j] = ranks[j]
+            if j < frames:
+                c.tucker_frames[j] = C.cast(frame, C.c_void_p)
+        return c
+
+    r = L.Result()
+    for fmt, code in ((3, -5), (0, -5)):           # TT and full-grid plans refuse it
+        plan = C.c_void_p()
+        assert lib.lrfg_plan_create(C.byref(_problem(L, N=(15, 15, 15), format=fmt, rank_cap=4)), C.byref(plan)) == 0
+        assert lib.lrfg_solve(plan, C.byref(tucker_coeff()), None, 3, C.c_void_p(256), 1 << 40, None,
+                              C.byref(r)) == code
+        lib.lrfg_plan_destroy(plan)
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, N=(15, 15, 15), format=2, rank_cap=4)), C.byref(plan)) == 0
+    # a missing frame, a rank above N
+    assert lib.lrfg_solve(plan, C.byref(tucker_coeff(frames=2)), None, 3, C.c_void_p(256), 1 << 40, None,
+                          C.byref(r)) == -1
+    assert lib.lrfg_solve(plan, C.byref(tucker_coeff(ranks=(2, 16, 2))), None, 3, C.c_void_p(256), 1 << 40, None,
+                          C.byref(r)) == -1
+    # a TT coefficient on the Tucker plan
+    c = L.Coeff()
+    c.tt_cores[0] = C.cast(core, C.c_void_p)
+    assert lib.lrfg_solve(plan, C.byref(c), None, 3, C.c_void_p(256), 1 << 40, None, C.byref(r)) == -5
+    lib.lrfg_plan_destroy(plan)
+
+
 def test_gram_cut_validation_before_device():
     lib = _lib().lib()
     buf = (C.c_double * 16)()
