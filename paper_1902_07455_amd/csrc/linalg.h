@@ -47,6 +47,13 @@ size_t gemm_scratch_doubles(const Gemm& g);
 // `scratch` may be null (no split-K).
 int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s);
 
+// Batched long dot products: out[t] = sum_i x[(t / xdiv) sx + i] y[t sy + i],
+// i < n, t < batch; blocks sum fixed chunks, a second pass adds the chunk
+// sums in a fixed order (deterministic).  scratch: dot_rows_scratch doubles.
+size_t dot_rows_scratch(long long n, int batch);
+int dot_rows(long long n, const double* x, long long sx, int xdiv, const double* y, long long sy, double* out,
+             int batch, double* scratch, size_t scratch_doubles, hipStream_t s);
+
 // Batched symmetric eigendecomposition, n <= kMaxEig: A_b (n x n, row-major,
 // leading dimension lda, batch stride sA) -> eigenvalues W_b (descending)
 // and eigenvectors V_b (column j = eigenvector j, row-major n x n).

@@ -888,6 +888,57 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   return LRFG_OK;
 }
 
+namespace {
+constexpr int kDotChunk = 16384;  // elements per block of dot_rows
+__global__ __launch_bounds__(256) void k_dot_partial(long long n, const double* __restrict__ x, long long sx,
+                                                     int xdiv, const double* __restrict__ y, long long sy,
+                                                     int nblk, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int t = blockIdx.y, blk = blockIdx.x;
+  const double* xp = x + (long long)(t / xdiv) * sx;
+  const double* yp = y + (long long)t * sy;
+  const long long i0 = (long long)blk * kDotChunk, i1 = min(n, i0 + kDotChunk);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  long long i = i0 + threadIdx.x;
+  for (; i + 768 < i1; i += 1024) {
+    a0 += xp[i] * yp[i];
+    a1 += xp[i + 256] * yp[i + 256];
+    a2 += xp[i + 512] * yp[i + 512];
+    a3 += xp[i + 768] * yp[i + 768];
+  }
+  for (; i < i1; i += 256) a0 += xp[i] * yp[i];
+  double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long long)t * nblk + blk] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+}  // namespace
+
+size_t dot_rows_scratch(long long n, int batch) {
+  const long long nblk = (n + kDotChunk - 1) / kDotChunk;
+  return (size_t)(nblk < 1 ? 1 : nblk) * batch;
+}
+
+int dot_rows(long long n, const double* x, long long sx, int xdiv, const double* y, long long sy, double* out,
+             int batch, double* scratch, size_t scratch_doubles, hipStream_t s) {
+  if (batch <= 0) return LRFG_OK;
+  const int nblk = (int)std::max<long long>(1, (n + kDotChunk - 1) / kDotChunk);
+  if (scratch == nullptr || scratch_doubles < (size_t)nblk * batch) {
+    set_error("dot_rows: scratch too small");
+    return LRFG_EWORKSPACE;
+  }
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblk, batch), dim3(256), 0, s, n, x, sx, xdiv < 1 ? 1 : xdiv, y, sy, nblk,
+                     scratch);
+  LRFG_LAUNCHED();
+  const int gr = (batch + 31) / 32;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, 1, 1, nblk, batch, (const double*)scratch, out,
+                     (long long)1, (long long)1, 1.0, 0.0);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
 int syevj(int n, const double* A, long long lda, long long sA, double* W, long long sW, double* V, long long sV,
           int batch, hipStream_t s) {
   if (n < 1 || n > kMaxEig) {

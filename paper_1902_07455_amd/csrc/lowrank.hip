@@ -1038,7 +1038,7 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   C.coef2 = ar.take<double>((size_t)2 * nE);
   C.done = ar.take<int>(nE);
   C.stage = ar.take<double>((size_t)pl->ra * (1 + N[0] + N[1] + N[2]));
-  size_t dn = tk_dot_scratch(C.kr, C.z, nE);
+  size_t dn = tk_dot_scratch(C.kr, C.z, 3 * nE);  // A_H cross terms: up to 3 pairs per system
   dn = std::max(dn, tk_dot_scratch(C.a, C.a, nE));
   dn = std::max(dn, tk_dot_scratch(C.z, C.z, nE));
   C.dscr = ar.take<double>(dn);
@@ -1390,12 +1390,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     for (int e = 0; e < nE; ++e) m1[(size_t)e * 3 + al] = v[e] / Ntot;
     TKB kr = C.kr;
     LRFG_TRY(tk_hadamard(C.a, g, kr, nE, s));
-    for (int i = 0; i < nE; ++i) {
-      for (int j = 0; j < nE; ++j) {
-        TKB ki = tk_sub(kr, i), gj = tk_sub(g, j);
-        LRFG_TRY(tk_dot(ki, gj, C.dots + i * nE + j, C.dscr, 1, s));
-      }
-    }
+    LRFG_TRY(tk_dot(kr, g, C.dots, C.dscr, nE, s, nE));  // every (i, j) pair in one pass
     std::vector<double> w2((size_t)nE * nE);
     LRFG_TRY(tk_read(C, C.dots, w2.data(), nE * nE));
     for (int i = 0; i < nE; ++i)

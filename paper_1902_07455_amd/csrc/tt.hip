@@ -289,7 +289,10 @@ int tt_dot(const TTB& x, const TTB& y, double* dots, double* scratch, int nE, hi
       sU = g.sC;
       u_is_y = false;
     }
-    // M_j = X_j^T U : (a1 x a0 N)(a0 N x b1)
+    // M_j = X_j^T U : (a1 x a0 N)(a0 N x b1); the last one (1 x 1) is a
+    // plain dot product
+    if (j == d - 1 && a1 == 1 && b1 == 1 && !u_is_y)
+      return dot_rows((long long)a0 * N, x.c[j], x.s[j], P, U, sU, dots, T, gs, gsn, s);
     double* Mn = (j == d - 1) ? dots : p;
     if (j < d - 1) p += (size_t)a1 * b1 * T;
     Gemm g;

@@ -47,9 +47,11 @@ int tk_sum(const TKTerm* terms, int nt, TKB& out, int nE, hipStream_t s);
 // (out's core must be cleared first); used for sums whose frames are
 // written by other kernels.
 int tk_place_core(const TKB& x, const double* coef, double mult, TKB& out, const int o[3], int nE, hipStream_t s);
-// dots[e] = <x_e, y_e>
+// dots[e] = <x_e, y_e>, scratch of tk_dot_scratch(x, y, nE) doubles.  With
+// pairs = P > 0 (nE a multiple of P): dots[e P + j] = <x_e, y_{(e/P) P + j}>,
+// scratch of tk_dot_scratch(x, y, nE P) doubles.
 size_t tk_dot_scratch(const TKB& x, const TKB& y, int nE);
-int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s);
+int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s, int pairs = 0);
 
 // Truncation of batched Tucker tensors to fixed mode ranks (randomised
 // HOSVD with Khatri-Rao sketches; see tucker.hip).

@@ -340,41 +340,60 @@ size_t tk_dot_scratch(const TKB& x, const TKB& y, int nE) {
   return n * nE + 4096 + kTkDotSplitK;
 }
 
-int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s) {
+int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s, int pairs) {
+  // With pairs = P the batch runs over t = e P + j: x system e with y system
+  // (e / P) P + j (every pair within each group of P systems).
+  const int P = pairs > 0 ? pairs : 1;
+  const int T = pairs > 0 ? nE * P : nE;
+  auto map_y_b = [&](GB& g, const double* p, long long ld, long long sy, bool t) {
+    g.b(p, ld, pairs > 0 ? sy * P : sy, t);
+    if (pairs > 0) {
+      g.g.bdiv = P * P;
+      g.g.bmod = P;
+      g.g.sB2 = sy;
+    }
+  };
   double* p = scratch;
   double* W[3];
+  double* gs = scratch + tk_dot_scratch(x, y, T) - kTkDotSplitK;
   for (int j = 0; j < 3; ++j) {
     W[j] = p;
-    p += (size_t)x.r[j] * y.r[j] * nE;
+    p += (size_t)x.r[j] * y.r[j] * T;
     // W_j = U_xj^T U_yj (rx_j x ry_j)
-    GB g(x.r[j], y.r[j], x.N[j], nE);
-    g.a(x.U[j], x.r[j], x.sU[j], true).b(y.U[j], y.r[j], y.sU[j]).c(W[j], y.r[j], (long long)x.r[j] * y.r[j]);
-    LRFG_TRY(gemm(g.g, scratch + tk_dot_scratch(x, y, nE) - kTkDotSplitK, kTkDotSplitK, s));
+    GB g(x.r[j], y.r[j], x.N[j], T);
+    g.a(x.U[j], x.r[j], x.sU[j], true);
+    g.g.adiv = P;
+    map_y_b(g, y.U[j], y.r[j], y.sU[j], false);
+    g.c(W[j], y.r[j], (long long)x.r[j] * y.r[j]);
+    LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s));
   }
-  double* gs = scratch + tk_dot_scratch(x, y, nE) - kTkDotSplitK;
   const int rx1 = x.r[0], rx2 = x.r[1], rx3 = x.r[2], ry1 = y.r[0], ry2 = y.r[1], ry3 = y.r[2];
   double* T1 = p;
-  p += (size_t)ry1 * ry2 * rx3 * nE;
+  p += (size_t)ry1 * ry2 * rx3 * T;
   double* T2 = p;
-  p += (size_t)rx1 * ry2 * rx3 * nE;
+  p += (size_t)rx1 * ry2 * rx3 * T;
   double* T3 = p;
   // T1 = G_y (ry1 ry2 x ry3) W3^T
-  { GB g(ry1 * ry2, rx3, ry3, nE); g.a(y.G, ry3, y.sG).b(W[2], ry3, (long long)rx3 * ry3, true)
-        .c(T1, rx3, (long long)ry1 * ry2 * rx3);
+  { GB g(ry1 * ry2, rx3, ry3, T);
+    g.a(y.G, ry3, pairs > 0 ? y.sG * P : y.sG);
+    if (pairs > 0) {
+      g.g.adiv = P * P;
+      g.g.amod = P;
+      g.g.sA2 = y.sG;
+    }
+    g.b(W[2], ry3, (long long)rx3 * ry3, true).c(T1, rx3, (long long)ry1 * ry2 * rx3);
     LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
   // T2 = W1 (rx1 x ry1) T1 (ry1 x ry2 rx3)
-  { GB g(rx1, ry2 * rx3, ry1, nE); g.a(W[0], ry1, (long long)rx1 * ry1).b(T1, (long long)ry2 * rx3, (long long)ry1 * ry2 * rx3)
+  { GB g(rx1, ry2 * rx3, ry1, T); g.a(W[0], ry1, (long long)rx1 * ry1).b(T1, (long long)ry2 * rx3, (long long)ry1 * ry2 * rx3)
         .c(T2, (long long)ry2 * rx3, (long long)rx1 * ry2 * rx3);
     LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
   // T3 = T2 x_2 W2 (rx2 x ry2)
   const long long n3 = (long long)rx1 * rx2 * rx3;
-  hipLaunchKernelGGL(k_mode2, dim3(grid_for(n3 * nE)), dim3(kB), 0, s, (const double*)T2, (long long)rx1 * ry2 * rx3,
-                     rx1, ry2, rx3, (const double*)W[1], (long long)rx2 * ry2, rx2, 0, T3, n3, nE);
+  hipLaunchKernelGGL(k_mode2, dim3(grid_for(n3 * T)), dim3(kB), 0, s, (const double*)T2, (long long)rx1 * ry2 * rx3,
+                     rx1, ry2, rx3, (const double*)W[1], (long long)rx2 * ry2, rx2, 0, T3, n3, T);
   LRFG_LAUNCHED();
-  // dots[e] = <G_x, T3>
-  { GB g(1, 1, (int)n3, nE); g.a(x.G, n3, x.sG).b(T3, 1, n3).c(dots, 1, 1);
-    LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
-  return LRFG_OK;
+  // dots[t] = <G_x, T3_t>
+  return dot_rows(n3, x.G, x.sG, P, T3, n3, dots, T, gs, kTkDotSplitK, s);
 }
 
 // ====================================================================== rounding
