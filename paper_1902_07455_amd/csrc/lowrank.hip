@@ -1269,7 +1269,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
   std::vector<int> kx(3 * nE, 0), kbest(3 * nE, 0);
   auto fetch_kept = [&]() -> int {
     for (int j = 0; j < 3; ++j)
-      LRFG_HIP(hipMemcpyAsync(kx.data() + j * nE, C.rd.kept + (long long)j * C.rd.nE, sizeof(int) * nE,
+      LRFG_HIP(hipMemcpyAsync(kx.data() + j * nE, C.rd.kept + (long long)j * C.rd.kept_batch, sizeof(int) * nE,
                               hipMemcpyDeviceToHost, s));
     return LRFG_OK;
   };

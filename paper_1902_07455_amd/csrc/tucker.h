@@ -65,9 +65,11 @@ struct TkRounder {
   uint64_t counter = 0;
   double* om[3] = {};
   double *Z[3], *H, *KR, *Yc[3], *Y[3], *Q[3], *M[3], *T1, *T2, *Cc, *Gr, *S[3], *T3, *T4, *Gs, *Ss, *Ytmp;
+  double *Yall, *Qall, *Sall;
   double* gscr = nullptr;
   size_t gscr_n = 0;
-  int* kept = nullptr;       // kept ranks per mode per system (diagnostics)
+  int* kept = nullptr;       // kept ranks of the last call: mode j of system e at kept[j kept_batch + e]
+  int kept_batch = 0;
   void carve(Arena& ar);
   int round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch = -1);
 };

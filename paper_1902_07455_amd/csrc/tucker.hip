@@ -169,20 +169,16 @@ __global__ void k_kr_rows(const double* __restrict__ Z1, long long s1, int R1, c
   }
 }
 
-// Gram matrix of the mode-2 unfolding of C (l x l x l):
-// Gr[e][b][b'] = sum_{a,c} C[e][a][b][c] C[e][a][b'][c]
-__global__ void k_gram_mode2(const double* __restrict__ Cc, long long sc, int l, double* __restrict__ Gr,
-                             long long sg, int nE) {
-  const long long per = (long long)l * l;
+// P[e][b][a][c] = C[e][a][b][c] (l x l x l), so that the mode-2 Gram matrix
+// is the GEMM P P^T over (a, c)
+__global__ void k_swap01(const double* __restrict__ Cc, long long sc, int l, double* __restrict__ P, int nE) {
+  const long long per = (long long)l * l * l;
   GRID_STRIDE(idx, per * nE) {
     const long long e = idx / per;
     const long long rem = idx - e * per;
-    const long long b = rem / l, bp = rem - b * l;
-    const double* c = Cc + e * sc;
-    double acc = 0.0;
-    for (int a = 0; a < l; ++a)
-      for (int k = 0; k < l; ++k) acc += c[((long long)a * l + b) * l + k] * c[((long long)a * l + bp) * l + k];
-    Gr[e * sg + rem] = acc;
+    const long long c = rem % l, ab = rem / l;
+    const long long b = ab % l, a = ab / l;
+    P[e * per + (b * l + a) * l + c] = Cc[e * sc + rem];
   }
 }
 
@@ -215,6 +211,25 @@ struct GB {
     return *this;
   }
 };
+
+// Mode-2 product out[e][a][b][c] = sum_q W'[e][b][q] in[e][a][q][c] (W' = W[e]
+// or, with wt, W[e]^T) as one batched GEMM over (e, a) when in and out are
+// compact per system, else by k_mode2.
+int mode2(const double* in, long long sin, int A, int Bi, int Cd, const double* W, long long sW, int Bo, int wt,
+          double* out, long long sout, int nE, double* gscr, size_t gscr_n, hipStream_t s) {
+  if (sin == (long long)A * Bi * Cd && sout == (long long)A * Bo * Cd) {
+    GB g(Bo, Cd, Bi, A * nE);
+    g.a(W, wt ? Bo : Bi, sW, wt != 0);
+    g.g.adiv = A;
+    g.b(in, Cd, (long long)Bi * Cd).c(out, Cd, (long long)Bo * Cd);
+    return gemm(g.g, gscr, gscr_n, s);
+  }
+  hipLaunchKernelGGL(k_mode2, dim3(grid_for((long long)A * Bo * Cd * nE)), dim3(kB), 0, s, in, sin, A, Bi, Cd, W, sW,
+                     Bo, wt, out, sout, nE);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
 
 constexpr size_t kTkDotSplitK = (size_t)2 * 1024 * 1024;
 
@@ -389,9 +404,8 @@ int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hi
     LRFG_TRY(gemm(g.g, gs, kTkDotSplitK, s)); }
   // T3 = T2 x_2 W2 (rx2 x ry2)
   const long long n3 = (long long)rx1 * rx2 * rx3;
-  hipLaunchKernelGGL(k_mode2, dim3(grid_for(n3 * T)), dim3(kB), 0, s, (const double*)T2, (long long)rx1 * ry2 * rx3,
-                     rx1, ry2, rx3, (const double*)W[1], (long long)rx2 * ry2, rx2, 0, T3, n3, T);
-  LRFG_LAUNCHED();
+  LRFG_TRY(mode2(T2, (long long)rx1 * ry2 * rx3, rx1, ry2, rx3, W[1], (long long)rx2 * ry2, rx2, 0, T3, n3, T, gs,
+                kTkDotSplitK, s));
   // dots[t] = <G_x, T3_t>
   return dot_rows(n3, x.G, x.sG, P, T3, n3, dots, T, gs, kTkDotSplitK, s);
 }
@@ -402,25 +416,27 @@ void TkRounder::carve(Arena& ar) {
   auto T = [&](long long n) { return ar.take<double>((size_t)n * nE); };
   const long long R1 = Rmax[0], R2 = Rmax[1], R3 = Rmax[2];
   long long Nm = 1;
+  for (int j = 0; j < 3; ++j) Nm = std::max<long long>(Nm, N[j]);
+  // Y, Q and S of the three modes live in one buffer each, so that the
+  // orthonormalisation and the cut of all modes can run as one batch
+  Yall = T(3 * Nm * L);
+  Qall = T(3 * Nm * L);
+  Sall = T(3LL * L * L);
   for (int j = 0; j < 3; ++j) {
     om[j] = ar.take<double>((size_t)N[j] * L);
     Z[j] = T(Rmax[j] * L);
     Yc[j] = T(Rmax[j] * L);
-    Y[j] = T((long long)N[j] * L);
-    Q[j] = T((long long)N[j] * L);
     M[j] = T(Rmax[j] * L);
-    S[j] = T((long long)L * L);
-    Nm = std::max<long long>(Nm, N[j]);
   }
   H = T(R1 * R2 * L);  // H, then the Khatri-Rao rows, then T1 (R1 R2 x l)
   T2 = T((long long)L * R2 * L);
   Cc = T((long long)L * L * L);
   T3 = T((long long)L * L * L);
   T4 = T((long long)L * L * L);
-  Gr = T((long long)L * L);
-  Gs = T((long long)L * L);
-  Ss = T((long long)L * L);
-  Ytmp = T(Nm * L);
+  Gr = T(3LL * L * L);
+  Gs = T(3LL * L * L);
+  Ss = T(3LL * L * L);
+  Ytmp = T(3 * Nm * L);
   kept = ar.take<int>((size_t)3 * nE);
   gscr_n = (size_t)4 * 1024 * 1024;
   gscr = ar.take<double>(gscr_n);
@@ -495,14 +511,33 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   LRFG_LAUNCHED();
   { GB g(R3, l, R1 * R2, nb); g.a(in.G, R3, in.sG, true).b(KR, l, sH).c(Yc[2], l, sZ[2]);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-  // 3. Y_j = U_j Yc_j, Q_j = orth(Y_j), M_j = Q_j^T U_j
+  // 3. Y_j = U_j Yc_j, Q_j = orth(Y_j), M_j = Q_j^T U_j; with equal N_j the
+  //    three modes sit back to back and are orthonormalised in one batch
+  const bool same_n = N[0] == N[1] && N[1] == N[2];
+  for (int j = 0; j < 3; ++j) {
+    Y[j] = Yall + (long long)j * nb * N[0] * l;
+    Q[j] = Qall + (long long)j * nb * N[0] * l;
+    if (!same_n) {
+      long long off = 0;
+      for (int q = 0; q < j; ++q) off += (long long)nb * N[q] * l;
+      Y[j] = Yall + off;
+      Q[j] = Qall + off;
+    }
+    const long long sY = (long long)N[j] * l;
+    GB g(N[j], l, Rj[j], nb);
+    g.a(in.U[j], Rj[j], in.sU[j]).b(Yc[j], l, sZ[j]).c(Y[j], l, sY);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  if (same_n) {
+    LRFG_TRY(tk_orth(*this, Yall, Qall, N[0], l, 3 * nb, s));
+  } else {
+    for (int j = 0; j < 3; ++j) LRFG_TRY(tk_orth(*this, Y[j], Q[j], N[j], l, nb, s));
+  }
   for (int j = 0; j < 3; ++j) {
     const long long sY = (long long)N[j] * l;
-    { GB g(N[j], l, Rj[j], nb); g.a(in.U[j], Rj[j], in.sU[j]).b(Yc[j], l, sZ[j]).c(Y[j], l, sY);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-    LRFG_TRY(tk_orth(*this, Y[j], Q[j], N[j], l, nb, s));
-    { GB g(l, Rj[j], N[j], nb); g.a(Q[j], l, sY, true).b(in.U[j], Rj[j], in.sU[j]).c(M[j], Rj[j], sZ[j]);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    GB g(l, Rj[j], N[j], nb);
+    g.a(Q[j], l, sY, true).b(in.U[j], Rj[j], in.sU[j]).c(M[j], Rj[j], sZ[j]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
   }
   // 4. C = G x_3 M3 x_1 M1 x_2 M2 (l x l x l)
   const long long l3 = (long long)l * l * l;
@@ -511,26 +546,37 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   const long long sT2 = (long long)l * R2 * l;
   { GB g(l, R2 * l, R1, nb); g.a(M[0], R1, sZ[0]).b(T1, (long long)R2 * l, sH).c(T2, (long long)R2 * l, sT2);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-  hipLaunchKernelGGL(k_mode2, dim3(grid_for(l3 * nb)), dim3(kB), 0, s, (const double*)T2, sT2, l, R2, l,
-                     (const double*)M[1], sZ[1], l, 0, Cc, l3, nb);
-  LRFG_LAUNCHED();
-  // 5. the cut: mode Gram matrices of C, kept eigenvectors S_j (l x c_j)
+  LRFG_TRY(mode2(T2, sT2, l, R2, l, M[1], sZ[1], l, 0, Cc, l3, nb, gscr, gscr_n, s));
+  // 5. the cut: mode Gram matrices of C (mode j's nb matrices at
+  //    Gr + j nb l^2), kept eigenvectors S_j (l x c_j); kept ranks of mode j
+  //    at kept + j nb; with equal c_j one cut launch for all three modes
   const long long sG2 = (long long)l * l;
-  for (int j = 0; j < 3; ++j) {
-    if (j == 0) {
-      GB g(l, l, l * l, nb);
-      g.a(Cc, (long long)l * l, l3).b(Cc, (long long)l * l, l3, true).c(Gr, l, sG2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
-    } else if (j == 1) {
-      hipLaunchKernelGGL(k_gram_mode2, dim3(grid_for(sG2 * nb)), dim3(kB), 0, s, (const double*)Cc, l3, l, Gr, sG2,
-                         nb);
-      LRFG_LAUNCHED();
-    } else {
-      GB g(l, l, l * l, nb);
-      g.a(Cc, l, l3, true).b(Cc, l, l3).c(Gr, l, sG2);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
-    }
-    LRFG_TRY(cut_psd(l, out.r[j], Gr, sG2, tol2, S[j], (long long)l * out.r[j], kept + j * nE, nb, s));
+  double* Grj[3] = {Gr, Gr + sG2 * nb, Gr + 2 * sG2 * nb};
+  {
+    GB g(l, l, l * l, nb);
+    g.a(Cc, (long long)l * l, l3).b(Cc, (long long)l * l, l3, true).c(Grj[0], l, sG2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  hipLaunchKernelGGL(k_swap01, dim3(grid_for(l3 * nb)), dim3(kB), 0, s, (const double*)Cc, l3, l, T3, nb);
+  LRFG_LAUNCHED();
+  {
+    GB g(l, l, l * l, nb);
+    g.a(T3, (long long)l * l, l3).b(T3, (long long)l * l, l3, true).c(Grj[1], l, sG2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  {
+    GB g(l, l, l * l, nb);
+    g.a(Cc, l, l3, true).b(Cc, l, l3).c(Grj[2], l, sG2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  kept_batch = nb;
+  const bool same_c = out.r[0] == out.r[1] && out.r[1] == out.r[2];
+  for (int j = 0; j < 3; ++j) S[j] = Sall + (long long)j * nb * l * (same_c ? out.r[0] : l);
+  if (same_c) {
+    LRFG_TRY(cut_psd(l, out.r[0], Gr, sG2, tol2, Sall, (long long)l * out.r[0], kept, 3 * nb, s));
+  } else {
+    for (int j = 0; j < 3; ++j)
+      LRFG_TRY(cut_psd(l, out.r[j], Grj[j], sG2, tol2, S[j], (long long)l * out.r[j], kept + j * nb, nb, s));
   }
   // 6. frames Q_j S_j and core C x_j S_j^T
   for (int j = 0; j < 3; ++j) {
@@ -545,10 +591,9 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
         .c(T4, (long long)l * c3, (long long)c1 * l * c3);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   const long long nout = (long long)c1 * c2 * c3;
-  hipLaunchKernelGGL(k_mode2, dim3(grid_for(nout * nb)), dim3(kB), 0, s, (const double*)T4, (long long)c1 * l * c3,
-                     c1, l, c3, (const double*)S[1], (long long)l * c2, c2, 1, out.G, out.sG, nb);
-  LRFG_LAUNCHED();
-  return LRFG_OK;
+  (void)nout;
+  return mode2(T4, (long long)c1 * l * c3, c1, l, c3, S[1], (long long)l * c2, c2, 1, out.G, out.sG, nb, gscr, gscr_n,
+               s);
 }
 
 }  // namespace lrfg
