@@ -286,6 +286,7 @@ def main(argv=None):
     ap.add_argument("--crossover", default="243,405", help="grid sizes of the crossover table")
     ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker-format leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-cap", type=int, default=None, help="TT rank cap (skips the cap sweep)")
@@ -404,7 +405,7 @@ def main(argv=None):
 
     # ------------------------------------------------------------ mixed precision (same workload)
     mixed = {}
-    for prec, peak in (("fp32", 157.3), ("bf16", 2500.0)):
+    for prec, peak in (() if args.no_mixed else (("fp32", 157.3), ("bf16", 2500.0))):
         mtol, msweep = None, []
         for tol in [ttol, 1e-3, 1e-4, 1e-5, 1e-6]:
             if tol > ttol:
