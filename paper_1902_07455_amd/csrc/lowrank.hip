@@ -1009,7 +1009,17 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
     cap[j] = m;
     C.cap[j] = m;
   }
-  C.kr = tk_alloc(ar, N, rkr, 3 * nE);
+  // Khatri-Rao frames of the d nE material products; their Kronecker cores
+  // are never formed inside the iterations (the truncation contracts the
+  // factor cores), only once per direction for A_H (nE cores)
+  for (int j = 0; j < 3; ++j) {
+    C.kr.N[j] = N[j];
+    C.kr.r[j] = rkr[j];
+    C.kr.sU[j] = C.kr.usize(j);
+    C.kr.U[j] = ar.take<double>((size_t)C.kr.sU[j] * 3 * nE);
+  }
+  C.kr.sG = C.kr.gsize();
+  C.kr.G = ar.take<double>((size_t)C.kr.sG * nE);
   C.comb = tk_alloc(ar, N, cap, 2 * nE);
   long long fmax = 0;
   for (int j = 0; j < 3; ++j) fmax = std::max(fmax, (long long)N[j] * rc[j]);
@@ -1027,6 +1037,7 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   R.oversample = pl->over;
   R.seed = pl->p.seed;
   R.Lmax = std::min(std::max(rc[0], std::max(rc[1], rc[2])) + pl->over, kMaxEig);
+  R.kron = true;
   R.carve(ar);
   C.dots = ar.take<double>((size_t)3 * nE + 64);
   C.rho = ar.take<double>(nE);
@@ -1071,15 +1082,16 @@ int tk_apply_K(TkCtx& C, const TKB& v, TKB& out) {
     g.U[al] = C.gframe;
     LRFG_TRY(tk_mode_apply(v, g, al, 0, 0.0, 1.0, C.f[al], nE, C.s));
     TKB kra = tk_sub(C.kr, (long long)al * nE);
-    LRFG_TRY(tk_hadamard(C.a, g, kra, nE, C.s));
+    LRFG_TRY(tk_hadamard_frames(C.a, g, kra, nE, C.s));
   }
   TKB kr = C.kr;
   for (int j = 0; j < 3; ++j) {
     kr.r[j] = C.a.r[j] * v.r[j];
     kr.sU[j] = kr.usize(j);
   }
-  kr.sG = kr.gsize();
-  LRFG_TRY(C.rd.round(kr, C.h, 0.0, C.s, 3 * nE));
+  // core of system al nE + e: G_a (x) G_v[e] (the derivative acts on frames)
+  const KronCore kc{C.a.G, C.a.sG, {C.a.r[0], C.a.r[1], C.a.r[2]}, v.G, v.sG, nE, {v.r[0], v.r[1], v.r[2]}};
+  LRFG_TRY(C.rd.round(kr, C.h, 0.0, C.s, 3 * nE, &kc));
   TKB hd[3];
   TKTerm terms[3];
   for (int al = 0; al < 3; ++al) {

@@ -53,6 +53,23 @@ int tk_place_core(const TKB& x, const double* coef, double mult, TKB& out, const
 size_t tk_dot_scratch(const TKB& x, const TKB& y, int nE);
 int tk_dot(const TKB& x, const TKB& y, double* dots, double* scratch, int nE, hipStream_t s, int pairs = 0);
 
+// out = a (.) x without the core: Khatri-Rao frames only (column i s_j + k).
+int tk_hadamard_frames(const TKB& a, const TKB& x, TKB& out, int nE, hipStream_t s);
+
+// The core of a Khatri-Rao product a (.) x given by its two factors
+// (G_a (x) G_x, index (i r_x + k) per mode), never formed: system t of a
+// truncation batch takes G_a at t sGa (sGa = 0: shared) and G_x at
+// (t % xmod) sGx.
+struct KronCore {
+  const double* Ga;
+  long long sGa;
+  int ra[3];
+  const double* Gx;
+  long long sGx;
+  int xmod;
+  int rx[3];
+};
+
 // Truncation of batched Tucker tensors to fixed mode ranks (randomised
 // HOSVD with Khatri-Rao sketches; see tucker.hip).
 struct TkRounder {
@@ -66,12 +83,17 @@ struct TkRounder {
   double* om[3] = {};
   double *Z[3], *H, *KR, *Yc[3], *Y[3], *Q[3], *M[3], *T1, *T2, *Cc, *Gr, *S[3], *T3, *T4, *Gs, *Ss, *Ytmp;
   double *Yall, *Qall, *Sall;
+  bool kron = false;         // carve the buffers of Kronecker-core inputs
+  double *Kp = nullptr, *Kh = nullptr, *Kw = nullptr, *KY = nullptr, *KM = nullptr;
   double* gscr = nullptr;
   size_t gscr_n = 0;
   int* kept = nullptr;       // kept ranks of the last call: mode j of system e at kept[j kept_batch + e]
   int kept_batch = 0;
   void carve(Arena& ar);
-  int round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch = -1);
+  // in's core is ignored when kc is given (the input is a Khatri-Rao
+  // product whose frames are in.U and whose core is described by kc)
+  int round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch = -1, const KronCore* kc = nullptr);
+  int kron_mode3(const KronCore& kc, const double* B, long long sB, int l, int nb, double* dst, hipStream_t s);
 };
 
 }  // namespace lrfg

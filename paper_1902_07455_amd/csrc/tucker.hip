@@ -169,6 +169,57 @@ __global__ void k_kr_rows(const double* __restrict__ Z1, long long s1, int R1, c
   }
 }
 
+// out[o][b][a][q] = in[o][a][b][q] (o < outer, a < A, b < B, q < inner)
+__global__ void k_swap_mid(const double* __restrict__ in, double* __restrict__ out, long long outer, int A, int B,
+                           long long inner) {
+  const long long per = (long long)A * B * inner;
+  GRID_STRIDE(idx, per * outer) {
+    const long long o = idx / per;
+    long long rem = idx - o * per;
+    const long long q = rem % inner;
+    rem /= inner;
+    const long long b = rem % B, a = rem / B;
+    out[o * per + (b * A + a) * inner + q] = in[idx];
+  }
+}
+
+// Kronecker-core unfolding: in[(i1, i2)][t][k1][q] (q < inner = rx2 l) ->
+// out[t][i1][k1][i2][q], the core-sketch layout [(i1, k1)][(i2, k2)][c].
+__global__ void k_kron_unfold(const double* __restrict__ in, double* __restrict__ out, int ra1, int ra2, int nb,
+                              int rx1, long long inner) {
+  const long long tot = (long long)ra1 * ra2 * nb * rx1 * inner;
+  GRID_STRIDE(idx, tot) {
+    long long rem = idx;
+    const long long q = rem % inner;
+    rem /= inner;
+    const long long k1 = rem % rx1;
+    rem /= rx1;
+    const long long t = rem % nb;
+    rem /= nb;
+    const long long i2 = rem % ra2, i1 = rem / ra2;
+    out[(((t * ra1 + i1) * rx1 + k1) * ra2 + i2) * inner + q] = in[idx];
+  }
+}
+
+// Khatri-Rao rows in Kronecker order: W[t][k1][k2][i1][i2][c] =
+// Z1[t][i1 rx1 + k1][c] Z2[t][i2 rx2 + k2][c]
+__global__ void k_kr_kron(const double* __restrict__ Z1, long long s1, const double* __restrict__ Z2, long long s2,
+                          int ra1, int rx1, int ra2, int rx2, int l, double* __restrict__ W, int nb) {
+  const long long per = (long long)rx1 * rx2 * ra1 * ra2 * l;
+  GRID_STRIDE(idx, per * nb) {
+    const long long t = idx / per;
+    long long rem = idx - t * per;
+    const long long c = rem % l;
+    rem /= l;
+    const long long i2 = rem % ra2;
+    rem /= ra2;
+    const long long i1 = rem % ra1;
+    rem /= ra1;
+    const long long k2 = rem % rx2, k1 = rem / rx2;
+    W[idx] = Z1[t * s1 + (i1 * rx1 + k1) * l + c] * Z2[t * s2 + (i2 * rx2 + k2) * l + c];
+  }
+}
+
 // P[e][b][a][c] = C[e][a][b][c] (l x l x l), so that the mode-2 Gram matrix
 // is the GEMM P P^T over (a, c)
 __global__ void k_swap01(const double* __restrict__ Cc, long long sc, int l, double* __restrict__ P, int nE) {
@@ -314,6 +365,18 @@ int tk_hadamard(const TKB& a, const TKB& x, TKB& out, int nE, hipStream_t s) {
   return LRFG_OK;
 }
 
+int tk_hadamard_frames(const TKB& a, const TKB& x, TKB& out, int nE, hipStream_t s) {
+  for (int j = 0; j < 3; ++j) {
+    out.r[j] = a.r[j] * x.r[j];
+    out.sU[j] = out.usize(j);
+    const long long tot = out.usize(j) * nE;
+    hipLaunchKernelGGL(k_frame_kr, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)a.U[j], a.sU[j], a.r[j],
+                       (const double*)x.U[j], x.sU[j], x.r[j], x.N[j], out.U[j], out.sU[j], nE);
+  }
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
 int tk_place_core(const TKB& x, const double* coef, double mult, TKB& out, const int o[3], int nE, hipStream_t s) {
   hipLaunchKernelGGL(k_core_place, dim3(grid_for(x.gsize() * nE)), dim3(kB), 0, s, (const double*)x.G, x.sG, x.r[0],
                      x.r[1], x.r[2], coef, mult, out.G, out.sG, out.r[1], out.r[2], o[0], o[1], o[2], nE);
@@ -437,6 +500,13 @@ void TkRounder::carve(Arena& ar) {
   Gs = T(3LL * L * L);
   Ss = T(3LL * L * L);
   Ytmp = T(3 * Nm * L);
+  if (kron) {
+    Kp = T(R1 * R2 * L);
+    Kh = T(R1 * R2 * L);
+    Kw = T(R1 * R2 * L);
+    KY = T(R3 * L);
+    KM = T(R3 * L);
+  }
   kept = ar.take<int>((size_t)3 * nE);
   gscr_n = (size_t)4 * 1024 * 1024;
   gscr = ar.take<double>(gscr_n);
@@ -466,7 +536,40 @@ int tk_orth(TkRounder& R, const double* Y, double* Q, int m, int l, int batch, h
 
 }  // namespace
 
-int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch) {
+// (G_a (x) G_x) x_3 B for B = (R3 x l) per system (Z3, or M3 transposed),
+// written to `dst` in the core-sketch layout [(i1, k1)][(i2, k2)][c]: a GEMM
+// over i3 with G_a, a GEMM over k3 with G_x (batch ordered (i1, i2) major),
+// and one reordering pass.
+int TkRounder::kron_mode3(const KronCore& kc, const double* B, long long sB, int l, int nb, double* dst,
+                          hipStream_t s) {
+  const int ra1 = kc.ra[0], ra2 = kc.ra[1], ra3 = kc.ra[2], rx1 = kc.rx[0], rx2 = kc.rx[1], rx3 = kc.rx[2];
+  // P[t][(i1, i2)][(k3, c)] = sum_{i3} Ga[(i1, i2)][i3] B[t][i3][(k3, c)]
+  {
+    GB g(ra1 * ra2, rx3 * l, ra3, nb);
+    g.a(kc.Ga, ra3, kc.sGa).b(B, (long long)rx3 * l, sB).c(Kp, (long long)rx3 * l, (long long)ra1 * ra2 * rx3 * l);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  // H'[(i1, i2)][t][(k1, k2)][c] = sum_{k3} Gx[t][(k1, k2)][k3] P[t][(i1, i2)][k3][c]
+  {
+    GB g(rx1 * rx2, l, rx3, ra1 * ra2 * nb);
+    g.a(kc.Gx, rx3, 0);
+    g.g.amod = kc.xmod;
+    g.g.sA2 = kc.sGx;
+    g.b(Kp, l, (long long)rx3 * l);
+    g.g.bdiv = nb;
+    g.g.bmod = nb;
+    g.g.sB2 = (long long)ra1 * ra2 * rx3 * l;
+    g.c(Kh, l, (long long)rx1 * rx2 * l);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  }
+  const long long tot = (long long)ra1 * ra2 * nb * rx1 * rx2 * l;
+  hipLaunchKernelGGL(k_kron_unfold, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)Kh, dst, ra1, ra2, nb, rx1,
+                     (long long)rx2 * l);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch, const KronCore* kc) {
   ProfScope ps_("tk_round", s);
   if (batch < 0) batch = nE;
   if (batch > nE) {
@@ -489,6 +592,23 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
     set_error("tk_round: sketch %d exceeds the plan's %d", l, Lmax);
     return LRFG_EINVAL;
   }
+  if (kc != nullptr) {
+    if (!kron) {
+      set_error("tk_round: the plan holds no Kronecker buffers");
+      return LRFG_EINVAL;
+    }
+    for (int j = 0; j < 3; ++j) {
+      if (kc->ra[j] * kc->rx[j] != Rj[j]) {
+        set_error("tk_round: Kronecker ranks do not match the frames");
+        return LRFG_EINVAL;
+      }
+    }
+    if ((long long)kc->ra[0] * kc->ra[1] * kc->rx[2] > (long long)Rmax[0] * Rmax[1] ||
+        (long long)kc->ra[2] * kc->rx[2] > Rmax[2] || kc->xmod < 1 || nb % kc->xmod != 0) {
+      set_error("tk_round: Kronecker shapes exceed the plan");
+      return LRFG_EINVAL;
+    }
+  }
   const double tol2 = tol * tol / 3.0;
   const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
   const long long sZ[3] = {(long long)R1 * l, (long long)R2 * l, (long long)R3 * l};
@@ -502,15 +622,52 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   // 2. sketch cores: H = G x_3 Z3^T, Y cores of modes 1 and 2 from H; mode 3
   //    from the Khatri-Rao rows of Z1, Z2
   const long long sH = (long long)R1 * R2 * l;
-  { GB g(R1 * R2, l, R3, nb); g.a(in.G, R3, in.sG).b(Z[2], l, sZ[2]).c(H, l, sH);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  if (kc == nullptr) {
+    GB g(R1 * R2, l, R3, nb);
+    g.a(in.G, R3, in.sG).b(Z[2], l, sZ[2]).c(H, l, sH);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  } else {
+    LRFG_TRY(kron_mode3(*kc, Z[2], sZ[2], l, nb, H, s));
+  }
   hipLaunchKernelGGL(k_tcontract, dim3(grid_for((long long)(R1 + R2) * l * nb)), dim3(kB), 0, s, (const double*)H, sH,
                      (const double*)Z[0], sZ[0], (const double*)Z[1], sZ[1], R1, R2, l, Yc[0], sZ[0], Yc[1], sZ[1], nb);
-  hipLaunchKernelGGL(k_kr_rows, dim3(grid_for(sH * nb)), dim3(kB), 0, s, (const double*)Z[0], sZ[0], R1,
-                     (const double*)Z[1], sZ[1], R2, l, KR, sH, nb);
   LRFG_LAUNCHED();
-  { GB g(R3, l, R1 * R2, nb); g.a(in.G, R3, in.sG, true).b(KR, l, sH).c(Yc[2], l, sZ[2]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  if (kc == nullptr) {
+    hipLaunchKernelGGL(k_kr_rows, dim3(grid_for(sH * nb)), dim3(kB), 0, s, (const double*)Z[0], sZ[0], R1,
+                       (const double*)Z[1], sZ[1], R2, l, KR, sH, nb);
+    LRFG_LAUNCHED();
+    GB g(R3, l, R1 * R2, nb);
+    g.a(in.G, R3, in.sG, true).b(KR, l, sH).c(Yc[2], l, sZ[2]);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  } else {
+    // Yc3[(i3, k3)][c] = sum Ga[i1, i2, i3] Gx[k1, k2, k3] Z1[(i1, k1)][c] Z2[(i2, k2)][c]
+    const int ra1 = kc->ra[0], ra2 = kc->ra[1], ra3 = kc->ra[2], rx1 = kc->rx[0], rx2 = kc->rx[1],
+              rx3 = kc->rx[2];
+    const long long sW = (long long)rx1 * rx2 * ra1 * ra2 * l;
+    hipLaunchKernelGGL(k_kr_kron, dim3(grid_for(sW * nb)), dim3(kB), 0, s, (const double*)Z[0], sZ[0],
+                       (const double*)Z[1], sZ[1], ra1, rx1, ra2, rx2, l, Kw, nb);
+    LRFG_LAUNCHED();
+    {
+      // V[t][k3][(i1, i2, c)] = sum_{(k1, k2)} Gx[t][(k1, k2)][k3] W[t][(k1, k2)][(i1, i2, c)]
+      GB g(rx3, ra1 * ra2 * l, rx1 * rx2, nb);
+      g.a(kc->Gx, rx3, 0, true);
+      g.g.amod = kc->xmod;
+      g.g.sA2 = kc->sGx;
+      g.b(Kw, (long long)ra1 * ra2 * l, sW).c(Kp, (long long)ra1 * ra2 * l, (long long)rx3 * ra1 * ra2 * l);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    }
+    {
+      // Y'[t][k3][i3][c] = sum_{(i1, i2)} Ga[(i1, i2)][i3] V[t][k3][(i1, i2)][c]
+      GB g(ra3, l, ra1 * ra2, nb * rx3);
+      g.a(kc->Ga, ra3, kc->sGa, true);
+      g.g.adiv = rx3;
+      g.b(Kp, l, (long long)ra1 * ra2 * l).c(KY, l, (long long)ra3 * l);
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    }
+    hipLaunchKernelGGL(k_swap_mid, dim3(grid_for((long long)R3 * l * nb)), dim3(kB), 0, s, (const double*)KY, Yc[2],
+                       (long long)nb, rx3, ra3, (long long)l);
+    LRFG_LAUNCHED();
+  }
   // 3. Y_j = U_j Yc_j, Q_j = orth(Y_j), M_j = Q_j^T U_j; with equal N_j the
   //    three modes sit back to back and are orthonormalised in one batch
   const bool same_n = N[0] == N[1] && N[1] == N[2];
@@ -541,8 +698,17 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   }
   // 4. C = G x_3 M3 x_1 M1 x_2 M2 (l x l x l)
   const long long l3 = (long long)l * l * l;
-  { GB g(R1 * R2, l, R3, nb); g.a(in.G, R3, in.sG).b(M[2], R3, sZ[2], true).c(T1, l, sH);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  if (kc == nullptr) {
+    GB g(R1 * R2, l, R3, nb);
+    g.a(in.G, R3, in.sG).b(M[2], R3, sZ[2], true).c(T1, l, sH);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+  } else {
+    // M3^T (R3 x l per system), then the structured mode-3 product
+    hipLaunchKernelGGL(k_swap_mid, dim3(grid_for((long long)R3 * l * nb)), dim3(kB), 0, s, (const double*)M[2], KM,
+                       (long long)nb, l, R3, (long long)1);
+    LRFG_LAUNCHED();
+    LRFG_TRY(kron_mode3(*kc, KM, sZ[2], l, nb, T1, s));
+  }
   const long long sT2 = (long long)l * R2 * l;
   { GB g(l, R2 * l, R1, nb); g.a(M[0], R1, sZ[0]).b(T1, (long long)R2 * l, sH).c(T2, (long long)R2 * l, sT2);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
