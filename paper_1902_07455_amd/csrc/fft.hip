@@ -306,9 +306,10 @@ int launch_mode_op_blocks(const double* xin, long long sx, int r0, int r1, int n
     tp.t[i] = i < M ? t[i] : 0.0;
     tp.sc[i] = i < M ? sc[i] : 0.0;
   }
-  const int T = lines_per_tile1(N);
+  const long long npair = (long long)nE * ((r0 * r1 + 1) / 2);
+  const int T = lines_per_tile1(N, (int)std::min<long long>(64, std::max<long long>(1, (npair * M + 511) / 512)));
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
-  dim3 grid(ceil_div((long long)nE * ((r0 * r1 + 1) / 2), T), M);
+  dim3 grid(ceil_div(npair, T), M);
   ProfScope ps_("mode_op_blocks", s);
   if (plan_generic(f))
     hipLaunchKernelGGL(k_mode_op_blocks<true>, grid, dim3(kFftBlock), shm, s, xin, sx, r0, r1, nE, out, so, R1,
@@ -372,7 +373,9 @@ int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, lon
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
   }
-  const int T = lines_per_tile1(N);
+  // few lines: fewer per block, so that they spread over the CUs (a line's
+  // transform is the same whatever the tile it sits in)
+  const int T = lines_per_tile1(N, (int)std::min<long long>(64, std::max<long long>(1, (npair + 511) / 512)));
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(npair, T);
   ProfScope ps_("mode_op", s);

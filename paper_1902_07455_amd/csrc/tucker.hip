@@ -142,16 +142,34 @@ __global__ void k_tcontract(const double* __restrict__ H, long long sH, const do
     const long long rem = idx - e * per;
     const long long row = rem / l, t = rem - row * l;
     const double* h = H + e * sH;
-    double acc = 0.0;
+    // four independent partial sums keep several loads in flight
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (row < R1) {
       const double* z = Z2 + e * sZ2;
-      for (int i2 = 0; i2 < R2; ++i2) acc += h[(row * R2 + i2) * l + t] * z[(long long)i2 * l + t];
-      y1[e * sy1 + row * l + t] = acc;
+      const double* hr = h + row * R2 * l + t;
+      int i2 = 0;
+      for (; i2 + 3 < R2; i2 += 4) {
+        a0 += hr[(long long)i2 * l] * z[(long long)i2 * l + t];
+        a1 += hr[(long long)(i2 + 1) * l] * z[(long long)(i2 + 1) * l + t];
+        a2 += hr[(long long)(i2 + 2) * l] * z[(long long)(i2 + 2) * l + t];
+        a3 += hr[(long long)(i2 + 3) * l] * z[(long long)(i2 + 3) * l + t];
+      }
+      for (; i2 < R2; ++i2) a0 += hr[(long long)i2 * l] * z[(long long)i2 * l + t];
+      y1[e * sy1 + row * l + t] = (a0 + a1) + (a2 + a3);
     } else {
       const long long i2 = row - R1;
       const double* z = Z1 + e * sZ1;
-      for (int i1 = 0; i1 < R1; ++i1) acc += h[((long long)i1 * R2 + i2) * l + t] * z[(long long)i1 * l + t];
-      y2[e * sy2 + i2 * l + t] = acc;
+      const double* hc = h + i2 * l + t;
+      const long long st = (long long)R2 * l;
+      int i1 = 0;
+      for (; i1 + 3 < R1; i1 += 4) {
+        a0 += hc[i1 * st] * z[(long long)i1 * l + t];
+        a1 += hc[(i1 + 1) * st] * z[(long long)(i1 + 1) * l + t];
+        a2 += hc[(i1 + 2) * st] * z[(long long)(i1 + 2) * l + t];
+        a3 += hc[(i1 + 3) * st] * z[(long long)(i1 + 3) * l + t];
+      }
+      for (; i1 < R1; ++i1) a0 += hc[i1 * st] * z[(long long)i1 * l + t];
+      y2[e * sy2 + i2 * l + t] = (a0 + a1) + (a2 + a3);
     }
   }
 }
