@@ -72,10 +72,12 @@ typedef enum {
   LRFG_SOLVER_MR = 1        /* minimal-residual iteration (Sec. 3.3)         */
 } lrfg_solver;
 
-/* Mixed precision (low-rank formats only): iterative refinement whose
- * inner truncated solves run the truncation's contractions with FP32 or
- * BF16 inputs and FP32 accumulation (inner tolerance max(solver_tol, 1e-4)
- * for FP32, max(solver_tol, 1e-2) for BF16), while the correction update,
+/* Mixed precision (TT and CP formats): iterative refinement whose inner
+ * truncated solves run the truncation's contractions with FP32 inputs and
+ * FP32 accumulation (FP32), or its sketch contractions with BF16 inputs and
+ * its projections with FP32 inputs (BF16) (inner tolerance
+ * max(solver_tol, 1e-4) for FP32, max(solver_tol, 1e-2) for BF16), while the
+ * correction update,
  * the residual b - K x, the small factorisations of the truncation, the
  * solver scalars and A_H stay FP64; it stops when the FP64 preconditioned
  * residual reaches solver_tol or when two outer steps in a row fail to

@@ -437,6 +437,10 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     return LRFG_EINVAL;
   }
   const int nE = batch;
+  // sketch contractions (against the Gaussian carriages) run in the
+  // Rounder's precision; projections onto the orthonormal bases need more
+  // than BF16's 8-bit significands and run in FP32 at the BF16 setting
+  const int pj = prec == LRFG_PREC_MIXED_BF16 ? LRFG_PREC_MIXED_FP32 : prec;
   const double tol2 = tol * tol / (double)(d - 1);
   const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
   if (d == 3) {
@@ -474,10 +478,10 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     LRFG_TRY(orth(*this, Y1, Q1, N1, l1, nE, s));
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     { GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
           .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     // Y2 = X2' W3 ((l1 N2) x l2) ; Q2 = orth(Y2)
     { GemmB g(l1 * N2, l2, R2, nE); g.a(X2p, R2, (long long)l1 * N2 * R2).b(W3, l2, (long long)R2 * l2)
           .c(Y2, l2, (long long)l1 * N2 * l2);
@@ -486,34 +490,34 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     // M2 = Q2^T X2' (l2 x R2) ; X3' = M2 X3 (l2 x N3)
     { GemmB g(l2, R2, l1 * N2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2, true).b(X2p, R2, (long long)l1 * N2 * R2)
           .c(M2, R2, (long long)l2 * R2);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     { GemmB g(l2, N3, R2, nE); g.a(M2, R2, (long long)l2 * R2).b(in.c[2], N3, in.s[2]).c(X3p, N3, (long long)l2 * N3);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     // ---- cut at bond 2: G = X3' X3'^T, S3 = kept eigenvectors (l2 x c2)
     { GemmB g(l2, l2, N3, nE); g.a(X3p, N3, (long long)l2 * N3).b(X3p, N3, (long long)l2 * N3, true).c(G, l2, (long long)l2 * l2);
       LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     LRFG_TRY(trunc_mask(*this, G, l2, c2, tol2, S3, kept + this->nE, nE, s));
     { GemmB g(c2, N3, l2, nE); g.a(S3, c2, (long long)l2 * c2, true).b(X3p, N3, (long long)l2 * N3).c(out.c[2], N3, out.s[2]);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     // Q2s = Q2 S3 ((l1 N2) x c2); P = X3 X3^T (c2 x c2); U = Q2s P
     { GemmB g(l1 * N2, c2, l2, nE); g.a(Q2, l2, (long long)l1 * N2 * l2).b(S3, c2, (long long)l2 * c2)
           .c(Q2s, c2, (long long)l1 * N2 * c2);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     { GemmB g(c2, c2, N3, nE); g.a(out.c[2], N3, out.s[2]).b(out.c[2], N3, out.s[2], true).c(P, c2, (long long)c2 * c2);
       LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     { GemmB g(l1 * N2, c2, c2, nE); g.a(Q2s, c2, (long long)l1 * N2 * c2).b(P, c2, (long long)c2 * c2)
           .c(U, c2, (long long)l1 * N2 * c2);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     // ---- cut at bond 1: G1 = U Q2s^T over (n, b) (l1 x l1)
     { GemmB g(l1, l1, N2 * c2, nE); g.a(U, (long long)N2 * c2, (long long)l1 * N2 * c2)
           .b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2, true).c(G, l1, (long long)l1 * l1);
       LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
     LRFG_TRY(trunc_mask(*this, G, l1, c1, tol2, S1, kept, nE, s));
     { GemmB g(N1, c1, l1, nE); g.a(Q1, l1, (long long)N1 * l1).b(S1, c1, (long long)l1 * c1).c(out.c[0], c1, out.s[0]);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     { GemmB g(c1, N2 * c2, l1, nE); g.a(S1, c1, (long long)l1 * c1, true).b(Q2s, (long long)N2 * c2, (long long)l1 * N2 * c2)
           .c(out.c[1], (long long)N2 * c2, out.s[1]);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
     return LRFG_OK;
   }
   // d = 2
@@ -536,16 +540,16 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   LRFG_TRY(orth(*this, Y1, Q1, N1, l, nE, s));
   { GemmB g(l, R1, N1, nE); g.a(Q1, l, (long long)N1 * l, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l * R1);
-    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
   { GemmB g(l, N2, R1, nE); g.a(M1, R1, (long long)l * R1).b(in.c[1], N2, in.s[1]).c(X3p, N2, (long long)l * N2);
-    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
   { GemmB g(l, l, N2, nE); g.a(X3p, N2, (long long)l * N2).b(X3p, N2, (long long)l * N2, true).c(G, l, (long long)l * l);
     LRFG_TRY(gemm(prec_of(g.g, LRFG_PREC_FP64), gscr, gscr_n, s)); }
   LRFG_TRY(trunc_mask(*this, G, l, c1, tol * tol, S1, kept, nE, s));
   { GemmB g(c1, N2, l, nE); g.a(S1, c1, (long long)l * c1, true).b(X3p, N2, (long long)l * N2).c(out.c[1], N2, out.s[1]);
-    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
   { GemmB g(N1, c1, l, nE); g.a(Q1, l, (long long)N1 * l).b(S1, c1, (long long)l * c1).c(out.c[0], c1, out.s[0]);
-    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
   return LRFG_OK;
 }
 
