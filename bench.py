@@ -24,7 +24,7 @@ hipExtLaunchKernelGGL, i.e. the dispatch's own timestamps), so the events do
 not perturb the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                    [--crossover 243,405] [--no-crossover]
+                    [--crossover 243,405,729] [--no-crossover]
 """
 from __future__ import annotations
 
@@ -283,7 +283,7 @@ def main(argv=None):
     ap.add_argument("--full-steps", type=int, default=200, help="timed full-grid solves")
     ap.add_argument("--prof-solves", type=int, default=5, help="solves in each kernel-timing pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--crossover", default="243,405", help="grid sizes of the crossover table")
+    ap.add_argument("--crossover", default="243,405,729", help="grid sizes of the crossover table")
     ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker-format leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
