@@ -539,9 +539,9 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long k) {
 // (the same in every thread).  With Z != null it also builds Z (LDS, row k
 // = z_k, original coordinates) with z_k = (e_p - sum_{j<k} L[j][p] z_j) /
 // L[k][p], the columns of P R^-1 (Gram-Schmidt in the G inner product), so
-// that Y z_k are orthonormal when G = Y^T Y.  Wave 0 picks the pivot; the
-// last wave builds z_k; all threads update the Schur complement, thread t
-// on row t / (NT / 64) and every (NT / 64)-th column.
+// that Y z_k are orthonormal when G = Y^T Y.  Wave 0 picks the pivot; all
+// threads update the Schur complement, thread t on row t / (NT / 64) and
+// every (NT / 64)-th column, and build z_k, NT / 64 threads per component.
 template <int NT>
 __device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L, double* __restrict__ Z,
                            int* __restrict__ perm, double tau, int* __restrict__ bc) {
@@ -549,7 +549,6 @@ __device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L
   const int tid = threadIdx.x;
   const bool w0 = tid < 64;
   const int lane = tid & 63;
-  const int zl = tid - (NT - 64);  // lane of the last wave
   const int ri = tid / CG, rj = tid - ri * CG;
   bool chosen = lane >= n;
   double d0 = 0.0;
@@ -590,19 +589,17 @@ __device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L
       if (li != 0.0)
         for (int j = rj; j < n; j += CG) g[ri * n + j] -= li * lk[j];
     }
-    if (Z != nullptr && zl >= 0 && zl < n) {
-      // four independent partial sums keep several LDS loads in flight
+    if (Z != nullptr) {
+      // component zc of z_k, its sum split over the CG threads of an
+      // aligned group (j = q, q + CG, ...) and added by DPP moves
       const int p = bc[1];
-      double a0 = (zl == p) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int j = 0;
-      for (; j + 3 < k; j += 4) {
-        a0 -= L[j * n + p] * Z[j * n + zl];
-        a1 -= L[(j + 1) * n + p] * Z[(j + 1) * n + zl];
-        a2 -= L[(j + 2) * n + p] * Z[(j + 2) * n + zl];
-        a3 -= L[(j + 3) * n + p] * Z[(j + 3) * n + zl];
-      }
-      for (; j < k; ++j) a0 -= L[j * n + p] * Z[j * n + zl];
-      Z[k * n + zl] = ((a0 + a1) + (a2 + a3)) / lk[p];
+      const int zc = tid / CG, q = tid - zc * CG;
+      double a = 0.0;
+      if (zc < n)
+        for (int j = q; j < k; j += CG) a += L[j * n + p] * Z[j * n + zc];
+      if (CG >= 2) a += dpp_move<kDppSwap1>(a);
+      if (CG >= 4) a += dpp_move<kDppSwap2>(a);
+      if (q == 0 && zc < n) Z[k * n + zc] = (((zc == p) ? 1.0 : 0.0) - a) / lk[p];
     }
     __syncthreads();
   }
