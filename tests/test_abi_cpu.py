@@ -223,6 +223,35 @@ def test_gram_cut_validation_before_device():
     assert lib.lrfg_gram_cut(4, 2, C.addressof(buf), 0, 0.0, C.addressof(buf), None, None, None) == 0
 
 
+def test_compress_tucker_validation_before_device():
+    """Bad sizes or pointers are refused before any device work; the
+    workspace size grows with the grid and the cap."""
+    lib = _lib().lib()
+    N = (C.c_int * 3)(15, 17, 19)
+    n1 = lib.lrfg_compress_tucker_workspace_bytes(N, 6, 10)
+    n2 = lib.lrfg_compress_tucker_workspace_bytes(N, 12, 10)
+    assert 0 < n1 < n2
+    assert lib.lrfg_compress_tucker_workspace_bytes(N, 0, 10) == 0
+    assert lib.lrfg_compress_tucker_workspace_bytes((C.c_int * 3)(15, 0, 19), 6, 10) == 0
+    buf = (C.c_double * 16)()
+    frames = (C.c_void_p * 3)(C.addressof(buf), C.addressof(buf), C.addressof(buf))
+    ranks = (C.c_int * 3)()
+    # null field, null outputs, negative or NaN tolerance, cap < 1
+    assert lib.lrfg_compress_tucker(N, None, 6, 0.0, 10, 0, frames, C.addressof(buf), ranks, None,
+                                    C.c_void_p(256), n1, None) == -1
+    assert lib.lrfg_compress_tucker(N, C.addressof(buf), 6, 0.0, 10, 0, None, C.addressof(buf), ranks, None,
+                                    C.c_void_p(256), n1, None) == -1
+    assert lib.lrfg_compress_tucker(N, C.addressof(buf), 6, -1.0, 10, 0, frames, C.addressof(buf), ranks, None,
+                                    C.c_void_p(256), n1, None) == -1
+    assert lib.lrfg_compress_tucker(N, C.addressof(buf), 6, float("nan"), 10, 0, frames, C.addressof(buf), ranks,
+                                    None, C.c_void_p(256), n1, None) == -1
+    assert lib.lrfg_compress_tucker(N, C.addressof(buf), 0, 0.0, 10, 0, frames, C.addressof(buf), ranks, None,
+                                    C.c_void_p(256), n1, None) == -1
+    # workspace below the reported size
+    assert lib.lrfg_compress_tucker(N, C.addressof(buf), 6, 0.0, 10, 0, frames, C.addressof(buf), ranks, None,
+                                    C.c_void_p(256), n1 - 1024, None) == -3
+
+
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and not os.path.exists("/dev/kfd"),
                     reason="no ROCm device nodes")
 def test_device_check_runs():

@@ -183,3 +183,36 @@ def test_server_arrivals_while_running(dev):
     for c in got:
         assert c.status == alone[c.tag].rc
         assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL
+
+
+def test_server_tucker_requests(dev):
+    """Tucker-format requests (CP and Tucker coefficient forms) through the
+    serving loop: each result equals its solo solve, and requests of one
+    problem with the same coefficient form are batched (run one after
+    another inside the batch)."""
+    import torch
+    N = 21
+    prob = dict(d=3, N=(N,) * 3, format="tucker", rank_cap=6, solver_tol=1e-6, max_iter=60, coeff_rank=9)
+    reqs = []
+    for i in range(4):
+        cp = _smooth(N, 200 + i, 3.0 + 5.0 * i)
+        if i % 2 == 0:
+            reqs.append(dict(cp=(cp.weights, cp.factors)))
+        else:
+            (core, frames), _ = P.compress_tucker(torch.from_numpy(cp.full()).to(dev), cap=6, seed=i)
+            reqs.append(dict(tucker=(core, frames)))
+    alone = []
+    for kw in reqs:
+        s = P.Solver(**prob)
+        alone.append(s.solve(**kw))
+        s.close()
+    srv = P.Server(slots=2, max_batch=4, pool_bytes=1 << 30)
+    for i, kw in enumerate(reqs):
+        srv.submit(prob, tag=i, **kw)
+    done = srv.drain()
+    srv.close()
+    assert sorted(c.tag for c in done) == list(range(4))
+    for c in done:
+        assert c.status == alone[c.tag].rc
+        assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL
+        assert list(c.result.iters) == list(alone[c.tag].iters)
