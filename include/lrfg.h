@@ -74,8 +74,9 @@ typedef enum {
 
 /* Mixed precision (TT and CP formats): iterative refinement whose inner
  * truncated solves run the truncation's contractions with FP32 inputs and
- * FP32 accumulation (FP32), or its sketch contractions with BF16 inputs and
- * its projections with FP32 inputs (BF16) (inner tolerance
+ * FP32 accumulation (FP32), or its sketch contractions on BF16 MFMA with
+ * each operand split into two BF16 terms (hi + lo, three products, FP32
+ * accumulation) and its projections with FP32 inputs (BF16) (inner tolerance
  * max(solver_tol, 1e-4) for FP32, max(solver_tol, 1e-2) for BF16), while the
  * correction update,
  * the residual b - K x, the small factorisations of the truncation, the

@@ -231,20 +231,34 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
     __syncthreads();
     if (k0 + LK < ke) fetch(k0 + LK);
     if (BF) {
-      bf16x8 a[2], b[2];
+      // two-term split of each FP32 operand: x = hi + lo (both BF16, lo =
+      // BF16(x - hi)); the product takes hi*hi + hi*lo + lo*hi (lo*lo, of
+      // relative size 2^-16, dropped), about 16 significant bits
+      bf16x8 a[2], b[2], al[2], bl[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[bi][j] = (__bf16)As[8 * (lane >> 4) + j][wm * 32 + bi * 16 + (lane & 15)];
+        for (int j = 0; j < 8; ++j) {
+          const float x = As[8 * (lane >> 4) + j][wm * 32 + bi * 16 + (lane & 15)];
+          a[bi][j] = (__bf16)x;
+          al[bi][j] = (__bf16)(x - (float)a[bi][j]);
+        }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) b[bj][j] = (__bf16)Bs[8 * (lane >> 4) + j][wn * 32 + bj * 16 + (lane & 15)];
+        for (int j = 0; j < 8; ++j) {
+          const float x = Bs[8 * (lane >> 4) + j][wn * 32 + bj * 16 + (lane & 15)];
+          b[bj][j] = (__bf16)x;
+          bl[bj][j] = (__bf16)(x - (float)b[bj][j]);
+        }
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj) {
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], b[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], bl[bj], acc[bi][bj], 0, 0, 0);
           acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
     } else {
 #pragma unroll
       for (int kk = 0; kk < LK; kk += 4) {

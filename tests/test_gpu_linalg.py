@@ -136,13 +136,23 @@ def _round_bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _split_bf16(x):
+    """The kernel's two-term split: x32 = FP32(x), hi = BF16(x32),
+    lo = BF16(x32 - hi) (the difference is exact in FP32)."""
+    x32 = x.astype(np.float32).astype(np.float64)
+    hi = _round_bf16(x32)
+    lo = _round_bf16(x32 - hi)
+    return hi, lo
+
+
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (64, 64, 32), (65, 63, 33), (100, 30, 4050), (2430, 30, 180),
                                    (30, 30, 24300), (7, 200, 1)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_gemm_mixed(dev, m, n, k, ta, tb, prec):
     """Reduced-precision MFMA GEMM against numpy on operands rounded the same
-    way; the FP32 accumulation error bound is k u32 sum|a||b| (u32 = 2^-24)."""
+    way (FP32; BF16 as the hi + lo split of the FP32 value, three products);
+    the FP32 accumulation error bound is (terms) u32 sum|a||b| (u32 = 2^-24)."""
     import torch
     rng = np.random.default_rng(m + 3 * n + 7 * k + 11 * ta + 13 * tb + len(prec))
     batch = 2
@@ -152,11 +162,20 @@ def test_gemm_mixed(dev, m, n, k, ta, tb, prec):
     tA, tB, tC = (torch.from_numpy(x).to(dev) for x in (A, B, C0))
     P.gemm(tA, tB, tC, ta=bool(ta), tb=bool(tb), alpha=0.5, beta=2.0, precision=prec)
     torch.cuda.synchronize()
-    rnd = _round_f32 if prec == "fp32" else _round_bf16
-    opA = rnd(np.swapaxes(A, 1, 2) if ta else A)
-    opB = rnd(np.swapaxes(B, 1, 2) if tb else B)
-    ref = 0.5 * opA @ opB + 2.0 * C0
-    bound = 0.5 * (k + 2) * 2.0 ** -24 * (np.abs(opA) @ np.abs(opB)) + 1e-15 * np.abs(ref)
+    A_ = np.swapaxes(A, 1, 2) if ta else A
+    B_ = np.swapaxes(B, 1, 2) if tb else B
+    if prec == "fp32":
+        opA, opB = _round_f32(A_), _round_f32(B_)
+        ref = 0.5 * opA @ opB + 2.0 * C0
+        mag = np.abs(opA) @ np.abs(opB)
+        nterm = k
+    else:
+        # hi*hi + hi*lo + lo*hi of the split operands
+        (ah, al), (bh, bl) = _split_bf16(A_), _split_bf16(B_)
+        ref = 0.5 * (ah @ bh + ah @ bl + al @ bh) + 2.0 * C0
+        mag = np.abs(ah) @ np.abs(bh) + np.abs(ah) @ np.abs(bl) + np.abs(al) @ np.abs(bh)
+        nterm = 3 * k
+    bound = 0.5 * (nterm + 2) * 2.0 ** -24 * mag + 1e-15 * np.abs(ref)
     assert np.all(np.abs(tC.cpu().numpy() - ref) <= bound)
     # and the rounding really happened (BF16 differs from FP64 visibly)
     if prec == "bf16" and k >= 32:
