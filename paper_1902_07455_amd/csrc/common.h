@@ -66,6 +66,28 @@ struct Arena {
   }
 };
 
+// ---------------------------------------------------------------- events
+// HIP events owned for one scope: destroyed on every return path.
+template <int K>
+struct ScopedEvents {
+  hipEvent_t e[K] = {};
+  int create(unsigned flags = hipEventDefault) {
+    for (int i = 0; i < K; ++i) {
+      if (hipEventCreateWithFlags(&e[i], flags) != hipSuccess) {
+        e[i] = nullptr;
+        set_error("hipEventCreate failed");
+        return LRFG_EDEVICE;
+      }
+    }
+    return LRFG_OK;
+  }
+  hipEvent_t& operator[](int i) { return e[i]; }
+  ~ScopedEvents() {
+    for (int i = 0; i < K; ++i)
+      if (e[i] != nullptr) (void)hipEventDestroy(e[i]);
+  }
+};
+
 // ---------------------------------------------------------------- complex
 __host__ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

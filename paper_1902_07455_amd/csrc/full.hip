@@ -624,10 +624,9 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     return LRFG_EWORKSPACE;
   }
   const G3 g = L.g;
-  hipEvent_t ev0, ev1, ev2;
-  LRFG_HIP(hipEventCreate(&ev0));
-  LRFG_HIP(hipEventCreate(&ev1));
-  LRFG_HIP(hipEventCreate(&ev2));
+  ScopedEvents<3> evs3;
+  LRFG_TRY(evs3.create());
+  hipEvent_t &ev0 = evs3[0], &ev1 = evs3[1], &ev2 = evs3[2];
   LRFG_HIP(hipEventRecord(ev0, s));
 
   FftDev f1, f2, f3;
@@ -703,8 +702,8 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   // ------------------------------------------------------------ PCG loop
   const int ring = 4;
   int* pinned = A.pinned_flags;  // ring * nE ints, pinned host memory from the plan
-  hipEvent_t evs[4];
-  for (int i = 0; i < ring; ++i) LRFG_HIP(hipEventCreateWithFlags(&evs[i], hipEventDisableTiming));
+  ScopedEvents<4> evs;
+  LRFG_TRY(evs.create(hipEventDisableTiming));
   int it = 0;
   bool all_done = false;
   int checked = -1;
@@ -771,7 +770,6 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   (void)checked;
   (void)all_done;
   LRFG_HIP(hipStreamSynchronize(s));
-  for (int i = 0; i < ring; ++i) LRFG_HIP(hipEventDestroy(evs[i]));
 
   // ------------------------------------------------------------ A_H
   // For each alpha: g_{e,alpha} = F^-1(2 pi i k_alpha x_e) into the q buffers
@@ -816,9 +814,6 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   float ms_setup = 0.f, ms_solve = 0.f;
   LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
   LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
-  LRFG_HIP(hipEventDestroy(ev0));
-  LRFG_HIP(hipEventDestroy(ev1));
-  LRFG_HIP(hipEventDestroy(ev2));
 
   // A_H[i][j] = mean(a) E_i.E_j + sum_alpha (E_i,alpha m1[j] + E_j,alpha m1[i] + m2[i][j])
   int rc = LRFG_OK;

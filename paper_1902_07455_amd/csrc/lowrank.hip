@@ -521,10 +521,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   }
   C.s = s;
   const int na = C.na;
-  hipEvent_t ev0, ev1, ev2;
-  LRFG_HIP(hipEventCreate(&ev0));
-  LRFG_HIP(hipEventCreate(&ev1));
-  LRFG_HIP(hipEventCreate(&ev2));
+  ScopedEvents<3> evs3;
+  LRFG_TRY(evs3.create());
+  hipEvent_t &ev0 = evs3[0], &ev1 = evs3[1], &ev2 = evs3[2];
   LRFG_HIP(hipEventRecord(ev0, s));
   for (int j = 0; j < d; ++j) {
     double2* tw = const_cast<double2*>(C.f[j].tw);
@@ -870,9 +869,6 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   float ms_setup = 0.f, ms_solve = 0.f;
   LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
   LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
-  LRFG_HIP(hipEventDestroy(ev0));
-  LRFG_HIP(hipEventDestroy(ev1));
-  LRFG_HIP(hipEventDestroy(ev2));
   int rc = LRFG_OK;
   for (int b = 0; b < nB; ++b) {
     lrfg_result* out = &outs[b];
@@ -1181,10 +1177,9 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     return LRFG_EWORKSPACE;
   }
   C.s = s;
-  hipEvent_t ev0, ev1, ev2;
-  LRFG_HIP(hipEventCreate(&ev0));
-  LRFG_HIP(hipEventCreate(&ev1));
-  LRFG_HIP(hipEventCreate(&ev2));
+  ScopedEvents<3> evs3;
+  LRFG_TRY(evs3.create());
+  hipEvent_t &ev0 = evs3[0], &ev1 = evs3[1], &ev2 = evs3[2];
   LRFG_HIP(hipEventRecord(ev0, s));
   for (int j = 0; j < 3; ++j) {
     double2* tw = const_cast<double2*>(C.f[j].tw);
@@ -1413,9 +1408,6 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
   float ms_setup = 0.f, ms_solve = 0.f;
   LRFG_HIP(hipEventElapsedTime(&ms_setup, ev0, ev1));
   LRFG_HIP(hipEventElapsedTime(&ms_solve, ev1, ev2));
-  LRFG_HIP(hipEventDestroy(ev0));
-  LRFG_HIP(hipEventDestroy(ev1));
-  LRFG_HIP(hipEventDestroy(ev2));
   int rc = LRFG_OK;
   for (int i = 0; i < nE; ++i) {
     for (int j = 0; j < nE; ++j) {
