@@ -72,7 +72,7 @@ typedef enum {
   LRFG_SOLVER_MR = 1        /* minimal-residual iteration (Sec. 3.3)         */
 } lrfg_solver;
 
-/* Mixed precision (TT and CP formats): iterative refinement whose inner
+/* Mixed precision (TT, Tucker and CP formats): iterative refinement whose inner
  * truncated solves run the truncation's contractions with FP32 inputs and
  * FP32 accumulation (FP32), or its sketch contractions on BF16 MFMA with
  * each operand split into two BF16 terms (hi + lo, three products, FP32

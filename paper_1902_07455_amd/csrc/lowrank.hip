@@ -371,8 +371,8 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
     }
   }
   if (p.format == LRFG_FORMAT_TUCKER) {
-    if (p.d != 3 || p.precision != LRFG_PREC_FP64) {
-      set_error("the Tucker format is built for d = 3 in FP64");
+    if (p.d != 3) {
+      set_error("the Tucker format is built for d = 3");
       delete pl;
       return LRFG_EUNSUPPORTED;
     }
@@ -954,6 +954,7 @@ struct TkCtx {
   TKB a;                    // coefficient (shared, stride 0)
   TKB xr, pq, x, r, p, q;   // [x; r], [p; q] and their halves
   TKB z, xb, b, tmp;
+  TKB b0, xa, xbest;        // refinement: right-hand side, iterate, best iterate
   TKB kr;                   // a (.) D_alpha v, d nE tensors
   TKB h;                    // truncated material terms, d nE tensors
   TKB comb;                 // block sums, 2 nE tensors (capacity ranks)
@@ -961,6 +962,7 @@ struct TkCtx {
   double* hframe[3];        // frame buffers for D_alpha^T h_alpha
   double* aframe[3];        // frames of D_alpha a (right-hand side)
   double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
+  double *ones, *mones;
   double* stage;            // host CP coefficient staged on the device
   int* done;
   int cap[3];
@@ -994,6 +996,11 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   C.xb = tk_alloc(ar, N, rc, nE);
   C.b = tk_alloc(ar, N, rc, nE);
   C.tmp = tk_alloc(ar, N, rc, nE);
+  if (pl->p.precision != LRFG_PREC_FP64) {
+    C.b0 = tk_alloc(ar, N, rc, nE);
+    C.xa = tk_alloc(ar, N, rc, nE);
+    C.xbest = tk_alloc(ar, N, rc, nE);
+  }
   C.h = tk_alloc(ar, N, rc, 3 * nE);
   int rkr[3], cap[3];
   for (int j = 0; j < 3; ++j) {
@@ -1044,6 +1051,8 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   C.Ecoef = ar.take<double>((size_t)3 * nE);
   C.coef2 = ar.take<double>((size_t)2 * nE);
   C.done = ar.take<int>(nE);
+  C.ones = ar.take<double>(nE);
+  C.mones = ar.take<double>(nE);
   C.stage = ar.take<double>((size_t)pl->ra * (1 + N[0] + N[1] + N[2]));
   size_t dn = tk_dot_scratch(C.kr, C.z, 3 * nE);  // A_H cross terms: up to 3 pairs per system
   dn = std::max(dn, tk_dot_scratch(C.a, C.a, nE));
@@ -1266,113 +1275,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     floor_abs[e] = 1e-14 * rms_a * std::sqrt(en) * std::sqrt(Ntot);
   }
   LRFG_HIP(hipEventRecord(ev1, s));
-  // ---------------------------------------------------------------- solver
-  const int maxit = P.max_iter;
-  std::vector<double> hist((size_t)nE * maxit, 0.0), best(nE, INFINITY), res0(nE, 0.0), zzh(nE);
-  std::vector<int> iters(nE, 0), hdone(nE, 0), status(nE, LRFG_OK), since_best(nE, 0);
-  const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
-  // kept mode ranks of the latest x truncation (mode j of system e at
-  // kx[j nE + e]) and those of each system's kept iterate
-  std::vector<int> kx(3 * nE, 0), kbest(3 * nE, 0);
-  auto fetch_kept = [&]() -> int {
-    for (int j = 0; j < 3; ++j)
-      LRFG_HIP(hipMemcpyAsync(kx.data() + j * nE, C.rd.kept + (long long)j * C.rd.kept_batch, sizeof(int) * nE,
-                              hipMemcpyDeviceToHost, s));
-    return LRFG_OK;
-  };
-  LRFG_TRY(tk_zero(C.xr, 2 * nE, s));
-  LRFG_TRY(tk_zero(C.xb, nE, s));
-  auto upload_done = [&]() -> int {
-    LRFG_HIP(hipMemcpyAsync(C.done, hdone.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
-    return LRFG_OK;
-  };
-  LRFG_TRY(upload_done());
-  if (P.solver == LRFG_SOLVER_PCG) {
-    LRFG_TRY(tk_copy(C.b, C.r, nE, s));
-    LRFG_TRY(tk_apply_P(C, C.r, C.z));
-    LRFG_TRY(tk_copy(C.z, C.p, nE, s));
-    LRFG_TRY(tk_dot(C.r, C.z, C.rho, C.dscr, nE, s));
-    LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
-  } else {
-    LRFG_TRY(tk_apply_P(C, C.b, C.z));
-    LRFG_TRY(tk_copy(C.z, C.b, nE, s));
-    LRFG_TRY(tk_copy(C.b, C.r, nE, s));
-    LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
-  }
-  LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
-  for (int e = 0; e < nE; ++e) {
-    res0[e] = std::sqrt(std::max(zzh[e], 0.0));
-    if (res0[e] <= floor_abs[e]) hdone[e] = 1;
-  }
-  LRFG_TRY(upload_done());
-  for (int it = 0; it < maxit; ++it) {
-    bool all = true;
-    for (int e = 0; e < nE; ++e) all = all && hdone[e];
-    if (all) break;
-    if (P.solver == LRFG_SOLVER_PCG) {
-      LRFG_TRY(tk_apply_K(C, C.p, C.q));
-      LRFG_TRY(tk_dot(C.p, C.q, C.pqd, C.dscr, nE, s));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.rho, (const double*)C.pqd,
-                         (const int*)C.done, C.alpha, nE);
-      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
-      LRFG_LAUNCHED();
-      LRFG_TRY(tk_update_xr(C));
-      LRFG_TRY(fetch_kept());
-      LRFG_TRY(tk_apply_P(C, C.r, C.z));
-      LRFG_TRY(tk_dot(C.r, C.z, C.dots, C.dscr, nE, s));
-      LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
-      hipLaunchKernelGGL(k_beta, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, C.rho, (const int*)C.done,
-                         C.beta, nE);
-      LRFG_LAUNCHED();
-      LRFG_TRY(tk_axpby(C, C.z, C.p, C.beta, C.tmp));
-      LRFG_TRY(tk_copy(C.tmp, C.p, nE, s));
-    } else {
-      LRFG_TRY(tk_apply_K(C, C.r, C.tmp));
-      LRFG_TRY(tk_apply_P(C, C.tmp, C.z));
-      LRFG_TRY(tk_dot(C.z, C.r, C.dots, C.dscr, nE, s));
-      LRFG_TRY(tk_dot(C.z, C.z, C.pqd, C.dscr, nE, s));
-      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, (const double*)C.pqd,
-                         (const int*)C.done, C.alpha, nE);
-      hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
-      LRFG_LAUNCHED();
-      LRFG_TRY(tk_copy(C.r, C.p, nE, s));
-      LRFG_TRY(tk_copy(C.z, C.q, nE, s));
-      LRFG_TRY(tk_update_xr(C));
-      LRFG_TRY(fetch_kept());
-      LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
-    }
-    LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
-    bool changed = false;
-    for (int e = 0; e < nE; ++e) {
-      if (hdone[e]) continue;
-      const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
-      hist[(size_t)e * maxit + it] = res;
-      iters[e] = it + 1;
-      if (res < best[e]) {
-        best[e] = res;
-        since_best[e] = 0;
-        LRFG_TRY(tk_copy_system(C.x, C.xb, e, s));
-        for (int j = 0; j < 3; ++j) kbest[j * nE + e] = kx[j * nE + e];
-      } else {
-        ++since_best[e];
-      }
-      if (res <= P.solver_tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
-        hdone[e] = 1;
-        changed = true;
-      } else if (since_best[e] >= patience) {
-        hdone[e] = 1;
-        changed = true;
-        if (best[e] > P.solver_tol) status[e] = LRFG_NOT_CONVERGED;
-      }
-    }
-    if (changed) LRFG_TRY(upload_done());
-  }
-  for (int e = 0; e < nE; ++e) {
-    if (!hdone[e]) status[e] = LRFG_NOT_CONVERGED;
-    if (res0[e] <= floor_abs[e]) status[e] = LRFG_OK;
-  }
-  // ---------------------------------------------------------------- A_H (eq. homog)
-  std::vector<double> m1((size_t)nE * 3), m2((size_t)nE * nE * 3);
+  // mean of the coefficient (the E.E term of the energy form)
   double mean_a = 0.0;
   {
     TKB one = C.tmp;
@@ -1387,6 +1290,225 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     LRFG_TRY(tk_read(C, C.dots, &mean_a, 1));
     mean_a /= Ntot;
   }
+  // Energy form of eq. (homog) for system e's own field (an upper bound of
+  // A_H E_e.E_e that decreases as x_e improves, Sec. 4.3), exact for the
+  // given Tucker tensors: the Hadamard core is formed for nE systems here.
+  auto energy_diag = [&](const TKB& X, std::vector<double>& en) -> int {
+    for (int e = 0; e < nE; ++e) {
+      double ee = 0.0;
+      for (int al = 0; al < 3; ++al) ee += E[e * 3 + al] * E[e * 3 + al];
+      en[e] = mean_a * ee;
+    }
+    std::vector<double> v(nE);
+    for (int al = 0; al < 3; ++al) {
+      TKB g = X;
+      g.U[al] = C.gframe;
+      LRFG_TRY(tk_mode_apply(X, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
+      LRFG_TRY(tk_dot(C.a, g, C.dots, C.dscr, nE, s));
+      LRFG_TRY(tk_read(C, C.dots, v.data(), nE));
+      for (int e = 0; e < nE; ++e) en[e] += 2.0 * E[e * 3 + al] * v[e] / Ntot;
+      TKB kr = C.kr;
+      LRFG_TRY(tk_hadamard(C.a, g, kr, nE, s));
+      LRFG_TRY(tk_dot(kr, g, C.dots, C.dscr, nE, s));
+      LRFG_TRY(tk_read(C, C.dots, v.data(), nE));
+      for (int e = 0; e < nE; ++e) en[e] += v[e] / Ntot;
+    }
+    return LRFG_OK;
+  };
+  // ---------------------------------------------------------------- solver
+  const int maxit = P.max_iter;
+  std::vector<double> hist((size_t)nE * maxit, 0.0), res0(nE, 0.0);
+  std::vector<int> iters(nE, 0), status(nE, LRFG_OK);
+  const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  // kept mode ranks of the latest x truncation (mode j of system e at
+  // kx[j nE + e]) and those of each system's kept iterate
+  std::vector<int> kx(3 * nE, 0), kbest(3 * nE, 0);
+  auto fetch_kept = [&]() -> int {
+    for (int j = 0; j < 3; ++j)
+      LRFG_HIP(hipMemcpyAsync(kx.data() + j * nE, C.rd.kept + (long long)j * C.rd.kept_batch, sizeof(int) * nE,
+                              hipMemcpyDeviceToHost, s));
+    return LRFG_OK;
+  };
+  auto upload_done = [&](const std::vector<int>& hd) -> int {
+    LRFG_HIP(hipMemcpyAsync(C.done, hd.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
+    return LRFG_OK;
+  };
+  // One truncated PCG (or MR) solve of K x = C.b, best iterate into C.xb, in
+  // the rounder's current precision; the same contract as the train path's.
+  auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& r0,
+                   std::vector<int>& st, bool record) -> int {
+    std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0);
+    std::vector<double> best(nE, INFINITY), zzh(nE);
+    for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
+    LRFG_TRY(tk_zero(C.xr, 2 * nE, s));
+    LRFG_TRY(tk_zero(C.xb, nE, s));
+    LRFG_TRY(upload_done(hdone));
+    if (P.solver == LRFG_SOLVER_PCG) {
+      LRFG_TRY(tk_copy(C.b, C.r, nE, s));
+      LRFG_TRY(tk_apply_P(C, C.r, C.z));
+      LRFG_TRY(tk_copy(C.z, C.p, nE, s));
+      LRFG_TRY(tk_dot(C.r, C.z, C.rho, C.dscr, nE, s));
+      LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+    } else {
+      LRFG_TRY(tk_apply_P(C, C.b, C.z));
+      LRFG_TRY(tk_copy(C.z, C.b, nE, s));
+      LRFG_TRY(tk_copy(C.b, C.r, nE, s));
+      LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
+    }
+    LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+    for (int e = 0; e < nE; ++e) {
+      r0[e] = std::sqrt(std::max(zzh[e], 0.0));
+      if (r0[e] <= floor_abs[e]) hdone[e] = 1;
+    }
+    LRFG_TRY(upload_done(hdone));
+    for (int it = 0; it < max_it; ++it) {
+      bool all = true;
+      for (int e = 0; e < nE; ++e) all = all && hdone[e];
+      if (all) break;
+      if (P.solver == LRFG_SOLVER_PCG) {
+        LRFG_TRY(tk_apply_K(C, C.p, C.q));
+        LRFG_TRY(tk_dot(C.p, C.q, C.pqd, C.dscr, nE, s));
+        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.rho, (const double*)C.pqd,
+                           (const int*)C.done, C.alpha, nE);
+        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+        LRFG_LAUNCHED();
+        LRFG_TRY(tk_update_xr(C));
+        LRFG_TRY(fetch_kept());
+        LRFG_TRY(tk_apply_P(C, C.r, C.z));
+        LRFG_TRY(tk_dot(C.r, C.z, C.dots, C.dscr, nE, s));
+        LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+        hipLaunchKernelGGL(k_beta, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, C.rho,
+                           (const int*)C.done, C.beta, nE);
+        LRFG_LAUNCHED();
+        LRFG_TRY(tk_axpby(C, C.z, C.p, C.beta, C.tmp));
+        LRFG_TRY(tk_copy(C.tmp, C.p, nE, s));
+      } else {
+        LRFG_TRY(tk_apply_K(C, C.r, C.tmp));
+        LRFG_TRY(tk_apply_P(C, C.tmp, C.z));
+        LRFG_TRY(tk_dot(C.z, C.r, C.dots, C.dscr, nE, s));
+        LRFG_TRY(tk_dot(C.z, C.z, C.pqd, C.dscr, nE, s));
+        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, (const double*)C.pqd,
+                           (const int*)C.done, C.alpha, nE);
+        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+        LRFG_LAUNCHED();
+        LRFG_TRY(tk_copy(C.r, C.p, nE, s));
+        LRFG_TRY(tk_copy(C.z, C.q, nE, s));
+        LRFG_TRY(tk_update_xr(C));
+        LRFG_TRY(fetch_kept());
+        LRFG_TRY(tk_dot(C.r, C.r, C.zz, C.dscr, nE, s));
+      }
+      LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+      bool changed = false;
+      for (int e = 0; e < nE; ++e) {
+        if (hdone[e]) continue;
+        const double res = std::sqrt(std::max(zzh[e], 0.0)) / r0[e];
+        if (record) hist[(size_t)e * maxit + it] = res;
+        its[e] = it + 1;
+        if (res < best[e]) {
+          best[e] = res;
+          since_best[e] = 0;
+          LRFG_TRY(tk_copy_system(C.x, C.xb, e, s));
+          if (record)
+            for (int j = 0; j < 3; ++j) kbest[j * nE + e] = kx[j * nE + e];
+        } else {
+          ++since_best[e];
+        }
+        if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
+          hdone[e] = 1;
+          changed = true;
+        } else if (since_best[e] >= patience) {
+          hdone[e] = 1;
+          changed = true;
+          if (best[e] > tol) st[e] = LRFG_NOT_CONVERGED;
+        }
+      }
+      if (changed) LRFG_TRY(upload_done(hdone));
+    }
+    for (int e = 0; e < nE; ++e) {
+      if (!hdone[e]) st[e] = LRFG_NOT_CONVERGED;
+      if (skip[e] || r0[e] <= floor_abs[e]) st[e] = LRFG_OK;
+      iters[e] = record ? its[e] : iters[e] + its[e];
+    }
+    return LRFG_OK;
+  };
+
+  const std::vector<int> none(nE, 0);
+  if (P.precision == LRFG_PREC_FP64) {
+    LRFG_TRY(inner(P.solver_tol, maxit, none, res0, status, true));
+  } else {
+    // Mixed precision: the train path's iterative refinement (inner solves
+    // in reduced precision on the residual, correction update, residual and
+    // energy in FP64, stop at solver_tol or after two outer steps without an
+    // energy gain, the first such step under BF16 moving the inner solves to
+    // FP32), with the Tucker operations.
+    int lowp = P.precision;
+    double tol_in = std::max(P.solver_tol, lowp == LRFG_PREC_MIXED_BF16 ? 1e-2 : 1e-4);
+    const double tol_en = std::max(P.solver_tol * P.solver_tol, 1e-15);
+    LRFG_TRY(tt_fill(C.ones, nE, 1.0, s));
+    LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
+    LRFG_TRY(tk_copy(C.b, C.b0, nE, s));
+    LRFG_TRY(tk_zero(C.xa, nE, s));
+    LRFG_TRY(tk_zero(C.xbest, nE, s));
+    C.rd.prec = LRFG_PREC_FP64;
+    std::vector<double> rn0(nE, 0.0), zzh(nE), best(nE, INFINITY), en(nE);
+    LRFG_TRY(tk_apply_P(C, C.b0, C.z));
+    LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+    LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+    std::vector<int> odone(nE, 0), st_in(nE), capped(nE, 1), no_gain(nE, 0);
+    for (int e = 0; e < nE; ++e) {
+      rn0[e] = std::sqrt(std::max(zzh[e], 0.0));
+      if (rn0[e] <= floor_abs[e]) {
+        odone[e] = 1;
+        capped[e] = 0;
+      }
+    }
+    std::vector<double> r0_in(nE);
+    for (int outer = 0; outer < maxit; ++outer) {
+      bool all = true;
+      for (int e = 0; e < nE; ++e) all = all && odone[e];
+      if (all) break;
+      C.rd.prec = lowp;
+      LRFG_TRY(inner(tol_in, maxit, odone, r0_in, st_in, false));
+      C.rd.prec = LRFG_PREC_FP64;
+      LRFG_TRY(tk_axpby(C, C.xa, C.xb, C.ones, C.tmp));   // x <- T(x + delta)
+      LRFG_TRY(fetch_kept());
+      LRFG_TRY(tk_copy(C.tmp, C.xa, nE, s));
+      LRFG_TRY(tk_apply_K(C, C.xa, C.tmp));               // r <- T(b - K x)
+      LRFG_TRY(tk_axpby(C, C.b0, C.tmp, C.mones, C.b));
+      LRFG_TRY(tk_apply_P(C, C.b, C.z));
+      LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+      LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+      LRFG_TRY(energy_diag(C.xa, en));
+      bool escalate = false;
+      for (int e = 0; e < nE; ++e) {
+        if (odone[e]) continue;
+        const double rel = std::sqrt(std::max(zzh[e], 0.0)) / rn0[e];
+        hist[(size_t)e * maxit + outer] = rel;
+        const bool gain = en[e] < best[e] - tol_en * std::fabs(en[e]);
+        if (en[e] < best[e]) {
+          best[e] = en[e];
+          LRFG_TRY(tk_copy_system(C.xa, C.xbest, e, s));
+          for (int j = 0; j < 3; ++j) kbest[j * nE + e] = kx[j * nE + e];
+        }
+        no_gain[e] = gain ? 0 : no_gain[e] + 1;
+        if (!gain && lowp == LRFG_PREC_MIXED_BF16) escalate = true;
+        if (rel <= P.solver_tol || no_gain[e] >= 2) {
+          odone[e] = 1;
+          capped[e] = 0;
+        }
+      }
+      if (escalate) {
+        lowp = LRFG_PREC_MIXED_FP32;
+        tol_in = std::max(P.solver_tol, 1e-4);
+        for (int e = 0; e < nE; ++e) no_gain[e] = 0;
+      }
+    }
+    for (int e = 0; e < nE; ++e) status[e] = capped[e] ? LRFG_NOT_CONVERGED : LRFG_OK;
+    LRFG_TRY(tk_copy(C.xbest, C.xb, nE, s));
+    res0 = rn0;
+  }
+  // ---------------------------------------------------------------- A_H (eq. homog)
+  std::vector<double> m1((size_t)nE * 3), m2((size_t)nE * nE * 3);
   for (int al = 0; al < 3; ++al) {
     TKB g = C.xb;
     g.U[al] = C.gframe;

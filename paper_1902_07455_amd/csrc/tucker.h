@@ -89,11 +89,13 @@ struct TkRounder {
   size_t gscr_n = 0;
   int* kept = nullptr;       // kept ranks of the last call: mode j of system e at kept[j kept_batch + e]
   int kept_batch = 0;
+  int prec = 0;              // lrfg_precision of the sketch contractions
   void carve(Arena& ar);
   // in's core is ignored when kc is given (the input is a Khatri-Rao
   // product whose frames are in.U and whose core is described by kc)
   int round(const TKB& in, TKB& out, double tol, hipStream_t s, int batch = -1, const KronCore* kc = nullptr);
-  int kron_mode3(const KronCore& kc, const double* B, long long sB, int l, int nb, double* dst, hipStream_t s);
+  int kron_mode3(const KronCore& kc, const double* B, long long sB, int l, int nb, double* dst, hipStream_t s,
+                 int gp);
 };
 
 }  // namespace lrfg

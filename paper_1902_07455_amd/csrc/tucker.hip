@@ -281,16 +281,24 @@ struct GB {
   }
 };
 
+// The truncation's contractions in a given precision (FP64, or FP32 / BF16
+// inputs with FP32 accumulation).
+inline Gemm& with_prec(Gemm& g, int prec) {
+  g.prec = prec;
+  return g;
+}
+
 // Mode-2 product out[e][a][b][c] = sum_q W'[e][b][q] in[e][a][q][c] (W' = W[e]
 // or, with wt, W[e]^T) as one batched GEMM over (e, a) when in and out are
 // compact per system, else by k_mode2.
 int mode2(const double* in, long long sin, int A, int Bi, int Cd, const double* W, long long sW, int Bo, int wt,
-          double* out, long long sout, int nE, double* gscr, size_t gscr_n, hipStream_t s) {
+          double* out, long long sout, int nE, double* gscr, size_t gscr_n, hipStream_t s, int prec = 0) {
   if (sin == (long long)A * Bi * Cd && sout == (long long)A * Bo * Cd) {
     GB g(Bo, Cd, Bi, A * nE);
     g.a(W, wt ? Bo : Bi, sW, wt != 0);
     g.g.adiv = A;
     g.b(in, Cd, (long long)Bi * Cd).c(out, Cd, (long long)Bo * Cd);
+    g.g.prec = prec;
     return gemm(g.g, gscr, gscr_n, s);
   }
   hipLaunchKernelGGL(k_mode2, dim3(grid_for((long long)A * Bo * Cd * nE)), dim3(kB), 0, s, in, sin, A, Bi, Cd, W, sW,
@@ -559,13 +567,13 @@ int tk_orth(TkRounder& R, const double* Y, double* Q, int m, int l, int batch, h
 // over i3 with G_a, a GEMM over k3 with G_x (batch ordered (i1, i2) major),
 // and one reordering pass.
 int TkRounder::kron_mode3(const KronCore& kc, const double* B, long long sB, int l, int nb, double* dst,
-                          hipStream_t s) {
+                          hipStream_t s, int gp) {
   const int ra1 = kc.ra[0], ra2 = kc.ra[1], ra3 = kc.ra[2], rx1 = kc.rx[0], rx2 = kc.rx[1], rx3 = kc.rx[2];
   // P[t][(i1, i2)][(k3, c)] = sum_{i3} Ga[(i1, i2)][i3] B[t][i3][(k3, c)]
   {
     GB g(ra1 * ra2, rx3 * l, ra3, nb);
     g.a(kc.Ga, ra3, kc.sGa).b(B, (long long)rx3 * l, sB).c(Kp, (long long)rx3 * l, (long long)ra1 * ra2 * rx3 * l);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, gp), gscr, gscr_n, s));
   }
   // H'[(i1, i2)][t][(k1, k2)][c] = sum_{k3} Gx[t][(k1, k2)][k3] P[t][(i1, i2)][k3][c]
   {
@@ -578,7 +586,7 @@ int TkRounder::kron_mode3(const KronCore& kc, const double* B, long long sB, int
     g.g.bmod = nb;
     g.g.sB2 = (long long)ra1 * ra2 * rx3 * l;
     g.c(Kh, l, (long long)rx1 * rx2 * l);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, gp), gscr, gscr_n, s));
   }
   const long long tot = (long long)ra1 * ra2 * nb * rx1 * rx2 * l;
   hipLaunchKernelGGL(k_kron_unfold, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)Kh, dst, ra1, ra2, nb, rx1,
@@ -627,6 +635,9 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
       return LRFG_EINVAL;
     }
   }
+  // sketch contractions in the rounder's precision, projections onto the
+  // orthonormal bases at least FP32, Gram matrices and factorisations FP64
+  const int pj = prec == LRFG_PREC_MIXED_BF16 ? LRFG_PREC_MIXED_FP32 : prec;
   const double tol2 = tol * tol / 3.0;
   const uint64_t key = (seed * 0x9E3779B97F4A7C15ull) ^ (0xD1B54A32D192ED03ull * (++counter));
   const long long sZ[3] = {(long long)R1 * l, (long long)R2 * l, (long long)R3 * l};
@@ -635,7 +646,7 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
     LRFG_TRY(launch_randn(om[j], (long long)N[j] * l, key ^ (0xA5A5A5A5A5A5A5A5ull * (uint64_t)(j + 1)), s));
     GB g(Rj[j], l, N[j], nb);
     g.a(in.U[j], Rj[j], in.sU[j], true).b(om[j], l, 0).c(Z[j], l, sZ[j]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
   }
   // 2. sketch cores: H = G x_3 Z3^T, Y cores of modes 1 and 2 from H; mode 3
   //    from the Khatri-Rao rows of Z1, Z2
@@ -643,9 +654,9 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   if (kc == nullptr) {
     GB g(R1 * R2, l, R3, nb);
     g.a(in.G, R3, in.sG).b(Z[2], l, sZ[2]).c(H, l, sH);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
   } else {
-    LRFG_TRY(kron_mode3(*kc, Z[2], sZ[2], l, nb, H, s));
+    LRFG_TRY(kron_mode3(*kc, Z[2], sZ[2], l, nb, H, s, prec));
   }
   hipLaunchKernelGGL(k_tcontract, dim3(grid_for((long long)(R1 + R2) * l * nb)), dim3(kB), 0, s, (const double*)H, sH,
                      (const double*)Z[0], sZ[0], (const double*)Z[1], sZ[1], R1, R2, l, Yc[0], sZ[0], Yc[1], sZ[1], nb);
@@ -656,7 +667,7 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
     LRFG_LAUNCHED();
     GB g(R3, l, R1 * R2, nb);
     g.a(in.G, R3, in.sG, true).b(KR, l, sH).c(Yc[2], l, sZ[2]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
   } else {
     // Yc3[(i3, k3)][c] = sum Ga[i1, i2, i3] Gx[k1, k2, k3] Z1[(i1, k1)][c] Z2[(i2, k2)][c]
     const int ra1 = kc->ra[0], ra2 = kc->ra[1], ra3 = kc->ra[2], rx1 = kc->rx[0], rx2 = kc->rx[1],
@@ -672,7 +683,7 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
       g.g.amod = kc->xmod;
       g.g.sA2 = kc->sGx;
       g.b(Kw, (long long)ra1 * ra2 * l, sW).c(Kp, (long long)ra1 * ra2 * l, (long long)rx3 * ra1 * ra2 * l);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+      LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
     }
     {
       // Y'[t][k3][i3][c] = sum_{(i1, i2)} Ga[(i1, i2)][i3] V[t][k3][(i1, i2)][c]
@@ -680,7 +691,7 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
       g.a(kc->Ga, ra3, kc->sGa, true);
       g.g.adiv = rx3;
       g.b(Kp, l, (long long)ra1 * ra2 * l).c(KY, l, (long long)ra3 * l);
-      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+      LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
     }
     hipLaunchKernelGGL(k_swap_mid, dim3(grid_for((long long)R3 * l * nb)), dim3(kB), 0, s, (const double*)KY, Yc[2],
                        (long long)nb, rx3, ra3, (long long)l);
@@ -701,7 +712,7 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
     const long long sY = (long long)N[j] * l;
     GB g(N[j], l, Rj[j], nb);
     g.a(in.U[j], Rj[j], in.sU[j]).b(Yc[j], l, sZ[j]).c(Y[j], l, sY);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, prec), gscr, gscr_n, s));
   }
   if (same_n) {
     LRFG_TRY(tk_orth(*this, Yall, Qall, N[0], l, 3 * nb, s));
@@ -712,25 +723,25 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
     const long long sY = (long long)N[j] * l;
     GB g(l, Rj[j], N[j], nb);
     g.a(Q[j], l, sY, true).b(in.U[j], Rj[j], in.sU[j]).c(M[j], Rj[j], sZ[j]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s));
   }
   // 4. C = G x_3 M3 x_1 M1 x_2 M2 (l x l x l)
   const long long l3 = (long long)l * l * l;
   if (kc == nullptr) {
     GB g(R1 * R2, l, R3, nb);
     g.a(in.G, R3, in.sG).b(M[2], R3, sZ[2], true).c(T1, l, sH);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s));
   } else {
     // M3^T (R3 x l per system), then the structured mode-3 product
     hipLaunchKernelGGL(k_swap_mid, dim3(grid_for((long long)R3 * l * nb)), dim3(kB), 0, s, (const double*)M[2], KM,
                        (long long)nb, l, R3, (long long)1);
     LRFG_LAUNCHED();
-    LRFG_TRY(kron_mode3(*kc, KM, sZ[2], l, nb, T1, s));
+    LRFG_TRY(kron_mode3(*kc, KM, sZ[2], l, nb, T1, s, pj));
   }
   const long long sT2 = (long long)l * R2 * l;
   { GB g(l, R2 * l, R1, nb); g.a(M[0], R1, sZ[0]).b(T1, (long long)R2 * l, sH).c(T2, (long long)R2 * l, sT2);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
-  LRFG_TRY(mode2(T2, sT2, l, R2, l, M[1], sZ[1], l, 0, Cc, l3, nb, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s)); }
+  LRFG_TRY(mode2(T2, sT2, l, R2, l, M[1], sZ[1], l, 0, Cc, l3, nb, gscr, gscr_n, s, pj));
   // 5. the cut: mode Gram matrices of C (mode j's nb matrices at
   //    Gr + j nb l^2), kept eigenvectors S_j (l x c_j); kept ranks of mode j
   //    at kept + j nb; with equal c_j one cut launch for all three modes
@@ -766,18 +777,18 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   for (int j = 0; j < 3; ++j) {
     GB g(N[j], out.r[j], l, nb);
     g.a(Q[j], l, (long long)N[j] * l).b(S[j], out.r[j], (long long)l * out.r[j]).c(out.U[j], out.r[j], out.sU[j]);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s));
   }
   const int c1 = out.r[0], c2 = out.r[1], c3 = out.r[2];
   { GB g(l * l, c3, l, nb); g.a(Cc, l, l3).b(S[2], c3, (long long)l * c3).c(T3, c3, (long long)l * l * c3);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s)); }
   { GB g(c1, l * c3, l, nb); g.a(S[0], c1, (long long)l * c1, true).b(T3, (long long)l * c3, (long long)l * l * c3)
         .c(T4, (long long)l * c3, (long long)c1 * l * c3);
-    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    LRFG_TRY(gemm(with_prec(g.g, pj), gscr, gscr_n, s)); }
   const long long nout = (long long)c1 * c2 * c3;
   (void)nout;
   return mode2(T4, (long long)c1 * l * c3, c1, l, c3, S[1], (long long)l * c2, c2, 1, out.G, out.sG, nb, gscr, gscr_n,
-               s);
+               s, pj);
 }
 
 }  // namespace lrfg

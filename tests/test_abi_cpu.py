@@ -74,7 +74,6 @@ def _problem(L, **kw):
     (dict(precond_terms=1), -1),
     (dict(precision=1), -5),                   # full grid is FP64 only
     (dict(solver=1), -5),                      # full grid uses PCG
-    (dict(format=2, precision=1), -5),         # Tucker path is FP64 only
     (dict(d=2, N=(15, 15), format=2), -5),     # Tucker path is d = 3 only
     (dict(N=(65, 65, 65), format=2, rank_cap=64), -5),  # sketch sizes beyond 64
 ])
@@ -121,6 +120,24 @@ def test_tucker_workspace_one_microstructure_at_a_time():
     assert sz[0] < sz[1] == sz[2] == sz[3]
     # at least x, r, p, q, z and the mode frames of 3 systems
     assert sz[1] >= 3 * 5 * 3 * 45 * 8 * 8
+
+
+def test_tucker_mixed_precision_workspace():
+    """Mixed precision adds the refinement's b0, x and best-x Tucker tensors
+    (three systems' frames and cores) on top of the FP64 workspace."""
+    L = _lib()
+    lib = L.lib()
+    sz = {}
+    for prec in (0, 1, 2):
+        plan = C.c_void_p()
+        pr = _problem(L, N=(45, 45, 45), format=2, rank_cap=8, precision=prec)
+        assert lib.lrfg_plan_create(C.byref(pr), C.byref(plan)) == 0
+        nb = C.c_size_t()
+        assert lib.lrfg_plan_workspace_bytes(plan, 3, C.byref(nb)) == 0
+        lib.lrfg_plan_destroy(plan)
+        sz[prec] = nb.value
+    extra = 3 * 3 * (3 * 45 * 8 + 8 ** 3) * 8
+    assert sz[1] == sz[2] >= sz[0] + extra
 
 
 def test_solve_rejects_bad_workspace_before_device():

@@ -175,6 +175,39 @@ def test_solve_smooth_45(dev):
     assert np.min(np.linalg.eigvalsh(0.5 * (D + D.T))) >= -1e-9
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_refinement(dev, prec):
+    """Mixed-precision Tucker solve (FP32 / BF16 sketch contractions, FP64
+    refinement) of the smooth 3D workload at N = 45, mode ranks 16: the A_H
+    error per entry against the FP64 oracle is within 1e-6 of max|A_H|, and
+    within the same bar of the FP64 Tucker solve of the same problem."""
+    N = 45
+    cp = W.smooth_cp(N, W.smooth_params(0))
+    o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
+    kw = dict(d=3, N=(N,) * 3, format="tucker", rank_cap=16, solver_tol=1e-5, max_iter=60, coeff_rank=9)
+    r = P.Solver(**kw, precision=prec).solve(cp=(cp.weights, cp.factors))
+    err = np.abs(r.A_H - o.A_H) / np.max(np.abs(o.A_H))
+    print("Tucker 45^3 cap 16", prec, ": A_H err", np.max(err), "iters", r.iters, "ranks", r.ranks)
+    assert np.max(err) <= 1e-6, err
+    for e in range(3):
+        hist = r.res_hist[e][r.res_hist[e] > 0]
+        assert hist.size >= 1 and np.min(hist) <= hist[0]
+    r64 = P.Solver(**kw).solve(cp=(cp.weights, cp.factors))
+    assert _rel(r.A_H, r64.A_H) <= 1e-6
+
+
+def test_mixed_precision_untruncated_exact(dev):
+    """Mode ranks at the grid size: the refined BF16 solve reaches the
+    full-grid oracle's A_H to 1e-10 (cube inclusion, contrast 10)."""
+    N = 15
+    cp = W.cube_cp(N, 10.0)
+    s = P.Solver(d=3, N=(N,) * 3, format="tucker", rank_cap=N, solver_tol=1e-11, max_iter=200, coeff_rank=2,
+                 precision="bf16")
+    r = s.solve(cp=(cp.weights, cp.factors))
+    o = fg.solve(cp.full(), tol=1e-12, max_iter=500)
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
 def test_solve_batch_runs_each_alone(dev):
     """A Tucker batch gives each microstructure's single-solve result."""
     N = 21
