@@ -542,87 +542,119 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long k) {
   return k;
 }
 
+// 1 / sqrt(x) from the hardware estimate plus two Newton steps
+__device__ inline double rsq_nr2(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;
+  y = fma(y, fma(-h, y, 0.5), y);
+  h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
+
+// Maximum of a 32-bit key over the 64-lane wave, returned uniform: DPP
+// maxima within each row of 16 lanes, then the four row results read out.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  unsigned t;
+  t = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kDppSwap1, 0xF, 0xF, false);
+  v = t > v ? t : v;
+  t = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kDppSwap2, 0xF, 0xF, false);
+  v = t > v ? t : v;
+  t = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kDppHalfMirror, 0xF, 0xF, false);
+  v = t > v ? t : v;
+  t = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kDppMirror, 0xF, 0xF, false);
+  v = t > v ? t : v;
+  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  const unsigned ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
 // Rank-revealing Cholesky with diagonal pivoting of the symmetric positive
-// semidefinite n x n matrix in g (LDS, overwritten by the Schur
-// complements), n <= 64, by a block of NT threads (a multiple of 64).
-// Step k takes the largest remaining diagonal entry p = perm[k] as pivot
-// (near-ties within 64 ulps go to the lower index) and stores the pivot
+// semidefinite n x n matrix G in g (LDS, read only), n <= NMAX <= 64, by
+// one wave (lane j owns index j).  Step k takes the largest remaining
+// diagonal entry p = perm[k] as pivot (entries within 2^-17 relative of
+// each other, compared in FP32, go to the lower index) and stores the pivot
 // column of the factor, in the original index order, as row k of L (LDS,
-// n x n): G = sum_{k<r} L[k]^T L[k].  It stops when the largest remaining
-// diagonal entry is at most tau times the largest initial one; returns r
-// (the same in every thread).  With Z != null it also builds Z (LDS, row k
-// = z_k, original coordinates) with z_k = (e_p - sum_{j<k} L[j][p] z_j) /
-// L[k][p], the columns of P R^-1 (Gram-Schmidt in the G inner product), so
-// that Y z_k are orthonormal when G = Y^T Y.  Wave 0 picks the pivot; all
-// threads update the Schur complement, thread t on row t / (NT / 64) and
-// every (NT / 64)-th column, and build z_k, NT / 64 threads per component.
-template <int NT>
-__device__ int pchol_block(int n, double* __restrict__ g, double* __restrict__ L, double* __restrict__ Z,
-                           int* __restrict__ perm, double tau, int* __restrict__ bc) {
-  constexpr int CG = NT / 64;
-  const int tid = threadIdx.x;
-  const bool w0 = tid < 64;
-  const int lane = tid & 63;
-  const int ri = tid / CG, rj = tid - ri * CG;
+// n x n, zero on entry): G = sum_{k<r} L[k]^T L[k].  It stops when the
+// largest remaining diagonal entry is at most tau times the largest initial
+// one and returns r (uniform).  With WITHZ it also builds Z (LDS, n x n,
+// zero on entry; row k = z_k, original coordinates), z_k = (e_p - sum_{j<k}
+// L[j][p] z_j) / L[k][p], the columns of P R^-1 (Gram-Schmidt in the G
+// inner product), so that Y z_k are orthonormal when G = Y^T Y.
+// Left-looking: the pivot row of the Schur complement is formed as
+// G[p][.] - sum_{m<k} L[m][p] L[m][.] from the rows of L written so far
+// (rows not yet written are zero, so chunks of 8 rows are skipped whole
+// once past k); the diagonal is kept in registers and updated with the
+// new row.  One wave needs no barrier: LDS operations of a wave complete
+// in order.
+template <int NMAX, bool WITHZ>
+__device__ int pchol_wave(int n, const double* __restrict__ g, double* __restrict__ L, double* __restrict__ Z,
+                          int* __restrict__ perm, double tau) {
+  constexpr int CH = 8;
+  static_assert(NMAX % CH == 0, "NMAX is a multiple of the row chunk");
+  const int lane = threadIdx.x & 63;
+  const int jc = lane < n ? lane : n - 1;  // loads of lanes >= n stay in range
+  double dg = lane < n ? g[lane * n + lane] : 0.0;
+  const double d0 =
+      __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(fmax(dg, 0.0))));
   bool chosen = lane >= n;
-  double d0 = 0.0;
-  if (w0) {
-    const double dv = (lane < n) ? fmax(g[lane * n + lane], 0.0) : 0.0;
-    d0 = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(dv)));
-  }
   int r = n;
   for (int k = 0; k < n; ++k) {
-    if (w0) {
-      // key: value bits of the (non-negative) diagonal, low 6 bits = 63 - lane
-      const double dv = chosen ? 0.0 : fmax(g[lane * n + lane], 0.0);
-      unsigned long long key = chosen ? 0ull : (((unsigned long long)__double_as_longlong(dv) & ~63ull) |
-                                                (unsigned long long)(63 - lane));
-      key = wave_max_u64(key);
-      const int p = 63 - (int)(key & 63ull);
-      const double best = (key == 0ull) ? 0.0 : g[p * n + p];
-      const bool stop = !(best > tau * d0) || !(best > 0.0);
-      if (!stop) {
-        const double inv = 1.0 / sqrt(best);
-        if (lane < n) L[k * n + lane] = chosen ? 0.0 : g[p * n + lane] * inv;
-        if (lane == p) chosen = true;
-        if (lane == 0) {
-          perm[k] = p;
-          bc[1] = p;
-        }
-      }
-      if (lane == 0) bc[0] = stop ? 1 : 0;
-    }
-    __syncthreads();
-    if (bc[0]) {
+    // key: FP32 value bits of the (non-negative) diagonal, low 6 bits = 63 - lane
+    const float fv = (float)fmax(dg, 0.0);
+    const unsigned key = wave_max_u32(chosen ? 0u : ((__float_as_uint(fv) & ~63u) | (unsigned)(63 - lane)));
+    const int p = 63 - (int)(key & 63u);
+    const double best = key == 0u ? 0.0
+                                  : __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dg), p),
+                                                     __builtin_amdgcn_readlane(__double2loint(dg), p));
+    if (!(best > tau * d0) || !(best > 0.0)) {
       r = k;
       break;
     }
-    const double* lk = L + k * n;
-    if (ri < n) {
-      const double li = lk[ri];
-      if (li != 0.0)
-        for (int j = rj; j < n; j += CG) g[ri * n + j] -= li * lk[j];
+    const double inv = rsq_nr2(best);
+    double s0 = g[p * n + jc], s1 = 0.0, a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NMAX / CH; ++c) {
+      if (c * CH < k) {
+        double lp[CH], lj[CH], zj[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int m = c * CH + i;
+          const int mc = m < n ? m : n - 1;
+          lp[i] = L[mc * n + p];
+          lj[i] = L[mc * n + jc];
+          if (WITHZ) zj[i] = Z[mc * n + jc];
+        }
+#pragma unroll
+        for (int i = 0; i < CH; i += 2) {
+          s0 = fma(-lp[i], lj[i], s0);
+          s1 = fma(-lp[i + 1], lj[i + 1], s1);
+          if (WITHZ) {
+            a0 = fma(lp[i], zj[i], a0);
+            a1 = fma(lp[i + 1], zj[i + 1], a1);
+          }
+        }
+      }
     }
-    if (Z != nullptr) {
-      // component zc of z_k, its sum split over the CG threads of an
-      // aligned group (j = q, q + CG, ...) and added by DPP moves
-      const int p = bc[1];
-      const int zc = tid / CG, q = tid - zc * CG;
-      double a = 0.0;
-      if (zc < n)
-        for (int j = q; j < k; j += CG) a += L[j * n + p] * Z[j * n + zc];
-      if (CG >= 2) a += dpp_move<kDppSwap1>(a);
-      if (CG >= 4) a += dpp_move<kDppSwap2>(a);
-      if (q == 0 && zc < n) Z[k * n + zc] = (((zc == p) ? 1.0 : 0.0) - a) / lk[p];
+    const double lrow = chosen ? 0.0 : (s0 + s1) * inv;
+    if (lane < n) {
+      L[k * n + lane] = lrow;
+      if (WITHZ) Z[k * n + lane] = (((lane == p) ? 1.0 : 0.0) - (a0 + a1)) * inv;
     }
-    __syncthreads();
+    dg = fma(-lrow, lrow, dg);
+    if (lane == p) chosen = true;
+    if (lane == 0) perm[k] = p;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   return r;
 }
 
 // S = P R^-1 (n x n) for the pivoted Cholesky factor of G (see
-// pchol_block): Q = Y S has orthonormal columns spanning the numerical
+// pchol_wave): Q = Y S has orthonormal columns spanning the numerical
 // range of Y when G = Y^T Y; columns r.. of S are zero.
+template <int NMAX>
 __global__ __launch_bounds__(256) void k_pchol_s(int n, const double* __restrict__ Gg, long long sG, double tau,
                                                  double* __restrict__ Sg, long long sS, int* __restrict__ rank_out) {
   extern __shared__ double sm[];
@@ -630,12 +662,21 @@ __global__ __launch_bounds__(256) void k_pchol_s(int n, const double* __restrict
   double* L = sm + n * n;
   double* Z = sm + 2 * n * n;
   __shared__ int perm[64];
-  __shared__ int bc[2];
+  __shared__ int rank_s;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* G = Gg + b * sG;
-  for (int e = tid; e < n * n; e += 256) g[e] = G[e];
+  for (int e = tid; e < n * n; e += 256) {
+    g[e] = G[e];
+    L[e] = 0.0;
+    Z[e] = 0.0;
+  }
   __syncthreads();
-  const int r = pchol_block<256>(n, g, L, Z, perm, tau, bc);
+  if (tid < 64) {
+    const int rr = pchol_wave<NMAX, true>(n, g, L, Z, perm, tau);
+    if (tid == 0) rank_s = rr;
+  }
+  __syncthreads();
+  const int r = rank_s;
   double* S = Sg + b * sS;
   const int ri = tid >> 2, rj = tid & 3;  // S[o][k] = z_k[o]
   if (ri < n)
@@ -686,12 +727,15 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   __shared__ int order[64];
   __shared__ double lam[64];
   __shared__ int flags[kCutSweeps];
-  __shared__ int bc[2];
+  __shared__ int rank_s;
   __shared__ double trace_s;
   __shared__ int kept_s;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* G = Gg + b * sG;
-  for (int e = tid; e < n * n; e += NT) g[e] = G[e];
+  for (int e = tid; e < n * n; e += NT) {
+    g[e] = G[e];
+    L[e] = 0.0;
+  }
   if (tid < kCutSweeps) flags[tid] = 0;
   __syncthreads();
   if (tid < 64) {
@@ -700,7 +744,12 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (tid == 0) trace_s = t;
   }
-  const int r = pchol_block<NT>(n, g, L, nullptr, perm, tau, bc);
+  if (tid < 64) {
+    const int rr = pchol_wave<NP, false>(n, g, L, nullptr, perm, tau);
+    if (tid == 0) rank_s = rr;
+  }
+  __syncthreads();
+  const int r = rank_s;
   for (int e = tid; e < r * NP; e += NT) {
     const int j = e / NP, i = e - (e / NP) * NP;
     W[e] = (i < n) ? L[j * n + i] : 0.0;
@@ -981,12 +1030,15 @@ int pchol_s(int n, const double* G, long long sG, double tau, double* S, long lo
   }
   if (batch <= 0) return LRFG_OK;
   const size_t shm = sizeof(double) * 3 * n * n;
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s<64>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)(sizeof(double) * 3 * kMaxEig * kMaxEig));
   (void)attr;
   ProfScope ps_("pchol", s);
-  hipLaunchKernelGGL(k_pchol_s, dim3(batch), dim3(256), shm, s, n, G, sG, tau, S, sS, rank);
+  if (n <= 32)
+    hipLaunchKernelGGL(k_pchol_s<32>, dim3(batch), dim3(256), shm, s, n, G, sG, tau, S, sS, rank);
+  else
+    hipLaunchKernelGGL(k_pchol_s<64>, dim3(batch), dim3(256), shm, s, n, G, sG, tau, S, sS, rank);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
