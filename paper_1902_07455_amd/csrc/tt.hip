@@ -71,6 +71,40 @@ __global__ void k_randn(double* __restrict__ out, long long n, uint64_t key) {
   }
 }
 
+// The same product for wide carriages (ra1 rx1 >= 64): rows (I, n) of the
+// output, kKrRows per block, one thread per output column J, so the row
+// indices are block-uniform and a thread splits its own J once; the rows'
+// loads are independent and issue together.
+constexpr int kKrRows = 8;
+__global__ __launch_bounds__(256) void k_khatri_rao_rows(const double* __restrict__ a, long long sa, int ra0,
+                                                         int ra1, const double* __restrict__ x, long long sx,
+                                                         int rx0, int rx1, int N, double* __restrict__ out,
+                                                         long long so) {
+  constexpr int RB = kKrRows;
+  const int R1 = ra1 * rx1;
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= R1) return;
+  const int j = J / rx1, m = J - (J / rx1) * rx1;
+  const int e = blockIdx.z;
+  const double* ae = a + e * sa;
+  const double* xe = x + e * sx;
+  double* oe = out + e * so;
+  const int nrows = ra0 * rx0 * N;
+  const int row0 = blockIdx.y * RB;
+  double av[RB], xv[RB];
+#pragma unroll
+  for (int t = 0; t < RB; ++t) {
+    const int row = row0 + t < nrows ? row0 + t : nrows - 1;
+    const int I = row / N, n = row - (row / N) * N;
+    const int i = I / rx0, k = I - (I / rx0) * rx0;
+    av[t] = ae[((long long)i * N + n) * ra1 + j];
+    xv[t] = xe[((long long)k * N + n) * rx1 + m];
+  }
+#pragma unroll
+  for (int t = 0; t < RB; ++t)
+    if (row0 + t < nrows) oe[(long long)(row0 + t) * R1 + J] = av[t] * xv[t];
+}
+
 // out[e][(i rx0 + k)][n][(j rx1 + m)] = a[i][n][j] x[e][k][n][m]
 __global__ void k_khatri_rao(const double* __restrict__ a, long long sa, int ra0, int ra1,
                              const double* __restrict__ x, long long sx, int rx0, int rx1, int N,
@@ -191,8 +225,19 @@ int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s) {
     }
     const long long tot = out.size(j) * nE;
     ProfScope ps_("khatri_rao", s);
-    hipLaunchKernelGGL(k_khatri_rao, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)a.c[j], a.s[j], a.r[j],
-                       a.r[j + 1], (const double*)x.c[j], x.s[j], x.r[j], x.r[j + 1], x.N[j], out.c[j], out.s[j], nE);
+    const int R1 = out.r[j + 1];
+    const long long nrows = (long long)out.r[j] * x.N[j];
+    const long long rblocks = (nrows + kKrRows - 1) / kKrRows;
+    if (R1 >= 64 && rblocks <= 65535 && nE <= 65535) {
+      const int bt = R1 >= 256 ? 256 : (R1 + 63) / 64 * 64;
+      const dim3 grid((unsigned)((R1 + bt - 1) / bt), (unsigned)rblocks, (unsigned)nE);
+      hipLaunchKernelGGL(k_khatri_rao_rows, grid, dim3(bt), 0, s, (const double*)a.c[j], a.s[j], a.r[j], a.r[j + 1],
+                         (const double*)x.c[j], x.s[j], x.r[j], x.r[j + 1], x.N[j], out.c[j], out.s[j]);
+    } else {
+      hipLaunchKernelGGL(k_khatri_rao, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)a.c[j], a.s[j], a.r[j],
+                         a.r[j + 1], (const double*)x.c[j], x.s[j], x.r[j], x.r[j + 1], x.N[j], out.c[j], out.s[j],
+                         nE);
+    }
     LRFG_LAUNCHED();
   }
   return LRFG_OK;
