@@ -127,22 +127,36 @@ __global__ void k_khatri_rao(const double* __restrict__ a, long long sa, int ra0
   }
 }
 
-// out[e][o0 + i][n][o1 + j] = c_e X[e][i][n][j]  (out dims R0 x N x R1)
-__global__ void k_block_copy(const double* __restrict__ X, long long sx, int r0, int N, int r1,
-                             double* __restrict__ out, long long so, int R1, int o0, int o1,
-                             const double* __restrict__ coef, double mult, int nE) {
-  const long long per = (long long)r0 * N * r1;
-  const long long tot = per * nE;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int e = (int)(idx / per);
-    long long r = idx - e * per;
-    const int j = (int)(r % r1);
-    r /= r1;
-    const int n = (int)(r % N);
-    const int i = (int)(r / N);
-    const double c = mult * (coef != nullptr ? coef[e] : 1.0);
-    out[e * so + ((long long)(o0 + i) * N + n) * R1 + o1 + j] = c * X[e * sx + ((long long)i * N + n) * r1 + j];
+// Carriage of a block sum of up to kSumTerms trains, every output element
+// written once: term t's carriage sits at row offset o0[t], column offset
+// o1[t] (times c_t = mult_t coef_t[e] on the first carriage), zeros
+// elsewhere.  Indices are per system (blockIdx.y), in 32 bits.
+constexpr int kSumTerms = 4;
+struct SumCarriage {
+  const double* x[kSumTerms];
+  long long sx[kSumTerms];
+  int r0[kSumTerms], r1[kSumTerms], o0[kSumTerms], o1[kSumTerms];
+  const double* coef[kSumTerms];
+  double mult[kSumTerms];
+  int nt;
+};
+__global__ __launch_bounds__(256) void k_sum_carriage(SumCarriage T, int R0, int N, int R1,
+                                                      double* __restrict__ out, long long so) {
+  const int e = blockIdx.y;
+  const int per = R0 * N * R1;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
+    const int J = idx % R1;
+    const int r = idx / R1;
+    const int n = r % N, I = r / N;
+    double v = 0.0;
+    for (int t = 0; t < T.nt; ++t) {
+      const int i = I - T.o0[t], j = J - T.o1[t];
+      if (i >= 0 && i < T.r0[t] && j >= 0 && j < T.r1[t]) {
+        const double c = T.mult[t] * (T.coef[t] != nullptr ? T.coef[t][e] : 1.0);
+        v = c * T.x[t][e * T.sx[t] + ((long long)i * N + n) * T.r1[t] + j];
+      }
+    }
+    out[e * so + idx] = v;
   }
 }
 
@@ -254,21 +268,36 @@ int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s) {
       return LRFG_EINVAL;
     }
   }
-  // middle carriages are block diagonal: clear first
-  for (int j = 1; j < d - 1; ++j) LRFG_TRY(tt_fill(out.c[j], out.size(j) * nE, 0.0, s));
+  long long biggest = 0;
+  for (int j = 0; j < d; ++j) biggest = std::max(biggest, out.size(j));
+  if (nt > kSumTerms || nE > 65535 || biggest > 0x7fffffffLL) {
+    set_error("tt_sum: %d terms (at most %d) or sizes beyond the kernel's", nt, kSumTerms);
+    return LRFG_EINVAL;
+  }
+  // one launch per carriage writes every block and the zeros between them
+  // (the middle carriages are block diagonal)
+  SumCarriage T[3];
+  for (int j = 0; j < d; ++j) T[j].nt = nt;
   for (int t = 0; t < nt; ++t) {
     const TTB& x = *terms[t].x;
     for (int j = 0; j < d; ++j) {
-      const int r0 = x.r[j], r1 = x.r[j + 1];
-      const long long tot = x.size(j) * nE;
-      const bool first = (j == 0);
-      const double* coef = first ? terms[t].coef : nullptr;
-      const double mult = first ? terms[t].mult : 1.0;
-      hipLaunchKernelGGL(k_block_copy, dim3(grid_for(tot)), dim3(kB), 0, s, (const double*)x.c[j], x.s[j], r0, x.N[j],
-                         r1, out.c[j], out.s[j], out.r[j + 1], o[j], o[j + 1], coef, mult, nE);
-      LRFG_LAUNCHED();
+      T[j].x[t] = x.c[j];
+      T[j].sx[t] = x.s[j];
+      T[j].r0[t] = x.r[j];
+      T[j].r1[t] = x.r[j + 1];
+      T[j].o0[t] = o[j];
+      T[j].o1[t] = o[j + 1];
+      T[j].coef[t] = j == 0 ? terms[t].coef : nullptr;
+      T[j].mult[t] = j == 0 ? terms[t].mult : 1.0;
     }
     for (int j = 1; j < d; ++j) o[j] += x.r[j];
+  }
+  for (int j = 0; j < d; ++j) {
+    const long long per = out.size(j);
+    const int gx = (int)std::min<long long>(1024, (per + kB - 1) / kB);
+    hipLaunchKernelGGL(k_sum_carriage, dim3(gx > 0 ? gx : 1, nE), dim3(kB), 0, s, T[j], out.r[j], out.N[j],
+                       out.r[j + 1], out.c[j], out.s[j]);
+    LRFG_LAUNCHED();
   }
   return LRFG_OK;
 }
