@@ -78,15 +78,56 @@ __global__ void k_core_kron(const double* __restrict__ a, long long sa, int a1, 
   }
 }
 
-// out[e][n][o + k] = x[e][n][k]   (frame of rank r into a frame of rank R)
-__global__ void k_frame_place(const double* __restrict__ x, long long sx, int r, int N, double* __restrict__ out,
-                              long long so, int R, int o, int nE) {
-  const long long per = (long long)N * r;
-  GRID_STRIDE(idx, per * nE) {
-    const long long e = idx / per;
-    const long long rem = idx - e * per;
-    const long long n = rem / r, k = rem - n * r;
-    out[e * so + n * R + o + k] = x[e * sx + rem];
+// Block sum of up to kTkSumTerms Tucker tensors in two launches: the frames
+// of mode blockIdx.z side by side (term t's columns at offset o[t][j]), and
+// the block-diagonal core (term t's block at (o[t][0], o[t][1], o[t][2]),
+// times mult_t coef_t[e], zeros elsewhere).  Per-system indices in 32 bits.
+constexpr int kTkSumTerms = 4;
+struct TkSumArgs {
+  const double* U[kTkSumTerms][3];
+  long long sU[kTkSumTerms][3];
+  const double* G[kTkSumTerms];
+  long long sG[kTkSumTerms];
+  int r[kTkSumTerms][3], o[kTkSumTerms][3];
+  const double* coef[kTkSumTerms];
+  double mult[kTkSumTerms];
+  int nt;
+};
+__global__ __launch_bounds__(256) void k_tk_sum_frames(TkSumArgs T, int N0, int N1, int N2, double* __restrict__ u0,
+                                                       double* __restrict__ u1, double* __restrict__ u2,
+                                                       long long so0, long long so1, long long so2, int R0, int R1,
+                                                       int R2) {
+  const int j = blockIdx.z, e = blockIdx.y;
+  const int N = j == 0 ? N0 : (j == 1 ? N1 : N2);
+  const int R = j == 0 ? R0 : (j == 1 ? R1 : R2);
+  double* out = (j == 0 ? u0 : (j == 1 ? u1 : u2)) + e * (j == 0 ? so0 : (j == 1 ? so1 : so2));
+  const int per = N * R;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
+    const int n = idx / R, K = idx - (idx / R) * R;
+    double v = 0.0;
+    for (int t = 0; t < T.nt; ++t) {
+      const int k = K - T.o[t][j];
+      if (k >= 0 && k < T.r[t][j]) v = T.U[t][j][e * T.sU[t][j] + (long long)n * T.r[t][j] + k];
+    }
+    out[idx] = v;
+  }
+}
+__global__ __launch_bounds__(256) void k_tk_sum_core(TkSumArgs T, int R0, int R1, int R2, double* __restrict__ out,
+                                                     long long so) {
+  const int e = blockIdx.y;
+  const int per = R0 * R1 * R2;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
+    const int K = idx % R2, r = idx / R2;
+    const int J = r % R1, I = r / R1;
+    double v = 0.0;
+    for (int t = 0; t < T.nt; ++t) {
+      const int i = I - T.o[t][0], jj = J - T.o[t][1], k = K - T.o[t][2];
+      if (i >= 0 && i < T.r[t][0] && jj >= 0 && jj < T.r[t][1] && k >= 0 && k < T.r[t][2]) {
+        const double c = T.mult[t] * (T.coef[t] != nullptr ? T.coef[t][e] : 1.0);
+        v = c * T.G[t][e * T.sG[t] + ((long long)i * T.r[t][1] + jj) * T.r[t][2] + k];
+      }
+    }
+    out[e * so + idx] = v;
   }
 }
 
@@ -420,18 +461,38 @@ int tk_sum(const TKTerm* terms, int nt, TKB& out, int nE, hipStream_t s) {
       return LRFG_EINVAL;
     }
   }
-  LRFG_HIP(hipMemsetAsync(out.G, 0, sizeof(double) * out.gsize() * nE, s));
+  long long biggest = out.gsize();
+  for (int j = 0; j < 3; ++j) biggest = std::max(biggest, out.usize(j));
+  if (nt > kTkSumTerms || nE > 65535 || biggest > 0x7fffffffLL) {
+    set_error("tk_sum: %d terms (at most %d) or sizes beyond the kernels'", nt, kTkSumTerms);
+    return LRFG_EINVAL;
+  }
+  TkSumArgs T;
+  T.nt = nt;
   int o[3] = {0, 0, 0};
   for (int t = 0; t < nt; ++t) {
     const TKB& x = *terms[t].x;
     for (int j = 0; j < 3; ++j) {
-      hipLaunchKernelGGL(k_frame_place, dim3(grid_for(x.usize(j) * nE)), dim3(kB), 0, s, (const double*)x.U[j],
-                         x.sU[j], x.r[j], x.N[j], out.U[j], out.sU[j], out.r[j], o[j], nE);
+      T.U[t][j] = x.U[j];
+      T.sU[t][j] = x.sU[j];
+      T.r[t][j] = x.r[j];
+      T.o[t][j] = o[j];
+      o[j] += x.r[j];
     }
-    LRFG_LAUNCHED();
-    LRFG_TRY(tk_place_core(x, terms[t].coef, terms[t].mult, out, o, nE, s));
-    for (int j = 0; j < 3; ++j) o[j] += x.r[j];
+    T.G[t] = x.G;
+    T.sG[t] = x.sG;
+    T.coef[t] = terms[t].coef;
+    T.mult[t] = terms[t].mult;
   }
+  long long fmax = 0;
+  for (int j = 0; j < 3; ++j) fmax = std::max(fmax, out.usize(j));
+  const int gf = (int)std::min<long long>(1024, (fmax + kB - 1) / kB);
+  hipLaunchKernelGGL(k_tk_sum_frames, dim3(gf > 0 ? gf : 1, nE, 3), dim3(kB), 0, s, T, out.N[0], out.N[1], out.N[2],
+                     out.U[0], out.U[1], out.U[2], out.sU[0], out.sU[1], out.sU[2], out.r[0], out.r[1], out.r[2]);
+  const int gc = (int)std::min<long long>(1024, (out.gsize() + kB - 1) / kB);
+  hipLaunchKernelGGL(k_tk_sum_core, dim3(gc > 0 ? gc : 1, nE), dim3(kB), 0, s, T, out.r[0], out.r[1], out.r[2], out.G,
+                     out.sG);
+  LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
