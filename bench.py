@@ -197,9 +197,10 @@ def serving_leg(nreq, nmax, capmax, dev):
     continuous-batching loop: saturated throughput (all queued at once),
     then Poisson arrivals at 0.7x that rate (p50/p99 latency); and a
     same-shape stream (16 smooth 135^3 microstructures, cap 16) solved one
-    by one vs in batches of 8.  Grids and rank caps are bounded (defaults
-    N <= 135, cap <= 20) so that the leg takes seconds; --serve-nmax 405
-    --serve-capmax 60 gives the full request distribution."""
+    by one, on four concurrent streams, and in batches of 8.  Grids and rank
+    caps are bounded (defaults N <= 135, cap <= 20) so that the leg takes
+    seconds; --serve-nmax 405 --serve-capmax 60 gives the full request
+    distribution."""
     import torch
 
     import paper_1902_07455_amd as P
@@ -257,8 +258,8 @@ def serving_leg(nreq, nmax, capmax, dev):
         sc.append((torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors]))
     prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=16, solver_tol=1e-2, max_iter=100, coeff_rank=9)
     res = {}
-    for name, mb in (("one_by_one", 1), ("batches_of_8", 8)):
-        srv = P.Server(slots=1, max_batch=mb, pool_bytes=32 << 30, device=dev)
+    for name, slots, mb in (("one_by_one", 1, 1), ("four_streams", 4, 1), ("batches_of_8", 1, 8)):
+        srv = P.Server(slots=slots, max_batch=mb, pool_bytes=32 << 30, device=dev)
         t0 = time.perf_counter()
         for i, (w, f) in enumerate(sc):
             srv.submit(prob, cp=(w, f), tag=i)
@@ -271,8 +272,9 @@ def serving_leg(nreq, nmax, capmax, dev):
                         f"contrast log-uniform [2, 100], TT rank cap in [10, {capmax}], solver tol 1e-3; 4 slots, "
                         "batches up to 8, device-resident factors; latency = submit to completion",
             "saturated": sat, "poisson": poi,
-            "same_shape_135": dict(res, workload="16 smooth 135^3 microstructures (seeds 0..15), cap 16, tol 1e-2, "
-                                                 "one slot")}
+            "same_shape_135": dict(res, workload="16 smooth 135^3 microstructures (seeds 0..15), cap 16, tol 1e-2; "
+                                                 "one slot, four slots (streams) of single solves, or one slot "
+                                                 "batching 8")}
 
 
 def main(argv=None):
