@@ -901,12 +901,14 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   const int KQ = g.prec != 0 ? LK : lay.tk();  // K slab of the kernel used
   const int kchunk = ks > 1 ? ((g.k + ks - 1) / ks + KQ - 1) / KQ * KQ : (g.k > 0 ? g.k : 1);
   if (ks > 1) ks = (g.k + kchunk - 1) / kchunk;
-  // matrices per launch: all of them, or as many as the split partials fit
+  // matrices per launch: all of them, or as many as the split partials fit,
+  // within the grid's z limit
   int chunk = g.batch;
   if (ks > 1) {
     const size_t per = (size_t)ks * g.m * g.n;
     chunk = (int)std::min<size_t>((size_t)g.batch, scratch_doubles / per);
   }
+  chunk = std::min(chunk, 65535 / ks);
   double* part = ks > 1 ? scratch : nullptr;
   for (int b0 = 0; b0 < g.batch; b0 += chunk) {
     Gemm c = g;

@@ -148,6 +148,7 @@ struct Ctx {
   TTB comb;                 // block sums (capacity ranks, 2 nE trains)
   TTB h;                    // rounded material terms, d nE trains
   double* gcore;            // carriage buffer for D_alpha v
+  double* gmid;             // middle carriages of the d gradients (d = 3), d nE compact
   double* hcore[3];         // carriage buffers for D_alpha^T h_alpha
   double* pcore;            // M * d carriage buffers for the preconditioner terms
   long long pcore_stride;
@@ -199,7 +200,19 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   C.h = tt_alloc(ar, d, pl->N, rc, d * nE);
   int rkr[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) rkr[j] = ra[j] * rc[j];
-  C.kr = tt_alloc(ar, d, pl->N, rkr, d * nE);
+  if (d == 3) {
+    // the material truncation takes the middle carriage unformed, so it is
+    // held for the nE products of the energy form and A_H only
+    C.kr.d = 3;
+    for (int j = 0; j < 3; ++j) C.kr.N[j] = pl->N[j];
+    for (int j = 0; j < 4; ++j) C.kr.r[j] = rkr[j];
+    for (int j = 0; j < 3; ++j) {
+      C.kr.s[j] = C.kr.size(j);
+      C.kr.c[j] = ar.take<double>((size_t)C.kr.s[j] * (j == 1 ? nE : d * nE));
+    }
+  } else {
+    C.kr = tt_alloc(ar, d, pl->N, rkr, d * nE);
+  }
   // block sums: d material terms, M preconditioner terms, 2 update terms, d coefficient terms
   int cap[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) {
@@ -214,6 +227,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   long long maxcore = 0;
   for (int j = 0; j < d; ++j) maxcore = std::max(maxcore, (long long)rc[j] * pl->N[j] * rc[j + 1]);
   C.gcore = ar.take<double>((size_t)maxcore * nE);
+  C.gmid = d == 3 ? ar.take<double>((size_t)maxcore * d * nE) : nullptr;
   for (int al = 0; al < d; ++al) C.hcore[al] = ar.take<double>((size_t)maxcore * nE);
   C.pcore_stride = maxcore * nE;
   C.pcore = ar.take<double>((size_t)C.pcore_stride * pl->M * d);
@@ -230,6 +244,11 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   for (int j = 1; j < d; ++j) {
     R.Rmax[j - 1] = std::max(cap[j], rkr[j]);
     R.Lmax[j - 1] = rc[j] + pl->over;
+  }
+  if (d == 3) {
+    // the material truncation takes the middle carriage as a (.) D v
+    R.kr_ra = pl->ra;
+    R.kr_rg = std::max(rc[1], rc[2]);
   }
   R.carve(ar);
   // per-system scalars (dots also holds the nE x 3 energy-form products)
@@ -255,18 +274,43 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
 
 // ------------------------------------------------------------------ operators
 // out = T(sum_alpha D_alpha^T T(a (.) D_alpha v)); the d material
-// truncations run as one batched truncation of d nE trains.
+// truncations run as one batched truncation of d nE trains.  For d = 3 the
+// middle carriage of a (.) D_alpha v, (r_a c)^2 N per train, is never formed:
+// the truncation contracts a's and D_alpha v's carriages in turn.
 int apply_K(Ctx& C, const TTB& v, TTB& out) {
   const int d = C.d, nE = C.nE;
+  const bool mid = d == 3;
+  const long long gs = v.size(1);
   for (int al = 0; al < d; ++al) {
     TTB g = v;
     g.c[al] = C.gcore;
     LRFG_TRY(tt_mode_apply(v, g, al, 0, 0.0, 1.0, C.f[al], nE, C.s));
     TTB kra = C.kr;
-    for (int j = 0; j < d; ++j) kra.c[j] = C.kr.c[j] + (long long)al * nE * C.kr.s[j];
-    LRFG_TRY(tt_hadamard(C.a, g, kra, nE, C.s));
+    for (int j = 0; j < d; ++j)
+      if (!(mid && j == 1)) kra.c[j] = C.kr.c[j] + (long long)al * nE * C.kr.s[j];
+    LRFG_TRY(tt_hadamard(C.a, g, kra, nE, C.s, mid ? 1 : -1));
+    if (mid) {
+      double* dst = C.gmid + (long long)al * nE * gs;
+      if (g.s[1] == gs) {
+        LRFG_HIP(hipMemcpyAsync(dst, g.c[1], sizeof(double) * gs * nE, hipMemcpyDeviceToDevice, C.s));
+      } else {
+        for (int e = 0; e < nE; ++e)
+          LRFG_HIP(hipMemcpyAsync(dst + e * gs, g.c[1] + e * g.s[1], sizeof(double) * gs, hipMemcpyDeviceToDevice,
+                                  C.s));
+      }
+    }
   }
-  LRFG_TRY(C.rd.round(C.kr, C.h, 0.0, C.s, d * nE));
+  KrMid km;
+  km.a = C.a.c[1];
+  km.sa = C.a.s[1];
+  km.ra0 = C.a.r[1];
+  km.ra1 = C.a.r[2];
+  km.amod = nE;
+  km.g = C.gmid;
+  km.sg = gs;
+  km.rg0 = v.r[1];
+  km.rg1 = v.r[2];
+  LRFG_TRY(C.rd.round(C.kr, C.h, 0.0, C.s, d * nE, mid ? &km : nullptr));
   TTB ha[3], hd[3];
   TTTerm terms[3];
   for (int al = 0; al < d; ++al) {

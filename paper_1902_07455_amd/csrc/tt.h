@@ -31,6 +31,19 @@ struct TTTerm {
   double mult;
 };
 
+// Middle carriage (d = 3) of a Hadamard product a (.) g given by its
+// factors instead of formed: X[i rg0 + k][n][j rg1 + m] = a[i][n][j]
+// g[k][n][m].  Input system s takes coefficient train s % amod (stride sa;
+// 0 = shared) and g train s (stride sg).
+struct KrMid {
+  const double* a = nullptr;
+  long long sa = 0;
+  int ra0 = 1, ra1 = 1, amod = 1;
+  const double* g = nullptr;
+  long long sg = 0;
+  int rg0 = 1, rg1 = 1;
+};
+
 // Randomised TT rounding (sketch, Gram-based orthonormalisation, SVD cut)
 // with fixed output ranks; see tt.hip.
 struct Rounder {
@@ -51,10 +64,15 @@ struct Rounder {
   double* gscr = nullptr;   // GEMM split-K scratch
   size_t gscr_n = 0;
   int* kept = nullptr;      // kept ranks per bond per system (diagnostics)
+  // with kr_ra > 0: scratch for a structured middle carriage of coefficient
+  // ranks up to kr_ra and factor ranks up to kr_rg
+  int kr_ra = 0, kr_rg = 0;
+  double* kz = nullptr;
   void carve(Arena& ar);
   // out (ranks preset to the nominal output ranks) <- T(in) for `batch`
-  // systems (default: nE, the capacity it was carved for)
-  int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1);
+  // systems (default: nE, the capacity it was carved for); with mid, the
+  // middle carriage of `in` is mid's Hadamard product (in.c[1] unused)
+  int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1, const KrMid* mid = nullptr);
 };
 
 int tt_fill(double* p, long long n, double v, hipStream_t s);
@@ -64,8 +82,9 @@ int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s);
 // 1: heat kernel exp(-t k^2)) along its mode index, times mult.
 int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, const FftDev& f, int nE,
                   hipStream_t s);
-// out = a (.) x, slice-wise Kronecker of the carriages (ranks multiply).
-int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s);
+// out = a (.) x, slice-wise Kronecker of the carriages (ranks multiply);
+// carriage `skip` (if >= 0) is left unformed.
+int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s, int skip = -1);
 // out = sum of terms as one TT with block carriages (ranks add); out's
 // ranks must equal the sums of the terms' ranks.
 int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s);

@@ -127,6 +127,50 @@ __global__ void k_khatri_rao(const double* __restrict__ a, long long sa, int ra0
   }
 }
 
+// Second steps of the structured middle carriage X2 = a (.) g (one thread
+// per output, the ra terms of its sum in order; system s = blockIdx.y reads
+// coefficient train s % amod):
+//   T2[s][i rg0 + k][n][l] = sum_j a[i][n][j] Z[s][j][k][n][l]
+//   X2'[s][p][n][j rg1 + m] = sum_i a[i][n][j] U[s][p][i][n][m]
+__global__ __launch_bounds__(256) void k_kr_t2(const double* __restrict__ a, long long sa, int amod, int ra0, int ra1,
+                                               int N, const double* __restrict__ Z, long long sz, int rg0, int l2,
+                                               double* __restrict__ T2, long long st) {
+  const int s = blockIdx.y;
+  const double* as = a + (long long)(s % amod) * sa;
+  const double* zs = Z + (long long)s * sz;
+  double* ts = T2 + (long long)s * st;
+  const int Q = rg0 * N * l2;  // (k, n, l) per j
+  const int per = ra0 * Q;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
+    const int i = idx / Q, q = idx - (idx / Q) * Q;
+    const int n = (q / l2) % N;
+    const double* ar = as + ((long long)i * N + n) * ra1;
+    double v = 0.0;
+    for (int j = 0; j < ra1; ++j) v = fma(ar[j], zs[(long long)j * Q + q], v);
+    ts[idx] = v;
+  }
+}
+__global__ __launch_bounds__(256) void k_kr_x2(const double* __restrict__ a, long long sa, int amod, int ra0, int ra1,
+                                               int N, const double* __restrict__ U, long long su, int rg1, int l1,
+                                               double* __restrict__ X, long long sx) {
+  const int s = blockIdx.y;
+  const double* as = a + (long long)(s % amod) * sa;
+  const double* us = U + (long long)s * su;
+  double* xs = X + (long long)s * sx;
+  const int per = l1 * N * ra1 * rg1;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
+    const int m = idx % rg1;
+    int r = idx / rg1;
+    const int j = r % ra1;
+    r /= ra1;
+    const int n = r % N, p = r / N;
+    const double* up = us + ((long long)p * ra0 * N + n) * rg1 + m;  // U[s][p][0][n][m]
+    double v = 0.0;
+    for (int i = 0; i < ra0; ++i) v = fma(as[((long long)i * N + n) * ra1 + j], up[(long long)i * N * rg1], v);
+    xs[idx] = v;
+  }
+}
+
 // Carriage of a block sum of up to kSumTerms trains, every output element
 // written once: term t's carriage sits at row offset o0[t], column offset
 // o1[t] (times c_t = mult_t coef_t[e] on the first carriage), zeros
@@ -231,12 +275,13 @@ int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, co
                             (long long)x.r[j] * x.r[j + 1]);
 }
 
-int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s) {
+int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s, int skip) {
   for (int j = 0; j < x.d; ++j) {
     if (out.r[j] != a.r[j] * x.r[j] || out.r[j + 1] != a.r[j + 1] * x.r[j + 1]) {
       set_error("tt_hadamard: output ranks");
       return LRFG_EINVAL;
     }
+    if (j == skip) continue;
     const long long tot = out.size(j) * nE;
     ProfScope ps_("khatri_rao", s);
     const int R1 = out.r[j + 1];
@@ -432,6 +477,11 @@ void Rounder::carve(Arena& ar) {
   S1 = T((long long)L * L);
   P = T((long long)L * L);
   kept = ar.take<int>((size_t)2 * nE);
+  if (d == 3 && kr_ra > 0) {
+    // Z = g x W3 (kr_ra kr_rg N2 L2) or U = M1 x g (L1 kr_ra N2 kr_rg) per system
+    const long long z = (long long)kr_ra * kr_rg * N2 * L2, u = (long long)L1 * kr_ra * N2 * kr_rg;
+    kz = T(z > u ? z : u);
+  }
   gscr_n = (size_t)4 * 1024 * 1024;
   gscr = ar.take<double>(gscr_n);
 }
@@ -503,7 +553,7 @@ static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, d
   return cut_psd(l, c, Gm, (long long)l * l, tol2, S, (long long)l * c, kept, nE, s);
 }
 
-int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch) {
+int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch, const KrMid* mid) {
   ProfScope ps_("tt_round", s);
   if (batch < 0) batch = nE;
   if (batch > nE) {
@@ -539,9 +589,33 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     // W3 = X3 Om3^T (R2 x l2)
     { GemmB g(R2, l2, N3, nE); g.a(in.c[2], N3, in.s[2]).b(om[2], N3, 0, true).c(W3, l2, (long long)R2 * l2);
       LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    if (mid != nullptr && (d != 3 || kz == nullptr || mid->ra0 * mid->rg0 != R1 || mid->ra1 * mid->rg1 != R2 ||
+                           mid->ra0 > kr_ra || mid->ra1 > kr_ra || mid->rg0 > kr_rg || mid->rg1 > kr_rg)) {
+      set_error("tt_round: structured middle carriage does not fit (R %d %d)", R1, R2);
+      return LRFG_EINVAL;
+    }
     // T2 = X2 W3 ((R1 N2) x l2)
-    { GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
-      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    if (mid == nullptr) {
+      GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s));
+    } else {
+      // X2 = a (.) g: Z[j][k][n][l] = sum_m g[k][n][m] W3[j rg1 + m][l] (GEMM,
+      // batch t = s ra1 + j), then T2[i rg0 + k][n][l] = sum_j a[i][n][j]
+      // Z[j][k][n][l] (k_kr_t2, FP64)
+      const int ra0 = mid->ra0, ra1 = mid->ra1, rg0 = mid->rg0, rg1 = mid->rg1;
+      const long long zs = (long long)ra1 * rg0 * N2 * l2;  // Z per system
+      { GemmB g(rg0 * N2, l2, rg1, nE * ra1);
+        g.a(mid->g, rg1, mid->sg).b(W3, l2, (long long)rg1 * l2).c(kz, l2, (long long)rg0 * N2 * l2);
+        g.g.adiv = ra1;
+        LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+      {
+        const long long per = (long long)ra0 * rg0 * N2 * l2;
+        const dim3 grid((unsigned)std::min<long long>(1024, (per + kB - 1) / kB), (unsigned)nE);
+        hipLaunchKernelGGL(k_kr_t2, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1, N2,
+                           (const double*)kz, zs, rg0, l2, T2, (long long)R1 * N2 * l2);
+        LRFG_LAUNCHED();
+      }
+    }
     // W2 = T2 Om2^T (R1 x l1), contraction over (n, l2)
     { GemmB g(R1, l1, N2 * l2, nE); g.a(T2, (long long)N2 * l2, (long long)R1 * N2 * l2).b(om[1], (long long)N2 * l2, 0, true)
           .c(W2, l1, (long long)R1 * l1);
@@ -553,9 +627,27 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
       LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
-    { GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
+    if (mid == nullptr) {
+      GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
           .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
-      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
+      LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s));
+    } else {
+      // U[l1][i][n][m] = sum_k M1[l1][i rg0 + k] g[k][n][m] (GEMM), then
+      // X2'[l1][n][j rg1 + m] = sum_i a[i][n][j] U[l1][i][n][m] (k_kr_x2, FP64)
+      const int ra0 = mid->ra0, ra1 = mid->ra1, rg0 = mid->rg0, rg1 = mid->rg1;
+      { GemmB g(l1 * ra0, N2 * rg1, rg0, nE);
+        g.a(M1, rg0, (long long)l1 * R1).b(mid->g, (long long)N2 * rg1, mid->sg)
+            .c(kz, (long long)N2 * rg1, (long long)l1 * ra0 * N2 * rg1);
+        LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
+      {
+        const long long per = (long long)l1 * N2 * ra1 * rg1;
+        const dim3 grid((unsigned)std::min<long long>(1024, (per + kB - 1) / kB), (unsigned)nE);
+        hipLaunchKernelGGL(k_kr_x2, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1, N2,
+                           (const double*)kz, (long long)l1 * ra0 * N2 * rg1, rg1, l1, X2p,
+                           (long long)l1 * N2 * R2);
+        LRFG_LAUNCHED();
+      }
+    }
     // Y2 = X2' W3 ((l1 N2) x l2) ; Q2 = orth(Y2)
     { GemmB g(l1 * N2, l2, R2, nE); g.a(X2p, R2, (long long)l1 * N2 * R2).b(W3, l2, (long long)R2 * l2)
           .c(Y2, l2, (long long)l1 * N2 * l2);
