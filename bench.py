@@ -17,11 +17,13 @@ is at most 1e-6:
 `value` is the low-rank (TT) path, the paper's method.  The full-grid FFT
 solve on the same GPU is reported next to it (`full_fft`, with the roofline
 of its axis-2 FFT pass), together with the crossover at larger grids.
-`roofline` is that of the TT path's dominant kernel, the MFMA FP64 GEMM of
-the truncation; it is measured in a separate pass of --prof-solves solves
-(start/stop events attached to every GEMM dispatch through
+`roofline` is that of the TT path's dominant kernel family, the MFMA FP64
+GEMM of the truncation; it is measured in a separate pass of --prof-solves
+solves (start/stop events attached to every GEMM dispatch through
 hipExtLaunchKernelGGL, i.e. the dispatch's own timestamps), so the events do
-not perturb the timed region.
+not perturb the timed region.  `latency_bound` gives the launch count,
+average duration and share of the solve of the two small-factorisation
+kernels (pivoted Cholesky, cut), which no throughput roofline bounds.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--crossover 243,405,729] [--no-crossover]
@@ -351,6 +353,14 @@ def main(argv=None):
     ttot, tlat, tr = timed(lambda: wl.run_tt(ts), args.steps, args.warmup)
     terr = rel_err(tr.A_H, A_ref)
     nl, kms, flops = profiled(lambda: wl.run_tt(ts), "gemm", args.prof_solves)
+    # the small factorisations: one workgroup per matrix, bound by their
+    # dependent pivot / rotation steps rather than by HBM or MFMA throughput
+    latency_bound = {"note": "one workgroup per small Gram matrix; bound by the chain of dependent pivot "
+                             "(k_pchol_s) and rotation (k_cut_psd) steps, not by HBM or MFMA throughput"}
+    for tag, kname in (("cut", "k_cut_psd"), ("pchol", "k_pchol_s")):
+        n_, ms_, _ = profiled(lambda: wl.run_tt(ts), tag, args.prof_solves)
+        latency_bound[kname] = {"launches": n_, "avg_us": round(ms_ / max(n_, 1) * 1e3, 2),
+                                "share_of_solve": round(ms_ / args.prof_solves / (1e3 * ttot / args.steps), 3)}
     ts.close()
     gavg = (kms / 1e3) / max(nl, 1)
     gach = flops / (kms / 1e3) / 1e12
@@ -387,6 +397,7 @@ def main(argv=None):
         "full_fft": full,
         "tt_over_full": round(value / full["solves_per_s"], 4),
         "roofline": roofline,
+        "latency_bound": latency_bound,
     }
 
     # ------------------------------------------------------------ Tucker format (same workload)
