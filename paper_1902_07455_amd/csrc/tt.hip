@@ -23,6 +23,9 @@
 // orthogonality to rounding level).  The cut's eigenvectors come from the
 // same pivoted Cholesky followed by one-sided Jacobi on the factor
 // (cut_psd), which needs a handful of sweeps on the graded factor.
+// A Hadamard product a (.) g can enter with its middle carriage unformed
+// (KrMid): the two contractions that read that carriage (the sketch T2 and
+// the projection X2') then run over g's and a's carriages in turn.
 #include <cmath>
 #include <cstdio>
 
