@@ -32,6 +32,24 @@ def test_gemm(dev, m, n, k, ta, tb, batch):
     assert err <= 1e-13 * max(1.0, np.sqrt(k)) * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("k", [9, 300])
+def test_gemm_batch_beyond_one_grid(dev, k):
+    """More matrices than one launch's grid z extent (65535) go in several
+    launches; every matrix of the batch is right (k = 300 also splits K)."""
+    import torch
+    batch, m, n = 70001, 2, 3
+    rng = np.random.default_rng(k)
+    A = rng.standard_normal((batch, m, k))
+    B = rng.standard_normal((batch, k, n))
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    tC = torch.zeros((batch, m, n), dtype=torch.float64, device=dev)
+    P.gemm(tA, tB, tC)
+    torch.cuda.synchronize()
+    ref = A @ B
+    err = np.max(np.abs(tC.cpu().numpy() - ref))
+    assert err <= 1e-13 * np.sqrt(k) * np.max(np.abs(ref))
+
+
 def test_gemm_beta_zero_ignores_nan(dev):
     import torch
     A = torch.ones((1, 4, 3), dtype=torch.float64, device=dev)
