@@ -173,45 +173,43 @@ __global__ void k_mode2(const double* __restrict__ in, long long sin, int A, int
 
 // Y cores of modes 1 and 2 from H = G x_3 Z_3^T (R1 x R2 x l):
 // y1[i1][t] = sum_i2 H[i1][i2][t] Z2[i2][t], y2[i2][t] = sum_i1 H[i1][i2][t] Z1[i1][t].
-__global__ void k_tcontract(const double* __restrict__ H, long long sH, const double* __restrict__ Z1,
-                            long long sZ1, const double* __restrict__ Z2, long long sZ2, int R1, int R2, int l,
-                            double* __restrict__ y1, long long sy1, double* __restrict__ y2, long long sy2,
-                            int nE) {
-  const long long per = (long long)(R1 + R2) * l;
-  GRID_STRIDE(idx, per * nE) {
-    const long long e = idx / per;
-    const long long rem = idx - e * per;
-    const long long row = rem / l, t = rem - row * l;
-    const double* h = H + e * sH;
-    // four independent partial sums keep several loads in flight
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+// One block per (output row, system): thread (p, t) of the 256 sums the
+// terms p, p + P, ... of column t (P = 256 / l partitions, each stream of
+// loads coalesced along t), then the P partial sums of each column are
+// added in partition order.
+__global__ __launch_bounds__(256) void k_tcontract(const double* __restrict__ H, long long sH,
+                                                   const double* __restrict__ Z1, long long sZ1,
+                                                   const double* __restrict__ Z2, long long sZ2, int R1, int R2,
+                                                   int l, double* __restrict__ y1, long long sy1,
+                                                   double* __restrict__ y2, long long sy2) {
+  __shared__ double part[256];
+  const int e = blockIdx.y, row = blockIdx.x;
+  const int P = 256 / l;
+  const int p = threadIdx.x / l, t = threadIdx.x - (threadIdx.x / l) * l;
+  double a = 0.0;
+  if (p < P) {
     if (row < R1) {
-      const double* z = Z2 + e * sZ2;
-      const double* hr = h + row * R2 * l + t;
-      int i2 = 0;
-      for (; i2 + 3 < R2; i2 += 4) {
-        a0 += hr[(long long)i2 * l] * z[(long long)i2 * l + t];
-        a1 += hr[(long long)(i2 + 1) * l] * z[(long long)(i2 + 1) * l + t];
-        a2 += hr[(long long)(i2 + 2) * l] * z[(long long)(i2 + 2) * l + t];
-        a3 += hr[(long long)(i2 + 3) * l] * z[(long long)(i2 + 3) * l + t];
-      }
-      for (; i2 < R2; ++i2) a0 += hr[(long long)i2 * l] * z[(long long)i2 * l + t];
-      y1[e * sy1 + row * l + t] = (a0 + a1) + (a2 + a3);
+      const double* hr = H + e * sH + (long long)row * R2 * l + t;
+      const double* z = Z2 + e * sZ2 + t;
+#pragma unroll 4
+      for (int i2 = p; i2 < R2; i2 += P) a = fma(hr[(long long)i2 * l], z[(long long)i2 * l], a);
     } else {
-      const long long i2 = row - R1;
-      const double* z = Z1 + e * sZ1;
-      const double* hc = h + i2 * l + t;
+      const double* hc = H + e * sH + (long long)(row - R1) * l + t;
+      const double* z = Z1 + e * sZ1 + t;
       const long long st = (long long)R2 * l;
-      int i1 = 0;
-      for (; i1 + 3 < R1; i1 += 4) {
-        a0 += hc[i1 * st] * z[(long long)i1 * l + t];
-        a1 += hc[(i1 + 1) * st] * z[(long long)(i1 + 1) * l + t];
-        a2 += hc[(i1 + 2) * st] * z[(long long)(i1 + 2) * l + t];
-        a3 += hc[(i1 + 3) * st] * z[(long long)(i1 + 3) * l + t];
-      }
-      for (; i1 < R1; ++i1) a0 += hc[i1 * st] * z[(long long)i1 * l + t];
-      y2[e * sy2 + i2 * l + t] = (a0 + a1) + (a2 + a3);
+#pragma unroll 4
+      for (int i1 = p; i1 < R1; i1 += P) a = fma(hc[i1 * st], z[(long long)i1 * l], a);
     }
+  }
+  part[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x < l) {
+    double v = 0.0;
+    for (int q = 0; q < P; ++q) v += part[q * l + threadIdx.x];
+    if (row < R1)
+      y1[e * sy1 + (long long)row * l + threadIdx.x] = v;
+    else
+      y2[e * sy2 + (long long)(row - R1) * l + threadIdx.x] = v;
   }
 }
 
@@ -719,8 +717,8 @@ int TkRounder::round(const TKB& in, TKB& out, double tol, hipStream_t s, int bat
   } else {
     LRFG_TRY(kron_mode3(*kc, Z[2], sZ[2], l, nb, H, s, prec));
   }
-  hipLaunchKernelGGL(k_tcontract, dim3(grid_for((long long)(R1 + R2) * l * nb)), dim3(kB), 0, s, (const double*)H, sH,
-                     (const double*)Z[0], sZ[0], (const double*)Z[1], sZ[1], R1, R2, l, Yc[0], sZ[0], Yc[1], sZ[1], nb);
+  hipLaunchKernelGGL(k_tcontract, dim3(R1 + R2, nb), dim3(256), 0, s, (const double*)H, sH, (const double*)Z[0], sZ[0],
+                     (const double*)Z[1], sZ[1], R1, R2, l, Yc[0], sZ[0], Yc[1], sZ[1]);
   LRFG_LAUNCHED();
   if (kc == nullptr) {
     hipLaunchKernelGGL(k_kr_rows, dim3(grid_for(sH * nb)), dim3(kB), 0, s, (const double*)Z[0], sZ[0], R1,
