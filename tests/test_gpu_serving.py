@@ -130,6 +130,37 @@ def test_server_solo_vs_mix(dev):
     assert max(c.batch_size for c in done) > 1
 
 
+def test_server_solo_vs_mix_64_requests(dev):
+    """64 requests of the serving generator (N odd in [45, 81], smooth or
+    cube coefficient, contrast log-uniform in [2, 100], caps 10..20), all
+    queued at once on 4 slots with batches of up to 8: every served A_H,
+    iteration count and status equals the request's solo solve."""
+    import torch
+    reqs = W.serving_requests(64, 1.0, seed=7, N_lo=45, N_hi=81, cap_lo=10, cap_hi=20)
+
+    def problem(q):
+        return dict(d=3, N=(q.N,) * 3, format="tt", rank_cap=q.rank_cap, solver_tol=1e-3, max_iter=60,
+                    coeff_rank=9 if q.kind == "smooth" else 2)
+
+    cps = [W.request_coeff(q) for q in reqs]
+    alone = []
+    for q, cp in zip(reqs, cps):
+        s = P.Solver(**problem(q))
+        alone.append(s.solve(cp=(cp.weights, cp.factors)))
+        s.close()
+    srv = P.Server(slots=4, max_batch=8, pool_bytes=8 << 30)
+    for i, (q, cp) in enumerate(zip(reqs, cps)):
+        srv.submit(problem(q), cp=(torch.from_numpy(cp.weights).to(dev),
+                                   [torch.from_numpy(f).to(dev) for f in cp.factors]), tag=i)
+    done = srv.drain()
+    srv.close()
+    assert sorted(c.tag for c in done) == list(range(64))
+    for c in done:
+        assert c.status == alone[c.tag].rc
+        assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL
+        assert list(c.result.iters) == list(alone[c.tag].iters)
+
+
 def test_server_admission_by_footprint(dev):
     """A pool that holds one request's workspace runs one batch at a time;
     a request larger than the pool is refused at submit."""
