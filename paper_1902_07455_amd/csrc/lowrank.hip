@@ -376,13 +376,6 @@ int read_dev(Ctx& C, const double* dptr, double* host, int n) {
   return LRFG_OK;
 }
 
-int copy_system(Ctx& C, const TTB& from, TTB& to, int e) {
-  for (int j = 0; j < C.d; ++j)
-    LRFG_HIP(hipMemcpyAsync(to.c[j] + e * to.s[j], from.c[j] + e * from.s[j], sizeof(double) * from.size(j),
-                            hipMemcpyDeviceToDevice, C.s));
-  return LRFG_OK;
-}
-
 }  // namespace
 
 // ====================================================================== plan
@@ -762,6 +755,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       }
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
       bool changed = false;
+      unsigned long long improved[4] = {0, 0, 0, 0};  // systems whose x becomes the best iterate
       for (int e = 0; e < nE; ++e) {
         if (hdone[e]) continue;
         const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
@@ -770,7 +764,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         if (res < best[e]) {
           best[e] = res;
           since_best[e] = 0;
-          LRFG_TRY(copy_system(C, C.x, C.xb, e));
+          improved[e >> 6] |= 1ull << (e & 63);
           if (record) {
             kbest[e] = kx[e];
             kbest[nE + e] = kx[nE + e];
@@ -787,6 +781,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
           if (best[e] > tol) st[e] = LRFG_NOT_CONVERGED;
         }
       }
+      LRFG_TRY(tt_copy_systems(C.x, C.xb, nE, improved, s));
       if (changed) LRFG_TRY(upload_done(hdone));
     }
     for (int e = 0; e < nE; ++e) {
@@ -856,6 +851,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
       LRFG_TRY(energy_diag(C.xa, en));
       bool escalate = false;
+      unsigned long long improved[4] = {0, 0, 0, 0};
       for (int e = 0; e < nE; ++e) {
         if (odone[e]) continue;
         const double rel = std::sqrt(std::max(zzh[e], 0.0)) / rn0[e];
@@ -863,7 +859,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         const bool gain = en[e] < best[e] - tol_en * std::fabs(en[e]);
         if (en[e] < best[e]) {
           best[e] = en[e];
-          LRFG_TRY(copy_system(C, C.xa, C.xbest, e));
+          improved[e >> 6] |= 1ull << (e & 63);
           kbest[e] = kx[e];
           kbest[nE + e] = kx[nE + e];
         }
@@ -874,6 +870,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
           capped[e] = 0;
         }
       }
+      LRFG_TRY(tt_copy_systems(C.xa, C.xbest, nE, improved, s));
       if (escalate) {
         lowp = LRFG_PREC_MIXED_FP32;
         tol_in = std::max(P.solver_tol, 1e-4);

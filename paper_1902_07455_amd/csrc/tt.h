@@ -78,6 +78,9 @@ struct Rounder {
 int tt_fill(double* p, long long n, double v, hipStream_t s);
 int tt_zero(TTB& x, int nE, hipStream_t s);
 int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s);
+// tt_copy of the systems e < nE (<= 256) whose bit e of mask[4] is set
+// (one launch; no launch when none is).
+int tt_copy_systems(const TTB& x, TTB& y, int nE, const unsigned long long* mask, hipStream_t s);
 // y = x with core j replaced by the real circulant op (0: derivative,
 // 1: heat kernel exp(-t k^2)) along its mode index, times mult.
 int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, const FftDev& f, int nE,

@@ -231,6 +231,24 @@ __global__ __launch_bounds__(256) void k_kr_x2_reg(const double* __restrict__ a,
 }
 constexpr int kKrRegRank = 16;
 
+// Copy of the carriages of the systems whose bit is set (one launch for
+// every carriage and system; system e = blockIdx.y).
+struct CopySel {
+  const double* x[3];
+  double* y[3];
+  long long sx[3], sy[3], n[3];
+  int d;
+  unsigned long long mask[4];
+};
+__global__ __launch_bounds__(256) void k_tt_copy_sel(CopySel A) {
+  const int e = blockIdx.y;
+  if (!((A.mask[e >> 6] >> (e & 63)) & 1ull)) return;
+  for (int j = 0; j < A.d; ++j)
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < A.n[j];
+         i += (long long)gridDim.x * blockDim.x)
+      A.y[j][e * A.sy[j] + i] = A.x[j][e * A.sx[j] + i];
+}
+
 // Carriage of a block sum of up to kSumTerms trains, every output element
 // written once: term t's carriage sits at row offset o0[t], column offset
 // o1[t] (times c_t = mult_t coef_t[e] on the first carriage), zeros
@@ -300,23 +318,40 @@ int tt_zero(TTB& x, int nE, hipStream_t s) {
   return LRFG_OK;
 }
 
-int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s) {
+int tt_copy_systems(const TTB& x, TTB& y, int nE, const unsigned long long* mask, hipStream_t s) {
+  if (nE <= 0) return LRFG_OK;
+  if (nE > 256) {
+    set_error("tt_copy: %d systems (at most 256)", nE);
+    return LRFG_EINVAL;
+  }
+  CopySel A;
+  A.d = x.d;
+  long long nmax = 0;
   for (int j = 0; j < x.d; ++j) {
     if (x.size(j) != y.size(j)) {
       set_error("tt_copy: rank mismatch");
       return LRFG_EINVAL;
     }
-    if (x.s[j] == x.size(j) && y.s[j] == y.size(j)) {
-      // both batches contiguous: one copy of the whole carriage batch
-      LRFG_HIP(hipMemcpyAsync(y.c[j], x.c[j], sizeof(double) * x.size(j) * nE, hipMemcpyDeviceToDevice, s));
-      continue;
-    }
-    for (int e = 0; e < nE; ++e)
-      LRFG_HIP(hipMemcpyAsync(y.c[j] + e * y.s[j], x.c[j] + e * x.s[j], sizeof(double) * x.size(j),
-                              hipMemcpyDeviceToDevice, s));
+    A.x[j] = x.c[j];
+    A.y[j] = y.c[j];
+    A.sx[j] = x.s[j];
+    A.sy[j] = y.s[j];
+    A.n[j] = x.size(j);
+    nmax = std::max(nmax, A.n[j]);
   }
+  bool any = false;
+  for (int k = 0; k < 4; ++k) {
+    A.mask[k] = mask != nullptr ? mask[k] : ~0ull;
+    any = any || A.mask[k] != 0ull;
+  }
+  if (!any) return LRFG_OK;
+  const int gx = (int)std::min<long long>(1024, std::max<long long>(1, (nmax + kB - 1) / kB));
+  hipLaunchKernelGGL(k_tt_copy_sel, dim3(gx, nE), dim3(kB), 0, s, A);
+  LRFG_LAUNCHED();
   return LRFG_OK;
 }
+
+int tt_copy(const TTB& x, TTB& y, int nE, hipStream_t s) { return tt_copy_systems(x, y, nE, nullptr, s); }
 
 int tt_mode_apply(const TTB& x, TTB& y, int j, int op, double t, double mult, const FftDev& f, int nE,
                   hipStream_t s) {
