@@ -515,8 +515,10 @@ __device__ inline unsigned long long dpp_move_u64(unsigned long long v) {
 }
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  // every lane of these patterns reads a lane of its own row, so no lane
+  // keeps an old value and none needs initialising
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 constexpr int kDppSwap1 = 0xB1;      // quad_perm [1,0,3,2]
@@ -695,12 +697,22 @@ __global__ __launch_bounds__(256) void k_pchol_s(int n, const double* __restrict
 // eigenvalue, zero columns beyond.  Groups of 8 lanes rotate one column
 // pair each (round-robin ordering, up to 32 pairs per round).
 constexpr int kCutSweeps = 30;
-// Sum over each aligned group of 8 lanes, the same value in all 8 lanes.
-__device__ inline double sum8(double v) {
-  v += dpp_move<kDppSwap1>(v);
-  v += dpp_move<kDppSwap2>(v);
-  v += dpp_move<kDppHalfMirror>(v);
-  return v;
+// Sums over each aligned group of 8 (LPG = 16: 16) lanes of three values,
+// the same sums in all lanes of the group; the three reductions advance a
+// stage at a time so that their DPP moves and adds overlap.
+template <int CTRL>
+__device__ inline void dpp_add3(double& a, double& b, double& c) {
+  const double ta = dpp_move<CTRL>(a), tb = dpp_move<CTRL>(b), tc = dpp_move<CTRL>(c);
+  a += ta;
+  b += tb;
+  c += tc;
+}
+template <int LPG>
+__device__ inline void sum_lanes3(double& a, double& b, double& c) {
+  dpp_add3<kDppSwap1>(a, b, c);
+  dpp_add3<kDppSwap2>(a, b, c);
+  dpp_add3<kDppHalfMirror>(a, b, c);
+  if (LPG == 16) dpp_add3<kDppMirror>(a, b, c);
 }
 // 1 / x and 1 / sqrt(x) from the hardware estimates plus one Newton step
 __device__ inline double rcp_nr(double x) {
@@ -718,6 +730,7 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
                                                  double tau, double eps, double tol2, double floor_rel,
                                                  double* __restrict__ Sg, long long sS, int* __restrict__ kept_out,
                                                  int* __restrict__ sweeps_out) {
+  static_assert(LPG == 8 || LPG == 16, "column pairs are rotated by 8 or 16 lanes");
   constexpr int NP = LPG * NE;  // padded column length
   extern __shared__ double sm[];
   double* g = sm;
@@ -789,29 +802,20 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
             bb += wq[t] * wq[t];
             gg += wp[t] * wq[t];
           }
-          a = sum8(a);
-          bb = sum8(bb);
-          gg = sum8(gg);
-          if (LPG == 16) {
-            a += dpp_move<kDppMirror>(a);
-            bb += dpp_move<kDppMirror>(bb);
-            gg += dpp_move<kDppMirror>(gg);
-          }
+          sum_lanes3<LPG>(a, bb, gg);
           if (gg * gg > eps2 * a * bb) {
             // the rotation angle comes from the hardware estimates alone:
             // any angle gives an orthogonal rotation, and an angle off by
             // the estimates' relative error leaves the pair's inner product
             // at that fraction of its old value for the next sweep; c is
-            // refined so that c^2 (1 + t^2) = 1 to rounding
-            const double z = (bb - a) * 0.5 * __builtin_amdgcn_rcp(gg);
-            double t;
-            if (fabs(z) > 1e150) {
-              t = 0.5 * __builtin_amdgcn_rcp(z);
-            } else {
-              const double w = 1.0 + z * z;
-              const double sq = w * __builtin_amdgcn_rsq(w);
-              t = (z >= 0.0 ? 1.0 : -1.0) * __builtin_amdgcn_rcp(fabs(z) + sq);
-            }
+            // refined so that c^2 (1 + t^2) = 1 to rounding.  t is the
+            // smaller root of t^2 + 2 z t - 1 = 0 with z = (b - a) / (2 g),
+            // written as sign(b - a) 2 g / (|b - a| + hypot(b - a, 2 g)) so
+            // that no quotient can overflow when g is tiny against b - a
+            const double tau = bb - a, rho = 2.0 * gg;
+            const double w = fma(tau, tau, rho * rho);
+            const double h = w * __builtin_amdgcn_rsq(w);
+            const double t = (tau >= 0.0 ? rho : -rho) * __builtin_amdgcn_rcp(fabs(tau) + h);
             const double cs = rsq_nr(1.0 + t * t), sn = t * cs;
 #pragma unroll
             for (int tt = 0; tt < NE; ++tt) {

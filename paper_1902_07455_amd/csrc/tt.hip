@@ -74,6 +74,23 @@ __global__ void k_randn(double* __restrict__ out, long long n, uint64_t key) {
   }
 }
 
+// Two independent streams of the same numbers in one launch: element i of
+// o1 is k_randn's element i under k1, element i of o2 its element i under k2.
+__global__ void k_randn2(double* __restrict__ o1, long long n1, uint64_t k1, double* __restrict__ o2, long long n2,
+                         uint64_t k2) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + n2;
+       t += (long long)gridDim.x * blockDim.x) {
+    const bool first = t < n1;
+    const long long i = first ? t : t - n1;
+    const uint64_t key = first ? k1 : k2;
+    const uint64_t a = smix(key ^ (2ull * (uint64_t)i));
+    const uint64_t b = smix(key ^ (2ull * (uint64_t)i + 1ull) ^ 0x5851F42D4C957F2Dull);
+    const double u1 = ((double)(a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((double)(b >> 11)) * (1.0 / 9007199254740992.0);
+    (first ? o1 : o2)[i] = sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2);
+  }
+}
+
 // The same product for wide carriages (ra1 rx1 >= 64): rows (I, n) of the
 // output, kKrRows per block, one thread per output column J, so the row
 // indices are block-uniform and a thread splits its own J once; the rows'
@@ -676,10 +693,9 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
       return LRFG_EINVAL;
     }
     // Gaussian sketch carriages
-    hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l1 * N2 * l2)), dim3(kB), 0, s, om[1],
-                       (long long)l1 * N2 * l2, key);
-    hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l2 * N3)), dim3(kB), 0, s, om[2], (long long)l2 * N3,
-                       key ^ 0xA5A5A5A5A5A5A5A5ull);
+    { const long long n1 = (long long)l1 * N2 * l2, n2 = (long long)l2 * N3;
+      hipLaunchKernelGGL(k_randn2, dim3(grid_for(n1 + n2)), dim3(kB), 0, s, om[1], n1, key, om[2], n2,
+                         key ^ 0xA5A5A5A5A5A5A5A5ull); }
     LRFG_LAUNCHED();
     // W3 = X3 Om3^T (R2 x l2)
     { GemmB g(R2, l2, N3, nE); g.a(in.c[2], N3, in.s[2]).b(om[2], N3, 0, true).c(W3, l2, (long long)R2 * l2);
