@@ -575,7 +575,8 @@ __device__ inline unsigned wave_max_u32(unsigned v) {
 // semidefinite n x n matrix G in g (LDS, read only), n <= NMAX <= 64, by
 // one wave (lane j owns index j).  Step k takes the largest remaining
 // diagonal entry p = perm[k] as pivot (entries within 2^-17 relative of
-// each other, compared in FP32, go to the lower index) and stores the pivot
+// each other, compared in FP32 as fractions of the largest initial diagonal
+// entry, go to the lower index) and stores the pivot
 // column of the factor, in the original index order, as row k of L (LDS,
 // n x n, zero on entry): G = sum_{k<r} L[k]^T L[k].  It stops when the
 // largest remaining diagonal entry is at most tau times the largest initial
@@ -599,11 +600,15 @@ __device__ int pchol_wave(int n, const double* __restrict__ g, double* __restric
   double dg = lane < n ? g[lane * n + lane] : 0.0;
   const double d0 =
       __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(fmax(dg, 0.0))));
+  // keys are taken relative to the largest diagonal entry, so that the FP32
+  // comparison neither overflows nor flushes for any scale of G
+  const double rel = d0 > 0.0 ? 1.0 / d0 : 0.0;
   bool chosen = lane >= n;
   int r = n;
   for (int k = 0; k < n; ++k) {
-    // key: FP32 value bits of the (non-negative) diagonal, low 6 bits = 63 - lane
-    const float fv = (float)fmax(dg, 0.0);
+    // key: FP32 value bits of the (non-negative) diagonal relative to d0,
+    // low 6 bits = 63 - lane
+    const float fv = (float)(fmax(dg, 0.0) * rel);
     const unsigned key = wave_max_u32(chosen ? 0u : ((__float_as_uint(fv) & ~63u) | (unsigned)(63 - lane)));
     const int p = 63 - (int)(key & 63u);
     const double best = key == 0u ? 0.0
@@ -743,6 +748,7 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   __shared__ int rank_s;
   __shared__ double trace_s;
   __shared__ int kept_s;
+  __shared__ int scale_s;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* G = Gg + b * sG;
   for (int e = tid; e < n * n; e += NT) {
@@ -750,6 +756,24 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
     L[e] = 0.0;
   }
   if (tid < kCutSweeps) flags[tid] = 0;
+  __syncthreads();
+  // G is used divided by a power of two near its largest diagonal entry
+  // (exact): the squared column norms of the Jacobi are then at most
+  // trace <= n and the smallest the Cholesky threshold lets through near
+  // tau, so the pair tests and angles stay in range whatever the scale of
+  // G, and G and 2^k G (neither with subnormal entries) give the same
+  // basis bit for bit
+  if (tid < 64) {
+    double dm = (tid < n) ? fmax(g[tid * n + tid], 0.0) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    if (tid == 0) scale_s = dm > 0.0 ? __builtin_amdgcn_frexp_exp(dm) : 0;
+  }
+  __syncthreads();
+  {
+    const int sx = scale_s;
+    for (int e = tid; e < n * n; e += NT) g[e] = __builtin_amdgcn_ldexp(g[e], -sx);
+  }
   __syncthreads();
   if (tid < 64) {
     double t = (tid < n) ? fmax(g[tid * n + tid], 0.0) : 0.0;
@@ -812,6 +836,8 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
             // smaller root of t^2 + 2 z t - 1 = 0 with z = (b - a) / (2 g),
             // written as sign(b - a) 2 g / (|b - a| + hypot(b - a, 2 g)) so
             // that no quotient can overflow when g is tiny against b - a
+            // (a, b <= trace(G) <= n after the scaling, so the squares stay
+            // in range)
             const double tau = bb - a, rho = 2.0 * gg;
             const double w = fma(tau, tau, rho * rho);
             const double h = w * __builtin_amdgcn_rsq(w);

@@ -125,6 +125,29 @@ def test_gram_cut_subspace(dev, n, rank, c, decades):
         assert sweeps[b] <= 12
 
 
+@pytest.mark.parametrize("n", [12, 26, 40, 64])
+def test_gram_cut_scale_invariant(dev, n):
+    """G scaled by 2^600 or 2^-600 (entries far outside FP32's range, squared
+    norms near FP64's limits): the cut works on G divided by a power of two
+    near its largest diagonal entry, so the basis and the kept count come
+    out bit for bit the same as for G itself."""
+    import torch
+    rng = np.random.default_rng(11 * n)
+    G = np.stack([_graded_gram(rng, n, n, 7) for _ in range(2)])
+    outs = []
+    for e in (0, 600, -600):
+        S, kept, _ = P.gram_cut(torch.from_numpy(np.ldexp(G, e)).to(dev), max(1, n - 6), tol=1e-4)
+        torch.cuda.synchronize()
+        outs.append((S.cpu().numpy(), kept.cpu().numpy()))
+    S0, k0 = outs[0]
+    assert np.all(k0 > 0)
+    lam = np.sort(np.linalg.eigvalsh(G[0]))[::-1]
+    assert np.max(np.abs(S0[0][:, :k0[0]].T @ G[0] @ S0[0][:, :k0[0]] - np.diag(lam[:k0[0]]))) <= 1e-12 * lam[0]
+    for S, kept in outs[1:]:
+        assert np.array_equal(kept, k0)
+        assert np.array_equal(S, S0)
+
+
 def test_gram_cut_tolerance_and_zero(dev):
     import torch
     rng = np.random.default_rng(3)

@@ -41,6 +41,21 @@ def test_exact_low_rank_is_reproduced(dev, Ns, ranks, cap):
         assert list(kept[:, e]) == [ranks[1], ranks[2]]
 
 
+@pytest.mark.parametrize("e2", [-300, 300])
+def test_exact_low_rank_any_scale(dev, e2):
+    """The same exact-rank case with the train scaled by 2^e2: Gram entries
+    far outside FP32's range must not change the ranks found, and the result
+    is the scaled reconstruction."""
+    Ns, ranks = (15, 17, 13), (1, 5, 4, 1)
+    X = W.random_tt(Ns, list(ranks), 21)
+    Xs = [np.ldexp(X[0], e2)] + [c.copy() for c in X[1:]]
+    outs, kept = P.tt_round(_dev([L.tt_add(Xs, Xs)], dev), cap=8, tol=0.0, oversample=4, seed=5)
+    want = np.ldexp(2.0 * L.tt_full(X), e2)
+    got = L.tt_full(_host(outs, 0))
+    assert list(kept[:, 0]) == [ranks[1], ranks[2]]
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
 @pytest.mark.parametrize("d", [2, 3])
 def test_truncation_error_near_optimal(dev, d):
     Ns = (30, 40) if d == 2 else (12, 14, 16)
