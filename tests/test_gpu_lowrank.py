@@ -74,6 +74,21 @@ def test_truncated_is_upper_bound(dev, cap):
     assert _rel(r.A_H, o.A_H) < 0.2
 
 
+@pytest.mark.parametrize("fmt", ["tt", "tucker"])
+@pytest.mark.parametrize("e2", [-150, 150])
+def test_scaled_coefficient(dev, fmt, e2):
+    """A_H is linear in the coefficient: the coefficient times 2^e2 (every
+    Gram matrix of the truncations then far outside FP32's range) gives
+    2^e2 times the unscaled result."""
+    N = 21
+    cp = W.square_cp(N, 3, inside=10.0)
+    kw = dict(d=3, N=(N,) * 3, format=fmt, rank_cap=6, solver_tol=1e-10, max_iter=100, coeff_rank=2)
+    r0 = P.Solver(**kw).solve(cp=_cp_args(cp))
+    r1 = P.Solver(**kw).solve(cp=(np.ldexp(cp.weights, e2), cp.factors))
+    assert np.all(np.asarray(r1.ranks) == np.asarray(r0.ranks))
+    assert _rel(np.ldexp(r1.A_H, -e2), r0.A_H) <= 1e-9
+
+
 def test_smooth_135_rank20(dev):
     """The benchmark workload: 135^3 smooth coefficient (CP rank 9), TT
     rank cap 20; error against the oracle reported and bounded."""

@@ -54,6 +54,25 @@ def test_exact_low_rank_is_reproduced(dev, Ns, ranks, cap):
         assert list(kept[:, e]) == [min(r, n) for r, n in zip(ranks, Ns)]
 
 
+@pytest.mark.parametrize("e2", [-300, 300])
+def test_exact_low_rank_any_scale(dev, e2):
+    """An exact-rank Tucker tensor scaled by 2^e2 (Gram entries far outside
+    FP32's range): the same ranks are found and the scaled tensor is
+    reproduced."""
+    import torch
+    rng = np.random.default_rng(5)
+    Ns, ranks = (13, 15, 11), (4, 3, 5)
+    frames, core = _random_tucker(rng, Ns, ranks)
+    core = np.ldexp(core, e2)
+    fo, co, kept = P.tucker_round(_dev([f[None] for f in frames], dev), _dev([core[None]], dev)[0], cap=6,
+                                  tol=0.0, oversample=6, seed=2)
+    torch.cuda.synchronize()
+    ref = _full(frames, core)
+    got = _full([f[0].cpu().numpy() for f in fo], co[0].cpu().numpy())
+    assert list(kept[:, 0]) == list(ranks)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
 def test_truncation_error_near_hosvd(dev):
     """Cap below the ranks: the error is within 1.5x the oracle's
     truncated HOSVD error at the same ranks (Appendix A.2), which itself is
