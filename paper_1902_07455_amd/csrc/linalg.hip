@@ -804,15 +804,14 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   int sweeps = 0;
   for (int sweep = 0; sweep < kCutSweeps && r > 1; ++sweep) {
     sweeps = sweep + 1;
+    // the group's two positions, less one, advance by one per step modulo
+    // m - 1 (group 0 keeps position 0)
+    int u0 = grp - 1, u1 = m - 2 - grp;
     for (int step = 0; step < m - 1; ++step) {
+      const int t0 = grp == 0 ? 0 : 1 + u0, t1 = 1 + u1;
+      u0 = u0 + 1 == m - 1 ? 0 : u0 + 1;
+      u1 = u1 + 1 == m - 1 ? 0 : u1 + 1;
       if (grp < np) {
-        int t0 = 0;
-        if (grp != 0) {
-          const int u = grp - 1 + step;
-          t0 = 1 + (u >= m - 1 ? u - (m - 1) : u);
-        }
-        const int u1 = (m - 1 - grp) - 1 + step;
-        const int t1 = 1 + (u1 >= m - 1 ? u1 - (m - 1) : u1);
         const int p = t0 < t1 ? t0 : t1, q = t0 < t1 ? t1 : t0;
         if (q < r) {
           double wp[NE], wq[NE];
