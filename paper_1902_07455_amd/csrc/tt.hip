@@ -191,26 +191,30 @@ __global__ __launch_bounds__(256) void k_kr_x2(const double* __restrict__ a, lon
   }
 }
 
-// The same two contractions with every coefficient-rank term of one
-// thread's column held in registers (coefficient ranks up to RA): a thread
-// reads its Z (or U) column once and writes all ra0 (or ra1) outputs of
-// it; sums in the same order as above.
+// The same two contractions with one block per (mode index n, train) and
+// every coefficient-rank term of one thread's column held in registers
+// (coefficient ranks up to RA): the slice a[:][n][:] is the same for the
+// whole block, so it is read through the scalar cache once per block rather
+// than by every thread, and a thread reads its Z (or U) column once and
+// writes all ra0 (or ra1) outputs of it; sums in the same order as above.
 template <int RA>
 __global__ __launch_bounds__(256) void k_kr_t2_reg(const double* __restrict__ a, long long sa, int amod, int ra0,
                                                    int ra1, int N, const double* __restrict__ Z, long long sz,
                                                    int rg0, int l2, double* __restrict__ T2, long long st) {
-  const int s = blockIdx.y;
-  const double* as = a + (long long)(s % amod) * sa;
+  const int n = blockIdx.x, s = blockIdx.y;
+  const double* an = a + (long long)(s % amod) * sa + (long long)n * ra1;  // a[i][n][j] = an[i N ra1 + j]
   const double* zs = Z + (long long)s * sz;
   double* ts = T2 + (long long)s * st;
-  const int Q = rg0 * N * l2;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Q; q += gridDim.x * blockDim.x) {
-    const int n = (q / l2) % N;
+  const long long Q = (long long)rg0 * N * l2;
+  const int E = rg0 * l2;  // (k, l) at this n
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const int k = e / l2, l = e - (e / l2) * l2;
+    const long long q = ((long long)k * N + n) * l2 + l;
     double z[RA];
 #pragma unroll
     for (int j = 0; j < RA; ++j) z[j] = j < ra1 ? zs[(long long)j * Q + q] : 0.0;
     for (int i = 0; i < ra0; ++i) {
-      const double* ar = as + ((long long)i * N + n) * ra1;
+      const double* ar = an + (long long)i * N * ra1;
       double v = 0.0;
 #pragma unroll
       for (int j = 0; j < RA; ++j)
@@ -223,15 +227,13 @@ template <int RA>
 __global__ __launch_bounds__(256) void k_kr_x2_reg(const double* __restrict__ a, long long sa, int amod, int ra0,
                                                    int ra1, int N, const double* __restrict__ U, long long su,
                                                    int rg1, int l1, double* __restrict__ X, long long sx) {
-  const int s = blockIdx.y;
-  const double* as = a + (long long)(s % amod) * sa;
+  const int n = blockIdx.x, s = blockIdx.y;
+  const double* an = a + (long long)(s % amod) * sa + (long long)n * ra1;  // a[i][n][j] = an[i N ra1 + j]
   const double* us = U + (long long)s * su;
   double* xs = X + (long long)s * sx;
-  const int per = l1 * N * rg1;  // (p, n, m)
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
-    const int m = idx % rg1;
-    const int r = idx / rg1;
-    const int n = r % N, p = r / N;
+  const int E = l1 * rg1;  // (p, m) at this n
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const int p = e / rg1, m = e - (e / rg1) * rg1;
     const double* up = us + ((long long)p * ra0 * N + n) * rg1 + m;
     double u[RA];
 #pragma unroll
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_kr_x2_reg(const double* __restrict__ a,
       double v = 0.0;
 #pragma unroll
       for (int i = 0; i < RA; ++i)
-        if (i < ra0) v = fma(as[((long long)i * N + n) * ra1 + j], u[i], v);
+        if (i < ra0) v = fma(an[(long long)i * N * ra1 + j], u[i], v);
       xo[(long long)j * rg1] = v;
     }
   }
@@ -720,8 +722,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
         g.g.adiv = ra1;
         LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
       if (ra1 <= kKrRegRank) {
-        const long long per = (long long)rg0 * N2 * l2;
-        const dim3 grid((unsigned)std::min<long long>(2048, (per + kB - 1) / kB), (unsigned)nE);
+        const dim3 grid((unsigned)N2, (unsigned)nE);
         hipLaunchKernelGGL(k_kr_t2_reg<kKrRegRank>, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1,
                            N2, (const double*)kz, zs, rg0, l2, T2, (long long)R1 * N2 * l2);
         LRFG_LAUNCHED();
@@ -757,8 +758,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
             .c(kz, (long long)N2 * rg1, (long long)l1 * ra0 * N2 * rg1);
         LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
       if (ra0 <= kKrRegRank) {
-        const long long per = (long long)l1 * N2 * rg1;
-        const dim3 grid((unsigned)std::min<long long>(2048, (per + kB - 1) / kB), (unsigned)nE);
+        const dim3 grid((unsigned)N2, (unsigned)nE);
         hipLaunchKernelGGL(k_kr_x2_reg<kKrRegRank>, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1,
                            N2, (const double*)kz, (long long)l1 * ra0 * N2 * rg1, rg1, l1, X2p,
                            (long long)l1 * N2 * R2);
