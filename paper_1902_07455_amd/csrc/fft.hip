@@ -68,10 +68,24 @@ const FftPlan* fft_plan_cached(int N) {
 // Tile = T consecutive line ids of the view x[outer][N][inner]; line id
 // l = o*inner + i.  Elements of a tile are loaded so that consecutive
 // threads touch consecutive addresses.
+// Line ids and inner strides stay below 2^32 (the launchers check), so the
+// split of a line id takes a 32-bit division rather than a 64-bit one.
 __device__ inline long long line_addr(long long l, int n, int N, int inner) {
-  const long long o = l / inner;
-  const long long i = l - o * inner;
-  return (o * N + n) * (long long)inner + i;
+  const unsigned lu = (unsigned)l, iu = (unsigned)inner;
+  const unsigned o = lu / iu;
+  const unsigned i = lu - o * iu;
+  return ((long long)o * N + n) * (long long)inner + i;
+}
+// The (line, index) of element idx < T N of a tile: line-fast when the
+// lines are adjacent in memory (inner > 1), index-fast otherwise.
+__device__ inline void tile_pos(int idx, bool line_fast, int T, float rT, int N, float rN, int* t, int* n) {
+  if (line_fast) {
+    *n = fdiv(idx, T, rT);
+    *t = idx - *n * T;
+  } else {
+    *t = fdiv(idx, N, rN);
+    *n = idx - *t * N;
+  }
 }
 
 template <int DIR, bool GEN>
@@ -93,6 +107,7 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
     if (all_done) return;
   }
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   double2 v[kFftMaxE];
@@ -100,14 +115,14 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     v[i] = (idx < total && t < tcount) ? x[line_addr(l0 + t, n, N, inner)] : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
@@ -116,7 +131,7 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     if (idx < total && t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(sm[t * N + n], scale);
   }
 }
@@ -126,9 +141,10 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
 // depends on a neighbouring system and a batch reproduces its systems'
 // single results bit for bit.  Pair p of P = ceil(F/2) per system.
 __device__ inline long long pair_first(long long p, long long F, long long P, bool* has_second) {
-  const long long e = p / P, q = p - e * P;
-  *has_second = 2 * q + 1 < F;
-  return e * F + 2 * q;
+  const unsigned pu = (unsigned)p, Pu = (unsigned)P;
+  const unsigned e = pu / Pu, q = pu - e * Pu;
+  *has_second = 2 * (long long)q + 1 < F;
+  return (long long)e * F + 2 * (long long)q;
 }
 
 // Real circulant along the mode index: two real fibres packed into one
@@ -146,6 +162,7 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   const long long npair = (nfib / F) * P;
   const long long p0 = (long long)blockIdx.x * T;
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   double2 v[kFftMaxE];
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     bool hb = false;
     const bool ok = idx < total && p0 + t < npair;
     const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
@@ -165,22 +182,21 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
   lds_fft1<-1, GEN>(sm, T, f, tw);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int n = idx % N;
+  // one factor per mode index, applied down the T lines of the tile
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     const int k = freq_of(n, N);
-    double2 w = sm[idx];
-    if (op == 0) {
-      w = cmul_i(w, mult * 2.0 * kPi * (double)k / (double)N);
-    } else {
-      w = cscale(w, mult * exp(-tparam * (double)k * (double)k) / (double)N);
+    const double fk = op == 0 ? mult * 2.0 * kPi * (double)k / (double)N
+                              : mult * exp(-tparam * (double)k * (double)k) / (double)N;
+    for (int t = 0; t < T; ++t) {
+      const double2 w = sm[t * N + n];
+      sm[t * N + n] = op == 0 ? cmul_i(w, fk) : cscale(w, fk);
     }
-    sm[idx] = w;
   }
   __syncthreads();
   lds_fft1<1, GEN>(sm, T, f, tw);
@@ -189,7 +205,7 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (inner > 1) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
     if (idx < total && p0 + t < npair) {
       bool hb = false;
       const long long fa = pair_first(p0 + t, F, P, &hb);
@@ -224,20 +240,31 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   const long long npair = (long long)nE * P;
   const long long p0 = (long long)blockIdx.x * T;
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   const int o0 = bl0 ? m * r0 : 0, o1 = bl1 ? m * r1 : 0;
+  // fibre ids l < nE r0 r1 < 2^32 (the launcher checks): 32-bit splits
+  const unsigned Fu = (unsigned)F, r1u = (unsigned)r1;
+  auto split = [&](long long l, unsigned* e, int* a, int* b) {
+    const unsigned lu = (unsigned)l;
+    *e = lu / Fu;
+    const unsigned rem = lu - *e * Fu;
+    const unsigned au = rem / r1u;
+    *a = (int)au;
+    *b = (int)(rem - au * r1u);
+  };
   auto in_addr = [&](long long l, int n) -> long long {
-    const long long e = l / ((long long)r0 * r1);
-    const long long rem = l - e * r0 * r1;
-    const int a = (int)(rem / r1), b = (int)(rem - (long long)(rem / r1) * r1);
-    return e * sx + ((long long)a * N + n) * r1 + b;
+    unsigned e;
+    int a, b;
+    split(l, &e, &a, &b);
+    return (long long)e * sx + ((long long)a * N + n) * r1 + b;
   };
   auto out_addr = [&](long long l, int n) -> long long {
-    const long long e = l / ((long long)r0 * r1);
-    const long long rem = l - e * r0 * r1;
-    const int a = (int)(rem / r1), b = (int)(rem - (long long)(rem / r1) * r1);
-    return e * so + ((long long)(o0 + a) * N + n) * R1 + o1 + b;
+    unsigned e;
+    int a, b;
+    split(l, &e, &a, &b);
+    return (long long)e * so + ((long long)(o0 + a) * N + n) * R1 + o1 + b;
   };
   const bool fibre_fast = r1 > 1;  // consecutive fibres are adjacent in memory
   double2 v[kFftMaxE];
@@ -245,7 +272,7 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
     bool hb = false;
     const bool ok = idx < total && p0 + t < npair;
     const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
@@ -257,17 +284,17 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
   lds_fft1<-1, GEN>(sm, T, f, tw);
   __syncthreads();
   const double tm = tp.t[m], scm = tp.sc[m];
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int n = idx % N;
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     const int k = freq_of(n, N);
-    sm[idx] = cscale(sm[idx], scm * exp(-tm * (double)k * (double)k) / (double)N);
+    const double fk = scm * exp(-tm * (double)k * (double)k) / (double)N;
+    for (int t = 0; t < T; ++t) sm[t * N + n] = cscale(sm[t * N + n], fk);
   }
   __syncthreads();
   lds_fft1<1, GEN>(sm, T, f, tw);
@@ -276,7 +303,7 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    if (fibre_fast) { t = idx % T; n = idx / T; } else { n = idx % N; t = idx / N; }
+    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
     if (idx < total && p0 + t < npair) {
       bool hb = false;
       const long long fa = pair_first(p0 + t, F, P, &hb);
@@ -301,6 +328,10 @@ int launch_mode_op_blocks(const double* xin, long long sx, int r0, int r1, int n
   }
   const long long nfib = (long long)nE * r0 * r1;
   if (nfib == 0) return LRFG_OK;
+  if (nfib >= (1ll << 32)) {
+    set_error("mode op: %lld fibres (at most 2^32 - 1)", nfib);
+    return LRFG_EUNSUPPORTED;
+  }
   TermParams tp;
   for (int i = 0; i < kMaxTerms; ++i) {
     tp.t[i] = i < M ? t[i] : 0.0;
@@ -337,6 +368,10 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
                      long long lines_per_flag) {
   const long long nlines = outer * inner;
   if (nlines == 0) return LRFG_OK;
+  if (nlines >= (1ll << 32) || inner >= (1ll << 31)) {
+    set_error("FFT lines: %lld lines of stride %lld (at most 2^32 - 1 and 2^31 - 1)", nlines, inner);
+    return LRFG_EUNSUPPORTED;
+  }
   if (N > kFftMaxE * kFftBlock) {
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
@@ -369,6 +404,10 @@ int launch_mode_op_oop(const double* xin, double* x, long long outer, int N, lon
     return LRFG_EINVAL;
   }
   const long long npair = (nfib / F) * ((F + 1) / 2);
+  if (nfib >= (1ll << 32) || inner >= (1ll << 31)) {
+    set_error("mode op: %lld fibres of stride %lld (at most 2^32 - 1 and 2^31 - 1)", nfib, inner);
+    return LRFG_EUNSUPPORTED;
+  }
   if (N > kFftMaxE * kFftBlock) {
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
