@@ -78,14 +78,13 @@ __device__ inline long long line_addr(long long l, int n, int N, int inner) {
 }
 // The (line, index) of element idx < T N of a tile: line-fast when the
 // lines are adjacent in memory (inner > 1), index-fast otherwise.
-__device__ inline void tile_pos(int idx, bool line_fast, int T, float rT, int N, float rN, int* t, int* n) {
+__device__ inline int2 tile_pos(int idx, bool line_fast, int T, float rT, int N, float rN) {
   if (line_fast) {
-    *n = fdiv(idx, T, rT);
-    *t = idx - *n * T;
-  } else {
-    *t = fdiv(idx, N, rN);
-    *n = idx - *t * N;
+    const int n = fdiv(idx, T, rT);
+    return make_int2(idx - n * T, n);
   }
+  const int t = fdiv(idx, N, rN);
+  return make_int2(t, idx - t * N);
 }
 
 template <int DIR, bool GEN>
@@ -115,14 +114,18 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     v[i] = (idx < total && t < tcount) ? x[line_addr(l0 + t, n, N, inner)] : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
@@ -131,7 +134,9 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total && t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(sm[t * N + n], scale);
   }
 }
@@ -170,7 +175,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     bool hb = false;
     const bool ok = idx < total && p0 + t < npair;
     const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
@@ -182,7 +189,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
@@ -205,7 +214,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, inner > 1, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, inner > 1, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total && p0 + t < npair) {
       bool hb = false;
       const long long fa = pair_first(p0 + t, F, P, &hb);
@@ -246,25 +257,13 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   const int o0 = bl0 ? m * r0 : 0, o1 = bl1 ? m * r1 : 0;
   // fibre ids l < nE r0 r1 < 2^32 (the launcher checks): 32-bit splits
   const unsigned Fu = (unsigned)F, r1u = (unsigned)r1;
-  auto split = [&](long long l, unsigned* e, int* a, int* b) {
-    const unsigned lu = (unsigned)l;
-    *e = lu / Fu;
-    const unsigned rem = lu - *e * Fu;
-    const unsigned au = rem / r1u;
-    *a = (int)au;
-    *b = (int)(rem - au * r1u);
-  };
   auto in_addr = [&](long long l, int n) -> long long {
-    unsigned e;
-    int a, b;
-    split(l, &e, &a, &b);
+    const unsigned lu = (unsigned)l, e = lu / Fu, rem = lu - e * Fu, a = rem / r1u, b = rem - a * r1u;
     return (long long)e * sx + ((long long)a * N + n) * r1 + b;
   };
   auto out_addr = [&](long long l, int n) -> long long {
-    unsigned e;
-    int a, b;
-    split(l, &e, &a, &b);
-    return (long long)e * so + ((long long)(o0 + a) * N + n) * R1 + o1 + b;
+    const unsigned lu = (unsigned)l, e = lu / Fu, rem = lu - e * Fu, a = rem / r1u, b = rem - a * r1u;
+    return (long long)e * so + ((long long)(o0 + (int)a) * N + n) * R1 + o1 + b;
   };
   const bool fibre_fast = r1 > 1;  // consecutive fibres are adjacent in memory
   double2 v[kFftMaxE];
@@ -272,7 +271,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, fibre_fast, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     bool hb = false;
     const bool ok = idx < total && p0 + t < npair;
     const long long fa = ok ? pair_first(p0 + t, F, P, &hb) : 0;
@@ -284,7 +285,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, fibre_fast, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total) sm[t * N + n] = v[i];
   }
   __syncthreads();
@@ -303,7 +306,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op_blocks(const double* __re
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
     int t, n;
-    tile_pos(idx, fibre_fast, T, rT, N, rN, &t, &n);
+    const int2 tn = tile_pos(idx, fibre_fast, T, rT, N, rN);
+    t = tn.x;
+    n = tn.y;
     if (idx < total && p0 + t < npair) {
       bool hb = false;
       const long long fa = pair_first(p0 + t, F, P, &hb);
