@@ -40,11 +40,15 @@ struct G3 {
   long long R;  // real entries
 };
 
+// Entry and line ids of a grid stay below 2^32 (full_solve and full_op
+// refuse larger grids), so their splits take 32-bit divisions.
 __device__ inline long long addr3(long long l, int n, int N, long long inner) {
-  const long long o = l / inner;
-  const long long i = l - o * inner;
-  return (o * N + n) * inner + i;
+  const unsigned lu = (unsigned)l, iu = (unsigned)inner;
+  const unsigned o = lu / iu;
+  const unsigned i = lu - o * iu;
+  return ((long long)o * N + n) * inner + i;
 }
+constexpr long long kMaxGridEntries = (1ll << 32) - 1;
 
 // Frequencies of half-spectrum entry (n1, n2, h).
 __device__ inline void kvec(const G3& g, int n1, int n2, int h, double k[3]) {
@@ -80,25 +84,26 @@ __global__ __launch_bounds__(kFftBlock) void k_grad_axis1(const double2* __restr
   const double2* s = src + (long long)e * g.S;
   double2* d = dst + e * dst_stride_e + a * dst_stride_a;
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   double2 v[kFftMaxE];
 #pragma unroll
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
-    const int t = idx % T, n = idx / T;
+    const int n = fdiv(idx, T, rT), t = idx - n * T;
     v[i] = (idx < total && t < tcount) ? s[(long long)n * inner + l0 + t] : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
-    const int t = idx % T, n = idx / T;
+    const int n = fdiv(idx, T, rT), t = idx - n * T;
     if (idx < total) {
       const long long ii = l0 + t;
       double kk;
       if (alpha == 0) kk = (double)freq_of(n, g.N1);
-      else if (alpha == 1) kk = (double)freq_of((int)(ii / g.H), g.N2);
-      else kk = (double)(ii % g.H);
+      else if (alpha == 1) kk = (double)freq_of((int)((unsigned)ii / (unsigned)g.H), g.N2);
+      else kk = (double)((unsigned)ii % (unsigned)g.H);
       sm[t * N + n] = cmul_i(v[i], 2.0 * kPi * kk);
     }
   }
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(kFftBlock) void k_grad_axis1(const double2* __restr
 #pragma unroll
   for (int i = 0; i < kFftMaxE; ++i) {
     const int idx = threadIdx.x + i * kFftBlock;
-    const int t = idx % T, n = idx / T;
+    const int n = fdiv(idx, T, rT), t = idx - n * T;
     if (idx < total && t < tcount) d[(long long)n * inner + l0 + t] = sm[t * N + n];
   }
 }
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
   const long long l0 = (long long)blockIdx.x * T;
   const int tcount = (int)min((long long)T, inner - l0);
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   double2 acc[kFftMaxE];
@@ -141,13 +147,13 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
 #pragma unroll
     for (int i = 0; i < kFftMaxE; ++i) {
       const int idx = threadIdx.x + i * kFftBlock;
-      const int tt = idx % T, n = idx / T;
+      const int n = fdiv(idx, T, rT), tt = idx - n * T;
       v[i] = (idx < total && tt < tcount) ? s[(long long)n * inner + l0 + tt] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int i = 0; i < kFftMaxE; ++i) {
       const int idx = threadIdx.x + i * kFftBlock;
-      const int tt = idx % T, n = idx / T;
+      const int n = fdiv(idx, T, rT), tt = idx - n * T;
       if (idx < total) sm[tt * N + n] = v[i];
     }
     __syncthreads();
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
     for (int j = 0; j < kFftMaxE; ++j) {
       const int idx = threadIdx.x + j * kFftBlock;
       if (idx < total) {
-        const int tt = idx % T, n = idx / T;
+        const int n = fdiv(idx, T, rT), tt = idx - n * T;
         const long long i = l0 + tt;
         double kk;
         if (alpha == 0) kk = (double)freq_of(n, g.N1);
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
 #pragma unroll
   for (int j = 0; j < kFftMaxE; ++j) {
     const int idx = threadIdx.x + j * kFftBlock;
-    const int tt = idx % T, n = idx / T;
+    const int n = fdiv(idx, T, rT), tt = idx - n * T;
     if (idx < total && tt < tcount) {
       const long long i = l0 + tt;
       const long long ad = (long long)n * inner + i;
@@ -209,6 +215,7 @@ __global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ sr
   const long long nl = (long long)g.N1 * g.N2;
   const long long p0 = (long long)blockIdx.x * T;      // first pair
   const int total = T * N;
+  const float rT = 1.0f / (float)T, rN = 1.0f / (float)N;
   double2* tw = sm + total;
   stage_twiddles(tw, f);
   // load (two real lines per complex line)
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ sr
 #pragma unroll
     for (int i = 0; i < kFftMaxE; ++i) {
       const int idx = threadIdx.x + i * kFftBlock;
-      const int n = idx % N, t = idx / N;
+      const int t = fdiv(idx, N, rN), n = idx - t * N;
       const long long la = 2 * (p0 + t), lb = la + 1;
       double2 z = make_double2(0.0, 0.0);
       if (idx < total) {
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ sr
 #pragma unroll
       for (int i = 0; i < kFftMaxE; ++i) {
         const int idx = threadIdx.x + i * kFftBlock;
-        const int n = idx % N, t = idx / N;
+        const int t = fdiv(idx, N, rN), n = idx - t * N;
         const long long la = 2 * (p0 + t), lb = la + 1;
         if (idx < total) {
           const double2 w = sm[idx];
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ sr
 #pragma unroll
     for (int i = 0; i < kFftMaxE; ++i) {
       const int idx = threadIdx.x + i * kFftBlock;
-      const int n = idx % N, t = idx / N;
+      const int t = fdiv(idx, N, rN), n = idx - t * N;
       const long long la = 2 * (p0 + t), lb = la + 1;
       if (idx < total) {
         const double aa = la < nl ? acoef[la * N + n] : 0.0;
@@ -313,10 +320,12 @@ struct CgState {
 };
 
 __device__ inline void decode(const G3& g, long long s, int& n1, int& n2, int& h) {
-  h = (int)(s % g.H);
-  const long long r = s / g.H;
-  n2 = (int)(r % g.N2);
-  n1 = (int)(r / g.N2);
+  const unsigned su = (unsigned)s, Hu = (unsigned)g.H, N2u = (unsigned)g.N2;
+  const unsigned r = su / Hu;
+  h = (int)(su - r * Hu);
+  const unsigned q = r / N2u;
+  n2 = (int)(r - q * N2u);
+  n1 = (int)q;
 }
 
 // Sum of part[0..n) by one block, same order in every block; result broadcast.
@@ -614,6 +623,10 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     N3d[2] = A.N[1];
   }
   const int alpha0 = 3 - d;
+  if ((long long)N3d[0] * N3d[1] * N3d[2] > kMaxGridEntries) {
+    set_error("full-grid solve: %d x %d x %d grid above 2^32 - 1 entries", N3d[0], N3d[1], N3d[2]);
+    return LRFG_EUNSUPPORTED;
+  }
   Arena ar;
   ar.base = static_cast<char*>(A.ws);
   ar.cap = A.ws_bytes;
@@ -857,6 +870,10 @@ size_t full_op_workspace_bytes(const int N[3]) {
 int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, const FftPlan* p3,
             const double* a, const double* u, double* outp, void* ws, size_t ws_bytes, hipStream_t s) {
   G3 g = make_g3(N);
+  if (g.R > kMaxGridEntries) {
+    set_error("full-grid operator: grid above 2^32 - 1 entries");
+    return LRFG_EUNSUPPORTED;
+  }
   Arena ar;
   ar.base = static_cast<char*>(ws);
   ar.cap = ws_bytes;
@@ -916,6 +933,10 @@ __global__ void k_pinv(const double2* __restrict__ u, double2* __restrict__ o, G
 int launch_pinv(const double2* u, double2* o, int N1, int N2, int N3, hipStream_t s) {
   const int N[3] = {N1, N2, N3};
   G3 g = make_g3(N);
+  if (g.R > kMaxGridEntries) {
+    set_error("inverse Laplacian: grid above 2^32 - 1 entries");
+    return LRFG_EUNSUPPORTED;
+  }
   long long gv = ceil_div(g.S, kBlock * 4);
   if (gv > 4096) gv = 4096;
   hipLaunchKernelGGL(k_pinv, dim3((int)gv), dim3(kBlock), 0, s, u, o, g);
