@@ -266,7 +266,7 @@ int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* st
 
 /* Truncation basis of batched symmetric positive semidefinite Gram
  * matrices (the l x l Gram matrices of the truncation's SVD cut, Sec. 3.1.4
- * and Appendix A.3), n <= 64, all pointers device: G is batch x n x n
+ * and Appendix A.3), n <= 128, all pointers device: G is batch x n x n
  * (row-major); S (batch x n x c) receives the eigenvectors of the kept
  * eigenvalues as columns, largest first, with zero columns beyond the kept
  * count.  Kept: at most c, above the rank threshold of the pivoted
@@ -276,7 +276,7 @@ int lrfg_syevj(int n, const double* A, int batch, double* W, double* V, void* st
  * tol^2 trace(G).  The eigenpairs come from one-sided Jacobi on the columns
  * of L^T.  kept and sweeps (batch ints each: kept count, Jacobi sweeps
  * used) may be NULL.  Stream-ordered; returns LRFG_EINVAL for n outside
- * [1, 64], c < 1, negative or NaN tol or null G/S. */
+ * [1, 128], c < 1, negative or NaN tol or null G/S. */
 int lrfg_gram_cut(int n, int c, const double* G, int batch, double tol, double* S, int* kept, int* sweeps,
                   void* stream);
 

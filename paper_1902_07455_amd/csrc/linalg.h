@@ -23,10 +23,11 @@ struct Gemm {
   int batch = 1;
   int prec = 0;  // lrfg_precision: FP64, or FP32 / BF16 inputs with FP32 accumulation
   // Batch index map: matrix t of the batch reads A at
-  // (t / adiv) sA + (t % amod) sA2 and B at (t / bdiv) sB + (t % bmod) sB2
-  // (a modulus of 0 drops that term); C is always at t sC.
-  int adiv = 1, amod = 0, bdiv = 1, bmod = 0;
-  long long sA2 = 0, sB2 = 0;
+  // (t / adiv) sA + (t % amod) sA2, B at (t / bdiv) sB + (t % bmod) sB2 and
+  // writes C at (t / cdiv) sC + (t % cmod) sC2 (a modulus of 0 drops that
+  // term; the defaults give t sA, t sB, t sC).
+  int adiv = 1, amod = 0, bdiv = 1, bmod = 0, cdiv = 1, cmod = 0;
+  long long sA2 = 0, sB2 = 0, sC2 = 0;
 };
 
 // The batch map as the kernels receive it; t = tbase + the launch's batch index.
@@ -34,6 +35,11 @@ struct BatchMap {
   long long tbase;
   int adiv, amod, bdiv, bmod;
   long long sA2, sB2;
+  int cdiv, cmod;
+  long long sC2;
+  __host__ __device__ long long c_off(long long t, long long sC) const {
+    return (t / cdiv) * sC + (cmod > 0 ? (t % cmod) * sC2 : 0);
+  }
   __host__ __device__ long long a_off(long long t, long long sA) const {
     return (t / adiv) * sA + (amod > 0 ? (t % amod) * sA2 : 0);
   }
@@ -54,10 +60,13 @@ size_t dot_rows_scratch(long long n, int batch);
 int dot_rows(long long n, const double* x, long long sx, int xdiv, const double* y, long long sy, double* out,
              int batch, double* scratch, size_t scratch_doubles, hipStream_t s);
 
-// Batched symmetric eigendecomposition, n <= kMaxEig: A_b (n x n, row-major,
+// Batched symmetric eigendecomposition, n <= kMaxSyevj: A_b (n x n, row-major,
 // leading dimension lda, batch stride sA) -> eigenvalues W_b (descending)
 // and eigenvectors V_b (column j = eigenvector j, row-major n x n).
-constexpr int kMaxEig = 64;
+constexpr int kMaxSyevj = 64;
+// Largest matrix of the truncation's small factorisations (pchol_s,
+// cut_psd): the sketch size, i.e. rank cap plus oversampling.
+constexpr int kMaxEig = 128;
 int syevj(int n, const double* A, long long lda, long long sA, double* W, long long sW, double* V,
           long long sV, int batch, hipStream_t s);
 

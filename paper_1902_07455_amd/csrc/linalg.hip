@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + tg * sC + (long long)row * ldc + col;
+            double* c = C + bm.c_off(tg, sC) + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + tg * sC + (long long)row * ldc + col;
+            double* c = C + bm.c_off(tg, sC) + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -302,7 +302,8 @@ __global__ __launch_bounds__(256) void k_gemm_lp(int m, int n, int k, const doub
 // loads in flight, and adds the 8 group sums in a fixed order.
 __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit, int batch,
                                                        const double* __restrict__ part, double* __restrict__ C,
-                                                       long long ldc, long long sC, double alpha, double beta) {
+                                                       long long ldc, long long sC, double alpha, double beta,
+                                                       BatchMap bm) {
   __shared__ double red[8][33];
   const long long mn = (long long)m * n;
   const long long tot = (long long)batch * mn;
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
                        ((red[4][o] + red[5][o]) + (red[6][o] + red[7][o]));
     const long long bt = e / mn, idx = e - bt * mn;
     const int row = (int)(idx / n), col = (int)(idx - (idx / n) * n);
-    double* c = C + bt * sC + (long long)row * ldc + col;
+    double* c = C + bm.c_off(bm.tbase + bt, sC) + (long long)row * ldc + col;
     *c = (beta == 0.0) ? alpha * sum : alpha * sum + beta * (*c);
   }
 }
@@ -908,6 +909,314 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
   }
 }
 
+// ---------------------------------------------------------------- n <= 128
+// The factorisations above keep G, the factor and Z (or the Jacobi columns)
+// as separate n x n arrays in LDS, which caps n at 64.  Sketch sizes up to
+// 128 (rank caps up to about 118) use the forms below, which keep one
+// n x n array: row perm[k] of G is read only at the step that takes perm[k]
+// as pivot, so the factor row k is written over it; and since row k of the
+// factor vanishes at the indices chosen before step k while z_k (the k-th
+// column of P R^-1) vanishes at the indices not yet chosen, z_k is stored
+// in the same row at the chosen indices (the two supports meet only at the
+// pivot, where z_k = 1 / L[k][p] is stored and L[k][p] is not needed again).
+
+constexpr int kBigN = 128;
+
+// Maximum of a 32-bit key over the wave with ties impossible: the low 7
+// bits carry 127 - index.
+__device__ inline int pivot_of(unsigned key) { return 127 - (int)(key & 127u); }
+
+// Rank-revealing pivoted Cholesky of the PSD n x n matrix in A (LDS, row
+// stride ld), 64 < n <= 128, by one wave: lane l owns indices l and l + 64.
+// The pivot rule, threshold and left-looking row formation are those of
+// pchol_wave.  On return row perm[k] (k < r) holds the factor row k; with
+// WITHZ, at the indices chosen at steps <= k it holds z_k instead.
+// kch[j] = the step at which index j was taken (n if never).
+template <bool WITHZ>
+__device__ int pchol_wave_big(int n, double* __restrict__ A, int ld, int* __restrict__ perm,
+                              int* __restrict__ kch, double tau) {
+  constexpr int CH = 8;
+  const int lane = threadIdx.x & 63;
+  const int j0 = lane, j1 = lane + 64;
+  const bool v0 = j0 < n, v1 = j1 < n;
+  const int jc0 = v0 ? j0 : n - 1, jc1 = v1 ? j1 : n - 1;  // loads of absent indices stay in range
+  double dg0 = v0 ? A[j0 * ld + j0] : 0.0, dg1 = v1 ? A[j1 * ld + j1] : 0.0;
+  const double d0 = __longlong_as_double(
+      (long long)wave_max_u64((unsigned long long)__double_as_longlong(fmax(fmax(dg0, dg1), 0.0))));
+  const double rel = d0 > 0.0 ? 1.0 / d0 : 0.0;
+  bool ch0 = !v0, ch1 = !v1;
+  int k0 = n, k1 = n;
+  int r = n;
+  for (int k = 0; k < n; ++k) {
+    const unsigned q0 = ch0 ? 0u
+                            : ((__float_as_uint((float)(fmax(dg0, 0.0) * rel)) & ~127u) | (unsigned)(127 - j0));
+    const unsigned q1 = ch1 ? 0u
+                            : ((__float_as_uint((float)(fmax(dg1, 0.0) * rel)) & ~127u) | (unsigned)(127 - j1));
+    const unsigned key = wave_max_u32(q0 > q1 ? q0 : q1);
+    const int p = pivot_of(key);
+    const int pl = p & 63;
+    const double b0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dg0), pl),
+                                       __builtin_amdgcn_readlane(__double2loint(dg0), pl));
+    const double b1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dg1), pl),
+                                       __builtin_amdgcn_readlane(__double2loint(dg1), pl));
+    const double best = key == 0u ? 0.0 : (p < 64 ? b0 : b1);
+    if (!(best > tau * d0) || !(best > 0.0)) {
+      r = k;
+      break;
+    }
+    const double inv = rsq_nr2(best);
+    double s0 = A[p * ld + jc0], s1 = A[p * ld + jc1];
+    double a0 = 0.0, a1 = 0.0;
+    for (int c = 0; c * CH < k; ++c) {
+      int pm[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) pm[i] = perm[c * CH + i];
+      double lp[CH], w0[CH], w1[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        lp[i] = c * CH + i < k ? A[pm[i] * ld + p] : 0.0;
+        w0[i] = A[pm[i] * ld + jc0];
+        w1[i] = A[pm[i] * ld + jc1];
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int m = c * CH + i;
+        if (WITHZ) {
+          // the stored entry is z_m at indices taken at steps <= m
+          if (m >= k0) a0 = fma(lp[i], w0[i], a0); else s0 = fma(-lp[i], w0[i], s0);
+          if (m >= k1) a1 = fma(lp[i], w1[i], a1); else s1 = fma(-lp[i], w1[i], s1);
+        } else {
+          s0 = fma(-lp[i], w0[i], s0);
+          s1 = fma(-lp[i], w1[i], s1);
+        }
+      }
+    }
+    const double l0 = ch0 ? 0.0 : s0 * inv, l1 = ch1 ? 0.0 : s1 * inv;
+    double o0 = l0, o1 = l1;
+    if (WITHZ) {
+      o0 = j0 == p ? inv : (ch0 ? -a0 * inv : l0);
+      o1 = j1 == p ? inv : (ch1 ? -a1 * inv : l1);
+    }
+    if (v0) A[p * ld + j0] = o0;
+    if (v1) A[p * ld + j1] = o1;
+    dg0 = fma(-l0, l0, dg0);
+    dg1 = fma(-l1, l1, dg1);
+    if (j0 == p) { ch0 = true; k0 = k; }
+    if (j1 == p) { ch1 = true; k1 = k; }
+    if (lane == 0) perm[k] = p;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (v0) kch[j0] = k0;
+  if (v1) kch[j1] = k1;
+  return r;
+}
+
+// S = P R^-1 (n x n, 64 < n <= 128) of the pivoted Cholesky factor of G;
+// see k_pchol_s.
+__global__ __launch_bounds__(256) void k_pchol_s_big(int n, const double* __restrict__ Gg, long long sG, double tau,
+                                                     double* __restrict__ Sg, long long sS,
+                                                     int* __restrict__ rank_out) {
+  extern __shared__ double sm[];
+  double* A = sm;
+  __shared__ int perm[kBigN];
+  __shared__ int kch[kBigN];
+  __shared__ int rank_s;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* G = Gg + b * sG;
+  for (int e = tid; e < n * n; e += 256) A[e] = G[e];
+  if (tid < kBigN) perm[tid] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    const int rr = pchol_wave_big<true>(n, A, n, perm, kch, tau);
+    if (tid == 0) rank_s = rr;
+  }
+  __syncthreads();
+  const int r = rank_s;
+  double* S = Sg + b * sS;
+  // S[o][k] = z_k[o], stored in row perm[k] at the indices taken by step k
+  for (int e = tid; e < n * n; e += 256) {
+    const int o = e / n, k = e - (e / n) * n;
+    S[e] = (k < r && kch[o] <= k) ? A[perm[k] * n + o] : 0.0;
+  }
+  if (tid == 0 && rank_out != nullptr) rank_out[b] = r;
+}
+
+// Truncation basis of a PSD Gram matrix G (n x n, 64 < n <= 128): the
+// steps of k_cut_psd (scaling, pivoted Cholesky, one-sided Jacobi on the
+// factor's rows, selection) with the factor formed in place and moved to
+// pivot order before the Jacobi.  NT = 16 lanes x NT / 16 column pairs
+// (2 NT / 16 >= n), rows padded to NP = 16 NE >= n.
+template <int NT, int NE>
+__global__ __launch_bounds__(NT) void k_cut_psd_big(int n, int c, const double* __restrict__ Gg, long long sG,
+                                                     double tau, double eps, double tol2, double floor_rel,
+                                                     double* __restrict__ Sg, long long sS,
+                                                     int* __restrict__ kept_out, int* __restrict__ sweeps_out) {
+  constexpr int LPG = 16;
+  constexpr int NP = LPG * NE;
+  constexpr int PER = (kBigN * NP + NT - 1) / NT;  // row elements per thread in the reordering
+  extern __shared__ double sm[];
+  double* W = sm;  // n rows of stride NP
+  __shared__ int perm[kBigN];
+  __shared__ int kch[kBigN];
+  __shared__ int order[kBigN];
+  __shared__ double lam[kBigN];
+  __shared__ int flags[kCutSweeps];
+  __shared__ int rank_s;
+  __shared__ double trace_s;
+  __shared__ int kept_s;
+  __shared__ int scale_s;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* G = Gg + b * sG;
+  for (int e = tid; e < n * NP; e += NT) {
+    const int i = e / NP, j = e - (e / NP) * NP;
+    W[e] = j < n ? G[i * n + j] : 0.0;
+  }
+  if (tid < kCutSweeps) flags[tid] = 0;
+  if (tid < kBigN) perm[tid] = 0;
+  __syncthreads();
+  // scale by a power of two near the largest diagonal entry (see k_cut_psd)
+  if (tid < 64) {
+    double dm = 0.0;
+    for (int i = tid; i < n; i += 64) dm = fmax(dm, fmax(W[i * NP + i], 0.0));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    if (tid == 0) scale_s = dm > 0.0 ? __builtin_amdgcn_frexp_exp(dm) : 0;
+  }
+  __syncthreads();
+  {
+    const int sx = scale_s;
+    for (int e = tid; e < n * NP; e += NT) W[e] = __builtin_amdgcn_ldexp(W[e], -sx);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double t = 0.0;
+    for (int i = tid; i < n; i += 64) t += fmax(W[i * NP + i], 0.0);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (tid == 0) trace_s = t;
+    const int rr = pchol_wave_big<false>(n, W, NP, perm, kch, tau);
+    if (tid == 0) rank_s = rr;
+  }
+  __syncthreads();
+  const int r = rank_s;
+  // factor row k (stored in row perm[k]) -> row k; rows r.. become zero
+  {
+    double t[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT;
+      const int k = e / NP, i = e - (e / NP) * NP;
+      t[u] = (k < r) ? W[perm[k] * NP + i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT;
+      if (e < n * NP) W[e] = t[u];
+    }
+  }
+  __syncthreads();
+  // one-sided Jacobi on rows 0..r-1 of W, as in k_cut_psd
+  const int sub = tid % LPG, grp = tid / LPG;
+  const int m = r + (r & 1), np = m / 2;
+  const double eps2 = (eps * n) * (eps * n);
+  const double big2 = eps * n;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < kCutSweeps && r > 1; ++sweep) {
+    sweeps = sweep + 1;
+    int u0 = grp - 1, u1 = m - 2 - grp;
+    for (int step = 0; step < m - 1; ++step) {
+      const int t0 = grp == 0 ? 0 : 1 + u0, t1 = 1 + u1;
+      u0 = u0 + 1 == m - 1 ? 0 : u0 + 1;
+      u1 = u1 + 1 == m - 1 ? 0 : u1 + 1;
+      if (grp < np) {
+        const int p = t0 < t1 ? t0 : t1, q = t0 < t1 ? t1 : t0;
+        if (q < r) {
+          double wp[NE], wq[NE];
+          double a = 0.0, bb = 0.0, gg = 0.0;
+#pragma unroll
+          for (int t = 0; t < NE; ++t) {
+            const int i = sub + LPG * t;
+            wp[t] = W[p * NP + i];
+            wq[t] = W[q * NP + i];
+            a += wp[t] * wp[t];
+            bb += wq[t] * wq[t];
+            gg += wp[t] * wq[t];
+          }
+          sum_lanes3<LPG>(a, bb, gg);
+          if (gg * gg > eps2 * a * bb) {
+            const double tau_ = bb - a, rho = 2.0 * gg;
+            const double w = fma(tau_, tau_, rho * rho);
+            const double h = w * __builtin_amdgcn_rsq(w);
+            const double t = (tau_ >= 0.0 ? rho : -rho) * __builtin_amdgcn_rcp(fabs(tau_) + h);
+            const double cs = rsq_nr(1.0 + t * t), sn = t * cs;
+#pragma unroll
+            for (int tt = 0; tt < NE; ++tt) {
+              const int i = sub + LPG * tt;
+              W[p * NP + i] = cs * wp[tt] - sn * wq[tt];
+              W[q * NP + i] = sn * wp[tt] + cs * wq[tt];
+            }
+            if (sub == 0 && gg * gg > big2 * a * bb) flags[sweep] = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!flags[sweep]) break;
+  }
+  for (int j = tid; j < r; j += NT) {
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) v += W[j * NP + i] * W[j * NP + i];
+    lam[j] = v;
+  }
+  __syncthreads();
+  for (int j = tid; j < r; j += NT) {
+    const double v = lam[j];
+    int rank = 0;
+    for (int i = 0; i < r; ++i) rank += (lam[i] > v) || (lam[i] == v && i < j);
+    order[rank] = j;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int j = 0; j < r; ++j) sum += lam[j];
+    int kept = c < r ? c : r;
+    const double l0 = r > 0 ? lam[order[0]] : 0.0;
+    while (kept > 0 && !(lam[order[kept - 1]] > floor_rel * l0 && lam[order[kept - 1]] > 0.0)) --kept;
+    if (tol2 > 0.0) {
+      const double total = trace_s;
+      double tail = fmax(total - sum, 0.0);
+      for (int j = r - 1; j >= kept; --j) tail += lam[order[j]];
+      while (kept > 1) {
+        const double t2 = tail + lam[order[kept - 1]];
+        if (t2 <= tol2 * total) {
+          tail = t2;
+          --kept;
+        } else {
+          break;
+        }
+      }
+    }
+    kept_s = kept;
+    if (kept_out != nullptr) kept_out[b] = kept;
+    if (sweeps_out != nullptr) sweeps_out[b] = sweeps;
+  }
+  __syncthreads();
+  const int kept = kept_s;
+  double* S = Sg + b * sS;
+  for (int e = tid; e < n * c; e += NT) {
+    const int i = e / c, j = e - (e / c) * c;
+    double v = 0.0;
+    if (j < kept) {
+      const int col = order[j];
+      v = W[col * NP + i] / sqrt(lam[col]);
+    }
+    S[e] = v;
+  }
+}
+
 }  // namespace
 
 size_t gemm_scratch_doubles(const Gemm& g) {
@@ -942,7 +1251,7 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   for (int b0 = 0; b0 < g.batch; b0 += chunk) {
     Gemm c = g;
     c.batch = std::min(chunk, g.batch - b0);
-    const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2};
+    const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2, g.cdiv, g.cmod, g.sC2};
     const int gtm = c.prec != 0 ? BM : lay.tm(), gtn = c.prec != 0 ? BN : lay.tn();
     dim3 grid(ceil_div(c.n, gtn), ceil_div(c.m, gtm), c.batch * ks);
 #define LRFG_GEMM_F64(TA, TB, WM, WN)                                                                         \
@@ -977,7 +1286,7 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
       const long long tot = (long long)c.batch * c.m * c.n;
       const int gr = (int)((tot + 31) / 32);
       hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, c.m, c.n, ks, c.batch, (const double*)part,
-                         c.C + (long long)b0 * c.sC, c.ldc, c.sC, c.alpha, c.beta);
+                         c.C, c.ldc, c.sC, c.alpha, c.beta, bm);
       LRFG_LAUNCHED();
     }
   }
@@ -1029,23 +1338,24 @@ int dot_rows(long long n, const double* x, long long sx, int xdiv, const double*
                      scratch);
   LRFG_LAUNCHED();
   const int gr = (batch + 31) / 32;
+  const BatchMap bm{0, 1, 0, 1, 0, 0, 0, 1, 0, 0};
   hipLaunchKernelGGL(k_splitk_reduce, dim3(gr), dim3(256), 0, s, 1, 1, nblk, batch, (const double*)scratch, out,
-                     (long long)1, (long long)1, 1.0, 0.0);
+                     (long long)1, (long long)1, 1.0, 0.0, bm);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
 int syevj(int n, const double* A, long long lda, long long sA, double* W, long long sW, double* V, long long sV,
           int batch, hipStream_t s) {
-  if (n < 1 || n > kMaxEig) {
-    set_error("syevj: n = %d outside [1, %d]", n, kMaxEig);
+  if (n < 1 || n > kMaxSyevj) {
+    set_error("syevj: n = %d outside [1, %d]", n, kMaxSyevj);
     return LRFG_EINVAL;
   }
   if (batch <= 0) return LRFG_OK;
   const size_t shm = sizeof(double) * 2 * n * n;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_syevj),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)(sizeof(double) * 2 * kMaxEig * kMaxEig));
+                                                     (int)(sizeof(double) * 2 * kMaxSyevj * kMaxSyevj));
   (void)attr;
   ProfScope ps_("syevj", s);
   hipLaunchKernelGGL(k_syevj, dim3(batch), dim3(256), shm, s, n, A, lda, sA, W, sW, V, sV, 20);
@@ -1060,12 +1370,22 @@ int pchol_s(int n, const double* G, long long sG, double tau, double* S, long lo
     return LRFG_EINVAL;
   }
   if (batch <= 0) return LRFG_OK;
+  ProfScope ps_("pchol", s);
+  if (n > 64) {
+    static const hipError_t attr_big = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s_big),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           (int)(sizeof(double) * kMaxEig * kMaxEig));
+    (void)attr_big;
+    hipLaunchKernelGGL(k_pchol_s_big, dim3(batch), dim3(256), sizeof(double) * n * n, s, n, G, sG, tau, S, sS,
+                       rank);
+    LRFG_LAUNCHED();
+    return LRFG_OK;
+  }
   const size_t shm = sizeof(double) * 3 * n * n;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s<64>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)(sizeof(double) * 3 * kMaxEig * kMaxEig));
+                                                     (int)(sizeof(double) * 3 * 64 * 64));
   (void)attr;
-  ProfScope ps_("pchol", s);
   if (n <= 32)
     hipLaunchKernelGGL(k_pchol_s<32>, dim3(batch), dim3(256), shm, s, n, G, sG, tau, S, sS, rank);
   else
@@ -1081,6 +1401,26 @@ int cut_psd(int n, int c, const double* G, long long sG, double tol2, double* S,
     return LRFG_EINVAL;
   }
   if (batch <= 0) return LRFG_OK;
+  if (n > 64) {
+    ProfScope ps_("cut", s);
+#define LRFG_CUT_BIG(NT, NE)                                                                                 \
+  do {                                                                                                       \
+    static const hipError_t attr = hipFuncSetAttribute(                                                      \
+        reinterpret_cast<const void*>(&k_cut_psd_big<NT, NE>), hipFuncAttributeMaxDynamicSharedMemorySize,   \
+        (int)(sizeof(double) * kMaxEig * 16 * NE));                                                          \
+    (void)attr;                                                                                              \
+    hipLaunchKernelGGL((k_cut_psd_big<NT, NE>), dim3(batch), dim3(NT), sizeof(double) * n * 16 * NE, s, n, c, \
+                       G, sG, kCutTau, kCutEps, tol2, kCutFloor, S, sS, kept, sweeps);                       \
+  } while (0)
+    // 16 lanes per column pair; rows padded to 96 or 128
+    if (n <= 96)
+      LRFG_CUT_BIG(768, 6);
+    else
+      LRFG_CUT_BIG(1024, 8);
+#undef LRFG_CUT_BIG
+    LRFG_LAUNCHED();
+    return LRFG_OK;
+  }
   const int np_ = n <= 16 ? 16 : (n <= 32 ? 32 : 64);  // padded column length of the launched variant
   const size_t shm = sizeof(double) * (2 * n * n + (size_t)n * np_);
   ProfScope ps_("cut", s);
@@ -1088,7 +1428,7 @@ int cut_psd(int n, int c, const double* G, long long sG, double tol2, double* S,
   do {                                                                                                       \
     static const hipError_t attr = hipFuncSetAttribute(                                                      \
         reinterpret_cast<const void*>(&k_cut_psd<NT, NE, LPG>), hipFuncAttributeMaxDynamicSharedMemorySize,  \
-        (int)(sizeof(double) * 3 * kMaxEig * kMaxEig));                                                      \
+        (int)(sizeof(double) * 3 * 64 * 64));                                                                \
     (void)attr;                                                                                              \
     hipLaunchKernelGGL((k_cut_psd<NT, NE, LPG>), dim3(batch), dim3(NT), shm, s, n, c, G, sG, kCutTau, kCutEps, \
                        tol2, kCutFloor, S, sS, kept, sweeps);                                                \

@@ -132,6 +132,20 @@ __global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, 
   }
 }
 
+// Restarts of a truncated PCG system from its best iterate before it is
+// declared stagnant.
+constexpr int kMaxRestarts = 3;
+
+// dst_e = src_e for the systems e whose bit is set in mask
+struct SysMask {
+  unsigned long long m[4];
+};
+__global__ void k_pick(double* __restrict__ dst, const double* __restrict__ src, SysMask mask, int nE) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nE && ((mask.m[e >> 6] >> (e & 63)) & 1ull)) dst[e] = src[e];
+}
+__device__ __host__ inline bool sys_bit(const SysMask& m, int e) { return (m.m[e >> 6] >> (e & 63)) & 1ull; }
+
 struct Ctx {
   LowRankPlan* pl;
   int d, nE;
@@ -201,14 +215,15 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   int rkr[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) rkr[j] = ra[j] * rc[j];
   if (d == 3) {
-    // the material truncation takes the middle carriage unformed, so it is
-    // held for the nE products of the energy form and A_H only
+    // the middle carriage of a (.) D_alpha v is never formed (the material
+    // truncation, the energy form and A_H contract a's and D_alpha v's
+    // middle carriages in turn), so only the first and last are held
     C.kr.d = 3;
     for (int j = 0; j < 3; ++j) C.kr.N[j] = pl->N[j];
     for (int j = 0; j < 4; ++j) C.kr.r[j] = rkr[j];
     for (int j = 0; j < 3; ++j) {
       C.kr.s[j] = C.kr.size(j);
-      C.kr.c[j] = ar.take<double>((size_t)C.kr.s[j] * (j == 1 ? nE : d * nE));
+      C.kr.c[j] = j == 1 ? nullptr : ar.take<double>((size_t)C.kr.s[j] * d * nE);
     }
   } else {
     C.kr = tt_alloc(ar, d, pl->N, rkr, d * nE);
@@ -265,8 +280,13 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   C.mones = ar.take<double>(nE);
   // dot scratch: largest pair (kr, c) or (a, a); the A_H cross terms take
   // up to 3 pairs per system
-  size_t dn = tt_dot_scratch(C.kr, C.z, 3 * nE);
+  size_t dn = tt_dot_scratch(C.z, C.z, 3 * nE);
+  dn = std::max(dn, tt_dot_scratch(C.a, C.z, nE));
   dn = std::max(dn, tt_dot_scratch(C.a, C.a, nE));
+  if (d == 3)
+    dn = std::max(dn, dot_rows_scratch((long long)rkr[1] * pl->N[1] * rc[2], nE));  // kr_dot
+  else
+    dn = std::max(dn, tt_dot_scratch(C.kr, C.z, 3 * nE));
   C.dscr_n = dn;
   C.dscr = ar.take<double>(dn);
   return LRFG_OK;
@@ -370,6 +390,23 @@ int axpby(Ctx& C, const TTB& x, const TTB& y, const double* cb, TTB& out) {
 
 int dot(Ctx& C, const TTB& x, const TTB& y, double* out) { return tt_dot(x, y, out, C.dscr, C.nE, C.s); }
 
+// The middle carriage of a (.) g (d = 3) as its factors: system e reads
+// coefficient train e % nE (one train shared, or one per system) and g's
+// middle carriage e.
+KrMid kr_mid(const Ctx& C, const TTB& g) {
+  KrMid km;
+  km.a = C.a.c[1];
+  km.sa = C.a.s[1];
+  km.ra0 = C.a.r[1];
+  km.ra1 = C.a.r[2];
+  km.amod = C.nE;
+  km.g = g.c[1];
+  km.sg = g.s[1];
+  km.rg0 = g.r[1];
+  km.rg1 = g.r[2];
+  return km;
+}
+
 int read_dev(Ctx& C, const double* dptr, double* host, int n) {
   LRFG_HIP(hipMemcpyAsync(host, dptr, sizeof(double) * n, hipMemcpyDeviceToHost, C.s));
   LRFG_HIP(hipStreamSynchronize(C.s));
@@ -389,6 +426,11 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
   }
   pl->ra = p.coeff_rank > 0 ? p.coeff_rank : 16;
   pl->over = p.oversample > 0 ? p.oversample : 10;
+  if (pl->ra > kMaxCoeffRank) {
+    set_error("coeff_rank %d exceeds the supported %d", pl->ra, kMaxCoeffRank);
+    delete pl;
+    return LRFG_EUNSUPPORTED;
+  }
   if (p.d == 3) {
     pl->c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1] * p.N[2]));
     pl->c[2] = std::min(p.rank_cap, std::min(p.N[2], p.N[0] * p.N[1]));
@@ -476,11 +518,11 @@ int load_coeff(Ctx& C, const lrfg_coeff& ac, int e, int* rk) {
       // stage host factors through the product buffer (not yet in use)
       size_t n = R;
       for (int j = 0; j < d; ++j) n += (size_t)R * pl->N[j];
-      if (n > (size_t)C.kr.size(1) * C.nE) {
+      if (n > (size_t)C.comb.size(0) * 2 * C.nE) {
         set_error("coefficient staging too small");
         return LRFG_EWORKSPACE;
       }
-      double* dstage = C.kr.c[1];
+      double* dstage = C.comb.c[0];
       LRFG_HIP(hipMemcpyAsync(dstage, w, sizeof(double) * R, hipMemcpyHostToDevice, s));
       size_t off = R;
       const double* df[3];
@@ -570,6 +612,20 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   int rk[4] = {0, 0, 0, 0};
   for (int b = 0; b < nB; ++b) LRFG_TRY(load_coeff(C, acs[b], na == 1 ? 0 : b * nEp, rk));
   for (int j = 1; j < d; ++j) C.a.r[j] = rk[j];
+  // admissibility (the coefficient must be positive and finite at every
+  // grid point, as for the full grid): truncated or user-given factors can
+  // undershoot, which would make the operator indefinite
+  for (int b = 0; b < nB; ++b) {
+    const double* cores[3];
+    for (int j = 0; j < d; ++j) cores[j] = C.a.c[j] + (long long)(na == 1 ? 0 : b * nEp) * C.a.s[j];
+    double amin = 0.0;
+    long long nonfin = 0;
+    LRFG_TRY(tt_coeff_check(d, pl->N, rk, cores, C.dots, s, &amin, &nonfin));
+    if (nonfin > 0 || !(amin > 0.0)) {
+      set_error("coefficient %d is not admissible: minimum %.6g, %lld non-finite values", b, amin, nonfin);
+      return LRFG_ECOEFF;
+    }
+  }
   if (na > 1) {
     // every field of microstructure b reads its own copy of the train
     for (int j = 0; j < d; ++j) C.a.s[j] = C.a.size(j);
@@ -658,8 +714,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(tt_dot(C.a, g, C.dots, C.dscr, nE, s));
       LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
       for (int e = 0; e < nE; ++e) en[e] += 2.0 * Ev(e, al) * v[e] / Ntot;
-      LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-      LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s));
+      if (d == 3) {
+        LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s, 1));
+        const KrMid km = kr_mid(C, g);
+        LRFG_TRY(C.rd.kr_dot(C.kr, km, g, C.dots, C.dscr, C.dscr_n, nE, s));
+      } else {
+        LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
+        LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s));
+      }
       LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
       for (int e = 0; e < nE; ++e) en[e] += v[e] / Ntot;
     }
@@ -671,6 +733,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   std::vector<double> hist((size_t)nE * maxit, 0.0);
   std::vector<int> iters(nE, 0), status(nE, LRFG_OK);
   const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  // truncated PCG: restarts from the best iterate with the true residual
+  // before a system is declared stagnant
+  const int max_restarts = (P.solver == LRFG_SOLVER_PCG) ? kMaxRestarts : 0;
   // kept ranks of the latest x truncation (bond 1 then bond 2, per system),
   // copied with the residual read, and those of each system's kept iterate
   std::vector<int> kx(2 * nE, 0), kbest(2 * nE, 0);
@@ -690,9 +755,10 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   // iteration counts to iters, else the counts are added to iters.
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& res0,
                    std::vector<int>& st, bool record) -> int {
-    std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0);
+    std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
     std::vector<double> best(nE, INFINITY), zzh(nE);
     for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
+    LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
     LRFG_TRY(tt_zero(C.xr, 2 * nE, s));
     LRFG_TRY(tt_zero(C.xb, nE, s));
     LRFG_TRY(upload_done(hdone));
@@ -756,6 +822,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
       bool changed = false;
       unsigned long long improved[4] = {0, 0, 0, 0};  // systems whose x becomes the best iterate
+      SysMask restart{{0, 0, 0, 0}};                  // systems restarted from their best iterate
       for (int e = 0; e < nE; ++e) {
         if (hdone[e]) continue;
         const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
@@ -775,6 +842,12 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
           hdone[e] = 1;
           changed = true;
+        } else if (since_best[e] >= patience && restarts[e] < max_restarts) {
+          // the recursive residual has drifted from b - K x under truncation
+          // (Sec. 3.3): restart from the best iterate
+          ++restarts[e];
+          since_best[e] = 0;
+          restart.m[e >> 6] |= 1ull << (e & 63);
         } else if (since_best[e] >= patience) {
           hdone[e] = 1;  // stagnation: the residual failed to decrease
           changed = true;
@@ -783,6 +856,26 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       }
       LRFG_TRY(tt_copy_systems(C.x, C.xb, nE, improved, s));
       if (changed) LRFG_TRY(upload_done(hdone));
+      if (restart.m[0] | restart.m[1] | restart.m[2] | restart.m[3]) {
+        // residual replacement: x = x_best, r = T(b - K x), z = T(P~^-1 r),
+        // p = z, rho = (r, z) for the restarted systems (the others keep
+        // their state: the batched steps run for every system and are
+        // copied into the restarted ones only)
+        LRFG_TRY(apply_K(C, C.xb, C.tmp));
+        LRFG_TRY(axpby(C, C.b, C.tmp, C.mones, C.z));
+        LRFG_TRY(tt_copy_systems(C.z, C.r, nE, restart.m, s));
+        LRFG_TRY(tt_copy_systems(C.xb, C.x, nE, restart.m, s));
+        LRFG_TRY(apply_P(C, C.r, C.z));
+        LRFG_TRY(tt_copy_systems(C.z, C.p, nE, restart.m, s));
+        LRFG_TRY(dot(C, C.r, C.z, C.dots));
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kMaxSystems), 0, s, C.rho, (const double*)C.dots, restart, nE);
+        LRFG_LAUNCHED();
+        // the best residual becomes the true one of the best iterate
+        LRFG_TRY(dot(C, C.z, C.z, C.zz));
+        LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+        for (int e = 0; e < nE; ++e)
+          if (sys_bit(restart, e)) best[e] = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+      }
     }
     for (int e = 0; e < nE; ++e) {
       if (!hdone[e]) st[e] = LRFG_NOT_CONVERGED;
@@ -896,11 +989,35 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     std::vector<double> v(nE);
     LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
     for (int e = 0; e < nE; ++e) m1[(size_t)e * d + al] = v[e] / Ntot;
-    // m2: <a (.) g_i, g_j> for every pair within each microstructure, one pass
-    LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-    LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s, nEp));
+    // m2: <a (.) g_i, g_j> for every pair within each microstructure
     std::vector<double> w2((size_t)nE * nEp);
-    LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nEp));
+    if (d == 3) {
+      // per microstructure b and field j: the nEp systems of b against g_j
+      LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s, 1));
+      std::vector<double> wj(nEp);
+      for (int b = 0; b < nB; ++b) {
+        TTB kb = C.kr, gb = g, gj = g;
+        for (int j = 0; j < d; ++j) {
+          kb.c[j] = j == 1 ? nullptr : C.kr.c[j] + (long long)b * nEp * C.kr.s[j];
+          gb.c[j] = g.c[j] + (long long)b * nEp * g.s[j];
+        }
+        KrMid km = kr_mid(C, gb);
+        km.a = C.a.c[1] + (long long)(na == 1 ? 0 : b * nEp) * C.a.s[1];
+        for (int j = 0; j < nEp; ++j) {
+          for (int q = 0; q < d; ++q) {
+            gj.c[q] = g.c[q] + (long long)(b * nEp + j) * g.s[q];
+            gj.s[q] = 0;
+          }
+          LRFG_TRY(C.rd.kr_dot(kb, km, gj, C.dots, C.dscr, C.dscr_n, nEp, s));
+          LRFG_TRY(read_dev(C, C.dots, wj.data(), nEp));
+          for (int i = 0; i < nEp; ++i) w2[(size_t)(b * nEp + i) * nEp + j] = wj[i];
+        }
+      }
+    } else {
+      LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
+      LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s, nEp));
+      LRFG_TRY(read_dev(C, C.dots, w2.data(), nE * nEp));
+    }
     for (size_t k = 0; k < w2.size(); ++k) m2[k * d + al] = w2[k] / Ntot;
   }
   // final ranks: those the truncation kept for each system's returned iterate
@@ -1005,6 +1122,7 @@ struct TkCtx {
   double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
   double *ones, *mones;
   double* stage;            // host CP coefficient staged on the device
+  double* wchk;             // admissibility check: U1 x_1 core
   int* done;
   int cap[3];
   int ra;
@@ -1095,6 +1213,7 @@ int tk_carve(Arena& ar, LowRankPlan* pl, int nE, TkCtx& C) {
   C.ones = ar.take<double>(nE);
   C.mones = ar.take<double>(nE);
   C.stage = ar.take<double>((size_t)pl->ra * (1 + N[0] + N[1] + N[2]));
+  C.wchk = ar.take<double>((size_t)N[0] * pl->ra * pl->ra);
   size_t dn = tk_dot_scratch(C.kr, C.z, 3 * nE);  // A_H cross terms: up to 3 pairs per system
   dn = std::max(dn, tk_dot_scratch(C.a, C.a, nE));
   dn = std::max(dn, tk_dot_scratch(C.z, C.z, nE));
@@ -1280,6 +1399,17 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     return LRFG_EUNSUPPORTED;
   }
   for (int j = 0; j < 3; ++j) C.a.r[j] = ra3[j];
+  {
+    // admissibility: positive and finite at every grid point
+    double amin = 0.0;
+    long long nonfin = 0;
+    const double* U[3] = {C.a.U[0], C.a.U[1], C.a.U[2]};
+    LRFG_TRY(tucker_coeff_check(pl->N, ra3, C.a.G, U, C.wchk, C.dots, s, &amin, &nonfin));
+    if (nonfin > 0 || !(amin > 0.0)) {
+      set_error("coefficient is not admissible: minimum %.6g, %lld non-finite values", amin, nonfin);
+      return LRFG_ECOEFF;
+    }
+  }
   for (int j = 0; j < 3; ++j) {
     C.kr.r[j] = ra3[j] * C.xr.r[j];
     C.kr.sU[j] = C.kr.usize(j);
@@ -1361,6 +1491,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
   std::vector<double> hist((size_t)nE * maxit, 0.0), res0(nE, 0.0);
   std::vector<int> iters(nE, 0), status(nE, LRFG_OK);
   const int patience = (P.solver == LRFG_SOLVER_PCG) ? 5 : 1;
+  const int max_restarts = (P.solver == LRFG_SOLVER_PCG) ? kMaxRestarts : 0;
   // kept mode ranks of the latest x truncation (mode j of system e at
   // kx[j nE + e]) and those of each system's kept iterate
   std::vector<int> kx(3 * nE, 0), kbest(3 * nE, 0);
@@ -1378,9 +1509,10 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
   // the rounder's current precision; the same contract as the train path's.
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& r0,
                    std::vector<int>& st, bool record) -> int {
-    std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0);
+    std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
     std::vector<double> best(nE, INFINITY), zzh(nE);
     for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
+    LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
     LRFG_TRY(tk_zero(C.xr, 2 * nE, s));
     LRFG_TRY(tk_zero(C.xb, nE, s));
     LRFG_TRY(upload_done(hdone));
@@ -1440,6 +1572,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
       }
       LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
       bool changed = false;
+      SysMask restart{{0, 0, 0, 0}};
       for (int e = 0; e < nE; ++e) {
         if (hdone[e]) continue;
         const double res = std::sqrt(std::max(zzh[e], 0.0)) / r0[e];
@@ -1457,6 +1590,10 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
         if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
           hdone[e] = 1;
           changed = true;
+        } else if (since_best[e] >= patience && restarts[e] < max_restarts) {
+          ++restarts[e];  // restart from the best iterate (as in the train path)
+          since_best[e] = 0;
+          restart.m[e >> 6] |= 1ull << (e & 63);
         } else if (since_best[e] >= patience) {
           hdone[e] = 1;
           changed = true;
@@ -1464,6 +1601,27 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
         }
       }
       if (changed) LRFG_TRY(upload_done(hdone));
+      if (restart.m[0] | restart.m[1] | restart.m[2] | restart.m[3]) {
+        // residual replacement for the restarted systems: x = x_best,
+        // r = T(b - K x), z = T(P~^-1 r), p = z, rho = (r, z)
+        LRFG_TRY(tk_apply_K(C, C.xb, C.tmp));
+        LRFG_TRY(tk_axpby(C, C.b, C.tmp, C.mones, C.z));
+        for (int e = 0; e < nE; ++e)
+          if (sys_bit(restart, e)) {
+            LRFG_TRY(tk_copy_system(C.z, C.r, e, s));
+            LRFG_TRY(tk_copy_system(C.xb, C.x, e, s));
+          }
+        LRFG_TRY(tk_apply_P(C, C.r, C.z));
+        for (int e = 0; e < nE; ++e)
+          if (sys_bit(restart, e)) LRFG_TRY(tk_copy_system(C.z, C.p, e, s));
+        LRFG_TRY(tk_dot(C.r, C.z, C.dots, C.dscr, nE, s));
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kMaxSystems), 0, s, C.rho, (const double*)C.dots, restart, nE);
+        LRFG_LAUNCHED();
+        LRFG_TRY(tk_dot(C.z, C.z, C.zz, C.dscr, nE, s));
+        LRFG_TRY(tk_read(C, C.zz, zzh.data(), nE));
+        for (int e = 0; e < nE; ++e)
+          if (sys_bit(restart, e)) best[e] = std::sqrt(std::max(zzh[e], 0.0)) / r0[e];
+      }
     }
     for (int e = 0; e < nE; ++e) {
       if (!hdone[e]) st[e] = LRFG_NOT_CONVERGED;

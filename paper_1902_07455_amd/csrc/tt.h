@@ -73,6 +73,13 @@ struct Rounder {
   // systems (default: nE, the capacity it was carved for); with mid, the
   // middle carriage of `in` is mid's Hadamard product (in.c[1] unused)
   int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1, const KrMid* mid = nullptr);
+  // dots[e] = <a (.) x_e, y_e> for ns systems (d = 3, FP64) with the middle
+  // carriage of a (.) x unformed: kr holds the product's first and last
+  // carriages (tt_hadamard with skip = 1), mid its middle as factors (x's
+  // middle carriage as g); y may have stride 0 (one train for every
+  // system).  Uses the rounding buffers; dscr: dot_rows scratch.
+  int kr_dot(const TTB& kr, const KrMid& mid, const TTB& y, double* dots, double* dscr, size_t dscr_n, int ns,
+             hipStream_t s);
 };
 
 int tt_fill(double* p, long long n, double v, hipStream_t s);

@@ -147,56 +147,17 @@ __global__ void k_khatri_rao(const double* __restrict__ a, long long sa, int ra0
   }
 }
 
-// Second steps of the structured middle carriage X2 = a (.) g (one thread
-// per output, the ra terms of its sum in order; system s = blockIdx.y reads
-// coefficient train s % amod):
+// Second steps of the structured middle carriage X2 = a (.) g (system s
+// reads coefficient train s % amod):
 //   T2[s][i rg0 + k][n][l] = sum_j a[i][n][j] Z[s][j][k][n][l]
 //   X2'[s][p][n][j rg1 + m] = sum_i a[i][n][j] U[s][p][i][n][m]
-__global__ __launch_bounds__(256) void k_kr_t2(const double* __restrict__ a, long long sa, int amod, int ra0, int ra1,
-                                               int N, const double* __restrict__ Z, long long sz, int rg0, int l2,
-                                               double* __restrict__ T2, long long st) {
-  const int s = blockIdx.y;
-  const double* as = a + (long long)(s % amod) * sa;
-  const double* zs = Z + (long long)s * sz;
-  double* ts = T2 + (long long)s * st;
-  const int Q = rg0 * N * l2;  // (k, n, l) per j
-  const int per = ra0 * Q;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
-    const int i = idx / Q, q = idx - (idx / Q) * Q;
-    const int n = (q / l2) % N;
-    const double* ar = as + ((long long)i * N + n) * ra1;
-    double v = 0.0;
-    for (int j = 0; j < ra1; ++j) v = fma(ar[j], zs[(long long)j * Q + q], v);
-    ts[idx] = v;
-  }
-}
-__global__ __launch_bounds__(256) void k_kr_x2(const double* __restrict__ a, long long sa, int amod, int ra0, int ra1,
-                                               int N, const double* __restrict__ U, long long su, int rg1, int l1,
-                                               double* __restrict__ X, long long sx) {
-  const int s = blockIdx.y;
-  const double* as = a + (long long)(s % amod) * sa;
-  const double* us = U + (long long)s * su;
-  double* xs = X + (long long)s * sx;
-  const int per = l1 * N * ra1 * rg1;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per; idx += gridDim.x * blockDim.x) {
-    const int m = idx % rg1;
-    int r = idx / rg1;
-    const int j = r % ra1;
-    r /= ra1;
-    const int n = r % N, p = r / N;
-    const double* up = us + ((long long)p * ra0 * N + n) * rg1 + m;  // U[s][p][0][n][m]
-    double v = 0.0;
-    for (int i = 0; i < ra0; ++i) v = fma(as[((long long)i * N + n) * ra1 + j], up[(long long)i * N * rg1], v);
-    xs[idx] = v;
-  }
-}
-
-// The same two contractions with one block per (mode index n, train) and
-// every coefficient-rank term of one thread's column held in registers
-// (coefficient ranks up to RA): the slice a[:][n][:] is the same for the
-// whole block, so it is read through the scalar cache once per block rather
-// than by every thread, and a thread reads its Z (or U) column once and
-// writes all ra0 (or ra1) outputs of it; sums in the same order as above.
+// For coefficient ranks up to RA: one block per (mode index n, train) and
+// every coefficient-rank term of one thread's column held in registers: the
+// slice a[:][n][:] is the same for the whole block, so it is read through
+// the scalar cache once per block rather than by every thread, and a thread
+// reads its Z (or U) column once and writes all ra0 (or ra1) outputs of it,
+// each sum over the coefficient rank in order.  Wider coefficients take
+// both steps as batched GEMMs (Rounder::round).
 template <int RA>
 __global__ __launch_bounds__(256) void k_kr_t2_reg(const double* __restrict__ a, long long sa, int amod, int ra0,
                                                    int ra1, int N, const double* __restrict__ Z, long long sz,
@@ -661,6 +622,84 @@ static int orth(Rounder& R, const double* Y, double* Q, int m, int l, int batch,
   return LRFG_OK;
 }
 
+// T2 = X2 W3 ((R1 N2) x l2 per system, R1 = ra0 rg0, R2 = ra1 rg1) for the
+// middle carriage X2 = a (.) g given by its factors, ns systems; W3 is
+// R2 x l2 per system (compact), kz scratch.  First the sum over g's rank:
+// Z = g x W3 (GEMM over m), then the sum over a's rank:
+// T2[i rg0 + k][n][l] = sum_j a[i][n][j] Z[j][k][n][l].
+static int kr_t2(const KrMid& mid, int N2, int l2, const double* W3, double* T2, double* kz, int nE, int prec,
+                 double* gscr, size_t gscr_n, hipStream_t s) {
+  const int ra0 = mid.ra0, ra1 = mid.ra1, rg0 = mid.rg0, rg1 = mid.rg1;
+  const int R1 = ra0 * rg0;
+  const long long zs = (long long)ra1 * rg0 * N2 * l2;  // Z per system
+  const long long st = (long long)R1 * N2 * l2;         // T2 per system
+  if (ra1 <= kKrRegRank) {
+    // Z[j][k][n][l] (GEMM, batch t = s ra1 + j), then the sum over j in
+    // registers (k_kr_t2_reg, FP64)
+    { GemmB g(rg0 * N2, l2, rg1, nE * ra1);
+      g.a(mid.g, rg1, mid.sg).b(W3, l2, (long long)rg1 * l2).c(kz, l2, (long long)rg0 * N2 * l2);
+      g.g.adiv = ra1;
+      LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+    const dim3 grid((unsigned)N2, (unsigned)nE);
+    hipLaunchKernelGGL(k_kr_t2_reg<kKrRegRank>, grid, dim3(kB), 0, s, mid.a, mid.sa, mid.amod, ra0, ra1, N2,
+                       (const double*)kz, zs, rg0, l2, T2, st);
+    LRFG_LAUNCHED();
+    return LRFG_OK;
+  }
+  // wide coefficient ranks: both steps on MFMA, Z stored as Z[k][n][j][l]
+  // so that the sum over j is one small GEMM per (k, n):
+  // Z[(k,n)][j][l] = sum_m g[k][n][m] W3[j rg1 + m][l]   (batch s ra1 + j)
+  { GemmB g(rg0 * N2, l2, rg1, nE * ra1);
+    g.a(mid.g, rg1, mid.sg).b(W3, l2, (long long)rg1 * l2).c(kz, (long long)ra1 * l2, zs);
+    g.g.adiv = ra1;
+    g.g.cdiv = ra1;
+    g.g.cmod = ra1;
+    g.g.sC2 = l2;
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
+  // T2[i rg0 + k][n][l] = sum_j a[i][n][j] Z[(k,n)][j][l]   (batch (s, k, n)),
+  // in groups of amod systems (system s reads coefficient s % amod)
+  const int amod = mid.amod > 0 ? mid.amod : nE;
+  for (int s0 = 0; s0 < nE; s0 += amod) {
+    const int ns = std::min(amod, nE - s0);
+    GemmB g(ra0, l2, ra1, ns * rg0 * N2);
+    g.a(mid.a, (long long)N2 * ra1, mid.sa).b(kz + s0 * zs, l2, (long long)ra1 * l2)
+        .c(T2 + s0 * st, (long long)rg0 * N2 * l2, st);
+    g.g.adiv = rg0 * N2;
+    g.g.amod = N2;
+    g.g.sA2 = ra1;
+    g.g.cdiv = rg0 * N2;
+    g.g.cmod = rg0 * N2;
+    g.g.sC2 = l2;
+    LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s));
+  }
+  return LRFG_OK;
+}
+
+int Rounder::kr_dot(const TTB& kr, const KrMid& mid, const TTB& y, double* dots, double* dscr, size_t dscr_n,
+                    int ns, hipStream_t s) {
+  ProfScope ps_("kr_dot", s);
+  const int N1 = N[0], N2 = N[1], N3 = N[2];
+  const int R1 = kr.r[1], R2 = kr.r[2], ry1 = y.r[1], ry2 = y.r[2];
+  if (d != 3 || ns > nE || kz == nullptr || mid.ra0 * mid.rg0 != R1 || mid.ra1 * mid.rg1 != R2 ||
+      mid.ra0 > kr_ra || mid.ra1 > kr_ra || mid.rg0 > kr_rg || mid.rg1 > kr_rg || R1 > Rmax[0] || R2 > Rmax[1] ||
+      ry1 > Lmax[0] || ry2 > Lmax[1] || (long long)R1 * ry2 > (long long)Lmax[0] * Rmax[1]) {
+    set_error("kr_dot: sizes (R %d %d, y ranks %d %d, %d systems) exceed the plan", R1, R2, ry1, ry2, ns);
+    return LRFG_EINVAL;
+  }
+  // Lf = X1^T y1 (R1 x ry1) and Rt = X3 y3^T (R2 x ry2)
+  { GemmB g(R1, ry1, N1, ns); g.a(kr.c[0], R1, kr.s[0], true).b(y.c[0], ry1, y.s[0]).c(W2, ry1, (long long)R1 * ry1);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  { GemmB g(R2, ry2, N3, ns); g.a(kr.c[2], N3, kr.s[2]).b(y.c[2], N3, y.s[2], true).c(W3, ry2, (long long)R2 * ry2);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  // T2' = X2 Rt over the unformed middle carriage, V = Lf y2; the product is <T2', V>
+  LRFG_TRY(kr_t2(mid, N2, ry2, W3, T2, kz, ns, LRFG_PREC_FP64, gscr, gscr_n, s));
+  const long long nv = (long long)R1 * N2 * ry2;
+  { GemmB g(R1, N2 * ry2, ry1, ns); g.a(W2, ry1, (long long)R1 * ry1).b(y.c[1], (long long)N2 * ry2, y.s[1])
+        .c(X2p, (long long)N2 * ry2, nv);
+    LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  return dot_rows(nv, T2, nv, 1, X2p, nv, dots, ns, dscr, dscr_n, s);
+}
+
 static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, double* S, int* kept,
                       int nE, hipStream_t s) {
   (void)R;
@@ -712,27 +751,7 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
       GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
       LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s));
     } else {
-      // X2 = a (.) g: Z[j][k][n][l] = sum_m g[k][n][m] W3[j rg1 + m][l] (GEMM,
-      // batch t = s ra1 + j), then T2[i rg0 + k][n][l] = sum_j a[i][n][j]
-      // Z[j][k][n][l] (k_kr_t2, FP64)
-      const int ra0 = mid->ra0, ra1 = mid->ra1, rg0 = mid->rg0, rg1 = mid->rg1;
-      const long long zs = (long long)ra1 * rg0 * N2 * l2;  // Z per system
-      { GemmB g(rg0 * N2, l2, rg1, nE * ra1);
-        g.a(mid->g, rg1, mid->sg).b(W3, l2, (long long)rg1 * l2).c(kz, l2, (long long)rg0 * N2 * l2);
-        g.g.adiv = ra1;
-        LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
-      if (ra1 <= kKrRegRank) {
-        const dim3 grid((unsigned)N2, (unsigned)nE);
-        hipLaunchKernelGGL(k_kr_t2_reg<kKrRegRank>, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1,
-                           N2, (const double*)kz, zs, rg0, l2, T2, (long long)R1 * N2 * l2);
-        LRFG_LAUNCHED();
-      } else {
-        const long long per = (long long)ra0 * rg0 * N2 * l2;
-        const dim3 grid((unsigned)std::min<long long>(1024, (per + kB - 1) / kB), (unsigned)nE);
-        hipLaunchKernelGGL(k_kr_t2, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1, N2,
-                           (const double*)kz, zs, rg0, l2, T2, (long long)R1 * N2 * l2);
-        LRFG_LAUNCHED();
-      }
+      LRFG_TRY(kr_t2(*mid, N2, l2, W3, T2, kz, nE, prec, gscr, gscr_n, s));
     }
     // W2 = T2 Om2^T (R1 x l1), contraction over (n, l2)
     { GemmB g(R1, l1, N2 * l2, nE); g.a(T2, (long long)N2 * l2, (long long)R1 * N2 * l2).b(om[1], (long long)N2 * l2, 0, true)
@@ -757,19 +776,29 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
         g.a(M1, rg0, (long long)l1 * R1).b(mid->g, (long long)N2 * rg1, mid->sg)
             .c(kz, (long long)N2 * rg1, (long long)l1 * ra0 * N2 * rg1);
         LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
+      const long long su = (long long)l1 * ra0 * N2 * rg1, sx = (long long)l1 * N2 * R2;
       if (ra0 <= kKrRegRank) {
         const dim3 grid((unsigned)N2, (unsigned)nE);
         hipLaunchKernelGGL(k_kr_x2_reg<kKrRegRank>, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1,
-                           N2, (const double*)kz, (long long)l1 * ra0 * N2 * rg1, rg1, l1, X2p,
-                           (long long)l1 * N2 * R2);
+                           N2, (const double*)kz, su, rg1, l1, X2p, sx);
         LRFG_LAUNCHED();
       } else {
-        const long long per = (long long)l1 * N2 * ra1 * rg1;
-        const dim3 grid((unsigned)std::min<long long>(1024, (per + kB - 1) / kB), (unsigned)nE);
-        hipLaunchKernelGGL(k_kr_x2, grid, dim3(kB), 0, s, mid->a, mid->sa, mid->amod, ra0, ra1, N2,
-                           (const double*)kz, (long long)l1 * ra0 * N2 * rg1, rg1, l1, X2p,
-                           (long long)l1 * N2 * R2);
-        LRFG_LAUNCHED();
+        // X2'[p][n][j rg1 + m] = sum_i a[i][n][j] U[p][i][n][m]: one small
+        // GEMM (a^T times U) per (system, p, n), in groups of amod systems
+        const int amod = mid->amod > 0 ? mid->amod : nE;
+        for (int s0 = 0; s0 < nE; s0 += amod) {
+          const int ns = std::min(amod, nE - s0);
+          GemmB g(ra1, rg1, ra0, ns * l1 * N2);
+          g.a(mid->a, (long long)N2 * ra1, mid->sa, true).b(kz + s0 * su, (long long)N2 * rg1, (long long)ra0 * N2 * rg1)
+              .c(X2p + s0 * sx, rg1, (long long)ra1 * rg1);
+          g.g.adiv = l1 * N2;
+          g.g.amod = N2;
+          g.g.sA2 = ra1;
+          g.g.bdiv = N2;
+          g.g.bmod = N2;
+          g.g.sB2 = rg1;
+          LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s));
+        }
       }
     }
     // Y2 = X2' W3 ((l1 N2) x l2) ; Q2 = orth(Y2)

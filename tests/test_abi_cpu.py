@@ -55,6 +55,7 @@ def _problem(L, **kw):
     p.precision = kw.get("precision", L.PREC_FP64)
     p.precond_terms = kw.get("precond_terms", 0)
     p.oversample = kw.get("oversample", 0)
+    p.coeff_rank = kw.get("coeff_rank", 0)
     p.seed = 0
     p.flags = kw.get("flags", 0)
     return p
@@ -75,7 +76,9 @@ def _problem(L, **kw):
     (dict(precision=1), -5),                   # full grid is FP64 only
     (dict(solver=1), -5),                      # full grid uses PCG
     (dict(d=2, N=(15, 15), format=2), -5),     # Tucker path is d = 3 only
-    (dict(N=(65, 65, 65), format=2, rank_cap=64), -5),  # sketch sizes beyond 64
+    (dict(N=(131, 131, 131), format=2, rank_cap=129), -5),  # sketch sizes beyond 128
+    (dict(N=(131, 131, 131), format=3, rank_cap=129), -5),
+    (dict(format=3, coeff_rank=129), -5),               # coefficient ranks beyond 128
 ])
 def test_plan_validation(kw, code):
     L = _lib()
@@ -230,7 +233,7 @@ def test_gram_cut_validation_before_device():
     lib = _lib().lib()
     buf = (C.c_double * 16)()
     # n out of range, c < 1, negative / NaN tol, null pointers: EINVAL, no device call
-    assert lib.lrfg_gram_cut(65, 4, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
+    assert lib.lrfg_gram_cut(129, 4, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
     assert lib.lrfg_gram_cut(0, 4, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
     assert lib.lrfg_gram_cut(4, 0, C.addressof(buf), 1, 0.0, C.addressof(buf), None, None, None) == -1
     assert lib.lrfg_gram_cut(4, 2, C.addressof(buf), 1, -1.0, C.addressof(buf), None, None, None) == -1

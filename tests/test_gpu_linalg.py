@@ -96,7 +96,10 @@ def _graded_gram(rng, n, rank, decades):
 
 
 @pytest.mark.parametrize("n,rank,c", [(1, 1, 1), (2, 2, 1), (5, 3, 4), (26, 26, 16), (26, 10, 16),
-                                      (40, 40, 30), (64, 64, 54), (64, 20, 40)])
+                                      (40, 40, 30), (64, 64, 54), (64, 20, 40),
+                                      # sketch sizes above 64 (rank caps up to 118)
+                                      (65, 65, 60), (90, 90, 80), (96, 50, 80), (97, 97, 87), (128, 128, 118),
+                                      (128, 70, 100)])
 @pytest.mark.parametrize("decades", [2, 7])
 def test_gram_cut_subspace(dev, n, rank, c, decades):
     """Kept eigenvectors of a PSD Gram matrix: orthonormal, eigen-relation,
@@ -125,7 +128,7 @@ def test_gram_cut_subspace(dev, n, rank, c, decades):
         assert sweeps[b] <= 12
 
 
-@pytest.mark.parametrize("n", [12, 26, 40, 64])
+@pytest.mark.parametrize("n", [12, 26, 40, 64, 90, 128])
 def test_gram_cut_scale_invariant(dev, n):
     """G scaled by 2^600 or 2^-600 (entries far outside FP32's range, squared
     norms near FP64's limits): the cut works on G divided by a power of two

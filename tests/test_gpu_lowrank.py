@@ -101,7 +101,7 @@ def test_smooth_135_rank20(dev):
     o = fg.solve(a, tol=1e-10)
     err = _rel(r.A_H, o.A_H)
     print("TT 135^3 cap 20: A_H rel err", err, "iters", r.iters, "ranks", r.ranks)
-    assert err <= 1e-4
+    assert err <= 1e-6
     D = r.A_H - o.A_H
     assert np.min(np.linalg.eigvalsh(0.5 * (D + D.T))) >= -1e-9
 
@@ -163,3 +163,54 @@ def test_ball_compressed_coefficient_solve(dev):
     d = np.diag(r.A_H) - np.diag(o.A_H)
     assert np.all(d >= -1e-9 * np.max(np.diag(o.A_H)))
     assert _rel(r.A_H, o.A_H) <= 5e-2
+
+
+def _spike_cp(Ns, where, depth):
+    """CP coefficient 1 - depth e_where (rank 2): positive except at one grid
+    point when depth > 1."""
+    d = len(Ns)
+    w = np.array([1.0, -float(depth)])
+    fac = []
+    for j in range(d):
+        f = np.zeros((2, Ns[j]))
+        f[0] = 1.0
+        f[1, where[j]] = 1.0
+        fac.append(f)
+    return w, fac
+
+
+def _cp_to_tt(w, fac):
+    """TT cores [r_{j-1}][N_j][r_j] of a CP coefficient (d = 3)."""
+    R = len(w)
+    G1 = (w[:, None] * fac[0]).T[None]                    # 1 x N x R
+    G2 = np.zeros((R, fac[1].shape[1], R))
+    for t in range(R):
+        G2[t, :, t] = fac[1][t]
+    G3 = fac[2][:, :, None]                                # R x N x 1
+    return [G1, G2, G3]
+
+
+@pytest.mark.parametrize("fmt", ["tt-cp", "tt-cores", "cp2d", "tucker", "full"])
+def test_negative_coefficient_rejected(dev, fmt):
+    """A coefficient that is negative at one grid point (1 - 2 e_x0) makes
+    the operator indefinite: every path rejects it with ECOEFF before
+    solving; the same construction with depth 0.5 (positive) solves."""
+    Ns = (15, 15) if fmt == "cp2d" else (15, 15, 15)
+    d = len(Ns)
+    where = (3, 11, 7)[:d]
+    for depth, ok in ((2.0, False), (0.5, True)):
+        w, fac = _spike_cp(Ns, where, depth)
+        if fmt == "full":
+            s = P.Solver(d=d, N=Ns, format="full", solver_tol=1e-8, max_iter=200)
+        else:
+            s = P.Solver(d=d, N=Ns, format="tucker" if fmt == "tucker" else ("cp" if fmt == "cp2d" else "tt"),
+                         rank_cap=6, solver_tol=1e-8, max_iter=200, coeff_rank=2)
+        kw = dict(tt=_cp_to_tt(w, fac)) if fmt == "tt-cores" else dict(cp=(w, fac))
+        if ok:
+            r = s.solve(**kw)
+            assert np.all(np.isfinite(r.A_H))
+        else:
+            with pytest.raises(P.LrfgError) as ei:
+                s.solve(**kw)
+            assert ei.value.status == -2
+            assert "admissible" in str(ei.value) or "positive" in str(ei.value)

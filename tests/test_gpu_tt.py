@@ -23,7 +23,9 @@ def _host(outs, e):
 
 @pytest.mark.parametrize("Ns,ranks,cap", [((9, 11, 13), (1, 3, 4, 1), 5), ((15, 15, 15), (1, 6, 6, 1), 20),
                                           ((45, 27, 35), (1, 8, 5, 1), 8), ((135, 135, 135), (1, 9, 9, 1), 20),
-                                          ((45, 45, 45), (1, 30, 28, 1), 40)])  # sketch 44 > 32
+                                          ((45, 45, 45), (1, 30, 28, 1), 40),   # sketch 44 > 32
+                                          ((90, 90, 90), (1, 40, 45, 1), 80),   # sketches 80, 84 > 64
+                                          ((81, 81, 81), (1, 55, 50, 1), 110)])  # sketches 81, 81
 def test_exact_low_rank_is_reproduced(dev, Ns, ranks, cap):
     """A sum of two trains whose true ranks fit the cap is reproduced to
     rounding level (the randomised sketch spans the exact range)."""

@@ -304,8 +304,10 @@ def test_solve_tucker_coefficient_host_and_device(dev):
     import torch
     N = 21
     a = W.ball_coeff(N, inside=10.0)
-    (core, frames), kept = P.compress_tucker(torch.from_numpy(a).to(dev), cap=6, seed=0)
-    s = P.Solver(d=3, N=(N,) * 3, format="tucker", rank_cap=6, solver_tol=1e-8, max_iter=100, coeff_rank=6)
+    # mode ranks 7 reproduce the ball exactly at N = 21 (rank 6 would leave
+    # the compressed field negative, which the solver rejects)
+    (core, frames), kept = P.compress_tucker(torch.from_numpy(a).to(dev), cap=7, seed=0)
+    s = P.Solver(d=3, N=(N,) * 3, format="tucker", rank_cap=6, solver_tol=1e-8, max_iter=100, coeff_rank=7)
     r_dev = s.solve(tucker=(core, frames))
     r_host = s.solve(tucker=(core.cpu().numpy(), [F.cpu().numpy() for F in frames]))
     assert _rel(r_dev.A_H, r_host.A_H) <= 1e-13
