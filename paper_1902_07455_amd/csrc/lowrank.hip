@@ -135,6 +135,8 @@ __global__ void k_beta(const double* __restrict__ rz, double* __restrict__ rho, 
 // Restarts of a truncated PCG system from its best iterate before it is
 // declared stagnant.
 constexpr int kMaxRestarts = 3;
+// Sketch counters of the restart steps (the iterations' counters stay far below).
+constexpr uint64_t kRestartKeys = 1ull << 62;
 
 // dst_e = src_e for the systems e whose bit is set in mask
 struct SysMask {
@@ -266,8 +268,8 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
     R.kr_rg = std::max(rc[1], rc[2]);
   }
   R.carve(ar);
-  // per-system scalars (dots also holds the nE x 3 energy-form products)
-  C.dots = ar.take<double>((size_t)3 * nE + 64);
+  // per-system scalars (dots also holds the 2 d nE energy-form products)
+  C.dots = ar.take<double>((size_t)6 * nE + 64);
   C.rho = ar.take<double>(nE);
   C.pqd = ar.take<double>(nE);
   C.alpha = ar.take<double>(nE);
@@ -706,25 +708,27 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       for (int al = 0; al < d; ++al) ee += Ev(e, al) * Ev(e, al);
       en[e] = mean_a[na == 1 ? 0 : e] * ee;
     }
-    std::vector<double> v(nE);
+    // <a, D_alpha x_e> into dots[2 alpha nE + e], <a (.) D_alpha x_e, D_alpha x_e>
+    // into dots[(2 alpha + 1) nE + e]; one read at the end
     for (int al = 0; al < d; ++al) {
       TTB g = X;
       g.c[al] = C.gcore;
       LRFG_TRY(tt_mode_apply(X, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
-      LRFG_TRY(tt_dot(C.a, g, C.dots, C.dscr, nE, s));
-      LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
-      for (int e = 0; e < nE; ++e) en[e] += 2.0 * Ev(e, al) * v[e] / Ntot;
+      LRFG_TRY(tt_dot(C.a, g, C.dots + 2 * al * nE, C.dscr, nE, s));
       if (d == 3) {
         LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s, 1));
         const KrMid km = kr_mid(C, g);
-        LRFG_TRY(C.rd.kr_dot(C.kr, km, g, C.dots, C.dscr, C.dscr_n, nE, s));
+        LRFG_TRY(C.rd.kr_dot(C.kr, km, g, C.dots + (2 * al + 1) * nE, C.dscr, C.dscr_n, nE, s));
       } else {
         LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-        LRFG_TRY(tt_dot(C.kr, g, C.dots, C.dscr, nE, s));
+        LRFG_TRY(tt_dot(C.kr, g, C.dots + (2 * al + 1) * nE, C.dscr, nE, s));
       }
-      LRFG_TRY(read_dev(C, C.dots, v.data(), nE));
-      for (int e = 0; e < nE; ++e) en[e] += v[e] / Ntot;
     }
+    std::vector<double> v((size_t)2 * d * nE);
+    LRFG_TRY(read_dev(C, C.dots, v.data(), 2 * d * nE));
+    for (int al = 0; al < d; ++al)
+      for (int e = 0; e < nE; ++e)
+        en[e] += (2.0 * Ev(e, al) * v[(size_t)2 * al * nE + e] + v[(size_t)(2 * al + 1) * nE + e]) / Ntot;
     return LRFG_OK;
   };
 
@@ -756,7 +760,16 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& res0,
                    std::vector<int>& st, bool record) -> int {
     std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
-    std::vector<double> best(nE, INFINITY), zzh(nE);
+    std::vector<double> best(nE, INFINITY), zzh(nE), en(nE), best_en(nE, INFINITY);
+    // Once a system's residual has failed to decrease, the FP64 PCG keeps
+    // the iterate of lowest energy (the energy form of eq. homog, evaluated
+    // exactly on the train): energy - A_H E.E is the squared energy norm of
+    // the iterate's error (Sec. 4.3), whereas the recursive residual of a
+    // truncated iteration carries the truncation noise and can fall while
+    // the error grows.  While the residual keeps decreasing it decides, and
+    // no energy is evaluated.
+    const bool by_energy = record && P.solver == LRFG_SOLVER_PCG && C.rd.prec == LRFG_PREC_FP64;
+    std::vector<char> emode(nE, 0);
     for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
     LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
     LRFG_TRY(tt_zero(C.xr, 2 * nE, s));
@@ -820,16 +833,27 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         LRFG_TRY(dot(C, C.r, C.r, C.zz));
       }
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
-      bool changed = false;
+      bool need_en = false;
+      for (int e = 0; e < nE; ++e) need_en = need_en || (!hdone[e] && emode[e]);
+      if (need_en) LRFG_TRY(energy_diag(C.x, en));
+      bool changed = false, switched = false;
       unsigned long long improved[4] = {0, 0, 0, 0};  // systems whose x becomes the best iterate
       SysMask restart{{0, 0, 0, 0}};                  // systems restarted from their best iterate
+      SysMask to_energy{{0, 0, 0, 0}};                // systems switching to the energy rule
       for (int e = 0; e < nE; ++e) {
         if (hdone[e]) continue;
         const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
         if (record) hist[(size_t)e * maxit + it] = res;
         its[e] = it + 1;
-        if (res < best[e]) {
-          best[e] = res;
+        const bool better = emode[e] ? en[e] < best_en[e] : res < best[e];
+        if (res < best[e]) best[e] = res;
+        if (!better && by_energy && !emode[e]) {
+          emode[e] = 1;
+          switched = true;
+          to_energy.m[e >> 6] |= 1ull << (e & 63);
+        }
+        if (better) {
+          if (emode[e]) best_en[e] = en[e];
           since_best[e] = 0;
           improved[e >> 6] |= 1ull << (e & 63);
           if (record) {
@@ -856,16 +880,30 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       }
       LRFG_TRY(tt_copy_systems(C.x, C.xb, nE, improved, s));
       if (changed) LRFG_TRY(upload_done(hdone));
+      if (switched) {
+        // the best iterate so far (by residual) enters the energy rule
+        std::vector<double> eb(nE);
+        LRFG_TRY(energy_diag(C.xb, eb));
+        for (int e = 0; e < nE; ++e)
+          if (sys_bit(to_energy, e)) best_en[e] = eb[e];
+      }
       if (restart.m[0] | restart.m[1] | restart.m[2] | restart.m[3]) {
         // residual replacement: x = x_best, r = T(b - K x), z = T(P~^-1 r),
         // p = z, rho = (r, z) for the restarted systems (the others keep
         // their state: the batched steps run for every system and are
         // copied into the restarted ones only)
+        // The restart's truncations draw their sketches from a key space of
+        // their own and leave the iteration's sequence as it was, so that a
+        // system's iterates do not depend on when other systems of a batch
+        // restart (batched solves equal single ones)
+        const uint64_t saved = C.rd.counter;
+        C.rd.counter = kRestartKeys | ((uint64_t)it << 8);
         LRFG_TRY(apply_K(C, C.xb, C.tmp));
         LRFG_TRY(axpby(C, C.b, C.tmp, C.mones, C.z));
         LRFG_TRY(tt_copy_systems(C.z, C.r, nE, restart.m, s));
         LRFG_TRY(tt_copy_systems(C.xb, C.x, nE, restart.m, s));
         LRFG_TRY(apply_P(C, C.r, C.z));
+        C.rd.counter = saved;
         LRFG_TRY(tt_copy_systems(C.z, C.p, nE, restart.m, s));
         LRFG_TRY(dot(C, C.r, C.z, C.dots));
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kMaxSystems), 0, s, C.rho, (const double*)C.dots, restart, nE);
@@ -873,8 +911,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         // the best residual becomes the true one of the best iterate
         LRFG_TRY(dot(C, C.z, C.z, C.zz));
         LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
-        for (int e = 0; e < nE; ++e)
-          if (sys_bit(restart, e)) best[e] = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+        if (!by_energy)
+          for (int e = 0; e < nE; ++e)
+            if (sys_bit(restart, e)) best[e] = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
       }
     }
     for (int e = 0; e < nE; ++e) {
@@ -1604,6 +1643,8 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
       if (restart.m[0] | restart.m[1] | restart.m[2] | restart.m[3]) {
         // residual replacement for the restarted systems: x = x_best,
         // r = T(b - K x), z = T(P~^-1 r), p = z, rho = (r, z)
+        const uint64_t saved = C.rd.counter;  // sketches of their own (see the train path)
+        C.rd.counter = kRestartKeys | ((uint64_t)it << 8);
         LRFG_TRY(tk_apply_K(C, C.xb, C.tmp));
         LRFG_TRY(tk_axpby(C, C.b, C.tmp, C.mones, C.z));
         for (int e = 0; e < nE; ++e)
@@ -1612,6 +1653,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
             LRFG_TRY(tk_copy_system(C.xb, C.x, e, s));
           }
         LRFG_TRY(tk_apply_P(C, C.r, C.z));
+        C.rd.counter = saved;
         for (int e = 0; e < nE; ++e)
           if (sys_bit(restart, e)) LRFG_TRY(tk_copy_system(C.z, C.p, e, s));
         LRFG_TRY(tk_dot(C.r, C.z, C.dots, C.dscr, nE, s));

@@ -315,15 +315,15 @@ def test_solve_tucker_coefficient_host_and_device(dev):
 
 @pytest.mark.parametrize("fmt", ["tucker", "tt"])
 def test_ball_243_compressed(dev, fmt):
-    """Config-3 size: a ball at N = 243 compressed to Tucker / TT ranks 12,
-    solved at rank cap 10; the full-grid GPU solve of the same compressed
-    field (expanded on the host) is the reference: the truncated A_H
-    dominates it (Sec. 4.3 energy identity) and is close.  Contrast 2: a
-    low-rank indicator overshoots at the sphere by a fixed fraction of the
-    jump, so at contrast 100 every rank this build reaches (<= 54) leaves the
-    compressed field negative there (HOSVD rank 12/24/40: min -16/-13/-16),
-    no admissible coefficient; at contrast 5 the randomised rank-12
-    compression still dips to -0.5."""
+    """A ball at N = 243 compressed to Tucker / TT ranks 12, solved at rank
+    cap 10; the full-grid GPU solve of the same compressed field (expanded
+    on the host) is the reference: the truncated A_H dominates it (Sec. 4.3
+    energy identity) and is close.  Contrast 2: a low-rank indicator
+    overshoots at the sphere by a fixed fraction of the jump, and only the
+    exact ranks (73 at N = 243) keep the contrast-100 ball positive; with
+    those, the Tucker product core (73 c)^3 is out of reach, so the Tucker
+    format is exercised on this admissible low-rank field (the TT format on
+    the contrast-100 ball itself: test_gpu_ball.py)."""
     import torch
     N = 243
     a = W.ball_coeff(N, inside=2.0)
