@@ -308,3 +308,53 @@ def test_expsum_approximates_reciprocal(R, M, band):
     y = np.exp(np.linspace(0.0, np.log(R), 4000))
     rel = expsum.expsum_eval(y, t, w) * y
     assert rel.min() > 1 - band and rel.max() < 1 + band
+
+
+# ---------------------------------------------------------------- remaining format operations
+def test_cp_add_expands_to_the_sum():
+    """CP addition (Table 1: ranks add) expands to the sum of the expansions."""
+    x = W.random_cp((6, 7, 8), 3, 11)
+    y = W.random_cp((6, 7, 8), 4, 12)
+    s = L.cp_add(L.CP(x.weights, x.factors), L.CP(y.weights, y.factors))
+    assert s.rank == 7
+    assert np.allclose(s.full(), x.full() + y.full(), rtol=0, atol=1e-12 * np.abs(x.full()).max())
+
+
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_tt_mode_apply_is_the_mode_product(j):
+    """A matrix applied along the mode index of carriage j (rank unchanged)
+    is numpy's mode-j product of the full tensor; with the spectral
+    derivative F^-1 diag(2 pi i k) F as the matrix it is numpy's FFT
+    derivative along axis j (Sec. 2.2.1, Appendix A.3)."""
+    Ns = (5, 7, 9)
+    cores = W.random_tt(Ns, [1, 3, 4, 1], 21)
+    X = L.tt_full(cores)
+    M = np.random.default_rng(j).standard_normal((Ns[j], Ns[j]))
+    Y = L.tt_full(L.tt_mode_apply(cores, j, M))
+    assert L.tt_ranks(L.tt_mode_apply(cores, j, M)) == [1, 3, 4, 1]
+    assert np.allclose(Y, np.moveaxis(np.tensordot(M, X, axes=(1, j)), 0, j), atol=1e-12)
+    n = Ns[j]
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    D = np.real(np.fft.ifft(2j * np.pi * k[:, None] * np.fft.fft(np.eye(n), axis=0), axis=0))
+    sh = [1, 1, 1]
+    sh[j] = n
+    want = np.real(np.fft.ifft(2j * np.pi * k.reshape(sh) * np.fft.fft(X, axis=j), axis=j))
+    assert np.allclose(L.tt_full(L.tt_mode_apply(cores, j, D)), want, atol=1e-11)
+
+
+@pytest.mark.parametrize("shape", [(15, 17, 19), (45, 45)])
+def test_precond_symbol_approximates_inverse_laplacian(shape):
+    """The separable preconditioner symbol is within the exponential sum's
+    band of 1/(4 pi^2 |k|^2) at every nonzero frequency of the grid, and
+    positive (Sec. 2.3, eq. Pls_GaNi_fourier)."""
+    sym = expsum.precond_symbol(shape)
+    d = len(shape)
+    kk = 0.0
+    for al, n in enumerate(shape):
+        sh = [1] * d
+        sh[al] = n
+        kk = kk + (np.fft.fftfreq(n, d=1.0 / n) ** 2).reshape(sh)
+    nz = kk > 0
+    ratio = sym[nz] * (4 * np.pi ** 2) * kk[nz]
+    assert np.all(sym > 0)
+    assert ratio.min() > 0.88 and ratio.max() < 1.12
