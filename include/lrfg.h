@@ -184,6 +184,22 @@ int lrfg_plan_workspace_bytes(const lrfg_plan* plan, int max_nE, size_t* bytes);
 int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE,
                void* d_ws, size_t ws_bytes, void* stream, lrfg_result* out);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): lrfg_solve with the library's own device workspace, one array
+ * of LRFG_NOALLOC_BYTES per GPU (held until the process ends) in place of
+ * d_ws.  The call allocates no device or pinned host memory (the plan must
+ * have been created with a device present; full-grid plans take their
+ * pinned flag ring there).  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other threads or streams) race and must be
+ * serialised by the caller.  The array keeps the last call's contents;
+ * nothing in a solve depends on them.  Returns LRFG_EWORKSPACE when
+ * lrfg_plan_workspace_bytes(plan, nE) exceeds LRFG_NOALLOC_BYTES (checked
+ * before any device call), otherwise as lrfg_solve. */
+#define LRFG_NOALLOC_BYTES ((size_t)128 << 20)
+int lrfg_solve_noalloc(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* stream,
+                       lrfg_result* out);
+
 /* Batched solve: `count` microstructures a[0..count-1] of the same problem
  * (and, for the low-rank formats, the same coefficient ranks), each with
  * the nE fields E, one result each in results[0..count-1].  The low-rank

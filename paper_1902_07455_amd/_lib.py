@@ -94,7 +94,7 @@ EXPORTS = [
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
     "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_gemm_mixed", "lrfg_syevj", "lrfg_gram_cut", "lrfg_compress_workspace_bytes", "lrfg_tucker_round_workspace_bytes", "lrfg_tucker_round", "lrfg_compress_tt", "lrfg_compress_tucker_workspace_bytes", "lrfg_compress_tucker", "lrfg_tt_round_workspace_bytes",
-    "lrfg_tt_round",
+    "lrfg_tt_round", "lrfg_solve_noalloc",
 ]
 
 
@@ -123,6 +123,9 @@ def lib():
     L.lrfg_solve.argtypes = [C.c_void_p, C.POINTER(Coeff), C.c_void_p, C.c_int, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.POINTER(Result)]
     L.lrfg_solve.restype = C.c_int
+    L.lrfg_solve_noalloc.argtypes = [C.c_void_p, C.POINTER(Coeff), C.c_void_p, C.c_int, C.c_void_p,
+                                     C.POINTER(Result)]
+    L.lrfg_solve_noalloc.restype = C.c_int
     L.lrfg_solve_batch.argtypes = [C.c_void_p, C.POINTER(Coeff), C.c_int, C.c_void_p, C.c_int, C.c_void_p,
                                    C.c_size_t, C.c_void_p, C.POINTER(Result)]
     L.lrfg_solve_batch.restype = C.c_int

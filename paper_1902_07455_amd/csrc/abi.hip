@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -193,6 +194,17 @@ int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
       delete pl;
       return rc;
     }
+  } else {
+    // the full-grid loop's pinned host flags, taken here when a device is
+    // present so that solving allocates nothing (else at the first solve)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 &&
+        hipHostMalloc((void**)&pl->pinned, sizeof(int) * 4 * 3, hipHostMallocDefault) == hipSuccess) {
+      pl->pinned_n = 12;
+    } else {
+      pl->pinned = nullptr;
+      (void)hipGetLastError();
+    }
   }
   *out = pl;
   return LRFG_OK;
@@ -362,6 +374,63 @@ static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int n
     out->solve_ms = fo.solve_ms;
     return rc;
   }
+}
+
+// ---------------------------------------------------------------- allocation-free solve
+}  // extern "C"
+
+namespace {
+// The workspace of lrfg_solve_noalloc: one array per GPU, held until the
+// process ends and shared by every call on that GPU.  Host code uses the
+// device address taken once per device (the array's name is only a host
+// stand-in for it).
+__device__ __align__(256) char scratch[LRFG_NOALLOC_BYTES];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
+
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  LRFG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    LRFG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr || (reinterpret_cast<uintptr_t>(p) & 255) != 0) {
+      set_error("device scratch address unusable");
+      return LRFG_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LRFG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lrfg_solve_noalloc(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE, void* stream,
+                       lrfg_result* out) {
+  clear_error();
+  if (plan == nullptr || nE < 1) {
+    set_error("plan must be non-NULL and nE >= 1");
+    return LRFG_EINVAL;
+  }
+  size_t need = 0;
+  LRFG_TRY(lrfg_plan_workspace_bytes(plan, nE, &need));
+  if (need > LRFG_NOALLOC_BYTES) {
+    set_error("the plan needs %zu bytes of workspace; the allocation-free solve holds %zu", need,
+              (size_t)LRFG_NOALLOC_BYTES);
+    return LRFG_EWORKSPACE;
+  }
+  if (plan->p.format == LRFG_FORMAT_FULL && plan->pinned == nullptr) {
+    set_error("the plan was created without a device (no pinned flag ring); create it with a device present");
+    return LRFG_EUNSUPPORTED;
+  }
+  LRFG_TRY(device_ok());
+  void* ws = nullptr;
+  LRFG_TRY(scratch_of_current_device(&ws));
+  return solve_impl(plan, a, 1, E, nE, ws, LRFG_NOALLOC_BYTES, stream, out);
 }
 
 size_t lrfg_fft_workspace_bytes(int N) { return sizeof(double2) * (size_t)(N > 0 ? N : 1) + 256; }

@@ -287,3 +287,21 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.findall(r"(?:import|from)\s+(\w+)", text), f
+
+
+def test_noalloc_oversized_refused_before_device():
+    """lrfg_solve_noalloc refuses a plan whose workspace exceeds the
+    library's array (LRFG_EWORKSPACE) before touching a device."""
+    L = _lib()
+    lib = L.lib()
+    plan = C.c_void_p()
+    assert lib.lrfg_plan_create(C.byref(_problem(L, N=(135, 135, 135), format=3, rank_cap=16, coeff_rank=9)),
+                                C.byref(plan)) == 0
+    nb = C.c_size_t()
+    assert lib.lrfg_plan_workspace_bytes(plan, 3, C.byref(nb)) == 0
+    assert nb.value > (128 << 20)
+    c = L.Coeff()
+    r = L.Result()
+    assert lib.lrfg_solve_noalloc(plan, C.byref(c), None, 3, None, C.byref(r)) == -3
+    assert b"allocation-free" in lib.lrfg_last_error()
+    lib.lrfg_plan_destroy(plan)
