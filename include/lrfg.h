@@ -374,9 +374,11 @@ int lrfg_compress_tucker(const int N[3], const double* a, int cap, double tol, i
  * outside the requests' workspaces) has room for their workspace: the
  * oldest request that fits is taken with the other queued requests of the
  * same problem, fields and coefficient ranks, up to max_batch of them, and
- * solved as one lrfg_solve_batch.  Requests arriving while others run join
- * the next batch a worker forms; batches on different streams overlap on
- * the device.  Results equal those of lrfg_solve up to rounding.
+ * solved as one lrfg_solve_batch (a low-rank batch holds at most 256
+ * correctors, so at most 256 / nE requests).  Requests arriving while
+ * others run join the next batch a worker forms; batches on different
+ * streams overlap on the device.  Results equal those of lrfg_solve up to
+ * rounding.
  * ---------------------------------------------------------------------- */
 typedef struct lrfg_server lrfg_server;
 
@@ -400,10 +402,15 @@ int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_
  * unchanged until the completion is polled), fields E (nE x d, copied;
  * NULL = canonical basis with nE = d), result `out` (the struct and its
  * arrays are written by the worker; read them after the completion).
- * Returns the plan-validation codes of lrfg_plan_create, LRFG_EWORKSPACE
- * when the request's workspace exceeds the whole pool. */
+ * Device coefficients (a->on_device) may still be being written by work
+ * queued on `stream` (the caller's stream; NULL = the default stream): an
+ * event recorded there at submit orders the worker's reads after that
+ * work.  Work the caller queues on other streams must be complete before
+ * submit.  Returns the plan-validation codes of lrfg_plan_create,
+ * LRFG_EWORKSPACE when the request's workspace exceeds the whole pool,
+ * LRFG_EDEVICE when the event cannot be recorded. */
 int lrfg_server_submit(lrfg_server* s, const lrfg_problem* p, const lrfg_coeff* a, const double* E,
-                       int nE, lrfg_result* out, uint64_t tag);
+                       int nE, lrfg_result* out, uint64_t tag, void* stream);
 
 /* Move up to `max` completions into done[0..*n-1]; waits up to timeout_ms
  * for the first (0: no wait, < 0: until one arrives). */

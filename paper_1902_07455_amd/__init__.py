@@ -283,7 +283,11 @@ class Server:
         if tag is None:
             tag = self._next
         self._next = max(self._next, int(tag)) + 1
-        check(lib().lrfg_server_submit(self._h, C.byref(pr), C.byref(c), Eptr, nE, C.byref(r), int(tag)))
+        torch = _torch()
+        with torch.cuda.device(torch.device(self.device)):
+            sh = _stream_handle(None)  # the caller's current stream: device inputs are ordered after it
+        check(lib().lrfg_server_submit(self._h, C.byref(pr), C.byref(c), Eptr, nE, C.byref(r), int(tag),
+                                       C.c_void_p(sh)))
         self._pending[int(tag)] = (h, pr, c, r, bufs)
         return int(tag)
 

@@ -132,7 +132,7 @@ def lib():
     L.lrfg_server_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
     L.lrfg_server_create.restype = C.c_int
     L.lrfg_server_submit.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Coeff), C.c_void_p, C.c_int,
-                                     C.POINTER(Result), C.c_uint64]
+                                     C.POINTER(Result), C.c_uint64, C.c_void_p]
     L.lrfg_server_submit.restype = C.c_int
     L.lrfg_server_poll.argtypes = [C.c_void_p, C.POINTER(Completion), C.c_int, C.POINTER(C.c_int), C.c_int]
     L.lrfg_server_poll.restype = C.c_int

@@ -10,6 +10,7 @@
 // next batch a worker forms; batches on different streams overlap on the
 // device.  The coefficient data is read where the caller keeps it (device
 // pointers stay on the device).
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -20,6 +21,7 @@
 #include <vector>
 
 #include "common.h"
+#include "lowrank.h"
 
 namespace lrfg {
 namespace {
@@ -39,6 +41,7 @@ struct Request {
   uint64_t tag = 0;
   lrfg_plan* plan = nullptr;
   size_t ws_one = 0;
+  hipEvent_t ready = nullptr;  // recorded on the submitter's stream: device inputs complete
   Clock::time_point t_submit;
 };
 
@@ -156,7 +159,9 @@ void worker_main(lrfg_server* S) {
         std::vector<size_t> pick = {hi};
         size_t need = head.ws_one;
         if (head.p.format != LRFG_FORMAT_FULL) {  // Tucker batches run one microstructure at a time
-          for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < S->max_batch; ++j) {
+          // a low-rank batch holds at most kMaxSystems correctors
+          const int cap = std::max(1, std::min(S->max_batch, kMaxSystems / head.nE));
+          for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < cap; ++j) {
             if (!same_batch_key(head, *S->queue[j])) continue;
             size_t more = 0;
             if (lrfg_plan_workspace_bytes(head.plan, (int)(pick.size() + 1) * head.nE, &more) != LRFG_OK) break;
@@ -188,6 +193,10 @@ void worker_main(lrfg_server* S) {
     Request& h = *batch[0];
     const int nE = h.nE;
     const double* E = h.E.empty() ? nullptr : h.E.data();
+    // the coefficients are read on this worker's stream: wait until the
+    // work that produced them on the submitters' streams is done
+    for (size_t k = 0; k < batch.size(); ++k)
+      if (batch[k]->ready != nullptr) (void)hipStreamWaitEvent(st, batch[k]->ready, 0);
     const int rc = lrfg_solve_batch(h.plan, coeffs.data(), (int)batch.size(), E, nE, S->pool_base + off, bytes, st,
                                     res.data());
     const Clock::time_point t1 = Clock::now();
@@ -216,6 +225,8 @@ void worker_main(lrfg_server* S) {
       S->done.push_back(c);
       lrfg_plan_destroy(r.plan);
       r.plan = nullptr;
+      if (r.ready != nullptr) (void)hipEventDestroy(r.ready);
+      r.ready = nullptr;
     }
     S->cv_done.notify_all();
     S->cv_work.notify_all();
@@ -254,7 +265,7 @@ int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_
 }
 
 int lrfg_server_submit(lrfg_server* S, const lrfg_problem* p, const lrfg_coeff* a, const double* E, int nE,
-                       lrfg_result* out, uint64_t tag) {
+                       lrfg_result* out, uint64_t tag, void* stream) {
   using namespace lrfg;
   clear_error();
   if (S == nullptr || p == nullptr || a == nullptr || out == nullptr) {
@@ -278,10 +289,22 @@ int lrfg_server_submit(lrfg_server* S, const lrfg_problem* p, const lrfg_coeff* 
     lrfg_plan_destroy(r->plan);
     return LRFG_EWORKSPACE;
   }
+  if (a->on_device) {
+    // device inputs are read by a worker's stream: order that read after
+    // the work already queued on the submitter's stream
+    if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+      if (r->ready != nullptr) (void)hipEventDestroy(r->ready);
+      lrfg_plan_destroy(r->plan);
+      set_error("could not record the submit event");
+      return LRFG_EDEVICE;
+    }
+  }
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) {
+      if (r->ready != nullptr) (void)hipEventDestroy(r->ready);
       lrfg_plan_destroy(r->plan);
       set_error("server is stopping");
       return LRFG_EINVAL;
@@ -332,8 +355,10 @@ void lrfg_server_destroy(lrfg_server* S) {
   }
   S->cv_work.notify_all();
   for (auto& t : S->workers) t.join();
-  for (auto& r : S->queue)
+  for (auto& r : S->queue) {
     if (r->plan) lrfg_plan_destroy(r->plan);
+    if (r->ready) (void)hipEventDestroy(r->ready);
+  }
   delete S;
 }
 

@@ -170,7 +170,7 @@ def test_server_validation_before_device():
     assert lib.lrfg_server_create(0, 2, 4, None, 1 << 20, C.byref(h)) == -1
     assert lib.lrfg_server_create(0, 2, 4, C.addressof(buf) + 8, 1 << 20, C.byref(h)) == -1
     n = C.c_int()
-    assert lib.lrfg_server_submit(None, None, None, None, 3, None, 0) == -1
+    assert lib.lrfg_server_submit(None, None, None, None, 3, None, 0, None) == -1
     assert lib.lrfg_server_poll(None, None, 0, C.byref(n), 0) == -1
     assert lib.lrfg_server_pending(None) == 0
     lib.lrfg_server_destroy(None)

@@ -247,3 +247,50 @@ def test_server_tucker_requests(dev):
         assert c.status == alone[c.tag].rc
         assert _rel(c.result.A_H, alone[c.tag].A_H) <= MIX_TOL
         assert list(c.result.iters) == list(alone[c.tag].iters)
+
+
+def test_server_reads_device_inputs_after_the_submitting_stream(dev):
+    """A coefficient still being written on the submitter's stream (behind
+    a long queue of work) when submit returns: the worker waits for it (the
+    event recorded at submit), so the result is that of the final values."""
+    import torch
+    N = 15
+    cp = W.cube_cp(N, 10.0)
+    prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=6, solver_tol=1e-10, max_iter=80, coeff_rank=2)
+    want = _alone([(prob, cp)], dev)[0]
+    side = torch.cuda.Stream(dev)
+    srv = P.Server(slots=2, max_batch=1, pool_bytes=1 << 30)
+    with torch.cuda.stream(side):
+        w = torch.zeros(2, dtype=torch.float64, device=dev)
+        f = [torch.zeros((2, N), dtype=torch.float64, device=dev) for _ in range(3)]
+        big = torch.ones((2048, 2048), dtype=torch.float64, device=dev)
+        for _ in range(16):
+            big = big @ big * (1.0 / 2048)      # keeps the stream busy for a while
+        w.copy_(torch.from_numpy(cp.weights).to(dev, non_blocking=True) + 0.0 * big[0, :2])
+        for x, y in zip(f, cp.factors):
+            x.copy_(torch.from_numpy(y).to(dev, non_blocking=True))
+        srv.submit(prob, cp=(w, f), tag=0)
+    done = srv.drain()
+    srv.close()
+    assert done[0].status == want.rc
+    assert _rel(done[0].result.A_H, want.A_H) <= MIX_TOL
+    assert list(done[0].result.iters) == list(want.iters)
+
+
+def test_server_caps_batches_at_the_system_limit(dev):
+    """max_batch far above 256 / nE: batches stop at 85 requests of 3
+    fields, and every request completes with its own result."""
+    N = 9
+    cp = W.cube_cp(N, 5.0)
+    prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=3, solver_tol=1e-6, max_iter=40, coeff_rank=2)
+    want = _alone([(prob, cp)], dev)[0]
+    srv = P.Server(slots=1, max_batch=1000, pool_bytes=8 << 30)
+    for i in range(100):
+        srv.submit(prob, cp=(cp.weights, cp.factors), tag=i)
+    done = srv.drain()
+    srv.close()
+    assert sorted(c.tag for c in done) == list(range(100))
+    assert max(c.batch_size for c in done) <= 85
+    assert all(c.status == want.rc for c in done)
+    for c in done:
+        assert _rel(c.result.A_H, want.A_H) <= MIX_TOL
