@@ -157,6 +157,117 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
       }
 }
 
+// The same product for large outputs: a 128 x 128 block tile, each of the
+// four waves (2 x 2) computing a 64 x 64 sub-tile as 4 x 4 MFMA 16 x 16
+// blocks, so a K slab of 16 staged in LDS feeds 64 MFMAs per wave (twice the
+// flops per staged byte of the 64 x 64 tile).  Same operand layouts, batch
+// map, split-K partials and block skipping as k_gemm.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const double* __restrict__ A, long long lda,
+                                                 long long sA, const double* __restrict__ B, long long ldb,
+                                                 long long sB, double* __restrict__ C, long long ldc, long long sC,
+                                                 double alpha, double beta, int ksplit, int kchunk,
+                                                 double* __restrict__ part, BatchMap bm) {
+  constexpr int TM = 128, TN = 128, TK = 16;
+  constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  const int bz = blockIdx.z;
+  const int bt = bz / ksplit;
+  const int ks = bz - bt * ksplit;
+  const long long tg = bm.tbase + bt;
+  A += bm.a_off(tg, sA);
+  B += bm.b_off(tg, sB);
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = ks * kchunk;
+  const int ke = min(k, kb + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // MFMA blocks of this wave that touch the output (wave-uniform)
+  bool rv[4], cv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rv[i] = m0 + wm * 64 + i * 16 < m;
+    cv[i] = n0 + wn * 64 + i * 16 < n;
+  }
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double pa[RA], pb[RB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
+      const int gi = m0 + i, gk = k0 + kk;
+      pa[r] = (gi < m && gk < ke) ? (TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
+      const int gk = k0 + kk, gj = n0 + j;
+      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
+      As[kk][i] = pa[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
+      Bs[kk][j] = pb[r];
+    }
+    __syncthreads();
+    if (k0 + TK < ke) fetch(k0 + TK);
+#pragma unroll
+    for (int kq = 0; kq < TK; kq += 4) {
+      const int kk = kq + (lane >> 4);
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (rv[i] && cv[j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const double v = acc[i][j][r];
+          if (part != nullptr) {
+            part[((long long)bz * m + row) * n + col] = v;
+          } else {
+            double* c = C + bm.c_off(tg, sC) + (long long)row * ldc + col;
+            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+          }
+        }
+      }
+}
+
 // Reduced-precision variant for the mixed-precision solve: FP64 operands
 // in memory, rounded to FP32 (BF = false) or BF16 (BF = true) when staged,
 // products accumulated in FP32 on MFMA, the sum stored as FP64.  Tile
@@ -337,13 +448,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
 // Wave layout of k_gemm for one matrix's shape: outputs of at most 32 x 32
 // split K four ways inside the block, narrow outputs stack the waves along
 // the long side, the rest use the 2 x 2 layout of 64 x 64 tiles.
+// {4, 4} stands for k_gemm128 (128 x 128 tiles, 64 x 64 per wave).
 struct GemmLayout {
   int wm, wn;
   int tm() const { return 32 * wm; }
   int tn() const { return 32 * wn; }
-  int tk() const { return 16 * (4 / (wm * wn)); }
+  int tk() const { return wm * wn == 16 ? 16 : 16 * (4 / (wm * wn)); }
 };
 GemmLayout gemm_layout(const Gemm& g) {
+  if (g.m >= 128 && g.n >= 128) return {4, 4};
   if (g.m <= 32 && g.n <= 32) return {1, 1};
   if (g.n <= 32) return g.m <= 64 ? GemmLayout{2, 1} : GemmLayout{4, 1};
   if (g.m <= 32) return g.n <= 64 ? GemmLayout{1, 2} : GemmLayout{1, 4};
@@ -1273,6 +1386,10 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     else if (lay.wm == 4 && lay.wn == 1) LRFG_GEMM_F64(TA, TB, 4, 1);                                         \
     else if (lay.wm == 1 && lay.wn == 2) LRFG_GEMM_F64(TA, TB, 1, 2);                                         \
     else if (lay.wm == 1 && lay.wn == 4) LRFG_GEMM_F64(TA, TB, 1, 4);                                         \
+    else if (lay.wm == 4 && lay.wn == 4)                                                                      \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm128<TA, TB>), grid, dim3(256),   \
+                        0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
+                        ks, kchunk, part, bm);                                                               \
     else LRFG_GEMM_F64(TA, TB, 2, 2);                                                                         \
   } while (0)
     if (!c.ta && !c.tb) LRFG_GEMM_LAUNCH(false, false);
