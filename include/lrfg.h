@@ -368,17 +368,24 @@ int lrfg_compress_tucker(const int N[3], const double* a, int cap, double tol, i
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching on one device.
- * `slots` worker threads (each with its own HIP stream at the default
- * priority) admit queued requests while the caller's device pool
- * (d_pool, pool_bytes, 256-byte aligned, owned by the caller and untouched
- * outside the requests' workspaces) has room for their workspace: the
- * oldest request that fits is taken with the other queued requests of the
- * same problem, fields and coefficient ranks, up to max_batch of them, and
- * solved as one lrfg_solve_batch (a low-rank batch holds at most 256
- * correctors, so at most 256 / nE requests).  Requests arriving while
- * others run join the next batch a worker forms; batches on different
- * streams overlap on the device.  Results equal those of lrfg_solve up to
- * rounding.
+ * Requests wait in a queue until the caller's device pool (d_pool,
+ * pool_bytes, 256-byte aligned, owned by the caller and untouched outside
+ * the requests' workspaces) has room for their workspace: the oldest
+ * request that fits is taken with the other queued requests of the same
+ * problem, fields and coefficient ranks, up to max_batch of them (a
+ * low-rank batch holds at most 256 correctors, so at most 256 / nE
+ * requests), and becomes a session solved as one lrfg_solve_batch on a host
+ * thread and HIP stream (default priority) of its own.  Sessions share
+ * `slots` device permits, granted in arrival order; a session gives its
+ * permit back between iterations (every iteration of the low-rank solvers,
+ * every four of the full-grid PCG) and queues for it again, so sessions run
+ * in turns of iteration blocks and up to `slots` of them have work on the
+ * device at once.  Admission happens at once while a permit is free and
+ * otherwise at the next such block boundary: a request that arrives while
+ * others run joins the rotation there (with the requests queued meanwhile,
+ * batched), and a finished session leaves it there, without waiting for
+ * other solves to end.  At most 4 slots sessions are admitted at a time.
+ * Results equal those of lrfg_solve up to rounding.
  * ---------------------------------------------------------------------- */
 typedef struct lrfg_server lrfg_server;
 
@@ -392,8 +399,9 @@ typedef struct {
   size_t workspace_bytes; /* pool bytes its batch held                      */
 } lrfg_completion;
 
-/* Start the loop on `device`; slots in [1, 16], max_batch >= 1.  Returns
- * LRFG_EINVAL for bad arguments, LRFG_EDEVICE for a missing device. */
+/* Start the loop on `device` with `slots` device permits (in [1, 16]) and
+ * batches of up to max_batch (>= 1) requests.  Returns LRFG_EINVAL for bad
+ * arguments, LRFG_EDEVICE for a missing device. */
 int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_t pool_bytes,
                        lrfg_server** out);
 

@@ -246,10 +246,11 @@ class Completion:
 
 
 class Server:
-    """Continuous-batching request loop (lrfg_server_*): `slots` worker
-    threads with their own HIP streams admit queued requests by workspace
-    footprint in a device pool of pool_bytes, batching queued requests of the
-    same problem (up to max_batch microstructures per solve)."""
+    """Continuous-batching request loop (lrfg_server_*): queued requests are
+    admitted by workspace footprint in a device pool of pool_bytes, batched
+    with queued requests of the same problem (up to max_batch per solve), and
+    run as sessions on their own threads and HIP streams that share `slots`
+    device permits in turns of iteration blocks."""
 
     def __init__(self, slots: int = 2, max_batch: int = 8, pool_bytes: int = 8 << 30, device: str = "cuda:0"):
         torch = _torch()

@@ -43,6 +43,22 @@ void clear_error();
     }                                                                         \
   } while (0)
 
+// ---------------------------------------------------------------- iteration gate
+// A solve running on a thread with a gate installed (the serving loop's
+// session threads) calls pass(ctx) between iterations, at host points where
+// none of its device work is being waited for: the scheduler may hand the
+// device to other solves there (continuous batching between iteration
+// blocks).  No gate is installed outside the serving loop.
+struct IterGate {
+  void (*pass)(void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+IterGate*& iter_gate();
+inline void gate_point() {
+  IterGate* g = iter_gate();
+  if (g != nullptr && g->pass != nullptr) g->pass(g->ctx);
+}
+
 // ---------------------------------------------------------------- workspace
 // Bump allocator over the caller's workspace.  In "measure" mode (base ==
 // nullptr) it only accumulates the size, so the same code path computes the

@@ -721,6 +721,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   bool all_done = false;
   int checked = -1;
   for (it = 0; it < A.max_iter; ++it) {
+    if (it > 0 && it % 4 == 0) gate_point();  // between blocks of 4 iterations (the flag ring's depth)
     // P1
     {
       ProfScope ps_("grad_axis1", s);

@@ -795,6 +795,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     }
     LRFG_TRY(upload_done(hdone));
     for (int it = 0; it < max_it; ++it) {
+      if (it > 0) gate_point();
       bool all = true;
       for (int e = 0; e < nE; ++e) all = all && hdone[e];
       if (all) break;
@@ -1574,6 +1575,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     }
     LRFG_TRY(upload_done(hdone));
     for (int it = 0; it < max_it; ++it) {
+      if (it > 0) gate_point();
       bool all = true;
       for (int e = 0; e < nE; ++e) all = all && hdone[e];
       if (all) break;

@@ -1,15 +1,19 @@
 // Request loop with continuous batching on one device (host runtime).
 //
 // Requests are homogenisation queries (a problem, its coefficient in place,
-// the fields E).  Worker threads, each with its own HIP stream, admit
-// queued requests while the caller's device pool has room for their
-// workspace (admission by HBM footprint, first fit): the oldest request that
-// fits is taken together with the other queued requests of the same problem
-// (and coefficient ranks and fields), up to max_batch of them, and solved as
-// one lrfg_solve_batch.  A request that arrives while others run joins the
-// next batch a worker forms; batches on different streams overlap on the
-// device.  The coefficient data is read where the caller keeps it (device
-// pointers stay on the device).
+// the fields E).  An admission thread takes queued requests while the
+// caller's device pool has room for their workspace (admission by HBM
+// footprint, first fit): the oldest request that fits, together with the
+// other queued requests of the same problem (and coefficient ranks and
+// fields), up to max_batch of them, becomes one session solved as one
+// lrfg_solve_batch on a thread and HIP stream of its own.  The sessions
+// share `slots` device permits handed out in arrival order: a session holds
+// one while it runs a block of iterations and gives it back at every
+// iteration gate of the solve, so a request admitted while others run joins
+// the rotation at the next block boundary, and a finished one leaves it
+// there, instead of waiting for whole solves to end; up to `slots`
+// sessions have work on the device at once.  The coefficient data is read
+// where the caller keeps it (device pointers stay on the device).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -24,6 +28,12 @@
 #include "lowrank.h"
 
 namespace lrfg {
+
+IterGate*& iter_gate() {
+  thread_local IterGate* g = nullptr;
+  return g;
+}
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -121,6 +131,8 @@ bool same_batch_key(const Request& x, const Request& y) {
 struct lrfg_server {
   int device = 0;
   int max_batch = 1;
+  int slots = 1;
+  int max_sessions = 4;
   char* pool_base = nullptr;
   std::unique_ptr<lrfg::Pool> pool;
   size_t pool_bytes = 0;
@@ -128,62 +140,71 @@ struct lrfg_server {
   std::condition_variable cv_work, cv_done;
   std::deque<std::unique_ptr<lrfg::Request>> queue;
   std::deque<lrfg_completion> done;
-  int running = 0;
+  int running = 0;  // sessions admitted and not yet completed
+  uint64_t gates = 0;   // iteration gates passed by the sessions
   bool stopping = false;
-  std::vector<std::thread> workers;
+  std::thread admitter;
   int worker_error = LRFG_OK;
+  // device permits, granted in request order
+  std::mutex pmu;
+  std::condition_variable pcv;
+  int permits = 1;
+  std::deque<uint64_t> waiting;
+  uint64_t next_ticket = 0;
 };
 
 namespace lrfg {
 namespace {
 
-void worker_main(lrfg_server* S) {
-  hipStream_t st = nullptr;
-  if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+// FIFO permits: a thread waits until it is the oldest waiter and a permit
+// is free.
+void permit_acquire(lrfg_server* S) {
+  std::unique_lock<std::mutex> lk(S->pmu);
+  const uint64_t me = S->next_ticket++;
+  S->waiting.push_back(me);
+  S->pcv.wait(lk, [&] { return S->permits > 0 && S->waiting.front() == me; });
+  S->waiting.pop_front();
+  --S->permits;
+  S->pcv.notify_all();
+}
+void permit_release(lrfg_server* S) {
+  std::lock_guard<std::mutex> lk(S->pmu);
+  ++S->permits;
+  S->pcv.notify_all();
+}
+// Iteration gate of a session: give the permit back and queue for it again.
+void session_gate(void* ctx) {
+  auto* S = static_cast<lrfg_server*>(ctx);
+  {
+    // a block boundary: the admission may let queued requests join here
     std::lock_guard<std::mutex> lk(S->mu);
-    S->worker_error = LRFG_EDEVICE;
-    S->cv_done.notify_all();
-    return;
+    ++S->gates;
   }
-  std::unique_lock<std::mutex> lk(S->mu);
-  for (;;) {
-    // admission: the oldest request whose batch workspace fits, plus queued
-    // requests with the same key
-    std::vector<std::unique_ptr<Request>> batch;
-    size_t off = 0, bytes = 0;
-    for (;;) {
-      if (S->stopping && S->queue.empty()) break;
-      for (size_t hi = 0; hi < S->queue.size(); ++hi) {
-        Request& head = *S->queue[hi];
-        if (head.ws_one > S->pool->largest()) continue;
-        std::vector<size_t> pick = {hi};
-        size_t need = head.ws_one;
-        if (head.p.format != LRFG_FORMAT_FULL) {  // Tucker batches run one microstructure at a time
-          // a low-rank batch holds at most kMaxSystems correctors
-          const int cap = std::max(1, std::min(S->max_batch, kMaxSystems / head.nE));
-          for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < cap; ++j) {
-            if (!same_batch_key(head, *S->queue[j])) continue;
-            size_t more = 0;
-            if (lrfg_plan_workspace_bytes(head.plan, (int)(pick.size() + 1) * head.nE, &more) != LRFG_OK) break;
-            if (more > S->pool->largest()) break;
-            pick.push_back(j);
-            need = more;
-          }
-        }
-        if (!S->pool->alloc(need, &off)) continue;
-        bytes = need;
-        for (size_t k = 0; k < pick.size(); ++k) batch.push_back(std::move(S->queue[pick[k]]));
-        for (size_t k = pick.size(); k-- > 0;) S->queue.erase(S->queue.begin() + (long)pick[k]);
-        break;
-      }
-      if (!batch.empty()) break;
-      S->cv_work.wait(lk);
-    }
-    if (batch.empty()) break;  // stopping and drained
-    ++S->running;
-    lk.unlock();
+  S->cv_work.notify_all();
+  permit_release(S);
+  permit_acquire(S);
+}
 
-    const Clock::time_point t0 = Clock::now();
+struct Session {
+  std::vector<std::unique_ptr<Request>> batch;
+  size_t off = 0, bytes = 0;
+};
+
+void session_main(lrfg_server* S, Session* se) {
+  std::unique_ptr<Session> own(se);
+  auto& batch = se->batch;
+  hipStream_t st = nullptr;
+  int rc = LRFG_OK;
+  Clock::time_point t0 = Clock::now(), t1 = t0;
+  if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    rc = LRFG_EDEVICE;
+  } else {
+    IterGate gate;
+    gate.pass = session_gate;
+    gate.ctx = S;
+    iter_gate() = &gate;
+    permit_acquire(S);
+    t0 = Clock::now();
     std::vector<lrfg_coeff> coeffs(batch.size());
     std::vector<lrfg_result> res(batch.size());
     for (size_t k = 0; k < batch.size(); ++k) {
@@ -191,48 +212,108 @@ void worker_main(lrfg_server* S) {
       res[k] = *batch[k]->out;
     }
     Request& h = *batch[0];
-    const int nE = h.nE;
     const double* E = h.E.empty() ? nullptr : h.E.data();
-    // the coefficients are read on this worker's stream: wait until the
+    // the coefficients are read on this session's stream: wait until the
     // work that produced them on the submitters' streams is done
     for (size_t k = 0; k < batch.size(); ++k)
       if (batch[k]->ready != nullptr) (void)hipStreamWaitEvent(st, batch[k]->ready, 0);
-    const int rc = lrfg_solve_batch(h.plan, coeffs.data(), (int)batch.size(), E, nE, S->pool_base + off, bytes, st,
-                                    res.data());
-    const Clock::time_point t1 = Clock::now();
-
-    lk.lock();
-    S->pool->release(off, bytes);
-    --S->running;
-    for (size_t k = 0; k < batch.size(); ++k) {
-      Request& r = *batch[k];
-      *r.out = res[k];
-      lrfg_completion c;
-      c.tag = r.tag;
-      int st_k = rc;
-      if (rc >= 0) {
-        st_k = LRFG_OK;
-        if (r.out->status != nullptr)
-          for (int e = 0; e < nE; ++e)
-            if (r.out->status[e] != LRFG_OK) st_k = LRFG_NOT_CONVERGED;
-      }
-      c.status = st_k;
-      c.batch_size = (int)batch.size();
-      c.queue_ms = ms_between(r.t_submit, t0);
-      c.run_ms = ms_between(t0, t1);
-      c.total_ms = ms_between(r.t_submit, t1);
-      c.workspace_bytes = bytes;
-      S->done.push_back(c);
-      lrfg_plan_destroy(r.plan);
-      r.plan = nullptr;
-      if (r.ready != nullptr) (void)hipEventDestroy(r.ready);
-      r.ready = nullptr;
-    }
-    S->cv_done.notify_all();
-    S->cv_work.notify_all();
+    rc = lrfg_solve_batch(h.plan, coeffs.data(), (int)batch.size(), E, h.nE, S->pool_base + se->off, se->bytes, st,
+                          res.data());
+    t1 = Clock::now();
+    permit_release(S);
+    iter_gate() = nullptr;
+    for (size_t k = 0; k < batch.size(); ++k) *batch[k]->out = res[k];
   }
-  lk.unlock();
-  (void)hipStreamDestroy(st);
+  if (st != nullptr) (void)hipStreamDestroy(st);
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->pool->release(se->off, se->bytes);
+  const int nE = batch[0]->nE;
+  for (size_t k = 0; k < batch.size(); ++k) {
+    Request& r = *batch[k];
+    lrfg_completion c;
+    c.tag = r.tag;
+    int st_k = rc;
+    if (rc >= 0) {
+      st_k = LRFG_OK;
+      if (r.out->status != nullptr)
+        for (int e = 0; e < nE; ++e)
+          if (r.out->status[e] != LRFG_OK) st_k = LRFG_NOT_CONVERGED;
+    }
+    c.status = st_k;
+    c.batch_size = (int)batch.size();
+    c.queue_ms = ms_between(r.t_submit, t0);
+    c.run_ms = ms_between(t0, t1);
+    c.total_ms = ms_between(r.t_submit, t1);
+    c.workspace_bytes = se->bytes;
+    S->done.push_back(c);
+    lrfg_plan_destroy(r.plan);
+    r.plan = nullptr;
+    if (r.ready != nullptr) (void)hipEventDestroy(r.ready);
+    r.ready = nullptr;
+  }
+  --S->running;
+  // notified under the lock: the server is not released before this
+  // thread has let go of it
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+}
+
+void admitter_main(lrfg_server* S) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  uint64_t seen = 0;  // gate count at the last admission
+  for (;;) {
+    // admission: the oldest request whose batch workspace fits, plus queued
+    // requests with the same key.  With a device permit free it happens at
+    // once; otherwise at the next iteration gate of a running session (the
+    // new session then queues for the permit that gate hands on), so that
+    // requests arriving in between are batched together.
+    std::unique_ptr<Session> se;
+    for (;;) {
+      if (S->stopping && S->queue.empty()) break;
+      const bool now = S->running < S->slots || S->gates != seen || S->stopping;
+      if (now && S->running < S->max_sessions) {
+        for (size_t hi = 0; hi < S->queue.size(); ++hi) {
+          Request& head = *S->queue[hi];
+          if (head.ws_one > S->pool->largest()) continue;
+          std::vector<size_t> pick = {hi};
+          size_t need = head.ws_one;
+          if (head.p.format != LRFG_FORMAT_FULL) {  // Tucker batches run one microstructure at a time
+            // a low-rank batch holds at most kMaxSystems correctors
+            const int cap = std::max(1, std::min(S->max_batch, kMaxSystems / head.nE));
+            for (size_t j = hi + 1; j < S->queue.size() && (int)pick.size() < cap; ++j) {
+              if (!same_batch_key(head, *S->queue[j])) continue;
+              size_t more = 0;
+              if (lrfg_plan_workspace_bytes(head.plan, (int)(pick.size() + 1) * head.nE, &more) != LRFG_OK) break;
+              if (more > S->pool->largest()) break;
+              pick.push_back(j);
+              need = more;
+            }
+          }
+          size_t off = 0;
+          if (!S->pool->alloc(need, &off)) continue;
+          se.reset(new Session());
+          se->off = off;
+          se->bytes = need;
+          for (size_t k = 0; k < pick.size(); ++k) se->batch.push_back(std::move(S->queue[pick[k]]));
+          for (size_t k = pick.size(); k-- > 0;) S->queue.erase(S->queue.begin() + (long)pick[k]);
+          break;
+        }
+      }
+      if (se) break;
+      S->cv_work.wait(lk);
+    }
+    if (!se) break;  // stopping and drained
+    seen = S->gates;
+    ++S->running;
+    try {
+      std::thread(session_main, S, se.release()).detach();
+    } catch (...) {
+      --S->running;
+      S->worker_error = LRFG_EDEVICE;
+      S->cv_done.notify_all();
+      break;
+    }
+  }
 }
 
 }  // namespace
@@ -256,10 +337,13 @@ int lrfg_server_create(int device, int slots, int max_batch, void* d_pool, size_
   auto* S = new lrfg_server();
   S->device = device;
   S->max_batch = max_batch;
+  S->slots = slots;
+  S->permits = slots;
+  S->max_sessions = 4 * slots;
   S->pool_base = static_cast<char*>(d_pool);
   S->pool_bytes = pool_bytes;
   S->pool.reset(new Pool(pool_bytes));
-  for (int i = 0; i < slots; ++i) S->workers.emplace_back(worker_main, S);
+  S->admitter = std::thread(admitter_main, S);
   *out = S;
   return LRFG_OK;
 }
@@ -354,7 +438,12 @@ void lrfg_server_destroy(lrfg_server* S) {
     S->stopping = true;
   }
   S->cv_work.notify_all();
-  for (auto& t : S->workers) t.join();
+  S->admitter.join();
+  {
+    // every admitted session has completed (and let go of the server)
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->running == 0; });
+  }
   for (auto& r : S->queue) {
     if (r->plan) lrfg_plan_destroy(r->plan);
     if (r->ready) (void)hipEventDestroy(r->ready);

@@ -294,3 +294,31 @@ def test_server_caps_batches_at_the_system_limit(dev):
     assert all(c.status == want.rc for c in done)
     for c in done:
         assert _rel(c.result.A_H, want.A_H) <= MIX_TOL
+
+
+def test_server_joins_between_iteration_blocks(dev):
+    """One device permit (slots = 1): a short request submitted while a long
+    solve runs joins at the long solve's next iteration gate and completes
+    before it (with whole-solve scheduling it would wait for the long
+    one); both results equal their solo solves."""
+    long_prob = dict(d=3, N=(81,) * 3, format="tt", rank_cap=24, solver_tol=1e-14, max_iter=80, coeff_rank=9)
+    cpl = _smooth(81, 1, 10.0)
+    short_prob = dict(d=2, N=(15, 15), format="tt", rank_cap=15, solver_tol=1e-8, max_iter=100, coeff_rank=2)
+    cps = W.square_cp(15, 2)
+    want_l = _alone([(long_prob, cpl)], dev)[0]
+    want_s = _alone([(short_prob, cps)], dev)[0]
+    srv = P.Server(slots=1, max_batch=1, pool_bytes=4 << 30)
+    srv.submit(long_prob, cp=(cpl.weights, cpl.factors), tag=0)
+    time.sleep(0.05)
+    srv.submit(short_prob, cp=(cps.weights, cps.factors), tag=1)
+    done = srv.drain()
+    srv.close()
+    by = {c.tag: c for c in done}
+    print({c.tag: (c.queue_ms, c.run_ms, c.total_ms, list(c.result.iters)) for c in done})
+    assert [c.tag for c in done].index(1) < [c.tag for c in done].index(0)
+    assert by[1].total_ms < by[0].total_ms
+    assert by[0].run_ms > 50.0
+    for tag, want in ((0, want_l), (1, want_s)):
+        assert by[tag].status == want.rc
+        assert _rel(by[tag].result.A_H, want.A_H) <= MIX_TOL
+        assert list(by[tag].result.iters) == list(want.iters)
