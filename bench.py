@@ -245,35 +245,51 @@ def profiled(run, tag, solves):
 
 
 def serving_leg(nreq, nmax, capmax, dev):
-    """Request stream of mixed homogenisation queries through the
-    continuous-batching loop: saturated throughput (all queued at once),
-    then Poisson arrivals at 0.7x that rate (p50/p99 latency); and a
-    same-shape stream (16 smooth 135^3 microstructures, cap 16) solved one
-    by one, on four concurrent streams, and in batches of 8.  Grids and rank
-    caps are bounded (defaults N <= 135, cap <= 20) so that the leg takes
-    seconds; --serve-nmax 405 --serve-capmax 60 gives the full request
-    distribution."""
+    """Request stream of the serving distribution (workloads.serving_requests,
+    seed 0: N odd uniform in [45, nmax], ball or smooth coefficient, contrast
+    log-uniform in [2, 100], TT rank cap uniform in [10, capmax]) through the
+    continuous-batching loop: saturated throughput (all queued at once), then
+    Poisson arrivals at 0.7x that rate (p50/p99 latency); and a same-shape
+    stream (16 smooth 135^3 microstructures, cap 16) solved one by one, on
+    four permits, and in batches of 8.  Ball requests carry the exact tensor
+    train of their nodal field (compressed on the device once per request,
+    before the timed runs; ranks about 0.3 N), smooth ones their CP factors
+    (rank 9); both stay on the device."""
     import torch
 
     import paper_1902_07455_amd as P
     import workloads as W
 
-    def problem(req):
-        return dict(d=3, N=(req.N,) * 3, format="tt", rank_cap=req.rank_cap, solver_tol=1e-3, max_iter=200,
-                    coeff_rank=9 if req.kind == "smooth" else 2)
-
-    def coeffs(reqs):
+    def build(reqs):
         out = []
         for q in reqs:
-            cp = W.request_coeff(q)
-            out.append((torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors]))
+            if q.kind == "ball":
+                a = torch.from_numpy(W.request_ball(q)).to(dev)
+                # exact: the ball's TT ranks (distinct |x_1| inside, plus one) are at most
+                # 123 for N <= 405, within the 128-column sketch
+                cap = min(q.N, 123)
+                cores, kept = P.compress_tt(a, cap=cap, tol=1e-12, oversample=min(10, 128 - cap), seed=q.rid)
+                k1, k2 = kept
+                tt = [cores[0][:, :, :k1].contiguous(), cores[1][:k1, :, :k2].contiguous(),
+                      cores[2][:k2].contiguous()]
+                del a, cores
+                out.append(("tt", tt, max(k1, k2)))
+            else:
+                cp = W.request_coeff(q)
+                out.append(("cp", (torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev)
+                                                                           for f in cp.factors]), cp.rank))
+        torch.cuda.synchronize()
         return out
 
-    def run(reqs, cps, slots, max_batch, arrivals):
-        srv = P.Server(slots=slots, max_batch=max_batch, pool_bytes=32 << 30, device=dev)
+    def problem(req, ra):
+        return dict(d=3, N=(req.N,) * 3, format="tt", rank_cap=req.rank_cap, solver_tol=1e-3, max_iter=200,
+                    coeff_rank=ra)
+
+    def run(reqs, cfs, slots, max_batch, arrivals):
+        srv = P.Server(slots=slots, max_batch=max_batch, pool_bytes=160 << 30, device=dev)
         t0 = time.perf_counter()
         done = []
-        for i, (q, (w, f)) in enumerate(zip(reqs, cps)):
+        for i, (q, (kind, c, ra)) in enumerate(zip(reqs, cfs)):
             if arrivals:
                 wait = t0 + q.arrival_s - time.perf_counter()
                 if wait > 0:
@@ -281,36 +297,37 @@ def serving_leg(nreq, nmax, capmax, dev):
                     wait = t0 + q.arrival_s - time.perf_counter()
                     if wait > 0:
                         time.sleep(wait)
-            srv.submit(problem(q), cp=(w, f), tag=i)
+            srv.submit(problem(q, ra), **{kind: c}, tag=i)
         done += srv.drain()
         span = time.perf_counter() - t0
         srv.close()
         lat = [c.total_ms for c in done]
+        nc = {k: sum(c.status != 0 and reqs[c.tag].kind == k for c in done) for k in ("ball", "smooth")}
         return {"requests": len(done), "solves_per_s": round(len(done) / span, 3),
                 "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-                "not_converged": sum(c.status != 0 for c in done),
+                "not_converged": sum(c.status != 0 for c in done), "not_converged_by_kind": nc,
                 "max_batch_seen": max(c.batch_size for c in done)}
 
     probe = W.serving_requests(nreq, 1.0, seed=0, N_lo=45, N_hi=nmax, cap_hi=capmax)
-    cps = coeffs(probe)
+    log(f"serving: building {nreq} request coefficients")
+    cfs = build(probe)
     log(f"serving: {nreq} requests, saturated")
-    sat = run(probe, cps, 4, 8, arrivals=False)
+    sat = run(probe, cfs, 4, 8, arrivals=False)
     rate = 0.7 * sat["solves_per_s"]
     reqs = W.serving_requests(nreq, rate, seed=0, N_lo=45, N_hi=nmax, cap_hi=capmax)
     log(f"serving: Poisson arrivals at {rate:.2f}/s")
-    poi = run(reqs, cps, 4, 8, arrivals=True)
+    poi = run(reqs, cfs, 4, 8, arrivals=True)
     poi["rate_per_s"] = round(rate, 3)
 
     # same-shape stream: batching proper
     N = 135
-    same = [W.ServingRequest(i, N, "smooth", 1.0, 16, 0.0) for i in range(16)]
     sc = []
-    for q in same:
-        cp = W.smooth_cp(N, W.smooth_params(q.rid))
+    for i in range(16):
+        cp = W.smooth_cp(N, W.smooth_params(i))
         sc.append((torch.from_numpy(cp.weights).to(dev), [torch.from_numpy(f).to(dev) for f in cp.factors]))
     prob = dict(d=3, N=(N,) * 3, format="tt", rank_cap=16, solver_tol=1e-2, max_iter=100, coeff_rank=9)
     res = {}
-    for name, slots, mb in (("one_by_one", 1, 1), ("four_streams", 4, 1), ("batches_of_8", 1, 8)):
+    for name, slots, mb in (("one_by_one", 1, 1), ("four_permits", 4, 1), ("batches_of_8", 1, 8)):
         srv = P.Server(slots=slots, max_batch=mb, pool_bytes=32 << 30, device=dev)
         t0 = time.perf_counter()
         for i, (w, f) in enumerate(sc):
@@ -319,13 +336,16 @@ def serving_leg(nreq, nmax, capmax, dev):
         span = time.perf_counter() - t0
         srv.close()
         res[name] = {"solves_per_s": round(len(done) / span, 3), "max_batch_seen": max(c.batch_size for c in done)}
-    return {"workload": f"{nreq} requests (workloads.serving_requests seed 0): N odd in [45, {nmax}], smooth "
-                        "(contrast-rescaled, CP rank 9) or the separable cube stand-in for the ball (rank 2), "
-                        f"contrast log-uniform [2, 100], TT rank cap in [10, {capmax}], solver tol 1e-3; 4 slots, "
-                        "batches up to 8, device-resident factors; latency = submit to completion",
+    kinds = {k: sum(q.kind == k for q in probe) for k in ("ball", "smooth")}
+    return {"workload": f"{nreq} requests (workloads.serving_requests seed 0, the first {nreq} of the stream): N odd "
+                        f"in [45, {nmax}], {kinds['ball']} balls (exact TT of the nodal field, ranks ~0.3 N) and "
+                        f"{kinds['smooth']} smooth (contrast-rescaled, CP rank 9), contrast log-uniform [2, 100], TT "
+                        f"rank cap in [10, {capmax}], solver tol 1e-3; 4 permits, batches up to 8, 160 GB pool, "
+                        "device-resident coefficients; latency = submit to completion",
+            "Ns": [q.N for q in probe], "caps": [q.rank_cap for q in probe],
             "saturated": sat, "poisson": poi,
             "same_shape_135": dict(res, workload="16 smooth 135^3 microstructures (seeds 0..15), cap 16, tol 1e-2; "
-                                                 "one slot, four slots (streams) of single solves, or one slot "
+                                                 "one permit, four permits of single solves, or one permit "
                                                  "batching 8")}
 
 
@@ -536,10 +556,10 @@ def main(argv=None):
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-tol", type=float, default=None, help="TT solver tolerance (skips the sweep)")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-nmax", type=int, default=135, help="largest grid of the serving requests")
-    ap.add_argument("--serve-capmax", type=int, default=20, help="largest rank cap of the serving requests")
+    ap.add_argument("--serve-nmax", type=int, default=405, help="largest grid of the serving requests")
+    ap.add_argument("--serve-capmax", type=int, default=60, help="largest rank cap of the serving requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale for HBM byte counters)")
     args = ap.parse_args(argv)

@@ -218,6 +218,12 @@ def cube_cp(N: int, contrast: float, half_side: float = 0.3, d: int = 3) -> CPCo
     return CPCoeff(np.array([1.0, contrast - 1.0]), [np.stack([ones, ind]) for _ in range(d)])
 
 
+def request_ball(req: "ServingRequest") -> np.ndarray:
+    """Nodal values of a ball request: the centred ball of radius 0.3 with
+    a = contrast inside and 1 outside."""
+    return ball_coeff(req.N, radius=0.3, inside=req.contrast, outside=1.0)
+
+
 def request_coeff(req: "ServingRequest") -> CPCoeff:
     """The CP coefficient of a serving request: the contrast-rescaled smooth
     family (seed = request id), or for kind "ball" its separable stand-in,
