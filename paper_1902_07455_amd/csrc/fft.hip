@@ -1,12 +1,14 @@
 // Host-side FFT plans and the generic batched line kernels
 // (lrfg_fft_lines, lrfg_mode_op).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
 
 #include "fft.h"
+#include "fft2.h"
 #include "prof.h"
 
 namespace lrfg {
@@ -49,6 +51,14 @@ int fft_plan_make(int N, FftPlan* out) {
   }
   *out = std::move(p);
   return LRFG_OK;
+}
+
+bool fft_two_level() {
+  static const bool on = [] {
+    const char* v = std::getenv("LRFG_FFT_TWO_LEVEL");
+    return v == nullptr || std::strcmp(v, "0") != 0;
+  }();
+  return on;
 }
 
 const FftPlan* fft_plan_cached(int N) {
@@ -139,6 +149,84 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
     n = tn.y;
     if (idx < total && t < tcount) x[line_addr(l0 + t, n, N, inner)] = cscale(sm[t * N + n], scale);
   }
+}
+
+// Two-level register form of k_fft_lines (fft2.h) for strided lines
+// (inner > 1) of the lengths split2_of covers.  Tile = T consecutive line
+// ids; work items are line-fast, so each load and store of a wave covers
+// T adjacent complex values per mode index.  In place: every element of
+// the tile is read in phase 1, before the barrier, and written in phase 2.
+template <int A, int B, int DIR>
+__global__ __launch_bounds__(kFftBlock) void k2_fft_lines(double2* __restrict__ x, long long nlines, int inner,
+                                                           FftDev f, double scale, const int* __restrict__ done,
+                                                           long long lines_per_flag) {
+  constexpr int N = A * B;
+  constexpr int T = split2_lines(N);
+  __shared__ double2 S[T * N];
+  __shared__ double2 tw[N];
+  const long long l0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * T;
+  const int tcount = (int)min((long long)T, nlines - l0);
+  if (done != nullptr) {
+    bool all_done = true;
+    for (long long e = l0 / lines_per_flag; e <= (l0 + tcount - 1) / lines_per_flag; ++e)
+      all_done = all_done && (done[e] != 0);
+    if (all_done) return;
+  }
+  for (int i = threadIdx.x; i < N; i += kFftBlock) tw[i] = f.tw[i];
+  __syncthreads();
+  for (int it = threadIdx.x; it < T * B; it += kFftBlock) {
+    const int t = it % T, b = it / T;
+    double2 v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      v[a] = t < tcount ? x[line_addr(l0 + t, b + B * a, N, inner)] : make_double2(0.0, 0.0);
+    split2_phase1<DIR, A, B>(v, b, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) S[(k1 * B + b) * T + t] = v[k1];
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < T * A; it += kFftBlock) {
+    const int t = it % T, k1 = it / T;
+    double2 y[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) y[b] = S[(k1 * B + b) * T + t];
+    rdft<DIR, B>(y);
+    if (t < tcount) {
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) x[line_addr(l0 + t, k1 + A * k2, N, inner)] = cscale(y[k2], scale);
+    }
+  }
+}
+
+template <int A, int B>
+int launch2_fft_lines(double2* x, long long nlines, int inner, int dir, const FftDev& f, double scale,
+                      hipStream_t s, const char* tag, const int* done, long long lines_per_flag) {
+  constexpr int T = split2_lines(A * B);
+  const int grid = ceil_div(nlines, T);
+  const double bytes = 2.0 * 16.0 * (double)nlines * (A * B);
+  if (dir < 0)
+    LRFG_LAUNCH_TIMED(tag, bytes, (k2_fft_lines<A, B, -1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner, f,
+                      scale, done, lines_per_flag);
+  else
+    LRFG_LAUNCH_TIMED(tag, bytes, (k2_fft_lines<A, B, 1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner, f,
+                      scale, done, lines_per_flag);
+  LRFG_LAUNCHED();
+  return LRFG_OK;
+}
+
+// The two-level kernels for N = A B (split2_of), or LRFG_EUNSUPPORTED.
+int launch2_fft_lines_any(double2* x, long long nlines, int N, int inner, int dir, const FftDev& f, double scale,
+                          hipStream_t s, const char* tag, const int* done, long long lines_per_flag) {
+#define LRFG_S2(NN)                                                                                          \
+  case NN:                                                                                                   \
+    return launch2_fft_lines<split2_of(NN).A, split2_of(NN).B>(x, nlines, inner, dir, f, scale, s, tag, done, \
+                                                               lines_per_flag);
+  switch (N) {
+    LRFG_S2(45) LRFG_S2(75) LRFG_S2(81) LRFG_S2(135) LRFG_S2(225) LRFG_S2(243) LRFG_S2(405) LRFG_S2(675)
+    LRFG_S2(729)
+    default: return LRFG_EUNSUPPORTED;
+  }
+#undef LRFG_S2
 }
 
 // Fibre pairs: the F fibres of each system are paired among themselves
@@ -381,6 +469,8 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
   }
+  if (inner > 1 && split2_of(N).A > 0 && fft_two_level())
+    return launch2_fft_lines_any(x, nlines, N, (int)inner, dir, f, scale, s, tag, done, lines_per_flag);
   const int T = lines_per_tile1(N);
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(nlines, T);

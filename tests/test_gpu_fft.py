@@ -12,7 +12,7 @@ LENGTHS = [1, 3, 5, 7, 9, 11, 13, 15, 25, 27, 45, 49, 81, 121, 125, 135, 243, 40
 
 
 # the largest lengths only with few lines, to keep the test short
-FFT_CASES = [(N, o, i) for N in LENGTHS for (o, i) in [(1, 1), (3, 1), (2, 37), (5, 16), (1, 100)]
+FFT_CASES = [(N, o, i) for N in LENGTHS for (o, i) in [(1, 1), (3, 1), (2, 37), (5, 16), (1, 100), (2, 13)]
              if N < 401 or o * i <= 40]
 
 
