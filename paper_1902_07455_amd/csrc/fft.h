@@ -44,7 +44,7 @@ int fft_plan_make(int N, FftPlan* out);
 const FftPlan* fft_plan_cached(int N);
 int fft_dev_upload(const FftPlan& p, double2* d_table, hipStream_t s, FftDev* out);
 // Whether the full-grid passes and strided line transforms use the
-// two-level register kernels (fft2.h) for the lengths they cover; set
+// register kernels (fft2.h) for the lengths they cover; set
 // LRFG_FFT_TWO_LEVEL=0 in the environment for the Stockham LDS kernels
 // everywhere (read once per process).
 bool fft_two_level();

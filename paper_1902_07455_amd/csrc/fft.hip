@@ -151,17 +151,20 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_lines(double2* __restrict__ x
   }
 }
 
-// Two-level register form of k_fft_lines (fft2.h) for strided lines
-// (inner > 1) of the lengths split2_of covers.  Tile = T consecutive line
-// ids; work items are line-fast, so each load and store of a wave covers
-// T adjacent complex values per mode index.  In place: every element of
-// the tile is read in phase 1, before the barrier, and written in phase 2.
-template <int A, int B, int DIR>
-__global__ __launch_bounds__(kFftBlock) void k2_fft_lines(double2* __restrict__ x, long long nlines, int inner,
+// Register form of k_fft_lines (fft2.h) for strided lines (inner > 1) of
+// the lengths split_of covers.  Tile = T consecutive line ids; work items
+// are line-fast, so each load and store of a wave covers T adjacent
+// complex values per mode index.  Addresses are 32-bit byte offsets from
+// the tile's first outer block (the launcher checks they fit).  In place:
+// every element of the tile is read in stage 1, before the first barrier,
+// and written in the last stage.
+template <int A, int B, int C, int DIR>
+__global__ __launch_bounds__(kFftBlock) void k3_fft_lines(double2* __restrict__ x, long long nlines, int inner,
                                                            FftDev f, double scale, const int* __restrict__ done,
                                                            long long lines_per_flag) {
-  constexpr int N = A * B;
-  constexpr int T = split2_lines(N);
+  constexpr int N = A * B * C;
+  constexpr int T = split_lines(N);
+  using F = Fft3<A, B, C, DIR, T, false, kFftBlock>;
   __shared__ double2 S[T * N];
   __shared__ double2 tw[N];
   const long long l0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * T;
@@ -172,61 +175,73 @@ __global__ __launch_bounds__(kFftBlock) void k2_fft_lines(double2* __restrict__ 
       all_done = all_done && (done[e] != 0);
     if (all_done) return;
   }
+  const unsigned in = (unsigned)inner;
+  const unsigned o0 = (unsigned)l0 / in;
+  double2* base = x + (long long)o0 * N * inner;
   for (int i = threadIdx.x; i < N; i += kFftBlock) tw[i] = f.tw[i];
   __syncthreads();
-  for (int it = threadIdx.x; it < T * B; it += kFftBlock) {
-    const int t = it % T, b = it / T;
+  for (int it = threadIdx.x; it < F::I1; it += kFftBlock) {
+    int t, j;
+    F::item1(it, t, j);
+    const bool ok = t < tcount;
+    const unsigned l = (unsigned)l0 + (unsigned)t, o = l / in;
+    const unsigned lo = (o - o0) * (unsigned)N * in + (l - o * in);
     double2 v[A];
 #pragma unroll
     for (int a = 0; a < A; ++a)
-      v[a] = t < tcount ? x[line_addr(l0 + t, b + B * a, N, inner)] : make_double2(0.0, 0.0);
-    split2_phase1<DIR, A, B>(v, b, tw);
-#pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) S[(k1 * B + b) * T + t] = v[k1];
+      v[a] = ok ? ld32(base, (lo + (unsigned)(j + F::M * a) * in) * 16u) : make_double2(0.0, 0.0);
+    F::stage1(v, t, j, S, tw);
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < T * A; it += kFftBlock) {
-    const int t = it % T, k1 = it / T;
-    double2 y[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) y[b] = S[(k1 * B + b) * T + t];
-    rdft<DIR, B>(y);
+  F::stage2(S, tw);
+  __syncthreads();
+  for (int it = threadIdx.x; it < F::IL; it += kFftBlock) {
+    int t, k1, k2;
+    F::itemL(it, t, k1, k2);
+    double2 z[F::R];
+    F::last(z, t, k1, k2, S);
     if (t < tcount) {
+      const unsigned l = (unsigned)l0 + (unsigned)t, o = l / in;
+      const unsigned lo = (o - o0) * (unsigned)N * in + (l - o * in);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) x[line_addr(l0 + t, k1 + A * k2, N, inner)] = cscale(y[k2], scale);
+      for (int r = 0; r < F::R; ++r)
+        st32(base, (lo + (unsigned)F::out_n(k1, k2, r) * in) * 16u, cscale(z[r], scale));
     }
   }
 }
 
-template <int A, int B>
-int launch2_fft_lines(double2* x, long long nlines, int inner, int dir, const FftDev& f, double scale,
+template <int A, int B, int C>
+int launch3_fft_lines(double2* x, long long nlines, int inner, int dir, const FftDev& f, double scale,
                       hipStream_t s, const char* tag, const int* done, long long lines_per_flag) {
-  constexpr int T = split2_lines(A * B);
+  constexpr int N = A * B * C;
+  constexpr int T = split_lines(N);
   const int grid = ceil_div(nlines, T);
-  const double bytes = 2.0 * 16.0 * (double)nlines * (A * B);
+  const double bytes = 2.0 * 16.0 * (double)nlines * N;
   if (dir < 0)
-    LRFG_LAUNCH_TIMED(tag, bytes, (k2_fft_lines<A, B, -1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner, f,
-                      scale, done, lines_per_flag);
+    LRFG_LAUNCH_TIMED(tag, bytes, (k3_fft_lines<A, B, C, -1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner,
+                      f, scale, done, lines_per_flag);
   else
-    LRFG_LAUNCH_TIMED(tag, bytes, (k2_fft_lines<A, B, 1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner, f,
-                      scale, done, lines_per_flag);
+    LRFG_LAUNCH_TIMED(tag, bytes, (k3_fft_lines<A, B, C, 1>), dim3(grid), dim3(kFftBlock), 0, s, x, nlines, inner,
+                      f, scale, done, lines_per_flag);
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
-// The two-level kernels for N = A B (split2_of), or LRFG_EUNSUPPORTED.
-int launch2_fft_lines_any(double2* x, long long nlines, int N, int inner, int dir, const FftDev& f, double scale,
+// The register kernels for N in split_of's table (LRFG_EUNSUPPORTED
+// otherwise, or when a tile's byte offsets would not fit 32 bits).
+int launch3_fft_lines_any(double2* x, long long nlines, int N, int inner, int dir, const FftDev& f, double scale,
                           hipStream_t s, const char* tag, const int* done, long long lines_per_flag) {
-#define LRFG_S2(NN)                                                                                          \
-  case NN:                                                                                                   \
-    return launch2_fft_lines<split2_of(NN).A, split2_of(NN).B>(x, nlines, inner, dir, f, scale, s, tag, done, \
-                                                               lines_per_flag);
+  if ((long long)(split_lines(N) + 1) * N * inner * 16 >= (1ll << 32)) return LRFG_EUNSUPPORTED;
+#define LRFG_S3(NN)                                                                                         \
+  case NN:                                                                                                  \
+    return launch3_fft_lines<split_of(NN).A, split_of(NN).B, split_of(NN).C>(x, nlines, inner, dir, f, scale, s, \
+                                                                              tag, done, lines_per_flag);
   switch (N) {
-    LRFG_S2(45) LRFG_S2(75) LRFG_S2(81) LRFG_S2(135) LRFG_S2(225) LRFG_S2(243) LRFG_S2(405) LRFG_S2(675)
-    LRFG_S2(729)
+    LRFG_S3(45) LRFG_S3(75) LRFG_S3(81) LRFG_S3(135) LRFG_S3(225) LRFG_S3(243) LRFG_S3(405) LRFG_S3(675)
+    LRFG_S3(729)
     default: return LRFG_EUNSUPPORTED;
   }
-#undef LRFG_S2
+#undef LRFG_S3
 }
 
 // Fibre pairs: the F fibres of each system are paired among themselves
@@ -469,8 +484,9 @@ int launch_fft_lines(double2* x, long long outer, int N, long long inner, int di
     set_error("FFT length %d above %d", N, kFftMaxE * kFftBlock);
     return LRFG_EUNSUPPORTED;
   }
-  if (inner > 1 && split2_of(N).A > 0 && fft_two_level())
-    return launch2_fft_lines_any(x, nlines, N, (int)inner, dir, f, scale, s, tag, done, lines_per_flag);
+  if (inner > 1 && split_of(N).A > 0 && fft_two_level() &&
+      (long long)(split_lines(N) + 1) * N * inner * 16 < (1ll << 32))
+    return launch3_fft_lines_any(x, nlines, N, (int)inner, dir, f, scale, s, tag, done, lines_per_flag);
   const int T = lines_per_tile1(N);
   const size_t shm = size_t(T + 1) * N * sizeof(double2);
   const int grid = ceil_div(nlines, T);

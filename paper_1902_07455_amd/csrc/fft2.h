@@ -1,24 +1,30 @@
-// Register-resident two-level DFT of lengths N = A B (A, B products of 3s
-// and 5s), for the full-grid passes and the batched line transform.
+// Register-resident DFTs of lengths N = A B C (factors products of 3s and
+// 5s, at most 15), for the full-grid passes and strided line transforms.
 //
 // The DFT of Sec. 2.2.1 along a line, X[k] = sum_n x[n] w^(n k) with
-// w = exp(DIR 2 pi i / N), is split once (Cooley-Tukey with n = b + B a,
-// k = k1 + A k2):
-//   X[k1 + A k2] = sum_b w_B^(b k2) [ w_N^(b k1) sum_a x[b + B a] w_A^(a k1) ]
-// Phase 1: one work item per (line, b) holds the A values x[b + B a] in
-// registers, transforms them (length A), multiplies by w_N^(b k1) and
-// writes them to LDS.  Phase 2: one item per (line, k1) reads the B values
-// of its k1, transforms them (length B) and holds X[k1 + A k2], k2 < B.
-// One LDS exchange per transform, against one read and one write of the
-// whole tile per radix stage in the Stockham form of fft.h.  The output
-// order of phase 2 (item k1 holds k1 + A k2) is the input order of the
-// <B, A> split, so an inverse and a forward transform chain without an
-// exchange between them.
+// w = exp(DIR 2 pi i / N), is split by Cooley-Tukey twice.  With M = B C,
+// n = j + M a and k = k1 + A k':
+//   X[k1 + A k'] = sum_j w_M^(j k') [ w_N^(j k1) sum_a x[j + M a] w_A^(a k1) ]
+// and the inner length-M transform over j = c + C b again as
+//   sum_c w_C^(c k3) [ w_M^(c k2) sum_b y[c + C b] w_B^(b k2) ],  k' = k2 + B k3.
+// Stage 1: one work item per (line, j) holds the A values x[j + M a] in
+// registers, transforms them, multiplies by w_N^(j k1) and writes them to
+// LDS.  Stage 2: one item per (line, k1, c) transforms its B values in
+// place (length B, twiddle w_M^(c k2)).  Last stage: one item per (line,
+// k1, k2) transforms its C values and holds X[k1 + A k2 + A B k3], k3 < C.
+// With C = 1 stage 2 is the last (items (line, k1), X[k1 + A k2]).  Two LDS
+// exchanges per transform at most, against one read and one write of the
+// whole tile per radix stage in the Stockham form of fft.h, and no item
+// holds more than 15 complex values.  The last stage's output order is the
+// input order of stage 1 of the mirrored split, so an inverse and a
+// forward transform chain without an exchange between them.
 //
-// Inside an item the length-A (or B) DFT is an unrolled mixed-radix
-// recursion L = p q (p = 3 or 5) over a register array whose twiddles are
-// compile-time constants (a table evaluated by the compiler).
+// Inside an item a DFT is an unrolled mixed-radix recursion L = p q
+// (p = 3 or 5) over a register array whose twiddles are compile-time
+// constants (a table evaluated by the compiler).
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -161,31 +167,30 @@ __host__ __device__ __forceinline__ void rdft(double2 (&x)[L]) {
   }
 }
 
-// ------------------------------------------------------------ two levels
-// The splits built as register kernels: N -> (A, B).  Other lengths take
-// the Stockham LDS path of fft.h.
-struct Split2 {
-  int A, B;
+// ------------------------------------------------------------ splits
+// The lengths built as register kernels: N -> (A, B, C).  Other lengths
+// take the Stockham LDS path of fft.h.
+struct Split3 {
+  int A, B, C;
 };
-constexpr Split2 split2_of(int N) {
+constexpr Split3 split_of(int N) {
   switch (N) {
-    case 45: return Split2{9, 5};
-    case 75: return Split2{15, 5};
-    case 81: return Split2{9, 9};
-    case 135: return Split2{15, 9};
-    case 225: return Split2{15, 15};
-    case 243: return Split2{27, 9};
-    case 405: return Split2{27, 15};
-    case 675: return Split2{27, 25};
-    case 729: return Split2{27, 27};
-    default: return Split2{0, 0};
+    case 45: return Split3{9, 5, 1};
+    case 75: return Split3{15, 5, 1};
+    case 81: return Split3{9, 9, 1};
+    case 135: return Split3{15, 9, 1};
+    case 225: return Split3{15, 15, 1};
+    case 243: return Split3{9, 9, 3};
+    case 405: return Split3{9, 9, 5};
+    case 675: return Split3{9, 15, 5};
+    case 729: return Split3{9, 9, 9};
+    default: return Split3{0, 0, 0};
   }
 }
 
-// Lines per tile and threads per block of the two-level kernels: the
-// tile's LDS exchange (T N complex values) stays near 32 KB, so that five
-// tiles share a CU.
-constexpr int split2_lines(int N) { return N <= 150 ? 16 : (N <= 300 ? 8 : 4); }
+// Lines per tile: the tile's LDS buffer (T N complex values) stays near
+// 32 KB, so that four or five tiles share a CU.
+constexpr int split_lines(int N) { return N <= 150 ? 16 : (N <= 300 ? 8 : (N <= 450 ? 5 : 3)); }
 
 // XCD-aware order of tiles: the dispatcher hands consecutive workgroups
 // to the eight XCDs in turn; this maps them so that each XCD takes one
@@ -197,20 +202,103 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned G) {
   return x * q + (x < r ? x : r) + j;
 }
 
-// Phase 1 of one item: x[a] = x[b + B a] on entry; leaves
-// w_N^(b k1) sum_a x[b + B a] w_A^(a k1) in x[k1].  tw: the length-N
-// table exp(-2 pi i e / N) in LDS.
-template <int DIR, int A, int B>
-__device__ __forceinline__ void split2_phase1(double2 (&x)[A], int b, const double2* __restrict__ tw) {
-  rdft<DIR, A>(x);
+// Element at a 32-bit byte offset from a wave-uniform base: one VGPR per
+// address (the callers' launchers check that the arrays stay below 4 GB).
+template <typename V>
+__device__ __forceinline__ V ld32(const V* base, unsigned byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename V>
+__device__ __forceinline__ void st32(V* base, unsigned byte_off, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// One split of a tile of T lines held in LDS, block of NT threads.  LF:
+// the lines are contiguous in memory (work items index-fast, LDS line by
+// line); otherwise the lines are adjacent entries of strided arrays (items
+// line-fast, LDS line-fast).  tw: exp(-2 pi i e / N), e < N, in LDS.
+template <int A_, int B_, int C_, int DIR, int T, bool LF, int NT>
+struct Fft3 {
+  static constexpr int A = A_, B = B_, C = C_;
+  static constexpr int M = B * C, N = A * M;
+  static constexpr int KL = C > 1 ? B : 1;   // k2 range of the last stage
+  static constexpr int R = C > 1 ? C : B;    // outputs per last-stage item
+  static constexpr int I1 = T * M, I2 = T * A * C, IL = T * A * KL;
+  static constexpr int P1 = (I1 + NT - 1) / NT, PL = (IL + NT - 1) / NT;  // items per thread
+
+  __host__ __device__ static int sidx(int t, int k1, int j) { return LF ? (t * A + k1) * M + j : (k1 * M + j) * T + t; }
+  __host__ __device__ static void item1(int i, int& t, int& j) {
+    if (LF) { j = i % M; t = i / M; } else { t = i % T; j = i / T; }
+  }
+  __host__ __device__ static void item2(int i, int& t, int& k1, int& c) {
+    if (LF) { c = i % C; const int r = i / C; k1 = r % A; t = r / A; }
+    else { t = i % T; const int r = i / T; c = r % C; k1 = r / C; }
+  }
+  __host__ __device__ static void itemL(int i, int& t, int& k1, int& k2) {
+    if (LF) { k1 = i % A; const int r = i / A; k2 = r % KL; t = r / KL; }
+    else { t = i % T; const int r = i / T; k1 = r % A; k2 = r / A; }
+  }
+  // output index of last-stage value r of item (k1, k2)
+  __host__ __device__ static constexpr int out_n(int k1, int k2, int r) { return k1 + A * k2 + A * KL * r; }
+
+  __host__ __device__ static double2 twid(const double2* tw, int e) {
+    double2 w = tw[e];
+    if (DIR > 0) w.y = -w.y;
+    return w;
+  }
+  // stage 1 of item (t, j): v[a] = x[j + M a] on entry; the register part,
+  // then the LDS write
+  __host__ __device__ static void stage1_regs(double2 (&v)[A], int j, const double2* tw) {
+    rdft<DIR, A>(v);
+    if (j != 0) {
 #pragma unroll
-  for (int k1 = 1; k1 < A; ++k1) {
-    if (b != 0) {
-      double2 w = tw[b * k1];
-      if (DIR > 0) w.y = -w.y;
-      x[k1] = cmul(x[k1], w);
+      for (int k1 = 1; k1 < A; ++k1) v[k1] = cmul(v[k1], twid(tw, j * k1));
     }
   }
-}
+  __host__ __device__ static void stage1_write(const double2 (&v)[A], int t, int j, double2* S) {
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) S[sidx(t, k1, j)] = v[k1];
+  }
+  __host__ __device__ static void stage1(double2 (&v)[A], int t, int j, double2* S, const double2* tw) {
+    stage1_regs(v, j, tw);
+    stage1_write(v, t, j, S);
+  }
+  // stage 2 of item i (C > 1); in place: an item reads and writes the
+  // same LDS entries
+  __host__ __device__ static void stage2_item(double2* S, const double2* tw, int i) {
+    int t, k1, c;
+    item2(i, t, k1, c);
+    double2 y[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) y[b] = S[sidx(t, k1, c + C * b)];
+    rdft<DIR, B>(y);
+    if (c != 0) {
+#pragma unroll
+      for (int k2 = 1; k2 < B; ++k2) y[k2] = cmul(y[k2], twid(tw, A * c * k2));
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) S[sidx(t, k1, c + C * k2)] = y[k2];
+  }
+  __device__ static void stage2(double2* S, const double2* tw) {
+    if constexpr (C > 1) {
+      for (int i = threadIdx.x; i < I2; i += NT) stage2_item(S, tw, i);
+    }
+  }
+  // last stage of item (t, k1, k2): z[r] = X[out_n(k1, k2, r)]
+  __host__ __device__ static void last(double2 (&z)[R], int t, int k1, int k2, const double2* S) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) z[q] = S[sidx(t, k1, k2 * R + q)];
+    rdft<DIR, R>(z);
+  }
+};
+
+// The split of the forward transform that takes the inverse's last-stage
+// output order as its stage-1 input order.
+template <class F>
+struct MirrorOf;
+template <int A, int B, int C, int DIR, int T, bool LF, int NT>
+struct MirrorOf<Fft3<A, B, C, DIR, T, LF, NT>> {
+  using type = std::conditional_t<(C > 1), Fft3<C, B, A, -DIR, T, LF, NT>, Fft3<B, A, 1, -DIR, T, LF, NT>>;
+};
 
 }  // namespace lrfg

@@ -308,79 +308,74 @@ __global__ __launch_bounds__(kFftBlock) void k_axis3(const void* __restrict__ sr
   }
 }
 
-// ---------------------------------------------------------------- two-level passes
+// ---------------------------------------------------------------- register passes
 // The hot passes in the register form of fft2.h, for N along the pass in
-// split2_of's table.  A tile holds T lines (axis 1) or T pairs of real
-// lines (axis 3), and every phase has at most one work item per thread.
-template <int A, int B>
-struct Tile2 {
-  static constexpr int N = A * B;
-  static constexpr int T = split2_lines(N);
-  static_assert(T * A <= kFftBlock && T * B <= kFftBlock, "one work item per thread and phase");
-};
+// split_of's table.  A tile holds T lines (axis 1) or T pairs of real lines
+// (axis 3).  Loads and stores address the arrays by 32-bit byte offsets
+// from wave-uniform bases (the launchers check that the arrays fit).
 
 // P1: dst[e][alpha - alpha0] = F^-1_axis1(2 pi i k_alpha src[e]) for the
 // nalpha directions from alpha0.  k_1 and k_2 are constant along an axis-1
 // line, so those outputs are one inverse transform of src scaled per line;
 // k_0 varies along the line and takes a transform of its own.
-template <int A, int B>
-__global__ __launch_bounds__(kFftBlock) void k2_grad_axis1(const double2* __restrict__ src, double2* __restrict__ dst,
+template <int A, int B, int C>
+__global__ __launch_bounds__(kFftBlock) void k3_grad_axis1(const double2* __restrict__ src, double2* __restrict__ dst,
                                                             G3 g, int alpha0, int nalpha, long long dst_stride_e,
                                                             long long dst_stride_a, FftDev f,
                                                             const int* __restrict__ done) {
-  using TL = Tile2<A, B>;
-  constexpr int N = TL::N, T = TL::T;
+  constexpr int N = A * B * C;
+  constexpr int T = split_lines(N);
+  using F = Fft3<A, B, C, 1, T, false, kFftBlock>;
   __shared__ double2 S[T * N];
   __shared__ double2 tw[N];
   const int e = blockIdx.y;
   if (done != nullptr && done[e]) return;
-  const long long inner = (long long)g.N2 * g.H;
-  const long long l0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * T;
-  const int tcount = (int)min((long long)T, inner - l0);
+  const unsigned inner = (unsigned)g.N2 * (unsigned)g.H;
+  const unsigned l0 = xcd_tile(blockIdx.x, gridDim.x) * (unsigned)T;
+  const int tcount = (int)min(T, (int)(inner - l0));
   const double2* s = src + (long long)e * g.S;
   double2* d = dst + e * dst_stride_e;
   for (int i = threadIdx.x; i < N; i += kFftBlock) tw[i] = f.tw[i];
-  const int tid = threadIdx.x;
-  const int t1 = tid % T, b = tid / T;     // phase 1 item (line, b)
-  const int t2 = tid % T, k1 = tid / T;    // phase 2 item (line, k1)
-  const long long l1 = l0 + t1, l2 = l0 + t2;
-  const bool ok1 = tid < T * B && t1 < tcount;
-  const bool ok2 = tid < T * A && t2 < tcount;
   const int a_end = alpha0 + nalpha;
   for (int pass = 0; pass < 2; ++pass) {
     // pass 0: the directions 1 and 2 (one transform); pass 1: direction 0
     const bool weighted = pass == 1;
     if (weighted ? alpha0 > 0 : a_end <= 1) continue;
     __syncthreads();  // tw staged / S free again
-    if (tid < T * B) {
+    for (int it = threadIdx.x; it < F::I1; it += kFftBlock) {
+      int t, j;
+      F::item1(it, t, j);
+      const bool ok = t < tcount;
+      const unsigned l = l0 + (unsigned)t;
       double2 v[A];
 #pragma unroll
       for (int a = 0; a < A; ++a) {
-        const int n = b + B * a;
-        const double2 x = ok1 ? s[(long long)n * inner + l1] : make_double2(0.0, 0.0);
+        const int n = j + F::M * a;
+        const double2 x = ok ? ld32(s, ((unsigned)n * inner + l) * 16u) : make_double2(0.0, 0.0);
         v[a] = weighted ? cmul_i(x, 2.0 * kPi * (double)freq_of(n, N)) : x;
       }
-      split2_phase1<1, A, B>(v, b, tw);
-#pragma unroll
-      for (int j = 0; j < A; ++j) S[(j * B + b) * T + t1] = v[j];
+      F::stage1(v, t, j, S, tw);
     }
     __syncthreads();
-    if (tid < T * A) {
-      double2 y[B];
-#pragma unroll
-      for (int j = 0; j < B; ++j) y[j] = S[(k1 * B + j) * T + t2];
-      rdft<1, B>(y);
-      if (ok2) {
+    F::stage2(S, tw);
+    __syncthreads();
+    for (int it = threadIdx.x; it < F::IL; it += kFftBlock) {
+      int t, k1, k2;
+      F::itemL(it, t, k1, k2);
+      double2 z[F::R];
+      F::last(z, t, k1, k2, S);
+      if (t < tcount) {
+        const unsigned l = l0 + (unsigned)t;
         if (weighted) {
 #pragma unroll
-          for (int k2 = 0; k2 < B; ++k2) d[(long long)(k1 + A * k2) * inner + l2] = y[k2];
+          for (int r = 0; r < F::R; ++r) st32(d, ((unsigned)F::out_n(k1, k2, r) * inner + l) * 16u, z[r]);
         } else {
-          const unsigned lu = (unsigned)l2;
           for (int al = alpha0 > 1 ? alpha0 : 1; al < a_end; ++al) {
-            const double kk = al == 1 ? (double)freq_of((int)(lu / (unsigned)g.H), g.N2) : (double)(lu % (unsigned)g.H);
+            const double kk = al == 1 ? (double)freq_of((int)(l / (unsigned)g.H), g.N2) : (double)(l % (unsigned)g.H);
             double2* da = d + (long long)(al - alpha0) * dst_stride_a;
 #pragma unroll
-            for (int k2 = 0; k2 < B; ++k2) da[(long long)(k1 + A * k2) * inner + l2] = cmul_i(y[k2], 2.0 * kPi * kk);
+            for (int r = 0; r < F::R; ++r)
+              st32(da, ((unsigned)F::out_n(k1, k2, r) * inner + l) * 16u, cmul_i(z[r], 2.0 * kPi * kk));
           }
         }
       }
@@ -392,90 +387,104 @@ __global__ __launch_bounds__(kFftBlock) void k2_grad_axis1(const double2* __rest
 // partial sums of (p[e], q[e]).  The directions 1 and 2 (constant k along
 // the line) are combined before one forward transform; direction 0 is
 // transformed alone and weighted after it.
-template <int A, int B>
-__global__ __launch_bounds__(kFftBlock) void k2_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
+template <int A, int B, int C>
+__global__ __launch_bounds__(kFftBlock) void k3_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
                                                            const double2* __restrict__ p, G3 g, int alpha0,
                                                            int nalpha, double inv_vol, FftDev f,
                                                            const int* __restrict__ done, double* __restrict__ part_pq) {
-  using TL = Tile2<A, B>;
-  constexpr int N = TL::N, T = TL::T;
+  constexpr int N = A * B * C;
+  constexpr int T = split_lines(N);
+  using F = Fft3<A, B, C, -1, T, false, kFftBlock>;
   __shared__ double2 S[T * N];
   __shared__ double2 tw[N];
   __shared__ double red[kFftBlock / 64];
   const int e = blockIdx.y;
   if (done[e]) return;
-  const long long inner = (long long)g.N2 * g.H;
-  const long long l0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * T;
-  const int tcount = (int)min((long long)T, inner - l0);
+  const unsigned inner = (unsigned)g.N2 * (unsigned)g.H;
+  const unsigned l0 = xcd_tile(blockIdx.x, gridDim.x) * (unsigned)T;
+  const int tcount = (int)min(T, (int)(inner - l0));
   for (int i = threadIdx.x; i < N; i += kFftBlock) tw[i] = f.tw[i];
-  const int tid = threadIdx.x;
-  const int t1 = tid % T, b = tid / T;
-  const int t2 = tid % T, k1 = tid / T;
-  const long long l1 = l0 + t1, l2 = l0 + t2;
-  const bool ok1 = tid < T * B && t1 < tcount;
-  const bool ok2 = tid < T * A && t2 < tcount;
   const int a_end = alpha0 + nalpha;
-  double2 acc[B];
+  double2 acc[F::PL][F::R];
 #pragma unroll
-  for (int j = 0; j < B; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int pi = 0; pi < F::PL; ++pi)
+#pragma unroll
+    for (int r = 0; r < F::R; ++r) acc[pi][r] = make_double2(0.0, 0.0);
   for (int pass = 0; pass < 2; ++pass) {
     // pass 0: direction 0 (weighted after the transform); pass 1: 1 and 2
     const bool along = pass == 0;
     if (along ? alpha0 > 0 : a_end <= 1) continue;
     __syncthreads();
-    if (tid < T * B) {
+    for (int it = threadIdx.x; it < F::I1; it += kFftBlock) {
+      int tt, j;
+      F::item1(it, tt, j);
+      const bool ok = tt < tcount;
+      const unsigned l = l0 + (unsigned)tt;
       double2 v[A];
       if (along) {
         const double2* s = t + ((long long)e * nalpha + (0 - alpha0)) * g.S;
 #pragma unroll
-        for (int a = 0; a < A; ++a) v[a] = ok1 ? s[(long long)(b + B * a) * inner + l1] : make_double2(0.0, 0.0);
+        for (int a = 0; a < A; ++a)
+          v[a] = ok ? ld32(s, ((unsigned)(j + F::M * a) * inner + l) * 16u) : make_double2(0.0, 0.0);
       } else {
 #pragma unroll
         for (int a = 0; a < A; ++a) v[a] = make_double2(0.0, 0.0);
-        const unsigned lu = (unsigned)l1;
         for (int al = alpha0 > 1 ? alpha0 : 1; al < a_end; ++al) {
-          const double kk = al == 1 ? (double)freq_of((int)(lu / (unsigned)g.H), g.N2) : (double)(lu % (unsigned)g.H);
+          const double kk = al == 1 ? (double)freq_of((int)(l / (unsigned)g.H), g.N2) : (double)(l % (unsigned)g.H);
           const double c = -2.0 * kPi * kk * inv_vol;
           const double2* s = t + ((long long)e * nalpha + (al - alpha0)) * g.S;
 #pragma unroll
           for (int a = 0; a < A; ++a) {
-            const double2 x = ok1 ? s[(long long)(b + B * a) * inner + l1] : make_double2(0.0, 0.0);
+            const double2 x = ok ? ld32(s, ((unsigned)(j + F::M * a) * inner + l) * 16u) : make_double2(0.0, 0.0);
             v[a] = cadd(v[a], cmul_i(x, c));
           }
         }
       }
-      split2_phase1<-1, A, B>(v, b, tw);
-#pragma unroll
-      for (int j = 0; j < A; ++j) S[(j * B + b) * T + t1] = v[j];
+      F::stage1(v, tt, j, S, tw);
     }
     __syncthreads();
-    if (tid < T * A) {
-      double2 y[B];
+    F::stage2(S, tw);
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < B; ++j) y[j] = S[(k1 * B + j) * T + t2];
-      rdft<-1, B>(y);
+    for (int pi = 0; pi < F::PL; ++pi) {
+      const int it = threadIdx.x + pi * kFftBlock;
+      if (it < F::IL) {
+        int tt, k1, k2;
+        F::itemL(it, tt, k1, k2);
+        double2 z[F::R];
+        F::last(z, tt, k1, k2, S);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) {
-        if (along) {
-          const double c = -2.0 * kPi * (double)freq_of(k1 + A * k2, N) * inv_vol;
-          acc[k2] = cmul_i(y[k2], c);
-        } else {
-          acc[k2] = cadd(acc[k2], y[k2]);
+        for (int r = 0; r < F::R; ++r) {
+          if (along) {
+            const double c = -2.0 * kPi * (double)freq_of(F::out_n(k1, k2, r), N) * inv_vol;
+            acc[pi][r] = cmul_i(z[r], c);
+          } else {
+            acc[pi][r] = cadd(acc[pi][r], z[r]);
+          }
         }
       }
     }
   }
   double pq = 0.0;
-  if (ok2) {
-    const double2* pe = p + (long long)e * g.S;
-    double2* qe = q + (long long)e * g.S;
-    const double w = ((unsigned)l2 % (unsigned)g.H) == 0 ? 1.0 : 2.0;
+  const double2* pe = p + (long long)e * g.S;
+  double2* qe = q + (long long)e * g.S;
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) {
-      const long long ad = (long long)(k1 + A * k2) * inner + l2;
-      qe[ad] = acc[k2];
-      const double2 pv = pe[ad];
-      pq += w * (pv.x * acc[k2].x + pv.y * acc[k2].y);
+  for (int pi = 0; pi < F::PL; ++pi) {
+    const int it = threadIdx.x + pi * kFftBlock;
+    if (it < F::IL) {
+      int tt, k1, k2;
+      F::itemL(it, tt, k1, k2);
+      if (tt < tcount) {
+        const unsigned l = l0 + (unsigned)tt;
+        const double w = (l % (unsigned)g.H) == 0 ? 1.0 : 2.0;
+#pragma unroll
+        for (int r = 0; r < F::R; ++r) {
+          const unsigned off = ((unsigned)F::out_n(k1, k2, r) * inner + l) * 16u;
+          st32(qe, off, acc[pi][r]);
+          const double2 pv = ld32(pe, off);
+          pq += w * (pv.x * acc[pi][r].x + pv.y * acc[pi][r].y);
+        }
+      }
     }
   }
   const double sum = block_sum(pq, red);
@@ -483,158 +492,180 @@ __global__ __launch_bounds__(kFftBlock) void k2_div_axis1(const double2* __restr
 }
 
 // P3: X <- R2C(a . C2R(X)) along axis 3 for the array blockIdx.y (two real
-// lines per complex line).  The inverse uses the <A, B> split and leaves
-// item (pair, k1) with the values at n = k1 + A k2, which are the inputs of
-// the forward <B, A> split's phase 1: coefficient and forward phase 1 run
-// on the same registers.  A last exchange pairs the entries h and N - h
-// that separate the two Hermitian spectra.
-template <int A, int B>
-__global__ __launch_bounds__(kFftBlock) void k2_axis3(double2* __restrict__ X, const double* __restrict__ acoef, G3 g,
+// lines per complex line).  The inverse's last stage leaves the values at
+// n = j + A B r (j = k1 + A k2) in registers, the input order of the
+// mirrored forward split's stage 1: coefficient and forward stage 1 run on
+// the same registers.  A last exchange pairs the entries h and N - h that
+// separate the two Hermitian spectra.
+template <int A, int B, int C>
+__global__ __launch_bounds__(kFftBlock) void k3_axis3(double2* __restrict__ X, const double* __restrict__ acoef, G3 g,
                                                        long long stride, FftDev f, const int* __restrict__ done,
                                                        int done_div) {
-  using TL = Tile2<A, B>;
-  constexpr int N = TL::N, T = TL::T, H = (N + 1) / 2;
+  constexpr int N = A * B * C;
+  constexpr int T = split_lines(N), H = (N + 1) / 2;
+  using FI = Fft3<A, B, C, 1, T, true, kFftBlock>;
+  using FF = typename MirrorOf<FI>::type;
+  static_assert(FF::A == FI::R && FF::M == A * FI::KL, "mirrored split");
   __shared__ double2 S[T * N];
   __shared__ double2 tw[N];
   const int bi = blockIdx.y;
   if (done != nullptr && done[bi / done_div]) return;
-  const long long nl = (long long)g.N1 * g.N2;
-  const long long p0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * T;
+  const unsigned nl = (unsigned)g.N1 * (unsigned)g.N2;
+  const unsigned p0 = xcd_tile(blockIdx.x, gridDim.x) * (unsigned)T;
   double2* x = X + bi * stride;
   for (int i = threadIdx.x; i < N; i += kFftBlock) tw[i] = f.tw[i];
   __syncthreads();
-  const int tid = threadIdx.x;
-  // inverse phase 1: items (pair, b), b fastest
-  if (tid < T * B) {
-    const int b = tid % B, tp = tid / B;
-    const long long la = 2 * (p0 + tp), lb = la + 1;
+  // inverse stage 1: items (pair, j), j fastest
+  for (int it = threadIdx.x; it < FI::I1; it += kFftBlock) {
+    int tp, j;
+    FI::item1(it, tp, j);
+    const unsigned la = 2 * (p0 + (unsigned)tp), lb = la + 1;
     double2 v[A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      const int n = b + B * a;
+      const int n = j + FI::M * a;
       const bool cj = n >= H;
-      const int m = cj ? N - n : n;
-      double2 xa = la < nl ? x[la * H + m] : make_double2(0.0, 0.0);
-      double2 xb = lb < nl ? x[lb * H + m] : make_double2(0.0, 0.0);
+      const unsigned m = (unsigned)(cj ? N - n : n);
+      double2 xa = la < nl ? ld32(x, (la * (unsigned)H + m) * 16u) : make_double2(0.0, 0.0);
+      double2 xb = lb < nl ? ld32(x, (lb * (unsigned)H + m) * 16u) : make_double2(0.0, 0.0);
       if (cj) {
         xa.y = -xa.y;
         xb.y = -xb.y;
       }
       v[a] = make_double2(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
     }
-    split2_phase1<1, A, B>(v, b, tw);
-#pragma unroll
-    for (int j = 0; j < A; ++j) S[(tp * A + j) * B + b] = v[j];
+    FI::stage1(v, tp, j, S, tw);
   }
   __syncthreads();
-  // inverse phase 2, coefficient, forward phase 1: items (pair, k1), k1 fastest
-  const bool act2 = tid < T * A;
-  const int k1 = tid % A, t2 = tid / A;
-  double2 y[B];
-  if (act2) {
+  FI::stage2(S, tw);
+  __syncthreads();
+  // inverse last stage, coefficient, forward stage 1 (held across the barrier)
+  double2 hold[FI::PL][FI::R];
 #pragma unroll
-    for (int j = 0; j < B; ++j) y[j] = S[(t2 * A + k1) * B + j];
-    rdft<1, B>(y);
-    const long long la = 2 * (p0 + t2), lb = la + 1;
+  for (int pi = 0; pi < FI::PL; ++pi) {
+    const int it = threadIdx.x + pi * kFftBlock;
+    if (it < FI::IL) {
+      int tp, k1, k2;
+      FI::itemL(it, tp, k1, k2);
+      FI::last(hold[pi], tp, k1, k2, S);
+      const unsigned la = 2 * (p0 + (unsigned)tp), lb = la + 1;
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) {
-      const int n = k1 + A * k2;
-      const double aa = la < nl ? acoef[la * N + n] : 0.0;
-      const double ab = lb < nl ? acoef[lb * N + n] : 0.0;
-      y[k2] = make_double2(y[k2].x * aa, y[k2].y * ab);
+      for (int r = 0; r < FI::R; ++r) {
+        const unsigned n = (unsigned)FI::out_n(k1, k2, r);
+        const double aa = la < nl ? ld32(acoef, (la * (unsigned)N + n) * 8u) : 0.0;
+        const double ab = lb < nl ? ld32(acoef, (lb * (unsigned)N + n) * 8u) : 0.0;
+        hold[pi][r] = make_double2(hold[pi][r].x * aa, hold[pi][r].y * ab);
+      }
+      FF::stage1_regs(hold[pi], k1 + A * k2, tw);
     }
-    split2_phase1<-1, B, A>(y, k1, tw);
   }
   __syncthreads();
-  if (act2) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) S[(t2 * B + j) * A + k1] = y[j];
+  for (int pi = 0; pi < FI::PL; ++pi) {
+    const int it = threadIdx.x + pi * kFftBlock;
+    if (it < FI::IL) {
+      int tp, k1, k2;
+      FI::itemL(it, tp, k1, k2);
+      FF::stage1_write(hold[pi], tp, k1 + A * k2, S);
+    }
   }
   __syncthreads();
-  // forward phase 2: items (pair, k1' < B) -> X[k1' + B k2']
-  const bool act3 = tid < T * B;
-  const int kk = tid % B, t3 = tid / B;
-  double2 z[A];
-  if (act3) {
+  FF::stage2(S, tw);
+  __syncthreads();
+  // forward last stage, then natural order in LDS for the separation
+  double2 fw[FF::PL][FF::R];
 #pragma unroll
-    for (int j = 0; j < A; ++j) z[j] = S[(t3 * B + kk) * A + j];
-    rdft<-1, A>(z);
+  for (int pi = 0; pi < FF::PL; ++pi) {
+    const int it = threadIdx.x + pi * kFftBlock;
+    if (it < FF::IL) {
+      int tp, k1, k2;
+      FF::itemL(it, tp, k1, k2);
+      FF::last(fw[pi], tp, k1, k2, S);
+    }
   }
   __syncthreads();
-  if (act3) {
 #pragma unroll
-    for (int j = 0; j < A; ++j) S[t3 * N + kk + B * j] = z[j];
+  for (int pi = 0; pi < FF::PL; ++pi) {
+    const int it = threadIdx.x + pi * kFftBlock;
+    if (it < FF::IL) {
+      int tp, k1, k2;
+      FF::itemL(it, tp, k1, k2);
+#pragma unroll
+      for (int r = 0; r < FF::R; ++r) S[tp * N + FF::out_n(k1, k2, r)] = fw[pi][r];
+    }
   }
   __syncthreads();
   // separate the two Hermitian spectra and store h in [0, H)
-  for (int it = tid; it < T * H; it += kFftBlock) {
+  for (int it = threadIdx.x; it < T * H; it += kFftBlock) {
     const int tp = it / H, h = it - tp * H;
-    const long long la = 2 * (p0 + tp), lb = la + 1;
+    const unsigned la = 2 * (p0 + (unsigned)tp), lb = la + 1;
     const double2 W1 = S[tp * N + h];
     const double2 W2 = S[tp * N + (h == 0 ? 0 : N - h)];
     const double2 xa = make_double2(0.5 * (W1.x + W2.x), 0.5 * (W1.y - W2.y));
     const double2 dd = make_double2(W1.x - W2.x, W1.y + W2.y);
     const double2 xb = make_double2(0.5 * dd.y, -0.5 * dd.x);
-    if (la < nl) x[la * H + h] = xa;
-    if (lb < nl) x[lb * H + h] = xb;
+    if (la < nl) st32(x, (la * (unsigned)H + (unsigned)h) * 16u, xa);
+    if (lb < nl) st32(x, (lb * (unsigned)H + (unsigned)h) * 16u, xb);
   }
 }
 
-// Launchers of the two-level passes for the lengths of split2_of's table
-// (LRFG_EUNSUPPORTED otherwise).
-#define LRFG_SPLIT2_CASES(X) X(45) X(75) X(81) X(135) X(225) X(243) X(405) X(675) X(729)
+// Launchers of the register passes for the lengths of split_of's table
+// whose arrays fit 32-bit byte offsets (LRFG_EUNSUPPORTED otherwise).
+#define LRFG_SPLIT_CASES(X) X(45) X(75) X(81) X(135) X(225) X(243) X(405) X(675) X(729)
 
-bool pass_two_level(int N) { return split2_of(N).A > 0 && fft_two_level(); }
-int pass_tiles1(const G3& g) { return ceil_div((long long)g.N2 * g.H, split2_lines(g.N1)); }
-int pass_tiles3(const G3& g) { return ceil_div(((long long)g.N1 * g.N2 + 1) / 2, split2_lines(g.N3)); }
+bool pass_register(int N, const G3& g) {
+  return split_of(N).A > 0 && fft_two_level() && g.S * 16 < (1ll << 32) && g.R * 8 < (1ll << 32);
+}
+int pass_tiles1(const G3& g) { return ceil_div((long long)g.N2 * g.H, split_lines(g.N1)); }
+int pass_tiles3(const G3& g) { return ceil_div(((long long)g.N1 * g.N2 + 1) / 2, split_lines(g.N3)); }
 
-int launch2_grad(const double2* src, double2* dst, const G3& g, int alpha0, int nalpha, long long dse,
+int launch3_grad(const double2* src, double2* dst, const G3& g, int alpha0, int nalpha, long long dse,
                  long long dsa, const FftDev& f, const int* done, int nsys, hipStream_t s) {
   const dim3 grid(pass_tiles1(g), nsys);
-#define LRFG_G2(NN)                                                                                             \
-  case NN:                                                                                                      \
-    hipLaunchKernelGGL((k2_grad_axis1<split2_of(NN).A, split2_of(NN).B>), grid, dim3(kFftBlock), 0, s, src, dst, \
-                       g, alpha0, nalpha, dse, dsa, f, done);                                                   \
+#define LRFG_G3(NN)                                                                                          \
+  case NN:                                                                                                   \
+    hipLaunchKernelGGL((k3_grad_axis1<split_of(NN).A, split_of(NN).B, split_of(NN).C>), grid, dim3(kFftBlock), 0, \
+                       s, src, dst, g, alpha0, nalpha, dse, dsa, f, done);                                   \
     break;
   switch (g.N1) {
-    LRFG_SPLIT2_CASES(LRFG_G2)
+    LRFG_SPLIT_CASES(LRFG_G3)
     default: return LRFG_EUNSUPPORTED;
   }
-#undef LRFG_G2
+#undef LRFG_G3
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
-int launch2_div(const double2* t, double2* q, const double2* p, const G3& g, int alpha0, int nalpha, double inv_vol,
+int launch3_div(const double2* t, double2* q, const double2* p, const G3& g, int alpha0, int nalpha, double inv_vol,
                 const FftDev& f, const int* done, double* part, int nsys, hipStream_t s) {
   const dim3 grid(pass_tiles1(g), nsys);
-#define LRFG_D2(NN)                                                                                          \
+#define LRFG_D3(NN)                                                                                          \
   case NN:                                                                                                   \
-    hipLaunchKernelGGL((k2_div_axis1<split2_of(NN).A, split2_of(NN).B>), grid, dim3(kFftBlock), 0, s, t, q, p, \
-                       g, alpha0, nalpha, inv_vol, f, done, part);                                           \
+    hipLaunchKernelGGL((k3_div_axis1<split_of(NN).A, split_of(NN).B, split_of(NN).C>), grid, dim3(kFftBlock), 0, \
+                       s, t, q, p, g, alpha0, nalpha, inv_vol, f, done, part);                               \
     break;
   switch (g.N1) {
-    LRFG_SPLIT2_CASES(LRFG_D2)
+    LRFG_SPLIT_CASES(LRFG_D3)
     default: return LRFG_EUNSUPPORTED;
   }
-#undef LRFG_D2
+#undef LRFG_D3
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
 
-int launch2_axis3(double2* x, const double* a, const G3& g, long long stride, const FftDev& f, const int* done,
+int launch3_axis3(double2* x, const double* a, const G3& g, long long stride, const FftDev& f, const int* done,
                   int done_div, int narrays, hipStream_t s) {
   const dim3 grid(pass_tiles3(g), narrays);
-#define LRFG_A2(NN)                                                                                            \
+#define LRFG_A3(NN)                                                                                            \
   case NN:                                                                                                     \
-    hipLaunchKernelGGL((k2_axis3<split2_of(NN).A, split2_of(NN).B>), grid, dim3(kFftBlock), 0, s, x, a, g, stride, \
-                       f, done, done_div);                                                                     \
+    hipLaunchKernelGGL((k3_axis3<split_of(NN).A, split_of(NN).B, split_of(NN).C>), grid, dim3(kFftBlock), 0, s, x, \
+                       a, g, stride, f, done, done_div);                                                       \
     break;
   switch (g.N3) {
-    LRFG_SPLIT2_CASES(LRFG_A2)
+    LRFG_SPLIT_CASES(LRFG_A3)
     default: return LRFG_EUNSUPPORTED;
   }
-#undef LRFG_A2
+#undef LRFG_A3
   LRFG_LAUNCHED();
   return LRFG_OK;
 }
@@ -904,7 +935,7 @@ static void carve(Arena& ar, FullLayout& L, const int N3d[3], int nE, int d, int
   L.T1 = tile1_lines(g.N1);
   L.T3 = lines_per_tile1(g.N3);
   L.tiles1 = ceil_div((long long)g.N2 * g.H, L.T1);
-  L.tdiv = pass_two_level(g.N1) ? pass_tiles1(g) : L.tiles1;
+  L.tdiv = pass_register(g.N1, g) ? pass_tiles1(g) : L.tiles1;
   long long gv = ceil_div(g.S, kBlock * 4);
   if (gv > 1024) gv = 1024;
   if (gv < 1) gv = 1;
@@ -981,7 +1012,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   LRFG_TRY(fft_dev_upload(*A.plan2, L.tw2, s, &f2));
   LRFG_TRY(fft_dev_upload(*A.plan3, L.tw3, s, &f3));
   const bool G1 = plan_generic(f1), G3 = plan_generic(f3);
-  const bool two1 = pass_two_level(g.N1), two3 = pass_two_level(g.N3);
+  const bool two1 = pass_register(g.N1, g), two3 = pass_register(g.N3, g);
 
   // coefficient
   if (A.a_on_device) {
@@ -1061,7 +1092,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     {
       ProfScope ps_("grad_axis1", s);
       if (two1) {
-        LRFG_TRY(launch2_grad((const double2*)L.p, L.t, g, alpha0, d, (long long)d * g.S, g.S, f1,
+        LRFG_TRY(launch3_grad((const double2*)L.p, L.t, g, alpha0, d, (long long)d * g.S, g.S, f1,
                               (const int*)L.done, nE, s));
       } else {
         hipLaunchKernelGGL((G1 ? k_grad_axis1<true> : k_grad_axis1<false>), dim3(L.tiles1 * d, nE), dim3(kBlock), shm1,
@@ -1077,7 +1108,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     {
       ProfScope ps_("axis3", s);
       if (two3) {
-        LRFG_TRY(launch2_axis3(L.t, (const double*)L.a, g, g.S, f3, (const int*)L.done, d, nE * d, s));
+        LRFG_TRY(launch3_axis3(L.t, (const double*)L.a, g, g.S, f3, (const int*)L.done, d, nE * d, s));
       } else {
         hipLaunchKernelGGL((G3 ? k_axis3<0, true> : k_axis3<0, false>), dim3(tiles3, nE * d), dim3(kBlock), shm3, s,
                            (const void*)L.t, (void*)nullptr, (const double*)L.a, g, g.S, 0LL, L.T3, f3, 1.0,
@@ -1092,7 +1123,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     {
       ProfScope ps_("div_axis1", s);
       if (two1) {
-        LRFG_TRY(launch2_div((const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, f1,
+        LRFG_TRY(launch3_div((const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, f1,
                              (const int*)L.done, L.part_pq, nE, s));
       } else {
         hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(L.tiles1, nE), dim3(kBlock), shm1, s,
@@ -1254,9 +1285,9 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   const size_t shm3 = size_t(T3 + 1) * g.N3 * sizeof(double2);
   const long long pairs = ((long long)g.N1 * g.N2 + 1) / 2;
   const int tiles3 = ceil_div(pairs, T3);
-  const bool two1 = pass_two_level(g.N1), two3 = pass_two_level(g.N3);
+  const bool two1 = pass_register(g.N1, g), two3 = pass_register(g.N3, g);
   if (two1) {
-    LRFG_TRY(launch2_grad(uh, t, g, 0, 3, 3 * g.S, g.S, f1, (const int*)done, 1, s));
+    LRFG_TRY(launch3_grad(uh, t, g, 0, 3, 3 * g.S, g.S, f1, (const int*)done, 1, s));
   } else {
     hipLaunchKernelGGL((G1 ? k_grad_axis1<true> : k_grad_axis1<false>), dim3(tiles1 * 3, 1), dim3(kBlock), shm1, s, uh,
                        t, g, 0, 3, 3 * g.S, g.S, T1, f1, (const int*)done);
@@ -1264,7 +1295,7 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   }
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, 1, f2, 1.0, s));
   if (two3) {
-    LRFG_TRY(launch2_axis3(t, a, g, g.S, f3, (const int*)done, 3, 3, s));
+    LRFG_TRY(launch3_axis3(t, a, g, g.S, f3, (const int*)done, 3, 3, s));
   } else {
     hipLaunchKernelGGL((G3 ? k_axis3<0, true> : k_axis3<0, false>), dim3(tiles3, 3), dim3(kBlock), shm3, s,
                        (const void*)t, (void*)nullptr, a, g, g.S, 0LL, T3, f3, 1.0, (const int*)done, 3);
@@ -1272,7 +1303,7 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   }
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, -1, f2, 1.0, s));
   if (two1) {
-    LRFG_TRY(launch2_div((const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, f1, (const int*)done, part, 1, s));
+    LRFG_TRY(launch3_div((const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, f1, (const int*)done, part, 1, s));
   } else {
     hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(tiles1, 1), dim3(kBlock), shm1, s,
                        (const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, T1, f1, (const int*)done, part);
