@@ -37,15 +37,15 @@ struct BatchMap {
   long long sA2, sB2;
   int cdiv, cmod;
   long long sC2;
-  __host__ __device__ long long c_off(long long t, long long sC) const {
-    return (t / cdiv) * sC + (cmod > 0 ? (t % cmod) * sC2 : 0);
+  // batch indices stay below 2^31 (gemm() launches at most 65535 matrices
+  // per chunk from a base below the batch count), so the splits are 32-bit
+  __host__ __device__ static long long off(long long t, int dv, int md, long long s1, long long s2) {
+    const unsigned u = (unsigned)t;
+    return (long long)(u / (unsigned)dv) * s1 + (md > 0 ? (long long)(u % (unsigned)md) * s2 : 0);
   }
-  __host__ __device__ long long a_off(long long t, long long sA) const {
-    return (t / adiv) * sA + (amod > 0 ? (t % amod) * sA2 : 0);
-  }
-  __host__ __device__ long long b_off(long long t, long long sB) const {
-    return (t / bdiv) * sB + (bmod > 0 ? (t % bmod) * sB2 : 0);
-  }
+  __host__ __device__ long long c_off(long long t, long long sC) const { return off(t, cdiv, cmod, sC, sC2); }
+  __host__ __device__ long long a_off(long long t, long long sA) const { return off(t, adiv, amod, sA, sA2); }
+  __host__ __device__ long long b_off(long long t, long long sB) const { return off(t, bdiv, bmod, sB, sB2); }
 };
 
 // Scratch doubles gemm() may use for a split-K reduction of this shape.

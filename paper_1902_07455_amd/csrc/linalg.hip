@@ -4,6 +4,7 @@
 // and a batched cyclic Jacobi eigensolver.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "linalg.h"
 #include "prof.h"
@@ -48,10 +49,11 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wk = wave / (WM * WN), wr = wave - wk * (WM * WN);
   const int wm = wr / WN, wn = wr - (wr / WN) * WN;
-  // which of the wave's 2 x 2 MFMA blocks touch the output
+  // which of the wave's 2 x 2 MFMA blocks touch the output (wave-uniform)
   const bool r0 = m0 + wm * 32 < m, r1 = m0 + wm * 32 + 16 < m;
   const bool c0 = n0 + wn * 32 < n, c1 = n0 + wn * 32 + 16 < n;
   dbl4 acc[2][2];
@@ -79,39 +81,55 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
       pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += TK) {
+  // The K loop with the wave's live MFMA blocks (NR x NC of its 2 x 2,
+  // wave-uniform) fixed at compile time: no branch between the MFMAs.
+  auto kloop = [&](auto nr_c, auto nc_c) {
+    constexpr int NR = decltype(nr_c)::value, NC = decltype(nc_c)::value;
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += TK) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int i, kk;
-      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
-      As[kk][i] = pa[r];
+      for (int r = 0; r < RA; ++r) {
+        const int e = threadIdx.x + r * 256;
+        int i, kk;
+        if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
+        As[kk][i] = pa[r];
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int e = threadIdx.x + r * 256;
+        int kk, j;
+        if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
+        Bs[kk][j] = pb[r];
+      }
+      __syncthreads();
+      if (k0 + TK < ke) fetch(k0 + TK);
+      if constexpr (NR > 0 && NC > 0) {
+#pragma unroll
+        for (int kq = 0; kq < 16; kq += 4) {
+          const int kk = wk * 16 + kq;
+          double a[2], b[2];
+#pragma unroll
+          for (int bi = 0; bi < NR; ++bi) a[bi] = As[kk + (lane >> 4)][wm * 32 + bi * 16 + (lane & 15)];
+#pragma unroll
+          for (int bj = 0; bj < NC; ++bj) b[bj] = Bs[kk + (lane >> 4)][wn * 32 + bj * 16 + (lane & 15)];
+#pragma unroll
+          for (int bi = 0; bi < NR; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NC; ++bj)
+              acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int kk, j;
-      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
-      Bs[kk][j] = pb[r];
-    }
-    __syncthreads();
-    if (k0 + TK < ke) fetch(k0 + TK);
-#pragma unroll
-    for (int kq = 0; kq < 16; kq += 4) {
-      const int kk = wk * 16 + kq;
-      double a[2], b[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) a[bi] = As[kk + (lane >> 4)][wm * 32 + bi * 16 + (lane & 15)];
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[kk + (lane >> 4)][wn * 32 + bj * 16 + (lane & 15)];
-      if (r0 && c0) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc[0][0], 0, 0, 0);
-      if (r0 && c1) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[1], acc[0][1], 0, 0, 0);
-      if (r1 && c0) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[0], acc[1][0], 0, 0, 0);
-      if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc[1][1], 0, 0, 0);
-    }
-    __syncthreads();
-  }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  if (r1 && c1) kloop(I2{}, I2{});
+  else if (r1 && c0) kloop(I2{}, I1{});
+  else if (r0 && c1) kloop(I1{}, I2{});
+  else if (r0 && c0) kloop(I1{}, I1{});
+  else kloop(I0{}, I0{});
   if (WK > 1) {
     // waves wk > 0 hand their sums to the wave wk = 0 of their sub-tile
     // through LDS
@@ -137,6 +155,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
     }
   }
   if (wk != 0) return;
+  double* const Cb = C + bm.c_off(tg, sC);
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -150,7 +169,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + bm.c_off(tg, sC) + (long long)row * ldc + col;
+            double* c = Cb + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -170,8 +189,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
                                                  double* __restrict__ part, BatchMap bm) {
   constexpr int TM = 128, TN = 128, TK = 16;
   constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
-  __shared__ double As[TK][TM + 1];
-  __shared__ double Bs[TK][TN + 1];
+  // two slab buffers: the next slab is written while the current one feeds
+  // the MFMAs, one barrier per slab
+  __shared__ double As[2][TK][TM + 1];
+  __shared__ double Bs[2][TK][TN + 1];
   const int bz = blockIdx.z;
   const int bt = bz / ksplit;
   const int ks = bz - bt * ksplit;
@@ -181,15 +202,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = ks * kchunk;
   const int ke = min(k, kb + kchunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;
-  // MFMA blocks of this wave that touch the output (wave-uniform)
-  bool rv[4], cv[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    rv[i] = m0 + wm * 64 + i * 16 < m;
-    cv[i] = n0 + wn * 64 + i * 16 < n;
-  }
   dbl4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -214,40 +229,52 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
       pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += TK) {
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const int e = threadIdx.x + r * 256;
       int i, kk;
       if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
-      As[kk][i] = pa[r];
+      As[buf][kk][i] = pa[r];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int e = threadIdx.x + r * 256;
       int kk, j;
       if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
-      Bs[kk][j] = pb[r];
+      Bs[buf][kk][j] = pb[r];
     }
-    __syncthreads();
-    if (k0 + TK < ke) fetch(k0 + TK);
+  };
+  if (kb < ke) {
+    fetch(kb);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+    const bool more = k0 + TK < ke;
+    if (more) fetch(k0 + TK);
+    // all sixteen MFMAs on every wave: the blocks outside the output
+    // multiply the zeros the staging wrote there, and the epilogue drops them
 #pragma unroll
     for (int kq = 0; kq < TK; kq += 4) {
       const int kk = kq + (lane >> 4);
       double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][wm * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][kk][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (rv[i] && cv[j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
+  double* const Cb = C + bm.c_off(tg, sC);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -261,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = C + bm.c_off(tg, sC) + (long long)row * ldc + col;
+            double* c = Cb + (long long)row * ldc + col;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
