@@ -302,10 +302,13 @@ def serving_leg(nreq, nmax, capmax, dev):
         span = time.perf_counter() - t0
         srv.close()
         lat = [c.total_ms for c in done]
-        nc = {k: sum(c.status != 0 and reqs[c.tag].kind == k for c in done) for k in ("ball", "smooth")}
+        def count(st):
+            return {k: sum(c.status == st and reqs[c.tag].kind == k for c in done) for k in ("ball", "smooth")}
         return {"requests": len(done), "solves_per_s": round(len(done) / span, 3),
                 "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-                "not_converged": sum(c.status != 0 for c in done), "not_converged_by_kind": nc,
+                "not_converged": sum(c.status == 1 for c in done), "not_converged_by_kind": count(1),
+                "rank_limited": sum(c.status == 2 for c in done), "rank_limited_by_kind": count(2),
+                "errors": sum(c.status < 0 for c in done),
                 "max_batch_seen": max(c.batch_size for c in done)}
 
     probe = W.serving_requests(nreq, 1.0, seed=0, N_lo=45, N_hi=nmax, cap_hi=capmax)

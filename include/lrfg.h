@@ -51,7 +51,14 @@ extern "C" {
 
 typedef enum {
   LRFG_OK = 0,
-  LRFG_NOT_CONVERGED = 1,   /* A_H written; some corrector hit max_iter      */
+  LRFG_NOT_CONVERGED = 1,   /* A_H written; some corrector hit max_iter (or
+                               a CG breakdown) above solver_tol            */
+  LRFG_RANK_LIMITED = 2,    /* A_H written; a low-rank corrector stopped
+                               because its truncated residual stopped
+                               decreasing above solver_tol (the floor the
+                               rank cap sets, Sec. 4.3); the best iterate is
+                               kept.  Worse than OK, better than
+                               NOT_CONVERGED when statuses are combined     */
   LRFG_EINVAL = -1,         /* bad argument (d, even or < 3 N, rank_cap < 1,
                                negative or NaN tolerance, CP with d = 3, ...) */
   LRFG_ECOEFF = -2,         /* coefficient not finite and positive           */
@@ -180,7 +187,9 @@ int lrfg_plan_workspace_bytes(const lrfg_plan* plan, int max_nE, size_t* bytes);
 /* Solve the d cell problems for E_1..E_nE and form A_H (eq. homog).
  * E: host array nE x d (row-major) or NULL for the canonical basis (nE = d).
  * Stream-ordered; synchronises `stream` before writing host results.
- * Returns LRFG_NOT_CONVERGED if some corrector stopped at max_iter. */
+ * Returns LRFG_NOT_CONVERGED if some corrector stopped at max_iter, else
+ * LRFG_RANK_LIMITED if some corrector stopped at its rank floor (per-corrector
+ * statuses in out->status). */
 int lrfg_solve(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int nE,
                void* d_ws, size_t ws_bytes, void* stream, lrfg_result* out);
 

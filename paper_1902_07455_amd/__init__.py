@@ -214,10 +214,11 @@ class Solver:
             sh = _stream_handle(stream)
             rc = L.lrfg_solve_batch(self._plan, cs, len(coeffs), Eptr, nE, C.c_void_p(ws.data_ptr()),
                                     self.workspace_bytes, C.c_void_p(sh), rs)
-        check(rc, allow=(_lib.OK, _lib.NOT_CONVERGED))
+        check(rc, allow=(_lib.OK, _lib.NOT_CONVERGED, _lib.RANK_LIMITED))
         out = []
         for k, (A, iters, hist, ranks, status) in enumerate(bufs):
-            rck = _lib.OK if np.all(status == 0) else _lib.NOT_CONVERGED
+            rck = (_lib.NOT_CONVERGED if np.any(status == _lib.NOT_CONVERGED) else
+                   _lib.RANK_LIMITED if np.any(status == _lib.RANK_LIMITED) else _lib.OK)
             out.append(SolveResult(A, iters, hist, ranks, status, rck, rs[k].setup_ms, rs[k].solve_ms))
         return out
 

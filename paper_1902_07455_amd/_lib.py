@@ -16,6 +16,7 @@ SOLVER_PCG, SOLVER_MR = 0, 1
 PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = 0, 1, 2
 
 OK, NOT_CONVERGED, EINVAL, ECOEFF, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
+RANK_LIMITED = 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)

@@ -139,6 +139,7 @@ const char* lrfg_status_string(int s) {
   switch (s) {
     case LRFG_OK: return "ok";
     case LRFG_NOT_CONVERGED: return "not converged (A_H written)";
+    case LRFG_RANK_LIMITED: return "stopped at the rank cap's residual floor (A_H written)";
     case LRFG_EINVAL: return "invalid argument";
     case LRFG_ECOEFF: return "coefficient not finite and positive";
     case LRFG_EWORKSPACE: return "workspace too small or misaligned";
@@ -309,7 +310,7 @@ static int solve_impl(lrfg_plan* plan, const lrfg_coeff* a, int count, const dou
   for (int b = 0; b < count; ++b) {
     const int rc = full_one(plan, &a[b], E, nE, d_ws, need, stream, &outs[b]);
     if (rc < 0) return rc;
-    if (rc != LRFG_OK) worst = rc;
+    worst = worse_status(worst, rc);
   }
   return worst;
 }

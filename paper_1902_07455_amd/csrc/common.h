@@ -105,6 +105,13 @@ struct ScopedEvents {
 };
 
 // ---------------------------------------------------------------- complex
+// The worse of two non-negative solve statuses: OK < RANK_LIMITED <
+// NOT_CONVERGED (negative codes are errors and are returned before).
+inline int worse_status(int a, int b) {
+  auto rank = [](int v) { return v == LRFG_OK ? 0 : (v == LRFG_RANK_LIMITED ? 1 : 2); };
+  return rank(a) >= rank(b) ? a : b;
+}
+
 __host__ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -581,8 +581,8 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     int rc = LRFG_OK;
     for (int b = 0; b < nB; ++b) {
       const int r = tucker_solve(pl, acs[b], E, nEp, ws, ws_bytes, s, &outs[b]);
-      if (r != LRFG_OK && r != LRFG_NOT_CONVERGED) return r;
-      if (r != LRFG_OK) rc = r;
+      if (r < 0) return r;
+      rc = worse_status(rc, r);
     }
     return rc;
   }
@@ -760,6 +760,9 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& res0,
                    std::vector<int>& st, bool record) -> int {
     std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
+    // whether the latest restart was followed by a new best iterate: a restart
+    // that brings none ends the solve (the residual sits at the rank floor)
+    std::vector<char> restart_paid(nE, 1);
     std::vector<double> best(nE, INFINITY), zzh(nE), en(nE), best_en(nE, INFINITY);
     // Once a system's residual has failed to decrease, the FP64 PCG keeps
     // the iterate of lowest energy (the energy form of eq. homog, evaluated
@@ -856,6 +859,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         if (better) {
           if (emode[e]) best_en[e] = en[e];
           since_best[e] = 0;
+          restart_paid[e] = 1;
           improved[e >> 6] |= 1ull << (e & 63);
           if (record) {
             kbest[e] = kx[e];
@@ -867,16 +871,17 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
           hdone[e] = 1;
           changed = true;
-        } else if (since_best[e] >= patience && restarts[e] < max_restarts) {
+        } else if (since_best[e] >= patience && restarts[e] < max_restarts && restart_paid[e]) {
           // the recursive residual has drifted from b - K x under truncation
           // (Sec. 3.3): restart from the best iterate
           ++restarts[e];
           since_best[e] = 0;
+          restart_paid[e] = 0;
           restart.m[e >> 6] |= 1ull << (e & 63);
         } else if (since_best[e] >= patience) {
           hdone[e] = 1;  // stagnation: the residual failed to decrease
           changed = true;
-          if (best[e] > tol) st[e] = LRFG_NOT_CONVERGED;
+          if (best[e] > tol) st[e] = LRFG_RANK_LIMITED;
         }
       }
       LRFG_TRY(tt_copy_systems(C.x, C.xb, nE, improved, s));
@@ -1085,7 +1090,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       }
       if (out->iters) out->iters[i] = iters[ei];
       if (out->status) out->status[i] = status[ei];
-      if (status[ei] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+      rc = worse_status(rc, status[ei]);
       if (out->res_hist)
         for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)ei * maxit + k];
       if (out->ranks) {
@@ -1550,6 +1555,9 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& r0,
                    std::vector<int>& st, bool record) -> int {
     std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
+    // whether the latest restart was followed by a new best iterate: a restart
+    // that brings none ends the solve (the residual sits at the rank floor)
+    std::vector<char> restart_paid(nE, 1);
     std::vector<double> best(nE, INFINITY), zzh(nE);
     for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
     LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
@@ -1622,6 +1630,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
         if (res < best[e]) {
           best[e] = res;
           since_best[e] = 0;
+          restart_paid[e] = 1;
           LRFG_TRY(tk_copy_system(C.x, C.xb, e, s));
           if (record)
             for (int j = 0; j < 3; ++j) kbest[j * nE + e] = kx[j * nE + e];
@@ -1631,14 +1640,15 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
         if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
           hdone[e] = 1;
           changed = true;
-        } else if (since_best[e] >= patience && restarts[e] < max_restarts) {
+        } else if (since_best[e] >= patience && restarts[e] < max_restarts && restart_paid[e]) {
           ++restarts[e];  // restart from the best iterate (as in the train path)
           since_best[e] = 0;
+          restart_paid[e] = 0;
           restart.m[e >> 6] |= 1ull << (e & 63);
         } else if (since_best[e] >= patience) {
           hdone[e] = 1;
           changed = true;
-          if (best[e] > tol) st[e] = LRFG_NOT_CONVERGED;
+          if (best[e] > tol) st[e] = LRFG_RANK_LIMITED;
         }
       }
       if (changed) LRFG_TRY(upload_done(hdone));
@@ -1786,7 +1796,7 @@ int tucker_solve(LowRankPlan* pl, const lrfg_coeff& ac, const double* E, int nE,
     }
     if (out->iters) out->iters[i] = iters[i];
     if (out->status) out->status[i] = status[i];
-    if (status[i] != LRFG_OK) rc = LRFG_NOT_CONVERGED;
+    rc = worse_status(rc, status[i]);
     if (out->res_hist)
       for (int k = 0; k < maxit; ++k) out->res_hist[(size_t)i * maxit + k] = hist[(size_t)i * maxit + k];
     if (out->ranks) {

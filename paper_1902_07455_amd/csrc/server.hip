@@ -237,7 +237,7 @@ void session_main(lrfg_server* S, Session* se) {
       st_k = LRFG_OK;
       if (r.out->status != nullptr)
         for (int e = 0; e < nE; ++e)
-          if (r.out->status[e] != LRFG_OK) st_k = LRFG_NOT_CONVERGED;
+          st_k = worse_status(st_k, r.out->status[e]);
     }
     c.status = st_k;
     c.batch_size = (int)batch.size();

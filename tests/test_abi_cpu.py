@@ -37,7 +37,7 @@ def test_version_and_status_strings():
     L = _lib()
     lib = L.lib()
     assert lib.lrfg_abi_version() == 1
-    for s in (0, 1, -1, -2, -3, -4, -5):
+    for s in (0, 1, 2, -1, -2, -3, -4, -5):
         assert len(lib.lrfg_status_string(s)) > 0
 
 

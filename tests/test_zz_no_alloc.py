@@ -43,7 +43,7 @@ def _call(L, plan, coeff_kw, E, d, max_iter, dev, noalloc):
         assert L.lrfg_plan_workspace_bytes(plan, nE, C.byref(nb)) == 0
         ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
         rc = L.lrfg_solve(plan, C.byref(c), Eptr, nE, C.c_void_p(ws.data_ptr()), nb.value, stream, C.byref(r))
-    assert rc in (0, 1), (rc, L.lrfg_last_error())
+    assert rc in (0, 1, 2), (rc, L.lrfg_last_error())
     return rc, bufs
 
 
