@@ -142,6 +142,13 @@ constexpr uint64_t kRestartKeys = 1ull << 62;
 struct SysMask {
   unsigned long long m[4];
 };
+// v[a] <-> v[b] (one thread)
+__global__ void k_swap2(double* __restrict__ v, int a, int b) {
+  const double t = v[a];
+  v[a] = v[b];
+  v[b] = t;
+}
+
 __global__ void k_pick(double* __restrict__ dst, const double* __restrict__ src, SysMask mask, int nE) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nE && ((mask.m[e >> 6] >> (e & 63)) & 1ull)) dst[e] = src[e];
@@ -701,34 +708,38 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   // Energy form of eq. (homog) for system e's own field: A(x_e) =
   // mean(a)|E_e|^2 + 2 E_e.m1 + sum_alpha <a (.) D_alpha x_e, D_alpha x_e>/|N|,
   // exact for the given trains (no truncation); it bounds A_H E_e.E_e from
-  // above and decreases as x_e improves (Sec. 4.3).
-  auto energy_diag = [&](const TTB& X, std::vector<double>& en) -> int {
-    for (int e = 0; e < nE; ++e) {
+  // above and decreases as x_e improves (Sec. 4.3).  For the first n trains
+  // of X; train k holds system slot[k] (all of them, in order, without slot).
+  auto energy_diag = [&](const TTB& X, std::vector<double>& en, int n, const int* slot) -> int {
+    for (int k = 0; k < n; ++k) {
+      const int e = slot != nullptr ? slot[k] : k;
       double ee = 0.0;
       for (int al = 0; al < d; ++al) ee += Ev(e, al) * Ev(e, al);
-      en[e] = mean_a[na == 1 ? 0 : e] * ee;
+      en[k] = mean_a[na == 1 ? 0 : e] * ee;
     }
-    // <a, D_alpha x_e> into dots[2 alpha nE + e], <a (.) D_alpha x_e, D_alpha x_e>
-    // into dots[(2 alpha + 1) nE + e]; one read at the end
+    // <a, D_alpha x_k> into dots[2 alpha n + k], <a (.) D_alpha x_k, D_alpha x_k>
+    // into dots[(2 alpha + 1) n + k]; one read at the end
     for (int al = 0; al < d; ++al) {
       TTB g = X;
       g.c[al] = C.gcore;
-      LRFG_TRY(tt_mode_apply(X, g, al, 0, 0.0, 1.0, C.f[al], nE, s));
-      LRFG_TRY(tt_dot(C.a, g, C.dots + 2 * al * nE, C.dscr, nE, s));
+      LRFG_TRY(tt_mode_apply(X, g, al, 0, 0.0, 1.0, C.f[al], n, s));
+      LRFG_TRY(tt_dot(C.a, g, C.dots + 2 * al * n, C.dscr, n, s));
       if (d == 3) {
-        LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s, 1));
+        LRFG_TRY(tt_hadamard(C.a, g, C.kr, n, s, 1));
         const KrMid km = kr_mid(C, g);
-        LRFG_TRY(C.rd.kr_dot(C.kr, km, g, C.dots + (2 * al + 1) * nE, C.dscr, C.dscr_n, nE, s));
+        LRFG_TRY(C.rd.kr_dot(C.kr, km, g, C.dots + (2 * al + 1) * n, C.dscr, C.dscr_n, n, s));
       } else {
-        LRFG_TRY(tt_hadamard(C.a, g, C.kr, nE, s));
-        LRFG_TRY(tt_dot(C.kr, g, C.dots + (2 * al + 1) * nE, C.dscr, nE, s));
+        LRFG_TRY(tt_hadamard(C.a, g, C.kr, n, s));
+        LRFG_TRY(tt_dot(C.kr, g, C.dots + (2 * al + 1) * n, C.dscr, n, s));
       }
     }
-    std::vector<double> v((size_t)2 * d * nE);
-    LRFG_TRY(read_dev(C, C.dots, v.data(), 2 * d * nE));
+    std::vector<double> v((size_t)2 * d * n);
+    LRFG_TRY(read_dev(C, C.dots, v.data(), 2 * d * n));
     for (int al = 0; al < d; ++al)
-      for (int e = 0; e < nE; ++e)
-        en[e] += (2.0 * Ev(e, al) * v[(size_t)2 * al * nE + e] + v[(size_t)(2 * al + 1) * nE + e]) / Ntot;
+      for (int k = 0; k < n; ++k) {
+        const int e = slot != nullptr ? slot[k] : k;
+        en[k] += (2.0 * Ev(e, al) * v[(size_t)2 * al * n + k] + v[(size_t)(2 * al + 1) * n + k]) / Ntot;
+      }
     return LRFG_OK;
   };
 
@@ -743,13 +754,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   // kept ranks of the latest x truncation (bond 1 then bond 2, per system),
   // copied with the residual read, and those of each system's kept iterate
   std::vector<int> kx(2 * nE, 0), kbest(2 * nE, 0);
-  auto fetch_kept = [&]() -> int {
-    LRFG_HIP(hipMemcpyAsync(kx.data(), C.rd.kept, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
-    LRFG_HIP(hipMemcpyAsync(kx.data() + nE, C.rd.kept + C.rd.nE, sizeof(int) * nE, hipMemcpyDeviceToHost, s));
+  // kx[k], kx[nE + k]: kept ranks of train k of the latest x truncation, k < n
+  auto fetch_kept = [&](int n) -> int {
+    LRFG_HIP(hipMemcpyAsync(kx.data(), C.rd.kept, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipMemcpyAsync(kx.data() + nE, C.rd.kept + C.rd.nE, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     return LRFG_OK;
   };
-  auto upload_done = [&](const std::vector<int>& hd) -> int {
-    LRFG_HIP(hipMemcpyAsync(C.done, hd.data(), sizeof(int) * nE, hipMemcpyHostToDevice, s));
+  auto upload_done = [&](const std::vector<int>& hd, int n) -> int {
+    LRFG_HIP(hipMemcpyAsync(C.done, hd.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     return LRFG_OK;
   };
   // One truncated PCG (or MR) solve of K x = C.b, best iterate into C.xb,
@@ -757,8 +769,21 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   // xb = 0.  res0[e] = ||P~^-1 b_e|| (Fourier-coefficient scaling), st[e] its
   // status; with `record` the relative residuals go to hist and the
   // iteration counts to iters, else the counts are added to iters.
+  //
+  // Host state is kept per system, device state per slot: slot k holds
+  // system perm[k].  With one coefficient train for all systems, a system
+  // that finishes leaves the batch: its slot takes the state of the last
+  // active slot and the batched steps run on the nA active slots only.  A
+  // system's arithmetic does not depend on its slot or on the batch it
+  // travels in (per-matrix GEMM splits, one sketch per truncation call), so
+  // the results are those of the full batch; the slot order is restored
+  // at the end.
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& res0,
                    std::vector<int>& st, bool record) -> int {
+    const bool compact = na == 1;
+    int nA = nE;
+    std::vector<int> perm(nE), slot_done(nE);
+    for (int k = 0; k < nE; ++k) perm[k] = k;
     std::vector<int> hdone(skip), since_best(nE, 0), its(nE, 0), restarts(nE, 0);
     // whether the latest restart was followed by a new best iterate: a restart
     // that brings none ends the solve (the residual sits at the rank floor)
@@ -773,11 +798,83 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     // no energy is evaluated.
     const bool by_energy = record && P.solver == LRFG_SOLVER_PCG && C.rd.prec == LRFG_PREC_FP64;
     std::vector<char> emode(nE, 0);
+    auto push_done = [&]() -> int {
+      for (int k = 0; k < nA; ++k) slot_done[k] = hdone[perm[k]];
+      return upload_done(slot_done, nA);
+    };
+    // train k of a batch view
+    auto one = [&](const TTB& X, int k) {
+      TTB v = X;
+      for (int j = 0; j < d; ++j) v.c[j] = X.c[j] + (long long)k * X.s[j];
+      return v;
+    };
+    auto swap_trains = [&](const TTB& X, int a, int b) -> int {
+      TTB t0 = one(C.tmp, 0), xa = one(X, a), xb = one(X, b);
+      LRFG_TRY(tt_copy(xa, t0, 1, s));
+      LRFG_TRY(tt_copy(xb, xa, 1, s));
+      LRFG_TRY(tt_copy(t0, xb, 1, s));
+      return LRFG_OK;
+    };
+    auto set_views = [&](int n) {
+      C.nE = n;
+      for (int j = 0; j < d; ++j) {
+        C.r.c[j] = C.xr.c[j] + (long long)n * C.xr.s[j];
+        C.q.c[j] = C.pq.c[j] + (long long)n * C.pq.s[j];
+      }
+    };
+    // finished systems leave the active prefix
+    auto compact_slots = [&]() -> int {
+      int n = nA;
+      for (int k = nA - 1; k >= 0; --k) {
+        if (!hdone[perm[k]]) continue;
+        const int last = n - 1;
+        if (k != last) {
+          LRFG_TRY(swap_trains(C.x, k, last));
+          LRFG_TRY(swap_trains(C.r, k, last));
+          LRFG_TRY(swap_trains(C.p, k, last));
+          LRFG_TRY(swap_trains(C.xb, k, last));
+          LRFG_TRY(swap_trains(C.b, k, last));
+          hipLaunchKernelGGL(k_swap2, dim3(1), dim3(1), 0, s, C.rho, k, last);
+          LRFG_LAUNCHED();
+          std::swap(perm[k], perm[last]);
+        }
+        --n;
+      }
+      if (n == nA) return LRFG_OK;
+      // r of the active systems moves down to follow x: [x; r] stays one
+      // batch of 2 n trains (ascending copies never overwrite a pending source)
+      for (int k = 0; k < n; ++k) {
+        TTB dst = one(C.xr, n + k);
+        LRFG_TRY(tt_copy(one(C.xr, nA + k), dst, 1, s));
+      }
+      nA = n;
+      set_views(nA);
+      return push_done();
+    };
+    // the slot order of the outputs back to the system order
+    auto restore_order = [&]() -> int {
+      bool moved = false;
+      for (int k = 0; k < nE; ++k) moved = moved || perm[k] != k;
+      if (moved) {
+        for (const TTB* X : {&C.xb, &C.b}) {
+          for (int k = 0; k < nE; ++k) {
+            TTB dst = one(C.z, perm[k]);
+            LRFG_TRY(tt_copy(one(*X, k), dst, 1, s));
+          }
+          TTB dst = *X;
+          LRFG_TRY(tt_copy(C.z, dst, nE, s));
+        }
+      }
+      nA = nE;
+      set_views(nE);
+      return LRFG_OK;
+    };
     for (int e = 0; e < nE; ++e) st[e] = LRFG_OK;
     LRFG_TRY(tt_fill(C.mones, nE, -1.0, s));
     LRFG_TRY(tt_zero(C.xr, 2 * nE, s));
     LRFG_TRY(tt_zero(C.xb, nE, s));
-    LRFG_TRY(upload_done(hdone));
+    set_views(nE);
+    LRFG_TRY(push_done());
     if (P.solver == LRFG_SOLVER_PCG) {
       LRFG_TRY(tt_copy(C.b, C.r, nE, s));
       LRFG_TRY(apply_P(C, C.r, C.z));
@@ -796,7 +893,8 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       res0[e] = std::sqrt(std::max(zzh[e], 0.0));
       if (res0[e] <= floor_abs[e]) hdone[e] = 1;
     }
-    LRFG_TRY(upload_done(hdone));
+    LRFG_TRY(push_done());
+    if (compact) LRFG_TRY(compact_slots());
     for (int it = 0; it < max_it; ++it) {
       if (it > 0) gate_point();
       bool all = true;
@@ -806,19 +904,19 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         LRFG_TRY(apply_K(C, C.p, C.q));
         LRFG_TRY(dot(C, C.p, C.q, C.pqd));
         hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.rho, (const double*)C.pqd,
-                           (const int*)C.done, C.alpha, nE);
-        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+                           (const int*)C.done, C.alpha, nA);
+        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nA);
         LRFG_LAUNCHED();
         LRFG_TRY(update_xr(C));   // x += alpha p ; r -= alpha q
-        LRFG_TRY(fetch_kept());
+        LRFG_TRY(fetch_kept(nA));
         LRFG_TRY(apply_P(C, C.r, C.z));
         LRFG_TRY(dot(C, C.r, C.z, C.dots));
         LRFG_TRY(dot(C, C.z, C.z, C.zz));
         hipLaunchKernelGGL(k_beta, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, C.rho,
-                           (const int*)C.done, C.beta, nE);
+                           (const int*)C.done, C.beta, nA);
         LRFG_LAUNCHED();
         LRFG_TRY(axpby(C, C.z, C.p, C.beta, C.tmp));
-        LRFG_TRY(tt_copy(C.tmp, C.p, nE, s));
+        LRFG_TRY(tt_copy(C.tmp, C.p, nA, s));
       } else {
         // Cr = T(P~^-1 T(K r)); omega = (Cr, r)/(Cr, Cr); u += omega r; r -= omega Cr
         LRFG_TRY(apply_K(C, C.r, C.tmp));
@@ -826,49 +924,50 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         LRFG_TRY(dot(C, C.z, C.r, C.dots));
         LRFG_TRY(dot(C, C.z, C.z, C.pqd));
         hipLaunchKernelGGL(k_ratio, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.dots, (const double*)C.pqd,
-                           (const int*)C.done, C.alpha, nE);
-        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nE);
+                           (const int*)C.done, C.alpha, nA);
+        hipLaunchKernelGGL(k_pm, dim3(1), dim3(kMaxSystems), 0, s, (const double*)C.alpha, C.coef2, nA);
         LRFG_LAUNCHED();
         // [p; q] = [r; Cr] then [u; r] += [omega; -omega] [r; Cr]
-        LRFG_TRY(tt_copy(C.r, C.p, nE, s));
-        LRFG_TRY(tt_copy(C.z, C.q, nE, s));
+        LRFG_TRY(tt_copy(C.r, C.p, nA, s));
+        LRFG_TRY(tt_copy(C.z, C.q, nA, s));
         LRFG_TRY(update_xr(C));
-        LRFG_TRY(fetch_kept());
+        LRFG_TRY(fetch_kept(nA));
         LRFG_TRY(dot(C, C.r, C.r, C.zz));
       }
-      LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+      LRFG_TRY(read_dev(C, C.zz, zzh.data(), nA));
       bool need_en = false;
-      for (int e = 0; e < nE; ++e) need_en = need_en || (!hdone[e] && emode[e]);
-      if (need_en) LRFG_TRY(energy_diag(C.x, en));
+      for (int k = 0; k < nA; ++k) need_en = need_en || (!hdone[perm[k]] && emode[perm[k]]);
+      if (need_en) LRFG_TRY(energy_diag(C.x, en, nA, perm.data()));
       bool changed = false, switched = false;
-      unsigned long long improved[4] = {0, 0, 0, 0};  // systems whose x becomes the best iterate
-      SysMask restart{{0, 0, 0, 0}};                  // systems restarted from their best iterate
-      SysMask to_energy{{0, 0, 0, 0}};                // systems switching to the energy rule
-      for (int e = 0; e < nE; ++e) {
+      unsigned long long improved[4] = {0, 0, 0, 0};  // slots whose x becomes the best iterate
+      SysMask restart{{0, 0, 0, 0}};                  // slots restarted from their best iterate
+      SysMask to_energy{{0, 0, 0, 0}};                // slots switching to the energy rule
+      for (int k = 0; k < nA; ++k) {
+        const int e = perm[k];
         if (hdone[e]) continue;
-        const double res = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+        const double res = std::sqrt(std::max(zzh[k], 0.0)) / res0[e];
         if (record) hist[(size_t)e * maxit + it] = res;
         its[e] = it + 1;
-        const bool better = emode[e] ? en[e] < best_en[e] : res < best[e];
+        const bool better = emode[e] ? en[k] < best_en[e] : res < best[e];
         if (res < best[e]) best[e] = res;
         if (!better && by_energy && !emode[e]) {
           emode[e] = 1;
           switched = true;
-          to_energy.m[e >> 6] |= 1ull << (e & 63);
+          to_energy.m[k >> 6] |= 1ull << (k & 63);
         }
         if (better) {
-          if (emode[e]) best_en[e] = en[e];
+          if (emode[e]) best_en[e] = en[k];
           since_best[e] = 0;
           restart_paid[e] = 1;
-          improved[e >> 6] |= 1ull << (e & 63);
+          improved[k >> 6] |= 1ull << (k & 63);
           if (record) {
-            kbest[e] = kx[e];
-            kbest[nE + e] = kx[nE + e];
+            kbest[e] = kx[k];
+            kbest[nE + e] = kx[nE + k];
           }
         } else {
           ++since_best[e];
         }
-        if (res <= tol || std::sqrt(std::max(zzh[e], 0.0)) <= floor_abs[e]) {
+        if (res <= tol || std::sqrt(std::max(zzh[k], 0.0)) <= floor_abs[e]) {
           hdone[e] = 1;
           changed = true;
         } else if (since_best[e] >= patience && restarts[e] < max_restarts && restart_paid[e]) {
@@ -877,26 +976,26 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
           ++restarts[e];
           since_best[e] = 0;
           restart_paid[e] = 0;
-          restart.m[e >> 6] |= 1ull << (e & 63);
+          restart.m[k >> 6] |= 1ull << (k & 63);
         } else if (since_best[e] >= patience) {
           hdone[e] = 1;  // stagnation: the residual failed to decrease
           changed = true;
           if (best[e] > tol) st[e] = LRFG_RANK_LIMITED;
         }
       }
-      LRFG_TRY(tt_copy_systems(C.x, C.xb, nE, improved, s));
-      if (changed) LRFG_TRY(upload_done(hdone));
+      LRFG_TRY(tt_copy_systems(C.x, C.xb, nA, improved, s));
+      if (changed) LRFG_TRY(push_done());
       if (switched) {
         // the best iterate so far (by residual) enters the energy rule
-        std::vector<double> eb(nE);
-        LRFG_TRY(energy_diag(C.xb, eb));
-        for (int e = 0; e < nE; ++e)
-          if (sys_bit(to_energy, e)) best_en[e] = eb[e];
+        std::vector<double> eb(nA);
+        LRFG_TRY(energy_diag(C.xb, eb, nA, perm.data()));
+        for (int k = 0; k < nA; ++k)
+          if (sys_bit(to_energy, k)) best_en[perm[k]] = eb[k];
       }
       if (restart.m[0] | restart.m[1] | restart.m[2] | restart.m[3]) {
         // residual replacement: x = x_best, r = T(b - K x), z = T(P~^-1 r),
         // p = z, rho = (r, z) for the restarted systems (the others keep
-        // their state: the batched steps run for every system and are
+        // their state: the batched steps run for every slot and are
         // copied into the restarted ones only)
         // The restart's truncations draw their sketches from a key space of
         // their own and leave the iteration's sequence as it was, so that a
@@ -906,22 +1005,24 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         C.rd.counter = kRestartKeys | ((uint64_t)it << 8);
         LRFG_TRY(apply_K(C, C.xb, C.tmp));
         LRFG_TRY(axpby(C, C.b, C.tmp, C.mones, C.z));
-        LRFG_TRY(tt_copy_systems(C.z, C.r, nE, restart.m, s));
-        LRFG_TRY(tt_copy_systems(C.xb, C.x, nE, restart.m, s));
+        LRFG_TRY(tt_copy_systems(C.z, C.r, nA, restart.m, s));
+        LRFG_TRY(tt_copy_systems(C.xb, C.x, nA, restart.m, s));
         LRFG_TRY(apply_P(C, C.r, C.z));
         C.rd.counter = saved;
-        LRFG_TRY(tt_copy_systems(C.z, C.p, nE, restart.m, s));
+        LRFG_TRY(tt_copy_systems(C.z, C.p, nA, restart.m, s));
         LRFG_TRY(dot(C, C.r, C.z, C.dots));
-        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kMaxSystems), 0, s, C.rho, (const double*)C.dots, restart, nE);
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kMaxSystems), 0, s, C.rho, (const double*)C.dots, restart, nA);
         LRFG_LAUNCHED();
         // the best residual becomes the true one of the best iterate
         LRFG_TRY(dot(C, C.z, C.z, C.zz));
-        LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+        LRFG_TRY(read_dev(C, C.zz, zzh.data(), nA));
         if (!by_energy)
-          for (int e = 0; e < nE; ++e)
-            if (sys_bit(restart, e)) best[e] = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+          for (int k = 0; k < nA; ++k)
+            if (sys_bit(restart, k)) best[perm[k]] = std::sqrt(std::max(zzh[k], 0.0)) / res0[perm[k]];
       }
+      if (compact && changed) LRFG_TRY(compact_slots());
     }
+    LRFG_TRY(restore_order());
     for (int e = 0; e < nE; ++e) {
       if (!hdone[e]) st[e] = LRFG_NOT_CONVERGED;
       if (skip[e] || res0[e] <= floor_abs[e]) st[e] = LRFG_OK;  // zero right-hand side: zero corrector
@@ -980,14 +1081,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       LRFG_TRY(inner(tol_in, maxit, odone, r0_in, st_in, false));
       C.rd.prec = LRFG_PREC_FP64;
       LRFG_TRY(axpby(C, C.xa, C.xb, C.ones, C.tmp));   // x <- T(x + delta)
-      LRFG_TRY(fetch_kept());
+      LRFG_TRY(fetch_kept(nE));
       LRFG_TRY(tt_copy(C.tmp, C.xa, nE, s));
       LRFG_TRY(apply_K(C, C.xa, C.tmp));               // r <- T(b - K x)
       LRFG_TRY(axpby(C, C.b0, C.tmp, C.mones, C.b));
       LRFG_TRY(apply_P(C, C.b, C.z));
       LRFG_TRY(dot(C, C.z, C.z, C.zz));
       LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
-      LRFG_TRY(energy_diag(C.xa, en));
+      LRFG_TRY(energy_diag(C.xa, en, nE, nullptr));
       bool escalate = false;
       unsigned long long improved[4] = {0, 0, 0, 0};
       for (int e = 0; e < nE; ++e) {
