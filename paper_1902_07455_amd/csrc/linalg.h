@@ -28,6 +28,12 @@ struct Gemm {
   // term; the defaults give t sA, t sB, t sC).
   int adiv = 1, amod = 0, bdiv = 1, bmod = 0, cdiv = 1, cmod = 0;
   long long sA2 = 0, sB2 = 0, sC2 = 0;
+  // Column map (FP64, B not transposed): column c of B lies at
+  // (c / bcw) bchi + c % bcw of its row, column c of C at
+  // (c / ccw) cchi + c % ccw (a width of 0: at c), so one product can run
+  // over columns gathered from several blocks of an array.
+  int bcw = 0, ccw = 0;
+  long long bchi = 0, cchi = 0;
 };
 
 // The batch map as the kernels receive it; t = tbase + the launch's batch index.
@@ -37,6 +43,8 @@ struct BatchMap {
   long long sA2, sB2;
   int cdiv, cmod;
   long long sC2;
+  int bcw, ccw;
+  long long bchi, cchi;
   // batch indices stay below 2^31 (gemm() launches at most 65535 matrices
   // per chunk from a base below the batch count), so the splits are 32-bit
   __host__ __device__ static long long off(long long t, int dv, int md, long long s1, long long s2) {
@@ -46,6 +54,13 @@ struct BatchMap {
   __host__ __device__ long long c_off(long long t, long long sC) const { return off(t, cdiv, cmod, sC, sC2); }
   __host__ __device__ long long a_off(long long t, long long sA) const { return off(t, adiv, amod, sA, sA2); }
   __host__ __device__ long long b_off(long long t, long long sB) const { return off(t, bdiv, bmod, sB, sB2); }
+  // column maps (columns below 2^31)
+  __host__ __device__ long long bcol(int c) const {
+    return bcw > 0 ? (long long)((unsigned)c / (unsigned)bcw) * bchi + (long long)((unsigned)c % (unsigned)bcw) : c;
+  }
+  __host__ __device__ long long ccol(int c) const {
+    return ccw > 0 ? (long long)((unsigned)c / (unsigned)ccw) * cchi + (long long)((unsigned)c % (unsigned)ccw) : c;
+  }
 };
 
 // Scratch doubles gemm() may use for a split-K reduction of this shape.

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
       int kk, j;
       if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
       const int gk = k0 + kk, gj = n0 + j;
-      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
+      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + bm.bcol(gj)]) : 0.0;
     }
   };
   // The K loop with the wave's live MFMA blocks (NR x NC of its 2 x 2,
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = Cb + (long long)row * ldc + col;
+            double* c = Cb + (long long)row * ldc + bm.ccol(col);
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
       int kk, j;
       if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
       const int gk = k0 + kk, gj = n0 + j;
-      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + gj]) : 0.0;
+      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + bm.bcol(gj)]) : 0.0;
     }
   };
   auto stage = [&](int buf) {
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
           if (part != nullptr) {
             part[((long long)bz * m + row) * n + col] = v;
           } else {
-            double* c = Cb + (long long)row * ldc + col;
+            double* c = Cb + (long long)row * ldc + bm.ccol(col);
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
           }
         }
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
                        ((red[4][o] + red[5][o]) + (red[6][o] + red[7][o]));
     const long long bt = e / mn, idx = e - bt * mn;
     const int row = (int)(idx / n), col = (int)(idx - (idx / n) * n);
-    double* c = C + bm.c_off(bm.tbase + bt, sC) + (long long)row * ldc + col;
+    double* c = C + bm.c_off(bm.tbase + bt, sC) + (long long)row * ldc + bm.ccol(col);
     *c = (beta == 0.0) ? alpha * sum : alpha * sum + beta * (*c);
   }
 }
@@ -484,6 +484,10 @@ struct GemmLayout {
 };
 GemmLayout gemm_layout(const Gemm& g) {
   if (g.m >= 128 && g.n >= 128) return {4, 4};
+  // a side of 65..96 fills three 32-wide tiles (76-100 %) rather than two
+  // 64-wide ones (51-75 %)
+  if (g.m > 64 && g.m <= 96 && g.n >= 128) return {1, 4};
+  if (g.n > 64 && g.n <= 96 && g.m >= 128) return {4, 1};
   if (g.m <= 32 && g.n <= 32) return {1, 1};
   if (g.n <= 32) return g.m <= 64 ? GemmLayout{2, 1} : GemmLayout{4, 1};
   if (g.m <= 32) return g.n <= 64 ? GemmLayout{1, 2} : GemmLayout{1, 4};
@@ -1367,6 +1371,10 @@ size_t gemm_scratch_doubles(const Gemm& g) {
 
 int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return LRFG_OK;
+  if ((g.bcw > 0 && (g.tb || g.prec != 0)) || (g.ccw > 0 && g.prec != 0)) {
+    set_error("gemm: column maps need FP64 and an untransposed B");
+    return LRFG_EUNSUPPORTED;
+  }
   int ks = choose_ksplit(g);
   if (ks > 1) {
     // as many splits as the scratch holds for one matrix
@@ -1391,7 +1399,8 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
   for (int b0 = 0; b0 < g.batch; b0 += chunk) {
     Gemm c = g;
     c.batch = std::min(chunk, g.batch - b0);
-    const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2, g.cdiv, g.cmod, g.sC2};
+    const BatchMap bm{b0, g.adiv, g.amod, g.bdiv, g.bmod, g.sA2, g.sB2, g.cdiv, g.cmod, g.sC2,
+                      g.bcw, g.ccw, g.bchi, g.cchi};
     const int gtm = c.prec != 0 ? BM : lay.tm(), gtn = c.prec != 0 ? BN : lay.tn();
     dim3 grid(ceil_div(c.n, gtn), ceil_div(c.m, gtm), c.batch * ks);
 #define LRFG_GEMM_F64(TA, TB, WM, WN)                                                                         \

@@ -783,21 +783,36 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
                            N2, (const double*)kz, su, rg1, l1, X2p, sx);
         LRFG_LAUNCHED();
       } else {
-        // X2'[p][n][j rg1 + m] = sum_i a[i][n][j] U[p][i][n][m]: one small
-        // GEMM (a^T times U) per (system, p, n), in groups of amod systems
+        // X2'[p][n][j rg1 + m] = sum_i a[i][n][j] U[p][i][n][m], in groups
+        // of amod systems.  FP64: one product a_n^T (ra1 x ra0) times
+        // U_n (ra0 x l1 rg1) per (system, n), its columns (p, m) mapped onto
+        // U's and X2''s layouts; otherwise one small product per (system,
+        // p, n)
         const int amod = mid->amod > 0 ? mid->amod : nE;
         for (int s0 = 0; s0 < nE; s0 += amod) {
           const int ns = std::min(amod, nE - s0);
-          GemmB g(ra1, rg1, ra0, ns * l1 * N2);
-          g.a(mid->a, (long long)N2 * ra1, mid->sa, true).b(kz + s0 * su, (long long)N2 * rg1, (long long)ra0 * N2 * rg1)
-              .c(X2p + s0 * sx, rg1, (long long)ra1 * rg1);
-          g.g.adiv = l1 * N2;
-          g.g.amod = N2;
-          g.g.sA2 = ra1;
-          g.g.bdiv = N2;
-          g.g.bmod = N2;
-          g.g.sB2 = rg1;
-          LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s));
+          if (pj == LRFG_PREC_FP64) {
+            GemmB g(ra1, l1 * rg1, ra0, ns * N2);
+            g.a(mid->a, (long long)N2 * ra1, mid->sa, true).b(kz + s0 * su, (long long)N2 * rg1, su)
+                .c(X2p + s0 * sx, rg1, sx);
+            g.g.adiv = N2; g.g.amod = N2; g.g.sA2 = ra1;
+            g.g.bdiv = N2; g.g.bmod = N2; g.g.sB2 = rg1;
+            g.g.cdiv = N2; g.g.cmod = N2; g.g.sC2 = R2;
+            g.g.bcw = rg1; g.g.bchi = (long long)ra0 * N2 * rg1;
+            g.g.ccw = rg1; g.g.cchi = (long long)N2 * R2;
+            LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+          } else {
+            GemmB g(ra1, rg1, ra0, ns * l1 * N2);
+            g.a(mid->a, (long long)N2 * ra1, mid->sa, true).b(kz + s0 * su, (long long)N2 * rg1, (long long)ra0 * N2 * rg1)
+                .c(X2p + s0 * sx, rg1, (long long)ra1 * rg1);
+            g.g.adiv = l1 * N2;
+            g.g.amod = N2;
+            g.g.sA2 = ra1;
+            g.g.bdiv = N2;
+            g.g.bmod = N2;
+            g.g.sB2 = rg1;
+            LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s));
+          }
         }
       }
     }
