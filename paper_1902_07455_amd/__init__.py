@@ -223,9 +223,11 @@ class Solver:
         return out
 
     def close(self):
+        """Destroy the plan and release its device workspace."""
         if self._plan:
             lib().lrfg_plan_destroy(self._plan)
             self._plan = C.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:
