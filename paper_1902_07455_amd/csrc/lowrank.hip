@@ -359,14 +359,19 @@ int apply_K(Ctx& C, const TTB& v, TTB& out) {
 
 // out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}:
 // the M terms are written straight into the block carriages of their sum
-// (one launch per carriage), then truncated.
+// (one launch per carriage), then truncated.  The middle carriage of the
+// sum is block diagonal; an FP64 truncation (d = 3) contracts its M
+// diagonal blocks alone, so the zeros off them are neither written nor
+// read.
 int apply_P(Ctx& C, const TTB& v, TTB& out) {
   const int d = C.d, nE = C.nE;
   const int M = C.pl->M;
+  const bool blocks = d == 3 && C.rd.prec == LRFG_PREC_FP64;
   TTB comb = C.comb;
   for (int j = 1; j < d; ++j) comb.r[j] = M * v.r[j];
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
-  for (int j = 1; j < d - 1; ++j) LRFG_TRY(tt_fill(comb.c[j], comb.size(j) * nE, 0.0, C.s));
+  if (!blocks)
+    for (int j = 1; j < d - 1; ++j) LRFG_TRY(tt_fill(comb.c[j], comb.size(j) * nE, 0.0, C.s));
   std::vector<double> sc(M), one(M, 1.0);
   for (int m = 0; m < M; ++m) sc[m] = C.pl->w[m] / (4.0 * kPi * kPi);
   for (int j = 0; j < d; ++j) {
@@ -374,7 +379,7 @@ int apply_P(Ctx& C, const TTB& v, TTB& out) {
                                    j > 0, j < d - 1, M, C.pl->t.data(), j == 0 ? sc.data() : one.data(), C.f[j],
                                    C.s));
   }
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE, nullptr, blocks ? M : 1);
 }
 
 // [x; r] <- T([x; r] + coef2 [p; q]) as one truncation of 2 nE trains

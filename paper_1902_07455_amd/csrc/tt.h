@@ -71,8 +71,12 @@ struct Rounder {
   void carve(Arena& ar);
   // out (ranks preset to the nominal output ranks) <- T(in) for `batch`
   // systems (default: nE, the capacity it was carved for); with mid, the
-  // middle carriage of `in` is mid's Hadamard product (in.c[1] unused)
-  int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1, const KrMid* mid = nullptr);
+  // middle carriage of `in` is mid's Hadamard product (in.c[1] unused);
+  // with nblk > 1 (d = 3, FP64, no mid) it is block diagonal, nblk blocks
+  // of (R1 / nblk) x N2 x (R2 / nblk) in the dense layout, and the entries
+  // off those blocks are never read (they need not be zero)
+  int round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch = -1, const KrMid* mid = nullptr,
+            int nblk = 1);
   // dots[e] = <a (.) x_e, y_e> for ns systems (d = 3, FP64) with the middle
   // carriage of a (.) x unformed: kr holds the product's first and last
   // carriages (tt_hadamard with skip = 1), mid its middle as factors (x's

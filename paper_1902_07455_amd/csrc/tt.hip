@@ -706,7 +706,7 @@ static int trunc_mask(Rounder& R, const double* Gm, int l, int c, double tol2, d
   return cut_psd(l, c, Gm, (long long)l * l, tol2, S, (long long)l * c, kept, nE, s);
 }
 
-int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch, const KrMid* mid) {
+int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch, const KrMid* mid, int nblk) {
   ProfScope ps_("tt_round", s);
   if (batch < 0) batch = nE;
   if (batch > nE) {
@@ -746,8 +746,25 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
       set_error("tt_round: structured middle carriage does not fit (R %d %d)", R1, R2);
       return LRFG_EINVAL;
     }
+    if (nblk != 1 && (nblk < 1 || mid != nullptr || prec != LRFG_PREC_FP64 || R1 % nblk != 0 || R2 % nblk != 0)) {
+      set_error("tt_round: %d diagonal blocks do not fit (R %d %d)", nblk, R1, R2);
+      return LRFG_EINVAL;
+    }
+    // block m of a block-diagonal middle carriage: rows (i, n), i in
+    // [m rb0, (m + 1) rb0), columns [m rb1, (m + 1) rb1); its first entry
+    // lies m (rb0 N2 R2 + rb1) past the carriage's
+    const int rb0 = R1 / nblk, rb1 = R2 / nblk;
+    const long long sblk = (long long)rb0 * N2 * R2 + rb1;
     // T2 = X2 W3 ((R1 N2) x l2)
-    if (mid == nullptr) {
+    if (nblk > 1) {
+      // rows of block m times rows [m rb1, (m + 1) rb1) of W3
+      GemmB g(rb0 * N2, l2, rb1, nE * nblk);
+      g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
+      g.g.adiv = nblk; g.g.amod = nblk; g.g.sA2 = sblk;
+      g.g.bdiv = nblk; g.g.bmod = nblk; g.g.sB2 = (long long)rb1 * l2;
+      g.g.cdiv = nblk; g.g.cmod = nblk; g.g.sC2 = (long long)rb0 * N2 * l2;
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    } else if (mid == nullptr) {
       GemmB g(R1 * N2, l2, R2, nE); g.a(in.c[1], R2, in.s[1]).b(W3, l2, (long long)R2 * l2).c(T2, l2, (long long)R1 * N2 * l2);
       LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s));
     } else {
@@ -764,7 +781,19 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
       LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
-    if (mid == nullptr) {
+    if (nblk > 1) {
+      // columns (n, [m rb1, (m + 1) rb1)) of X2' = M1[:, m rb0 .. (m + 1) rb0)
+      // times block m, both sides' columns mapped to (n, k) -> n R2 + k
+      GemmB g(l1, N2 * rb1, rb0, nE * nblk);
+      g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
+          .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
+      g.g.adiv = nblk; g.g.amod = nblk; g.g.sA2 = rb0;
+      g.g.bdiv = nblk; g.g.bmod = nblk; g.g.sB2 = sblk;
+      g.g.cdiv = nblk; g.g.cmod = nblk; g.g.sC2 = rb1;
+      g.g.bcw = rb1; g.g.bchi = R2;
+      g.g.ccw = rb1; g.g.cchi = R2;
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s));
+    } else if (mid == nullptr) {
       GemmB g(l1, N2 * R2, R1, nE); g.a(M1, R1, (long long)l1 * R1).b(in.c[1], (long long)N2 * R2, in.s[1])
           .c(X2p, (long long)N2 * R2, (long long)l1 * N2 * R2);
       LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s));
