@@ -1056,142 +1056,181 @@ __global__ __launch_bounds__(NT) void k_cut_psd(int n, int c, const double* __re
 // ---------------------------------------------------------------- n <= 128
 // The factorisations above keep G, the factor and Z (or the Jacobi columns)
 // as separate n x n arrays in LDS, which caps n at 64.  Sketch sizes up to
-// 128 (rank caps up to about 118) use the forms below, which keep one
-// n x n array: row perm[k] of G is read only at the step that takes perm[k]
-// as pivot, so the factor row k is written over it; and since row k of the
-// factor vanishes at the indices chosen before step k while z_k (the k-th
-// column of P R^-1) vanishes at the indices not yet chosen, z_k is stored
-// in the same row at the chosen indices (the two supports meet only at the
-// pivot, where z_k = 1 / L[k][p] is stored and L[k][p] is not needed again).
+// 128 (rank caps up to about 118) use the forms below, which hold the
+// Schur complement in registers spread over the whole block.
 
 constexpr int kBigN = 128;
 
-// Maximum of a 32-bit key over the wave with ties impossible: the low 7
-// bits carry 127 - index.
+// Maximum of a 32-bit key with ties impossible: the low 7 bits carry
+// 127 - index.
 __device__ inline int pivot_of(unsigned key) { return 127 - (int)(key & 127u); }
 
-// Rank-revealing pivoted Cholesky of the PSD n x n matrix in A (LDS, row
-// stride ld), 64 < n <= 128, by one wave: lane l owns indices l and l + 64.
-// The pivot rule, threshold and left-looking row formation are those of
-// pchol_wave.  On return row perm[k] (k < r) holds the factor row k; with
-// WITHZ, at the indices chosen at steps <= k it holds z_k instead.
-// kch[j] = the step at which index j was taken (n if never).
-template <bool WITHZ>
-__device__ int pchol_wave_big(int n, double* __restrict__ A, int ld, int* __restrict__ perm,
-                              int* __restrict__ kch, double tau) {
-  constexpr int CH = 8;
-  const int lane = threadIdx.x & 63;
-  const int j0 = lane, j1 = lane + 64;
-  const bool v0 = j0 < n, v1 = j1 < n;
-  const int jc0 = v0 ? j0 : n - 1, jc1 = v1 ? j1 : n - 1;  // loads of absent indices stay in range
-  double dg0 = v0 ? A[j0 * ld + j0] : 0.0, dg1 = v1 ? A[j1 * ld + j1] : 0.0;
-  const double d0 = __longlong_as_double(
-      (long long)wave_max_u64((unsigned long long)__double_as_longlong(fmax(fmax(dg0, dg1), 0.0))));
+// Rank-revealing pivoted Cholesky of a PSD n x n matrix, n <= NP <= 128,
+// right-looking over a block of NT = (NP / BR) (NP / BC) threads: thread
+// (ti, tj) holds in a[][] the BR x BC block of the Schur complement at rows
+// BR ti.., columns BC tj.. (zero beyond n), and with WITHZ the same block of
+// bz[q][j] = sum_{m<k} L[m][q] z_m[j] (zero on entry).  Step k takes the
+// largest remaining diagonal entry p as pivot (the key rule of pchol_wave:
+// FP32 value bits relative to the largest initial diagonal entry d0, ties
+// to the lower index), publishes row p of both through LDS, and stops when
+// that entry is at most tau d0.  The factor row is L[k][j] = a[p][j] /
+// sqrt(a[p][p]) at the indices not chosen before (zero at the others); z_k
+// (column k of P R^-1, so that Y z_k are orthonormal when G = Y^T Y) is
+// 1 / L[k][p] at p, -bz[p][j] / L[k][p] at the indices chosen before and
+// zero elsewhere.  Every entry is updated by fma(-L[k][i], L[k][j], a)
+// (and bz by fma(L[k][q], z_k[j], bz)) in step order, which are the fma
+// chains of the left-looking formation.  out(k, j, L[k][j], z_k[j]) is
+// called once per step and index j < NP by the threads of block row 0.
+// Returns the rank r (uniform).  LDS: rowbuf (2 NP doubles), keys (2),
+// dmax (1).  Every thread of the block must call it.
+template <int NT, int NP, int BR, int BC, bool WITHZ, class Out>
+__device__ int pchol_block(int n, double (&a)[BR][BC], double (&bz)[BR][BC], double tau, double* rowbuf,
+                           unsigned* keys, unsigned long long* dmax, Out out) {
+  constexpr int TC = NP / BC;
+  static_assert((NP / BR) * TC == NT && NP % BR == 0 && NP % BC == 0 && NP <= kBigN, "block grid");
+  const int tid = threadIdx.x, ti = tid / TC, tj = tid - (tid / TC) * TC;
+  const int i0 = BR * ti, j0 = BC * tj;
+  // chosen (or absent) row and column indices of this thread's block
+  unsigned rch = 0u, cch = 0u;
+#pragma unroll
+  for (int u = 0; u < BR; ++u) rch |= (i0 + u >= n) ? (1u << u) : 0u;
+#pragma unroll
+  for (int v = 0; v < BC; ++v) cch |= (j0 + v >= n) ? (1u << v) : 0u;
+  // largest key over this thread's diagonal entries (0: none left)
+  auto diag_key = [&](double rel) -> unsigned {
+    unsigned best = 0u;
+#pragma unroll
+    for (int u = 0; u < BR; ++u)
+#pragma unroll
+      for (int v = 0; v < BC; ++v)
+        if (i0 + u == j0 + v && !((rch >> u) & 1u)) {
+          const float fv = (float)(fmax(a[u][v], 0.0) * rel);
+          const unsigned q = (__float_as_uint(fv) & ~127u) | (unsigned)(127 - (i0 + u));
+          best = q > best ? q : best;
+        }
+    return best;
+  };
+  if (tid == 0) {
+    keys[0] = 0u;
+    keys[1] = 0u;
+    *dmax = 0ull;
+  }
+  __syncthreads();
+  {
+    unsigned long long dm = 0ull;
+#pragma unroll
+    for (int u = 0; u < BR; ++u)
+#pragma unroll
+      for (int v = 0; v < BC; ++v)
+        if (i0 + u == j0 + v && i0 + u < n) {
+          const unsigned long long q = (unsigned long long)__double_as_longlong(fmax(a[u][v], 0.0));
+          dm = q > dm ? q : dm;
+        }
+    if (dm != 0ull) atomicMax(dmax, dm);
+  }
+  __syncthreads();
+  const double d0 = __longlong_as_double((long long)*dmax);
   const double rel = d0 > 0.0 ? 1.0 / d0 : 0.0;
-  bool ch0 = !v0, ch1 = !v1;
-  int k0 = n, k1 = n;
+  {
+    const unsigned q = diag_key(rel);
+    if (q != 0u) atomicMax(&keys[0], q);
+  }
+  __syncthreads();
   int r = n;
   for (int k = 0; k < n; ++k) {
-    const unsigned q0 = ch0 ? 0u
-                            : ((__float_as_uint((float)(fmax(dg0, 0.0) * rel)) & ~127u) | (unsigned)(127 - j0));
-    const unsigned q1 = ch1 ? 0u
-                            : ((__float_as_uint((float)(fmax(dg1, 0.0) * rel)) & ~127u) | (unsigned)(127 - j1));
-    const unsigned key = wave_max_u32(q0 > q1 ? q0 : q1);
+    const unsigned key = keys[k & 1];
     const int p = pivot_of(key);
-    const int pl = p & 63;
-    const double b0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dg0), pl),
-                                       __builtin_amdgcn_readlane(__double2loint(dg0), pl));
-    const double b1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dg1), pl),
-                                       __builtin_amdgcn_readlane(__double2loint(dg1), pl));
-    const double best = key == 0u ? 0.0 : (p < 64 ? b0 : b1);
+    if (tid == 0) keys[(k + 1) & 1] = 0u;
+    // publish row p (its owners: block row p / BR)
+    if (ti == p / BR) {
+      const int up = p - i0;
+#pragma unroll
+      for (int u = 0; u < BR; ++u)
+        if (u == up) {
+#pragma unroll
+          for (int v = 0; v < BC; ++v) {
+            rowbuf[j0 + v] = a[u][v];
+            if (WITHZ) rowbuf[NP + j0 + v] = bz[u][v];
+          }
+        }
+    }
+    __syncthreads();
+    const double best = key == 0u ? 0.0 : rowbuf[p];
     if (!(best > tau * d0) || !(best > 0.0)) {
       r = k;
       break;
     }
     const double inv = rsq_nr2(best);
-    double s0 = A[p * ld + jc0], s1 = A[p * ld + jc1];
-    double a0 = 0.0, a1 = 0.0;
-    for (int c = 0; c * CH < k; ++c) {
-      int pm[CH];
+    double li[BR], lj[BC], zj[BC];
 #pragma unroll
-      for (int i = 0; i < CH; ++i) pm[i] = perm[c * CH + i];
-      double lp[CH], w0[CH], w1[CH];
+    for (int u = 0; u < BR; ++u) li[u] = ((rch >> u) & 1u) ? 0.0 : rowbuf[i0 + u] * inv;
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        lp[i] = c * CH + i < k ? A[pm[i] * ld + p] : 0.0;
-        w0[i] = A[pm[i] * ld + jc0];
-        w1[i] = A[pm[i] * ld + jc1];
-      }
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int m = c * CH + i;
-        if (WITHZ) {
-          // the stored entry is z_m at indices taken at steps <= m
-          if (m >= k0) a0 = fma(lp[i], w0[i], a0); else s0 = fma(-lp[i], w0[i], s0);
-          if (m >= k1) a1 = fma(lp[i], w1[i], a1); else s1 = fma(-lp[i], w1[i], s1);
-        } else {
-          s0 = fma(-lp[i], w0[i], s0);
-          s1 = fma(-lp[i], w1[i], s1);
-        }
-      }
+    for (int v = 0; v < BC; ++v) {
+      const bool chv = (cch >> v) & 1u;
+      lj[v] = chv ? 0.0 : rowbuf[j0 + v] * inv;
+      if (WITHZ) zj[v] = (j0 + v == p) ? inv : (chv ? -rowbuf[NP + j0 + v] * inv : 0.0);
     }
-    const double l0 = ch0 ? 0.0 : s0 * inv, l1 = ch1 ? 0.0 : s1 * inv;
-    double o0 = l0, o1 = l1;
-    if (WITHZ) {
-      o0 = j0 == p ? inv : (ch0 ? -a0 * inv : l0);
-      o1 = j1 == p ? inv : (ch1 ? -a1 * inv : l1);
+    if (ti == 0)
+#pragma unroll
+      for (int v = 0; v < BC; ++v) out(k, j0 + v, lj[v], WITHZ ? zj[v] : 0.0);
+#pragma unroll
+    for (int u = 0; u < BR; ++u)
+#pragma unroll
+      for (int v = 0; v < BC; ++v) {
+        a[u][v] = fma(-li[u], lj[v], a[u][v]);
+        if (WITHZ) bz[u][v] = fma(li[u], zj[v], bz[u][v]);
+      }
+    if (p >= i0 && p < i0 + BR) rch |= 1u << (p - i0);
+    if (p >= j0 && p < j0 + BC) cch |= 1u << (p - j0);
+    {
+      const unsigned q = diag_key(rel);
+      if (q != 0u) atomicMax(&keys[(k + 1) & 1], q);
     }
-    if (v0) A[p * ld + j0] = o0;
-    if (v1) A[p * ld + j1] = o1;
-    dg0 = fma(-l0, l0, dg0);
-    dg1 = fma(-l1, l1, dg1);
-    if (j0 == p) { ch0 = true; k0 = k; }
-    if (j1 == p) { ch1 = true; k1 = k; }
-    if (lane == 0) perm[k] = p;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
   }
-  if (v0) kch[j0] = k0;
-  if (v1) kch[j1] = k1;
   return r;
 }
 
-// S = P R^-1 (n x n, 64 < n <= 128) of the pivoted Cholesky factor of G;
-// see k_pchol_s.
-__global__ __launch_bounds__(256) void k_pchol_s_big(int n, const double* __restrict__ Gg, long long sG, double tau,
+// S = P R^-1 (n x n, 64 < n <= 128) of the pivoted Cholesky factor of G
+// (pchol_block, 512 threads holding 8 x 4 blocks); see k_pchol_s.
+__global__ __launch_bounds__(512) void k_pchol_s_big(int n, const double* __restrict__ Gg, long long sG, double tau,
                                                      double* __restrict__ Sg, long long sS,
                                                      int* __restrict__ rank_out) {
-  extern __shared__ double sm[];
-  double* A = sm;
-  __shared__ int perm[kBigN];
-  __shared__ int kch[kBigN];
-  __shared__ int rank_s;
+  constexpr int NT = 512, NP = kBigN, BR = 8, BC = 4, TC = NP / BC;
+  __shared__ double rowbuf[2 * NP];
+  __shared__ unsigned keys[2];
+  __shared__ unsigned long long dmax;
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int i0 = BR * (tid / TC), j0 = BC * (tid - (tid / TC) * TC);
   const double* G = Gg + b * sG;
-  for (int e = tid; e < n * n; e += 256) A[e] = G[e];
-  if (tid < kBigN) perm[tid] = 0;
-  __syncthreads();
-  if (tid < 64) {
-    const int rr = pchol_wave_big<true>(n, A, n, perm, kch, tau);
-    if (tid == 0) rank_s = rr;
-  }
-  __syncthreads();
-  const int r = rank_s;
   double* S = Sg + b * sS;
-  // S[o][k] = z_k[o], stored in row perm[k] at the indices taken by step k
-  for (int e = tid; e < n * n; e += 256) {
-    const int o = e / n, k = e - (e / n) * n;
-    S[e] = (k < r && kch[o] <= k) ? A[perm[k] * n + o] : 0.0;
+  double a[BR][BC], bz[BR][BC];
+#pragma unroll
+  for (int u = 0; u < BR; ++u)
+#pragma unroll
+    for (int v = 0; v < BC; ++v) {
+      const int i = i0 + u, j = j0 + v;
+      a[u][v] = (i < n && j < n) ? G[(long long)i * n + j] : 0.0;
+      bz[u][v] = 0.0;
+    }
+  // S[o][k] = z_k[o]
+  const int r = pchol_block<NT, NP, BR, BC, true>(n, a, bz, tau, rowbuf, keys, &dmax,
+                                                  [&](int k, int j, double, double z) {
+                                                    if (j < n) S[(long long)j * n + k] = z;
+                                                  });
+  for (int e = tid; e < n * n; e += NT) {
+    const int k = e - (e / n) * n;
+    if (k >= r) S[e] = 0.0;
   }
   if (tid == 0 && rank_out != nullptr) rank_out[b] = r;
 }
 
 // Truncation basis of a PSD Gram matrix G (n x n, 64 < n <= 128): the
 // steps of k_cut_psd (scaling, pivoted Cholesky, one-sided Jacobi on the
-// factor's rows, selection) with the factor formed in place and moved to
-// pivot order before the Jacobi.  NT = 16 lanes x NT / 16 column pairs
-// (2 NT / 16 >= n), rows padded to NP = 16 NE >= n.
+// factor's rows, selection), the factor formed by pchol_block (the whole
+// block, 4 x 4 or 3 x 4 register blocks) and written in pivot order.
+// NT = 16 lanes x NT / 16 column pairs (2 NT / 16 >= n), rows padded to
+// NP = 16 NE >= n.
 template <int NT, int NE>
 __global__ __launch_bounds__(NT) void k_cut_psd_big(int n, int c, const double* __restrict__ Gg, long long sG,
                                                      double tau, double eps, double tol2, double floor_rel,
@@ -1199,68 +1238,64 @@ __global__ __launch_bounds__(NT) void k_cut_psd_big(int n, int c, const double* 
                                                      int* __restrict__ kept_out, int* __restrict__ sweeps_out) {
   constexpr int LPG = 16;
   constexpr int NP = LPG * NE;
-  constexpr int PER = (kBigN * NP + NT - 1) / NT;  // row elements per thread in the reordering
+  constexpr int BR = NP / 32, BC = 4, TC = NP / BC;  // pchol_block grid: 32 x TC threads
   extern __shared__ double sm[];
   double* W = sm;  // n rows of stride NP
-  __shared__ int perm[kBigN];
-  __shared__ int kch[kBigN];
   __shared__ int order[kBigN];
   __shared__ double lam[kBigN];
   __shared__ int flags[kCutSweeps];
-  __shared__ int rank_s;
   __shared__ double trace_s;
   __shared__ int kept_s;
-  __shared__ int scale_s;
+  __shared__ unsigned long long dm_s;
+  __shared__ double rowbuf[NP];
+  __shared__ unsigned keys[2];
+  __shared__ unsigned long long dmax;
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int i0 = BR * (tid / TC), j0 = BC * (tid - (tid / TC) * TC);
   const double* G = Gg + b * sG;
-  for (int e = tid; e < n * NP; e += NT) {
-    const int i = e / NP, j = e - (e / NP) * NP;
-    W[e] = j < n ? G[i * n + j] : 0.0;
-  }
+  for (int e = tid; e < n * NP; e += NT) W[e] = 0.0;
   if (tid < kCutSweeps) flags[tid] = 0;
-  if (tid < kBigN) perm[tid] = 0;
+  if (tid == 0) dm_s = 0ull;
+  double a[BR][BC], bz[BR][BC];
+#pragma unroll
+  for (int u = 0; u < BR; ++u)
+#pragma unroll
+    for (int v = 0; v < BC; ++v) {
+      const int i = i0 + u, j = j0 + v;
+      a[u][v] = (i < n && j < n) ? G[(long long)i * n + j] : 0.0;
+      bz[u][v] = 0.0;
+    }
   __syncthreads();
   // scale by a power of two near the largest diagonal entry (see k_cut_psd)
-  if (tid < 64) {
-    double dm = 0.0;
-    for (int i = tid; i < n; i += 64) dm = fmax(dm, fmax(W[i * NP + i], 0.0));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-    if (tid == 0) scale_s = dm > 0.0 ? __builtin_amdgcn_frexp_exp(dm) : 0;
-  }
-  __syncthreads();
   {
-    const int sx = scale_s;
-    for (int e = tid; e < n * NP; e += NT) W[e] = __builtin_amdgcn_ldexp(W[e], -sx);
+    unsigned long long dm = 0ull;
+#pragma unroll
+    for (int u = 0; u < BR; ++u)
+#pragma unroll
+      for (int v = 0; v < BC; ++v)
+        if (i0 + u == j0 + v && i0 + u < n) {
+          const unsigned long long q = (unsigned long long)__double_as_longlong(fmax(a[u][v], 0.0));
+          dm = q > dm ? q : dm;
+        }
+    if (dm != 0ull) atomicMax(&dm_s, dm);
   }
   __syncthreads();
+  const double dmx = __longlong_as_double((long long)dm_s);
+  const int sx = dmx > 0.0 ? __builtin_amdgcn_frexp_exp(dmx) : 0;
+#pragma unroll
+  for (int u = 0; u < BR; ++u)
+#pragma unroll
+    for (int v = 0; v < BC; ++v) a[u][v] = __builtin_amdgcn_ldexp(a[u][v], -sx);
   if (tid < 64) {
     double t = 0.0;
-    for (int i = tid; i < n; i += 64) t += fmax(W[i * NP + i], 0.0);
+    for (int i = tid; i < n; i += 64) t += fmax(__builtin_amdgcn_ldexp(G[(long long)i * n + i], -sx), 0.0);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (tid == 0) trace_s = t;
-    const int rr = pchol_wave_big<false>(n, W, NP, perm, kch, tau);
-    if (tid == 0) rank_s = rr;
   }
-  __syncthreads();
-  const int r = rank_s;
-  // factor row k (stored in row perm[k]) -> row k; rows r.. become zero
-  {
-    double t[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      const int k = e / NP, i = e - (e / NP) * NP;
-      t[u] = (k < r) ? W[perm[k] * NP + i] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (e < n * NP) W[e] = t[u];
-    }
-  }
+  // factor row k -> row k of W (rows r.. stay zero)
+  const int r = pchol_block<NT, NP, BR, BC, false>(n, a, bz, tau, rowbuf, keys, &dmax,
+                                                   [&](int k, int j, double l, double) { W[k * NP + j] = l; });
   __syncthreads();
   // one-sided Jacobi on rows 0..r-1 of W, as in k_cut_psd
   const int sub = tid % LPG, grp = tid / LPG;
@@ -1525,12 +1560,7 @@ int pchol_s(int n, const double* G, long long sG, double tau, double* S, long lo
   if (batch <= 0) return LRFG_OK;
   ProfScope ps_("pchol", s);
   if (n > 64) {
-    static const hipError_t attr_big = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pchol_s_big),
-                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                           (int)(sizeof(double) * kMaxEig * kMaxEig));
-    (void)attr_big;
-    hipLaunchKernelGGL(k_pchol_s_big, dim3(batch), dim3(256), sizeof(double) * n * n, s, n, G, sG, tau, S, sS,
-                       rank);
+    hipLaunchKernelGGL(k_pchol_s_big, dim3(batch), dim3(512), 0, s, n, G, sG, tau, S, sS, rank);
     LRFG_LAUNCHED();
     return LRFG_OK;
   }
