@@ -34,6 +34,9 @@ struct Gemm {
   // over columns gathered from several blocks of an array.
   int bcw = 0, ccw = 0;
   long long bchi = 0, cchi = 0;
+  // one K range per matrix (no split-K): for batches that fill the device
+  // by themselves
+  bool nosplit = false;
 };
 
 // The batch map as the kernels receive it; t = tbase + the launch's batch index.

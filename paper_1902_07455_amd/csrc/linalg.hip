@@ -295,6 +295,123 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
       }
 }
 
+// The same product for outputs with a side of 65..96: a 96 x 96 block
+// tile, each of the four waves (2 x 2) computing a 48 x 48 sub-tile as
+// 3 x 3 MFMA 16 x 16 blocks, so such a side fits one tile (each operand is
+// read once per tile row or column instead of three times with 32-wide
+// tiles) and a K slab of 16 feeds 36 MFMAs per wave.  Double-buffered K
+// slabs as in k_gemm128; every MFMA runs (the staging writes zeros outside
+// the output, the epilogue drops those entries).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm96(int m, int n, int k, const double* __restrict__ A, long long lda,
+                                                long long sA, const double* __restrict__ B, long long ldb,
+                                                long long sB, double* __restrict__ C, long long ldc, long long sC,
+                                                double alpha, double beta, int ksplit, int kchunk,
+                                                double* __restrict__ part, BatchMap bm) {
+  constexpr int TM = 96, TN = 96, TK = 16;
+  constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
+  __shared__ double As[2][TK][TM + 1];
+  __shared__ double Bs[2][TK][TN + 1];
+  const int bz = blockIdx.z;
+  const int bt = bz / ksplit;
+  const int ks = bz - bt * ksplit;
+  const long long tg = bm.tbase + bt;
+  A += bm.a_off(tg, sA);
+  B += bm.b_off(tg, sB);
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = ks * kchunk;
+  const int ke = min(k, kb + kchunk);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  dbl4 acc[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double pa[RA], pb[RB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
+      const int gi = m0 + i, gk = k0 + kk;
+      pa[r] = (gi < m && gk < ke) ? (TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
+      const int gk = k0 + kk, gj = n0 + j;
+      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + bm.bcol(gj)]) : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int i, kk;
+      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
+      As[buf][kk][i] = pa[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = threadIdx.x + r * 256;
+      int kk, j;
+      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
+      Bs[buf][kk][j] = pb[r];
+    }
+  };
+  if (kb < ke) {
+    fetch(kb);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+    const bool more = k0 + TK < ke;
+    if (more) fetch(k0 + TK);
+#pragma unroll
+    for (int kq = 0; kq < TK; kq += 4) {
+      const int kk = kq + (lane >> 4);
+      double a[3], b[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a[i] = As[buf][kk][wm * 48 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) b[j] = Bs[buf][kk][wn * 48 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // the other buffer was last read before the previous barrier
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* const Cb = C + bm.c_off(tg, sC);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 48 + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn * 48 + j * 16 + (lane & 15);
+        if (row < m && col < n) {
+          const double v = acc[i][j][r];
+          if (part != nullptr) {
+            part[((long long)bz * m + row) * n + col] = v;
+          } else {
+            double* c = Cb + (long long)row * ldc + bm.ccol(col);
+            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+          }
+        }
+      }
+}
+
 // Reduced-precision variant for the mixed-precision solve: FP64 operands
 // in memory, rounded to FP32 (BF = false) or BF16 (BF = true) when staged,
 // products accumulated in FP32 on MFMA, the sum stored as FP64.  Tile
@@ -475,15 +592,20 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
 // Wave layout of k_gemm for one matrix's shape: outputs of at most 32 x 32
 // split K four ways inside the block, narrow outputs stack the waves along
 // the long side, the rest use the 2 x 2 layout of 64 x 64 tiles.
-// {4, 4} stands for k_gemm128 (128 x 128 tiles, 64 x 64 per wave).
+// {4, 4} stands for k_gemm128 (128 x 128 tiles, 64 x 64 per wave) and
+// {3, 3} for k_gemm96 (96 x 96 tiles, 48 x 48 per wave).
 struct GemmLayout {
   int wm, wn;
   int tm() const { return 32 * wm; }
   int tn() const { return 32 * wn; }
-  int tk() const { return wm * wn == 16 ? 16 : 16 * (4 / (wm * wn)); }
+  int tk() const { return (wm * wn == 16 || wm * wn == 9) ? 16 : 16 * (4 / (wm * wn)); }
 };
 GemmLayout gemm_layout(const Gemm& g) {
   if (g.m >= 128 && g.n >= 128) return {4, 4};
+  // a side of 65..96 and the other of 65..96 or above 128: 96 x 96 tiles
+  // ({3, 3}, k_gemm96), one tile across that side
+  const int lo = g.m < g.n ? g.m : g.n, hi = g.m < g.n ? g.n : g.m;
+  if (lo > 64 && lo <= 96 && (hi <= 96 || hi > 128)) return {3, 3};
   // a side of 65..96 fills three 32-wide tiles (76-100 %) rather than two
   // 64-wide ones (51-75 %)
   if (g.m > 64 && g.m <= 96 && g.n >= 128) return {1, 4};
@@ -498,6 +620,7 @@ GemmLayout gemm_layout(const Gemm& g) {
 // summation order whatever the batch it travels in (batched solves
 // reproduce single solves bit for bit).
 int choose_ksplit(const Gemm& g) {
+  if (g.nosplit) return 1;
   const bool lp = g.prec != 0;
   const GemmLayout L = lp ? GemmLayout{2, 2} : gemm_layout(g);
   const long long tiles = (long long)ceil_div(g.m, L.tm()) * ceil_div(g.n, L.tn());
@@ -1459,6 +1582,10 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
     else if (lay.wm == 1 && lay.wn == 4) LRFG_GEMM_F64(TA, TB, 1, 4);                                         \
     else if (lay.wm == 4 && lay.wn == 4)                                                                      \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm128<TA, TB>), grid, dim3(256),   \
+                        0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
+                        ks, kchunk, part, bm);                                                               \
+    else if (lay.wm == 3 && lay.wn == 3)                                                                      \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm96<TA, TB>), grid, dim3(256),    \
                         0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
                         ks, kchunk, part, bm);                                                               \
     else LRFG_GEMM_F64(TA, TB, 2, 2);                                                                         \

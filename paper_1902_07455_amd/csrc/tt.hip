@@ -26,6 +26,7 @@
 // A Hadamard product a (.) g can enter with its middle carriage unformed
 // (KrMid): the two contractions that read that carriage (the sketch T2 and
 // the projection X2') then run over g's and a's carriages in turn.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -557,7 +558,17 @@ void Rounder::carve(Arena& ar) {
     const long long z = (long long)kr_ra * kr_rg * N2 * L2, u = (long long)L1 * kr_ra * N2 * kr_rg;
     kz = T(z > u ? z : u);
   }
+  // split-K partials: at least 4 Mi doubles, and for d = 3 enough for the
+  // two long contractions (W2 and M2) of all nE trains in one launch, which
+  // then fill the device, up to 96 Mi doubles
   gscr_n = (size_t)4 * 1024 * 1024;
+  if (d == 3) {
+    Gemm w2, m2;
+    w2.m = R1; w2.n = L1; w2.k = N2 * L2; w2.batch = nE; w2.tb = true;
+    m2.m = L2; m2.n = R2; m2.k = L1 * N2; m2.batch = nE; m2.ta = true;
+    const size_t need = std::max(gemm_scratch_doubles(w2), gemm_scratch_doubles(m2));
+    gscr_n = std::min<size_t>(std::max(gscr_n, need), (size_t)96 * 1024 * 1024);
+  }
   gscr = ar.take<double>(gscr_n);
 }
 
@@ -691,9 +702,44 @@ int Rounder::kr_dot(const TTB& kr, const KrMid& mid, const TTB& y, double* dots,
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
   { GemmB g(R2, ry2, N3, ns); g.a(kr.c[2], N3, kr.s[2]).b(y.c[2], N3, y.s[2], true).c(W3, ry2, (long long)R2 * ry2);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+  const long long nv = (long long)R1 * N2 * ry2;
+  const int ra0 = mid.ra0, ra1 = mid.ra1, rg0 = mid.rg0, rg1 = mid.rg1;
+  // (H fits T2's space and the dot scratch when ra0 ra1 <= Rmax[0] Lmax[1]
+  // and ra1 <= rg0 ry2)
+  if (ra1 > kKrRegRank && (long long)ra0 * ra1 <= (long long)Rmax[0] * Lmax[1] &&
+      (long long)ra1 <= (long long)rg0 * ry2) {
+    // <a (.) g, y> = sum_n sum_{i,j} a[i][n][j] H[i][n][j] with
+    // H_n = V_n Z_n^T over (k, l) (K = rg0 ry2, one product per grid index):
+    // V[n][i][k][l] = sum_j' Lf[i rg0 + k][j'] y2[j'][n][l] and
+    // Z[n][j][k][l] = sum_m g[k][n][m] Rt[j rg1 + m][l]; the same sums as
+    // <X2 Rt, Lf y2> regrouped, with the long contraction on MFMA
+    const long long zn = (long long)ra1 * rg0 * ry2, sh = (long long)ra0 * N2 * ra1;
+    { GemmB g(rg0, ra1 * ry2, rg1, ns * N2);
+      g.a(mid.g, (long long)N2 * rg1, mid.sg).b(W3, ry2, (long long)R2 * ry2).c(kz, ry2, zn);
+      g.g.adiv = N2; g.g.amod = N2; g.g.sA2 = rg1;
+      g.g.bdiv = N2;
+      g.g.bcw = ry2; g.g.bchi = (long long)rg1 * ry2;
+      g.g.ccw = ry2; g.g.cchi = (long long)rg0 * ry2;
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(R1, N2 * ry2, ry1, ns);
+      g.a(W2, ry1, (long long)R1 * ry1).b(y.c[1], (long long)N2 * ry2, y.s[1]).c(X2p, ry2, nv);
+      g.g.ccw = ry2; g.g.cchi = (long long)R1 * ry2;
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    { GemmB g(ra0, ra1, rg0 * ry2, ns * N2);
+      g.a(X2p, (long long)rg0 * ry2, nv).b(kz, (long long)rg0 * ry2, zn, true).c(T2, (long long)N2 * ra1, sh);
+      g.g.adiv = N2; g.g.amod = N2; g.g.sA2 = (long long)R1 * ry2;
+      g.g.cdiv = N2; g.g.cmod = N2; g.g.sC2 = ra1;
+      g.g.nosplit = true;
+      LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
+    // system e reads coefficient e % amod
+    const int amod = mid.amod > 0 ? mid.amod : ns;
+    if (amod == 1) return dot_rows(sh, mid.a, 0, 1, T2, sh, dots, ns, dscr, dscr_n, s);
+    for (int s0 = 0; s0 < ns; s0 += amod)
+      LRFG_TRY(dot_rows(sh, mid.a, mid.sa, 1, T2 + s0 * sh, sh, dots + s0, std::min(amod, ns - s0), dscr, dscr_n, s));
+    return LRFG_OK;
+  }
   // T2' = X2 Rt over the unformed middle carriage, V = Lf y2; the product is <T2', V>
   LRFG_TRY(kr_t2(mid, N2, ry2, W3, T2, kz, ns, LRFG_PREC_FP64, gscr, gscr_n, s));
-  const long long nv = (long long)R1 * N2 * ry2;
   { GemmB g(R1, N2 * ry2, ry1, ns); g.a(W2, ry1, (long long)R1 * ry1).b(y.c[1], (long long)N2 * ry2, y.s[1])
         .c(X2p, (long long)N2 * ry2, nv);
     LRFG_TRY(gemm(g.g, gscr, gscr_n, s)); }
