@@ -14,8 +14,9 @@ to 1e-10 (it equals the CPU oracle's stored value to 1e-10, tests/golden).
 Each timed path uses the loosest solver tolerance whose A_H error,
 max|A - A*| / max|A*|, is at most 1e-6, from one ladder of five rungs per
 decade (1, 0.7, 0.5, 0.3, 0.2 x 10^-e): the full grid's PCG tolerance, and
-the TT PCG's at rank cap 90 (sketches of 128 columns, 24 exponential-sum
-terms of the preconditioner: of 6 to 32 terms the fastest at the target).
+the TT PCG's at the smaller of rank caps 85 and 90 that reaches the target
+(sketches of 128 columns, 24 exponential-sum terms of the preconditioner:
+of 6 to 32 terms the fastest at the target).
 
 `value` is the TT path, the paper's method; `full_fft` the full-grid solve
 with the roofline of its longest kernel.  `roofline` is that of the TT
@@ -46,6 +47,9 @@ if ROOT not in sys.path:
 TARGET_ERR = 1e-6
 N_MAIN = 135          # smooth-coefficient workload (secondary)
 N_BALL = 243          # headline workload
+# TT settings of the ball, tried in this order: (rank cap, oversampling),
+# each a sketch of 128 columns; 24 exponential-sum terms
+BALL_CAPS = [(85, 43), (90, 38)]
 BALL_CAP, BALL_OVER, BALL_M = 90, 38, 24
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
@@ -429,20 +433,30 @@ def ball_leg(args, dev):
                          "avg_us": lk["avg_us"], "bytes_per_launch": lk["bytes_per_launch"]},
             "kernels": kern}
 
-    # tensor train: loosest solver tolerance meeting the target at the cap
-    tsweep, ttol = [], None
-    for tol in ([args.tt_tol] if args.tt_tol else BALL_TOLS):
-        s = wl.tt_solver(tol)
-        r = wl.run_tt(s)
-        s.close()
-        e = rel_err(r.A_H, A_ref)
-        tsweep.append([tol, e, r.iters.tolist()])
-        log(f"TT tol {tol}: err {e:.2e} iters {r.iters.tolist()} ({r.solve_ms:.0f} ms)")
-        if e <= TARGET_ERR:
-            ttol = tol
+    # tensor train: the smallest rank cap of BALL_CAPS that reaches the
+    # target, at the loosest solver tolerance that does; a cap is left for
+    # the next once a rung ends rank-limited (its truncation floor) above
+    # the target
+    import paper_1902_07455_amd as P
+    tsweep, ttol, tcap, tover = [], None, None, None
+    for cap, over in ([(args.tt_cap, 128 - args.tt_cap)] if args.tt_cap else BALL_CAPS):
+        for tol in ([args.tt_tol] if args.tt_tol else BALL_TOLS):
+            s = wl.tt_solver(tol, cap, over)
+            r = wl.run_tt(s)
+            s.close()
+            e = rel_err(r.A_H, A_ref)
+            tsweep.append([cap, tol, e, r.iters.tolist(), r.status.tolist()])
+            log(f"TT cap {cap} tol {tol}: err {e:.2e} iters {r.iters.tolist()} status {r.status.tolist()} "
+                f"({r.solve_ms:.0f} ms)")
+            if e <= TARGET_ERR:
+                ttol, tcap, tover = tol, cap, over
+                break
+            if any(int(x) == P._lib.RANK_LIMITED for x in r.status):
+                break
+        if ttol is not None:
             break
     assert ttol is not None, "no TT setting reaches the target"
-    ts = wl.tt_solver(ttol)
+    ts = wl.tt_solver(ttol, tcap, tover)
     ttot, tlat, tr = timed(lambda: wl.run_tt(ts), args.steps, args.warmup)
     terr = rel_err(tr.A_H, A_ref)
     nl, kms, flops = profiled(lambda: wl.run_tt(ts), "gemm", 1)
@@ -453,7 +467,7 @@ def ball_leg(args, dev):
     latency_bound = {"note": "one workgroup per small Gram matrix (sketch 128): bound by the chain of dependent "
                              "pivot (k_pchol_s_big) and rotation (k_cut_psd_big) steps, not by HBM or MFMA; "
                              "timed on a solve at solver tol 1e-4"}
-    ls = wl.tt_solver(1e-4)
+    ls = wl.tt_solver(1e-4, tcap, tover)
     for tag, kname in (("cut", "k_cut_psd_big"), ("pchol", "k_pchol_s_big")):
         import paper_1902_07455_amd as P
         P.prof_enable(tag)
@@ -471,7 +485,7 @@ def ball_leg(args, dev):
                 "launches": nl, "avg_us": round((kms / 1e3) / max(nl, 1) * 1e6, 2),
                 "flops_per_launch": round(flops / max(nl, 1)), "share_of_solve": round(kms / per_solve_ms, 3)}
     value = args.steps / ttot
-    tt = {"path": "tensor-train PCG (randomised TT rounding)", "rank_cap": BALL_CAP, "oversample": BALL_OVER,
+    tt = {"path": "tensor-train PCG (randomised TT rounding)", "rank_cap": tcap, "oversample": tover,
           "precond_terms": BALL_M, "solver_tol": ttol, "iters": tr.iters.tolist(), "ranks": tr.ranks.tolist(),
           "status": tr.status.tolist(), "A_H_rel_err": terr, "sweep": tsweep}
     return wl, A_ref, value, ttot, tlat, tt, full, roofline, latency_bound, ref_vs_oracle
@@ -578,6 +592,8 @@ def main(argv=None):
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-tol", type=float, default=None, help="TT solver tolerance (skips the sweep)")
+    ap.add_argument("--tt-cap", type=int, default=None,
+                    help="TT rank cap of the ball (oversampling 128 - cap; skips the cap choice)")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-nmax", type=int, default=405, help="largest grid of the serving requests")
