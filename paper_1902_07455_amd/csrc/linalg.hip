@@ -176,21 +176,23 @@ __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, const double*
       }
 }
 
-// The same product for large outputs: a 128 x 128 block tile, each of the
-// four waves (2 x 2) computing a 64 x 64 sub-tile as 4 x 4 MFMA 16 x 16
-// blocks, so a K slab of 16 staged in LDS feeds 64 MFMAs per wave (twice the
-// flops per staged byte of the 64 x 64 tile).  Same operand layouts, batch
-// map, split-K partials and block skipping as k_gemm.
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const double* __restrict__ A, long long lda,
-                                                 long long sA, const double* __restrict__ B, long long ldb,
-                                                 long long sB, double* __restrict__ C, long long ldc, long long sC,
-                                                 double alpha, double beta, int ksplit, int kchunk,
-                                                 double* __restrict__ part, BatchMap bm) {
-  constexpr int TM = 128, TN = 128, TK = 16;
+// The block tile of the large-tile kernels: WM x WN waves, each computing
+// BI x BJ MFMA 16 x 16 blocks, so the tile is (16 BI WM) x (16 BJ WN) and a
+// K slab of 16 staged in LDS feeds 4 BI BJ MFMAs per wave.  Two slab
+// buffers: the next slab is written while the current one feeds the MFMAs,
+// one barrier per slab.  Every MFMA runs (the staging writes zeros outside
+// the output, and the epilogue drops those entries).  Same operand layouts,
+// batch and column maps and split-K partials as k_gemm.
+template <bool TA, bool TB, int WM, int WN, int BI, int BJ>
+__device__ __forceinline__ void gemm_tile(int m, int n, int k, const double* __restrict__ A, long long lda,
+                                          long long sA, const double* __restrict__ B, long long ldb, long long sB,
+                                          double* __restrict__ C, long long ldc, long long sC, double alpha,
+                                          double beta, int ksplit, int kchunk, double* __restrict__ part,
+                                          const BatchMap& bm) {
+  static_assert(WM * WN == 4, "four waves");
+  constexpr int TM = 16 * BI * WM, TN = 16 * BJ * WN, TK = 16;
   constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
-  // two slab buffers: the next slab is written while the current one feeds
-  // the MFMAs, one barrier per slab
+  static_assert(RA * 256 == TM * TK && RB * 256 == TK * TN, "staging split");
   __shared__ double As[2][TK][TM + 1];
   __shared__ double Bs[2][TK][TN + 1];
   const int bz = blockIdx.z;
@@ -204,12 +206,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
   const int ke = min(k, kb + kchunk);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
-  dbl4 acc[4][4];
+  const int wm = wave / WN, wn = wave - (wave / WN) * WN;
+  dbl4 acc[BI][BJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < BJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   double pa[RA], pb[RB];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -254,20 +256,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
   for (int k0 = kb; k0 < ke; k0 += TK) {
     const bool more = k0 + TK < ke;
     if (more) fetch(k0 + TK);
-    // all sixteen MFMAs on every wave: the blocks outside the output
-    // multiply the zeros the staging wrote there, and the epilogue drops them
 #pragma unroll
     for (int kq = 0; kq < TK; kq += 4) {
       const int kk = kq + (lane >> 4);
-      double a[4], b[4];
+      double a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[buf][kk][wm * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < BI; ++i) a[i] = As[buf][kk][wm * 16 * BI + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < BJ; ++j) b[j] = Bs[buf][kk][wn * 16 * BJ + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     // the other buffer was last read before the previous barrier
     if (more) stage(buf ^ 1);
@@ -276,13 +276,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
   }
   double* const Cb = C + bm.c_off(tg, sC);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int row = m0 + wm * 16 * BI + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn * 16 * BJ + j * 16 + (lane & 15);
         if (row < m && col < n) {
           const double v = acc[i][j][r];
           if (part != nullptr) {
@@ -295,122 +295,27 @@ __global__ __launch_bounds__(256, 2) void k_gemm128(int m, int n, int k, const d
       }
 }
 
-// The same product for outputs with a side of 65..96: a 96 x 96 block
-// tile, each of the four waves (2 x 2) computing a 48 x 48 sub-tile as
-// 3 x 3 MFMA 16 x 16 blocks, so such a side fits one tile (each operand is
-// read once per tile row or column instead of three times with 32-wide
-// tiles) and a K slab of 16 feeds 36 MFMAs per wave.  Double-buffered K
-// slabs as in k_gemm128; every MFMA runs (the staging writes zeros outside
-// the output, the epilogue drops those entries).
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm96(int m, int n, int k, const double* __restrict__ A, long long lda,
-                                                long long sA, const double* __restrict__ B, long long ldb,
-                                                long long sB, double* __restrict__ C, long long ldc, long long sC,
-                                                double alpha, double beta, int ksplit, int kchunk,
-                                                double* __restrict__ part, BatchMap bm) {
-  constexpr int TM = 96, TN = 96, TK = 16;
-  constexpr int RA = (TM * TK) / 256, RB = (TK * TN) / 256;
-  __shared__ double As[2][TK][TM + 1];
-  __shared__ double Bs[2][TK][TN + 1];
-  const int bz = blockIdx.z;
-  const int bt = bz / ksplit;
-  const int ks = bz - bt * ksplit;
-  const long long tg = bm.tbase + bt;
-  A += bm.a_off(tg, sA);
-  B += bm.b_off(tg, sB);
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kb = ks * kchunk;
-  const int ke = min(k, kb + kchunk);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
-  dbl4 acc[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  double pa[RA], pb[RB];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int i, kk;
-      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
-      const int gi = m0 + i, gk = k0 + kk;
-      pa[r] = (gi < m && gk < ke) ? (TA ? A[(long long)gk * lda + gi] : A[(long long)gi * lda + gk]) : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int kk, j;
-      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
-      const int gk = k0 + kk, gj = n0 + j;
-      pb[r] = (gj < n && gk < ke) ? (TB ? B[(long long)gj * ldb + gk] : B[(long long)gk * ldb + bm.bcol(gj)]) : 0.0;
-    }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int i, kk;
-      if (!TA) { i = e / TK; kk = e % TK; } else { kk = e / TM; i = e % TM; }
-      As[buf][kk][i] = pa[r];
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int e = threadIdx.x + r * 256;
-      int kk, j;
-      if (!TB) { kk = e / TN; j = e % TN; } else { j = e / TK; kk = e % TK; }
-      Bs[buf][kk][j] = pb[r];
-    }
-  };
-  if (kb < ke) {
-    fetch(kb);
-    stage(0);
+#define LRFG_GEMM_TILE_KERNEL(NAME, BOUNDS, WM, WN, BI, BJ)                                                    \
+  template <bool TA, bool TB>                                                                                 \
+  __global__ BOUNDS void NAME(int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,  \
+                              const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C, \
+                              long long ldc, long long sC, double alpha, double beta, int ksplit, int kchunk,   \
+                              double* __restrict__ part, BatchMap bm) {                                        \
+    gemm_tile<TA, TB, WM, WN, BI, BJ>(m, n, k, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, ksplit, kchunk,  \
+                                      part, bm);                                                               \
   }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += TK) {
-    const bool more = k0 + TK < ke;
-    if (more) fetch(k0 + TK);
-#pragma unroll
-    for (int kq = 0; kq < TK; kq += 4) {
-      const int kk = kq + (lane >> 4);
-      double a[3], b[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) a[i] = As[buf][kk][wm * 48 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) b[j] = Bs[buf][kk][wn * 48 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    // the other buffer was last read before the previous barrier
-    if (more) stage(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-  double* const Cb = C + bm.c_off(tg, sC);
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 48 + i * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + wn * 48 + j * 16 + (lane & 15);
-        if (row < m && col < n) {
-          const double v = acc[i][j][r];
-          if (part != nullptr) {
-            part[((long long)bz * m + row) * n + col] = v;
-          } else {
-            double* c = Cb + (long long)row * ldc + bm.ccol(col);
-            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
-          }
-        }
-      }
-}
+// 128 x 128 tiles, 2 x 2 waves of 64 x 64: twice the flops per staged byte
+// of the 64 x 64 tile of k_gemm
+LRFG_GEMM_TILE_KERNEL(k_gemm128, __launch_bounds__(256, 2), 2, 2, 4, 4)
+// 96 x 96 tiles, 2 x 2 waves of 48 x 48, for outputs with a side of 65..96:
+// such a side fits one tile, so each operand is read once per tile row or
+// column instead of three times with 32-wide tiles
+LRFG_GEMM_TILE_KERNEL(k_gemm96, __launch_bounds__(256), 2, 2, 3, 3)
+// 80 x 128 tiles, 1 x 4 waves of 80 x 32, for m of 65..80 against n of at
+// least 128 (the products over the coefficient's ranks): 9 % padding on m
+// where the 96 x 96 tile has 42 %
+LRFG_GEMM_TILE_KERNEL(k_gemm80, __launch_bounds__(256), 1, 4, 5, 2)
+#undef LRFG_GEMM_TILE_KERNEL
 
 // Reduced-precision variant for the mixed-precision solve: FP64 operands
 // in memory, rounded to FP32 (BF = false) or BF16 (BF = true) when staged,
@@ -592,16 +497,20 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int m, int n, int ksplit,
 // Wave layout of k_gemm for one matrix's shape: outputs of at most 32 x 32
 // split K four ways inside the block, narrow outputs stack the waves along
 // the long side, the rest use the 2 x 2 layout of 64 x 64 tiles.
-// {4, 4} stands for k_gemm128 (128 x 128 tiles, 64 x 64 per wave) and
-// {3, 3} for k_gemm96 (96 x 96 tiles, 48 x 48 per wave).
+// {4, 4} stands for k_gemm128 (128 x 128 tiles, 64 x 64 per wave), {3, 3}
+// for k_gemm96 (96 x 96 tiles, 48 x 48 per wave) and {5, 2} for k_gemm80
+// (80 x 128 tiles, 80 x 32 per wave).
 struct GemmLayout {
   int wm, wn;
-  int tm() const { return 32 * wm; }
-  int tn() const { return 32 * wn; }
-  int tk() const { return (wm * wn == 16 || wm * wn == 9) ? 16 : 16 * (4 / (wm * wn)); }
+  bool large() const { return wm * wn == 16 || wm * wn == 9 || wm == 5; }
+  int tm() const { return wm == 5 ? 80 : 32 * wm; }
+  int tn() const { return wm == 5 ? 128 : 32 * wn; }
+  int tk() const { return large() ? 16 : 16 * (4 / (wm * wn)); }
 };
 GemmLayout gemm_layout(const Gemm& g) {
   if (g.m >= 128 && g.n >= 128) return {4, 4};
+  // m of 65..80 against n of at least 128: 80 x 128 tiles ({5, 2}, k_gemm80)
+  if (g.m > 64 && g.m <= 80 && g.n >= 128) return {5, 2};
   // a side of 65..96 and the other of 65..96 or above 128: 96 x 96 tiles
   // ({3, 3}, k_gemm96), one tile across that side
   const int lo = g.m < g.n ? g.m : g.n, hi = g.m < g.n ? g.n : g.m;
@@ -1586,6 +1495,10 @@ int gemm(const Gemm& g, double* scratch, size_t scratch_doubles, hipStream_t s) 
                         ks, kchunk, part, bm);                                                               \
     else if (lay.wm == 3 && lay.wn == 3)                                                                      \
       LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm96<TA, TB>), grid, dim3(256),    \
+                        0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
+                        ks, kchunk, part, bm);                                                               \
+    else if (lay.wm == 5)                                                                                     \
+      LRFG_LAUNCH_TIMED("gemm", 2.0 * c.m * c.n * (double)c.k * c.batch, (k_gemm80<TA, TB>), grid, dim3(256),    \
                         0, s, c.m, c.n, c.k, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.C, c.ldc, c.sC, c.alpha, c.beta, \
                         ks, kchunk, part, bm);                                                               \
     else LRFG_GEMM_F64(TA, TB, 2, 2);                                                                         \

@@ -8,13 +8,16 @@ pytestmark = pytest.mark.gpu
 
 # every wave layout of the FP64 kernel: m, n <= 32 (K split in the block),
 # n <= 32 with m <= 64 / m > 64, m <= 32 with n <= 64 / n > 64, 64 x 64, the
-# 96 x 96 tile kernel (a side of 65..96, the other of 65..96 or above 128)
-# and the 128 x 128 tile kernel
+# 96 x 96 tile kernel (a side of 65..96, the other of 65..96 or above 128),
+# the 80 x 128 tile kernel (m of 65..80, n of at least 128) and the 128 x 128
+# tile kernel
 SHAPES = [(1, 1, 1), (5, 7, 3), (64, 64, 16), (65, 63, 17), (100, 30, 4050), (2430, 30, 180),
           (30, 30, 24300), (180, 20, 2700), (1, 1, 24300), (7, 200, 1), (45, 26, 135), (26, 45, 135),
           (64, 32, 2025), (32, 64, 300), (33, 33, 97), (16, 16, 135),
           # 96 x 96 tiles, ragged edges and split K
-          (96, 96, 16), (73, 73, 811), (90, 65, 90), (73, 1500, 73), (1500, 96, 33), (65, 200, 500),
+          (96, 96, 16), (73, 73, 811), (90, 65, 90), (85, 1500, 73), (1500, 96, 33), (90, 200, 500),
+          # 80 x 128 tiles (m of 65..80, n >= 128), ragged edges and split K
+          (73, 1500, 73), (80, 128, 16), (65, 300, 500), (73, 128, 73),
           # 128 x 128 tiles (m, n >= 128), ragged edges and split K
           (128, 128, 16), (129, 300, 97), (300, 129, 1000), (257, 140, 5000), (1000, 520, 33)]
 
