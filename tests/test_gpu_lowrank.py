@@ -49,6 +49,39 @@ def test_untruncated_equals_full_square(dev, d, N):
     assert _rel(r.A_H, o.A_H) <= 1e-10
 
 
+def _wide_tt_coeff(N, r, seed):
+    """TT cores of a = 3 + 0.9 p / max|p| with p a random train of ranks r:
+    ranks r + 1 (the constant is a rank-one train beside p), positive
+    (a >= 2.1 everywhere); also the full field."""
+    rng = np.random.default_rng(seed)
+    R = [rng.standard_normal((1, N, r)), rng.standard_normal((r, N, r)), rng.standard_normal((r, N, 1))]
+    p = np.einsum("aib,bjc,ckd->ijk", *R)
+    sc = 0.9 / np.max(np.abs(p))
+    one = np.ones(N)
+    G1 = np.concatenate([3.0 * one[None, :, None], sc * R[0]], axis=2)
+    G2 = np.zeros((r + 1, N, r + 1))
+    G2[0, :, 0] = one
+    G2[1:, :, 1:] = R[1]
+    G3 = np.concatenate([one[None, :, None], R[2]], axis=0)
+    a = np.einsum("aib,bjc,ckd->ijk", G1, G2, G3)
+    return [G1, G2, G3], a
+
+
+def test_untruncated_equals_full_wide_coefficient(dev):
+    """A coefficient train of ranks 21 (above the 16 the register paths of
+    the material contractions take: the mapped products per grid index and
+    the regrouped energy form) with the rank cap at the grid size, so no
+    truncation: the TT solve is the full solve."""
+    import torch
+    N = 21
+    cores, a = _wide_tt_coeff(N, 20, 5)
+    assert np.min(a) >= 2.0
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=N, solver_tol=1e-12, max_iter=300, coeff_rank=21)
+    r = s.solve(tt=[torch.from_numpy(c).to(dev) for c in cores])
+    o = fg.solve(a, tol=1e-12)
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
 def test_cp_format_2d_config(dev):
     """2D square (N = 45) in the CP format = the d = 2 train."""
     cp = W.square_cp(45, 2)
