@@ -953,7 +953,11 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         const double res = std::sqrt(std::max(zzh[k], 0.0)) / res0[e];
         if (record) hist[(size_t)e * maxit + it] = res;
         its[e] = it + 1;
-        const bool better = emode[e] ? en[k] < best_en[e] : res < best[e];
+        // an energy step counts when it exceeds solver_tol^2 of the energy:
+        // below that it is under the accuracy the tolerance asks for
+        const bool better =
+            emode[e] ? (std::isfinite(best_en[e]) ? en[k] < best_en[e] - tol * tol * std::fabs(best_en[e]) : true)
+                     : res < best[e];
         if (res < best[e]) best[e] = res;
         if (!better && by_energy && !emode[e]) {
           emode[e] = 1;
