@@ -69,3 +69,41 @@ def solve(a: np.ndarray, Es: Optional[Sequence[Sequence[float]]] = None) -> np.n
         for j in range(nE):
             A[i, j] = float(np.sum(W * fields[i] * fields[j]))
     return A
+
+
+def solve_tensor(A: np.ndarray, Es: Optional[Sequence[Sequence[float]]] = None) -> np.ndarray:
+    """The same dense minimisation for a matrix-valued coefficient A (shape
+    (d, d, N..)): mean_x A(x)(E + D v).(E + D v), with the quadrature weight
+    now a d x d block per grid point (Sec. 4.4's a I + B is one case)."""
+    A = np.asarray(A, dtype=np.float64)
+    d = A.shape[0]
+    shape = A.shape[2:]
+    n = int(np.prod(shape))
+    if Es is None:
+        Es = [np.eye(d)[i] for i in range(d)]
+    Ds = []
+    for alpha in range(d):
+        mats = [np.eye(s) for s in shape]
+        mats[alpha] = derivative_matrix_1d(shape[alpha])
+        M = mats[0]
+        for m in mats[1:]:
+            M = np.kron(M, m)
+        Ds.append(M)
+    D = np.vstack(Ds)                       # (d n) x n
+    W = np.zeros((d * n, d * n))            # block (alpha, beta) = diag(A_ab)/n
+    for al in range(d):
+        for be in range(d):
+            W[al * n:(al + 1) * n, be * n:(be + 1) * n] = np.diag(A[al, be].reshape(-1)) / n
+    K = D.T @ W @ D
+    Kp = np.linalg.pinv(K, rcond=1e-13, hermitian=True)
+    fields = []
+    for E in Es:
+        eE = np.concatenate([np.full(n, float(E[al])) for al in range(d)])
+        v = Kp @ (-D.T @ (W @ eE))
+        fields.append(eE + D @ v)
+    nE = len(Es)
+    out = np.zeros((nE, nE))
+    for i in range(nE):
+        for j in range(nE):
+            out[i, j] = float(fields[j] @ (W @ fields[i]))
+    return out

@@ -23,7 +23,7 @@ __all__ = [
     "grid_points", "CPCoeff", "square_coeff", "cube_coeff", "ball_coeff",
     "laminate_coeff", "constant_coeff", "smooth_params", "smooth_cp",
     "smooth_coeff", "random_positive_coeff", "random_cp", "random_tt",
-    "ServingRequest", "serving_requests",
+    "ServingRequest", "serving_requests", "anisotropy",
 ]
 
 
@@ -132,6 +132,18 @@ def laminate_coeff(N: int, d: int, profile: np.ndarray, axis: int = 0) -> np.nda
 
 def constant_coeff(N: int, d: int, value: float) -> np.ndarray:
     return np.full((N,) * d, float(value))
+
+
+def anisotropy(d: int) -> np.ndarray:
+    """The constant matrix B that Sec. 4.4 adds to an isotropic material
+    (A~ = a I + B); the paper gives its eigenvalues as (1, 10) in 2D and
+    (1, 5, 10) in 3D."""
+    if d == 2:
+        return np.array([[5.5, -4.5], [-4.5, 5.5]])
+    if d == 3:
+        q = 1.25 * math.sqrt(2.0)
+        return np.array([[4.25, -3.25, -q], [-3.25, 4.25, q], [-q, q, 7.5]])
+    raise ValueError("d must be 2 or 3")
 
 
 # --------------------------------------------------------------------------
