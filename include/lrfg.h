@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LRFG_ABI_VERSION 1
+#define LRFG_ABI_VERSION 2
 
 typedef enum {
   LRFG_OK = 0,
@@ -116,6 +116,15 @@ typedef struct {
                            (CP terms or TT ranks) a solve will receive;
                            sizes the workspace (0 = 16)                      */
   uint32_t flags;       /* reserved, must be 0                               */
+  double aniso[9];      /* constant symmetric positive semi-definite matrix B
+                           added to the isotropic coefficient, A~(x) =
+                           a(x) I + B (the anisotropic materials of Sec.
+                           4.4), row-major d x d in the first d*d entries,
+                           the rest 0.  All zero: the isotropic problem.
+                           Non-symmetric (beyond 1e-12 max|B|), indefinite
+                           or non-finite B, or nonzero entries past d*d:
+                           LRFG_EINVAL.  Full-grid and TT/CP formats;
+                           Tucker with B != 0: LRFG_EUNSUPPORTED           */
 } lrfg_problem;
 
 /* Coefficient a(x) > 0 (scalar isotropic A = a I).  For FULL, `full` holds

@@ -131,7 +131,8 @@ def _result_buffers(r, nE, d, max_iter):
 
 
 def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-10, max_iter=1000,
-                  solver="pcg", precision="fp64", precond_terms=0, oversample=0, seed=0, coeff_rank=0):
+                  solver="pcg", precision="fp64", precond_terms=0, oversample=0, seed=0, coeff_rank=0,
+                  aniso=None):
     p = _lib.Problem()
     p.d = int(d)
     Ns = list(N) + [1] * (3 - len(N))
@@ -149,6 +150,12 @@ def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-
     p.seed = int(seed)
     p.coeff_rank = int(coeff_rank)
     p.flags = 0
+    if aniso is not None:
+        B = np.asarray(aniso, dtype=np.float64)
+        if B.shape != (int(d), int(d)):
+            raise ValueError("aniso must be a d x d matrix")
+        for i, v in enumerate(B.reshape(-1)):
+            p.aniso[i] = float(v)
     return p
 
 
@@ -159,10 +166,10 @@ class Solver:
                  trunc_tol: float = 0.0, solver_tol: float = 1e-10, max_iter: int = 1000,
                  solver: str = "pcg", precision: str = "fp64", precond_terms: int = 0,
                  oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
-                 coeff_rank: int = 0, device: str = "cuda:0"):
+                 coeff_rank: int = 0, device: str = "cuda:0", aniso=None):
         L = lib()
         p = _make_problem(d, N, format, rank_cap, trunc_tol, solver_tol, max_iter, solver, precision,
-                          precond_terms, oversample, seed, coeff_rank)
+                          precond_terms, oversample, seed, coeff_rank, aniso)
         self.problem = p
         self.d = int(d)
         self.max_iter = int(max_iter)

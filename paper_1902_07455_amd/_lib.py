@@ -38,6 +38,7 @@ class Problem(C.Structure):
         ("seed", C.c_uint64),
         ("coeff_rank", C.c_int),
         ("flags", C.c_uint32),
+        ("aniso", C.c_double * 9),
     ]
 
 

@@ -1,5 +1,6 @@
 // C ABI of liblrfg: validation, plans, dispatch to the solve paths and the
 // operation-level entry points.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,6 +107,51 @@ int validate(const lrfg_problem* p) {
   if (p->flags != 0) {
     set_error("flags must be 0");
     return LRFG_EINVAL;
+  }
+  {
+    // B (Sec. 4.4): finite, symmetric and positive semi-definite (every
+    // principal minor >= 0, to a rounding margin), zero past d x d
+    const int d = p->d;
+    double m = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      if (!std::isfinite(p->aniso[i])) {
+        set_error("aniso[%d] is not finite", i);
+        return LRFG_EINVAL;
+      }
+      if (i >= d * d && p->aniso[i] != 0.0) {
+        set_error("aniso[%d] must be 0 for d = %d (B is d x d, row-major)", i, d);
+        return LRFG_EINVAL;
+      }
+      m = std::max(m, std::fabs(p->aniso[i]));
+    }
+    if (m > 0.0) {
+      auto b = [&](int i, int j) { return p->aniso[i * d + j]; };
+      const double eps = 1e-12;
+      bool ok = true;
+      for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j) ok = ok && std::fabs(b(i, j) - b(j, i)) <= eps * m;
+      if (!ok) {
+        set_error("aniso: B must be symmetric");
+        return LRFG_EINVAL;
+      }
+      for (int i = 0; i < d; ++i) ok = ok && b(i, i) >= -eps * m;
+      for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j) ok = ok && b(i, i) * b(j, j) - b(i, j) * b(j, i) >= -eps * m * m;
+      if (d == 3) {
+        const double det = b(0, 0) * (b(1, 1) * b(2, 2) - b(1, 2) * b(2, 1)) -
+                           b(0, 1) * (b(1, 0) * b(2, 2) - b(1, 2) * b(2, 0)) +
+                           b(0, 2) * (b(1, 0) * b(2, 1) - b(1, 1) * b(2, 0));
+        ok = ok && det >= -eps * m * m * m;
+      }
+      if (!ok) {
+        set_error("aniso: B must be positive semi-definite");
+        return LRFG_EINVAL;
+      }
+      if (p->format == LRFG_FORMAT_TUCKER) {
+        set_error("the anisotropic term is built for the full-grid and TT/CP formats");
+        return LRFG_EUNSUPPORTED;
+      }
+    }
   }
   if (p->format == LRFG_FORMAT_FULL && p->precision != LRFG_PREC_FP64) {
     set_error("the full-grid path runs in FP64 only");
@@ -365,6 +411,7 @@ static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int n
     fa.ws_bytes = full_need;
     fa.stream = stream;
     fa.pinned_flags = plan->pinned;
+    for (int i = 0; i < p.d * p.d; ++i) fa.B[i] = p.aniso[i];
     FullSolveOut fo;
     fo.A_H = out->A_H;
     fo.iters = out->iters;

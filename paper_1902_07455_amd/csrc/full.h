@@ -21,6 +21,7 @@ struct FullSolveArgs {
   size_t ws_bytes;
   void* stream;
   int* pinned_flags;      // pinned host ints, 4 * nE
+  double B[9] = {};       // constant anisotropic part, d x d row-major (all 0: isotropic)
 };
 
 struct FullSolveOut {

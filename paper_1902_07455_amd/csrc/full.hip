@@ -63,6 +63,21 @@ __device__ inline double pinv_of(const double k[3]) {
   return kk > 0.0 ? 1.0 / (4.0 * kPi * kPi * kk) : 0.0;
 }
 
+// Constant anisotropic part B of the coefficient A~ = a I + B (Sec. 4.4),
+// embedded in the internal 3-D axes.  Its share of the operator,
+// grad*^ B grad^ = 4 pi^2 k.Bk, is diagonal in Fourier space, so it is added
+// to the divergence pass's output from the input p it reads anyway; its
+// share of A_H, mean_x B grad u_i . grad u_j, is the Fourier sum of
+// 4 pi^2 k.Bk Re(u^_i conj u^_j).
+struct Aniso3 {
+  double b00, b11, b22, b01, b02, b12;  // scaled by 4 pi^2
+  int on;
+};
+__device__ inline double aniso_symbol(const Aniso3& B, double k0, double k1, double k2) {
+  return B.b00 * k0 * k0 + B.b11 * k1 * k1 + B.b22 * k2 * k2 +
+         2.0 * (B.b01 * k0 * k1 + B.b02 * k0 * k2 + B.b12 * k1 * k2);
+}
+
 // ---------------------------------------------------------------- P1
 // dst[e][a] = F^-1_axis1 ( 2 pi i k_alpha src[e] ),  alpha = alpha0 + a.
 // grid.x = tiles * nalpha (alpha fastest, so the tiles of one src share L2),
@@ -125,7 +140,8 @@ template <bool GEN>
 __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
                                                           const double2* __restrict__ p, G3 g, int alpha0, int nalpha,
                                                           double inv_vol, int T, FftDev f,
-                                                          const int* __restrict__ done, double* __restrict__ part_pq) {
+                                                          const int* __restrict__ done, double* __restrict__ part_pq,
+                                                          Aniso3 an) {
   extern __shared__ double2 sm[];
   __shared__ double red[kBlock / 64];
   const int e = blockIdx.y;
@@ -187,8 +203,14 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
     if (idx < total && tt < tcount) {
       const long long i = l0 + tt;
       const long long ad = (long long)n * inner + i;
-      qe[ad] = acc[j];
       const double2 pv = pe[ad];
+      if (an.on) {
+        const double c = aniso_symbol(an, (double)freq_of(n, g.N1), (double)freq_of((int)(i / g.H), g.N2),
+                                      (double)(i % g.H));
+        acc[j].x += c * pv.x;
+        acc[j].y += c * pv.y;
+      }
+      qe[ad] = acc[j];
       const double w = (i % g.H) == 0 ? 1.0 : 2.0;
       pq += w * (pv.x * acc[j].x + pv.y * acc[j].y);
     }
@@ -391,7 +413,8 @@ template <int A, int B, int C>
 __global__ __launch_bounds__(kFftBlock) void k3_div_axis1(const double2* __restrict__ t, double2* __restrict__ q,
                                                            const double2* __restrict__ p, G3 g, int alpha0,
                                                            int nalpha, double inv_vol, FftDev f,
-                                                           const int* __restrict__ done, double* __restrict__ part_pq) {
+                                                           const int* __restrict__ done, double* __restrict__ part_pq,
+                                                           Aniso3 an) {
   constexpr int N = A * B * C;
   constexpr int T = split_lines(N);
   using F = Fft3<A, B, C, -1, T, false, kFftBlock>;
@@ -479,9 +502,16 @@ __global__ __launch_bounds__(kFftBlock) void k3_div_axis1(const double2* __restr
         const double w = (l % (unsigned)g.H) == 0 ? 1.0 : 2.0;
 #pragma unroll
         for (int r = 0; r < F::R; ++r) {
-          const unsigned off = ((unsigned)F::out_n(k1, k2, r) * inner + l) * 16u;
-          st32(qe, off, acc[pi][r]);
+          const int n1 = F::out_n(k1, k2, r);
+          const unsigned off = ((unsigned)n1 * inner + l) * 16u;
           const double2 pv = ld32(pe, off);
+          if (an.on) {
+            const double c = aniso_symbol(an, (double)freq_of(n1, N), (double)freq_of((int)(l / (unsigned)g.H), g.N2),
+                                          (double)(l % (unsigned)g.H));
+            acc[pi][r].x += c * pv.x;
+            acc[pi][r].y += c * pv.y;
+          }
+          st32(qe, off, acc[pi][r]);
           pq += w * (pv.x * acc[pi][r].x + pv.y * acc[pi][r].y);
         }
       }
@@ -637,12 +667,12 @@ int launch3_grad(const double2* src, double2* dst, const G3& g, int alpha0, int 
 }
 
 int launch3_div(const double2* t, double2* q, const double2* p, const G3& g, int alpha0, int nalpha, double inv_vol,
-                const FftDev& f, const int* done, double* part, int nsys, hipStream_t s) {
+                const FftDev& f, const int* done, double* part, int nsys, hipStream_t s, const Aniso3& an) {
   const dim3 grid(pass_tiles1(g), nsys);
 #define LRFG_D3(NN)                                                                                          \
   case NN:                                                                                                   \
     hipLaunchKernelGGL((k3_div_axis1<split_of(NN).A, split_of(NN).B, split_of(NN).C>), grid, dim3(kFftBlock), 0, \
-                       s, t, q, p, g, alpha0, nalpha, inv_vol, f, done, part);                               \
+                       s, t, q, p, g, alpha0, nalpha, inv_vol, f, done, part, an);                           \
     break;
   switch (g.N1) {
     LRFG_SPLIT_CASES(LRFG_D3)
@@ -889,6 +919,33 @@ __global__ void k_ah_reduce(const double* __restrict__ a, const double* __restri
   }
 }
 
+// Per-block partial sums of sum_k w 4 pi^2 k.Bk Re(x^_i conj x^_j), i <= j,
+// over the half spectrum (w = 1 on h = 0, else 2): the B share of A_H
+// (the Fourier coefficients carry the grid mean's normalisation).
+__global__ void k_aniso_energy(const double2* __restrict__ x, G3 g, int nE, Aniso3 an,
+                               double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const int nv = nE * (nE + 1) / 2;
+  double acc[6];
+  for (int v = 0; v < nv; ++v) acc[v] = 0.0;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    const double c = (h == 0 ? 1.0 : 2.0) *
+                     aniso_symbol(an, (double)freq_of(n1, g.N1), (double)freq_of(n2, g.N2), (double)h);
+    double2 xv[3];
+    for (int e = 0; e < nE; ++e) xv[e] = x[(long long)e * g.S + s];
+    int v = 0;
+    for (int i = 0; i < nE; ++i)
+      for (int j = i; j < nE; ++j) acc[v++] += c * (xv[i].x * xv[j].x + xv[i].y * xv[j].y);
+  }
+  for (int v = 0; v < nv; ++v) {
+    const double t = block_sum(acc[v], red);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * nv + v] = t;
+  }
+}
+
 }  // namespace
 
 // ====================================================================== host
@@ -991,6 +1048,23 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   if ((long long)N3d[0] * N3d[1] * N3d[2] > kMaxGridEntries) {
     set_error("full-grid solve: %d x %d x %d grid above 2^32 - 1 entries", N3d[0], N3d[1], N3d[2]);
     return LRFG_EUNSUPPORTED;
+  }
+  // B embedded in the internal axes (d = 2: axes 1 and 2), times 4 pi^2
+  Aniso3 an{};
+  {
+    double B3[3][3] = {};
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        B3[alpha0 + i][alpha0 + j] = A.B[i * d + j];
+        if (A.B[i * d + j] != 0.0) an.on = 1;
+      }
+    const double f = 4.0 * kPi * kPi;
+    an.b00 = f * B3[0][0];
+    an.b11 = f * B3[1][1];
+    an.b22 = f * B3[2][2];
+    an.b01 = f * 0.5 * (B3[0][1] + B3[1][0]);
+    an.b02 = f * 0.5 * (B3[0][2] + B3[2][0]);
+    an.b12 = f * 0.5 * (B3[1][2] + B3[2][1]);
   }
   Arena ar;
   ar.base = static_cast<char*>(A.ws);
@@ -1124,11 +1198,11 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
       ProfScope ps_("div_axis1", s);
       if (two1) {
         LRFG_TRY(launch3_div((const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, f1,
-                             (const int*)L.done, L.part_pq, nE, s));
+                             (const int*)L.done, L.part_pq, nE, s, an));
       } else {
         hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(L.tiles1, nE), dim3(kBlock), shm1, s,
                            (const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1,
-                           (const int*)L.done, L.part_pq);
+                           (const int*)L.done, L.part_pq, an);
         LRFG_LAUNCHED();
       }
     }
@@ -1197,6 +1271,28 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
         m2[((size_t)j * nE + i) * d + al] = val;
       }
   }
+  // B share of A_H: E_i.B E_j + mean_x B grad u_i . grad u_j
+  std::vector<double> mb((size_t)nE * nE, 0.0);
+  if (an.on) {
+    const int nb = nE * (nE + 1) / 2;
+    hipLaunchKernelGGL(k_aniso_energy, dim3(L.nstat), dim3(kBlock), 0, s, (const double2*)L.x, g, nE, an,
+                       L.part_misc);
+    LRFG_LAUNCHED();
+    std::vector<double> pb((size_t)L.nstat * nb);
+    LRFG_HIP(hipMemcpyAsync(pb.data(), L.part_misc, sizeof(double) * L.nstat * nb, hipMemcpyDeviceToHost, s));
+    LRFG_HIP(hipStreamSynchronize(s));
+    std::vector<double> acc(nb, 0.0);
+    for (int b = 0; b < L.nstat; ++b)
+      for (int v = 0; v < nb; ++v) acc[v] += pb[(size_t)b * nb + v];
+    int v = 0;
+    for (int i = 0; i < nE; ++i)
+      for (int j = i; j < nE; ++j) {
+        double eb = 0.0;
+        for (int al = 0; al < d; ++al)
+          for (int be = 0; be < d; ++be) eb += A.E[i * d + al] * A.B[al * d + be] * A.E[j * d + be];
+        mb[(size_t)i * nE + j] = mb[(size_t)j * nE + i] = eb + acc[v++];
+      }
+  }
   LRFG_HIP(hipEventRecord(ev2, s));
   std::vector<CgState> st(nE);
   LRFG_HIP(hipMemcpyAsync(st.data(), L.st, sizeof(CgState) * nE, hipMemcpyDeviceToHost, s));
@@ -1214,7 +1310,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   int rc = LRFG_OK;
   for (int i = 0; i < nE; ++i) {
     for (int j = 0; j < nE; ++j) {
-      double v = 0.0;
+      double v = mb[(size_t)i * nE + j];
       for (int al = 0; al < d; ++al) {
         const double ei = A.E[i * d + al], ej = A.E[j * d + al];
         v += mean_a * ei * ej + ei * m1[j * d + al] + ej * m1[i * d + al] + m2[((size_t)i * nE + j) * d + al];
@@ -1303,10 +1399,12 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   }
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, -1, f2, 1.0, s));
   if (two1) {
-    LRFG_TRY(launch3_div((const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, f1, (const int*)done, part, 1, s));
+    LRFG_TRY(launch3_div((const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, f1, (const int*)done, part, 1, s,
+                         Aniso3{}));
   } else {
     hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(tiles1, 1), dim3(kBlock), shm1, s,
-                       (const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, T1, f1, (const int*)done, part);
+                       (const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, T1, f1, (const int*)done, part,
+                       Aniso3{});
     LRFG_LAUNCHED();
   }
   return LRFG_OK;

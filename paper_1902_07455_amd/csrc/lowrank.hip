@@ -47,6 +47,8 @@ struct LowRankPlan {
   int M = 2;                 // exponential-sum terms
   std::vector<double> t, w;  // exponents and weights
   int over = 10;
+  bool aniso = false;        // constant anisotropic part B present (Sec. 4.4)
+  double B[3][3] = {};
 };
 
 namespace {
@@ -176,6 +178,8 @@ struct Ctx {
   double* pcore;            // M * d carriage buffers for the preconditioner terms
   long long pcore_stride;
   double* acore[3];         // carriage buffers of D_alpha a (right-hand side)
+  double* bcore;            // anisotropic part: D_j v_j and D_j^2 v_j, 2 d carriage buffers
+  long long bstride;
   TTB tmp;                  // extra corrector-size train
   TTB b0, xa, xbest;        // mixed precision: right-hand side, corrector, best corrector
   double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
@@ -244,6 +248,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
     if (pl->M * rc[j] > m) m = pl->M * rc[j];
     if (2 * rc[j] > m) m = 2 * rc[j];
     if (d * ra[j] > m) m = d * ra[j];
+    if (pl->aniso && (d + 3) * rc[j] > m) m = (d + 3) * rc[j];  // material terms + K_B v
     cap[j] = m;
   }
   for (int j = 0; j < 4; ++j) C.comb_cap[j] = cap[j];
@@ -258,6 +263,8 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   long long acmax = 0;
   for (int j = 0; j < d; ++j) acmax = std::max(acmax, (long long)ra[j] * pl->N[j] * ra[j + 1]);
   for (int al = 0; al < d; ++al) C.acore[al] = ar.take<double>((size_t)acmax * na);
+  C.bstride = maxcore * nE;
+  C.bcore = pl->aniso ? ar.take<double>((size_t)C.bstride * 2 * d) : nullptr;
   // rounding workspace
   Rounder& R = C.rd;
   R.d = d;
@@ -276,7 +283,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   }
   R.carve(ar);
   // per-system scalars (dots also holds the 2 d nE energy-form products)
-  C.dots = ar.take<double>((size_t)6 * nE + 64);
+  C.dots = ar.take<double>((size_t)7 * nE + 64);
   C.rho = ar.take<double>(nE);
   C.pqd = ar.take<double>(nE);
   C.alpha = ar.take<double>(nE);
@@ -296,9 +303,87 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
     dn = std::max(dn, dot_rows_scratch((long long)rkr[1] * pl->N[1] * rc[2], nE));  // kr_dot
   else
     dn = std::max(dn, tt_dot_scratch(C.kr, C.z, 3 * nE));
+  if (pl->aniso) {
+    // <x, K_B x> with K_B x of ranks 3 c
+    TTB w = C.z;
+    for (int j = 1; j < d; ++j) w.r[j] = 3 * rc[j];
+    dn = std::max(dn, tt_dot_scratch(C.z, w, nE));
+  }
   C.dscr_n = dn;
   C.dscr = ar.take<double>(dn);
   return LRFG_OK;
+}
+
+// ------------------------------------------------------------------ anisotropic part
+// K_B v = sum_{alpha beta} B_{alpha beta} D_alpha^T D_beta v for the constant
+// matrix B of Sec. 4.4 (D_alpha^T = -D_alpha).  Its symbol 4 pi^2 k.Bk is a
+// quadratic form in separate variables, so K_B is a TT operator of ranks 3
+// whose carriages hold I, D and D^2 of one mode:
+//   first   [ -B00 D^2 | D | I ]
+//   middle  [ I 0 0 ; -2 B01 D | -2 B02 I | 0 ; -B11 D^2 | -2 B12 D | I ]
+//   last    [ I ; D ; -B22 D^2 ]           (d = 3)
+//   last    [ I ; -2 B01 D ; -B11 D^2 ]    (d = 2)
+// and K_B v is a train of ranks 3 r whose carriage blocks are those
+// operators applied to v's carriages.  Appends these blocks, placed at the
+// bond offsets o[0..d] (o[0] = o[d] = 0), to blk/nb; D v_j and D^2 v_j go to
+// C.bcore.
+constexpr int kMaxBlk = 12;
+int aniso_blocks(Ctx& C, const TTB& v, int n, const int o[4], TTBlock blk[3][kMaxBlk], int nb[3]) {
+  const int d = C.d;
+  const double(*B)[3] = C.pl->B;
+  TTB dv[3], d2v[3];
+  for (int j = 0; j < d; ++j) {
+    dv[j] = v;
+    dv[j].c[j] = C.bcore + (long long)(2 * j) * C.bstride;
+    LRFG_TRY(tt_mode_apply(v, dv[j], j, 0, 0.0, 1.0, C.f[j], n, C.s));
+    d2v[j] = dv[j];
+    d2v[j].c[j] = C.bcore + (long long)(2 * j + 1) * C.bstride;
+    LRFG_TRY(tt_mode_apply(dv[j], d2v[j], j, 0, 0.0, 1.0, C.f[j], n, C.s));
+  }
+  auto add = [&](int j, const TTB& src, int a, int b, double mult) {
+    TTBlock t;
+    t.x = src.c[j];
+    t.sx = src.s[j];
+    t.r0 = v.r[j];
+    t.r1 = v.r[j + 1];
+    t.o0 = o[j] + a * v.r[j];
+    t.o1 = o[j + 1] + b * v.r[j + 1];
+    t.coef = nullptr;
+    t.mult = mult;
+    blk[j][nb[j]++] = t;
+  };
+  add(0, d2v[0], 0, 0, -B[0][0]);
+  add(0, dv[0], 0, 1, 1.0);
+  add(0, v, 0, 2, 1.0);
+  if (d == 3) {
+    add(1, v, 0, 0, 1.0);
+    add(1, dv[1], 1, 0, -2.0 * B[0][1]);
+    add(1, v, 1, 1, -2.0 * B[0][2]);
+    add(1, d2v[1], 2, 0, -B[1][1]);
+    add(1, dv[1], 2, 1, -2.0 * B[1][2]);
+    add(1, v, 2, 2, 1.0);
+    add(2, v, 0, 0, 1.0);
+    add(2, dv[2], 1, 0, 1.0);
+    add(2, d2v[2], 2, 0, -B[2][2]);
+  } else {
+    add(1, v, 0, 0, 1.0);
+    add(1, dv[1], 1, 0, -2.0 * B[0][1]);
+    add(1, d2v[1], 2, 0, -B[1][1]);
+  }
+  return LRFG_OK;
+}
+
+// W = K_B v for n trains, into C.comb (ranks 3 r)
+int aniso_train(Ctx& C, const TTB& v, int n, TTB& W) {
+  TTBlock blk[3][kMaxBlk];
+  int nb[3] = {0, 0, 0};
+  const int o[4] = {0, 0, 0, 0};
+  LRFG_TRY(aniso_blocks(C, v, n, o, blk, nb));
+  W = C.comb;
+  for (int j = 1; j < C.d; ++j) W.r[j] = 3 * v.r[j];
+  for (int j = 0; j < C.d; ++j) W.s[j] = W.size(j);
+  const TTBlock* bp[3] = {blk[0], blk[1], blk[2]};
+  return tt_blocks(bp, nb, W, n, C.s);
 }
 
 // ------------------------------------------------------------------ operators
@@ -351,9 +436,37 @@ int apply_K(Ctx& C, const TTB& v, TTB& out) {
     terms[al] = TTTerm{&hd[al], nullptr, 1.0};
   }
   TTB comb = C.comb;
-  for (int j = 1; j < d; ++j) comb.r[j] = d * v.r[j];
+  if (!C.pl->aniso) {
+    for (int j = 1; j < d; ++j) comb.r[j] = d * v.r[j];
+    for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
+    LRFG_TRY(tt_sum(terms, d, comb, nE, C.s));
+    return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+  }
+  // with the anisotropic part: the d material terms (block diagonal) and
+  // K_B v (ranks 3 r, exact) in one sum before the truncation
+  TTBlock blk[3][kMaxBlk];
+  int nb[3] = {0, 0, 0};
+  const TTB& h = C.h;
+  for (int j = 0; j < d; ++j)
+    for (int al = 0; al < d; ++al) {
+      TTBlock t;
+      t.x = hd[al].c[j];
+      t.sx = hd[al].s[j];
+      t.r0 = h.r[j];
+      t.r1 = h.r[j + 1];
+      t.o0 = al * (j == 0 ? 0 : h.r[j]);
+      t.o1 = al * (j == d - 1 ? 0 : h.r[j + 1]);
+      t.coef = nullptr;
+      t.mult = 1.0;
+      blk[j][nb[j]++] = t;
+    }
+  int o[4] = {0, 0, 0, 0};
+  for (int j = 1; j < d; ++j) o[j] = d * h.r[j];
+  LRFG_TRY(aniso_blocks(C, v, nE, o, blk, nb));
+  for (int j = 1; j < d; ++j) comb.r[j] = d * h.r[j] + 3 * v.r[j];
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
-  LRFG_TRY(tt_sum(terms, d, comb, nE, C.s));
+  const TTBlock* bp[3] = {blk[0], blk[1], blk[2]};
+  LRFG_TRY(tt_blocks(bp, nb, comb, nE, C.s));
   return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
 }
 
@@ -438,6 +551,11 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
     pl->N[j] = p.N[j];
     pl->mode[j] = mode[j];
   }
+  for (int i = 0; i < p.d; ++i)
+    for (int j = 0; j < p.d; ++j) {
+      pl->B[i][j] = p.aniso[i * p.d + j];
+      if (pl->B[i][j] != 0.0) pl->aniso = true;
+    }
   pl->ra = p.coeff_rank > 0 ? p.coeff_rank : 16;
   pl->over = p.oversample > 0 ? p.oversample : 10;
   if (pl->ra > kMaxCoeffRank) {
@@ -738,12 +856,27 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
         LRFG_TRY(tt_dot(C.kr, g, C.dots + (2 * al + 1) * n, C.dscr, n, s));
       }
     }
-    std::vector<double> v((size_t)2 * d * n);
-    LRFG_TRY(read_dev(C, C.dots, v.data(), 2 * d * n));
+    // anisotropic part: E.B E + <x_k, K_B x_k>/|N| into dots[2 d n + k]
+    const int nv = (pl->aniso ? 2 * d + 1 : 2 * d) * n;
+    if (pl->aniso) {
+      TTB W;
+      LRFG_TRY(aniso_train(C, X, n, W));
+      LRFG_TRY(tt_dot(X, W, C.dots + 2 * d * n, C.dscr, n, s));
+    }
+    std::vector<double> v((size_t)nv);
+    LRFG_TRY(read_dev(C, C.dots, v.data(), nv));
     for (int al = 0; al < d; ++al)
       for (int k = 0; k < n; ++k) {
         const int e = slot != nullptr ? slot[k] : k;
         en[k] += (2.0 * Ev(e, al) * v[(size_t)2 * al * n + k] + v[(size_t)(2 * al + 1) * n + k]) / Ntot;
+      }
+    if (pl->aniso)
+      for (int k = 0; k < n; ++k) {
+        const int e = slot != nullptr ? slot[k] : k;
+        double eb = 0.0;
+        for (int al = 0; al < d; ++al)
+          for (int be = 0; be < d; ++be) eb += Ev(e, al) * pl->B[al][be] * Ev(e, be);
+        en[k] += eb + v[(size_t)2 * d * n + k] / Ntot;
       }
     return LRFG_OK;
   };
@@ -1175,6 +1308,31 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     }
     for (size_t k = 0; k < w2.size(); ++k) m2[k * d + al] = w2[k] / Ntot;
   }
+  // anisotropic part: mb[i][j] = E_i.B E_j + <x_j, K_B x_i>/|N|, per microstructure
+  std::vector<double> mb((size_t)nE * nEp, 0.0);
+  if (pl->aniso) {
+    TTB W;
+    LRFG_TRY(aniso_train(C, C.xb, nE, W));
+    std::vector<double> wj(nEp);
+    for (int b = 0; b < nB; ++b) {
+      TTB xb = C.xb, w1 = W;
+      for (int q = 0; q < d; ++q) xb.c[q] = C.xb.c[q] + (long long)b * nEp * C.xb.s[q];
+      for (int j = 0; j < nEp; ++j) {
+        for (int q = 0; q < d; ++q) {
+          w1.c[q] = W.c[q] + (long long)(b * nEp + j) * W.s[q];
+          w1.s[q] = 0;
+        }
+        LRFG_TRY(tt_dot(xb, w1, C.dots, C.dscr, nEp, s));
+        LRFG_TRY(read_dev(C, C.dots, wj.data(), nEp));
+        for (int i = 0; i < nEp; ++i) {
+          double eb = 0.0;
+          for (int al = 0; al < d; ++al)
+            for (int be = 0; be < d; ++be) eb += E[i * d + al] * pl->B[al][be] * E[j * d + be];
+          mb[(size_t)(b * nEp + i) * nEp + j] = eb + wj[i] / Ntot;
+        }
+      }
+    }
+  }
   // final ranks: those the truncation kept for each system's returned iterate
   const std::vector<int>& kept = kbest;
   LRFG_HIP(hipEventRecord(ev2, s));
@@ -1190,7 +1348,7 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
       const int ei = b * nEp + i;
       for (int j = 0; j < nEp; ++j) {
         const int ej = b * nEp + j;
-        double v = 0.0;
+        double v = mb[(size_t)ei * nEp + j];
         for (int al = 0; al < d; ++al) {
           const double xi = E[i * d + al], xj = E[j * d + al];
           v += ma * xi * xj + xi * m1[(size_t)ej * d + al] + xj * m1[(size_t)ei * d + al] +

@@ -14,6 +14,7 @@
 // there, instead of waiting for whole solves to end; up to `slots`
 // sessions have work on the device at once.  The coefficient data is read
 // where the caller keeps it (device pointers stay on the device).
+#include <cstring>
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -104,7 +105,8 @@ bool same_problem(const lrfg_problem& x, const lrfg_problem& y) {
          x.rank_cap == y.rank_cap && x.trunc_tol == y.trunc_tol && x.solver_tol == y.solver_tol &&
          x.max_iter == y.max_iter && x.solver == y.solver && x.precision == y.precision &&
          x.precond_terms == y.precond_terms && x.oversample == y.oversample && x.seed == y.seed &&
-         x.coeff_rank == y.coeff_rank && x.flags == y.flags;
+         x.coeff_rank == y.coeff_rank && x.flags == y.flags &&
+         std::memcmp(x.aniso, y.aniso, sizeof(x.aniso)) == 0;
 }
 
 bool same_batch_key(const Request& x, const Request& y) {

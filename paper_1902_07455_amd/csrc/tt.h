@@ -102,6 +102,20 @@ int tt_hadamard(const TTB& a, const TTB& x, TTB& out, int nE, hipStream_t s, int
 // out = sum of terms as one TT with block carriages (ranks add); out's
 // ranks must equal the sums of the terms' ranks.
 int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s);
+// One block of an assembled carriage: rows [o0, o0 + r0) and columns
+// [o1, o1 + r1) take coef_e * mult * x (x: [r0][N][r1] per system at
+// x + e * sx; coef may be NULL).
+struct TTBlock {
+  const double* x;
+  long long sx;
+  int r0, r1, o0, o1;
+  const double* coef;
+  double mult;
+};
+// out's carriage j (j < d) assembled from blocks[j][0..nb[j]) (at most 12,
+// not overlapping), zeros elsewhere: block-structured trains such as a
+// train multiplied by a low-rank TT operator.
+int tt_blocks(const TTBlock* const blocks[3], const int nb[3], TTB& out, int nE, hipStream_t s);
 // dots[e] = <x_e, y_e>; scratch of tt_dot_scratch(x, y, nE) doubles.  With
 // pairs = P > 0 (nE a multiple of P): dots[e P + j] = <x_e, y_{(e/P) P + j}>,
 // every pair within each group of P systems, scratch of

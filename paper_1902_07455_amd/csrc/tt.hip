@@ -56,6 +56,15 @@ __global__ void k_fill(double* __restrict__ p, long long n, double v) {
     p[i] = v;
 }
 
+// batch identity matrices n x n (row-major, stride n * n)
+__global__ void k_eye(double* __restrict__ p, int n, int batch) {
+  const long long tot = (long long)n * n * batch;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+    const long long k = i % ((long long)n * n);
+    p[i] = (k / n == k % n) ? 1.0 : 0.0;
+  }
+}
+
 __device__ inline uint64_t smix(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -234,7 +243,7 @@ __global__ __launch_bounds__(256) void k_tt_copy_sel(CopySel A) {
 // written once: term t's carriage sits at row offset o0[t], column offset
 // o1[t] (times c_t = mult_t coef_t[e] on the first carriage), zeros
 // elsewhere.  Indices are per system (blockIdx.y), in 32 bits.
-constexpr int kSumTerms = 4;
+constexpr int kSumTerms = 12;
 struct SumCarriage {
   const double* x[kSumTerms];
   long long sx[kSumTerms];
@@ -417,6 +426,43 @@ int tt_sum(const TTTerm* terms, int nt, TTB& out, int nE, hipStream_t s) {
     const long long per = out.size(j);
     const int gx = (int)std::min<long long>(1024, (per + kB - 1) / kB);
     hipLaunchKernelGGL(k_sum_carriage, dim3(gx > 0 ? gx : 1, nE), dim3(kB), 0, s, T[j], out.r[j], out.N[j],
+                       out.r[j + 1], out.c[j], out.s[j]);
+    LRFG_LAUNCHED();
+  }
+  return LRFG_OK;
+}
+
+int tt_blocks(const TTBlock* const blocks[3], const int nb[3], TTB& out, int nE, hipStream_t s) {
+  const int d = out.d;
+  if (nE > 65535) {
+    set_error("tt_blocks: %d systems", nE);
+    return LRFG_EINVAL;
+  }
+  for (int j = 0; j < d; ++j) {
+    if (nb[j] < 1 || nb[j] > kSumTerms || out.size(j) > 0x7fffffffLL) {
+      set_error("tt_blocks: %d blocks in carriage %d (1..%d) or sizes beyond the kernel's", nb[j], j, kSumTerms);
+      return LRFG_EINVAL;
+    }
+    SumCarriage T;
+    T.nt = nb[j];
+    for (int t = 0; t < nb[j]; ++t) {
+      const TTBlock& b = blocks[j][t];
+      if (b.o0 < 0 || b.o1 < 0 || b.o0 + b.r0 > out.r[j] || b.o1 + b.r1 > out.r[j + 1]) {
+        set_error("tt_blocks: block %d of carriage %d outside the %d x %d carriage", t, j, out.r[j], out.r[j + 1]);
+        return LRFG_EINVAL;
+      }
+      T.x[t] = b.x;
+      T.sx[t] = b.sx;
+      T.r0[t] = b.r0;
+      T.r1[t] = b.r1;
+      T.o0[t] = b.o0;
+      T.o1[t] = b.o1;
+      T.coef[t] = b.coef;
+      T.mult[t] = b.mult;
+    }
+    const long long per = out.size(j);
+    const int gx = (int)std::min<long long>(1024, (per + kB - 1) / kB);
+    hipLaunchKernelGGL(k_sum_carriage, dim3(gx > 0 ? gx : 1, nE), dim3(kB), 0, s, T, out.r[j], out.N[j],
                        out.r[j + 1], out.c[j], out.s[j]);
     LRFG_LAUNCHED();
   }
@@ -779,11 +825,20 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
       set_error("tt_round: sizes (R %d %d, l %d %d) exceed the plan", R1, R2, l1, l2);
       return LRFG_EINVAL;
     }
-    // Gaussian sketch carriages
+    // Gaussian sketch carriages.  A sketch as wide as the whole space it
+    // samples needs no randomness: bond 2's (l2 = N3) is the identity, so
+    // Y2 is the unfolding itself, and bond 1's basis (l1 = N1) is the
+    // identity (below).  A square Gaussian factor would only worsen the
+    // conditioning, and the Gram-based orthonormalisation then loses the
+    // directions it shrinks below its threshold.
     { const long long n1 = (long long)l1 * N2 * l2, n2 = (long long)l2 * N3;
       hipLaunchKernelGGL(k_randn2, dim3(grid_for(n1 + n2)), dim3(kB), 0, s, om[1], n1, key, om[2], n2,
                          key ^ 0xA5A5A5A5A5A5A5A5ull); }
     LRFG_LAUNCHED();
+    if (l2 == N3) {
+      hipLaunchKernelGGL(k_eye, dim3(grid_for((long long)N3 * N3)), dim3(kB), 0, s, om[2], N3, 1);
+      LRFG_LAUNCHED();
+    }
     // W3 = X3 Om3^T (R2 x l2)
     { GemmB g(R2, l2, N3, nE); g.a(in.c[2], N3, in.s[2]).b(om[2], N3, 0, true).c(W3, l2, (long long)R2 * l2);
       LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
@@ -823,7 +878,12 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     // Y1 = X1 W2 (N1 x l1) ; Q1 = orth(Y1)
     { GemmB g(N1, l1, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l1, (long long)R1 * l1).c(Y1, l1, (long long)N1 * l1);
       LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
-    LRFG_TRY(orth(*this, Y1, Q1, N1, l1, nE, s));
+    if (l1 == N1) {
+      hipLaunchKernelGGL(k_eye, dim3(grid_for((long long)N1 * N1 * nE)), dim3(kB), 0, s, Q1, N1, nE);
+      LRFG_LAUNCHED();
+    } else {
+      LRFG_TRY(orth(*this, Y1, Q1, N1, l1, nE, s));
+    }
     // M1 = Q1^T X1 (l1 x R1) ; X2' = M1 X2 (l1 x N2 R2)
     { GemmB g(l1, R1, N1, nE); g.a(Q1, l1, (long long)N1 * l1, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l1 * R1);
       LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
@@ -941,13 +1001,23 @@ int Rounder::round(const TTB& in, TTB& out, double tol, hipStream_t s, int batch
     set_error("tt_round: sizes exceed the plan");
     return LRFG_EINVAL;
   }
-  hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l * N2)), dim3(kB), 0, s, om[2], (long long)l * N2, key);
+  // a sketch as wide as the space it samples is the identity (see d = 3)
+  if (l == N2) {
+    hipLaunchKernelGGL(k_eye, dim3(grid_for((long long)N2 * N2)), dim3(kB), 0, s, om[2], N2, 1);
+  } else {
+    hipLaunchKernelGGL(k_randn, dim3(grid_for((long long)l * N2)), dim3(kB), 0, s, om[2], (long long)l * N2, key);
+  }
   LRFG_LAUNCHED();
   { GemmB g(R1, l, N2, nE); g.a(in.c[1], N2, in.s[1]).b(om[2], N2, 0, true).c(W2, l, (long long)R1 * l);
     LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
   { GemmB g(N1, l, R1, nE); g.a(in.c[0], R1, in.s[0]).b(W2, l, (long long)R1 * l).c(Y1, l, (long long)N1 * l);
     LRFG_TRY(gemm(prec_of(g.g, prec), gscr, gscr_n, s)); }
-  LRFG_TRY(orth(*this, Y1, Q1, N1, l, nE, s));
+  if (l == N1) {
+    hipLaunchKernelGGL(k_eye, dim3(grid_for((long long)N1 * N1 * nE)), dim3(kB), 0, s, Q1, N1, nE);
+    LRFG_LAUNCHED();
+  } else {
+    LRFG_TRY(orth(*this, Y1, Q1, N1, l, nE, s));
+  }
   { GemmB g(l, R1, N1, nE); g.a(Q1, l, (long long)N1 * l, true).b(in.c[0], R1, in.s[0]).c(M1, R1, (long long)l * R1);
     LRFG_TRY(gemm(prec_of(g.g, pj), gscr, gscr_n, s)); }
   { GemmB g(l, N2, R1, nE); g.a(M1, R1, (long long)l * R1).b(in.c[1], N2, in.s[1]).c(X3p, N2, (long long)l * N2);

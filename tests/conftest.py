@@ -21,6 +21,6 @@ def dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
     import paper_1902_07455_amd as P
-    assert P.abi_version() == 1          # loads liblrfg.so or raises
+    assert P.abi_version() == 2          # loads liblrfg.so or raises
     assert P.device_check() == 0
     return torch.device("cuda:0")

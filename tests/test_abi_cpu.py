@@ -36,7 +36,7 @@ def test_header_symbols_exported():
 def test_version_and_status_strings():
     L = _lib()
     lib = L.lib()
-    assert lib.lrfg_abi_version() == 1
+    assert lib.lrfg_abi_version() == 2
     for s in (0, 1, 2, -1, -2, -3, -4, -5):
         assert len(lib.lrfg_status_string(s)) > 0
 
@@ -58,6 +58,8 @@ def _problem(L, **kw):
     p.coeff_rank = kw.get("coeff_rank", 0)
     p.seed = 0
     p.flags = kw.get("flags", 0)
+    for i, v in enumerate(kw.get("aniso", ())):
+        p.aniso[i] = v
     return p
 
 
@@ -79,6 +81,13 @@ def _problem(L, **kw):
     (dict(N=(131, 131, 131), format=2, rank_cap=129), -5),  # sketch sizes beyond 128
     (dict(N=(131, 131, 131), format=3, rank_cap=129), -5),
     (dict(format=3, coeff_rank=129), -5),               # coefficient ranks beyond 128
+    (dict(aniso=(1, 0.5, 0, 0.4, 1, 0, 0, 0, 1)), -1),  # B not symmetric
+    (dict(aniso=(1, 2, 0, 2, 1, 0, 0, 0, 1)), -1),      # B indefinite (2 x 2 minor < 0)
+    (dict(aniso=(1, 0, 0, 0, -1e-3, 0, 0, 0, 1)), -1),  # negative diagonal entry
+    (dict(aniso=(2, 1, 1, 1, 2, -1, 1, -1, 0.5)), -1),  # minors of order 2 fine, det < 0
+    (dict(aniso=(1, 0, 0, 0, 1, 0, 0, 0, float("inf"))), -1),
+    (dict(d=2, N=(15, 15), aniso=(1, 0, 0, 1, 1)), -1),  # entry past d x d
+    (dict(format=2, aniso=(1, 0, 0, 0, 1, 0, 0, 0, 1)), -5),  # Tucker: isotropic only
 ])
 def test_plan_validation(kw, code):
     L = _lib()
@@ -88,6 +97,22 @@ def test_plan_validation(kw, code):
     assert rc == code
     assert not plan.value
     assert len(lib.lrfg_last_error()) > 0
+
+
+@pytest.mark.parametrize("d,B", [
+    (2, (5.5, -4.5, -4.5, 5.5)),
+    (3, (4.25, -3.25, -1.25 * 2 ** 0.5, -3.25, 4.25, 1.25 * 2 ** 0.5, -1.25 * 2 ** 0.5, 1.25 * 2 ** 0.5, 7.5)),
+    (3, (1, 1, 0, 1, 1, 0, 0, 0, 0)),           # singular PSD is admissible
+])
+def test_plan_accepts_psd_anisotropy(d, B):
+    L = _lib()
+    lib = L.lib()
+    for fmt in (L.FORMAT_FULL, L.FORMAT_TT):
+        plan = C.c_void_p()
+        N = (15,) * d + (1,) * (3 - d)
+        rc = lib.lrfg_plan_create(C.byref(_problem(L, d=d, N=N, format=fmt, aniso=B)), C.byref(plan))
+        assert rc == 0, lib.lrfg_last_error()
+        lib.lrfg_plan_destroy(plan)
 
 
 def test_plan_and_workspace_sizes():
