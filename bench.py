@@ -25,10 +25,12 @@ path's dominant kernel family, the MFMA FP64 GEMM of the truncation (about
 to every GEMM dispatch through hipExtLaunchKernelGGL, the dispatch's own
 timestamps).  Secondary keys: `smooth135` (135^3 smooth coefficient, CP
 rank 9: TT, Tucker, mixed precision), `crossover` (the smooth coefficient
-at larger grids), `serving` and `cpu_baseline` (the oracle on the host).
+at larger grids), `anisotropic` (the anisotropic materials a I + B of
+Sec. 4.4: the smooth coefficient at 135^3 and at the crossover grids, and
+the 243^3 ball), `serving` and `cpu_baseline` (the oracle on the host).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                    [--crossover 405,729] [--no-crossover] [--serve-requests R]
+                    [--crossover 405,729] [--no-crossover] [--no-aniso] [--serve-requests R]
 """
 from __future__ import annotations
 
@@ -117,16 +119,18 @@ class Workload:
         self.a = torch.from_numpy(self.a_np).to(dev)
         self.w = torch.from_numpy(self.cp.weights).to(dev)
         self.f = [torch.from_numpy(x).to(dev) for x in self.cp.factors]
+        self.aniso = None     # constant anisotropic part B (Sec. 4.4), or None
         torch.cuda.synchronize()
 
     def full_solver(self, tol):
         import paper_1902_07455_amd as P
-        return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=500, device=self.dev)
+        return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=500, device=self.dev,
+                        aniso=self.aniso)
 
     def tt_solver(self, cap, tol, fmt="tt"):
         import paper_1902_07455_amd as P
         return P.Solver(d=3, N=(self.N,) * 3, format=fmt, rank_cap=cap, trunc_tol=0.0, solver_tol=tol,
-                        max_iter=100, coeff_rank=self.cp.rank, device=self.dev)
+                        max_iter=100, coeff_rank=self.cp.rank, device=self.dev, aniso=self.aniso)
 
     def run_full(self, s):
         return s.solve(full=self.a)
@@ -157,17 +161,19 @@ class BallWorkload:
         self.tt_err = float(torch.linalg.norm(full - self.a) / torch.linalg.norm(self.a))
         self.tt_min = float(full.min())
         del full
+        self.aniso = None     # constant anisotropic part B (Sec. 4.4), or None
         torch.cuda.synchronize()
 
     def full_solver(self, tol):
         import paper_1902_07455_amd as P
-        return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=2000, device=self.dev)
+        return P.Solver(d=3, N=(self.N,) * 3, format="full", solver_tol=tol, max_iter=2000, device=self.dev,
+                        aniso=self.aniso)
 
     def tt_solver(self, tol, cap=BALL_CAP, over=BALL_OVER, M=BALL_M, precision="fp64"):
         import paper_1902_07455_amd as P
         return P.Solver(d=3, N=(self.N,) * 3, format="tt", rank_cap=cap, trunc_tol=0.0, solver_tol=tol,
                         max_iter=150, coeff_rank=max(self.tt_ranks), oversample=over, precond_terms=M,
-                        precision=precision, device=self.dev)
+                        precision=precision, device=self.dev, aniso=self.aniso)
 
     def run_full(self, s):
         return s.solve(full=self.a)
@@ -549,6 +555,118 @@ def crossover_leg(sizes, dev):
     return rows
 
 
+def aniso_leg(args, dev, ball_wl=None):
+    """The anisotropic materials of Sec. 4.4, a(x) I + B with B of
+    eigenvalues (1, 5, 10): the 135^3 smooth coefficient (the stand-in for
+    the paper's material S) at equal accuracy, the same settings at the
+    crossover grids, and the 243^3 ball (contrast 100)."""
+    import torch
+
+    import paper_1902_07455_amd as P
+    import workloads as W
+    B = W.anisotropy(3)
+    out = {"B": B.round(12).tolist()}
+    wl = Workload(N_MAIN, dev)
+    wl.aniso = B
+    A_ref = reference(wl)
+    full_tol, fsweep = sweep_full(wl, A_ref)
+    cap, tol, tsweep = sweep_tt(wl, A_ref, caps=[8, 12, 16, 24, 32])
+    log(f"aniso 135: full tol {full_tol}, TT cap {cap} tol {tol}; sweeps {fsweep} {tsweep}")
+    row = {"workload": f"3D cell problem, N={N_MAIN}^3, smooth coefficient (8 cosine products, seed 0, CP rank 9) "
+                       "+ B, E=e1,e2,e3", "full_sweep": fsweep, "tt_sweep": tsweep}
+    if full_tol is not None:
+        fs = wl.full_solver(full_tol)
+        sec, lat, r = timed(lambda: wl.run_full(fs), 20, 2)
+        fs.close()
+        row["full_fft"] = {"solves_per_s": round(20 / sec, 3), "solver_tol": full_tol, "iters": int(r.iters.max()),
+                           "A_H_rel_err": rel_err(r.A_H, A_ref)}
+    if tol is not None:
+        ts = wl.tt_solver(cap, tol)
+        sec, lat, r = timed(lambda: wl.run_tt(ts), 20, 2)
+        ts.close()
+        row["tt"] = {"solves_per_s": round(20 / sec, 3), "rank_cap": cap, "solver_tol": tol,
+                     "iters": r.iters.tolist(), "A_H_rel_err": rel_err(r.A_H, A_ref)}
+    if "full_fft" in row and "tt" in row:
+        row["tt_over_full"] = round(row["tt"]["solves_per_s"] / row["full_fft"]["solves_per_s"], 4)
+    if not getattr(args, "no_cpu", False) and "full_fft" in row:
+        # the matrix-valued oracle on the same workload: 1 and 2 PCG
+        # iterations of all three correctors plus A_H (median of 3 after a
+        # warm-up), extrapolated to the full grid's iteration count
+        from oracle import fg, fg_tensor
+        log("aniso: CPU oracle baseline")
+        At = fg_tensor.isotropic_plus_constant(wl.a_np, B)
+        fg_tensor.solve(At, tol=1e-30, max_iter=1)
+
+        def med(k):
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                fg_tensor.solve(At, tol=1e-30, max_iter=k)
+                ts.append(time.perf_counter() - t0)
+            return float(np.median(ts))
+
+        t1, t2 = med(1), med(2)
+        n_it = row["full_fft"]["iters"]
+        est = t1 + (n_it - 1) * (t2 - t1)
+        row["cpu_baseline"] = {"value": round(1.0 / est, 5), "unit": "A_H solves/s", "cores": fg.FFT_WORKERS,
+                               "kind": "oracle", "sample": f"oracle.fg_tensor on the {N_MAIN}^3 smooth coefficient + B, "
+                               f"1 and 2 PCG iterations ({t1:.2f} s, {t2:.2f} s), extrapolated to {n_it}"}
+        del At
+    out["smooth135"] = row
+    del wl
+    torch.cuda.empty_cache()
+    # crossover: the 135^3 settings at larger grids, each error against its own 1e-12 reference
+    rows = []
+    for Nx in [int(x) for x in args.crossover.split(",") if x] if (full_tol and tol) else []:
+        log(f"aniso crossover N={Nx}")
+        w2 = Workload(Nx, dev)
+        w2.aniso = B
+        Ar = reference(w2)
+        s = w2.full_solver(full_tol)
+        fsec, _, r1 = timed(lambda: w2.run_full(s), 5, 1)
+        s.close()
+        s = w2.tt_solver(cap, tol)
+        tsec, _, r2 = timed(lambda: w2.run_tt(s), 5, 1)
+        nl, kms, flops = profiled(lambda: w2.run_tt(s), "gemm", 1)
+        s.close()
+        gach = flops / (kms / 1e3) / 1e12
+        rows.append({"N": Nx, "full_ms": round(1e3 * fsec / 5, 3), "full_err": rel_err(r1.A_H, Ar),
+                     "full_iters": int(r1.iters.max()), "tt_ms": round(1e3 * tsec / 5, 3), "tt_cap": cap,
+                     "tt_tol": tol, "tt_err": rel_err(r2.A_H, Ar), "tt_iters": r2.iters.tolist(),
+                     "tt_speedup": round(fsec / tsec, 3),
+                     "tt_gemm": {"launches": nl, "share_of_solve": round(kms / (1e3 * tsec / 5), 3),
+                                 "achieved_tflops": round(gach, 3),
+                                 "frac_fp64_mfma": round(gach / FP64_MFMA_PEAK_TFLOPS, 4)}})
+        del w2
+        torch.cuda.empty_cache()
+    out["crossover"] = rows
+    # the 243^3 ball with B: full grid at equal accuracy; TT at the largest
+    # rank cap the 128-wide sketches allow (85, oversampling 43)
+    wb = ball_wl if ball_wl is not None else BallWorkload(dev)
+    wb.aniso = B
+    s = wb.full_solver(1e-10)
+    Ab = wb.run_full(s).A_H
+    s.close()
+    bt, bsweep = sweep_full(wb, Ab)
+    ball = {"workload": "3D cell problem, N=243^3, ball r=0.3 contrast 100 + B, E=e1,e2,e3", "full_sweep": bsweep}
+    if bt is not None:
+        fs = wb.full_solver(bt)
+        sec, lat, r = timed(lambda: wb.run_full(fs), 5, 1)
+        fs.close()
+        ball["full_fft"] = {"solves_per_s": round(5 / sec, 3), "solver_tol": bt, "iters": int(r.iters.max()),
+                            "A_H_rel_err": rel_err(r.A_H, Ab)}
+    ts = wb.tt_solver(7e-6, 85, 43)
+    r = wb.run_tt(ts)
+    ts.close()
+    ball["tt_cap85"] = {"solver_tol": 7e-6, "A_H_rel_err": rel_err(r.A_H, Ab), "iters": r.iters.tolist(),
+                        "status": r.status.tolist(), "ranks": r.ranks.tolist(), "solve_ms": round(r.solve_ms, 1),
+                        "note": "rank-limited: the anisotropic correctors need ranks above the largest cap the "
+                                "sketch size allows, so TT does not reach 1e-6 here"}
+    wb.aniso = None
+    out["ball243"] = ball
+    return out
+
+
 def cpu_baseline(a_np, N, n_iters):
     """The oracle (oracle.fg, FFTs on every host core) on the headline
     workload: a bounded sample of one and of two PCG iterations of all three
@@ -589,6 +707,9 @@ def main(argv=None):
     ap.add_argument("--no-smooth", action="store_true", help="skip the 135^3 smooth-coefficient legs")
     ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker-format leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic (a I + B) legs")
+    ap.add_argument("--aniso-only", action="store_true",
+                    help="run only the anisotropic legs and print their JSON (profiling; no benchmark line)")
     ap.add_argument("--full-tol", type=float, default=None,
                     help="full-grid PCG tolerance (skips the sweep; the A_H error is still checked)")
     ap.add_argument("--tt-tol", type=float, default=None, help="TT solver tolerance (skips the sweep)")
@@ -618,6 +739,10 @@ def main(argv=None):
         log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
 
+    if args.aniso_only:
+        # the anisotropic legs alone (for profiling them); not the benchmark line
+        print(json.dumps({"anisotropic": aniso_leg(args, dev)}), flush=True)
+        return 0
     wl, A_ref, value, ttot, tlat, tt, full, roofline, latency_bound, ref_vs_oracle = ball_leg(args, dev)
     out = {
         "metric": "A_H solves/sec at 1e-6 rel. err (TT vs full-FFT, same GPU); p50/p99 latency",
@@ -644,6 +769,8 @@ def main(argv=None):
     }
     n_iters = full["iters"]
     ball_np, ball_N = wl.a_np, wl.N
+    if not args.no_aniso:
+        out["anisotropic"] = aniso_leg(args, dev, wl)
     del wl
     torch.cuda.empty_cache()
     if not args.no_smooth:
