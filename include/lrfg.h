@@ -457,7 +457,10 @@ void lrfg_server_destroy(lrfg_server* s);
  * "khatri_rao", "tt_round"; "fft_axis2" is the axis-2 pass of the
  * full-grid PCG matvec, "gemm" the MFMA GEMM kernel without its split-K
  * reduction) bracketed by HIP events on the stream it runs on; NULL
- * disables and clears.  lrfg_prof_read synchronises those events and
+ * disables and clears.  Every call destroys the events of the previous
+ * timing (a recorded event keeps the memory its launch used from returning
+ * to the device when it is freed), so read before switching.
+ * lrfg_prof_read synchronises those events and
  * returns the number of timed launches and their summed duration in
  * milliseconds; lrfg_prof_work returns the summed algorithmic work of those
  * launches: FLOPs (2 m n k per GEMM) for "gemm", bytes read plus written

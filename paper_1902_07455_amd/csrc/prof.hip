@@ -74,6 +74,11 @@ int lrfg_prof_enable(const char* kernel) {
   using namespace lrfg;
   std::lock_guard<std::mutex> lk(g_mu);
   g_target = kernel ? kernel : "";
+  // A recorded event keeps its launch (and with it the memory that launch
+  // used) referenced until the event is destroyed, so a freed workspace
+  // would not return to the device: the pool is destroyed at every switch.
+  for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
+  g_pool.clear();
   g_used = 0;
   g_open = false;
   g_work = 0.0;
