@@ -27,7 +27,9 @@ timestamps).  Secondary keys: `smooth135` (135^3 smooth coefficient, CP
 rank 9: TT, Tucker, mixed precision), `crossover` (the smooth coefficient
 at larger grids), `anisotropic` (the anisotropic materials a I + B of
 Sec. 4.4: the smooth coefficient at 135^3 and at the crossover grids, and
-the 243^3 ball), `serving` and `cpu_baseline` (the oracle on the host).
+the 243^3 ball), `rank_adaptive` (one rank-adaptive TT solve of the ball,
+caps 57 then the headline cap), `serving` and `cpu_baseline` (the oracle on
+the host).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--crossover 405,729] [--no-crossover] [--no-aniso] [--serve-requests R]
@@ -490,10 +492,28 @@ def ball_leg(args, dev):
                 "frac": round(gach / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": measured_traffic("gemm_ball243"),
                 "launches": nl, "avg_us": round((kms / 1e3) / max(nl, 1) * 1e6, 2),
                 "flops_per_launch": round(flops / max(nl, 1)), "share_of_solve": round(kms / per_solve_ms, 3)}
+    # rank-adaptive schedule (Sec. 4.2's proposal): stages at caps 57 and
+    # tcap, the second continuing from the first's corrector; one solve
+    ra = None
+    if not args.no_adaptive:
+        import paper_1902_07455_amd as P
+        ras = P.Solver(d=3, N=(wl.N,) * 3, format="tt", rank_cap=tcap, trunc_tol=0.0, solver_tol=ttol, max_iter=150,
+                       coeff_rank=max(wl.tt_ranks), oversample=tover, precond_terms=BALL_M, rank_start=57,
+                       device=dev)
+        t0 = time.perf_counter()
+        rr = wl.run_tt(ras)
+        ra_ms = 1e3 * (time.perf_counter() - t0)
+        ras.close()
+        ra = {"rank_start": 57, "caps": [57, tcap], "solver_tol": ttol, "ms_per_solve": round(ra_ms, 1),
+              "A_H_rel_err": rel_err(rr.A_H, A_ref), "iters": rr.iters.tolist(), "status": rr.status.tolist(),
+              "vs_fixed_time": round(ra_ms / (1e3 * ttot / args.steps), 3)}
+        log(f"rank-adaptive 57 -> {tcap}: err {ra['A_H_rel_err']:.2e} iters {ra['iters']} ({ra_ms:.0f} ms)")
     value = args.steps / ttot
     tt = {"path": "tensor-train PCG (randomised TT rounding)", "rank_cap": tcap, "oversample": tover,
           "precond_terms": BALL_M, "solver_tol": ttol, "iters": tr.iters.tolist(), "ranks": tr.ranks.tolist(),
           "status": tr.status.tolist(), "A_H_rel_err": terr, "sweep": tsweep}
+    if ra is not None:
+        tt["rank_adaptive"] = ra
     return wl, A_ref, value, ttot, tlat, tt, full, roofline, latency_bound, ref_vs_oracle
 
 
@@ -708,6 +728,7 @@ def main(argv=None):
     ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker-format leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic (a I + B) legs")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the rank-adaptive TT solve of the ball")
     ap.add_argument("--aniso-only", action="store_true",
                     help="run only the anisotropic legs and print their JSON (profiling; no benchmark line)")
     ap.add_argument("--full-tol", type=float, default=None,
@@ -767,6 +788,9 @@ def main(argv=None):
         "roofline": roofline,
         "latency_bound": latency_bound,
     }
+    ra = out["config"].pop("rank_adaptive", None)
+    if ra is not None:
+        out["rank_adaptive"] = ra
     n_iters = full["iters"]
     ball_np, ball_N = wl.a_np, wl.N
     if not args.no_aniso:

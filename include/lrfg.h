@@ -125,6 +125,17 @@ typedef struct {
                            or non-finite B, or nonzero entries past d*d:
                            LRFG_EINVAL.  Full-grid and TT/CP formats;
                            Tucker with B != 0: LRFG_EUNSUPPORTED           */
+  int rank_start;       /* TT/CP, FP64 PCG: rank-adaptive solve (Sec. 4.2: a
+                           solver that starts at a low solution rank and
+                           raises it during the iterations) when 0 <
+                           rank_start < rank_cap: stages at the caps
+                           rank_start, then x1.5 (at least +1) up to
+                           rank_cap, each started from the previous stage's
+                           corrector; a system leaves at the stage that
+                           reaches solver_tol.  0 (or >= rank_cap): one
+                           solve at rank_cap.  Negative: LRFG_EINVAL; other
+                           formats, precisions or solvers with rank_start >
+                           0: LRFG_EUNSUPPORTED                            */
 } lrfg_problem;
 
 /* Coefficient a(x) > 0 (scalar isotropic A = a I).  For FULL, `full` holds

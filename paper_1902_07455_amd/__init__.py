@@ -132,7 +132,7 @@ def _result_buffers(r, nE, d, max_iter):
 
 def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-10, max_iter=1000,
                   solver="pcg", precision="fp64", precond_terms=0, oversample=0, seed=0, coeff_rank=0,
-                  aniso=None):
+                  aniso=None, rank_start=0):
     p = _lib.Problem()
     p.d = int(d)
     Ns = list(N) + [1] * (3 - len(N))
@@ -156,6 +156,7 @@ def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-
             raise ValueError("aniso must be a d x d matrix")
         for i, v in enumerate(B.reshape(-1)):
             p.aniso[i] = float(v)
+    p.rank_start = int(rank_start)
     return p
 
 
@@ -166,10 +167,10 @@ class Solver:
                  trunc_tol: float = 0.0, solver_tol: float = 1e-10, max_iter: int = 1000,
                  solver: str = "pcg", precision: str = "fp64", precond_terms: int = 0,
                  oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
-                 coeff_rank: int = 0, device: str = "cuda:0", aniso=None):
+                 coeff_rank: int = 0, device: str = "cuda:0", aniso=None, rank_start: int = 0):
         L = lib()
         p = _make_problem(d, N, format, rank_cap, trunc_tol, solver_tol, max_iter, solver, precision,
-                          precond_terms, oversample, seed, coeff_rank, aniso)
+                          precond_terms, oversample, seed, coeff_rank, aniso, rank_start)
         self.problem = p
         self.d = int(d)
         self.max_iter = int(max_iter)

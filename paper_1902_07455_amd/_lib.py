@@ -39,6 +39,7 @@ class Problem(C.Structure):
         ("coeff_rank", C.c_int),
         ("flags", C.c_uint32),
         ("aniso", C.c_double * 9),
+        ("rank_start", C.c_int),
     ]
 
 

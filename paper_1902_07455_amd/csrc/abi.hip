@@ -153,6 +153,16 @@ int validate(const lrfg_problem* p) {
       }
     }
   }
+  if (p->rank_start < 0) {
+    set_error("rank_start must be >= 0");
+    return LRFG_EINVAL;
+  }
+  if (p->rank_start > 0 && p->rank_start < p->rank_cap &&
+      (!(p->format == LRFG_FORMAT_TT || p->format == LRFG_FORMAT_CP) || p->precision != LRFG_PREC_FP64 ||
+       p->solver != LRFG_SOLVER_PCG)) {
+    set_error("the rank-adaptive solve is built for the TT/CP formats, FP64, PCG");
+    return LRFG_EUNSUPPORTED;
+  }
   if (p->format == LRFG_FORMAT_FULL && p->precision != LRFG_PREC_FP64) {
     set_error("the full-grid path runs in FP64 only");
     return LRFG_EUNSUPPORTED;

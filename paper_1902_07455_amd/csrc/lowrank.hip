@@ -181,6 +181,7 @@ struct Ctx {
   double* bcore;            // anisotropic part: D_j v_j and D_j^2 v_j, 2 d carriage buffers
   long long bstride;
   TTB tmp;                  // extra corrector-size train
+  TTB x0;                   // starting corrector of a rank-adaptive stage
   TTB b0, xa, xbest;        // mixed precision: right-hand side, corrector, best corrector
   double *dots, *rho, *pqd, *alpha, *beta, *zz, *Ecoef, *coef2, *dscr;
   double *ones, *mones;     // per-system +1 / -1 coefficients
@@ -219,6 +220,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   C.xb = tt_alloc(ar, d, pl->N, rc, nE);
   C.b = tt_alloc(ar, d, pl->N, rc, nE);
   C.tmp = tt_alloc(ar, d, pl->N, rc, nE);
+  C.x0 = tt_alloc(ar, d, pl->N, rc, nE);
   if (pl->p.precision != LRFG_PREC_FP64) {
     C.b0 = tt_alloc(ar, d, pl->N, rc, nE);
     C.xa = tt_alloc(ar, d, pl->N, rc, nE);
@@ -543,6 +545,17 @@ int read_dev(Ctx& C, const double* dptr, double* host, int n) {
 }  // namespace
 
 // ====================================================================== plan
+// nominal corrector ranks: the rank cap, limited by the unfoldings' sizes
+static void plan_ranks(LowRankPlan& pl) {
+  const lrfg_problem& p = pl.p;
+  if (p.d == 3) {
+    pl.c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1] * p.N[2]));
+    pl.c[2] = std::min(p.rank_cap, std::min(p.N[2], p.N[0] * p.N[1]));
+  } else {
+    pl.c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1]));
+  }
+}
+
 int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out) {
   LowRankPlan* pl = new LowRankPlan();
   pl->p = p;
@@ -563,12 +576,7 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
     delete pl;
     return LRFG_EUNSUPPORTED;
   }
-  if (p.d == 3) {
-    pl->c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1] * p.N[2]));
-    pl->c[2] = std::min(p.rank_cap, std::min(p.N[2], p.N[0] * p.N[1]));
-  } else {
-    pl->c[1] = std::min(p.rank_cap, std::min(p.N[0], p.N[1]));
-  }
+  plan_ranks(*pl);
   for (int j = 1; j < p.d; ++j) {
     if (pl->c[j] + pl->over > kMaxEig) {
       // the sketch size bounds the small eigenproblems
@@ -702,8 +710,22 @@ int load_coeff(Ctx& C, const lrfg_coeff& ac, int e, int* rk) {
 
 }  // namespace
 
-int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E, int nEp, void* ws,
-                  size_t ws_bytes, hipStream_t s, lrfg_result* outs) {
+// Correctors kept on the host between the stages of a rank-adaptive solve:
+// nE trains of ranks r, carriage j of system e at core[j][e * size_j].
+struct HostTrains {
+  int r[4] = {1, 1, 1, 1};
+  std::vector<double> core[3];
+};
+
+namespace {
+
+// One solve at the plan's ranks.  With x0 (FP64 PCG): the truncated PCG
+// continues from x0 (zero-padded to the plan's ranks) with its true residual
+// T(b - K x0), residuals relative to ||P~^-1 b||; a system whose true
+// residual already meets solver_tol stops there.  With xout: the returned
+// correctors, copied to the host.
+int solve_stage(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E, int nEp, void* ws,
+                size_t ws_bytes, hipStream_t s, lrfg_result* outs, const HostTrains* x0, HostTrains* xout) {
   const int d = pl->d;
   const lrfg_problem& P = pl->p;
   if (P.format == LRFG_FORMAT_TUCKER) {
@@ -916,8 +938,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
   // travels in (per-matrix GEMM splits, one sketch per truncation call), so
   // the results are those of the full batch; the slot order is restored
   // at the end.
+  //
+  // With xstart (PCG): the iteration starts from that corrector instead of
+  // zero (r = T(b - K x), p = z = T(P~^-1 r), the start as the first best
+  // iterate, skipped systems keep it) and residuals are relative to ref
+  // (the norms ||P~^-1 b|| of the unshifted start).
   auto inner = [&](double tol, int max_it, const std::vector<int>& skip, std::vector<double>& res0,
-                   std::vector<int>& st, bool record) -> int {
+                   std::vector<int>& st, bool record, const TTB* xstart = nullptr,
+                   const std::vector<double>* ref = nullptr) -> int {
     const bool compact = na == 1;
     int nA = nE;
     std::vector<int> perm(nE), slot_done(nE);
@@ -1013,7 +1041,17 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     LRFG_TRY(tt_zero(C.xb, nE, s));
     set_views(nE);
     LRFG_TRY(push_done());
-    if (P.solver == LRFG_SOLVER_PCG) {
+    const bool from_x = xstart != nullptr && P.solver == LRFG_SOLVER_PCG;
+    if (from_x) {
+      LRFG_TRY(tt_copy(*xstart, C.x, nE, s));
+      LRFG_TRY(tt_copy(*xstart, C.xb, nE, s));
+      LRFG_TRY(apply_K(C, C.x, C.tmp));
+      LRFG_TRY(axpby(C, C.b, C.tmp, C.mones, C.r));
+      LRFG_TRY(apply_P(C, C.r, C.z));
+      LRFG_TRY(tt_copy(C.z, C.p, nE, s));
+      LRFG_TRY(dot(C, C.r, C.z, C.rho));
+      LRFG_TRY(dot(C, C.z, C.z, C.zz));
+    } else if (P.solver == LRFG_SOLVER_PCG) {
       LRFG_TRY(tt_copy(C.b, C.r, nE, s));
       LRFG_TRY(apply_P(C, C.r, C.z));
       LRFG_TRY(tt_copy(C.z, C.p, nE, s));
@@ -1028,8 +1066,14 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     }
     LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
     for (int e = 0; e < nE; ++e) {
-      res0[e] = std::sqrt(std::max(zzh[e], 0.0));
+      res0[e] = from_x ? (*ref)[e] : std::sqrt(std::max(zzh[e], 0.0));
       if (res0[e] <= floor_abs[e]) hdone[e] = 1;
+      if (from_x && res0[e] > 0.0) {
+        // the start is the first best iterate; reaching the tolerance there
+        // ends the system at once
+        best[e] = std::sqrt(std::max(zzh[e], 0.0)) / res0[e];
+        if (best[e] <= tol) hdone[e] = 1;
+      }
     }
     LRFG_TRY(push_done());
     if (compact) LRFG_TRY(compact_slots());
@@ -1175,7 +1219,33 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
 
   const std::vector<int> none(nE, 0);
   std::vector<double> res0(nE, 0.0);
-  if (P.precision == LRFG_PREC_FP64) {
+  if (P.precision == LRFG_PREC_FP64 && x0 != nullptr) {
+    // continue from x0: its carriages zero-padded to this stage's ranks
+    for (int j = 0; j < d; ++j) {
+      const int a0 = x0->r[j], a1 = x0->r[j + 1], b0 = C.x0.r[j], b1 = C.x0.r[j + 1], Nj = pl->N[j];
+      if (a0 > b0 || a1 > b1) {
+        set_error("rank-adaptive stage: starting ranks above the stage's");
+        return LRFG_EINVAL;
+      }
+      const long long sa = (long long)a0 * Nj * a1, sb = (long long)b0 * Nj * b1;
+      std::vector<double> h((size_t)sb * nE, 0.0);
+      for (int e = 0; e < nE; ++e)
+        for (int i = 0; i < a0; ++i)
+          for (int n = 0; n < Nj; ++n)
+            for (int k = 0; k < a1; ++k)
+              h[(size_t)(e * sb + ((long long)i * Nj + n) * b1 + k)] =
+                  x0->core[j][(size_t)(e * sa + ((long long)i * Nj + n) * a1 + k)];
+      LRFG_HIP(hipMemcpyAsync(C.x0.c[j], h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
+      LRFG_HIP(hipStreamSynchronize(s));
+    }
+    // residuals relative to ||P~^-1 b||, as in a solve from zero
+    std::vector<double> zzh(nE), ref(nE);
+    LRFG_TRY(apply_P(C, C.b, C.z));
+    LRFG_TRY(dot(C, C.z, C.z, C.zz));
+    LRFG_TRY(read_dev(C, C.zz, zzh.data(), nE));
+    for (int e = 0; e < nE; ++e) ref[e] = std::sqrt(std::max(zzh[e], 0.0));
+    LRFG_TRY(inner(P.solver_tol, maxit, none, res0, status, true, &C.x0, &ref));
+  } else if (P.precision == LRFG_PREC_FP64) {
     LRFG_TRY(inner(P.solver_tol, maxit, none, res0, status, true));
   } else {
     // Mixed precision (iterative refinement): the inner solves run their
@@ -1374,6 +1444,75 @@ int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* 
     }
     out->setup_ms = ms_setup;
     out->solve_ms = ms_solve;
+  }
+  if (xout != nullptr) {
+    for (int j = 0; j <= d; ++j) xout->r[j] = C.xb.r[j];
+    for (int j = 0; j < d; ++j) {
+      xout->core[j].resize((size_t)C.xb.size(j) * nE);
+      for (int e = 0; e < nE; ++e)
+        LRFG_HIP(hipMemcpyAsync(xout->core[j].data() + (size_t)e * C.xb.size(j), C.xb.c[j] + (long long)e * C.xb.s[j],
+                                sizeof(double) * C.xb.size(j), hipMemcpyDeviceToHost, s));
+    }
+    LRFG_HIP(hipStreamSynchronize(s));
+  }
+  return rc;
+}
+
+}  // namespace
+
+// Rank-adaptive solve (Sec. 4.2: start at a low solution rank and raise it
+// during the iterations).  Stages at rank caps c_0 = rank_start,
+// c_{k+1} = min(rank_cap, max(c_k + 1, ceil(1.5 c_k))), each a truncated PCG
+// at its cap; the first starts from zero, every later one continues from the
+// previous stage's corrector (zero-padded to the larger ranks) with its true
+// residual, so a system that a stage's recursive residual called converged
+// is checked again (and stops at once if it is).  A stage ends for a system
+// at solver_tol, stagnant at the rank floor of its cap, or at max_iter (per
+// stage).  A_H, the statuses and the ranks are those of the last stage, the
+// iteration counts and times add up over the stages, and res_hist holds the
+// first stage's history.
+int lowrank_solve(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E, int nEp, void* ws,
+                  size_t ws_bytes, hipStream_t s, lrfg_result* outs) {
+  const lrfg_problem& P = pl->p;
+  const bool adaptive = P.rank_start > 0 && P.rank_start < P.rank_cap && P.format != LRFG_FORMAT_TUCKER;
+  if (!adaptive) return solve_stage(pl, acs, nB, E, nEp, ws, ws_bytes, s, outs, nullptr, nullptr);
+  std::vector<int> caps;
+  for (int c = P.rank_start; c < P.rank_cap; c = std::max(c + 1, (int)std::ceil(1.5 * c))) caps.push_back(c);
+  caps.push_back(P.rank_cap);
+  const int nE = nB * nEp;
+  HostTrains xa, xb;
+  std::vector<int> its(nE, 0), st_it(nE), st_st(nE);
+  std::vector<double> setup(nB, 0.0), solve(nB, 0.0);
+  std::vector<lrfg_result> r(nB);
+  int rc = LRFG_OK;
+  for (size_t k = 0; k < caps.size(); ++k) {
+    LowRankPlan stp = *pl;
+    stp.p.rank_cap = caps[k];
+    stp.p.rank_start = 0;
+    plan_ranks(stp);
+    const bool last = k + 1 == caps.size();
+    for (int b = 0; b < nB; ++b) {
+      r[b] = outs[b];
+      r[b].iters = st_it.data() + b * nEp;
+      r[b].status = st_st.data() + b * nEp;
+      if (k > 0) r[b].res_hist = nullptr;  // the first stage's history stays
+    }
+    rc = solve_stage(&stp, acs, nB, E, nEp, ws, ws_bytes, s, r.data(), k > 0 ? &xa : nullptr, last ? nullptr : &xb);
+    if (rc < 0) return rc;
+    for (int e = 0; e < nE; ++e) its[e] += st_it[e];
+    for (int b = 0; b < nB; ++b) {
+      setup[b] += r[b].setup_ms;
+      solve[b] += r[b].solve_ms;
+    }
+    std::swap(xa, xb);
+  }
+  for (int b = 0; b < nB; ++b) {
+    for (int i = 0; i < nEp; ++i) {
+      if (outs[b].iters) outs[b].iters[i] = its[b * nEp + i];
+      if (outs[b].status) outs[b].status[i] = st_st[b * nEp + i];
+    }
+    outs[b].setup_ms = setup[b];
+    outs[b].solve_ms = solve[b];
   }
   return rc;
 }

@@ -60,6 +60,7 @@ def _problem(L, **kw):
     p.flags = kw.get("flags", 0)
     for i, v in enumerate(kw.get("aniso", ())):
         p.aniso[i] = v
+    p.rank_start = kw.get("rank_start", 0)
     return p
 
 
@@ -88,6 +89,11 @@ def _problem(L, **kw):
     (dict(aniso=(1, 0, 0, 0, 1, 0, 0, 0, float("inf"))), -1),
     (dict(d=2, N=(15, 15), aniso=(1, 0, 0, 1, 1)), -1),  # entry past d x d
     (dict(format=2, aniso=(1, 0, 0, 0, 1, 0, 0, 0, 1)), -5),  # Tucker: isotropic only
+    (dict(format=3, rank_start=-1), -1),
+    (dict(format=3, rank_start=4, solver=1), -5),     # rank-adaptive: PCG only
+    (dict(format=3, rank_start=4, precision=1), -5),  # rank-adaptive: FP64 only
+    (dict(format=2, rank_start=4), -5),               # rank-adaptive: TT/CP only
+    (dict(rank_start=4), -5),                         # not the full grid
 ])
 def test_plan_validation(kw, code):
     L = _lib()
