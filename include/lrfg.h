@@ -98,6 +98,25 @@ typedef enum {
   LRFG_PREC_MIXED_BF16 = 2
 } lrfg_precision;
 
+/* Discretisation of the bilinear form (Sec. 2.2). */
+typedef enum {
+  LRFG_DISC_GANI = 0,       /* numerical integration on the grid (Sec. 2.2.2,
+                               eq. ls_GaNi_fourier)                          */
+  LRFG_DISC_GA = 1          /* exact integration by the double grid 2N - 1
+                               (DoGIP, Sec. 2.2.3, eq. ls_Ga_fourier): the
+                               coefficient's Fourier integrals up to |m| <= N-1
+                               on the double grid, trial and test functions in
+                               T_N (every iterate masked to its frequencies);
+                               full grid only                                */
+} lrfg_discretisation;
+
+/* Inclusion coefficients with closed-form Fourier integrals (Ga only). */
+typedef enum {
+  LRFG_INCLUSION_NONE = 0,
+  LRFG_INCLUSION_SQUARE = 1,  /* centred square (2D) / cube (3D), |x_i| < size */
+  LRFG_INCLUSION_BALL = 2     /* centred ball |x| < size (3D)                  */
+} lrfg_inclusion;
+
 /* Problem description (the paper's problem statement, Sec. 2.1-2.3, 3.2). */
 typedef struct {
   int d;                /* 2 or 3                                            */
@@ -136,6 +155,9 @@ typedef struct {
                            solve at rank_cap.  Negative: LRFG_EINVAL; other
                            formats, precisions or solvers with rank_start >
                            0: LRFG_EUNSUPPORTED                            */
+  int discretisation;   /* lrfg_discretisation; LRFG_DISC_GA (full grid only)
+                           takes an inclusion coefficient (lrfg_coeff) and
+                           runs on the double grid 2N - 1                   */
 } lrfg_problem;
 
 /* Coefficient a(x) > 0 (scalar isotropic A = a I).  For FULL, `full` holds
@@ -165,6 +187,11 @@ typedef struct {
   int tucker_ranks[3];            /* Tucker form: r_1..r_3                      */
   const double* tucker_core;      /* Tucker form: [r_1][r_2][r_3]               */
   const double* tucker_frames[3]; /* Tucker form: N_i x r_i                      */
+  int inclusion;                  /* lrfg_inclusion (LRFG_DISC_GA only): value
+                                     incl_inside in the inclusion of half side /
+                                     radius incl_size in (0, 1/2), incl_outside
+                                     elsewhere (both > 0)                      */
+  double incl_size, incl_inside, incl_outside;
 } lrfg_coeff;
 
 /* Results, host memory owned by the caller (any pointer may be NULL). */

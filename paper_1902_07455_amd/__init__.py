@@ -86,10 +86,20 @@ class SolveResult:
     solve_ms: float
 
 
-def _fill_coeff(c, h, full=None, cp=None, tt=None, tucker=None):
-    """Fill an lrfg_coeff from numpy arrays or torch tensors (kept alive by h)."""
+_INCLUSIONS = {"square": 1, "cube": 1, "ball": 2}
+
+
+def _fill_coeff(c, h, full=None, cp=None, tt=None, tucker=None, inclusion=None):
+    """Fill an lrfg_coeff from numpy arrays or torch tensors (kept alive by h);
+    inclusion: dict(shape="square"|"cube"|"ball", size=, inside=, outside=)
+    (the Ga discretisation's coefficient)."""
     on_dev = 0
-    if full is not None:
+    if inclusion is not None:
+        c.inclusion = _INCLUSIONS[inclusion["shape"]]
+        c.incl_size = float(inclusion["size"])
+        c.incl_inside = float(inclusion["inside"])
+        c.incl_outside = float(inclusion["outside"])
+    elif full is not None:
         ptr, on_dev = h.ptr(full)
         c.full = ptr
     elif cp is not None:
@@ -132,7 +142,7 @@ def _result_buffers(r, nE, d, max_iter):
 
 def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-10, max_iter=1000,
                   solver="pcg", precision="fp64", precond_terms=0, oversample=0, seed=0, coeff_rank=0,
-                  aniso=None, rank_start=0):
+                  aniso=None, rank_start=0, discretisation="gani"):
     p = _lib.Problem()
     p.d = int(d)
     Ns = list(N) + [1] * (3 - len(N))
@@ -157,6 +167,7 @@ def _make_problem(d, N, format="full", rank_cap=0, trunc_tol=0.0, solver_tol=1e-
         for i, v in enumerate(B.reshape(-1)):
             p.aniso[i] = float(v)
     p.rank_start = int(rank_start)
+    p.discretisation = {"gani": 0, "ga": 1}[discretisation]
     return p
 
 
@@ -167,10 +178,11 @@ class Solver:
                  trunc_tol: float = 0.0, solver_tol: float = 1e-10, max_iter: int = 1000,
                  solver: str = "pcg", precision: str = "fp64", precond_terms: int = 0,
                  oversample: int = 0, seed: int = 0, max_nE: Optional[int] = None,
-                 coeff_rank: int = 0, device: str = "cuda:0", aniso=None, rank_start: int = 0):
+                 coeff_rank: int = 0, device: str = "cuda:0", aniso=None, rank_start: int = 0,
+                 discretisation: str = "gani"):
         L = lib()
         p = _make_problem(d, N, format, rank_cap, trunc_tol, solver_tol, max_iter, solver, precision,
-                          precond_terms, oversample, seed, coeff_rank, aniso, rank_start)
+                          precond_terms, oversample, seed, coeff_rank, aniso, rank_start, discretisation)
         self.problem = p
         self.d = int(d)
         self.max_iter = int(max_iter)
@@ -189,11 +201,13 @@ class Solver:
             self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def solve(self, full=None, cp=None, tt=None, tucker=None, E=None, stream=None) -> SolveResult:
+    def solve(self, full=None, cp=None, tt=None, tucker=None, E=None, stream=None, inclusion=None) -> SolveResult:
         """full: nodal values; cp: (weights (R,), [factors (R, N_i)]);
         tt: list of cores [r_{i-1}][N_i][r_i]; tucker: (core (r_1, r_2, r_3),
-        [frames (N_i, r_i)]).  E: (nE, d) or None."""
-        return self.solve_batch([dict(full=full, cp=cp, tt=tt, tucker=tucker)], E=E, stream=stream)[0]
+        [frames (N_i, r_i)]); inclusion: dict(shape, size, inside, outside)
+        for discretisation="ga".  E: (nE, d) or None."""
+        return self.solve_batch([dict(full=full, cp=cp, tt=tt, tucker=tucker, inclusion=inclusion)], E=E,
+                                stream=stream)[0]
 
     def solve_batch(self, coeffs, E=None, stream=None):
         """Several microstructures of this problem in one batched solve
@@ -205,7 +219,7 @@ class Solver:
         h = _Held(self.device)
         cs = (_lib.Coeff * len(coeffs))()
         for k, kw in enumerate(coeffs):
-            _fill_coeff(cs[k], h, kw.get("full"), kw.get("cp"), kw.get("tt"), kw.get("tucker"))
+            _fill_coeff(cs[k], h, kw.get("full"), kw.get("cp"), kw.get("tt"), kw.get("tucker"), kw.get("inclusion"))
         d = self.d
         if E is None:
             nE = d

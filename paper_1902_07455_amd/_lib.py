@@ -40,6 +40,7 @@ class Problem(C.Structure):
         ("flags", C.c_uint32),
         ("aniso", C.c_double * 9),
         ("rank_start", C.c_int),
+        ("discretisation", C.c_int),
     ]
 
 
@@ -55,6 +56,10 @@ class Coeff(C.Structure):
         ("tucker_ranks", C.c_int * 3),
         ("tucker_core", C.c_void_p),
         ("tucker_frames", C.c_void_p * 3),
+        ("inclusion", C.c_int),
+        ("incl_size", C.c_double),
+        ("incl_inside", C.c_double),
+        ("incl_outside", C.c_double),
     ]
 
 

@@ -153,6 +153,21 @@ int validate(const lrfg_problem* p) {
       }
     }
   }
+  if (p->discretisation != LRFG_DISC_GANI && p->discretisation != LRFG_DISC_GA) {
+    set_error("unknown discretisation %d", p->discretisation);
+    return LRFG_EINVAL;
+  }
+  if (p->discretisation == LRFG_DISC_GA) {
+    if (p->format != LRFG_FORMAT_FULL) {
+      set_error("the Ga discretisation is built for the full grid");
+      return LRFG_EUNSUPPORTED;
+    }
+    for (int i = 0; i < p->d; ++i)
+      if (p->N[i] > 1024) {
+        set_error("Ga: N[%d] = %d above 1024 (double grid above 2047)", i, p->N[i]);
+        return LRFG_EUNSUPPORTED;
+      }
+  }
   if (p->rank_start < 0) {
     set_error("rank_start must be >= 0");
     return LRFG_EINVAL;
@@ -222,14 +237,17 @@ int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
   LRFG_TRY(validate(p));
   lrfg_plan* pl = new lrfg_plan();
   pl->p = *p;
+  // full-grid geometry: the double grid 2N - 1 for Ga
+  const int g2 = p->discretisation == LRFG_DISC_GA ? 2 : 1;
+  auto gridN = [&](int i) { return g2 * p->N[i] - (g2 - 1); };
   if (p->d == 3) {
-    pl->N3d[0] = p->N[0];
-    pl->N3d[1] = p->N[1];
-    pl->N3d[2] = p->N[2];
+    pl->N3d[0] = gridN(0);
+    pl->N3d[1] = gridN(1);
+    pl->N3d[2] = gridN(2);
   } else {
     pl->N3d[0] = 1;
-    pl->N3d[1] = p->N[0];
-    pl->N3d[2] = p->N[1];
+    pl->N3d[1] = gridN(0);
+    pl->N3d[2] = gridN(1);
   }
   for (int i = 0; i < 3; ++i) {
     int rc = fft_plan_make(pl->N3d[i], &pl->axis[i]);
@@ -325,10 +343,35 @@ static int solve_impl(lrfg_plan* plan, const lrfg_coeff* a, int count, const dou
   }
   for (int b = 0; b < count; ++b) {
     const int nsrc = (a[b].full != nullptr) + (a[b].weights != nullptr) + (a[b].tt_cores[0] != nullptr) +
-                     (a[b].tucker_core != nullptr);
+                     (a[b].tucker_core != nullptr) + (a[b].inclusion != LRFG_INCLUSION_NONE);
     if (nsrc != 1) {
-      set_error("coefficient %d: exactly one of full / weights / tt_cores / tucker_core must be given", b);
+      set_error("coefficient %d: exactly one of full / weights / tt_cores / tucker_core / inclusion must be given",
+                b);
       return LRFG_EINVAL;
+    }
+    if ((a[b].inclusion != LRFG_INCLUSION_NONE) != (p.discretisation == LRFG_DISC_GA)) {
+      set_error("coefficient %d: the Ga discretisation takes an inclusion coefficient, and only it does", b);
+      return LRFG_EINVAL;
+    }
+    if (a[b].inclusion != LRFG_INCLUSION_NONE) {
+      const lrfg_coeff& c = a[b];
+      if (c.inclusion != LRFG_INCLUSION_SQUARE && c.inclusion != LRFG_INCLUSION_BALL) {
+        set_error("coefficient %d: unknown inclusion %d", b, c.inclusion);
+        return LRFG_EINVAL;
+      }
+      if (c.inclusion == LRFG_INCLUSION_BALL && p.d != 3) {
+        set_error("coefficient %d: the ball inclusion is 3D", b);
+        return LRFG_EUNSUPPORTED;
+      }
+      if (!(std::isfinite(c.incl_size) && c.incl_size > 0.0 && c.incl_size < 0.5)) {
+        set_error("coefficient %d: inclusion size must be in (0, 1/2)", b);
+        return LRFG_EINVAL;
+      }
+      if (!(std::isfinite(c.incl_inside) && c.incl_inside > 0.0 && std::isfinite(c.incl_outside) &&
+            c.incl_outside > 0.0)) {
+        set_error("coefficient %d: inclusion values must be finite and positive", b);
+        return LRFG_ECOEFF;
+      }
     }
     const bool tucker_in = a[b].tucker_core != nullptr;
     if (tucker_in != (p.format == LRFG_FORMAT_TUCKER && a[b].weights == nullptr)) {
@@ -399,6 +442,8 @@ static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int n
     const size_t full_need = need - stage;
     if (a->full != nullptr) {
       afull = a->full;
+    } else if (a->inclusion != LRFG_INCLUSION_NONE) {
+      afull = nullptr;  // built on the double grid by the solve
     } else {
       double* dst = reinterpret_cast<double*>(wsc + full_need);
       LRFG_TRY(expand_coeff(p, *a, dst, stage, s));
@@ -422,6 +467,17 @@ static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int n
     fa.stream = stream;
     fa.pinned_flags = plan->pinned;
     for (int i = 0; i < p.d * p.d; ++i) fa.B[i] = p.aniso[i];
+    if (p.discretisation == LRFG_DISC_GA) {
+      // the double grid M = 2N - 1; trial and test functions on the N-frequencies
+      for (int i = 0; i < p.d; ++i) {
+        fa.ga_N[i] = p.N[i];
+        fa.N[i] = 2 * p.N[i] - 1;
+      }
+      fa.incl = a->inclusion;
+      fa.incl_size = a->incl_size;
+      fa.incl_in = a->incl_inside;
+      fa.incl_out = a->incl_outside;
+    }
     FullSolveOut fo;
     fo.A_H = out->A_H;
     fo.iters = out->iters;

@@ -22,6 +22,12 @@ struct FullSolveArgs {
   void* stream;
   int* pinned_flags;      // pinned host ints, 4 * nE
   double B[9] = {};       // constant anisotropic part, d x d row-major (all 0: isotropic)
+  // Ga (exact integration, Sec. 2.2.3): N above is the double grid 2 ga_N - 1,
+  // a is built from the inclusion's Fourier integrals, and every iterate is
+  // kept on the frequencies of ga_N (0: GaNi)
+  int ga_N[3] = {0, 0, 0};
+  int incl = 0;           // lrfg_inclusion
+  double incl_size = 0.0, incl_in = 0.0, incl_out = 0.0;
 };
 
 struct FullSolveOut {

@@ -73,6 +73,18 @@ struct Aniso3 {
   double b00, b11, b22, b01, b02, b12;  // scaled by 4 pi^2
   int on;
 };
+// Ga (exact integration, Sec. 2.2.3): trial and test functions in T_N, kept
+// on the double grid M = 2N - 1 as spectra whose frequencies beyond
+// |k_i| <= kmax_i are zero (the injection I and its adjoint I*).  on = 0:
+// GaNi, no mask.
+struct Mask3 {
+  int k0, k1, k2;
+  int on;
+};
+__device__ inline bool masked_out(const Mask3& m, int f0, int f1, int h) {
+  return m.on && (abs(f0) > m.k0 || abs(f1) > m.k1 || h > m.k2);
+}
+
 __device__ inline double aniso_symbol(const Aniso3& B, double k0, double k1, double k2) {
   return B.b00 * k0 * k0 + B.b11 * k1 * k1 + B.b22 * k2 * k2 +
          2.0 * (B.b01 * k0 * k1 + B.b02 * k0 * k2 + B.b12 * k1 * k2);
@@ -141,7 +153,7 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
                                                           const double2* __restrict__ p, G3 g, int alpha0, int nalpha,
                                                           double inv_vol, int T, FftDev f,
                                                           const int* __restrict__ done, double* __restrict__ part_pq,
-                                                          Aniso3 an) {
+                                                          Aniso3 an, Mask3 mk) {
   extern __shared__ double2 sm[];
   __shared__ double red[kBlock / 64];
   const int e = blockIdx.y;
@@ -210,6 +222,8 @@ __global__ __launch_bounds__(kFftBlock) void k_div_axis1(const double2* __restri
         acc[j].x += c * pv.x;
         acc[j].y += c * pv.y;
       }
+      if (masked_out(mk, freq_of(n, g.N1), freq_of((int)(i / g.H), g.N2), (int)(i % g.H)))
+        acc[j] = make_double2(0.0, 0.0);
       qe[ad] = acc[j];
       const double w = (i % g.H) == 0 ? 1.0 : 2.0;
       pq += w * (pv.x * acc[j].x + pv.y * acc[j].y);
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(kFftBlock) void k3_div_axis1(const double2* __restr
                                                            const double2* __restrict__ p, G3 g, int alpha0,
                                                            int nalpha, double inv_vol, FftDev f,
                                                            const int* __restrict__ done, double* __restrict__ part_pq,
-                                                           Aniso3 an) {
+                                                           Aniso3 an, Mask3 mk) {
   constexpr int N = A * B * C;
   constexpr int T = split_lines(N);
   using F = Fft3<A, B, C, -1, T, false, kFftBlock>;
@@ -511,6 +525,8 @@ __global__ __launch_bounds__(kFftBlock) void k3_div_axis1(const double2* __restr
             acc[pi][r].x += c * pv.x;
             acc[pi][r].y += c * pv.y;
           }
+          if (masked_out(mk, freq_of(n1, N), freq_of((int)(l / (unsigned)g.H), g.N2), (int)(l % (unsigned)g.H)))
+            acc[pi][r] = make_double2(0.0, 0.0);
           st32(qe, off, acc[pi][r]);
           pq += w * (pv.x * acc[pi][r].x + pv.y * acc[pi][r].y);
         }
@@ -667,12 +683,13 @@ int launch3_grad(const double2* src, double2* dst, const G3& g, int alpha0, int 
 }
 
 int launch3_div(const double2* t, double2* q, const double2* p, const G3& g, int alpha0, int nalpha, double inv_vol,
-                const FftDev& f, const int* done, double* part, int nsys, hipStream_t s, const Aniso3& an) {
+                const FftDev& f, const int* done, double* part, int nsys, hipStream_t s, const Aniso3& an,
+                const Mask3& mk) {
   const dim3 grid(pass_tiles1(g), nsys);
 #define LRFG_D3(NN)                                                                                          \
   case NN:                                                                                                   \
     hipLaunchKernelGGL((k3_div_axis1<split_of(NN).A, split_of(NN).B, split_of(NN).C>), grid, dim3(kFftBlock), 0, \
-                       s, t, q, p, g, alpha0, nalpha, inv_vol, f, done, part, an);                           \
+                       s, t, q, p, g, alpha0, nalpha, inv_vol, f, done, part, an, mk);                       \
     break;
   switch (g.N1) {
     LRFG_SPLIT_CASES(LRFG_D3)
@@ -735,7 +752,7 @@ __device__ inline double block_reduce_array(const double* __restrict__ part, int
 // r = b^ = 2 pi i (k.E_e) a^ ; x = 0 ; z = P^-1 r ; p = z ; partial (r,z), (z,z)
 __global__ void k_cg_init(const double2* __restrict__ ahat, const double* __restrict__ E3, G3 g,
                           double2* __restrict__ x, double2* __restrict__ r, double2* __restrict__ p,
-                          double* __restrict__ part_rz, double* __restrict__ part_zz) {
+                          double* __restrict__ part_rz, double* __restrict__ part_zz, Mask3 mk) {
   __shared__ double red[kBlock / 64];
   const int e = blockIdx.y;
   const double* E = E3 + 3 * e;
@@ -748,7 +765,7 @@ __global__ void k_cg_init(const double2* __restrict__ ahat, const double* __rest
     double k[3];
     kvec(g, n1, n2, h, k);
     const double ke = k[0] * E[0] + k[1] * E[1] + k[2] * E[2];
-    const double2 rv = cmul_i(ahat[s], 2.0 * kPi * ke);
+    const double2 rv = masked_out(mk, (int)k[0], (int)k[1], h) ? make_double2(0.0, 0.0) : cmul_i(ahat[s], 2.0 * kPi * ke);
     const double pi = pinv_of(k);
     const double2 zv = cscale(rv, pi);
     x[off + s] = make_double2(0.0, 0.0);
@@ -919,6 +936,45 @@ __global__ void k_ah_reduce(const double* __restrict__ a, const double* __restri
   }
 }
 
+// Ga's coefficient on the double grid (Sec. 2.2.3): the half spectrum
+// C(m) = A^(m) prod_i exp(-pi i m_i (M_i - 1)/M_i), A^(m) the exact Fourier
+// integral of the inclusion coefficient (value vin inside, vout outside):
+// square/cube |x_i| < size: (vin - vout) prod_i s(m_i) + vout delta_m0 with
+// s(0) = 2 size, s(m) = sin(2 pi m size)/(pi m); ball |x| < size:
+// (vin - vout)(sin z - z cos z)/(2 pi^2 rho^3) + vout delta_m0, z = 2 pi size rho
+// (4 pi size^3 / 3 at rho = 0).  The phase places the unnormalised inverse DFT
+// at the points x_j = -1/2 + (j + 1/2)/M.  d = 2 uses axes 1 and 2.
+__global__ void k_incl_spectrum(double2* __restrict__ out, G3 g, int d, int shape, double size, double vin,
+                                double vout) {
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    int n1, n2, h;
+    decode(g, s, n1, n2, h);
+    double k[3];
+    kvec(g, n1, n2, h, k);
+    const int Ms[3] = {g.N1, g.N2, g.N3};
+    double chi;
+    if (shape == 1) {
+      chi = 1.0;
+      for (int a = 3 - d; a < 3; ++a)
+        chi *= k[a] == 0.0 ? 2.0 * size : sin(2.0 * kPi * k[a] * size) / (kPi * k[a]);
+    } else {
+      const double rho = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+      if (rho == 0.0) {
+        chi = 4.0 * kPi * size * size * size / 3.0;
+      } else {
+        const double z = 2.0 * kPi * size * rho;
+        chi = (sin(z) - z * cos(z)) / (2.0 * kPi * kPi * rho * rho * rho);
+      }
+    }
+    double v = (vin - vout) * chi;
+    if (k[0] == 0.0 && k[1] == 0.0 && k[2] == 0.0) v += vout;
+    double ph = 0.0;
+    for (int a = 0; a < 3; ++a) ph -= kPi * k[a] * (double)(Ms[a] - 1) / (double)Ms[a];
+    out[s] = make_double2(v * cos(ph), v * sin(ph));
+  }
+}
+
 // Per-block partial sums of sum_k w 4 pi^2 k.Bk Re(x^_i conj x^_j), i <= j,
 // over the half spectrum (w = 1 on h = 0, else 2): the B share of A_H
 // (the Fourier coefficients carry the grid mean's normalisation).
@@ -1066,6 +1122,14 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     an.b02 = f * 0.5 * (B3[0][2] + B3[2][0]);
     an.b12 = f * 0.5 * (B3[1][2] + B3[2][1]);
   }
+  // Ga: the N-frequencies in the internal axes (d = 2: axes 1 and 2)
+  const bool ga = A.ga_N[0] > 0;
+  Mask3 mk{0, 0, 0, 0};
+  if (ga) {
+    int lim[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i) lim[alpha0 + i] = (A.ga_N[i] - 1) / 2;
+    mk = Mask3{lim[0], lim[1], lim[2], 1};
+  }
   Arena ar;
   ar.base = static_cast<char*>(A.ws);
   ar.cap = A.ws_bytes;
@@ -1089,7 +1153,24 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   const bool two1 = pass_register(g.N1, g), two3 = pass_register(g.N3, g);
 
   // coefficient
-  if (A.a_on_device) {
+  if (ga) {
+    // the inclusion's Fourier integrals on the double grid, then the
+    // unnormalised inverse transform (axes 1 and 2, C2R along axis 3) to its
+    // nodal values; q[0] is free until the first matvec
+    hipLaunchKernelGGL(k_incl_spectrum, dim3(L.grid_vec), dim3(kBlock), 0, s, L.q, g, d, A.incl, A.incl_size,
+                       A.incl_in, A.incl_out);
+    LRFG_LAUNCHED();
+    LRFG_TRY(launch_fft_lines(L.q, 1, g.N1, (long long)g.N2 * g.H, 1, f1, 1.0, s));
+    LRFG_TRY(launch_fft_lines(L.q, g.N1, g.N2, g.H, 1, f2, 1.0, s));
+    {
+      const size_t shm3c = size_t(L.T3 + 1) * g.N3 * sizeof(double2);
+      const int tiles3c = ceil_div(((long long)g.N1 * g.N2 + 1) / 2, L.T3);
+      hipLaunchKernelGGL((G3 ? k_axis3<2, true> : k_axis3<2, false>), dim3(tiles3c, 1), dim3(kBlock), shm3c, s,
+                         (const void*)L.q, (void*)L.a, (const double*)nullptr, g, g.S, 0LL, L.T3, f3, 1.0,
+                         (const int*)nullptr, 1);
+      LRFG_LAUNCHED();
+    }
+  } else if (A.a_on_device) {
     LRFG_HIP(hipMemcpyAsync(L.a, A.a, sizeof(double) * g.R, hipMemcpyDeviceToDevice, s));
   } else {
     LRFG_HIP(hipMemcpyAsync(L.a, A.a, sizeof(double) * g.R, hipMemcpyHostToDevice, s));
@@ -1111,7 +1192,10 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   LRFG_HIP(hipMemcpyAsync(stat.data(), L.part_misc, sizeof(double) * 2 * L.nstat, hipMemcpyDeviceToHost, s));
   LRFG_HIP(hipMemcpyAsync(&bad, L.bad, sizeof(int), hipMemcpyDeviceToHost, s));
   LRFG_HIP(hipStreamSynchronize(s));
-  if (bad) {
+  // Ga's double-grid coefficient is a truncated Fourier series: it may dip
+  // below zero near the inclusion's boundary while the bilinear form (the
+  // integral of the true coefficient) stays positive
+  if (bad && !ga) {
     set_error("coefficient must be finite and positive");
     return LRFG_ECOEFF;
   }
@@ -1145,7 +1229,7 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
   LRFG_TRY(launch_fft_lines(ahat, 1, g.N1, (long long)g.N2 * g.H, -1, f1, inv_vol, s));
 
   hipLaunchKernelGGL(k_cg_init, dim3(L.grid_vec, nE), dim3(kBlock), 0, s, (const double2*)ahat,
-                     (const double*)L.E3, g, L.x, L.r, L.p, L.part_rz, L.part_zz);
+                     (const double*)L.E3, g, L.x, L.r, L.p, L.part_rz, L.part_zz, mk);
   LRFG_LAUNCHED();
   hipLaunchKernelGGL(k_cg_init2, dim3(nE), dim3(kBlock), 0, s, L.st, L.done, (const double*)L.part_rz,
                      (const double*)L.part_zz, L.grid_vec, (const double*)L.floor_abs);
@@ -1198,11 +1282,11 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
       ProfScope ps_("div_axis1", s);
       if (two1) {
         LRFG_TRY(launch3_div((const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, f1,
-                             (const int*)L.done, L.part_pq, nE, s, an));
+                             (const int*)L.done, L.part_pq, nE, s, an, mk));
       } else {
         hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(L.tiles1, nE), dim3(kBlock), shm1, s,
                            (const double2*)L.t, L.q, (const double2*)L.p, g, alpha0, d, inv_vol, L.T1, f1,
-                           (const int*)L.done, L.part_pq, an);
+                           (const int*)L.done, L.part_pq, an, mk);
         LRFG_LAUNCHED();
       }
     }
@@ -1400,11 +1484,11 @@ int full_op(int which, const int N[3], const FftPlan* p1, const FftPlan* p2, con
   LRFG_TRY(launch_fft_lines(t, 3LL * g.N1, g.N2, g.H, -1, f2, 1.0, s));
   if (two1) {
     LRFG_TRY(launch3_div((const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, f1, (const int*)done, part, 1, s,
-                         Aniso3{}));
+                         Aniso3{}, Mask3{}));
   } else {
     hipLaunchKernelGGL((G1 ? k_div_axis1<true> : k_div_axis1<false>), dim3(tiles1, 1), dim3(kBlock), shm1, s,
                        (const double2*)t, oh, uh, g, 0, 3, 1.0 / (double)g.R, T1, f1, (const int*)done, part,
-                       Aniso3{});
+                       Aniso3{}, Mask3{});
     LRFG_LAUNCHED();
   }
   return LRFG_OK;

@@ -106,7 +106,8 @@ bool same_problem(const lrfg_problem& x, const lrfg_problem& y) {
          x.max_iter == y.max_iter && x.solver == y.solver && x.precision == y.precision &&
          x.precond_terms == y.precond_terms && x.oversample == y.oversample && x.seed == y.seed &&
          x.coeff_rank == y.coeff_rank && x.flags == y.flags &&
-         std::memcmp(x.aniso, y.aniso, sizeof(x.aniso)) == 0 && x.rank_start == y.rank_start;
+         std::memcmp(x.aniso, y.aniso, sizeof(x.aniso)) == 0 && x.rank_start == y.rank_start &&
+         x.discretisation == y.discretisation;
 }
 
 bool same_batch_key(const Request& x, const Request& y) {

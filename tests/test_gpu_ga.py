@@ -1,0 +1,93 @@
+"""Fourier-Galerkin with exact integration (Ga, Sec. 2.2.3) on the GPU's
+double grid against the CPU oracle (oracle.fg_ga)."""
+import numpy as np
+import pytest
+
+import paper_1902_07455_amd as P
+import workloads as W
+from oracle import fg_ga as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(A, B):
+    return np.max(np.abs(A - B)) / np.max(np.abs(B))
+
+
+@pytest.mark.parametrize("shape,d,N,inside", [("square", 2, 15, 10.0), ("square", 2, 23, 10.0),
+                                              ("square", 3, 15, 10.0), ("ball", 3, 15, 100.0),
+                                              ("ball", 3, 23, 10.0), ("square", 2, 45, 0.1)])
+def test_ga_equals_oracle(dev, shape, d, N, inside):
+    """2N - 1 = 29, 45 (register passes), 89 (prime, generic passes)."""
+    size = 0.3
+    s = P.Solver(d=d, N=(N,) * d, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000)
+    r = s.solve(inclusion=dict(shape=shape, size=size, inside=inside, outside=1.0))
+    o = G.solve(G.Inclusion(shape, size, inside, 1.0), [N] * d, tol=1e-12, max_iter=3000)
+    assert r.rc == 0
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+    assert abs(int(r.iters.max()) - max(o.iters)) <= 2
+
+
+def test_ga_nonsquare_grid_and_general_E(dev):
+    N = (9, 15, 11)
+    inc = dict(shape="square", size=0.25, inside=5.0, outside=1.0)
+    E = np.array([[1.0, -0.5, 0.3], [0.2, 1.0, 0.7]])
+    s = P.Solver(d=3, N=N, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000, max_nE=3)
+    A = s.solve(inclusion=inc).A_H
+    G2 = s.solve(inclusion=inc, E=E).A_H
+    o = G.solve(G.Inclusion("square", 0.25, 5.0, 1.0), list(N), tol=1e-12, max_iter=3000)
+    assert _rel(A, o.A_H) <= 1e-10
+    assert _rel(G2, E @ A @ E.T) <= 1e-10
+
+
+def test_ga_with_anisotropy(dev):
+    """Ga with the constant B of Sec. 4.4: B is integrated exactly too."""
+    N = 15
+    B = W.anisotropy(3)
+    s = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000, aniso=B)
+    r = s.solve(inclusion=dict(shape="ball", size=0.3, inside=10.0, outside=1.0))
+    # oracle: Ga of the matrix coefficient a I + B, from the same double-grid
+    # coefficient (a constant B only adds B at the zero frequency)
+    from oracle import fg_tensor as FT
+    inc = G.Inclusion("ball", 0.3, 10.0, 1.0)
+    AM = G.coefficient_on_double_grid(inc, [N] * 3)
+    AT = FT.isotropic_plus_constant(AM, B)
+    Es = [np.eye(3)[i] for i in range(3)]
+    uhs = []
+    for E in Es:
+        bh = -G.fg.div_hat([G.restrict(G.fg.fwd(sum(AT[al, be] * E[be] for be in range(3))), [N] * 3)
+                           for al in range(3)])
+        op = lambda v: G.fg.div_hat([G.restrict(G.fg.fwd(h), [N] * 3) for h in FT.material_law(
+            AT, [G.fg.inv(G.pad(gh, AM.shape)) for gh in G.fg.grad_hat(v)])])
+        uh, _, _ = FT.pcg(op, bh, 1e-12, 3000, 0.0)
+        uhs.append(uh)
+    fields = []
+    for E, uh in zip(Es, uhs):
+        g = [G.fg.inv(G.pad(gh, AM.shape)) for gh in G.fg.grad_hat(uh)]
+        fields.append([E[a] + g[a] for a in range(3)])
+    Ao = np.array([[np.mean(sum(f * e for f, e in zip(FT.material_law(AT, fields[i]), fields[j])))
+                    for j in range(3)] for i in range(3)])
+    assert _rel(r.A_H, Ao) <= 1e-10
+
+
+def test_ga_upper_bound_decreasing_in_N(dev):
+    """Nested trial spaces: the Ga a_H falls as N grows (Galerkin minimum)."""
+    inc = dict(shape="ball", size=0.3, inside=10.0, outside=1.0)
+    prev = None
+    for N in (9, 15, 23):
+        r = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12,
+                     max_iter=3000).solve(inclusion=inc)
+        a = r.A_H[0, 0]
+        if prev is not None:
+            assert a < prev + 1e-12
+        prev = a
+
+
+def test_ga_rejects_bad_inclusions(dev):
+    s = P.Solver(d=2, N=(15, 15), format="full", discretisation="ga", solver_tol=1e-8, max_iter=100)
+    with pytest.raises(Exception):
+        s.solve(inclusion=dict(shape="ball", size=0.3, inside=10.0, outside=1.0))   # the ball is 3D
+    with pytest.raises(Exception):
+        s.solve(inclusion=dict(shape="square", size=0.6, inside=10.0, outside=1.0))  # size beyond 1/2
+    with pytest.raises(Exception):
+        s.solve(full=np.ones((15, 15)))                                              # Ga takes inclusions
