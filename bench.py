@@ -28,8 +28,9 @@ rank 9: TT, Tucker, mixed precision), `crossover` (the smooth coefficient
 at larger grids), `anisotropic` (the anisotropic materials a I + B of
 Sec. 4.4: the smooth coefficient at 135^3 and at the crossover grids, and
 the 243^3 ball), `rank_adaptive` (one rank-adaptive TT solve of the ball,
-caps 57 then the headline cap), `serving` and `cpu_baseline` (the oracle on
-the host).
+caps 57 then the headline cap), `ga` (Galerkin with exact integration on
+the double grid, Sec. 2.2.3: the ball at N = 63 and 203, full grid),
+`serving` and `cpu_baseline` (the oracle on the host).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--crossover 405,729] [--no-crossover] [--no-aniso] [--serve-requests R]
@@ -687,6 +688,75 @@ def aniso_leg(args, dev, ball_wl=None):
     return out
 
 
+def ga_leg(args, dev):
+    """Fourier-Galerkin with exact integration (Sec. 2.2.3) on the full grid:
+    the ball |x| < 0.3 of contrast 100 through the double grid 2N - 1, at
+    N = 63 and 203 (double grids 125 and 405, both 3^a 5^b), each at the
+    loosest PCG tolerance within 1e-6 of its own 1e-10 Ga reference; the
+    per-pass roofline at N = 203 and the Ga oracle timed at N = 63."""
+    import torch
+
+    import paper_1902_07455_amd as P
+    inc = dict(shape="ball", size=0.3, inside=100.0, outside=1.0)
+    rows = []
+    for N in (63, 203):
+        M = 2 * N - 1
+        log(f"Ga N={N} (double grid {M})")
+
+        def solver(tol):
+            return P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=tol, max_iter=3000,
+                            device=dev)
+
+        s = solver(1e-10)
+        A_ref = s.solve(inclusion=inc).A_H
+        s.close()
+        tol_ok, sweep = None, []
+        for tol in FULL_TOLS:
+            s = solver(tol)
+            r = s.solve(inclusion=inc)
+            s.close()
+            e = rel_err(r.A_H, A_ref)
+            sweep.append([tol, e, int(r.iters.max())])
+            if e <= TARGET_ERR:
+                tol_ok = tol
+                break
+        row = {"N": N, "double_grid": M, "a_H_ref": float(A_ref[0, 0]), "sweep": sweep}
+        if tol_ok is not None:
+            s = solver(tol_ok)
+            sec, lat, r = timed(lambda: s.solve(inclusion=inc), 5, 1)
+            row.update({"solver_tol": tol_ok, "iters": int(r.iters.max()), "A_H_rel_err": rel_err(r.A_H, A_ref),
+                        "ms_per_solve": round(1e3 * sec / 5, 3), "solves_per_s": round(5 / sec, 3)})
+            if N == 203:
+                kern = full_grid_kernels(lambda: s.solve(inclusion=inc), M, 3, 1)
+                longest = max(kern, key=lambda k: kern[k]["avg_us"])
+                row["roofline"] = {"bound": "hbm", "kernel": f"{longest} (longest pass, double grid {M}^3)",
+                                   "achieved": kern[longest]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": kern[longest]["frac"], "kernels": kern}
+            s.close()
+        if N == 63 and not getattr(args, "no_cpu", False):
+            from oracle import fg, fg_ga
+            gi = fg_ga.Inclusion("ball", 0.3, 100.0, 1.0)
+            fg_ga.solve(gi, [N] * 3, tol=1e-30, max_iter=1)
+
+            def med(k):
+                ts = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    fg_ga.solve(gi, [N] * 3, tol=1e-30, max_iter=k)
+                    ts.append(time.perf_counter() - t0)
+                return float(np.median(ts))
+
+            t1, t2 = med(1), med(2)
+            n_it = row.get("iters", 1)
+            est = t1 + (n_it - 1) * (t2 - t1)
+            row["cpu_baseline"] = {"value": round(1.0 / est, 5), "unit": "A_H solves/s", "cores": fg.FFT_WORKERS,
+                                   "kind": "oracle", "sample": f"oracle.fg_ga on the ball at N={N} (double grid "
+                                   f"{M}), 1 and 2 PCG iterations ({t1:.2f} s, {t2:.2f} s), extrapolated to {n_it}"}
+        rows.append(row)
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(a_np, N, n_iters):
     """The oracle (oracle.fg, FFTs on every host core) on the headline
     workload: a bounded sample of one and of two PCG iterations of all three
@@ -729,6 +799,9 @@ def main(argv=None):
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic (a I + B) legs")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the rank-adaptive TT solve of the ball")
+    ap.add_argument("--no-ga", action="store_true", help="skip the Ga (exact integration) legs")
+    ap.add_argument("--ga-only", action="store_true",
+                    help="run only the Ga legs and print their JSON (profiling; no benchmark line)")
     ap.add_argument("--aniso-only", action="store_true",
                     help="run only the anisotropic legs and print their JSON (profiling; no benchmark line)")
     ap.add_argument("--full-tol", type=float, default=None,
@@ -764,6 +837,10 @@ def main(argv=None):
         # the anisotropic legs alone (for profiling them); not the benchmark line
         print(json.dumps({"anisotropic": aniso_leg(args, dev)}), flush=True)
         return 0
+    if args.ga_only:
+        # the Ga legs alone (for profiling them); not the benchmark line
+        print(json.dumps({"ga": ga_leg(args, dev)}), flush=True)
+        return 0
     wl, A_ref, value, ttot, tlat, tt, full, roofline, latency_bound, ref_vs_oracle = ball_leg(args, dev)
     out = {
         "metric": "A_H solves/sec at 1e-6 rel. err (TT vs full-FFT, same GPU); p50/p99 latency",
@@ -795,6 +872,8 @@ def main(argv=None):
     ball_np, ball_N = wl.a_np, wl.N
     if not args.no_aniso:
         out["anisotropic"] = aniso_leg(args, dev, wl)
+    if not args.no_ga:
+        out["ga"] = ga_leg(args, dev)
     del wl
     torch.cuda.empty_cache()
     if not args.no_smooth:
