@@ -30,7 +30,9 @@ Sec. 4.4: the smooth coefficient at 135^3 and at the crossover grids, and
 the 243^3 ball), `rank_adaptive` (one rank-adaptive TT solve of the ball,
 caps 57 then the headline cap), `ga` (Galerkin with exact integration on
 the double grid, Sec. 2.2.3: the ball at N = 63 and 203, full grid),
-`serving` and `cpu_baseline` (the oracle on the host).
+`material_S` (the paper's stochastic material S, TT rank 10, at 135^3,
+243^3 and 729^3, isotropic and with B), `serving` and `cpu_baseline` (the oracle on the
+host).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--crossover 405,729] [--no-crossover] [--no-aniso] [--serve-requests R]
@@ -757,6 +759,90 @@ def ga_leg(args, dev):
     return rows
 
 
+def material_s_leg(args, dev):
+    """The paper's stochastic material S (Sec. 4.1, eq. shape_fun2: the
+    exponential of 26 low Fourier modes, scaled to [1, 10]), compressed to TT
+    rank 10 as in the paper; the full grid solves the compressed field, as
+    the paper did.  N = 135, 243 and 729, isotropic and with the B of Sec. 4.4:
+    the full grid at its loosest PCG tolerance within 1e-6 of the 1e-10
+    full-grid reference, TT at the fastest (rank cap, solver tolerance) pair
+    within it (the smallest cap is not the fastest here: at cap 8 the
+    isotropic field needs many more iterations)."""
+    import torch
+
+    import paper_1902_07455_amd as P
+    import workloads as W
+    rows = []
+    for N in (135, 243, 729):
+        a0 = torch.from_numpy(W.material_s(N, 3, seed=0)).to(dev)
+        cores, kept = P.compress_tt(a0, cap=10, tol=0.0, seed=2)
+        k1, k2 = kept
+        tt = [cores[0][:, :, :k1].contiguous(), cores[1][:k1, :, :k2].contiguous(), cores[2][:k2].contiguous()]
+        full = torch.einsum("ia,ajb,bk->ijk", tt[0][0], tt[1], tt[2][:, :, 0]).contiguous()
+        cerr = float(torch.linalg.norm(full - a0) / torch.linalg.norm(a0))
+        del a0
+        for aniso in (None, W.anisotropy(3)):
+            tag = "S" if aniso is None else "S + B"
+            log(f"material {tag} N={N}")
+
+            def fsolver(tol):
+                return P.Solver(d=3, N=(N,) * 3, format="full", solver_tol=tol, max_iter=2000, device=dev,
+                                aniso=aniso)
+
+            def tsolver(cap, tol):
+                return P.Solver(d=3, N=(N,) * 3, format="tt", rank_cap=cap, solver_tol=tol, max_iter=150,
+                                coeff_rank=max(k1, k2), device=dev, aniso=aniso)
+
+            s = fsolver(1e-10)
+            A_ref = s.solve(full=full).A_H
+            s.close()
+            row = {"N": N, "material": tag, "coeff_tt_ranks": [1, k1, k2, 1], "coeff_rel_err": cerr}
+            ftol = None
+            for tol in FULL_TOLS:
+                s = fsolver(tol)
+                r = s.solve(full=full)
+                s.close()
+                if rel_err(r.A_H, A_ref) <= TARGET_ERR:
+                    ftol = tol
+                    break
+            if ftol is not None:
+                s = fsolver(ftol)
+                sec, _, r = timed(lambda: s.solve(full=full), 5, 1)
+                s.close()
+                row["full_fft"] = {"solver_tol": ftol, "iters": int(r.iters.max()), "A_H_rel_err": rel_err(r.A_H, A_ref),
+                                   "ms_per_solve": round(1e3 * sec / 5, 3)}
+            # the fastest (rank cap, solver tol) within the target: for each cap
+            # the loosest tolerance that reaches it, each timed once (warm)
+            tcap, ttol, tbest, sweep = None, None, None, []
+            for cap in (8, 12, 16, 24):
+                for tol in (1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6):
+                    s = tsolver(cap, tol)
+                    s.solve(tt=tt)
+                    t0 = time.perf_counter()
+                    r = s.solve(tt=tt)
+                    ms = 1e3 * (time.perf_counter() - t0)
+                    s.close()
+                    e = rel_err(r.A_H, A_ref)
+                    sweep.append([cap, tol, e, round(ms, 2)])
+                    if e <= TARGET_ERR:
+                        if tbest is None or ms < tbest:
+                            tcap, ttol, tbest = cap, tol, ms
+                        break
+            row["tt_sweep"] = sweep
+            if ttol is not None:
+                s = tsolver(tcap, ttol)
+                sec, _, r = timed(lambda: s.solve(tt=tt), 5, 1)
+                s.close()
+                row["tt"] = {"rank_cap": tcap, "solver_tol": ttol, "iters": r.iters.tolist(),
+                             "A_H_rel_err": rel_err(r.A_H, A_ref), "ms_per_solve": round(1e3 * sec / 5, 3)}
+                if "full_fft" in row:
+                    row["tt_speedup"] = round(row["full_fft"]["ms_per_solve"] / row["tt"]["ms_per_solve"], 3)
+            rows.append(row)
+        del full, tt, cores
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(a_np, N, n_iters):
     """The oracle (oracle.fg, FFTs on every host core) on the headline
     workload: a bounded sample of one and of two PCG iterations of all three
@@ -800,6 +886,9 @@ def main(argv=None):
     ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic (a I + B) legs")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the rank-adaptive TT solve of the ball")
     ap.add_argument("--no-ga", action="store_true", help="skip the Ga (exact integration) legs")
+    ap.add_argument("--no-material-s", action="store_true", help="skip the material-S legs")
+    ap.add_argument("--s-only", action="store_true",
+                    help="run only the material-S legs and print their JSON (no benchmark line)")
     ap.add_argument("--ga-only", action="store_true",
                     help="run only the Ga legs and print their JSON (profiling; no benchmark line)")
     ap.add_argument("--aniso-only", action="store_true",
@@ -836,6 +925,9 @@ def main(argv=None):
     if args.aniso_only:
         # the anisotropic legs alone (for profiling them); not the benchmark line
         print(json.dumps({"anisotropic": aniso_leg(args, dev)}), flush=True)
+        return 0
+    if args.s_only:
+        print(json.dumps({"material_S": material_s_leg(args, dev)}), flush=True)
         return 0
     if args.ga_only:
         # the Ga legs alone (for profiling them); not the benchmark line
@@ -874,6 +966,8 @@ def main(argv=None):
         out["anisotropic"] = aniso_leg(args, dev, wl)
     if not args.no_ga:
         out["ga"] = ga_leg(args, dev)
+    if not args.no_material_s:
+        out["material_S"] = material_s_leg(args, dev)
     del wl
     torch.cuda.empty_cache()
     if not args.no_smooth:

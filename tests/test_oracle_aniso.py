@@ -153,3 +153,28 @@ def test_zero_B_reduces_to_the_scalar_oracle():
     a = W.random_positive_coeff(9, 3, 7)
     A = FT.isotropic_plus_constant(a, np.zeros((3, 3)))
     assert np.allclose(FT.solve(A, tol=1e-13).A_H, fg.solve(a, tol=1e-13).A_H, atol=1e-12)
+
+
+# ---------------------------------------------------------------- material S
+@pytest.mark.parametrize("d,n,k2", [(2, 20, {1, 2, 4, 5}), (3, 26, {1, 2, 3})])
+def test_material_s_modes(d, n, k2):
+    """Sec. 4.1: 20 modes in 2D and 26 in 3D, the lowest frequencies (cos and
+    sin of one k per pair +-k), coefficients in [-0.5, 0.5]."""
+    p = W.material_s_params(d, seed=3)
+    assert len(p.c) == n and np.all(np.abs(p.c) <= 0.5)
+    assert {int(k @ k) for k in p.ks} == k2
+    pairs = {(tuple(k), int(t)) for k, t in zip(p.ks, p.kinds)}
+    assert len(pairs) == n                                   # no mode twice
+    assert all(tuple(-k) not in {tuple(q) for q in p.ks} for k in p.ks)
+
+
+def test_material_s_range_and_periodicity():
+    a = W.material_s(27, 3, seed=0)
+    assert np.isclose(a.min(), 1.0) and np.isclose(a.max(), 10.0)
+    # the exponent is a trigonometric polynomial of degree 1 per axis and
+    # |k|^2 <= 3: log a has no Fourier content beyond it
+    la = np.log(a)
+    spec = np.fft.fftn(la) / la.size
+    k = np.fft.fftfreq(27, d=1 / 27)
+    K2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+    assert np.max(np.abs(spec[K2 > 3])) < 1e-12

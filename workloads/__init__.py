@@ -23,7 +23,7 @@ __all__ = [
     "grid_points", "CPCoeff", "square_coeff", "cube_coeff", "ball_coeff",
     "laminate_coeff", "constant_coeff", "smooth_params", "smooth_cp",
     "smooth_coeff", "random_positive_coeff", "random_cp", "random_tt",
-    "ServingRequest", "serving_requests", "anisotropy",
+    "ServingRequest", "serving_requests", "anisotropy", "MaterialS", "material_s_params", "material_s",
 ]
 
 
@@ -132,6 +132,55 @@ def laminate_coeff(N: int, d: int, profile: np.ndarray, axis: int = 0) -> np.nda
 
 def constant_coeff(N: int, d: int, value: float) -> np.ndarray:
     return np.full((N,) * d, float(value))
+
+
+@dataclasses.dataclass
+class MaterialS:
+    """Parameters of one sample of the paper's stochastic material S."""
+    ks: np.ndarray       # (n, d) integer frequency of each real mode
+    kinds: np.ndarray    # (n,) 0: cos(2 pi k.x), 1: sin(2 pi k.x)
+    c: np.ndarray        # (n,) coefficients ~ U(-0.5, 0.5)
+
+
+def material_s_params(d: int, seed: int = 0) -> MaterialS:
+    """Sec. 4.1, eq. shape_fun2: the leading modes of a Karhunen-Loeve
+    expansion of a squared-exponential covariance on the periodic cell are
+    the real Fourier modes of the lowest frequencies; 20 modes in 2D and 26
+    in 3D are exactly cos and sin of one k of each pair +-k with |k|^2 <= 5
+    (2D) or |k|^2 <= 3 (3D).  Modes in order of |k|^2, then k
+    lexicographically (first nonzero component positive), cos before sin;
+    default_rng(seed) draws the n coefficients c ~ U(-0.5, 0.5) in that
+    order."""
+    kmax2 = {2: 5, 3: 3}[d]
+    r = int(math.isqrt(kmax2))
+    ks = []
+    for k in np.ndindex(*(2 * r + 1,) * d):
+        k = np.array(k) - r
+        nz = k[np.nonzero(k)[0]]
+        if nz.size == 0 or nz[0] < 0 or int(k @ k) > kmax2:
+            continue
+        ks.append(k)
+    ks.sort(key=lambda k: (int(k @ k), tuple(k)))
+    ks = np.array([k for k in ks for _ in (0, 1)])
+    kinds = np.tile([0, 1], len(ks) // 2)
+    c = np.random.default_rng(seed).uniform(-0.5, 0.5, len(ks))
+    return MaterialS(ks, kinds, c)
+
+
+def material_s(N: int, d: int, seed: int = 0, amin: float = 1.0, amax: float = 10.0) -> np.ndarray:
+    """Nodal values of a(x) = exp(C + D sum_k c[k] phi_k(x)) (eq. shape_fun2),
+    C and D chosen so that the grid samples span [amin, amax] (the paper
+    scales the sample to [1, 10])."""
+    p = material_s_params(d, seed)
+    x = grid_points(N)
+    grids = np.meshgrid(*([x] * d), indexing="ij")
+    s = np.zeros((N,) * d)
+    for k, kind, c in zip(p.ks, p.kinds, p.c):
+        ph = 2.0 * np.pi * sum(int(k[a]) * grids[a] for a in range(d))
+        s += c * (np.cos(ph) if kind == 0 else np.sin(ph))
+    D = math.log(amax / amin) / (s.max() - s.min())
+    C = math.log(amin) - D * s.min()
+    return np.exp(C + D * s)
 
 
 def anisotropy(d: int) -> np.ndarray:
