@@ -775,7 +775,12 @@ def material_s_leg(args, dev):
     rows = []
     for N in (135, 243, 729):
         a0 = torch.from_numpy(W.material_s(N, 3, seed=0)).to(dev)
+        P.compress_tt(a0, cap=10, tol=0.0, seed=2)       # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         cores, kept = P.compress_tt(a0, cap=10, tol=0.0, seed=2)
+        torch.cuda.synchronize()
+        compress_ms = 1e3 * (time.perf_counter() - t0)
         k1, k2 = kept
         tt = [cores[0][:, :, :k1].contiguous(), cores[1][:k1, :, :k2].contiguous(), cores[2][:k2].contiguous()]
         full = torch.einsum("ia,ajb,bk->ijk", tt[0][0], tt[1], tt[2][:, :, 0]).contiguous()
@@ -796,7 +801,8 @@ def material_s_leg(args, dev):
             s = fsolver(1e-10)
             A_ref = s.solve(full=full).A_H
             s.close()
-            row = {"N": N, "material": tag, "coeff_tt_ranks": [1, k1, k2, 1], "coeff_rel_err": cerr}
+            row = {"N": N, "material": tag, "coeff_tt_ranks": [1, k1, k2, 1], "coeff_rel_err": cerr,
+                   "compress_ms": round(compress_ms, 2)}
             ftol = None
             for tol in FULL_TOLS:
                 s = fsolver(tol)
