@@ -292,6 +292,9 @@ int lrfg_fft_lines(double* x, int outer, int N, int inner, int direction,
  *   op 0: s(k) = 2 pi i k                (spectral derivative, eq. grad_trig)
  *   op 1: s(k) = exp(-t k^2)             (heat kernel factor of the
  *                                         exponential-sum preconditioner)
+ *   op 2: s(k) = 1 for |k| <= t, else 0  (projection onto the trigonometric
+ *                                         polynomials of degree t: the
+ *                                         low-rank Ga's N-frequencies)
  * k the centred frequency.  This is the per-mode 1-D DFT the low-rank
  * formats apply to their factors (Sec. 3.1, Appendix A). */
 int lrfg_mode_op(double* x, int outer, int N, int inner, int op, double t,

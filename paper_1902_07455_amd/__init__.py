@@ -392,7 +392,8 @@ def fft_lines(x, outer: int, N: int, inner: int, direction: int, stream=None):
 
 def mode_op(x, outer: int, N: int, inner: int, op: int, t: float = 0.0, stream=None):
     """In-place real circulant along the middle index of a float64 CUDA
-    tensor [outer][N][inner]: op 0 derivative, op 1 heat kernel exp(-t k^2)."""
+    tensor [outer][N][inner]: op 0 derivative, op 1 heat kernel exp(-t k^2),
+    op 2 projection onto the frequencies |k| <= t."""
     L = lib()
     ws = _ws_tensor(L.lrfg_fft_workspace_bytes(N), x.device)
     check(L.lrfg_mode_op(C.c_void_p(x.data_ptr()), outer, N, inner, op, float(t),

@@ -158,8 +158,8 @@ int validate(const lrfg_problem* p) {
     return LRFG_EINVAL;
   }
   if (p->discretisation == LRFG_DISC_GA) {
-    if (p->format != LRFG_FORMAT_FULL) {
-      set_error("the Ga discretisation is built for the full grid");
+    if (p->format == LRFG_FORMAT_TUCKER || (p->format != LRFG_FORMAT_FULL && p->precision != LRFG_PREC_FP64)) {
+      set_error("the Ga discretisation is built for the full grid and the TT/CP formats in FP64");
       return LRFG_EUNSUPPORTED;
     }
     for (int i = 0; i < p->d; ++i)
@@ -256,15 +256,18 @@ int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
       return rc;
     }
   }
+  // low-rank Ga: the carriages live on the double grid 2N - 1
+  lrfg_problem pm = *p;
+  for (int i = 0; i < p->d; ++i) pm.N[i] = gridN(i);
   for (int i = 0; i < p->d; ++i) {
-    int rc = fft_plan_make(p->N[i], &pl->mode[i]);
+    int rc = fft_plan_make(pm.N[i], &pl->mode[i]);
     if (rc != LRFG_OK) {
       delete pl;
       return rc;
     }
   }
   if (p->format != LRFG_FORMAT_FULL) {
-    int rc = lowrank_plan_create(*p, pl->mode, &pl->lr);
+    int rc = lowrank_plan_create(pm, pl->mode, &pl->lr, p->discretisation == LRFG_DISC_GA ? p->N : nullptr);
     if (rc != LRFG_OK) {
       delete pl;
       return rc;
@@ -361,6 +364,10 @@ static int solve_impl(lrfg_plan* plan, const lrfg_coeff* a, int count, const dou
       }
       if (c.inclusion == LRFG_INCLUSION_BALL && p.d != 3) {
         set_error("coefficient %d: the ball inclusion is 3D", b);
+        return LRFG_EUNSUPPORTED;
+      }
+      if (c.inclusion == LRFG_INCLUSION_BALL && p.format != LRFG_FORMAT_FULL) {
+        set_error("coefficient %d: the low-rank Ga takes the square/cube (CP rank 2 on the double grid)", b);
         return LRFG_EUNSUPPORTED;
       }
       if (!(std::isfinite(c.incl_size) && c.incl_size > 0.0 && c.incl_size < 0.5)) {
@@ -576,7 +583,7 @@ int lrfg_fft_lines(double* x, int outer, int N, int inner, int direction, void* 
 int lrfg_mode_op(double* x, int outer, int N, int inner, int op, double t, void* d_ws, size_t ws_bytes,
                  void* stream) {
   clear_error();
-  if (x == nullptr || outer < 0 || inner < 1 || (op != 0 && op != 1) || !std::isfinite(t)) {
+  if (x == nullptr || outer < 0 || inner < 1 || (op < 0 || op > 2) || !std::isfinite(t)) {
     set_error("bad arguments");
     return LRFG_EINVAL;
   }

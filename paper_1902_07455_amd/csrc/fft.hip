@@ -257,7 +257,9 @@ __device__ inline long long pair_first(long long p, long long F, long long P, bo
 
 // Real circulant along the mode index: two real fibres packed into one
 // complex line (the operator is real, so it acts on real and imaginary
-// parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2); result times mult.
+// parts separately).  op 0: 2 pi i k; op 1: exp(-t k^2); op 2: 1 for |k| <= t,
+// else 0 (the projection onto the trigonometric polynomials of degree t);
+// result times mult.
 // Reads xin, writes x (the same array for in-place use).  Fibres are paired
 // within groups of F (one system).
 template <bool GEN>
@@ -303,8 +305,9 @@ __global__ __launch_bounds__(kFftBlock) void k_mode_op(const double* xin, double
   // one factor per mode index, applied down the T lines of the tile
   for (int n = threadIdx.x; n < N; n += blockDim.x) {
     const int k = freq_of(n, N);
-    const double fk = op == 0 ? mult * 2.0 * kPi * (double)k / (double)N
-                              : mult * exp(-tparam * (double)k * (double)k) / (double)N;
+    const double fk = op == 0   ? mult * 2.0 * kPi * (double)k / (double)N
+                      : op == 1 ? mult * exp(-tparam * (double)k * (double)k) / (double)N
+                                : ((double)abs(k) <= tparam ? mult / (double)N : 0.0);
     for (int t = 0; t < T; ++t) {
       const double2 w = sm[t * N + n];
       sm[t * N + n] = op == 0 ? cmul_i(w, fk) : cscale(w, fk);

@@ -26,7 +26,9 @@ int tt_coeff_check(int d, const int N[3], const int rk[4], const double* const* 
 int tucker_coeff_check(const int N[3], const int r[3], const double* core, const double* const* U, double* W,
                        void* scratch, hipStream_t s, double* min_out, long long* nonfinite_out);
 
-int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out);
+// ga_N: Ga (Sec. 2.2.3) with p.N the double grid 2 ga_N - 1 (NULL: GaNi).
+int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out,
+                        const int* ga_N = nullptr);
 void lowrank_plan_destroy(LowRankPlan* lr);
 // Systems in one solve (microstructures x fields) are limited to this.
 constexpr int kMaxSystems = 256;

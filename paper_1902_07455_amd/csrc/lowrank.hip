@@ -49,6 +49,10 @@ struct LowRankPlan {
   int over = 10;
   bool aniso = false;        // constant anisotropic part B present (Sec. 4.4)
   double B[3][3] = {};
+  // Ga (exact integration, Sec. 2.2.3): N above is the double grid 2 ga_N - 1
+  // and every corrector-side train is kept on the frequencies of ga_N
+  // (0: GaNi)
+  int ga_N[3] = {0, 0, 0};
 };
 
 namespace {
@@ -226,7 +230,21 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
     C.xa = tt_alloc(ar, d, pl->N, rc, nE);
     C.xbest = tt_alloc(ar, d, pl->N, rc, nE);
   }
-  C.h = tt_alloc(ar, d, pl->N, rc, d * nE);
+  // material truncation ranks: the corrector's, except under Ga, where the
+  // product a (.) D v on the double grid leaves T_N and its projection back
+  // is taken after the truncation, so the truncation keeps the product's
+  // full rank r_a c (bounded by the unfoldings) and loses nothing
+  int rh[4] = {1, 1, 1, 1};
+  for (int j = 1; j < d; ++j) rh[j] = rc[j];
+  if (pl->ga_N[0] > 0) {
+    if (d == 3) {
+      rh[1] = std::min(ra[1] * rc[1], std::min(pl->N[0], pl->N[1] * pl->N[2]));
+      rh[2] = std::min(ra[2] * rc[2], std::min(pl->N[2], pl->N[0] * pl->N[1]));
+    } else {
+      rh[1] = std::min(ra[1] * rc[1], std::min(pl->N[0], pl->N[1]));
+    }
+  }
+  C.h = tt_alloc(ar, d, pl->N, rh, d * nE);
   int rkr[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) rkr[j] = ra[j] * rc[j];
   if (d == 3) {
@@ -246,11 +264,11 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   // block sums: d material terms, M preconditioner terms, 2 update terms, d coefficient terms
   int cap[4] = {1, 1, 1, 1};
   for (int j = 1; j < d; ++j) {
-    int m = d * rc[j];
+    int m = d * rh[j];
     if (pl->M * rc[j] > m) m = pl->M * rc[j];
     if (2 * rc[j] > m) m = 2 * rc[j];
     if (d * ra[j] > m) m = d * ra[j];
-    if (pl->aniso && (d + 3) * rc[j] > m) m = (d + 3) * rc[j];  // material terms + K_B v
+    if (pl->aniso && d * rh[j] + 3 * rc[j] > m) m = d * rh[j] + 3 * rc[j];  // material terms + K_B v
     cap[j] = m;
   }
   for (int j = 0; j < 4; ++j) C.comb_cap[j] = cap[j];
@@ -259,7 +277,9 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   for (int j = 0; j < d; ++j) maxcore = std::max(maxcore, (long long)rc[j] * pl->N[j] * rc[j + 1]);
   C.gcore = ar.take<double>((size_t)maxcore * nE);
   C.gmid = d == 3 ? ar.take<double>((size_t)maxcore * d * nE) : nullptr;
-  for (int al = 0; al < d; ++al) C.hcore[al] = ar.take<double>((size_t)maxcore * nE);
+  long long maxh = 0;
+  for (int j = 0; j < d; ++j) maxh = std::max(maxh, (long long)rh[j] * pl->N[j] * rh[j + 1]);
+  for (int al = 0; al < d; ++al) C.hcore[al] = ar.take<double>((size_t)maxh * nE);
   C.pcore_stride = maxcore * nE;
   C.pcore = ar.take<double>((size_t)C.pcore_stride * pl->M * d);
   long long acmax = 0;
@@ -276,7 +296,7 @@ int carve_ctx(Arena& ar, LowRankPlan* pl, int nE, int na, Ctx& C) {
   R.seed = pl->p.seed;
   for (int j = 1; j < d; ++j) {
     R.Rmax[j - 1] = std::max(cap[j], rkr[j]);
-    R.Lmax[j - 1] = rc[j] + pl->over;
+    R.Lmax[j - 1] = std::max(rc[j], rh[j]) + pl->over;
   }
   if (d == 3) {
     // the material truncation takes the middle carriage as a (.) D v
@@ -375,6 +395,26 @@ int aniso_blocks(Ctx& C, const TTB& v, int n, const int o[4], TTBlock blk[3][kMa
   return LRFG_OK;
 }
 
+// Ga: the trains' mode fibres projected onto the trigonometric polynomials
+// of the corrector's grid (|k_j| <= (N_j - 1)/2 on the double grid), in place
+int ga_project(Ctx& C, TTB& x, int n) {
+  for (int j = 0; j < C.d; ++j) {
+    TTB y = x;
+    LRFG_TRY(tt_mode_apply(x, y, j, 2, (double)((C.pl->ga_N[j] - 1) / 2), 1.0, C.f[j], n, C.s));
+  }
+  return LRFG_OK;
+}
+
+// T(in) into out; under Ga the result is projected onto T_N's frequencies
+// again: the Gram-based orthonormalisation works to about sqrt(eps), and the
+// components it leaves outside T_N are invisible to the projected operator
+// but not to the double-grid energy form, so they must not accumulate
+int round_s(Ctx& C, const TTB& in, TTB& out, double tol, int batch, const KrMid* mid = nullptr, int nblk = 1) {
+  LRFG_TRY(C.rd.round(in, out, tol, C.s, batch, mid, nblk));
+  if (C.pl->ga_N[0] > 0) LRFG_TRY(ga_project(C, out, batch));
+  return LRFG_OK;
+}
+
 // W = K_B v for n trains, into C.comb (ranks 3 r)
 int aniso_train(Ctx& C, const TTB& v, int n, TTB& W) {
   TTBlock blk[3][kMaxBlk];
@@ -435,14 +475,18 @@ int apply_K(Ctx& C, const TTB& v, TTB& out) {
     hd[al] = ha[al];
     hd[al].c[al] = C.hcore[al];
     LRFG_TRY(tt_mode_apply(ha[al], hd[al], al, 0, 0.0, -1.0, C.f[al], nE, C.s));
+    // Ga: the test functions are T_N's, so the material terms are projected
+    // back onto its frequencies before the sum's truncation (I* of eq.
+    // ls_Ga_fourier)
+    if (C.pl->ga_N[0] > 0) LRFG_TRY(ga_project(C, hd[al], nE));
     terms[al] = TTTerm{&hd[al], nullptr, 1.0};
   }
   TTB comb = C.comb;
   if (!C.pl->aniso) {
-    for (int j = 1; j < d; ++j) comb.r[j] = d * v.r[j];
+    for (int j = 1; j < d; ++j) comb.r[j] = d * C.h.r[j];
     for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
     LRFG_TRY(tt_sum(terms, d, comb, nE, C.s));
-    return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+    return round_s(C, comb, out, C.pl->p.trunc_tol, nE);
   }
   // with the anisotropic part: the d material terms (block diagonal) and
   // K_B v (ranks 3 r, exact) in one sum before the truncation
@@ -469,7 +513,7 @@ int apply_K(Ctx& C, const TTB& v, TTB& out) {
   for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
   const TTBlock* bp[3] = {blk[0], blk[1], blk[2]};
   LRFG_TRY(tt_blocks(bp, nb, comb, nE, C.s));
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE);
+  return round_s(C, comb, out, C.pl->p.trunc_tol, nE);
 }
 
 // out = T(P~^-1 v), P~^-1 = (1/4 pi^2) sum_m w_m prod_alpha H_{m,alpha}:
@@ -494,7 +538,7 @@ int apply_P(Ctx& C, const TTB& v, TTB& out) {
                                    j > 0, j < d - 1, M, C.pl->t.data(), j == 0 ? sc.data() : one.data(), C.f[j],
                                    C.s));
   }
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, nE, nullptr, blocks ? M : 1);
+  return round_s(C, comb, out, C.pl->p.trunc_tol, nE, nullptr, blocks ? M : 1);
 }
 
 // [x; r] <- T([x; r] + coef2 [p; q]) as one truncation of 2 nE trains
@@ -504,7 +548,7 @@ int update_xr(Ctx& C) {
   for (int j = 1; j < C.d; ++j) comb.r[j] = 2 * C.xr.r[j];
   for (int j = 0; j < C.d; ++j) comb.s[j] = comb.size(j);
   LRFG_TRY(tt_sum(t, 2, comb, 2 * C.nE, C.s));
-  return C.rd.round(comb, C.xr, C.pl->p.trunc_tol, C.s, 2 * C.nE);
+  return round_s(C, comb, C.xr, C.pl->p.trunc_tol, 2 * C.nE);
 }
 
 // out = T(x + cb y) for nE trains
@@ -514,7 +558,7 @@ int axpby(Ctx& C, const TTB& x, const TTB& y, const double* cb, TTB& out) {
   for (int j = 1; j < C.d; ++j) comb.r[j] = x.r[j] + y.r[j];
   for (int j = 0; j < C.d; ++j) comb.s[j] = comb.size(j);
   LRFG_TRY(tt_sum(t, 2, comb, C.nE, C.s));
-  return C.rd.round(comb, out, C.pl->p.trunc_tol, C.s, C.nE);
+  return round_s(C, comb, out, C.pl->p.trunc_tol, C.nE);
 }
 
 int dot(Ctx& C, const TTB& x, const TTB& y, double* out) { return tt_dot(x, y, out, C.dscr, C.nE, C.s); }
@@ -556,9 +600,11 @@ static void plan_ranks(LowRankPlan& pl) {
   }
 }
 
-int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out) {
+int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan** out, const int* ga_N) {
   LowRankPlan* pl = new LowRankPlan();
   pl->p = p;
+  if (ga_N != nullptr)
+    for (int j = 0; j < p.d; ++j) pl->ga_N[j] = ga_N[j];
   pl->d = p.d;
   for (int j = 0; j < p.d; ++j) {
     pl->N[j] = p.N[j];
@@ -570,6 +616,7 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
       if (pl->B[i][j] != 0.0) pl->aniso = true;
     }
   pl->ra = p.coeff_rank > 0 ? p.coeff_rank : 16;
+  if (pl->ga_N[0] > 0) pl->ra = 2;  // Ga's square/cube coefficient: CP rank 2 on the double grid
   pl->over = p.oversample > 0 ? p.oversample : 10;
   if (pl->ra > kMaxCoeffRank) {
     set_error("coeff_rank %d exceeds the supported %d", pl->ra, kMaxCoeffRank);
@@ -578,9 +625,11 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
   }
   plan_ranks(*pl);
   for (int j = 1; j < p.d; ++j) {
-    if (pl->c[j] + pl->over > kMaxEig) {
+    // under Ga the material truncation keeps ranks up to r_a c (see carve_ctx)
+    const int cj = pl->ga_N[0] > 0 ? std::min(pl->ra * pl->c[j], j == 1 ? p.N[0] : p.N[p.d - 1]) : pl->c[j];
+    if (cj + pl->over > kMaxEig) {
       // the sketch size bounds the small eigenproblems
-      int o = kMaxEig - pl->c[j];
+      int o = kMaxEig - cj;
       if (o < 0) {
         set_error("rank_cap %d exceeds the supported %d", p.rank_cap, kMaxEig);
         delete pl;
@@ -602,8 +651,12 @@ int lowrank_plan_create(const lrfg_problem& p, const FftPlan* mode, LowRankPlan*
       return LRFG_EUNSUPPORTED;
     }
   }
+  // the preconditioner's range: the corrector's frequencies (Ga: those of ga_N)
   double R = 0.0;
-  for (int j = 0; j < p.d; ++j) R += (double)((p.N[j] - 1) / 2) * ((p.N[j] - 1) / 2);
+  for (int j = 0; j < p.d; ++j) {
+    const int n = ga_N != nullptr ? ga_N[j] : p.N[j];
+    R += (double)((n - 1) / 2) * ((n - 1) / 2);
+  }
   expsum(R, p.precond_terms, &pl->M, &pl->t, &pl->w);
   *out = pl;
   return LRFG_OK;
@@ -710,6 +763,36 @@ int load_coeff(Ctx& C, const lrfg_coeff& ac, int e, int* rk) {
 
 }  // namespace
 
+// Ga's coefficient of a square/cube inclusion on the double grid as a CP
+// tensor of rank 2: A_M = vout + (vin - vout) prod_j chi_j, chi_j the Fourier
+// series of the 1-D indicator of |x| < size truncated to |m| <= N_j - 1
+// (coefficients 2 size at m = 0, sin(2 pi m size)/(pi m) otherwise) at the
+// double-grid points x_p = -1/2 + (p + 1/2)/M_j.
+struct GaCP {
+  std::vector<double> w, f[3];
+  lrfg_coeff c{};
+};
+static void ga_cp(const LowRankPlan* pl, const lrfg_coeff& ac, GaCP& g) {
+  const int d = pl->d;
+  g.w = {ac.incl_outside, ac.incl_inside - ac.incl_outside};
+  g.c = lrfg_coeff{};
+  g.c.on_device = 0;
+  g.c.rank = 2;
+  g.c.weights = g.w.data();
+  for (int j = 0; j < d; ++j) {
+    const int M = pl->N[j], N = pl->ga_N[j];
+    g.f[j].assign((size_t)2 * M, 1.0);
+    for (int p = 0; p < M; ++p) {
+      const double x = -0.5 + (p + 0.5) / M;
+      double chi = 2.0 * ac.incl_size;
+      for (int m = 1; m <= N - 1; ++m)
+        chi += 2.0 * std::sin(2.0 * kPi * m * ac.incl_size) / (kPi * m) * std::cos(2.0 * kPi * m * x);
+      g.f[j][(size_t)M + p] = chi;
+    }
+    g.c.factors[j] = g.f[j].data();
+  }
+}
+
 // Correctors kept on the host between the stages of a rank-adaptive solve:
 // nE trains of ranks r, carriage j of system e at core[j][e * size_j].
 struct HostTrains {
@@ -764,12 +847,23 @@ int solve_stage(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E,
   }
   // ---------------------------------------------------------------- coefficient trains
   int rk[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nB; ++b) LRFG_TRY(load_coeff(C, acs[b], na == 1 ? 0 : b * nEp, rk));
+  const bool ga = pl->ga_N[0] > 0;
+  std::vector<GaCP> gcp(ga ? nB : 0);
+  for (int b = 0; b < nB; ++b) {
+    if (ga) {
+      ga_cp(pl, acs[b], gcp[b]);
+      LRFG_TRY(load_coeff(C, gcp[b].c, na == 1 ? 0 : b * nEp, rk));
+    } else {
+      LRFG_TRY(load_coeff(C, acs[b], na == 1 ? 0 : b * nEp, rk));
+    }
+  }
   for (int j = 1; j < d; ++j) C.a.r[j] = rk[j];
   // admissibility (the coefficient must be positive and finite at every
   // grid point, as for the full grid): truncated or user-given factors can
   // undershoot, which would make the operator indefinite
-  for (int b = 0; b < nB; ++b) {
+  // (Ga's double-grid coefficient is a truncated Fourier series: it may dip
+  // below zero at the interface while the bilinear form stays positive)
+  for (int b = 0; b < nB && !ga; ++b) {
     const double* cores[3];
     for (int j = 0; j < d; ++j) cores[j] = C.a.c[j] + (long long)(na == 1 ? 0 : b * nEp) * C.a.s[j];
     double amin = 0.0;
@@ -814,7 +908,13 @@ int solve_stage(LowRankPlan* pl, const lrfg_coeff* acs, int nB, const double* E,
     for (int j = 1; j < d; ++j) comb.r[j] = d * C.a.r[j];
     for (int j = 0; j < d; ++j) comb.s[j] = comb.size(j);
     LRFG_TRY(tt_sum(terms, d, comb, nE, s));
-    LRFG_TRY(C.rd.round(comb, C.b, P.trunc_tol, s, nE));
+    if (ga) {
+      // Ga: the right-hand side's test functions are T_N's (I* of eq.
+      // ls_Ga_fourier), projected before the truncation
+      TTB cb = comb;
+      LRFG_TRY(ga_project(C, cb, nE));
+    }
+    LRFG_TRY(round_s(C, comb, C.b, P.trunc_tol, nE));
   }
   // scale for the zero-right-hand-side floor: rms(a) |E|, per coefficient train
   std::vector<double> a2(na, 0.0);

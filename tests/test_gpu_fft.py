@@ -61,3 +61,21 @@ def test_mode_heat_kernel(dev, N, tpar):
     k = np.fft.fftfreq(N, 1.0 / N).round()
     ref = np.fft.ifft(np.exp(-tpar * k ** 2)[None, :, None] * np.fft.fft(x, axis=1), axis=1).real
     assert np.max(np.abs(t.cpu().numpy() - ref)) <= 1e-13 * max(1.0, np.max(np.abs(x)))
+
+
+@pytest.mark.parametrize("N,K", [(29, 7), (45, 11), (17, 0), (89, 22), (243, 60)])
+def test_mode_low_pass(dev, N, K):
+    """op 2: the projection of each fibre onto the trigonometric polynomials
+    of degree K (frequencies |k| <= K kept, the rest zeroed)."""
+    import torch
+    rng = np.random.default_rng(11 + N)
+    outer, inner = 5, 7
+    x = rng.standard_normal((outer, N, inner))
+    t = torch.from_numpy(x.copy()).to(dev)
+    P.mode_op(t, outer, N, inner, 2, K)
+    torch.cuda.synchronize()
+    X = np.fft.fft(x, axis=1)
+    k = np.fft.fftfreq(N, d=1.0 / N)
+    X[:, np.abs(k) > K, :] = 0.0
+    ref = np.fft.ifft(X, axis=1).real
+    assert np.max(np.abs(t.cpu().numpy() - ref)) <= 1e-13 * max(1.0, np.max(np.abs(x))) * np.log2(N + 1)

@@ -91,3 +91,47 @@ def test_ga_rejects_bad_inclusions(dev):
         s.solve(inclusion=dict(shape="square", size=0.6, inside=10.0, outside=1.0))  # size beyond 1/2
     with pytest.raises(Exception):
         s.solve(full=np.ones((15, 15)))                                              # Ga takes inclusions
+
+
+# ---------------------------------------------------------------- low-rank Ga
+@pytest.mark.parametrize("fmt,d,N", [("tt", 3, 9), ("tt", 3, 15), ("tt", 2, 21), ("cp", 2, 21)])
+def test_lowrank_ga_untruncated_equals_oracle(dev, fmt, d, N):
+    """The TT solve on the double grid, every train kept on T_N's frequencies;
+    rank cap N (the dimension of T_N per axis): no truncation."""
+    s = P.Solver(d=d, N=(N,) * d, format=fmt, discretisation="ga", rank_cap=N, solver_tol=1e-12, max_iter=400,
+                 coeff_rank=2)
+    r = s.solve(inclusion=dict(shape="square", size=0.3, inside=10.0, outside=1.0))
+    o = G.solve(G.Inclusion("square", 0.3, 10.0, 1.0), [N] * d, tol=1e-12, max_iter=3000)
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+
+
+def test_lowrank_ga_truncated_upper_bound(dev):
+    """Truncated correctors in T_N: the exact Ga energy form bounds the Ga
+    A_H from above (Sec. 4.3's identity holds for any Galerkin space)."""
+    N = 21
+    o = G.solve(G.Inclusion("square", 0.3, 10.0, 1.0), [N] * 3, tol=1e-12, max_iter=3000).A_H
+    s = P.Solver(d=3, N=(N,) * 3, format="tt", discretisation="ga", rank_cap=6, solver_tol=1e-10, max_iter=150,
+                 coeff_rank=2)
+    r = s.solve(inclusion=dict(shape="square", size=0.3, inside=10.0, outside=1.0))
+    D = r.A_H - o
+    assert np.linalg.eigvalsh(0.5 * (D + D.T)).min() >= -1e-9 * np.max(np.abs(o))
+    assert _rel(r.A_H, o) < 0.1
+
+
+def test_lowrank_ga_with_anisotropy(dev):
+    """Low-rank Ga with B against the full-grid Ga with B (itself checked
+    against the oracle above)."""
+    N = 15
+    B = W.anisotropy(3)
+    inc = dict(shape="square", size=0.3, inside=10.0, outside=1.0)
+    f = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000,
+                 aniso=B).solve(inclusion=inc)
+    t = P.Solver(d=3, N=(N,) * 3, format="tt", discretisation="ga", rank_cap=N, solver_tol=1e-12, max_iter=400,
+                 coeff_rank=2, aniso=B).solve(inclusion=inc)
+    assert _rel(t.A_H, f.A_H) <= 1e-10
+
+
+def test_lowrank_ga_ball_unsupported(dev):
+    s = P.Solver(d=3, N=(9, 9, 9), format="tt", discretisation="ga", rank_cap=4, solver_tol=1e-6, max_iter=20)
+    with pytest.raises(Exception):
+        s.solve(inclusion=dict(shape="ball", size=0.3, inside=10.0, outside=1.0))
