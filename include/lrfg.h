@@ -102,12 +102,14 @@ typedef enum {
 typedef enum {
   LRFG_DISC_GANI = 0,       /* numerical integration on the grid (Sec. 2.2.2,
                                eq. ls_GaNi_fourier)                          */
-  LRFG_DISC_GA = 1          /* exact integration by the double grid 2N - 1
-                               (DoGIP, Sec. 2.2.3, eq. ls_Ga_fourier): the
+  LRFG_DISC_GA = 1          /* exact integration on a double grid of at
+                               least 2N - 1 points (lrfg_ga_double_grid;
+                               DoGIP, Sec. 2.2.3, eq. ls_Ga_fourier): the
                                coefficient's Fourier integrals up to |m| <= N-1
                                on the double grid, trial and test functions in
-                               T_N (every iterate masked to its frequencies);
-                               full grid only                                */
+                               T_N (every iterate masked to, every low-rank
+                               train projected onto, its frequencies); full
+                               grid and TT/CP in FP64                        */
 } lrfg_discretisation;
 
 /* Inclusion coefficients with closed-form Fourier integrals (Ga only). */
@@ -155,9 +157,11 @@ typedef struct {
                            solve at rank_cap.  Negative: LRFG_EINVAL; other
                            formats, precisions or solvers with rank_start >
                            0: LRFG_EUNSUPPORTED                            */
-  int discretisation;   /* lrfg_discretisation; LRFG_DISC_GA (full grid only)
-                           takes an inclusion coefficient (lrfg_coeff) and
-                           runs on the double grid 2N - 1                   */
+  int discretisation;   /* lrfg_discretisation; LRFG_DISC_GA (full grid,
+                           TT and CP) takes an inclusion coefficient
+                           (lrfg_coeff; the low-rank formats the square/cube
+                           only) and runs on the double grid
+                           lrfg_ga_double_grid(N)                           */
 } lrfg_problem;
 
 /* Coefficient a(x) > 0 (scalar isotropic A = a I).  For FULL, `full` holds
@@ -212,6 +216,15 @@ typedef struct lrfg_plan lrfg_plan;
 
 /* Version of this ABI (LRFG_ABI_VERSION). */
 int lrfg_abi_version(void);
+
+/* The double grid M that the Ga discretisation (Sec. 2.2.3) uses for N points
+ * per axis.  Products of two gradients of T_N carry frequencies |m| <= N - 1,
+ * so every odd grid of at least 2N - 1 points integrates the bilinear and
+ * energy forms exactly; the paper takes 2N - 1.  Returned: the smallest odd
+ * 3^a 5^b >= 2N - 1 (all transforms on the fast passes), or 2N - 1 when that
+ * exceeds 2048.  The solution is the same on any such grid, up to rounding.
+ * N must be odd and in [1, 1024] (else LRFG_EINVAL).  Host only. */
+int lrfg_ga_double_grid(int N);
 
 /* Static description of a status code. */
 const char* lrfg_status_string(int status);

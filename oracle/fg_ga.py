@@ -86,20 +86,33 @@ class Inclusion:
 
 
 def double_grid(N: Sequence[int]) -> List[int]:
+    """The paper's double grid 2N - 1: the smallest odd grid whose mean
+    integrates T_{2N-1} (the products of two gradients of T_N) exactly.  Any
+    odd M >= 2N - 1 does as well and gives the same system; `solve` takes
+    such an M as an option."""
     return [2 * n - 1 for n in N]
 
 
-def coefficient_on_double_grid(inc: Inclusion, N: Sequence[int]) -> np.ndarray:
+def coefficient_on_double_grid(inc: Inclusion, N: Sequence[int],
+                               M: Optional[Sequence[int]] = None) -> np.ndarray:
     """A_M: values at the M-grid points x_j = -1/2 + (j + 1/2)/M of the
-    Fourier series of the coefficient truncated to |m_alpha| <= N_alpha - 1."""
-    M = double_grid(N)
+    Fourier series of the coefficient truncated to |m_alpha| <= N_alpha - 1
+    (M odd, at least 2N - 1; default 2N - 1)."""
+    M = double_grid(N) if M is None else list(M)
     d = len(N)
+    for n, mm in zip(N, M):
+        if mm % 2 == 0 or mm < 2 * n - 1:
+            raise ValueError("the double grid must be odd and at least 2N - 1")
     ms = []
-    for a, (n, mm) in enumerate(zip(N, M)):
+    for a, mm in enumerate(M):
         sh = [1] * d
         sh[a] = mm
-        ms.append(np.arange(-(n - 1), n).reshape(sh))        # centred order
+        ms.append(np.arange(-(mm // 2), mm // 2 + 1).reshape(sh))  # centred order
     Ahat = inc.hat(ms)
+    keep = np.ones(Ahat.shape, dtype=bool)
+    for m, n in zip(ms, N):
+        keep &= np.abs(np.broadcast_to(m, Ahat.shape)) <= n - 1
+    Ahat = np.where(keep, Ahat, 0.0)
     # sum_m A^(m) exp(2 pi i m x_j) over centred m and centred x: an inverse
     # DFT between centred orders (ifftshift / fftshift around numpy's ifftn)
     vals = np.fft.fftshift(np.fft.ifftn(np.fft.ifftshift(Ahat))) * float(np.prod(M))
@@ -166,15 +179,16 @@ class GaResult:
 
 
 def solve(inc: Inclusion, N: Sequence[int], Es: Optional[Sequence[Sequence[float]]] = None,
-          tol: float = 1e-10, max_iter: int = 1000) -> GaResult:
-    """Homogenised matrix of an inclusion coefficient by Ga (DoGIP)."""
+          tol: float = 1e-10, max_iter: int = 1000, M: Optional[Sequence[int]] = None) -> GaResult:
+    """Homogenised matrix of an inclusion coefficient by Ga (DoGIP) on the
+    double grid M (default 2N - 1)."""
     N = list(N)
     d = len(N)
     if any(n % 2 == 0 for n in N):
         raise ValueError("odd grid sizes only (Sec. 2.2.1)")
     if Es is None:
         Es = [np.eye(d)[i] for i in range(d)]
-    AM = coefficient_on_double_grid(inc, N)
+    AM = coefficient_on_double_grid(inc, N, M)
     scale = float(np.sqrt(np.mean(AM * AM)))
     uhs, iters, hists = [], [], []
     for E in Es:

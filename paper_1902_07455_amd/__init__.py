@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import LrfgError, check, lib
 
 __all__ = ["Solver", "SolveResult", "LrfgError", "lib", "fft_lines", "mode_op", "full_op",
-           "gemm", "syevj", "gram_cut", "compress_tt", "compress_tucker", "tucker_round", "tt_round", "abi_version", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
+           "gemm", "syevj", "gram_cut", "compress_tt", "compress_tucker", "tucker_round", "tt_round", "abi_version", "ga_double_grid", "device_check", "prof_enable", "prof_read", "prof_work", "Server",
            "Completion"]
 
 _FORMATS = {"full": _lib.FORMAT_FULL, "cp": _lib.FORMAT_CP, "tucker": _lib.FORMAT_TUCKER,
@@ -32,6 +32,15 @@ _PRECS = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_MIXED_FP32, "bf16": _lib.PRE
 
 def abi_version() -> int:
     return lib().lrfg_abi_version()
+
+
+def ga_double_grid(N: int) -> int:
+    """The double grid of the Ga discretisation for N points per axis: the
+    smallest odd 3^a 5^b >= 2N - 1 (2N - 1 above 2048)."""
+    m = lib().lrfg_ga_double_grid(int(N))
+    if m < 0:
+        check(m)
+    return m
 
 
 def device_check() -> int:

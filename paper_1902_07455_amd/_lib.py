@@ -102,7 +102,7 @@ EXPORTS = [
     "lrfg_fft_workspace_bytes", "lrfg_fft_lines", "lrfg_mode_op",
     "lrfg_full_op_workspace_bytes", "lrfg_full_op", "lrfg_prof_enable", "lrfg_prof_read", "lrfg_prof_work",
     "lrfg_gemm_workspace_bytes", "lrfg_gemm", "lrfg_gemm_mixed", "lrfg_syevj", "lrfg_gram_cut", "lrfg_compress_workspace_bytes", "lrfg_tucker_round_workspace_bytes", "lrfg_tucker_round", "lrfg_compress_tt", "lrfg_compress_tucker_workspace_bytes", "lrfg_compress_tucker", "lrfg_tt_round_workspace_bytes",
-    "lrfg_tt_round", "lrfg_solve_noalloc",
+    "lrfg_tt_round", "lrfg_solve_noalloc", "lrfg_ga_double_grid",
 ]
 
 
@@ -120,6 +120,8 @@ def lib():
     import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     L.lrfg_abi_version.restype = C.c_int
+    L.lrfg_ga_double_grid.argtypes = [C.c_int]
+    L.lrfg_ga_double_grid.restype = C.c_int
     L.lrfg_status_string.restype = C.c_char_p
     L.lrfg_status_string.argtypes = [C.c_int]
     L.lrfg_last_error.restype = C.c_char_p

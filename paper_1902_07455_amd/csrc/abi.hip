@@ -47,6 +47,21 @@ namespace {
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
+// Ga's double grid for n points per axis: the products of two gradients of
+// T_n have frequencies |m| <= n - 1, so any odd grid of at least 2n - 1
+// points integrates the bilinear and energy forms exactly (Sec. 2.2.3 takes
+// 2n - 1, the smallest).  The smallest odd 3^a 5^b >= 2n - 1 keeps every
+// transform on the register passes; above 2025 (the largest below the grid
+// limit 2048) the grid stays at 2n - 1.
+int ga_double_grid(int n) {
+  const int lo = 2 * n - 1;
+  int best = 0;
+  for (long long p3 = 1; p3 <= 2048; p3 *= 3)
+    for (long long v = p3; v <= 2048; v *= 5)
+      if (v >= lo && (best == 0 || v < best)) best = (int)v;
+  return best > 0 ? best : lo;
+}
+
 int validate(const lrfg_problem* p) {
   if (p == nullptr) {
     set_error("problem is NULL");
@@ -206,6 +221,16 @@ extern "C" {
 
 int lrfg_abi_version(void) { return LRFG_ABI_VERSION; }
 
+int lrfg_ga_double_grid(int N) {
+  using namespace lrfg;
+  clear_error();
+  if (N < 1 || N % 2 == 0 || N > 1024) {
+    set_error("Ga grid size N = %d: odd, in [1, 1024]", N);
+    return LRFG_EINVAL;
+  }
+  return ga_double_grid(N);
+}
+
 const char* lrfg_status_string(int s) {
   switch (s) {
     case LRFG_OK: return "ok";
@@ -237,9 +262,9 @@ int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
   LRFG_TRY(validate(p));
   lrfg_plan* pl = new lrfg_plan();
   pl->p = *p;
-  // full-grid geometry: the double grid 2N - 1 for Ga
-  const int g2 = p->discretisation == LRFG_DISC_GA ? 2 : 1;
-  auto gridN = [&](int i) { return g2 * p->N[i] - (g2 - 1); };
+  // full-grid geometry: Ga's double grid (at least 2N - 1)
+  const bool ga = p->discretisation == LRFG_DISC_GA;
+  auto gridN = [&](int i) { return ga ? ga_double_grid(p->N[i]) : p->N[i]; };
   if (p->d == 3) {
     pl->N3d[0] = gridN(0);
     pl->N3d[1] = gridN(1);
@@ -256,7 +281,7 @@ int lrfg_plan_create(const lrfg_problem* p, lrfg_plan** out) {
       return rc;
     }
   }
-  // low-rank Ga: the carriages live on the double grid 2N - 1
+  // low-rank Ga: the carriages live on the double grid
   lrfg_problem pm = *p;
   for (int i = 0; i < p->d; ++i) pm.N[i] = gridN(i);
   for (int i = 0; i < p->d; ++i) {
@@ -475,10 +500,10 @@ static int full_one(lrfg_plan* plan, const lrfg_coeff* a, const double* E, int n
     fa.pinned_flags = plan->pinned;
     for (int i = 0; i < p.d * p.d; ++i) fa.B[i] = p.aniso[i];
     if (p.discretisation == LRFG_DISC_GA) {
-      // the double grid M = 2N - 1; trial and test functions on the N-frequencies
+      // the double grid M >= 2N - 1; trial and test functions on the N-frequencies
       for (int i = 0; i < p.d; ++i) {
         fa.ga_N[i] = p.N[i];
-        fa.N[i] = 2 * p.N[i] - 1;
+        fa.N[i] = ga_double_grid(p.N[i]);
       }
       fa.incl = a->inclusion;
       fa.incl_size = a->incl_size;

@@ -74,7 +74,7 @@ struct Aniso3 {
   int on;
 };
 // Ga (exact integration, Sec. 2.2.3): trial and test functions in T_N, kept
-// on the double grid M = 2N - 1 as spectra whose frequencies beyond
+// on the double grid M >= 2N - 1 as spectra whose frequencies beyond
 // |k_i| <= kmax_i are zero (the injection I and its adjoint I*).  on = 0:
 // GaNi, no mask.
 struct Mask3 {
@@ -945,7 +945,7 @@ __global__ void k_ah_reduce(const double* __restrict__ a, const double* __restri
 // (4 pi size^3 / 3 at rho = 0).  The phase places the unnormalised inverse DFT
 // at the points x_j = -1/2 + (j + 1/2)/M.  d = 2 uses axes 1 and 2.
 __global__ void k_incl_spectrum(double2* __restrict__ out, G3 g, int d, int shape, double size, double vin,
-                                double vout) {
+                                double vout, Mask3 trunc) {
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < g.S;
        s += (long long)gridDim.x * blockDim.x) {
     int n1, n2, h;
@@ -969,6 +969,8 @@ __global__ void k_incl_spectrum(double2* __restrict__ out, G3 g, int d, int shap
     }
     double v = (vin - vout) * chi;
     if (k[0] == 0.0 && k[1] == 0.0 && k[2] == 0.0) v += vout;
+    // the series stops at |m_i| <= N_i - 1 (a double grid above 2N - 1 holds more)
+    if (fabs(k[0]) > trunc.k0 || fabs(k[1]) > trunc.k1 || fabs(k[2]) > trunc.k2) v = 0.0;
     double ph = 0.0;
     for (int a = 0; a < 3; ++a) ph -= kPi * k[a] * (double)(Ms[a] - 1) / (double)Ms[a];
     out[s] = make_double2(v * cos(ph), v * sin(ph));
@@ -1157,8 +1159,10 @@ int full_solve(const FullSolveArgs& A, FullSolveOut* out) {
     // the inclusion's Fourier integrals on the double grid, then the
     // unnormalised inverse transform (axes 1 and 2, C2R along axis 3) to its
     // nodal values; q[0] is free until the first matvec
+    int lim[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i) lim[alpha0 + i] = A.ga_N[i] - 1;
     hipLaunchKernelGGL(k_incl_spectrum, dim3(L.grid_vec), dim3(kBlock), 0, s, L.q, g, d, A.incl, A.incl_size,
-                       A.incl_in, A.incl_out);
+                       A.incl_in, A.incl_out, Mask3{lim[0], lim[1], lim[2], 1});
     LRFG_LAUNCHED();
     LRFG_TRY(launch_fft_lines(L.q, 1, g.N1, (long long)g.N2 * g.H, 1, f1, 1.0, s));
     LRFG_TRY(launch_fft_lines(L.q, g.N1, g.N2, g.H, 1, f2, 1.0, s));

@@ -41,6 +41,20 @@ def test_version_and_status_strings():
         assert len(lib.lrfg_status_string(s)) > 0
 
 
+def test_ga_double_grid():
+    """The smallest odd 3^a 5^b >= 2N - 1 (2N - 1 beyond 2025); bad N rejected."""
+    L = _lib()
+    lib = L.lib()
+    smooth = sorted(3 ** a * 5 ** b for a in range(8) for b in range(6) if 3 ** a * 5 ** b <= 2048)
+    for N in (1, 3, 13, 15, 23, 63, 203, 243, 313, 609, 939, 1013):
+        want = next(m for m in smooth if m >= 2 * N - 1)
+        assert lib.lrfg_ga_double_grid(N) == want
+    assert [lib.lrfg_ga_double_grid(N) for N in (15, 63, 203, 243, 939)] == [45, 125, 405, 625, 2025]
+    assert lib.lrfg_ga_double_grid(1015) == 2029 and lib.lrfg_ga_double_grid(1023) == 2045
+    for bad in (0, -3, 4, 1025):
+        assert lib.lrfg_ga_double_grid(bad) == -1
+
+
 def _problem(L, **kw):
     p = L.Problem()
     p.d = kw.get("d", 3)

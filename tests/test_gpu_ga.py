@@ -18,7 +18,9 @@ def _rel(A, B):
                                               ("square", 3, 15, 10.0), ("ball", 3, 15, 100.0),
                                               ("ball", 3, 23, 10.0), ("square", 2, 45, 0.1)])
 def test_ga_equals_oracle(dev, shape, d, N, inside):
-    """2N - 1 = 29, 45 (register passes), 89 (prime, generic passes)."""
+    """Double grids 45, 45 and 125 (the smallest odd 3^a 5^b >= 2N - 1)
+    against the oracle on its grid 2N - 1 = 29, 45 and 89: the same Galerkin
+    system."""
     size = 0.3
     s = P.Solver(d=d, N=(N,) * d, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000)
     r = s.solve(inclusion=dict(shape=shape, size=size, inside=inside, outside=1.0))

@@ -66,6 +66,24 @@ def test_double_grid_equals_dense_galerkin(shape, d, N):
     assert np.max(np.abs(A1 - A2)) <= 1e-12 * np.max(np.abs(A2))
 
 
+@pytest.mark.parametrize("shape,d,N,M", [("square", 2, 5, 15), ("square", 2, 7, 25), ("ball", 3, 3, 9),
+                                         ("square", 3, 5, 15)])
+def test_larger_double_grid_is_the_same_galerkin_system(shape, d, N, M):
+    """Any odd double grid of at least 2N - 1 points integrates the products
+    of T_N's gradients exactly, so the solve on M (here the smallest odd
+    3^a 5^b >= 2N - 1, as the GPU path takes it, and 3^a 5^b above that)
+    is the dense Galerkin solve."""
+    inc = G.Inclusion(shape, 0.3, 10.0, 1.0)
+    A1 = G.solve(inc, [N] * d, tol=1e-15, max_iter=2000, M=[M] * d).A_H
+    A2 = _dense_galerkin(inc, N, d)
+    assert np.max(np.abs(A1 - A2)) <= 1e-12 * np.max(np.abs(A2))
+
+
+def test_double_grid_below_2n_minus_1_rejected():
+    with pytest.raises(ValueError):
+        G.coefficient_on_double_grid(G.Inclusion("square", 0.3, 10.0, 1.0), [5, 5], [7, 9])
+
+
 def test_nested_spaces_decrease_the_energy():
     """T_N is contained in T_{N+2}: the Galerkin energy minimum can only fall."""
     inc = G.Inclusion("square", 0.3, 10.0, 1.0)
