@@ -31,8 +31,8 @@ the 243^3 ball), `rank_adaptive` (one rank-adaptive TT solve of the ball,
 caps 57 then the headline cap), `ga` (Galerkin with exact integration on
 the double grid, Sec. 2.2.3: the ball at N = 63 and 203, full grid),
 `ga_lowrank` (the paper's Ga comparison: material square, full Ga on N^3
-against TT Ga on (3N)^3 at the lowest rank as accurate, N = 63, 203, 313,
-isotropic and with B),
+against TT Ga on (3N)^3 at the lowest rank as accurate, 2D N = 45, 135 and
+3D N = 63, 203, 313, isotropic and with B),
 `material_S` (the paper's stochastic material S, TT rank 10, at 135^3,
 243^3 and 729^3, isotropic and with B), `serving` and `cpu_baseline` (the oracle on the
 host).
@@ -766,52 +766,53 @@ GA_LR_RANKS = (3, 5, 7, 11, 15, 21, 31)
 
 
 def ga_lowrank_leg(args, dev):
-    """The paper's Ga comparison (Sec. 5, Table 4): material square (the cube
-    |x_i| < 0.3 with 1 + rho chi, rho = 10), isotropic and with the B of
-    Sec. 4.4.  Full Ga on N^3 with CG stopped at 1e-6 against low-rank TT Ga
-    on (3N)^3, the rank raised along a ladder until the low-rank A_H (a
-    Galerkin upper bound, as the full one) is at least as tight in trace: the
-    energy over the three unit fields.  Each TT solve stops at 1e-8 or where
-    its residual stops decreasing."""
+    """The paper's Ga comparison (Sec. 5, Table 4): material square (the
+    square / cube |x_i| < 0.3 with 1 + rho chi, rho = 10), isotropic and with
+    the B of Sec. 4.4, in 2D (N = 45, 135) and 3D (N = 63, 203, 313).  Full
+    Ga on N^d with CG stopped at 1e-6 against low-rank TT Ga on (3N)^d, the
+    rank raised along a ladder until the low-rank A_H (a Galerkin upper
+    bound, as the full one) is at least as tight in trace: the energy over
+    the d unit fields.  Each TT solve stops at 1e-8 or where its residual
+    stops decreasing."""
     import torch
 
     import paper_1902_07455_amd as P
     import workloads as W
-    inc = dict(shape="cube", size=0.3, inside=11.0, outside=1.0)
+    inc = dict(shape="square", size=0.3, inside=11.0, outside=1.0)
     rows = []
-    for aniso in (False, True):
-        B = W.anisotropy(3) if aniso else None
-        for N in (63, 203, 313):
-            log(f"Ga low rank: N={N} full against 3N={3 * N} TT (aniso={aniso})")
-            s = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-6, max_iter=3000,
-                         aniso=B, device=dev)
-            sec, _, rf = timed(lambda: s.solve(inclusion=inc), 3, 1)
-            s.close()
-            tr_full = float(np.trace(rf.A_H))
-            row = {"aniso": aniso, "N": N, "full": {
-                "double_grid": P.ga_double_grid(N), "trace_A_H": tr_full, "iters": int(rf.iters.max()),
-                "ms_per_solve": round(1e3 * sec / 3, 3)}}
-            ladder = []
-            for r in GA_LR_RANKS:
-                t = P.Solver(d=3, N=(3 * N,) * 3, format="tt", rank_cap=r, discretisation="ga", solver_tol=1e-8,
-                             max_iter=100, aniso=B, device=dev)
-                sec, _, rl = timed(lambda: t.solve(inclusion=inc), 1, 1)
-                tr = float(np.trace(rl.A_H))
-                ladder.append([r, tr, int(rl.iters.max()), round(1e3 * sec, 3)])
-                if tr <= tr_full:
-                    sec, _, rl = timed(lambda: t.solve(inclusion=inc), 2, 0)
-                    D = rf.A_H - rl.A_H
-                    row["tt"] = {"N": 3 * N, "double_grid": P.ga_double_grid(3 * N), "rank": r,
-                                 "trace_A_H": tr, "iters": int(rl.iters.max()), "ms_per_solve": round(1e3 * sec / 2, 3),
-                                 "min_eig_full_minus_tt": float(np.linalg.eigvalsh(0.5 * (D + D.T)).min())}
-                    t.close()
-                    break
+    cases = [(d, aniso, N) for d, Ns in ((2, (45, 135)), (3, (63, 203, 313))) for aniso in (False, True) for N in Ns]
+    for d, aniso, N in cases:
+        B = W.anisotropy(d) if aniso else None
+        log(f"Ga low rank: {d}D N={N} full against 3N={3 * N} TT (aniso={aniso})")
+        s = P.Solver(d=d, N=(N,) * d, format="full", discretisation="ga", solver_tol=1e-6, max_iter=3000,
+                     aniso=B, device=dev)
+        sec, _, rf = timed(lambda: s.solve(inclusion=inc), 3, 1)
+        s.close()
+        tr_full = float(np.trace(rf.A_H))
+        row = {"d": d, "aniso": aniso, "N": N, "full": {
+            "double_grid": P.ga_double_grid(N), "trace_A_H": tr_full, "iters": int(rf.iters.max()),
+            "ms_per_solve": round(1e3 * sec / 3, 3)}}
+        ladder = []
+        for r in GA_LR_RANKS:
+            t = P.Solver(d=d, N=(3 * N,) * d, format="tt", rank_cap=r, discretisation="ga", solver_tol=1e-8,
+                         max_iter=100, aniso=B, device=dev)
+            sec, _, rl = timed(lambda: t.solve(inclusion=inc), 1, 1)
+            tr = float(np.trace(rl.A_H))
+            ladder.append([r, tr, int(rl.iters.max()), round(1e3 * sec, 3)])
+            if tr <= tr_full:
+                sec, _, rl = timed(lambda: t.solve(inclusion=inc), 2, 0)
+                D = rf.A_H - rl.A_H
+                row["tt"] = {"N": 3 * N, "double_grid": P.ga_double_grid(3 * N), "rank": r,
+                             "trace_A_H": tr, "iters": int(rl.iters.max()), "ms_per_solve": round(1e3 * sec / 2, 3),
+                             "min_eig_full_minus_tt": float(np.linalg.eigvalsh(0.5 * (D + D.T)).min())}
                 t.close()
-            row["ladder"] = ladder
-            if "tt" in row:
-                row["full_over_tt_time"] = round(row["full"]["ms_per_solve"] / row["tt"]["ms_per_solve"], 3)
-            rows.append(row)
-            torch.cuda.empty_cache()
+                break
+            t.close()
+        row["ladder"] = ladder
+        if "tt" in row:
+            row["full_over_tt_time"] = round(row["full"]["ms_per_solve"] / row["tt"]["ms_per_solve"], 3)
+        rows.append(row)
+        torch.cuda.empty_cache()
     return rows
 
 
