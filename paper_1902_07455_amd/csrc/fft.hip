@@ -237,8 +237,8 @@ int launch3_fft_lines_any(double2* x, long long nlines, int N, int inner, int di
     return launch3_fft_lines<split_of(NN).A, split_of(NN).B, split_of(NN).C>(x, nlines, inner, dir, f, scale, s, \
                                                                               tag, done, lines_per_flag);
   switch (N) {
-    LRFG_S3(45) LRFG_S3(75) LRFG_S3(81) LRFG_S3(135) LRFG_S3(225) LRFG_S3(243) LRFG_S3(405) LRFG_S3(675)
-    LRFG_S3(729)
+    LRFG_S3(45) LRFG_S3(75) LRFG_S3(81) LRFG_S3(135) LRFG_S3(225) LRFG_S3(243) LRFG_S3(405) LRFG_S3(625)
+    LRFG_S3(675) LRFG_S3(729)
     default: return LRFG_EUNSUPPORTED;
   }
 #undef LRFG_S3

@@ -182,6 +182,7 @@ constexpr Split3 split_of(int N) {
     case 225: return Split3{15, 15, 1};
     case 243: return Split3{9, 9, 3};
     case 405: return Split3{9, 9, 5};
+    case 625: return Split3{5, 25, 5};
     case 675: return Split3{9, 15, 5};
     case 729: return Split3{9, 9, 9};
     default: return Split3{0, 0, 0};

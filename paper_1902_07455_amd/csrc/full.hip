@@ -657,7 +657,7 @@ __global__ __launch_bounds__(kFftBlock) void k3_axis3(double2* __restrict__ X, c
 
 // Launchers of the register passes for the lengths of split_of's table
 // whose arrays fit 32-bit byte offsets (LRFG_EUNSUPPORTED otherwise).
-#define LRFG_SPLIT_CASES(X) X(45) X(75) X(81) X(135) X(225) X(243) X(405) X(675) X(729)
+#define LRFG_SPLIT_CASES(X) X(45) X(75) X(81) X(135) X(225) X(243) X(405) X(625) X(675) X(729)
 
 bool pass_register(int N, const G3& g) {
   return split_of(N).A > 0 && fft_two_level() && g.S * 16 < (1ll << 32) && g.R * 8 < (1ll << 32);

@@ -8,7 +8,7 @@ from oracle import brute
 
 pytestmark = pytest.mark.gpu
 
-LENGTHS = [1, 3, 5, 7, 9, 11, 13, 15, 25, 27, 45, 49, 81, 121, 125, 135, 243, 401, 405, 729]
+LENGTHS = [1, 3, 5, 7, 9, 11, 13, 15, 25, 27, 45, 49, 81, 121, 125, 135, 243, 401, 405, 625, 675, 729]
 
 
 # the largest lengths only with few lines, to keep the test short

@@ -80,6 +80,20 @@ def test_random_2d_nonsquare(dev, N):
     assert _rel(r.A_H, o.A_H) <= 1e-10
 
 
+@pytest.mark.parametrize("N", [(625, 3, 675), (729, 625, 3), (3, 675, 405)])
+def test_register_pass_lengths_against_oracle(dev, N):
+    """The lengths with register passes above 243 (405, 625, 675, 729; the
+    benchmark's and the Ga double grids') on each of the three internal
+    axes: axis 1 (gradient / divergence passes), axis 2 (line passes) and
+    axis 3 (the coefficient pass), the other axes short."""
+    a = np.random.default_rng(sum(N)).uniform(0.5, 2.0, N)
+    r = _solve(a, 3, tol=1e-11)
+    o = fg.solve(a, tol=1e-11)
+    assert r.rc == 0
+    assert _rel(r.A_H, o.A_H) <= 1e-10
+    assert abs(int(r.iters.max()) - max(o.iters)) <= 1
+
+
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_laminate_closed_form(dev, axis):
     N = 27
