@@ -42,34 +42,38 @@ def test_ga_nonsquare_grid_and_general_E(dev):
     assert _rel(G2, E @ A @ E.T) <= 1e-10
 
 
-def test_ga_with_anisotropy(dev):
-    """Ga with the constant B of Sec. 4.4: B is integrated exactly too."""
-    N = 15
-    B = W.anisotropy(3)
-    s = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000, aniso=B)
-    r = s.solve(inclusion=dict(shape="ball", size=0.3, inside=10.0, outside=1.0))
-    # oracle: Ga of the matrix coefficient a I + B, from the same double-grid
-    # coefficient (a constant B only adds B at the zero frequency)
+def _ga_aniso_oracle(shape, d, N, inside, B):
+    """Ga of the matrix coefficient a I + B from the oracle's double-grid
+    coefficient (a constant B only adds B at the zero frequency): the
+    oracle's Ga steps with the tensor material law."""
     from oracle import fg_tensor as FT
-    inc = G.Inclusion("ball", 0.3, 10.0, 1.0)
-    AM = G.coefficient_on_double_grid(inc, [N] * 3)
+    inc = G.Inclusion(shape, 0.3, inside, 1.0)
+    AM = G.coefficient_on_double_grid(inc, [N] * d)
     AT = FT.isotropic_plus_constant(AM, B)
-    Es = [np.eye(3)[i] for i in range(3)]
+    Es = [np.eye(d)[i] for i in range(d)]
     uhs = []
     for E in Es:
-        bh = -G.fg.div_hat([G.restrict(G.fg.fwd(sum(AT[al, be] * E[be] for be in range(3))), [N] * 3)
-                           for al in range(3)])
-        op = lambda v: G.fg.div_hat([G.restrict(G.fg.fwd(h), [N] * 3) for h in FT.material_law(
+        bh = -G.fg.div_hat([G.restrict(G.fg.fwd(sum(AT[al, be] * E[be] for be in range(d))), [N] * d)
+                           for al in range(d)])
+        op = lambda v: G.fg.div_hat([G.restrict(G.fg.fwd(h), [N] * d) for h in FT.material_law(
             AT, [G.fg.inv(G.pad(gh, AM.shape)) for gh in G.fg.grad_hat(v)])])
         uh, _, _ = FT.pcg(op, bh, 1e-12, 3000, 0.0)
         uhs.append(uh)
     fields = []
     for E, uh in zip(Es, uhs):
         g = [G.fg.inv(G.pad(gh, AM.shape)) for gh in G.fg.grad_hat(uh)]
-        fields.append([E[a] + g[a] for a in range(3)])
-    Ao = np.array([[np.mean(sum(f * e for f, e in zip(FT.material_law(AT, fields[i]), fields[j])))
-                    for j in range(3)] for i in range(3)])
-    assert _rel(r.A_H, Ao) <= 1e-10
+        fields.append([E[a] + g[a] for a in range(d)])
+    return np.array([[np.mean(sum(f * e for f, e in zip(FT.material_law(AT, fields[i]), fields[j])))
+                      for j in range(d)] for i in range(d)])
+
+
+def test_ga_with_anisotropy(dev):
+    """Ga with the constant B of Sec. 4.4: B is integrated exactly too."""
+    N = 15
+    B = W.anisotropy(3)
+    s = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000, aniso=B)
+    r = s.solve(inclusion=dict(shape="ball", size=0.3, inside=10.0, outside=1.0))
+    assert _rel(r.A_H, _ga_aniso_oracle("ball", 3, N, 10.0, B)) <= 1e-10
 
 
 def test_ga_upper_bound_decreasing_in_N(dev):
@@ -120,17 +124,19 @@ def test_lowrank_ga_truncated_upper_bound(dev):
     assert _rel(r.A_H, o) < 0.1
 
 
-def test_lowrank_ga_with_anisotropy(dev):
-    """Low-rank Ga with B against the full-grid Ga with B (itself checked
-    against the oracle above)."""
-    N = 15
-    B = W.anisotropy(3)
+@pytest.mark.parametrize("fmt,d,N", [("tt", 3, 15), ("tt", 2, 21), ("cp", 2, 21)])
+def test_lowrank_ga_with_anisotropy(dev, fmt, d, N):
+    """Low-rank Ga with B, untruncated, against the oracle's Ga of a I + B
+    and against the full-grid Ga with B."""
+    B = W.anisotropy(d)
     inc = dict(shape="square", size=0.3, inside=10.0, outside=1.0)
-    f = P.Solver(d=3, N=(N,) * 3, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000,
+    f = P.Solver(d=d, N=(N,) * d, format="full", discretisation="ga", solver_tol=1e-12, max_iter=3000,
                  aniso=B).solve(inclusion=inc)
-    t = P.Solver(d=3, N=(N,) * 3, format="tt", discretisation="ga", rank_cap=N, solver_tol=1e-12, max_iter=400,
+    t = P.Solver(d=d, N=(N,) * d, format=fmt, discretisation="ga", rank_cap=N, solver_tol=1e-12, max_iter=400,
                  coeff_rank=2, aniso=B).solve(inclusion=inc)
-    assert _rel(t.A_H, f.A_H) <= 1e-10
+    o = _ga_aniso_oracle("square", d, N, 10.0, B)
+    assert _rel(t.A_H, o) <= 1e-10
+    assert _rel(f.A_H, o) <= 1e-10
 
 
 def test_lowrank_ga_ball_unsupported(dev):
