@@ -695,9 +695,10 @@ def aniso_leg(args, dev, ball_wl=None):
 
 def ga_leg(args, dev):
     """Fourier-Galerkin with exact integration (Sec. 2.2.3) on the full grid:
-    the ball |x| < 0.3 of contrast 100 through the double grid 2N - 1, at
-    N = 63 and 203 (double grids 125 and 405, both 3^a 5^b), each at the
-    loosest PCG tolerance within 1e-6 of its own 1e-10 Ga reference; the
+    the ball |x| < 0.3 of contrast 100 through the double grid (the smallest
+    odd 3^a 5^b of at least 2N - 1 points) at N = 63 and 203 (double grids
+    125 and 405), each at the loosest PCG tolerance within 1e-6 of its own
+    1e-10 Ga reference; the
     per-pass roofline at N = 203 and the Ga oracle timed at N = 63."""
     import torch
 
@@ -705,7 +706,7 @@ def ga_leg(args, dev):
     inc = dict(shape="ball", size=0.3, inside=100.0, outside=1.0)
     rows = []
     for N in (63, 203):
-        M = 2 * N - 1
+        M = P.ga_double_grid(N)
         log(f"Ga N={N} (double grid {M})")
 
         def solver(tol):

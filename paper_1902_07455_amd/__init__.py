@@ -36,7 +36,7 @@ def abi_version() -> int:
 
 def ga_double_grid(N: int) -> int:
     """The double grid of the Ga discretisation for N points per axis: the
-    smallest odd 3^a 5^b >= 2N - 1 (2N - 1 above 2048)."""
+    smallest odd 3^a 5^b >= 2N - 1, or 2N - 1 when that exceeds 2048."""
     m = lib().lrfg_ga_double_grid(int(N))
     if m < 0:
         check(m)
